@@ -1,0 +1,215 @@
+/*
+ * pmg.h -- C-ABI of libpmg.so: iterative solution of the Laplace problem of
+ * fully nonlinear potential flow (Sec. 2, eq. laplaceproblem) discretised by
+ * the Galerkin spectral element method on extruded, curvilinear prism meshes
+ * (Sec. 3.1, eq. laplaceproblemdiscrete), solved by a Krylov method
+ * preconditioned by geometric p-multigrid V-cycles that coarsen the
+ * polynomial order P -> floor(P/2) -> ... -> 1 on one fixed mesh (Sec. 5,
+ * Alg. 1-3), on one AMD Instinct MI355X (gfx950).
+ *
+ * Conventions
+ *  - Status: 0 ok; > 0 warning (outputs valid); < 0 error.  On error the
+ *    outputs are untouched unless stated; pmg_last_error() gives the message.
+ *  - Pointers marked "device" are device memory of the context's GPU (for
+ *    example torch tensor data_ptr()); "host" pointers are CPU memory.  The
+ *    caller owns every pointer it passes; the context owns what it allocates
+ *    and frees it in pmg_destroy().
+ *  - `stream` is a hipStream_t (NULL = default stream); all device work is
+ *    enqueued on it in order.  Calls that return host data synchronise it.
+ *  - Indices are 0-based int32.  Global node numbering of level l
+ *    (order P_l): g = id2d * (L*P_l + 1) + z, z = layer*P_l + c, with the 2D
+ *    numbering documented at pmg_gather_map().  Element e = t*L + layer, local
+ *    node n = c*Np_tri + a (c vertical LGL node, a triangle node).
+ *  - A context is not thread safe; distinct contexts are independent.
+ *  - Results are deterministic: the same inputs on the same device give
+ *    bitwise identical outputs (fixed reduction order, no atomics in sums).
+ */
+#ifndef PMG_H
+#define PMG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PMG_ABI_VERSION 1
+
+enum pmg_status {
+  PMG_OK = 0,
+  PMG_NOT_CONVERGED = 1,   /* imax reached; phi holds the last iterate       */
+  PMG_FALLBACK_USED = 2,   /* learned guess rejected; baseline guess used     */
+  PMG_EINVAL = -1,         /* bad argument                                    */
+  PMG_ENOMEM = -2,         /* device allocation failed                        */
+  PMG_EDEVICE = -3,        /* HIP runtime error                               */
+  PMG_EBREAKDOWN = -4,     /* p^T A p <= 0 or z^T r <= 0 (indefinite M or A)   */
+  PMG_ENONFINITE = -5,     /* NaN/Inf in boundary data or iterate             */
+  PMG_EMESH = -6,          /* non-positive Jacobian (inverted element)        */
+  PMG_ESTATE = -7          /* call not valid in this state (e.g. host-only)    */
+};
+
+/* Arithmetic of the preconditioner (Sec. 1 mentions mixed precision as a way to
+ * accelerate multigrid; the outer residual and Krylov recurrences are always
+ * FP64). */
+enum pmg_precision { PMG_FP64 = 0, PMG_MIXED_FP32 = 1, PMG_MIXED_BF16 = 2 };
+
+/* Outer iteration: Alg. 3 (PCG), flexible PCG (Polak-Ribiere beta), Alg. 2
+ * (preconditioned defect correction), stand-alone V-cycles. */
+enum pmg_krylov { PMG_PCG = 0, PMG_FPCG = 1, PMG_PDC = 2, PMG_MG = 3 };
+
+enum pmg_guess { PMG_GUESS_GIVEN = 0, PMG_GUESS_ZERO = 1, PMG_GUESS_LEARNED = 2 };
+
+/* Coarsest (P = 1) level of Alg. 1: exact solve through a dense inverse of the
+ * free-node matrix, or a fixed-degree Jacobi-preconditioned Chebyshev
+ * iteration on [lmin, lmax] (a linear, symmetric approximation). */
+enum pmg_coarse { PMG_COARSE_EXACT = 0, PMG_COARSE_CHEBYSHEV = 1 };
+
+typedef struct pmg_ctx pmg_ctx;
+typedef struct pmg_net pmg_net;
+
+/* Triangle mesh of the xy-plane extruded over n_layers uniform sigma layers
+ * between a flat bottom z = -depth and the free surface z = eta (Sec. 3.1,
+ * Sec. 6.2).  Host memory, read only during pmg_create. */
+typedef struct pmg_mesh {
+  int32_t nv;
+  const double* xy;          /* [nv][2] vertex coordinates                      */
+  int32_t nt;
+  const int32_t* tri;        /* [nt][3] counter-clockwise vertex ids            */
+  const int32_t* edge_tag;   /* [nt][3] tag (0..31) of edge (tri[i], tri[i+1]); 0 interior */
+  int32_t ncurved;
+  const int32_t* curved_edge;/* [ncurved][2] vertex pairs on a circle (nullable) */
+  const double* circle;      /* [ncurved][3] cx, cy, R (nullable)               */
+  int32_t n_layers;
+  double depth;
+} pmg_mesh;
+
+typedef struct pmg_options {
+  int32_t P;              /* finest order, 1..8; levels P, floor(P/2), ..., 1    */
+  int32_t nu1, nu2;       /* damped-Jacobi pre/post sweeps (Alg. 1)              */
+  double omega[8];        /* per level; <= 0: 4/(3*lambda) with lambda = 1.05 x
+                             30-step power estimate of lambda_max(D^-1 A)       */
+  int32_t precision;      /* pmg_precision of the V-cycle                        */
+  int32_t krylov;         /* pmg_krylov                                          */
+  uint32_t dirichlet_tags;/* bit k set: lateral edges tagged k are Dirichlet      */
+  int32_t top_neumann;    /* 1: no Dirichlet at the surface (pure Neumann tests) */
+  int32_t coarse;         /* pmg_coarse                                          */
+  int32_t cheb_degree;    /* Chebyshev steps of the coarse solve                 */
+  double cheb_lmin, cheb_lmax; /* interval; lmax <= 0: power estimate; lmin <= 0:
+                             lmax / cheb_ratio                                   */
+  double cheb_ratio;
+  int32_t exact_max;      /* largest free coarse size for the dense inverse      */
+  uint64_t seed;          /* counter-based start vector of the power iterations  */
+  int32_t host_only;      /* 1: numbering only, no device memory (queries only)  */
+} pmg_options;
+
+typedef struct pmg_level_info {
+  int32_t order;          /* P_l */
+  int32_t np;             /* nodes per prism (P+1)^2 (P+2)/2 */
+  int32_t nq;             /* cubature points per prism (P+1)^3 */
+  int32_t n_colours;
+  int64_t n_dof;          /* all global nodes of the level */
+  int64_t n_free;         /* nodes not on the Dirichlet boundary */
+  int64_t n_elem;
+  int64_t n_surface;      /* 2D nodes = surface nodes of the level */
+} pmg_level_info;
+
+typedef struct pmg_stats {
+  int32_t iters;          /* outer iterations performed */
+  int32_t n_hist;         /* entries of res_hist (iters + 1, capped at 512) */
+  double rel_res;         /* ||f - A phi||_2 / ||f||_2 over free nodes, FP64 (stop-test quantity) */
+  double norm_f;          /* ||f||_2 of the lifted right-hand side */
+  double res_hist[512];   /* ||r_m||_2, m = 0..iters; q_m = res_hist[m]/res_hist[m-1] (eq. convrate) */
+  double t_solve_ms;      /* wall time of pmg_solve on the stream (hipEvents) */
+  double t_guess_ms;      /* part spent building the initial guess */
+  int32_t fallback;       /* 1 if a learned guess was rejected */
+  int32_t n_vcycles;      /* preconditioner applications */
+  int32_t n_fine_applies; /* FP64 fine-operator applications */
+} pmg_stats;
+
+/* Fill `opt` with defaults: P=6, nu1=nu2=2, auto omega, FP64, PCG, exact
+ * coarse solve with exact_max=12000, Chebyshev degree 30 and ratio 100. */
+void pmg_options_default(pmg_options* opt);
+
+/* Build the level hierarchy: numbering, gather maps, colouring, reference
+ * matrices and transfers of every level (Sec. 5, Sec. 5.1), and device
+ * buffers.  The geometry is set by pmg_set_surface() (flat eta = 0 after
+ * create).  Errors: EINVAL (bad sizes/order), EMESH (degenerate triangle),
+ * ENOMEM, EDEVICE; message from pmg_global_error(). */
+int pmg_create(const pmg_mesh* mesh, const pmg_options* opt, pmg_ctx** out);
+void pmg_destroy(pmg_ctx* ctx);
+const char* pmg_last_error(const pmg_ctx* ctx);
+const char* pmg_global_error(void);
+int pmg_abi_version(void);
+
+int pmg_n_levels(const pmg_ctx* ctx);
+int pmg_level_info_get(const pmg_ctx* ctx, int level, pmg_level_info* info);
+
+/* Gather map of level `level`, host [n_elem][np]: global node of local node
+ * n of element e.  2D numbering: vertex v -> v; edge-interior node m = 1..P-1
+ * counted from the lower vertex id -> nv + edge*(P-1) + m-1, edges being the
+ * (min,max) vertex pairs sorted lexicographically; triangle-interior node of
+ * rank k (local order: j outer, i inner) -> nv + ne*(P-1) + t*(P-1)(P-2)/2 + k.
+ * Bit-exact contract. */
+int pmg_gather_map(const pmg_ctx* ctx, int level, int32_t* map);
+/* Greedy element colouring (host [n_elem]): ascending elements take the
+ * smallest colour not used by a lower element sharing a node. */
+int pmg_colours(const pmg_ctx* ctx, int level, int32_t* colour);
+/* xy of the surface (= 2D) nodes of the finest level, host [n_surface][2]. */
+int pmg_surface_xy(const pmg_ctx* ctx, double* xy);
+/* 1 for Dirichlet nodes of a level, host [n_dof]. */
+int pmg_dirichlet_mask(const pmg_ctx* ctx, int level, uint8_t* mask);
+
+/* Set the free surface: eta at the finest-level surface nodes (device
+ * [n_surface] FP64).  Nodes follow z = -depth + sigma*(eta + depth) (Sec. 3.1's
+ * sigma coordinate with d = eta + h); recomputes the geometric factors of all
+ * levels at their cubature points from the finest isoparametric map, the
+ * Jacobi diagonals, omega (when automatic) and the coarse solver.
+ * Errors: EMESH if any det J <= 0 (context keeps its previous surface). */
+int pmg_set_surface(pmg_ctx* ctx, const double* eta, void* stream);
+/* xyz of the global nodes of a level under the current surface, host [n_dof][3]. */
+int pmg_node_xyz(pmg_ctx* ctx, int level, double* xyz);
+
+/* y = A_l x (stiffness of level l, eq. laplaceproblemdiscrete with A = -L).
+ * precision PMG_FP64: x, y double; PMG_MIXED_FP32 / PMG_MIXED_BF16: x, y float
+ * with FP32 or BF16 geometric factors.  flags bit 0: mask (x and y taken as
+ * zero on Dirichlet nodes, i.e. A_FF). Device [n_dof]. */
+int pmg_apply(pmg_ctx* ctx, int level, int precision, int flags, const void* x, void* y, void* stream);
+/* Diagonal of A_l (device double [n_dof]). */
+int pmg_diagonal(pmg_ctx* ctx, int level, double* d, void* stream);
+/* Damped Jacobi sweeps u <- u + omega D^-1 (f - A u) on free nodes (eq. sec_form). */
+int pmg_smooth(pmg_ctx* ctx, int level, int precision, int sweeps, const void* f, void* u, void* stream);
+/* Nested-space transfers between level l and l+1 (Sec. 5.1): prolongation
+ * interpolates and averages over the elements sharing a node; restriction is
+ * its transpose (eq. rest).  Both zero on Dirichlet nodes. */
+int pmg_prolong(pmg_ctx* ctx, int level, int precision, const void* xc, void* yf, void* stream);
+int pmg_restrict(pmg_ctx* ctx, int level, int precision, const void* xf, void* yc, void* stream);
+/* Coarsest-level solve of Alg. 1 (exact or Chebyshev, per options). */
+int pmg_coarse_solve(pmg_ctx* ctx, int precision, const void* f, void* u, void* stream);
+/* One V-cycle of Alg. 1 from a zero guess: z = M^-1 r on the finest level. */
+int pmg_vcycle(pmg_ctx* ctx, int precision, const void* r, void* z, void* stream);
+/* Smoothing weights and coarse interval in use. */
+int pmg_get_params(const pmg_ctx* ctx, double* omega /*[n_levels]*/, double* cheb_lmin, double* cheb_lmax);
+int pmg_set_params(pmg_ctx* ctx, const double* omega /*[n_levels] or NULL*/, double cheb_lmin, double cheb_lmax);
+
+/* Solve A phi = b (b = 0: no-flux walls, bottom and bodies) with phi = Dirichlet
+ * data on the Dirichlet nodes (lifting f = -A phi_D), to
+ * ||f - A phi||_2 <= rtol ||f||_2 + atol (stop test of Sec. 5), with the outer
+ * iteration and precision of the options.
+ *  phi_surf: device [n_surface] values at the surface nodes, or NULL;
+ *  phi_bc:   device [n_dof] values read at every Dirichlet node, or NULL
+ *            (required when lateral Dirichlet tags are set);
+ *  phi:      device [n_dof]; in: guess (GUESS_GIVEN), out: solution.
+ *  net:      learned model for GUESS_LEARNED (else NULL); hist_phi: device
+ *            pointers to the two previous solutions [n_dof] (learned/extrapolated
+ *            guesses) or NULL.
+ *  stats:    host, may be NULL.
+ * Returns OK, NOT_CONVERGED (phi = last iterate), FALLBACK_USED, or an error
+ * (EBREAKDOWN, ENONFINITE, EINVAL, EDEVICE). */
+int pmg_solve(pmg_ctx* ctx, const double* phi_surf, const double* phi_bc, double* phi, int guess_mode,
+              const pmg_net* net, const double* const* hist_phi, double rtol, double atol, int32_t imax,
+              pmg_stats* stats, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PMG_H */

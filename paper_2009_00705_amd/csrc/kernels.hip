@@ -1,0 +1,836 @@
+// Device kernels of the p-multigrid SEM Laplace solve (gfx950, wave64).
+//
+// Layouts (all chosen by this library):
+//  * L-vectors: global node g = id2d*(L*P+1) + z, columns contiguous.
+//  * E-vectors ("Y"): [t][a][layer][c] so that the column of triangle node a
+//    of triangle t is contiguous (L*(P+1) values) and the node-centric sum
+//    reads it with unit stride.
+//  * G: [e][6][Nq] with components (rr, rs, rt, ss, st, tt) and cubature index
+//    k*Nq_tri + q.
+//  * Reference matrices ("mats"): [Dr | Ds | B] (Nq_tri x Np_tri each, row
+//    major) followed by [Bz | Dz] ((P+1) x (P+1) each).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "kernels.hpp"
+
+namespace pmg {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bf16_to_f32(bf16_t h) {
+  return __uint_as_float(uint32_t(h) << 16);
+}
+__device__ __forceinline__ bf16_t f32_to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);  // round to nearest even
+  return bf16_t(u >> 16);
+}
+template <typename T> __device__ __forceinline__ T ldg(const double* p, size_t i) { return T(p[i]); }
+template <typename T> __device__ __forceinline__ T ldg(const float* p, size_t i) { return T(p[i]); }
+template <typename T> __device__ __forceinline__ T ldg(const bf16_t* p, size_t i) { return T(bf16_to_f32(p[i])); }
+
+// deterministic block sum (256 threads); result valid in thread 0
+__device__ double block_sum256(double v) {
+  __shared__ double sh[4];
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[w] = v;
+  __syncthreads();
+  return threadIdx.x == 0 ? (sh[0] + sh[1]) + (sh[2] + sh[3]) : 0.0;
+}
+
+static inline int grid_for(int64_t n, int per = 256, int cap = 65535 * 4) {
+  int64_t g = (n + per - 1) / per;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return int(g);
+}
+
+// position of vertical level z inside a column of L*(P+1) element values;
+// p2 >= 0 when z is an interior layer interface (two element copies)
+__device__ __forceinline__ void column_pos(int z, int P, int L, int& p1, int& p2) {
+  if (z == 0) { p1 = 0; p2 = -1; return; }
+  const int layer = (z - 1) / P;
+  const int c = z - layer * P;
+  p1 = layer * (P + 1) + c;
+  p2 = (c == P && layer + 1 < L) ? p1 + 1 : -1;
+}
+
+// ---------------------------------------------------------------------------
+// generic element operator (all orders, LDS staged)
+// ---------------------------------------------------------------------------
+template <int P> struct Dims {
+  static constexpr int N1 = P + 1, NPT = (P + 1) * (P + 2) / 2, NP = NPT * N1;
+  static constexpr int NQT = N1 * N1, NQ = NQT * N1;
+  static constexpr int NMAT = 3 * NQT * NPT + 2 * N1 * N1;
+  static constexpr int PER_EL = (NP > 3 * NQ ? NP : 3 * NQ) + 2 * N1 * NPT;
+  static constexpr int NEB = (4096 / PER_EL) < 1 ? 1 : ((4096 / PER_EL) > 64 ? 64 : (4096 / PER_EL));
+};
+
+template <int P, typename T, typename TG>
+__global__ __launch_bounds__(256) void k_ax(const int32_t* __restrict__ map2d, int L, int nz,
+                                            int64_t n_elem, const T* __restrict__ mats,
+                                            const TG* __restrict__ G, const T* __restrict__ u,
+                                            T* __restrict__ Y) {
+  using D = Dims<P>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NP = D::NP, NQT = D::NQT, NQ = D::NQ, NEB = D::NEB;
+  constexpr int SA = (NP > 3 * NQ ? NP : 3 * NQ), SB = 2 * N1 * NPT;
+  __shared__ T sm_mat[D::NMAT];
+  __shared__ T sm_a[NEB * SA];
+  __shared__ T sm_b[NEB * SB];
+  for (int i = threadIdx.x; i < D::NMAT; i += 256) sm_mat[i] = mats[i];
+  const T* Dr = sm_mat;
+  const T* Ds = Dr + NQT * NPT;
+  const T* Bt = Ds + NQT * NPT;
+  const T* Bz = Bt + NQT * NPT;
+  const T* Dz = Bz + N1 * N1;
+  for (int64_t e0 = int64_t(blockIdx.x) * NEB; e0 < n_elem; e0 += int64_t(gridDim.x) * NEB) {
+    const int ne = int(n_elem - e0 < NEB ? n_elem - e0 : NEB);
+    __syncthreads();
+    // gather: item (el, a, c), c fastest (contiguous in the L-vector)
+    for (int i = threadIdx.x; i < ne * NP; i += 256) {
+      const int el = i / NP, r = i - el * NP, a = r / N1, c = r - a * N1;
+      const int64_t e = e0 + el;
+      const int t = int(e / L), layer = int(e - int64_t(t) * L);
+      const int64_t g = int64_t(map2d[size_t(t) * NPT + a]) * nz + layer * P + c;
+      sm_a[el * SA + c * NPT + a] = u[g];
+    }
+    __syncthreads();
+    // vertical: W[k][a] = sum_c Bz[k][c] U[c][a], Wz with Dz
+    for (int i = threadIdx.x; i < ne * N1 * NPT; i += 256) {
+      const int el = i / (N1 * NPT), r = i - el * N1 * NPT, k = r / NPT, a = r - k * NPT;
+      const T* U = sm_a + el * SA;
+      T w = 0, wz = 0;
+#pragma unroll
+      for (int c = 0; c < N1; ++c) {
+        const T uv = U[c * NPT + a];
+        w += Bz[k * N1 + c] * uv;
+        wz += Dz[k * N1 + c] * uv;
+      }
+      sm_b[el * SB + k * NPT + a] = w;
+      sm_b[el * SB + N1 * NPT + k * NPT + a] = wz;
+    }
+    __syncthreads();
+    // triangle contractions + geometric factors at every cubature point
+    for (int i = threadIdx.x; i < ne * NQ; i += 256) {
+      const int el = i / NQ, r = i - el * NQ, k = r / NQT, q = r - k * NQT;
+      const T* W = sm_b + el * SB + k * NPT;
+      const T* Wz = W + N1 * NPT;
+      T ur = 0, us = 0, ut = 0;
+#pragma unroll 4
+      for (int a = 0; a < NPT; ++a) {
+        ur += Dr[q * NPT + a] * W[a];
+        us += Ds[q * NPT + a] * W[a];
+        ut += Bt[q * NPT + a] * Wz[a];
+      }
+      const size_t gb = size_t(e0 + el) * 6 * NQ + r;
+      const T g0 = ldg<T>(G, gb), g1 = ldg<T>(G, gb + NQ), g2 = ldg<T>(G, gb + 2 * NQ);
+      const T g3 = ldg<T>(G, gb + 3 * NQ), g4 = ldg<T>(G, gb + 4 * NQ), g5 = ldg<T>(G, gb + 5 * NQ);
+      T* V = sm_a + el * SA;
+      V[r] = g0 * ur + g1 * us + g2 * ut;
+      V[NQ + r] = g1 * ur + g3 * us + g4 * ut;
+      V[2 * NQ + r] = g2 * ur + g4 * us + g5 * ut;
+    }
+    __syncthreads();
+    // transposed triangle contractions
+    for (int i = threadIdx.x; i < ne * N1 * NPT; i += 256) {
+      const int el = i / (N1 * NPT), r = i - el * N1 * NPT, k = r / NPT, a = r - k * NPT;
+      const T* vr = sm_a + el * SA + k * NQT;
+      const T* vs = vr + NQ;
+      const T* vt = vr + 2 * NQ;
+      T yr = 0, yt = 0;
+#pragma unroll 4
+      for (int q = 0; q < NQT; ++q) {
+        yr += Dr[q * NPT + a] * vr[q] + Ds[q * NPT + a] * vs[q];
+        yt += Bt[q * NPT + a] * vt[q];
+      }
+      sm_b[el * SB + k * NPT + a] = yr;
+      sm_b[el * SB + N1 * NPT + k * NPT + a] = yt;
+    }
+    __syncthreads();
+    // vertical transpose, store E-layout
+    for (int i = threadIdx.x; i < ne * NP; i += 256) {
+      const int el = i / NP, r = i - el * NP, a = r / N1, c = r - a * N1;
+      const T* Yr = sm_b + el * SB;
+      const T* Yt = Yr + N1 * NPT;
+      T y = 0;
+#pragma unroll
+      for (int k = 0; k < N1; ++k) y += Bz[k * N1 + c] * Yr[k * NPT + a] + Dz[k * N1 + c] * Yt[k * NPT + a];
+      const int64_t e = e0 + el;
+      const int t = int(e / L), layer = int(e - int64_t(t) * L);
+      Y[((size_t(t) * NPT + a) * L + layer) * N1 + c] = y;
+    }
+  }
+}
+
+template <int P, typename T>
+static void ax_dispatch_g(const LevelView& lv, const T* mats, const void* G, int gstore, const T* u,
+                          T* Y, hipStream_t st) {
+  constexpr int NEB = Dims<P>::NEB;
+  const int64_t nb = (lv.n_elem + NEB - 1) / NEB;
+  const int grid = int(nb < 262144 ? nb : 262144);
+  if (gstore == G_F64)
+    hipLaunchKernelGGL((k_ax<P, T, double>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
+                       lv.n_elem, mats, (const double*)G, u, Y);
+  else if (gstore == G_F32)
+    hipLaunchKernelGGL((k_ax<P, T, float>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
+                       lv.n_elem, mats, (const float*)G, u, Y);
+  else
+    hipLaunchKernelGGL((k_ax<P, T, bf16_t>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
+                       lv.n_elem, mats, (const bf16_t*)G, u, Y);
+}
+
+template <typename T>
+void launch_ax(const LevelView& lv, const T* mats, const void* G, int gstore, const T* u, T* Y,
+               hipStream_t st) {
+  switch (lv.P) {
+    case 1: ax_dispatch_g<1, T>(lv, mats, G, gstore, u, Y, st); break;
+    case 2: ax_dispatch_g<2, T>(lv, mats, G, gstore, u, Y, st); break;
+    case 3: ax_dispatch_g<3, T>(lv, mats, G, gstore, u, Y, st); break;
+    case 4: ax_dispatch_g<4, T>(lv, mats, G, gstore, u, Y, st); break;
+    case 5: ax_dispatch_g<5, T>(lv, mats, G, gstore, u, Y, st); break;
+    case 6: ax_dispatch_g<6, T>(lv, mats, G, gstore, u, Y, st); break;
+    case 7: ax_dispatch_g<7, T>(lv, mats, G, gstore, u, Y, st); break;
+    case 8: ax_dispatch_g<8, T>(lv, mats, G, gstore, u, Y, st); break;
+    default: break;
+  }
+}
+template void launch_ax<double>(const LevelView&, const double*, const void*, int, const double*, double*, hipStream_t);
+template void launch_ax<float>(const LevelView&, const float*, const void*, int, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// node-centric direct-stiffness sum with fused epilogues
+// ---------------------------------------------------------------------------
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, int P,
+                                                  const int32_t* __restrict__ inc_ptr,
+                                                  const int32_t* __restrict__ inc,
+                                                  const uint8_t* __restrict__ dir2d, int top_dir,
+                                                  const T* __restrict__ Y, T* __restrict__ out,
+                                                  const T* __restrict__ a1, const T* __restrict__ a2,
+                                                  T* __restrict__ a3, T omega, T c1,
+                                                  double* __restrict__ partial) {
+  const int colen = L * (P + 1);
+  double acc = 0.0;
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n_dof; g += int64_t(gridDim.x) * 256) {
+    const int64_t g2 = g / nz;
+    const int z = int(g - g2 * nz);
+    const bool dir = dir2d[g2] || (top_dir && z == nz - 1);
+    int p1, p2;
+    column_pos(z, P, L, p1, p2);
+    T s = 0;
+    const int j0 = inc_ptr[g2], j1 = inc_ptr[g2 + 1];
+    for (int j = j0; j < j1; ++j) {
+      const T* col = Y + size_t(inc[j]) * colen;
+      s += col[p1];
+      if (p2 >= 0) s += col[p2];
+    }
+    if (OP == OP_RAW) {
+      out[g] = s;
+    } else if (OP == OP_STORE) {
+      out[g] = dir ? T(0) : s;
+    } else if (OP == OP_AVG_ADD || OP == OP_AVG_STORE) {
+      const T m = T((j1 - j0) * (p2 >= 0 ? 2 : 1));
+      const T v = dir ? T(0) : s / m;
+      if (OP == OP_AVG_ADD) out[g] += v; else out[g] = v;
+    } else if (OP == OP_RESID) {
+      out[g] = dir ? T(0) : a1[g] - s;
+    } else if (OP == OP_JACOBI) {
+      if (!dir) out[g] += omega * a2[g] * (a1[g] - s);
+    } else if (OP == OP_STORE_DOT) {
+      const T v = dir ? T(0) : s;
+      out[g] = v;
+      acc += double(a1[g]) * double(v);
+    } else if (OP == OP_CHEB) {
+      // x = out, r = a1 (in/out through a3 alias), d = a3
+      if (!dir) {
+        T* r = const_cast<T*>(a1);
+        const T rn = r[g] - s;
+        r[g] = rn;
+        const T dn = omega * a3[g] + c1 * a2[g] * rn;
+        a3[g] = dn;
+        out[g] += dn;
+      }
+    }
+  }
+  if (OP == OP_STORE_DOT) {
+    const double b = block_sum256(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+  }
+}
+
+template <typename T>
+void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a1, const T* a2, T* a3,
+                     double omega, double c1, double* partial, hipStream_t st) {
+  const int grid = op == OP_STORE_DOT ? RED_BLOCKS : grid_for(lv.n_dof);
+#define PMG_ASM(OPV)                                                                                   \
+  hipLaunchKernelGGL((k_assemble<T, OPV>), dim3(grid), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.L,  \
+                     lv.P, lv.inc_ptr, lv.inc, lv.dir2d, lv.top_dir, Y, out, a1, a2, a3, T(omega),    \
+                     T(c1), partial)
+  switch (op) {
+    case OP_STORE: PMG_ASM(OP_STORE); break;
+    case OP_AVG_ADD: PMG_ASM(OP_AVG_ADD); break;
+    case OP_RESID: PMG_ASM(OP_RESID); break;
+    case OP_JACOBI: PMG_ASM(OP_JACOBI); break;
+    case OP_STORE_DOT: PMG_ASM(OP_STORE_DOT); break;
+    case OP_AVG_STORE: PMG_ASM(OP_AVG_STORE); break;
+    case OP_CHEB: PMG_ASM(OP_CHEB); break;
+    case OP_RAW: PMG_ASM(OP_RAW); break;
+    default: break;
+  }
+#undef PMG_ASM
+}
+template void launch_assemble<double>(const LevelView&, int, const double*, double*, const double*, const double*, double*, double, double, double*, hipStream_t);
+template void launch_assemble<float>(const LevelView&, int, const float*, float*, const float*, const float*, float*, double, double, double*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// geometric factors (thread per triangle x triangle cubature point)
+// ---------------------------------------------------------------------------
+template <int PF, int PL>
+__global__ __launch_bounds__(256) void k_geom(int nt, int L, double depth,
+                                              const double* __restrict__ xyt,
+                                              const double* __restrict__ eta,
+                                              const int32_t* __restrict__ map2d_f,
+                                              const double* __restrict__ gmats,
+                                              const double* __restrict__ wq,
+                                              const double* __restrict__ zq,
+                                              const double* __restrict__ zw, double* __restrict__ G64,
+                                              float* __restrict__ G32, bf16_t* __restrict__ G16,
+                                              int* __restrict__ bad) {
+  constexpr int NPTF = (PF + 1) * (PF + 2) / 2;
+  constexpr int N1L = PL + 1, NQTL = N1L * N1L, NQL = NQTL * N1L;
+  const int64_t item = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (item >= int64_t(nt) * NQTL) return;
+  const int t = int(item / NQTL), q = int(item - int64_t(t) * NQTL);
+  const double* Bf = gmats;
+  const double* Drf = Bf + NQTL * NPTF;
+  const double* Dsf = Drf + NQTL * NPTF;
+  double xr = 0, xs = 0, yr = 0, ys = 0, eq = 0, er = 0, es = 0;
+  for (int a = 0; a < NPTF; ++a) {
+    const double x = xyt[(size_t(t) * NPTF + a) * 2], y = xyt[(size_t(t) * NPTF + a) * 2 + 1];
+    const double h = eta[map2d_f[size_t(t) * NPTF + a]];
+    const double br = Drf[q * NPTF + a], bs = Dsf[q * NPTF + a], bb = Bf[q * NPTF + a];
+    xr += br * x; xs += bs * x; yr += br * y; ys += bs * y;
+    eq += bb * h; er += br * h; es += bs * h;
+  }
+  const double j2 = xr * ys - xs * yr;
+  const double Krx = ys / j2, Kry = -xs / j2, Ksx = -yr / j2, Ksy = xr / j2;
+  const double zt = (eq + depth) / (2.0 * L);
+  int badv = (j2 <= 0.0 || zt <= 0.0 || !(j2 == j2) || !(zt == zt)) ? 1 : 0;
+  for (int layer = 0; layer < L; ++layer) {
+    const size_t e = size_t(t) * L + layer;
+    for (int k = 0; k < N1L; ++k) {
+      const double sig = (layer + 0.5 * (1.0 + zq[k])) / L;
+      const double zr = sig * er, zs = sig * es;
+      const double Ktx = -(zr * Krx + zs * Ksx) / zt, Kty = -(zr * Kry + zs * Ksy) / zt, Ktz = 1.0 / zt;
+      const double w = wq[q] * zw[k] * zt * j2;
+      double g[6];
+      g[0] = w * (Krx * Krx + Kry * Kry);
+      g[1] = w * (Krx * Ksx + Kry * Ksy);
+      g[2] = w * (Krx * Ktx + Kry * Kty);
+      g[3] = w * (Ksx * Ksx + Ksy * Ksy);
+      g[4] = w * (Ksx * Ktx + Ksy * Kty);
+      g[5] = w * (Ktx * Ktx + Kty * Kty + Ktz * Ktz);
+      const size_t base = e * 6 * NQL + size_t(k) * NQTL + q;
+#pragma unroll
+      for (int m = 0; m < 6; ++m) {
+        if (G64) G64[base + size_t(m) * NQL] = g[m];
+        if (G32) G32[base + size_t(m) * NQL] = float(g[m]);
+        if (G16) G16[base + size_t(m) * NQL] = f32_to_bf16(float(g[m]));
+      }
+    }
+  }
+  if (badv) atomicOr(bad, 1);
+}
+
+template <int PF>
+static void geom_pl(int PL, int nt, int L, double depth, const double* xyt, const double* eta,
+                    const int32_t* map2d_f, const double* gm, const double* wq, const double* zq,
+                    const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st) {
+  const int64_t items = int64_t(nt) * (PL + 1) * (PL + 1);
+  const int grid = int((items + 255) / 256);
+#define PMG_GEOM(PLV)                                                                               \
+  hipLaunchKernelGGL((k_geom<PF, PLV>), dim3(grid), dim3(256), 0, st, nt, L, depth, xyt, eta,       \
+                     map2d_f, gm, wq, zq, zw, G64, G32, G16, bad)
+  switch (PL) {
+    case 1: PMG_GEOM(1); break;
+    case 2: PMG_GEOM(2); break;
+    case 3: PMG_GEOM(3); break;
+    case 4: PMG_GEOM(4); break;
+    case 5: PMG_GEOM(5); break;
+    case 6: PMG_GEOM(6); break;
+    case 7: PMG_GEOM(7); break;
+    case 8: PMG_GEOM(8); break;
+    default: break;
+  }
+#undef PMG_GEOM
+}
+
+void launch_geom(const LevelView& fine, const LevelView& lvl, double depth, const double* xyt,
+                 const double* eta, const double* gmats, const double* wq, const double* zq,
+                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st) {
+  switch (fine.P) {
+    case 1: geom_pl<1>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    case 2: geom_pl<2>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    case 3: geom_pl<3>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    case 4: geom_pl<4>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    case 5: geom_pl<5>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    case 6: geom_pl<6>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    case 7: geom_pl<7>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    case 8: geom_pl<8>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
+    default: break;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// diagonal of the element matrices, E-layout (thread per (e, a, c))
+// ---------------------------------------------------------------------------
+template <int P>
+__global__ __launch_bounds__(256) void k_diag(int64_t n_elem, int L, const double* __restrict__ mats,
+                                              const double* __restrict__ G, double* __restrict__ Y) {
+  constexpr int N1 = P + 1, NPT = (P + 1) * (P + 2) / 2, NP = NPT * N1, NQT = N1 * N1, NQ = NQT * N1;
+  const double* Dr = mats;
+  const double* Ds = Dr + NQT * NPT;
+  const double* Bt = Ds + NQT * NPT;
+  const double* Bz = Bt + NQT * NPT;
+  const double* Dz = Bz + N1 * N1;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n_elem * NP; i += int64_t(gridDim.x) * 256) {
+    const int64_t e = i / NP;
+    const int r = int(i - e * NP), a = r / N1, c = r - a * N1;
+    const double* Ge = G + size_t(e) * 6 * NQ;
+    double d = 0.0;
+    for (int k = 0; k < N1; ++k) {
+      const double bz = Bz[k * N1 + c], dz = Dz[k * N1 + c];
+      for (int q = 0; q < NQT; ++q) {
+        const int p = k * NQT + q;
+        const double dr = bz * Dr[q * NPT + a], ds = bz * Ds[q * NPT + a], dt = dz * Bt[q * NPT + a];
+        d += dr * (Ge[p] * dr + 2.0 * Ge[NQ + p] * ds + 2.0 * Ge[2 * NQ + p] * dt) +
+             ds * (Ge[3 * NQ + p] * ds + 2.0 * Ge[4 * NQ + p] * dt) + dt * Ge[5 * NQ + p] * dt;
+      }
+    }
+    const int t = int(e / L), layer = int(e - int64_t(t) * L);
+    Y[((size_t(t) * NPT + a) * L + layer) * N1 + c] = d;
+  }
+}
+
+void launch_diag(const LevelView& lv, const double* mats, const double* G64, double* Y, hipStream_t st) {
+  const int64_t n = lv.n_elem * lv.np;
+  const int grid = grid_for(n);
+#define PMG_DIAG(PV) hipLaunchKernelGGL((k_diag<PV>), dim3(grid), dim3(256), 0, st, lv.n_elem, lv.L, mats, G64, Y)
+  switch (lv.P) {
+    case 1: PMG_DIAG(1); break;
+    case 2: PMG_DIAG(2); break;
+    case 3: PMG_DIAG(3); break;
+    case 4: PMG_DIAG(4); break;
+    case 5: PMG_DIAG(5); break;
+    case 6: PMG_DIAG(6); break;
+    case 7: PMG_DIAG(7); break;
+    case 8: PMG_DIAG(8); break;
+    default: break;
+  }
+#undef PMG_DIAG
+}
+
+// ---------------------------------------------------------------------------
+// transfers: per-element interpolation Pi = Pi_z (x) Pi_tri
+// ---------------------------------------------------------------------------
+template <int PF, int PC, typename T>
+__global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int nzc,
+                                                      const int32_t* __restrict__ map2d_c,
+                                                      const T* __restrict__ pit,
+                                                      const T* __restrict__ piz,
+                                                      const T* __restrict__ uc, T* __restrict__ Yf) {
+  constexpr int N1F = PF + 1, NPTF = (PF + 1) * (PF + 2) / 2, NPF = NPTF * N1F;
+  constexpr int N1C = PC + 1, NPTC = (PC + 1) * (PC + 2) / 2, NPC = NPTC * N1C;
+  constexpr int NEB = 8;
+  __shared__ T sUc[NEB * NPC];
+  __shared__ T sT1[NEB * N1C * NPTF];
+  for (int64_t e0 = int64_t(blockIdx.x) * NEB; e0 < n_elem; e0 += int64_t(gridDim.x) * NEB) {
+    const int ne = int(n_elem - e0 < NEB ? n_elem - e0 : NEB);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * NPC; i += 256) {
+      const int el = i / NPC, r = i - el * NPC, a = r / N1C, c = r - a * N1C;
+      const int64_t e = e0 + el;
+      const int t = int(e / L), layer = int(e - int64_t(t) * L);
+      sUc[el * NPC + c * NPTC + a] = uc[int64_t(map2d_c[size_t(t) * NPTC + a]) * nzc + layer * PC + c];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * N1C * NPTF; i += 256) {
+      const int el = i / (N1C * NPTF), r = i - el * N1C * NPTF, c = r / NPTF, a = r - c * NPTF;
+      T s = 0;
+      for (int b = 0; b < NPTC; ++b) s += pit[a * NPTC + b] * sUc[el * NPC + c * NPTC + b];
+      sT1[el * N1C * NPTF + c * NPTF + a] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * NPF; i += 256) {
+      const int el = i / NPF, r = i - el * NPF, a = r / N1F, c = r - a * N1F;
+      T s = 0;
+      for (int cc = 0; cc < N1C; ++cc) s += piz[c * N1C + cc] * sT1[el * N1C * NPTF + cc * NPTF + a];
+      const int64_t e = e0 + el;
+      const int t = int(e / L), layer = int(e - int64_t(t) * L);
+      Yf[((size_t(t) * NPTF + a) * L + layer) * N1F + c] = s;
+    }
+  }
+}
+
+template <int PF, int PC, typename T>
+__global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, int nzf,
+                                                       const int32_t* __restrict__ map2d_f,
+                                                       const int32_t* __restrict__ inc_ptr_f,
+                                                       const uint8_t* __restrict__ dir2d_f, int top_dir,
+                                                       const T* __restrict__ pit,
+                                                       const T* __restrict__ piz,
+                                                       const T* __restrict__ rf, T* __restrict__ Yc) {
+  constexpr int N1F = PF + 1, NPTF = (PF + 1) * (PF + 2) / 2, NPF = NPTF * N1F;
+  constexpr int N1C = PC + 1, NPTC = (PC + 1) * (PC + 2) / 2;
+  constexpr int NEB = 4;
+  __shared__ T sRf[NEB * NPF];
+  __shared__ T sT1[NEB * N1F * NPTC];
+  for (int64_t e0 = int64_t(blockIdx.x) * NEB; e0 < n_elem; e0 += int64_t(gridDim.x) * NEB) {
+    const int ne = int(n_elem - e0 < NEB ? n_elem - e0 : NEB);
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * NPF; i += 256) {
+      const int el = i / NPF, r = i - el * NPF, a = r / N1F, c = r - a * N1F;
+      const int64_t e = e0 + el;
+      const int t = int(e / L), layer = int(e - int64_t(t) * L);
+      const int g2 = map2d_f[size_t(t) * NPTF + a];
+      const int z = layer * PF + c;
+      const bool dir = dir2d_f[g2] || (top_dir && z == nzf - 1);
+      const int cnt = inc_ptr_f[g2 + 1] - inc_ptr_f[g2];
+      const bool iface = (z % PF == 0) && z > 0 && z < nzf - 1;
+      const T m = T(cnt * (iface ? 2 : 1));
+      sRf[el * NPF + c * NPTF + a] = dir ? T(0) : rf[int64_t(g2) * nzf + z] / m;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * N1F * NPTC; i += 256) {
+      const int el = i / (N1F * NPTC), r = i - el * N1F * NPTC, c = r / NPTC, b = r - c * NPTC;
+      T s = 0;
+      for (int a = 0; a < NPTF; ++a) s += pit[a * NPTC + b] * sRf[el * NPF + c * NPTF + a];
+      sT1[el * N1F * NPTC + c * NPTC + b] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < ne * NPTC * N1C; i += 256) {
+      const int el = i / (NPTC * N1C), r = i - el * NPTC * N1C, b = r / N1C, cc = r - b * N1C;
+      T s = 0;
+      for (int c = 0; c < N1F; ++c) s += piz[c * N1C + cc] * sT1[el * N1F * NPTC + c * NPTC + b];
+      const int64_t e = e0 + el;
+      const int t = int(e / L), layer = int(e - int64_t(t) * L);
+      Yc[((size_t(t) * NPTC + b) * L + layer) * N1C + cc] = s;
+    }
+  }
+}
+
+#define PMG_PAIRS(X) X(2, 1) X(3, 1) X(4, 2) X(5, 2) X(6, 3) X(7, 3) X(8, 4)
+
+template <typename T>
+void launch_prolong_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* uc,
+                         T* Yf, hipStream_t st) {
+  const int grid = grid_for(f.n_elem, 8, 262144);
+#define PMG_PRO(PFV, PCV)                                                                            \
+  if (f.P == PFV && c.P == PCV) {                                                                    \
+    hipLaunchKernelGGL((k_prolong_elem<PFV, PCV, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L,   \
+                       int(c.nz), c.map2d, pit, piz, uc, Yf);                                        \
+    return;                                                                                          \
+  }
+  PMG_PAIRS(PMG_PRO)
+#undef PMG_PRO
+}
+
+template <typename T>
+void launch_restrict_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* rf,
+                          T* Yc, hipStream_t st) {
+  const int grid = grid_for(f.n_elem, 4, 262144);
+#define PMG_RES(PFV, PCV)                                                                            \
+  if (f.P == PFV && c.P == PCV) {                                                                    \
+    hipLaunchKernelGGL((k_restrict_elem<PFV, PCV, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L,  \
+                       int(f.nz), f.map2d, f.inc_ptr, f.dir2d, f.top_dir, pit, piz, rf, Yc);        \
+    return;                                                                                          \
+  }
+  PMG_PAIRS(PMG_RES)
+#undef PMG_RES
+}
+template void launch_prolong_elem<double>(const LevelView&, const LevelView&, const double*, const double*, const double*, double*, hipStream_t);
+template void launch_prolong_elem<float>(const LevelView&, const LevelView&, const float*, const float*, const float*, float*, hipStream_t);
+template void launch_restrict_elem<double>(const LevelView&, const LevelView&, const double*, const double*, const double*, double*, hipStream_t);
+template void launch_restrict_elem<float>(const LevelView&, const LevelView&, const float*, const float*, const float*, float*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// coarse exact solve (dense inverse on the free coarse nodes)
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_gather_idx(int n, const int32_t* __restrict__ idx, const T* __restrict__ x, T* __restrict__ y) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < n) y[i] = x[idx[i]];
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemv_rows(int n, const int32_t* __restrict__ idx,
+                                                   const T* __restrict__ A, const T* __restrict__ x,
+                                                   T* __restrict__ y) {
+  // one wave per row, deterministic lane-strided sum then butterfly
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= n) return;
+  const T* a = A + size_t(row) * n;
+  double s = 0.0;
+  for (int j = lane; j < n; j += 64) s += double(a[j]) * double(x[j]);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if (lane == 0) y[idx[row]] = T(s);
+}
+
+template <typename T>
+void launch_coarse_dense(int n, const int32_t* idx, const T* Ainv, const T* x, T* y, T* tmp, int64_t n_dof,
+                         hipStream_t st) {
+  launch_fill<T>(y, T(0), n_dof, st);
+  hipLaunchKernelGGL((k_gather_idx<T>), dim3((n + 255) / 256), dim3(256), 0, st, n, idx, x, tmp);
+  hipLaunchKernelGGL((k_gemv_rows<T>), dim3((n + 3) / 4), dim3(256), 0, st, n, idx, Ainv, tmp, y);
+}
+template void launch_coarse_dense<double>(int, const int32_t*, const double*, const double*, double*, double*, int64_t, hipStream_t);
+template void launch_coarse_dense<float>(int, const int32_t*, const float*, const float*, float*, float*, int64_t, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// vector kernels
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(T* x, T v, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) x[i] = v;
+}
+template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(grid_for(n)), dim3(256), 0, st, x, v, n);
+}
+template <typename T>
+__global__ void k_copy(const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) y[i] = x[i];
+}
+template <typename T> void launch_copy(const T* x, T* y, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_copy<T>), dim3(grid_for(n)), dim3(256), 0, st, x, y, n);
+}
+template <typename T>
+__global__ void k_scale_diag(const T* __restrict__ d, const T* __restrict__ x, T* __restrict__ y, T w, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) y[i] = w * d[i] * x[i];
+}
+template <typename T>
+void launch_scale_diag(const T* d, const T* x, T* y, double omega, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_scale_diag<T>), dim3(grid_for(n)), dim3(256), 0, st, d, x, y, T(omega), n);
+}
+template <typename Ts, typename Td>
+__global__ void k_cast(const Ts* __restrict__ x, Td* __restrict__ y, double s, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    y[i] = Td(double(x[i]) * s);
+}
+template <typename Ts, typename Td>
+void launch_cast(const Ts* x, Td* y, double scale, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_cast<Ts, Td>), dim3(grid_for(n)), dim3(256), 0, st, x, y, scale, n);
+}
+template <typename T>
+__global__ __launch_bounds__(256) void k_dot(const T* __restrict__ x, const T* __restrict__ y, int64_t n,
+                                             double* __restrict__ partial) {
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    acc += double(x[i]) * double(y[i]);
+  const double b = block_sum256(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+template <typename T>
+void launch_dot(const T* x, const T* y, int64_t n, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL((k_dot<T>), dim3(RED_BLOCKS), dim3(256), 0, st, x, y, n, partial);
+}
+template <typename T>
+__global__ void k_dinv(int64_t n, int nz, const uint8_t* __restrict__ dir2d, int top_dir,
+                       const double* __restrict__ diag, T* __restrict__ dinv) {
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
+    const int64_t g2 = g / nz;
+    const int z = int(g - g2 * nz);
+    const bool dir = dir2d[g2] || (top_dir && z == nz - 1);
+    dinv[g] = dir ? T(0) : T(1.0 / diag[g]);
+  }
+}
+template <typename T>
+void launch_dinv(const LevelView& lv, const T*, const double* diag, T* dinv, hipStream_t st) {
+  hipLaunchKernelGGL((k_dinv<T>), dim3(grid_for(lv.n_dof)), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.dir2d,
+                     lv.top_dir, diag, dinv);
+}
+
+__global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ partial, double* __restrict__ scal,
+                                                  int slot, int op) {
+  double a = 0.0, b = 0.0;
+  for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) a += partial[i];
+  if (op == FIN_BETA_PR)
+    for (int i = threadIdx.x; i < RED_BLOCKS; i += 256) b += partial[RED_BLOCKS + i];
+  const double sa = block_sum256(a);
+  const double sb = block_sum256(b);
+  if (threadIdx.x == 0) {
+    if (op == FIN_SET) {
+      scal[slot] = sa;
+    } else if (op == FIN_ALPHA) {
+      scal[S_PQ] = sa;
+      scal[S_ALPHA] = scal[S_DELTA] / sa;
+    } else if (op == FIN_BETA_FR) {
+      scal[S_ZR] = sa;
+      scal[S_BETA] = sa / scal[S_DELTA];
+      scal[S_DELTA] = sa;
+    } else if (op == FIN_BETA_PR) {
+      scal[S_ZR] = sa;
+      scal[S_BETA] = (sa - sb) / scal[S_DELTA];
+      scal[S_DELTA] = sa;
+    } else if (op == FIN_DELTA) {
+      scal[S_DELTA] = sa;
+      scal[S_ZR] = sa;
+    }
+  }
+}
+void launch_finalize(const double* partial, double* scal, int slot, int op, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, st, partial, scal, slot, op);
+}
+
+__global__ __launch_bounds__(256) void k_cg_update(double* __restrict__ u, double* __restrict__ r,
+                                                   const double* __restrict__ p, const double* __restrict__ q,
+                                                   const double* __restrict__ scal, double* __restrict__ partial,
+                                                   int64_t n) {
+  const double alpha = scal[S_ALPHA];
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    u[i] += alpha * p[i];
+    const double rn = r[i] - alpha * q[i];
+    r[i] = rn;
+    acc += rn * rn;
+  }
+  const double b = block_sum256(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+void launch_cg_update(double* u, double* r, const double* p, const double* q, const double* scal,
+                      double* partial, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_update, dim3(RED_BLOCKS), dim3(256), 0, st, u, r, p, q, scal, partial, n);
+}
+__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ scal,
+                         int64_t n) {
+  const double beta = scal[S_BETA];
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    p[i] = z[i] + beta * p[i];
+}
+void launch_cg_dir(double* p, const double* z, const double* scal, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(n)), dim3(256), 0, st, p, z, scal, n);
+}
+__global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) y[i] += a * x[i];
+}
+void launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy, dim3(grid_for(n)), dim3(256), 0, st, y, x, a, n);
+}
+__global__ __launch_bounds__(256) void k_resid_norm(double* __restrict__ r, const double* __restrict__ f,
+                                                    const double* __restrict__ y, double* __restrict__ partial,
+                                                    int64_t n) {
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const double v = f[i] - y[i];
+    r[i] = v;
+    acc += v * v;
+  }
+  const double b = block_sum256(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+void launch_resid_norm(double* r, const double* f, const double* y, double* partial, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid_norm, dim3(RED_BLOCKS), dim3(256), 0, st, r, f, y, partial, n);
+}
+__global__ void k_lift(int64_t n, int nz, const uint8_t* __restrict__ dir2d, int top_dir,
+                       const double* __restrict__ surf, const double* __restrict__ bc, double* __restrict__ out) {
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
+    const int64_t g2 = g / nz;
+    const int z = int(g - g2 * nz);
+    const bool top = top_dir && z == nz - 1;
+    const bool dir = dir2d[g2] || top;
+    double v = 0.0;
+    if (dir) v = bc ? bc[g] : (top && surf ? surf[g2] : 0.0);
+    out[g] = v;
+  }
+}
+void launch_lift(const LevelView& lv, const double* surf, const double* bc, double* phiD, hipStream_t st) {
+  hipLaunchKernelGGL(k_lift, dim3(grid_for(lv.n_dof)), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.dir2d,
+                     lv.top_dir, surf, bc, phiD);
+}
+__global__ void k_merge_free(int64_t n, int nz, const uint8_t* __restrict__ dir2d, int top_dir,
+                             const double* __restrict__ a, const double* __restrict__ b, double* __restrict__ out) {
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
+    const int64_t g2 = g / nz;
+    const int z = int(g - g2 * nz);
+    const bool dir = dir2d[g2] || (top_dir && z == nz - 1);
+    out[g] = dir ? (b ? b[g] : 0.0) : a[g];
+  }
+}
+void launch_merge_free(const LevelView& lv, const double* a, const double* b, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_merge_free, dim3(grid_for(lv.n_dof)), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.dir2d,
+                     lv.top_dir, a, b, out);
+}
+__global__ __launch_bounds__(256) void k_nonfinite(const double* __restrict__ x, int64_t n, double* __restrict__ partial) {
+  double acc = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    acc += isfinite(x[i]) ? 0.0 : 1.0;
+  const double b = block_sum256(acc);
+  if (threadIdx.x == 0) partial[blockIdx.x] = b;
+}
+void launch_count_nonfinite(const double* x, int64_t n, double* partial, hipStream_t st) {
+  hipLaunchKernelGGL(k_nonfinite, dim3(RED_BLOCKS), dim3(256), 0, st, x, n, partial);
+}
+
+template void launch_fill<double>(double*, double, int64_t, hipStream_t);
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+template void launch_copy<double>(const double*, double*, int64_t, hipStream_t);
+template void launch_copy<float>(const float*, float*, int64_t, hipStream_t);
+template void launch_scale_diag<double>(const double*, const double*, double*, double, int64_t, hipStream_t);
+template void launch_scale_diag<float>(const float*, const float*, float*, double, int64_t, hipStream_t);
+template void launch_cast<double, float>(const double*, float*, double, int64_t, hipStream_t);
+template void launch_cast<float, double>(const float*, double*, double, int64_t, hipStream_t);
+template void launch_cast<double, double>(const double*, double*, double, int64_t, hipStream_t);
+template void launch_dot<double>(const double*, const double*, int64_t, double*, hipStream_t);
+template void launch_dot<float>(const float*, const float*, int64_t, double*, hipStream_t);
+template void launch_dinv<double>(const LevelView&, const double*, const double*, double*, hipStream_t);
+template void launch_dinv<float>(const LevelView&, const float*, const double*, float*, hipStream_t);
+
+}  // namespace pmg
+
+namespace pmg {
+__global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ x, const double* __restrict__ y1,
+                                              const double* __restrict__ y2, int64_t n,
+                                              double* __restrict__ partial) {
+  double a = 0.0, b = 0.0;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    a += x[i] * y1[i];
+    b += x[i] * y2[i];
+  }
+  const double sa = block_sum256(a);
+  const double sb = block_sum256(b);
+  if (threadIdx.x == 0) {
+    partial[blockIdx.x] = sa;
+    partial[RED_BLOCKS + blockIdx.x] = sb;
+  }
+}
+void launch_dot2(const double* x, const double* y1, const double* y2, int64_t n, double* partial,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_dot2, dim3(RED_BLOCKS), dim3(256), 0, st, x, y1, y2, n, partial);
+}
+}  // namespace pmg
+
+namespace pmg {
+template <typename T>
+__global__ void k_mask(int64_t n, int nz, const uint8_t* __restrict__ dir2d, int top_dir, const T* __restrict__ x,
+                       T* __restrict__ out) {
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
+    const int64_t g2 = g / nz;
+    const int z = int(g - g2 * nz);
+    const bool dir = dir2d[g2] || (top_dir && z == nz - 1);
+    out[g] = dir ? T(0) : x[g];
+  }
+}
+template <typename T>
+void launch_mask(const LevelView& lv, const T* x, T* out, hipStream_t st) {
+  hipLaunchKernelGGL((k_mask<T>), dim3(grid_for(lv.n_dof)), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.dir2d,
+                     lv.top_dir, x, out);
+}
+template void launch_mask<double>(const LevelView&, const double*, double*, hipStream_t);
+template void launch_mask<float>(const LevelView&, const float*, float*, hipStream_t);
+}  // namespace pmg

@@ -1,0 +1,117 @@
+// Launchers of the device kernels (gfx950).  Every pointer is device memory
+// unless stated; every launch is enqueued on the given stream.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pmg {
+
+typedef uint16_t bf16_t;  // bfloat16 storage (upper half of an IEEE float)
+
+enum GStore { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
+
+// Reduction buffer: fixed grid so the summation order never changes.
+constexpr int RED_BLOCKS = 512;
+
+// Scalar slots of the Krylov loop (device double array of size N_SCAL).
+enum Scal {
+  S_DELTA = 0, S_PQ, S_ALPHA, S_RR, S_ZR, S_BETA, S_FF, S_TMP0, S_TMP1, S_ZRO, S_NF, N_SCAL = 16
+};
+
+// Per-level device description.
+struct LevelView {
+  int P, L, nt;
+  int np_tri, np, nq;
+  int64_t n2d, nz, n_dof, n_elem;
+  const int32_t* map2d;    // [nt][np_tri]
+  const int32_t* inc_ptr;  // [n2d+1]
+  const int32_t* inc;      // [nnz] = t*np_tri + a
+  const uint8_t* dir2d;    // [n2d] lateral Dirichlet columns
+  int top_dir;             // surface nodes are Dirichlet
+};
+
+// ---- element operator: Y_E = blockdiag(A_e) Q u (E-layout [t][a][layer][c])
+template <typename T>
+void launch_ax(const LevelView& lv, const T* mats, const void* G, int gstore, const T* u, T* Y,
+               hipStream_t st);
+
+// ---- direct-stiffness sum of an E-layout vector (atomic-free, node-centric)
+enum AsmOp {
+  OP_STORE = 0,     // out = mask * sum
+  OP_AVG_ADD = 1,   // out += mask * sum / multiplicity
+  OP_RESID = 2,     // out = mask * (a1 - sum)
+  OP_JACOBI = 3,    // out += omega * a2 * (a1 - sum)      (a2 = masked D^-1)
+  OP_STORE_DOT = 4, // out = mask * sum; partial += a1 . out
+  OP_AVG_STORE = 5, // out = mask * sum / multiplicity
+  OP_CHEB = 6,      // Chebyshev step on (x=out, r=a1, d=a3): r -= sum; x += d_new ...
+  OP_RAW = 7        // out = sum (no mask)
+};
+template <typename T>
+void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a1, const T* a2,
+                     T* a3, double omega, double c1, double* partial, hipStream_t st);
+
+// ---- geometric factors at level cubature from the fine isoparametric map
+void launch_geom(const LevelView& fine, const LevelView& lvl, double depth, const double* xyt,
+                 const double* eta, const double* gmats, const double* wq, const double* zq,
+                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st);
+
+// ---- diagonal of the element matrices (E-layout), FP64
+void launch_diag(const LevelView& lv, const double* mats, const double* G64, double* Y, hipStream_t st);
+
+// ---- transfers between level f and the next coarser level c (E-layout output)
+template <typename T>
+void launch_prolong_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz,
+                         const T* uc, T* Yf, hipStream_t st);
+template <typename T>
+void launch_restrict_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz,
+                          const T* rf, T* Yc, hipStream_t st);
+
+// ---- coarse exact solve: y[idx[i]] = sum_j Ainv[i][j] x[idx[j]], y zero elsewhere
+template <typename T>
+void launch_coarse_dense(int n, const int32_t* idx, const T* Ainv, const T* x, T* y, T* tmp,
+                         int64_t n_dof, hipStream_t st);
+
+// ---- vector kernels
+template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
+template <typename T> void launch_copy(const T* x, T* y, int64_t n, hipStream_t st);
+template <typename T>  // y = omega * d .* x
+void launch_scale_diag(const T* d, const T* x, T* y, double omega, int64_t n, hipStream_t st);
+template <typename Ts, typename Td>  // y = (Td)(x * scale)
+void launch_cast(const Ts* x, Td* y, double scale, int64_t n, hipStream_t st);
+template <typename T>  // partial[b] = sum x.y
+void launch_dot(const T* x, const T* y, int64_t n, double* partial, hipStream_t st);
+template <typename T>
+void launch_dinv(const LevelView& lv, const T* diag_src_unused, const double* diag, T* dinv,
+                 hipStream_t st);
+
+// finalize: reduce partial into scal[slot] (optionally sets derived scalars)
+enum FinOp { FIN_SET = 0, FIN_ALPHA = 1, FIN_BETA_FR = 2, FIN_BETA_PR = 3, FIN_DELTA = 4 };
+void launch_finalize(const double* partial, double* scal, int slot, int op, hipStream_t st);
+
+// PCG vector updates (FP64)
+// u += alpha p; r -= alpha q; partial = ||r||^2    (alpha = scal[S_ALPHA])
+void launch_cg_update(double* u, double* r, const double* p, const double* q, const double* scal,
+                      double* partial, int64_t n, hipStream_t st);
+// p = z + beta p (beta = scal[S_BETA])
+void launch_cg_dir(double* p, const double* z, const double* scal, int64_t n, hipStream_t st);
+// u += z ; partial of nothing
+void launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
+// r = f - y (masked by a2 != 0 when mask given) ; partial ||r||^2
+void launch_resid_norm(double* r, const double* f, const double* y, double* partial, int64_t n,
+                       hipStream_t st);
+// Dirichlet lifting: phiD at Dirichlet nodes from surf (per 2D node) or bc (full), zero elsewhere
+void launch_lift(const LevelView& lv, const double* surf, const double* bc, double* phiD,
+                 hipStream_t st);
+// out = where(free, a, b)
+void launch_merge_free(const LevelView& lv, const double* a, const double* b, double* out,
+                       hipStream_t st);
+// partial[0..RED_BLOCKS) = x.y1, partial[RED_BLOCKS..) = x.y2
+void launch_dot2(const double* x, const double* y1, const double* y2, int64_t n, double* partial,
+                 hipStream_t st);
+// out = x on free nodes, 0 on Dirichlet nodes
+template <typename T> void launch_mask(const LevelView& lv, const T* x, T* out, hipStream_t st);
+// non-finite count into partial (as double)
+void launch_count_nonfinite(const double* x, int64_t n, double* partial, hipStream_t st);
+
+}  // namespace pmg

@@ -1,0 +1,1136 @@
+// libpmg: host orchestration and C-ABI (see include/pmg.h).
+//
+// The context owns, per level l (order P_l = P, floor(P/2), ..., 1 on one
+// mesh, Sec. 5): numbering and incidence lists, reference matrices, the
+// geometric factors G_l (FP64 plus FP32 and BF16 copies for the mixed
+// preconditioner), the Jacobi diagonal, the transfer matrices to level l+1,
+// and work vectors.  The V-cycle follows Alg. 1; the outer iterations follow
+// Alg. 2 and Alg. 3 of the paper.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.hpp"
+#include "mesh.hpp"
+#include "pmg.h"
+#include "refelem.hpp"
+
+namespace pmg {
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHK(expr)                                                                           \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      throw Error(e_ == hipErrorOutOfMemory ? PMG_ENOMEM : PMG_EDEVICE,                        \
+                  std::string(#expr) + ": " + hipGetErrorString(e_));                          \
+  } while (0)
+
+template <typename T>
+static T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  HIPCHK(hipMalloc(&p, n * sizeof(T)));
+  return static_cast<T*>(p);
+}
+template <typename T>
+static T* dupload(const std::vector<T>& h) {
+  T* p = dalloc<T>(h.size());
+  if (!h.empty()) HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return p;
+}
+static std::vector<float> to_f32(const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); }
+
+// splitmix64 counter generator: unit(i) = top 53 bits of splitmix64(seed + (i+1)*golden)
+static double splitmix_unit(uint64_t seed, uint64_t i) {
+  uint64_t z = seed + (i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  return double(z >> 11) * (1.0 / 9007199254740992.0);
+}
+
+struct Level {
+  int P = 0;
+  std::unique_ptr<RefElem> re;
+  Numbering num;
+  std::vector<uint8_t> dir2d_h;
+  int64_t n_free = 0;
+  int top_dir = 1;
+  // device
+  int32_t *map2d = nullptr, *inc_ptr = nullptr, *inc = nullptr;
+  uint8_t* dir2d = nullptr;
+  double* mats64 = nullptr;
+  float* mats32 = nullptr;
+  double *gmats = nullptr, *wq = nullptr, *zq = nullptr, *zw = nullptr;
+  double* G64 = nullptr;
+  float* G32 = nullptr;
+  bf16_t* G16 = nullptr;
+  double *diag = nullptr, *dinv64 = nullptr;
+  float* dinv32 = nullptr;
+  double *f64 = nullptr, *u64 = nullptr, *r64 = nullptr;
+  float *f32 = nullptr, *u32 = nullptr, *r32 = nullptr;
+  double *pit64 = nullptr, *piz64 = nullptr;  // transfer to the next coarser level
+  float *pit32 = nullptr, *piz32 = nullptr;
+  double omega = 0.0;
+  double omega_user = 0.0;
+  LevelView view{};
+
+  template <typename T> T* f();
+  template <typename T> T* u();
+  template <typename T> T* r();
+  template <typename T> T* dinv();
+  template <typename T> T* mats();
+  template <typename T> T* pit();
+  template <typename T> T* piz();
+};
+template <> double* Level::f<double>() { return f64; }
+template <> float* Level::f<float>() { return f32; }
+template <> double* Level::u<double>() { return u64; }
+template <> float* Level::u<float>() { return u32; }
+template <> double* Level::r<double>() { return r64; }
+template <> float* Level::r<float>() { return r32; }
+template <> double* Level::dinv<double>() { return dinv64; }
+template <> float* Level::dinv<float>() { return dinv32; }
+template <> double* Level::mats<double>() { return mats64; }
+template <> float* Level::mats<float>() { return mats32; }
+template <> double* Level::pit<double>() { return pit64; }
+template <> float* Level::pit<float>() { return pit32; }
+template <> double* Level::piz<double>() { return piz64; }
+template <> float* Level::piz<float>() { return piz32; }
+
+}  // namespace pmg
+
+struct pmg_ctx {
+  std::string err;
+  pmg::MeshIn mesh;
+  pmg_options opt{};
+  int nl = 0;
+  int device = 0;
+  bool host_only = false;
+  std::vector<pmg::Level> lv;
+  std::vector<double> xyt_h;  // fine triangle-node xy [nt][NPT][2]
+  std::vector<double> eta_h;  // current surface (host copy)
+  double* xyt = nullptr;
+  double* eta = nullptr;
+  int* bad = nullptr;
+  double* Y = nullptr;        // E-layout work buffer (bytes for max E*Np doubles)
+  double* partial = nullptr;  // 2*RED_BLOCKS
+  double* scal = nullptr;     // N_SCAL
+  double* scal_h = nullptr;   // pinned mirror
+  // coarse solve
+  int nc = 0;
+  int32_t* cidx = nullptr;
+  double* cinv64 = nullptr;
+  float* cinv32 = nullptr;
+  double* ctmp64 = nullptr;
+  float* ctmp32 = nullptr;
+  double cheb_lmin = 0, cheb_lmax = 0;
+  bool coarse_exact = true;
+  // solve work (finest level)
+  double *s_phiD = nullptr, *s_f = nullptr, *s_u = nullptr, *s_r = nullptr, *s_p = nullptr, *s_q = nullptr,
+         *s_z = nullptr, *s_rold = nullptr, *s_y = nullptr;
+  float *s_r32 = nullptr, *s_z32 = nullptr;
+  int lowp = pmg::G_F32;      // G storage of the float V-cycle
+  int n_vcycles = 0, n_fine_applies = 0;
+  std::vector<void*> allocs;
+
+  template <typename T> T* A(size_t n) {
+    T* p = pmg::dalloc<T>(n);
+    allocs.push_back(p);
+    return p;
+  }
+  template <typename T> T* U(const std::vector<T>& h) {
+    T* p = pmg::dupload<T>(h);
+    allocs.push_back(p);
+    return p;
+  }
+  ~pmg_ctx() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (scal_h) (void)hipHostFree(scal_h);
+  }
+};
+
+namespace pmg {
+
+static thread_local std::string g_err;
+
+// ---------------------------------------------------------------------------
+// setup
+// ---------------------------------------------------------------------------
+static std::vector<double> pack_mats(const RefElem& re) {
+  std::vector<double> m;
+  m.insert(m.end(), re.Dr.v.begin(), re.Dr.v.end());
+  m.insert(m.end(), re.Ds.v.begin(), re.Ds.v.end());
+  m.insert(m.end(), re.B.v.begin(), re.B.v.end());
+  m.insert(m.end(), re.Bz.v.begin(), re.Bz.v.end());
+  m.insert(m.end(), re.Dz.v.begin(), re.Dz.v.end());
+  return m;
+}
+
+static void build_levels(pmg_ctx* c) {
+  const pmg_options& o = c->opt;
+  std::vector<int> orders{o.P};
+  while (orders.back() > 1) orders.push_back(std::max(1, orders.back() / 2));
+  c->nl = int(orders.size());
+  c->lv.resize(c->nl);
+  for (int i = 0; i < c->nl; ++i) {
+    Level& L = c->lv[i];
+    L.P = orders[i];
+    L.re.reset(new RefElem(L.P));
+    L.num.build(c->mesh, L.P);
+    L.dir2d_h = lateral_dirichlet(c->mesh, L.num, o.dirichlet_tags);
+    L.top_dir = o.top_neumann ? 0 : 1;
+    int64_t nd = 0;
+    for (int64_t g2 = 0; g2 < L.num.n2d; ++g2)
+      nd += L.dir2d_h[g2] ? L.num.nz : (L.top_dir ? 1 : 0);
+    L.n_free = L.num.n_dof - nd;
+    L.omega_user = (i < 8) ? o.omega[i] : 0.0;
+  }
+  const RefElem& rf = *c->lv[0].re;
+  c->xyt_h = triangle_node_xy(c->mesh, rf, c->lv[0].num);
+  // check straight/curved triangles are not inverted (flat surface)
+  for (int t = 0; t < c->mesh.nt; ++t) {
+    const int* tv = &c->mesh.tri[3 * t];
+    const double* p0 = &c->mesh.xy[2 * tv[0]];
+    const double* p1 = &c->mesh.xy[2 * tv[1]];
+    const double* p2 = &c->mesh.xy[2 * tv[2]];
+    const double a2 = (p1[0] - p0[0]) * (p2[1] - p0[1]) - (p1[1] - p0[1]) * (p2[0] - p0[0]);
+    if (!(a2 > 0)) throw Error(PMG_EMESH, "triangle " + std::to_string(t) + " is not counter-clockwise");
+  }
+  c->eta_h.assign(size_t(c->lv[0].num.n2d), 0.0);
+}
+
+static void upload_levels(pmg_ctx* c) {
+  const RefElem& rf = *c->lv[0].re;
+  int64_t maxE = 0;
+  for (int i = 0; i < c->nl; ++i) {
+    Level& L = c->lv[i];
+    const RefElem& re = *L.re;
+    L.map2d = c->U(L.num.map2d);
+    L.inc_ptr = c->U(L.num.inc_ptr);
+    L.inc = c->U(L.num.inc);
+    L.dir2d = c->U(L.dir2d_h);
+    std::vector<double> m = pack_mats(re);
+    L.mats64 = c->U(m);
+    L.mats32 = c->U(to_f32(m));
+    // fine basis at this level's cubature (geometry of every level uses the fine map)
+    Mat Bf, Drf, Dsf;
+    rf.tri_eval(re.cr, re.cs, Bf, Drf, Dsf);
+    std::vector<double> gm;
+    gm.insert(gm.end(), Bf.v.begin(), Bf.v.end());
+    gm.insert(gm.end(), Drf.v.begin(), Drf.v.end());
+    gm.insert(gm.end(), Dsf.v.begin(), Dsf.v.end());
+    L.gmats = c->U(gm);
+    L.wq = c->U(re.cw);
+    L.zq = c->U(re.zq);
+    L.zw = c->U(re.zw);
+    const int64_t E = L.num.n_elem, N = L.num.n_dof;
+    L.G64 = c->A<double>(size_t(E) * 6 * re.nq);
+    L.G32 = c->A<float>(size_t(E) * 6 * re.nq);
+    L.G16 = c->A<bf16_t>(size_t(E) * 6 * re.nq);
+    L.diag = c->A<double>(N);
+    L.dinv64 = c->A<double>(N);
+    L.dinv32 = c->A<float>(N);
+    L.r64 = c->A<double>(N);
+    L.r32 = c->A<float>(N);
+    if (i > 0) {
+      L.f64 = c->A<double>(N);
+      L.u64 = c->A<double>(N);
+      L.f32 = c->A<float>(N);
+      L.u32 = c->A<float>(N);
+    }
+    maxE = std::max(maxE, E * re.np);
+    L.view = LevelView{L.P, L.num.L, L.num.nt, re.np_tri, re.np, re.nq, L.num.n2d, L.num.nz, N, E,
+                       L.map2d, L.inc_ptr, L.inc, L.dir2d, L.top_dir};
+    if (i + 1 < c->nl) {
+      const RefElem& rc = *c->lv[i + 1].re;
+      // coarse nodal basis at the fine nodes
+      Mat Bt, d1, d2;
+      rc.tri_eval(re.r, re.s, Bt, d1, d2);
+      Mat Bz1, dz1;
+      rc.line_eval(re.t, Bz1, dz1);
+      L.pit64 = c->U(Bt.v);
+      L.piz64 = c->U(Bz1.v);
+      L.pit32 = c->U(to_f32(Bt.v));
+      L.piz32 = c->U(to_f32(Bz1.v));
+    }
+  }
+  c->Y = c->A<double>(size_t(maxE));
+  c->partial = c->A<double>(2 * RED_BLOCKS);
+  c->scal = c->A<double>(N_SCAL);
+  HIPCHK(hipHostMalloc((void**)&c->scal_h, N_SCAL * sizeof(double), hipHostMallocDefault));
+  c->bad = c->A<int>(1);
+  c->xyt = c->U(c->xyt_h);
+  c->eta = c->A<double>(size_t(c->lv[0].num.n2d));
+  HIPCHK(hipMemset(c->eta, 0, sizeof(double) * c->lv[0].num.n2d));
+  const int64_t N = c->lv[0].num.n_dof;
+  c->s_phiD = c->A<double>(N);
+  c->s_f = c->A<double>(N);
+  c->s_u = c->A<double>(N);
+  c->s_r = c->A<double>(N);
+  c->s_p = c->A<double>(N);
+  c->s_q = c->A<double>(N);
+  c->s_z = c->A<double>(N);
+  c->s_rold = c->A<double>(N);
+  c->s_y = c->A<double>(N);
+  c->s_r32 = c->A<float>(N);
+  c->s_z32 = c->A<float>(N);
+}
+
+// ---------------------------------------------------------------------------
+// operator building blocks
+// ---------------------------------------------------------------------------
+template <typename T> static const void* gptr(pmg_ctx* c, Level& L, int& gstore);
+template <> const void* gptr<double>(pmg_ctx*, Level& L, int& gs) { gs = G_F64; return L.G64; }
+template <> const void* gptr<float>(pmg_ctx* c, Level& L, int& gs) {
+  gs = c->lowp;
+  return c->lowp == G_BF16 ? (const void*)L.G16 : (const void*)L.G32;
+}
+
+template <typename T>
+static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
+  Level& L = c->lv[i];
+  int gs;
+  const void* G = gptr<T>(c, L, gs);
+  launch_ax<T>(L.view, L.mats<T>(), G, gs, x, reinterpret_cast<T*>(c->Y), st);
+  if (i == 0 && sizeof(T) == 8) c->n_fine_applies++;
+}
+
+template <typename T>
+static void assemble(pmg_ctx* c, int i, int op, T* out, const T* a1, const T* a2, T* a3, double w, double c1,
+                     hipStream_t st) {
+  launch_assemble<T>(c->lv[i].view, op, reinterpret_cast<const T*>(c->Y), out, a1, a2, a3, w, c1, c->partial, st);
+}
+
+template <typename T>
+static void jacobi_sweep(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
+  Level& L = c->lv[i];
+  ax_elem<T>(c, i, u, st);
+  assemble<T>(c, i, OP_JACOBI, u, f, L.dinv<T>(), nullptr, L.omega, 0.0, st);
+}
+
+static double read_scal(pmg_ctx* c, int slot, hipStream_t st) {
+  HIPCHK(hipMemcpyAsync(c->scal_h, c->scal, N_SCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return c->scal_h[slot];
+}
+
+static double dot_host(pmg_ctx* c, const double* x, const double* y, int64_t n, hipStream_t st) {
+  launch_dot<double>(x, y, n, c->partial, st);
+  launch_finalize(c->partial, c->scal, S_TMP0, FIN_SET, st);
+  return read_scal(c, S_TMP0, st);
+}
+
+// ---------------------------------------------------------------------------
+// coarse solve
+// ---------------------------------------------------------------------------
+template <typename T> static T* cinv(pmg_ctx* c);
+template <> double* cinv<double>(pmg_ctx* c) { return c->cinv64; }
+template <> float* cinv<float>(pmg_ctx* c) { return c->cinv32; }
+template <typename T> static T* ctmp(pmg_ctx* c);
+template <> double* ctmp<double>(pmg_ctx* c) { return c->ctmp64; }
+template <> float* ctmp<float>(pmg_ctx* c) { return c->ctmp32; }
+
+template <typename T>
+static void coarse_solve(pmg_ctx* c, const T* f, T* u, hipStream_t st) {
+  const int i = c->nl - 1;
+  Level& L = c->lv[i];
+  if (c->coarse_exact) {
+    launch_coarse_dense<T>(c->nc, c->cidx, cinv<T>(c), f, u, ctmp<T>(c), L.num.n_dof, st);
+    return;
+  }
+  // Jacobi-preconditioned Chebyshev iteration from zero (three-term recurrence)
+  const int k = std::max(1, c->opt.cheb_degree);
+  const double lmin = c->cheb_lmin, lmax = c->cheb_lmax;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  T* r = L.r<T>();
+  T* d = ctmp<T>(c);
+  const int64_t N = L.num.n_dof;
+  launch_copy<T>(f, r, N, st);
+  launch_scale_diag<T>(L.dinv<T>(), f, d, 1.0 / theta, N, st);  // d0 = D^-1 r / theta
+  launch_copy<T>(d, u, N, st);                                    // x1 = d0
+  double rho = 1.0 / sigma;
+  for (int j = 1; j < k; ++j) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    ax_elem<T>(c, i, d, st);
+    // r -= A d; d = rho_new rho d + 2 rho_new/delta D^-1 r; x += d
+    assemble<T>(c, i, OP_CHEB, u, r, L.dinv<T>(), d, rho_new * rho, 2.0 * rho_new / delta, st);
+    rho = rho_new;
+  }
+}
+
+// power estimate of lambda_max(D^-1 A) on level i (free nodes), 1.05 x Rayleigh quotient
+static double lambda_max(pmg_ctx* c, int i, hipStream_t st) {
+  Level& L = c->lv[i];
+  const int64_t N = L.num.n_dof;
+  std::vector<double> x0(N);
+  for (int64_t g = 0; g < N; ++g) x0[g] = splitmix_unit(c->opt.seed, uint64_t(g));
+  double* x = L.r64;
+  double* y = c->s_y;  // finest-size scratch >= N
+  HIPCHK(hipMemcpyAsync(y, x0.data(), N * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // x0 is a temporary host buffer
+  launch_mask<double>(L.view, y, x, st);
+  for (int it = 0; it < 30; ++it) {
+    ax_elem<double>(c, i, x, st);
+    assemble<double>(c, i, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+    launch_scale_diag<double>(L.dinv64, y, y, 1.0, N, st);
+    const double nrm = std::sqrt(dot_host(c, y, y, N, st));
+    if (!(nrm > 0)) throw Error(PMG_EBREAKDOWN, "power iteration collapsed");
+    launch_cast<double, double>(y, x, 1.0 / nrm, N, st);
+  }
+  ax_elem<double>(c, i, x, st);
+  assemble<double>(c, i, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+  const double xax = dot_host(c, x, y, N, st);
+  launch_scale_diag<double>(L.diag, x, y, 1.0, N, st);
+  const double xdx = dot_host(c, x, y, N, st);
+  return 1.05 * xax / xdx;
+}
+
+// dense inverse of the free-node P=1 matrix (host, from the device G of the level)
+static void coarse_exact_setup(pmg_ctx* c, hipStream_t st) {
+  Level& L = c->lv[c->nl - 1];
+  const RefElem& re = *L.re;
+  const int64_t E = L.num.n_elem, N = L.num.n_dof;
+  const int np = re.np, nq = re.nq, npt = re.np_tri, nqt = re.nq_tri, n1 = re.n1;
+  std::vector<double> G(size_t(E) * 6 * nq);
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipMemcpy(G.data(), L.G64, G.size() * sizeof(double), hipMemcpyDeviceToHost));
+  // free-node index
+  std::vector<int32_t> fidx(N, -1), idx;
+  for (int64_t g = 0; g < N; ++g) {
+    const int64_t g2 = g / L.num.nz;
+    const int z = int(g - g2 * L.num.nz);
+    const bool dir = L.dir2d_h[g2] || (L.top_dir && z == L.num.nz - 1);
+    if (!dir) { fidx[g] = int32_t(idx.size()); idx.push_back(int32_t(g)); }
+  }
+  const int n = int(idx.size());
+  c->nc = n;
+  // reference derivative matrices of the prism (nq x np)
+  std::vector<double> Dp[3];
+  for (int a = 0; a < 3; ++a) Dp[a].assign(size_t(nq) * np, 0.0);
+  for (int k = 0; k < n1; ++k)
+    for (int q = 0; q < nqt; ++q)
+      for (int cc = 0; cc < n1; ++cc)
+        for (int aa = 0; aa < npt; ++aa) {
+          const size_t o = size_t(k * nqt + q) * np + cc * npt + aa;
+          Dp[0][o] = re.Bz(k, cc) * re.Dr(q, aa);
+          Dp[1][o] = re.Bz(k, cc) * re.Ds(q, aa);
+          Dp[2][o] = re.Dz(k, cc) * re.B(q, aa);
+        }
+  std::vector<int32_t> map(size_t(E) * np);
+  L.num.gather_map(map.data());
+  // bandwidth of the free ordering
+  int bw = 0;
+  for (int64_t e = 0; e < E; ++e)
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < np; ++b) {
+        const int fa = fidx[map[e * np + a]], fb = fidx[map[e * np + b]];
+        if (fa >= 0 && fb >= 0) bw = std::max(bw, std::abs(fa - fb));
+      }
+  const int W = bw + 1;
+  std::vector<double> band(size_t(n) * W, 0.0);  // band[i*W + (i-j)] = A(i, j), j <= i
+  const int comp[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  std::vector<double> Ae(size_t(np) * np);
+  for (int64_t e = 0; e < E; ++e) {
+    std::fill(Ae.begin(), Ae.end(), 0.0);
+    const double* Ge = &G[size_t(e) * 6 * nq];
+    for (int p = 0; p < nq; ++p)
+      for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+          const double gab = Ge[comp[a][b] * nq + p];
+          for (int x = 0; x < np; ++x) {
+            const double da = Dp[a][size_t(p) * np + x] * gab;
+            if (da == 0.0) continue;
+            for (int y = 0; y < np; ++y) Ae[x * np + y] += da * Dp[b][size_t(p) * np + y];
+          }
+        }
+    for (int x = 0; x < np; ++x) {
+      const int fi = fidx[map[e * np + x]];
+      if (fi < 0) continue;
+      for (int y = 0; y < np; ++y) {
+        const int fj = fidx[map[e * np + y]];
+        if (fj < 0 || fj > fi) continue;
+        band[size_t(fi) * W + (fi - fj)] += Ae[x * np + y];
+      }
+    }
+  }
+  // banded Cholesky A = L L^T (in place)
+  for (int i = 0; i < n; ++i) {
+    const int j0 = std::max(0, i - bw);
+    for (int j = j0; j <= i; ++j) {
+      double s = band[size_t(i) * W + (i - j)];
+      const int k0 = std::max(j0, j - bw);
+      for (int k = k0; k < j; ++k) s -= band[size_t(i) * W + (i - k)] * band[size_t(j) * W + (j - k)];
+      if (j == i) {
+        if (!(s > 0)) throw Error(PMG_EBREAKDOWN, "coarse matrix not positive definite");
+        band[size_t(i) * W] = std::sqrt(s);
+      } else {
+        band[size_t(i) * W + (i - j)] = s / band[size_t(j) * W];
+      }
+    }
+  }
+  // inverse columns by forward/backward substitution, in parallel
+  std::vector<double> inv(size_t(n) * n, 0.0);
+  unsigned nth = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  std::vector<std::thread> th;
+  for (unsigned tid = 0; tid < nth; ++tid)
+    th.emplace_back([&, tid]() {
+      std::vector<double> y(n);
+      for (int col = int(tid); col < n; col += int(nth)) {
+        std::fill(y.begin(), y.end(), 0.0);
+        for (int i = col; i < n; ++i) {  // L y = e_col
+          double s = (i == col) ? 1.0 : 0.0;
+          const int k0 = std::max(col, i - bw);
+          for (int k = k0; k < i; ++k) s -= band[size_t(i) * W + (i - k)] * y[k];
+          y[i] = s / band[size_t(i) * W];
+        }
+        for (int i = n - 1; i >= 0; --i) {  // L^T x = y
+          double s = y[i];
+          const int k1 = std::min(n - 1, i + bw);
+          for (int k = i + 1; k <= k1; ++k) s -= band[size_t(k) * W + (k - i)] * y[k];
+          y[i] = s / band[size_t(i) * W];
+        }
+        for (int i = 0; i < n; ++i) inv[size_t(i) * n + col] = y[i];
+      }
+    });
+  for (auto& t : th) t.join();
+  // (re)upload
+  if (!c->cidx) {
+    c->cidx = c->U(idx);
+    c->cinv64 = c->A<double>(size_t(n) * n);
+    c->cinv32 = c->A<float>(size_t(n) * n);
+    c->ctmp64 = c->A<double>(std::max<int64_t>(n, N));
+    c->ctmp32 = c->A<float>(std::max<int64_t>(n, N));
+  }
+  HIPCHK(hipMemcpy(c->cinv64, inv.data(), inv.size() * sizeof(double), hipMemcpyHostToDevice));
+  std::vector<float> inv32(inv.begin(), inv.end());
+  HIPCHK(hipMemcpy(c->cinv32, inv32.data(), inv32.size() * sizeof(float), hipMemcpyHostToDevice));
+}
+
+// ---------------------------------------------------------------------------
+// surface / geometry
+// ---------------------------------------------------------------------------
+static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
+  Level& F = c->lv[0];
+  const int64_t n2 = F.num.n2d;
+  HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), st));
+  for (int i = 0; i < c->nl; ++i) {
+    Level& L = c->lv[i];
+    launch_geom(F.view, L.view, c->mesh.depth, c->xyt, eta, L.gmats, L.wq, L.zq, L.zw, L.G64, L.G32, L.G16,
+                c->bad, st);
+  }
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) {
+    // restore the previous surface
+    HIPCHK(hipMemcpyAsync(c->eta, c->eta_h.data(), n2 * sizeof(double), hipMemcpyHostToDevice, st));
+    for (int i = 0; i < c->nl; ++i) {
+      Level& L = c->lv[i];
+      launch_geom(F.view, L.view, c->mesh.depth, c->xyt, c->eta, L.gmats, L.wq, L.zq, L.zw, L.G64, L.G32,
+                  L.G16, c->bad, st);
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    throw Error(PMG_EMESH, "non-positive Jacobian for the given surface (eta <= -depth?)");
+  }
+  if (eta != c->eta) HIPCHK(hipMemcpyAsync(c->eta, eta, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(c->eta_h.data(), c->eta, n2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  // Jacobi diagonals
+  for (int i = 0; i < c->nl; ++i) {
+    Level& L = c->lv[i];
+    launch_diag(L.view, L.mats64, L.G64, c->Y, st);
+    launch_assemble<double>(L.view, OP_RAW, c->Y, L.diag, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
+    launch_dinv<double>(L.view, nullptr, L.diag, L.dinv64, st);
+    launch_dinv<float>(L.view, nullptr, L.diag, L.dinv32, st);
+  }
+  for (int i = 0; i + 1 < c->nl; ++i) {
+    Level& L = c->lv[i];
+    L.omega = L.omega_user > 0 ? L.omega_user : 4.0 / (3.0 * lambda_max(c, i, st));
+  }
+  // coarse solver
+  Level& C = c->lv[c->nl - 1];
+  c->coarse_exact = c->opt.coarse == PMG_COARSE_EXACT;
+  if (c->coarse_exact && C.n_free > c->opt.exact_max)
+    throw Error(PMG_EINVAL, "free coarse size " + std::to_string(C.n_free) + " exceeds exact_max; use the "
+                            "Chebyshev coarse solve");
+  if (c->coarse_exact) {
+    coarse_exact_setup(c, st);
+  } else {
+    if (!c->ctmp64) {
+      c->ctmp64 = c->A<double>(C.num.n_dof);
+      c->ctmp32 = c->A<float>(C.num.n_dof);
+    }
+    c->cheb_lmax = c->opt.cheb_lmax > 0 ? c->opt.cheb_lmax : lambda_max(c, c->nl - 1, st);
+    c->cheb_lmin = c->opt.cheb_lmin > 0 ? c->opt.cheb_lmin : c->cheb_lmax / std::max(1.0001, c->opt.cheb_ratio);
+  }
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// ---------------------------------------------------------------------------
+// V-cycle (Alg. 1) with zero initial guess
+// ---------------------------------------------------------------------------
+template <typename T>
+static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
+  if (i == c->nl - 1) {
+    coarse_solve<T>(c, f, u, st);
+    return;
+  }
+  Level& L = c->lv[i];
+  Level& C = c->lv[i + 1];
+  const int64_t N = L.num.n_dof;
+  if (c->opt.nu1 >= 1) {
+    launch_scale_diag<T>(L.dinv<T>(), f, u, L.omega, N, st);
+    for (int m = 1; m < c->opt.nu1; ++m) jacobi_sweep<T>(c, i, f, u, st);
+  } else {
+    launch_fill<T>(u, T(0), N, st);
+  }
+  T* r = L.r<T>();
+  ax_elem<T>(c, i, u, st);
+  assemble<T>(c, i, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
+  launch_restrict_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), r, reinterpret_cast<T*>(c->Y), st);
+  assemble<T>(c, i + 1, OP_STORE, C.f<T>(), nullptr, nullptr, nullptr, 0, 0, st);
+  vcycle<T>(c, i + 1, C.f<T>(), C.u<T>(), st);
+  launch_prolong_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), C.u<T>(), reinterpret_cast<T*>(c->Y), st);
+  assemble<T>(c, i, OP_AVG_ADD, u, nullptr, nullptr, nullptr, 0, 0, st);
+  for (int m = 0; m < c->opt.nu2; ++m) jacobi_sweep<T>(c, i, f, u, st);
+}
+
+// z = M^-1 r at the finest level in the context's precision (r, z FP64)
+static void precond(pmg_ctx* c, const double* r, double* z, hipStream_t st) {
+  c->n_vcycles++;
+  const int64_t N = c->lv[0].num.n_dof;
+  if (c->opt.precision == PMG_FP64) {
+    vcycle<double>(c, 0, r, z, st);
+    return;
+  }
+  c->lowp = c->opt.precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+  launch_cast<double, float>(r, c->s_r32, 1.0, N, st);
+  vcycle<float>(c, 0, c->s_r32, c->s_z32, st);
+  launch_cast<float, double>(c->s_z32, z, 1.0, N, st);
+}
+
+// y = A_FF x (FP64, finest), partial of p.y when dot_with != nullptr
+static void fine_apply(pmg_ctx* c, const double* x, double* y, const double* dot_with, hipStream_t st) {
+  ax_elem<double>(c, 0, x, st);
+  if (dot_with)
+    assemble<double>(c, 0, OP_STORE_DOT, y, dot_with, nullptr, nullptr, 0, 0, st);
+  else
+    assemble<double>(c, 0, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+}
+
+static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, int guess, const double* const* hist,
+                 double rtol, double atol, int imax, pmg_stats* stats, hipStream_t st) {
+  Level& F = c->lv[0];
+  const int64_t N = F.num.n_dof;
+  (void)hist;
+  if (!surf && !bc) throw Error(PMG_EINVAL, "no Dirichlet data (phi_surf and phi_bc are NULL)");
+  if (!bc && c->opt.dirichlet_tags) throw Error(PMG_EINVAL, "lateral Dirichlet tags need phi_bc");
+  if (!phi) throw Error(PMG_EINVAL, "phi is NULL");
+  if (!(rtol >= 0) || !(atol >= 0) || imax < 0) throw Error(PMG_EINVAL, "bad tolerance");
+  if (guess != PMG_GUESS_GIVEN && guess != PMG_GUESS_ZERO)
+    throw Error(PMG_EINVAL, "guess mode not available");
+  hipEvent_t ev0, ev1;
+  HIPCHK(hipEventCreate(&ev0));
+  HIPCHK(hipEventCreate(&ev1));
+  HIPCHK(hipEventRecord(ev0, st));
+  c->n_vcycles = 0;
+  c->n_fine_applies = 0;
+  // non-finite boundary data
+  launch_count_nonfinite(bc ? bc : surf, bc ? N : F.num.n2d, c->partial, st);
+  launch_finalize(c->partial, c->scal, S_TMP1, FIN_SET, st);
+  if (read_scal(c, S_TMP1, st) != 0.0) throw Error(PMG_ENONFINITE, "non-finite Dirichlet data");
+  // lifting: f = -A phi_D on free nodes
+  launch_lift(F.view, surf, bc, c->s_phiD, st);
+  fine_apply(c, c->s_phiD, c->s_y, nullptr, st);
+  launch_cast<double, double>(c->s_y, c->s_f, -1.0, N, st);
+  const double nf = std::sqrt(dot_host(c, c->s_f, c->s_f, N, st));
+  // initial guess
+  if (guess == PMG_GUESS_GIVEN) {
+    launch_count_nonfinite(phi, N, c->partial, st);
+    launch_finalize(c->partial, c->scal, S_TMP1, FIN_SET, st);
+    if (read_scal(c, S_TMP1, st) != 0.0) throw Error(PMG_ENONFINITE, "non-finite initial guess");
+    launch_merge_free(F.view, phi, nullptr, c->s_u, st);
+  } else {
+    launch_fill<double>(c->s_u, 0.0, N, st);
+  }
+  HIPCHK(hipEventRecord(ev1, st));
+  HIPCHK(hipEventSynchronize(ev1));
+  float tg = 0;
+  HIPCHK(hipEventElapsedTime(&tg, ev0, ev1));
+  // r = f - A u
+  ax_elem<double>(c, 0, c->s_u, st);
+  assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+  std::vector<double> hist_r{std::sqrt(dot_host(c, c->s_r, c->s_r, N, st))};
+  const double tol = rtol * nf + atol;
+  int it = 0;
+  int status = PMG_OK;
+  const int kry = c->opt.krylov;
+  if (kry == PMG_PCG || kry == PMG_FPCG) {
+    if (hist_r.back() > tol && imax > 0) {
+      precond(c, c->s_r, c->s_z, st);
+      launch_copy<double>(c->s_z, c->s_p, N, st);
+      launch_dot<double>(c->s_z, c->s_r, N, c->partial, st);
+      launch_finalize(c->partial, c->scal, 0, FIN_DELTA, st);
+    }
+    while (it < imax && hist_r.back() > tol) {
+      fine_apply(c, c->s_p, c->s_q, c->s_p, st);
+      launch_finalize(c->partial, c->scal, 0, FIN_ALPHA, st);
+      if (kry == PMG_FPCG) launch_copy<double>(c->s_r, c->s_rold, N, st);
+      launch_cg_update(c->s_u, c->s_r, c->s_p, c->s_q, c->scal, c->partial, N, st);
+      launch_finalize(c->partial, c->scal, S_RR, FIN_SET, st);
+      HIPCHK(hipMemcpyAsync(c->scal_h, c->scal, N_SCAL * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      const double pq = c->scal_h[S_PQ], delta = c->scal_h[S_DELTA], rr = c->scal_h[S_RR];
+      if (!(pq > 0) || !(delta > 0)) { status = PMG_EBREAKDOWN; break; }
+      if (!std::isfinite(rr)) { status = PMG_ENONFINITE; break; }
+      hist_r.push_back(std::sqrt(rr));
+      ++it;
+      if (hist_r.back() <= tol || it >= imax) break;
+      precond(c, c->s_r, c->s_z, st);
+      if (kry == PMG_PCG) {
+        launch_dot<double>(c->s_z, c->s_r, N, c->partial, st);
+        launch_finalize(c->partial, c->scal, 0, FIN_BETA_FR, st);
+      } else {
+        launch_dot2(c->s_z, c->s_r, c->s_rold, N, c->partial, st);
+        launch_finalize(c->partial, c->scal, 0, FIN_BETA_PR, st);
+      }
+      launch_cg_dir(c->s_p, c->s_z, c->scal, N, st);
+    }
+  } else if (kry == PMG_PDC || kry == PMG_MG) {
+    while (it < imax && hist_r.back() > tol) {
+      precond(c, c->s_r, c->s_z, st);
+      launch_axpy(c->s_u, c->s_z, 1.0, N, st);
+      ax_elem<double>(c, 0, c->s_u, st);
+      assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+      const double rr = dot_host(c, c->s_r, c->s_r, N, st);
+      if (!std::isfinite(rr)) { status = PMG_ENONFINITE; break; }
+      hist_r.push_back(std::sqrt(rr));
+      ++it;
+    }
+  } else {
+    throw Error(PMG_EINVAL, "unknown krylov method");
+  }
+  // phi = phi_D + u; true relative residual in FP64
+  launch_merge_free(F.view, c->s_u, c->s_phiD, phi, st);
+  ax_elem<double>(c, 0, c->s_u, st);
+  assemble<double>(c, 0, OP_RESID, c->s_y, c->s_f, nullptr, nullptr, 0, 0, st);
+  const double rtrue = std::sqrt(dot_host(c, c->s_y, c->s_y, N, st));
+  HIPCHK(hipEventRecord(ev1, st));
+  HIPCHK(hipEventSynchronize(ev1));
+  float tms = 0;
+  HIPCHK(hipEventElapsedTime(&tms, ev0, ev1));
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  if (status == PMG_OK && hist_r.back() > tol) status = PMG_NOT_CONVERGED;
+  if (stats) {
+    std::memset(stats, 0, sizeof(*stats));
+    stats->iters = it;
+    stats->n_hist = int(std::min<size_t>(hist_r.size(), 512));
+    for (int k = 0; k < stats->n_hist; ++k) stats->res_hist[k] = hist_r[k];
+    stats->rel_res = nf > 0 ? rtrue / nf : 0.0;
+    stats->norm_f = nf;
+    stats->t_solve_ms = tms;
+    stats->t_guess_ms = tg;
+    stats->n_vcycles = c->n_vcycles;
+    stats->n_fine_applies = c->n_fine_applies;
+  }
+  if (status < 0) throw Error(status, status == PMG_EBREAKDOWN ? "breakdown: p^T A p <= 0 or z^T r <= 0"
+                                                               : "non-finite iterate");
+  return status;
+}
+
+// host xyz of level nodes under the current surface (fine isoparametric map)
+static void node_xyz(pmg_ctx* c, int level, double* xyz) {
+  Level& F = c->lv[0];
+  Level& L = c->lv[level];
+  const RefElem& rf = *F.re;
+  const RefElem& rl = *L.re;
+  Mat Bf, d1, d2;
+  rf.tri_eval(rl.r, rl.s, Bf, d1, d2);  // fine basis at level nodes
+  const int nptf = rf.np_tri, nptl = rl.np_tri;
+  std::vector<double> xy2(size_t(L.num.n2d) * 2), eta2(size_t(L.num.n2d));
+  for (int t = 0; t < L.num.nt; ++t)
+    for (int a = 0; a < nptl; ++a) {
+      double x = 0, y = 0, h = 0;
+      for (int b = 0; b < nptf; ++b) {
+        const double w = Bf(a, b);
+        x += w * c->xyt_h[(size_t(t) * nptf + b) * 2];
+        y += w * c->xyt_h[(size_t(t) * nptf + b) * 2 + 1];
+        h += w * c->eta_h[F.num.map2d[size_t(t) * nptf + b]];
+      }
+      const int32_t g2 = L.num.map2d[size_t(t) * nptl + a];
+      if (level == 0) {
+        x = c->xyt_h[(size_t(t) * nptf + a) * 2];
+        y = c->xyt_h[(size_t(t) * nptf + a) * 2 + 1];
+        h = c->eta_h[g2];
+      }
+      xy2[2 * g2] = x;
+      xy2[2 * g2 + 1] = y;
+      eta2[g2] = h;
+    }
+  const double hd = c->mesh.depth;
+  const int Lr = L.num.L, P = L.P;
+  for (int64_t g2 = 0; g2 < L.num.n2d; ++g2)
+    for (int z = 0; z < L.num.nz; ++z) {
+      const int layer = std::min(z / P, Lr - 1);
+      const int cc = z - layer * P;
+      const double sig = (layer + 0.5 * (1.0 + rl.t[cc])) / Lr;
+      const size_t g = size_t(g2) * L.num.nz + z;
+      xyz[3 * g] = xy2[2 * g2];
+      xyz[3 * g + 1] = xy2[2 * g2 + 1];
+      xyz[3 * g + 2] = -hd + sig * (eta2[g2] + hd);
+    }
+}
+
+}  // namespace pmg
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+using namespace pmg;
+
+#define PMG_TRY(ctx, body)                                   \
+  try {                                                      \
+    body;                                                    \
+  } catch (const Error& e) {                                 \
+    if (ctx) (ctx)->err = e.what();                          \
+    g_err = e.what();                                        \
+    return e.code;                                           \
+  } catch (const std::exception& e) {                        \
+    if (ctx) (ctx)->err = e.what();                          \
+    g_err = e.what();                                        \
+    return PMG_EINVAL;                                       \
+  }
+
+static hipStream_t S(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+static void need_device(pmg_ctx* c) {
+  if (c->host_only) throw Error(PMG_ESTATE, "context was created host-only");
+  HIPCHK(hipSetDevice(c->device));
+}
+static void check_level(const pmg_ctx* c, int level) {
+  if (level < 0 || level >= c->nl) throw Error(PMG_EINVAL, "level out of range");
+}
+
+template <typename T>
+static void smooth_t(pmg_ctx* c, int level, int sweeps, const T* f, T* u, hipStream_t st) {
+  for (int m = 0; m < sweeps; ++m) jacobi_sweep<T>(c, level, f, u, st);
+}
+
+template <typename T>
+static void transfer_t(pmg_ctx* c, int level, bool prolong, const T* x, T* y, hipStream_t st) {
+  Level& L = c->lv[level];
+  Level& C = c->lv[level + 1];
+  if (prolong) {
+    launch_prolong_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), x, reinterpret_cast<T*>(c->Y), st);
+    assemble<T>(c, level, OP_AVG_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+  } else {
+    launch_restrict_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), x, reinterpret_cast<T*>(c->Y), st);
+    assemble<T>(c, level + 1, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+  }
+}
+
+extern "C" {
+
+void pmg_options_default(pmg_options* o) {
+  std::memset(o, 0, sizeof(*o));
+  o->P = 6;
+  o->nu1 = 2;
+  o->nu2 = 2;
+  o->precision = PMG_FP64;
+  o->krylov = PMG_PCG;
+  o->coarse = PMG_COARSE_EXACT;
+  o->cheb_degree = 30;
+  o->cheb_ratio = 100.0;
+  o->exact_max = 12000;
+  o->seed = 0;
+}
+
+int pmg_abi_version(void) { return PMG_ABI_VERSION; }
+const char* pmg_global_error(void) { return g_err.c_str(); }
+const char* pmg_last_error(const pmg_ctx* c) { return c ? c->err.c_str() : g_err.c_str(); }
+
+int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
+  pmg_ctx* c = nullptr;
+  try {
+    if (!m || !o || !out) throw Error(PMG_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (o->P < 1 || o->P > 8) throw Error(PMG_EINVAL, "P must be in 1..8");
+    if (m->nv < 3 || m->nt < 1 || !m->xy || !m->tri || m->n_layers < 1 || !(m->depth > 0))
+      throw Error(PMG_EINVAL, "bad mesh sizes");
+    if (o->nu1 < 0 || o->nu2 < 0) throw Error(PMG_EINVAL, "negative sweep count");
+    if (o->precision < 0 || o->precision > 2) throw Error(PMG_EINVAL, "bad precision");
+    if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
+    c = new pmg_ctx();
+    c->opt = *o;
+    c->host_only = o->host_only != 0;
+    MeshIn& mi = c->mesh;
+    mi.nv = m->nv;
+    mi.nt = m->nt;
+    mi.L = m->n_layers;
+    mi.depth = m->depth;
+    mi.xy.assign(m->xy, m->xy + 2 * size_t(m->nv));
+    mi.tri.assign(m->tri, m->tri + 3 * size_t(m->nt));
+    if (m->edge_tag) mi.edge_tag.assign(m->edge_tag, m->edge_tag + 3 * size_t(m->nt));
+    else mi.edge_tag.assign(3 * size_t(m->nt), 0);
+    for (int32_t v : mi.tri)
+      if (v < 0 || v >= m->nv) throw Error(PMG_EINVAL, "triangle vertex id out of range");
+    if (m->ncurved > 0) {
+      if (!m->curved_edge || !m->circle) throw Error(PMG_EINVAL, "curved edges without circle data");
+      mi.curved.assign(m->curved_edge, m->curved_edge + 2 * size_t(m->ncurved));
+      mi.circle.assign(m->circle, m->circle + 3 * size_t(m->ncurved));
+    }
+    build_levels(c);
+    if (!c->host_only) {
+      HIPCHK(hipGetDevice(&c->device));
+      upload_levels(c);
+      set_surface(c, c->eta, nullptr);
+    }
+    *out = c;
+    return PMG_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    delete c;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    delete c;
+    return PMG_EINVAL;
+  }
+}
+
+void pmg_destroy(pmg_ctx* c) {
+  if (!c) return;
+  if (!c->host_only) (void)hipSetDevice(c->device);
+  delete c;
+}
+
+int pmg_n_levels(const pmg_ctx* c) { return c ? c->nl : PMG_EINVAL; }
+
+int pmg_level_info_get(const pmg_ctx* c, int level, pmg_level_info* info) {
+  if (!c || !info) return PMG_EINVAL;
+  PMG_TRY(const_cast<pmg_ctx*>(c), {
+    check_level(c, level);
+    const Level& L = c->lv[level];
+    info->order = L.P;
+    info->np = L.re->np;
+    info->nq = L.re->nq;
+    info->n_dof = L.num.n_dof;
+    info->n_free = L.n_free;
+    info->n_elem = L.num.n_elem;
+    info->n_surface = L.num.n2d;
+    std::vector<int32_t> col = L.num.colours();
+    info->n_colours = col.empty() ? 0 : 1 + *std::max_element(col.begin(), col.end());
+  });
+  return PMG_OK;
+}
+
+int pmg_gather_map(const pmg_ctx* c, int level, int32_t* map) {
+  if (!c || !map) return PMG_EINVAL;
+  PMG_TRY(const_cast<pmg_ctx*>(c), {
+    check_level(c, level);
+    c->lv[level].num.gather_map(map);
+  });
+  return PMG_OK;
+}
+
+int pmg_colours(const pmg_ctx* c, int level, int32_t* colour) {
+  if (!c || !colour) return PMG_EINVAL;
+  PMG_TRY(const_cast<pmg_ctx*>(c), {
+    check_level(c, level);
+    std::vector<int32_t> col = c->lv[level].num.colours();
+    std::copy(col.begin(), col.end(), colour);
+  });
+  return PMG_OK;
+}
+
+int pmg_surface_xy(const pmg_ctx* c, double* xy) {
+  if (!c || !xy) return PMG_EINVAL;
+  const Level& F = c->lv[0];
+  const int npt = F.re->np_tri;
+  for (int t = 0; t < F.num.nt; ++t)
+    for (int a = 0; a < npt; ++a) {
+      const int32_t g2 = F.num.map2d[size_t(t) * npt + a];
+      xy[2 * size_t(g2)] = c->xyt_h[(size_t(t) * npt + a) * 2];
+      xy[2 * size_t(g2) + 1] = c->xyt_h[(size_t(t) * npt + a) * 2 + 1];
+    }
+  return PMG_OK;
+}
+
+int pmg_dirichlet_mask(const pmg_ctx* c, int level, uint8_t* mask) {
+  if (!c || !mask) return PMG_EINVAL;
+  PMG_TRY(const_cast<pmg_ctx*>(c), {
+    check_level(c, level);
+    const Level& L = c->lv[level];
+    for (int64_t g2 = 0; g2 < L.num.n2d; ++g2)
+      for (int z = 0; z < L.num.nz; ++z)
+        mask[g2 * L.num.nz + z] = (L.dir2d_h[g2] || (L.top_dir && z == L.num.nz - 1)) ? 1 : 0;
+  });
+  return PMG_OK;
+}
+
+int pmg_set_surface(pmg_ctx* c, const double* eta, void* stream) {
+  if (!c || !eta) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    set_surface(c, eta, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_node_xyz(pmg_ctx* c, int level, double* xyz) {
+  if (!c || !xyz) return PMG_EINVAL;
+  PMG_TRY(c, {
+    check_level(c, level);
+    node_xyz(c, level, xyz);
+  });
+  return PMG_OK;
+}
+
+int pmg_apply(pmg_ctx* c, int level, int precision, int flags, const void* x, void* y, void* stream) {
+  if (!c || !x || !y) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    check_level(c, level);
+    hipStream_t st = S(stream);
+    Level& L = c->lv[level];
+    if (precision == PMG_FP64) {
+      const double* xin = (const double*)x;
+      if (flags & 1) { launch_mask<double>(L.view, xin, L.r64, st); xin = L.r64; }
+      ax_elem<double>(c, level, xin, st);
+      assemble<double>(c, level, (flags & 1) ? OP_STORE : OP_RAW, (double*)y, nullptr, nullptr, nullptr, 0, 0, st);
+    } else if (precision == PMG_MIXED_FP32 || precision == PMG_MIXED_BF16) {
+      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+      const float* xin = (const float*)x;
+      if (flags & 1) { launch_mask<float>(L.view, xin, L.r32, st); xin = L.r32; }
+      ax_elem<float>(c, level, xin, st);
+      assemble<float>(c, level, (flags & 1) ? OP_STORE : OP_RAW, (float*)y, nullptr, nullptr, nullptr, 0, 0, st);
+    } else {
+      throw Error(PMG_EINVAL, "bad precision");
+    }
+  });
+  return PMG_OK;
+}
+
+int pmg_diagonal(pmg_ctx* c, int level, double* d, void* stream) {
+  if (!c || !d) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    check_level(c, level);
+    launch_copy<double>(c->lv[level].diag, d, c->lv[level].num.n_dof, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_smooth(pmg_ctx* c, int level, int precision, int sweeps, const void* f, void* u, void* stream) {
+  if (!c || !f || !u || sweeps < 0) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    check_level(c, level);
+    if (level == c->nl - 1) throw Error(PMG_EINVAL, "no smoother on the coarsest level");
+    if (precision == PMG_FP64) smooth_t<double>(c, level, sweeps, (const double*)f, (double*)u, S(stream));
+    else {
+      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+      smooth_t<float>(c, level, sweeps, (const float*)f, (float*)u, S(stream));
+    }
+  });
+  return PMG_OK;
+}
+
+int pmg_prolong(pmg_ctx* c, int level, int precision, const void* xc, void* yf, void* stream) {
+  if (!c || !xc || !yf) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    if (level < 0 || level + 1 >= c->nl) throw Error(PMG_EINVAL, "level out of range");
+    if (precision == PMG_FP64) transfer_t<double>(c, level, true, (const double*)xc, (double*)yf, S(stream));
+    else transfer_t<float>(c, level, true, (const float*)xc, (float*)yf, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_restrict(pmg_ctx* c, int level, int precision, const void* xf, void* yc, void* stream) {
+  if (!c || !xf || !yc) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    if (level < 0 || level + 1 >= c->nl) throw Error(PMG_EINVAL, "level out of range");
+    if (precision == PMG_FP64) transfer_t<double>(c, level, false, (const double*)xf, (double*)yc, S(stream));
+    else transfer_t<float>(c, level, false, (const float*)xf, (float*)yc, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_coarse_solve(pmg_ctx* c, int precision, const void* f, void* u, void* stream) {
+  if (!c || !f || !u) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    if (precision == PMG_FP64) coarse_solve<double>(c, (const double*)f, (double*)u, S(stream));
+    else {
+      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+      coarse_solve<float>(c, (const float*)f, (float*)u, S(stream));
+    }
+  });
+  return PMG_OK;
+}
+
+int pmg_vcycle(pmg_ctx* c, int precision, const void* r, void* z, void* stream) {
+  if (!c || !r || !z) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    if (precision == PMG_FP64) vcycle<double>(c, 0, (const double*)r, (double*)z, S(stream));
+    else {
+      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+      vcycle<float>(c, 0, (const float*)r, (float*)z, S(stream));
+    }
+  });
+  return PMG_OK;
+}
+
+int pmg_get_params(const pmg_ctx* c, double* omega, double* lmin, double* lmax) {
+  if (!c) return PMG_EINVAL;
+  if (omega)
+    for (int i = 0; i < c->nl; ++i) omega[i] = c->lv[i].omega;
+  if (lmin) *lmin = c->cheb_lmin;
+  if (lmax) *lmax = c->cheb_lmax;
+  return PMG_OK;
+}
+
+int pmg_set_params(pmg_ctx* c, const double* omega, double lmin, double lmax) {
+  if (!c) return PMG_EINVAL;
+  if (omega)
+    for (int i = 0; i + 1 < c->nl; ++i) {
+      if (!(omega[i] > 0)) return PMG_EINVAL;
+      c->lv[i].omega = omega[i];
+      c->lv[i].omega_user = omega[i];
+    }
+  if (lmax > 0) c->cheb_lmax = lmax;
+  if (lmin > 0) c->cheb_lmin = lmin;
+  return PMG_OK;
+}
+
+int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* phi, int guess_mode,
+              const pmg_net* net, const double* const* hist_phi, double rtol, double atol, int32_t imax,
+              pmg_stats* stats, void* stream) {
+  if (!c) return PMG_EINVAL;
+  (void)net;
+  int rc = PMG_OK;
+  PMG_TRY(c, {
+    need_device(c);
+    rc = solve(c, phi_surf, phi_bc, phi, guess_mode, hist_phi, rtol, atol, imax, stats, S(stream));
+  });
+  return rc;
+}
+
+}  // extern "C"

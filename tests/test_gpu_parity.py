@@ -1,0 +1,158 @@
+"""GPU parity of every hot-path step against the FP64 oracle, through the C-ABI.
+
+Floating-point tolerances: FP64 steps 1e-12 relative to the output's max
+(different summation orders only); the FP64 solve 1e-10 (residual history
+and potential, equal iteration counts).  FP32 steps carry G and vectors
+rounded to 2^-24: 2e-5.  BF16 geometric factors carry 2^-9 relative
+rounding: 1e-2.  Integer maps are bit-exact (tests/test_lib_host.py).
+"""
+import numpy as np
+import pytest
+
+from oracle import krylov as K
+from oracle import mesh as M
+from paper_2009_00705_amd import workloads as W
+
+from gpu_common import dev, host, make_pair, rel_err
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    # name: (mesh factory, P)
+    "c1": (lambda: W.config_mesh("c1"), 4),
+    "box5x5_L3_P6": (lambda: W.box_mesh(5, 3), 6),        # several blocks + ragged tail
+    "cyl_P3": (lambda: W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=3), 3),
+    "box2_L1_P8": (lambda: W.box_mesh(2, 1), 8),
+}
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def pair(request):
+    mk, P = CASES[request.param]
+    h, ctx = make_pair(mk(), P)
+    yield request.param, h, ctx
+    ctx.close()
+
+
+def _rand(n, seed):
+    return W.random_vector(n, seed)
+
+
+def test_operator_fp64_all_levels(pair):
+    name, h, ctx = pair
+    import torch
+    for lvl, lv in enumerate(h.levels):
+        n = lv.num.n_dof
+        x = _rand(n, 10 + lvl)
+        y = torch.empty(n, dtype=torch.float64, device="cuda")
+        ctx.apply(lvl, dev(x), y, "fp64", masked=False)
+        ref = lv.op.apply(x)
+        assert rel_err(host(y), ref) < 1e-12, (name, lvl)
+        ctx.apply(lvl, dev(x), y, "fp64", masked=True)
+        assert rel_err(host(y), lv.A(x)) < 1e-12, (name, lvl)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2)])
+def test_operator_low_precision(pair, prec, tol):
+    name, h, ctx = pair
+    import torch
+    lv = h.levels[0]
+    n = lv.num.n_dof
+    x = _rand(n, 3)
+    y = torch.empty(n, dtype=torch.float32, device="cuda")
+    ctx.apply(0, dev(x, torch.float32), y, prec, masked=True)
+    assert rel_err(host(y), lv.A(x.astype(np.float32).astype(np.float64))) < tol
+
+
+def test_diagonal(pair):
+    name, h, ctx = pair
+    import torch
+    for lvl, lv in enumerate(h.levels):
+        d = torch.empty(lv.num.n_dof, dtype=torch.float64, device="cuda")
+        ctx.diagonal(lvl, d)
+        assert rel_err(host(d), lv.diag) < 1e-12
+
+
+def test_transfers(pair):
+    name, h, ctx = pair
+    import torch
+    for i in range(len(h.levels) - 1):
+        lf, lc = h.levels[i], h.levels[i + 1]
+        xc = np.where(lc.free, _rand(lc.num.n_dof, 20 + i), 0)
+        yf = torch.empty(lf.num.n_dof, dtype=torch.float64, device="cuda")
+        ctx.prolong(i, dev(xc), yf)
+        assert rel_err(host(yf), h.prolong(i, xc)) < 1e-12
+        xf = _rand(lf.num.n_dof, 30 + i)
+        yc = torch.empty(lc.num.n_dof, dtype=torch.float64, device="cuda")
+        ctx.restrict(i, dev(xf), yc)
+        assert rel_err(host(yc), h.restrict(i, xf)) < 1e-12
+
+
+def test_smoother_and_coarse_solve(pair):
+    name, h, ctx = pair
+    import torch
+    lv = h.levels[0]
+    f = np.where(lv.free, _rand(lv.num.n_dof, 40), 0)
+    u = np.where(lv.free, _rand(lv.num.n_dof, 41), 0)
+    ud = dev(u)
+    ctx.smooth(0, dev(f), ud, sweeps=3)
+    assert rel_err(host(ud), h.smooth(0, u, f, 3)) < 1e-12
+    lc = h.levels[-1]
+    fc = np.where(lc.free, _rand(lc.num.n_dof, 42), 0)
+    uc = torch.empty(lc.num.n_dof, dtype=torch.float64, device="cuda")
+    ctx.coarse_solve(dev(fc), uc)
+    assert rel_err(host(uc), h.coarse_solve(fc)) < 1e-11
+
+
+def test_vcycle(pair):
+    name, h, ctx = pair
+    import torch
+    lv = h.levels[0]
+    r = np.where(lv.free, _rand(lv.num.n_dof, 50), 0)
+    z = torch.empty(lv.num.n_dof, dtype=torch.float64, device="cuda")
+    ctx.vcycle(dev(r), z)
+    assert rel_err(host(z), h.vcycle(r)) < 1e-11
+
+
+def _dirichlet(h, ctx, k=1.0):
+    num = h.levels[0].num
+    xyz_o = M.node_xyz(h.mesh, num, h.eta2d)
+    phi_o = W.linear_wave(xyz_o[:, 0], xyz_o[:, 1], xyz_o[:, 2], k)
+    xyz_l = ctx.node_xyz(0)
+    phi_l = W.linear_wave(xyz_l[:, 0], xyz_l[:, 1], xyz_l[:, 2], k)
+    surf_l = phi_l[num.surface_nodes]
+    return phi_o, surf_l
+
+
+@pytest.fixture(scope="module", params=sorted(CASES))
+def solve_pair(request):
+    mk, P = CASES[request.param]
+    h, ctx = make_pair(mk(), P, omega="auto")
+    yield request.param, h, ctx
+    ctx.close()
+
+
+def test_auto_omega_matches_oracle():
+    h, ctx = make_pair(W.config_mesh("c1"), 4, omega="lib")
+    om, _, _ = ctx.params()
+    for i, lv in enumerate(h.levels[:-1]):
+        assert abs(om[i] - lv.omega) < 1e-9 * lv.omega
+    ctx.close()
+
+
+def test_pcg_solve_parity(solve_pair):
+    name, h, ctx = solve_pair
+    import torch
+    phi_o, surf_l = _dirichlet(h, ctx)
+    ref = K.solve(h, phi_o, method="pcg", rtol=1e-10, imax=300)
+    phi = torch.zeros(h.levels[0].num.n_dof, dtype=torch.float64, device="cuda")
+    rc, st = ctx.solve(phi, phi_surf=dev(surf_l), rtol=1e-10, imax=300)
+    assert rc == 0
+    assert st["iters"] == ref.iters
+    np.testing.assert_allclose(st["res_hist"], ref.res_hist, rtol=1e-10 * 10, atol=1e-10 * ref.res_hist[0])
+    assert rel_err(host(phi), ref.phi) < 1e-10
+    assert st["rel_res"] <= 1e-10
+    # a second solve is bitwise identical
+    phi2 = torch.zeros_like(phi)
+    ctx.solve(phi2, phi_surf=dev(surf_l), rtol=1e-10, imax=300)
+    assert torch.equal(phi, phi2)

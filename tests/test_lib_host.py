@@ -1,0 +1,111 @@
+"""Host-side checks of libpmg.so (no GPU): exports, numbering and colouring.
+
+The gather maps and colours of the library are a bit-exact contract with the
+oracle's numbering; node coordinates agree to rounding.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import mesh as M
+from paper_2009_00705_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "pmg.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmg_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2009_00705_amd import pmg
+    L = pmg.lib()
+    names = _header_functions()
+    assert len(names) >= 20
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in pmg.SIGNATURES, f"binding lacks {n}"
+    assert L.pmg_abi_version() == 1
+
+
+def _host_ctx(mesh, P, **kw):
+    from paper_2009_00705_amd import pmg
+    return pmg.Context(mesh, P=P, host_only=1, **kw)
+
+
+MESHES = {
+    "box": lambda: W.box_mesh(3, 2),
+    "cyl": lambda: W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=3),
+}
+
+
+@pytest.mark.parametrize("meshname", sorted(MESHES))
+@pytest.mark.parametrize("P", [1, 2, 3, 4, 6, 8])
+def test_gather_maps_bit_exact(meshname, P):
+    m = MESHES[meshname]()
+    ctx = _host_ctx(m, P)
+    orders = [P]
+    while orders[-1] > 1:
+        orders.append(max(1, orders[-1] // 2))
+    assert ctx.n_levels == len(orders)
+    for lvl, p in enumerate(orders):
+        num = M.Numbering(m, p)
+        info = ctx.levels[lvl]
+        assert info["order"] == p and info["n_dof"] == num.n_dof and info["n_elem"] == num.n_elem
+        assert info["n_surface"] == num.n2d
+        np.testing.assert_array_equal(ctx.gather_map(lvl), num.map.astype(np.int32))
+    ctx.close()
+
+
+@pytest.mark.parametrize("meshname", sorted(MESHES))
+@pytest.mark.parametrize("P", [1, 3])
+def test_colours_bit_exact(meshname, P):
+    m = MESHES[meshname]()
+    ctx = _host_ctx(m, P)
+    np.testing.assert_array_equal(ctx.colours(0), M.Numbering(m, P).colours().astype(np.int32))
+
+
+@pytest.mark.parametrize("meshname", sorted(MESHES))
+def test_surface_xy_and_node_xyz(meshname):
+    m = MESHES[meshname]()
+    P = 4
+    ctx = _host_ctx(m, P)
+    num = M.Numbering(m, P)
+    np.testing.assert_allclose(ctx.surface_xy(), M.unique_xy_2d(m, num), atol=1e-14)
+    np.testing.assert_allclose(ctx.node_xyz(0), M.node_xyz(m, num, np.zeros(num.n2d)), atol=1e-14)
+
+
+def test_dirichlet_mask_and_free_counts():
+    m = W.box_mesh(3, 2)
+    ctx = _host_ctx(m, 3, dirichlet_tags=0b00110)
+    num = M.Numbering(m, 3)
+    lat = M.lateral_dirichlet_2d(m, num, 0b00110)
+    want = np.zeros(num.n_dof, np.uint8)
+    want[num.surface_nodes] = 1
+    for g2 in lat:
+        want[g2 * num.nz:(g2 + 1) * num.nz] = 1
+    np.testing.assert_array_equal(ctx.dirichlet_mask(0), want)
+    assert ctx.levels[0]["n_free"] == int((want == 0).sum())
+
+
+def test_create_rejects_bad_input():
+    from paper_2009_00705_amd import pmg
+    m = W.box_mesh(2, 1)
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.Context(m, P=9, host_only=1)
+    assert e.value.code == -1
+    bad = dict(m)
+    bad["tri"] = m["tri"][:, [0, 2, 1]]       # clockwise triangles
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.Context(bad, P=2, host_only=1)
+    assert e.value.code == -6
+    ctx = pmg.Context(m, P=2, host_only=1)
+    import torch
+    with pytest.raises(pmg.PmgError) as e:   # device call on a host-only context
+        ctx._c(pmg.lib().pmg_set_surface(ctx.h, ctypes.c_void_p(1), None))
+    assert e.value.code == -7
