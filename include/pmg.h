@@ -209,6 +209,20 @@ int pmg_solve(pmg_ctx* ctx, const double* phi_surf, const double* phi_bc, double
               const pmg_net* net, const double* const* hist_phi, double rtol, double atol, int32_t imax,
               pmg_stats* stats, void* stream);
 
+/* Change the preconditioner precision and the outer iteration of later solves
+ * (pmg_precision, pmg_krylov).  The hierarchy is kept. */
+int pmg_set_solver(pmg_ctx* ctx, int precision, int krylov);
+
+/* Kernels that pmg_time_kernel() can time in isolation. */
+enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, PMG_K_RESTRICT = 3,
+                  PMG_K_PROLONG = 4 };
+/* Average duration (ms) of `reps` back-to-back launches of one kernel of
+ * level `level` on `stream`, bracketed by hipEvents on that stream (for
+ * roofline measurement).  The element operator reads the level's work vector;
+ * results are discarded. */
+int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps, double* ms_per_launch,
+                    void* stream);
+
 #ifdef __cplusplus
 }
 #endif

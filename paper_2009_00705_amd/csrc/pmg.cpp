@@ -802,9 +802,9 @@ static void node_xyz(pmg_ctx* c, int level, double* xyz) {
 // ===========================================================================
 using namespace pmg;
 
-#define PMG_TRY(ctx, body)                                   \
+#define PMG_TRY(ctx, ...)                                    \
   try {                                                      \
-    body;                                                    \
+    __VA_ARGS__;                                             \
   } catch (const Error& e) {                                 \
     if (ctx) (ctx)->err = e.what();                          \
     g_err = e.what();                                        \
@@ -1131,6 +1131,70 @@ int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* 
     rc = solve(c, phi_surf, phi_bc, phi, guess_mode, hist_phi, rtol, atol, imax, stats, S(stream));
   });
   return rc;
+}
+
+int pmg_set_solver(pmg_ctx* c, int precision, int krylov) {
+  if (!c || precision < 0 || precision > 2 || krylov < 0 || krylov > 3) return PMG_EINVAL;
+  c->opt.precision = precision;
+  c->opt.krylov = krylov;
+  return PMG_OK;
+}
+
+int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, double* ms, void* stream) {
+  if (!c || !ms || reps < 1) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    check_level(c, level);
+    hipStream_t st = S(stream);
+    Level& L = c->lv[level];
+    const bool f64 = precision == PMG_FP64;
+    c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+    if ((kernel == PMG_K_RESTRICT || kernel == PMG_K_PROLONG) && level + 1 >= c->nl)
+      throw Error(PMG_EINVAL, "no coarser level");
+    launch_fill<double>(L.r64, 1.0, L.num.n_dof, st);
+    launch_fill<float>(L.r32, 1.0f, L.num.n_dof, st);
+    auto one = [&]() {
+      switch (kernel) {
+        case PMG_K_ELEMENT_OP:
+          if (f64) ax_elem<double>(c, level, L.r64, st); else ax_elem<float>(c, level, L.r32, st);
+          break;
+        case PMG_K_ASSEMBLE:
+          if (f64) assemble<double>(c, level, OP_STORE, c->s_y, nullptr, nullptr, nullptr, 0, 0, st);
+          else assemble<float>(c, level, OP_STORE, c->s_z32, nullptr, nullptr, nullptr, 0, 0, st);
+          break;
+        case PMG_K_GEOMETRY:
+          launch_geom(c->lv[0].view, L.view, c->mesh.depth, c->xyt, c->eta, L.gmats, L.wq, L.zq, L.zw, L.G64,
+                      L.G32, L.G16, c->bad, st);
+          break;
+        case PMG_K_RESTRICT:
+          if (f64) launch_restrict_elem<double>(L.view, c->lv[level + 1].view, L.pit64, L.piz64, L.r64, c->Y, st);
+          else launch_restrict_elem<float>(L.view, c->lv[level + 1].view, L.pit32, L.piz32, L.r32,
+                                           reinterpret_cast<float*>(c->Y), st);
+          break;
+        case PMG_K_PROLONG: {
+          Level& C = c->lv[level + 1];
+          if (f64) launch_prolong_elem<double>(L.view, C.view, L.pit64, L.piz64, C.r64, c->Y, st);
+          else launch_prolong_elem<float>(L.view, C.view, L.pit32, L.piz32, C.r32, reinterpret_cast<float*>(c->Y), st);
+          break;
+        }
+        default: throw Error(PMG_EINVAL, "unknown kernel");
+      }
+    };
+    one();  // warm
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    for (int k = 0; k < reps; ++k) one();
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float t = 0;
+    HIPCHK(hipEventElapsedTime(&t, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    *ms = double(t) / reps;
+  });
+  return PMG_OK;
 }
 
 }  // extern "C"

@@ -98,7 +98,10 @@ SIGNATURES = {
     "pmg_get_params": (_I, [_VP, _VP, _VP, _VP]),
     "pmg_set_params": (_I, [_VP, _VP, _D, _D]),
     "pmg_solve": (_I, [_VP, _VP, _VP, _VP, _I, _VP, _VP, _D, _D, C.c_int32, C.POINTER(Stats), _VP]),
+    "pmg_set_solver": (_I, [_VP, _I, _I]),
+    "pmg_time_kernel": (_I, [_VP, _I, _I, _I, _I, C.POINTER(C.c_double), _VP]),
 }
+KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4}
 
 
 def lib():
@@ -275,6 +278,16 @@ class Context:
 
     def vcycle(self, r, z, precision="fp64", stream=None):
         self._c(lib().pmg_vcycle(self.h, PRECISIONS[precision], _dptr(r), _dptr(z), _stream(stream)))
+
+    def set_solver(self, precision="fp64", krylov="pcg"):
+        self._c(lib().pmg_set_solver(self.h, PRECISIONS[precision], KRYLOV[krylov]))
+
+    def time_kernel(self, kernel, level=0, precision="fp64", reps=20, stream=None) -> float:
+        """Average ms per launch of one kernel, timed with hipEvents on the stream."""
+        ms = C.c_double()
+        self._c(lib().pmg_time_kernel(self.h, KERNELS[kernel], level, PRECISIONS[precision], reps,
+                                      C.byref(ms), _stream(stream)))
+        return ms.value
 
     def solve(self, phi, phi_surf=None, phi_bc=None, guess="zero", rtol=1e-8, atol=0.0, imax=500,
               net=None, hist=None, stream=None):
