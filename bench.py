@@ -95,7 +95,9 @@ def main():
     ap.add_argument("--P", type=int, default=6)
     ap.add_argument("--precisions", default="fp64,fp32,bf16")
     ap.add_argument("--rtol", type=float, default=1e-8)
-    ap.add_argument("--coarse-degree", type=int, default=30)
+    ap.add_argument("--coarse-degree", type=int, default=0, help="Chebyshev coarse degree (0: automatic)")
+    ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "jacobi"])
+    ap.add_argument("--nu", type=int, default=0, help="smoothing degree/sweeps (0: 3 Chebyshev, 2 Jacobi)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     a = ap.parse_args()
@@ -114,7 +116,9 @@ def main():
     nc_free = probe.levels[-1]["n_free"]
     probe.close()
     coarse = "exact" if nc_free <= 12000 else "chebyshev"
-    ctx = pmg.Context(mesh, P=a.P, coarse=coarse, cheb_degree=a.coarse_degree)
+    nu = a.nu if a.nu > 0 else (3 if a.smoother == "chebyshev" else 2)
+    ctx = pmg.Context(mesh, P=a.P, coarse=coarse, cheb_degree=a.coarse_degree, smoother=a.smoother,
+                      nu1=nu, nu2=nu)
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
@@ -125,8 +129,8 @@ def main():
     phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
     torch.cuda.synchronize()
     t_setup = time.perf_counter() - t0
-    log(f"[bench] setup {t_setup:.1f}s  N={info0['n_dof']}  E={info0['n_elem']}  coarse={coarse} "
-        f"(free coarse {nc_free})")
+    cinfo = ctx.coarse_info()
+    log(f"[bench] setup {t_setup:.1f}s  N={info0['n_dof']}  E={info0['n_elem']}  coarse={cinfo}")
 
     paths = {}
     for prec in [p for p in a.precisions.split(",") if p]:
@@ -188,7 +192,7 @@ def main():
            "data": "synthetic", "dof_per_s": res["dof_per_s"],
            "config": {"workload": wl_desc, "P": a.P, "levels": [l["order"] for l in ctx.levels],
                       "n_dof": info0["n_dof"], "n_elem": info0["n_elem"], "rtol": a.rtol,
-                      "smoother": "damped Jacobi 2+2", "coarse": coarse,
+                      "smoother": f"{a.smoother} {nu}+{nu}", "coarse": cinfo,
                       "guess": "zero", "precision": best, "krylov": res["krylov"]},
            "paths": paths, "roofline": roof}
     if "fp64" in paths and best != "fp64":

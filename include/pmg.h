@@ -64,6 +64,11 @@ enum pmg_guess { PMG_GUESS_GIVEN = 0, PMG_GUESS_ZERO = 1, PMG_GUESS_LEARNED = 2 
  * iteration on [lmin, lmax] (a linear, symmetric approximation). */
 enum pmg_coarse { PMG_COARSE_EXACT = 0, PMG_COARSE_CHEBYSHEV = 1 };
 
+/* Smoother of eq. sec_form on every non-coarsest level: damped Jacobi
+ * (S^-1 = omega D^-1, nu sweeps) or Chebyshev-accelerated Jacobi (a degree-nu
+ * polynomial in D^-1 A, linear and symmetric, so Alg. 3 applies unchanged). */
+enum pmg_smoother { PMG_SMOOTH_JACOBI = 0, PMG_SMOOTH_CHEBYSHEV = 1 };
+
 typedef struct pmg_ctx pmg_ctx;
 typedef struct pmg_net pmg_net;
 
@@ -93,13 +98,19 @@ typedef struct pmg_options {
   uint32_t dirichlet_tags;/* bit k set: lateral edges tagged k are Dirichlet      */
   int32_t top_neumann;    /* 1: no Dirichlet at the surface (pure Neumann tests) */
   int32_t coarse;         /* pmg_coarse                                          */
-  int32_t cheb_degree;    /* Chebyshev steps of the coarse solve                 */
-  double cheb_lmin, cheb_lmax; /* interval; lmax <= 0: power estimate; lmin <= 0:
-                             lmax / cheb_ratio                                   */
-  double cheb_ratio;
+  int32_t cheb_degree;    /* Chebyshev steps of the coarse solve; <= 0: the degree
+                             giving a 0.1 error reduction over [lmin, lmax]      */
+  double cheb_lmin, cheb_lmax; /* interval of D^-1 A; <= 0: estimated (below)      */
+  double cheb_ratio;      /* > 0: lmax from a power estimate, lmin = lmax/ratio;
+                             <= 0: both from 120 Lanczos steps (0.9 x smallest,
+                             1.05 x largest Ritz value)                          */
   int32_t exact_max;      /* largest free coarse size for the dense inverse      */
   uint64_t seed;          /* counter-based start vector of the power iterations  */
   int32_t host_only;      /* 1: numbering only, no device memory (queries only)  */
+  int32_t kernel_variant; /* 0: MFMA element operator where available, 1: generic */
+  int32_t smoother;       /* pmg_smoother                                         */
+  double smooth_ratio;    /* Chebyshev smoother interval [lambda/ratio, lambda],
+                             lambda = 4/(3 omega) of the level                   */
 } pmg_options;
 
 typedef struct pmg_level_info {
@@ -127,7 +138,8 @@ typedef struct pmg_stats {
 } pmg_stats;
 
 /* Fill `opt` with defaults: P=6, nu1=nu2=2, auto omega, FP64, PCG, exact
- * coarse solve with exact_max=12000, Chebyshev degree 30 and ratio 100. */
+ * coarse solve with exact_max=12000 (Chebyshev: Lanczos interval, automatic
+ * degree). */
 void pmg_options_default(pmg_options* opt);
 
 /* Build the level hierarchy: numbering, gather maps, colouring, reference
@@ -187,6 +199,9 @@ int pmg_restrict(pmg_ctx* ctx, int level, int precision, const void* xf, void* y
 int pmg_coarse_solve(pmg_ctx* ctx, int precision, const void* f, void* u, void* stream);
 /* One V-cycle of Alg. 1 from a zero guess: z = M^-1 r on the finest level. */
 int pmg_vcycle(pmg_ctx* ctx, int precision, const void* r, void* z, void* stream);
+/* Coarse solver in use: mode (pmg_coarse), Chebyshev degree and interval,
+ * free unknowns of the coarsest level. */
+int pmg_coarse_info(const pmg_ctx* ctx, int* mode, int* degree, double* lmin, double* lmax, int64_t* n_free);
 /* Smoothing weights and coarse interval in use. */
 int pmg_get_params(const pmg_ctx* ctx, double* omega /*[n_levels]*/, double* cheb_lmin, double* cheb_lmax);
 int pmg_set_params(pmg_ctx* ctx, const double* omega /*[n_levels] or NULL*/, double cheb_lmin, double cheb_lmax);

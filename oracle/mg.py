@@ -8,7 +8,10 @@
   the fine nodes (Pi = Pi_z (x) Pi_tri), then one value per shared fine node
   (the average over the elements holding it).  Restriction is its transpose
   (eq. rest).
-* Smoother (eq. sec_form with S^-1 = omega D^-1): damped Jacobi.
+* Smoother (eq. sec_form): damped Jacobi, S^-1 = omega D^-1, or a
+  Chebyshev-accelerated Jacobi polynomial of the same degree as the sweep
+  count on [lambda/ratio, lambda] with lambda = 4/(3 omega) (the power
+  estimate of lambda_max(D^-1 A)); both are linear and symmetric.
 * Coarsest level (P = 1): exact solve (dense Cholesky or sparse LU), or a
   fixed-degree Jacobi-preconditioned Chebyshev iteration on a given interval.
 * V-cycle: Alg. 1 with zero initial guess below the top.
@@ -84,7 +87,8 @@ class Hierarchy:
 
     def __init__(self, mesh: dict, P: int, eta2d=None, nu1=2, nu2=2, omega=None,
                  dirichlet_tags: int = 0, top_neumann: bool = False,
-                 coarse: str = "exact", cheb=None, seed: int = 0):
+                 coarse: str = "exact", cheb=None, seed: int = 0,
+                 smoother: str = "jacobi", smooth_ratio: float = 15.0):
         self.mesh = mesh
         self.P = P
         self.orders = level_orders(P)
@@ -109,6 +113,10 @@ class Hierarchy:
                 lv.omega = float(omega)
             else:
                 lv.omega = float(omega[i])
+        if smoother not in ("jacobi", "chebyshev"):
+            raise ValueError(smoother)
+        self.smoother = smoother
+        self.smooth_ratio = float(smooth_ratio)
         self.coarse_mode = coarse
         self.cheb = cheb
         self._coarse_setup()
@@ -172,6 +180,11 @@ class Hierarchy:
     # -- Alg. 1
     def smooth(self, i: int, u: np.ndarray, f: np.ndarray, sweeps: int) -> np.ndarray:
         lv = self.levels[i]
+        if self.smoother == "chebyshev":
+            if sweeps <= 0:
+                return u
+            lmax = 4.0 / (3.0 * lv.omega)
+            return u + chebyshev(lv.A, lv.dinv, f - lv.A(u), sweeps, lmax / self.smooth_ratio, lmax)
         for _ in range(sweeps):
             u = u + lv.omega * lv.dinv * (f - lv.A(u))
         return u

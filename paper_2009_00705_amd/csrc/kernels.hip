@@ -834,3 +834,25 @@ void launch_mask(const LevelView& lv, const T* x, T* out, hipStream_t st) {
 template void launch_mask<double>(const LevelView&, const double*, double*, hipStream_t);
 template void launch_mask<float>(const LevelView&, const float*, float*, hipStream_t);
 }  // namespace pmg
+
+namespace pmg {
+__global__ void k_xpay(double* __restrict__ p, const double* __restrict__ z, double beta, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
+    p[i] = z[i] + beta * p[i];
+}
+void launch_xpay(double* p, const double* z, double beta, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_xpay, dim3(grid_for(n)), dim3(256), 0, st, p, z, beta, n);
+}
+}  // namespace pmg
+
+namespace pmg {
+template <typename T>
+__global__ void k_axpy_t(T* __restrict__ y, const T* __restrict__ x, T a, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) y[i] += a * x[i];
+}
+template <typename T> void launch_axpy_t(T* y, const T* x, double a, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL((k_axpy_t<T>), dim3(grid_for(n)), dim3(256), 0, st, y, x, T(a), n);
+}
+template void launch_axpy_t<double>(double*, const double*, double, int64_t, hipStream_t);
+template void launch_axpy_t<float>(float*, const float*, double, int64_t, hipStream_t);
+}  // namespace pmg

@@ -109,6 +109,10 @@ void launch_merge_free(const LevelView& lv, const double* a, const double* b, do
 // partial[0..RED_BLOCKS) = x.y1, partial[RED_BLOCKS..) = x.y2
 void launch_dot2(const double* x, const double* y1, const double* y2, int64_t n, double* partial,
                  hipStream_t st);
+// y += a x
+template <typename T> void launch_axpy_t(T* y, const T* x, double a, int64_t n, hipStream_t st);
+// p = z + beta p (beta from the host)
+void launch_xpay(double* p, const double* z, double beta, int64_t n, hipStream_t st);
 // out = x on free nodes, 0 on Dirichlet nodes
 template <typename T> void launch_mask(const LevelView& lv, const T* x, T* out, hipStream_t st);
 // non-finite count into partial (as double)

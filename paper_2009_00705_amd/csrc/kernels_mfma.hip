@@ -1,0 +1,500 @@
+// MFMA element operator for the fine levels (gfx950).
+//
+// y_e = sum_{a,b in r,s,t} D_a^T diag(G_ab) D_b u_e for 16 prisms per wave:
+// the 16 prisms are the 16 columns of every MFMA tile.
+//   1. vertical (VALU): W[k][a] = sum_c Bz[k][c] u[c][a],  Wz with Dz
+//   2. triangle (MFMA): [ur|us|ut][q] = [Dr|Ds|B][q][a] x [W|W|Wz][a]
+//      (A operand = reference matrix tile from LDS, B operand = W in registers)
+//   3. pointwise (VALU): (vr, vs, vt) = G (ur, us, ut), G streamed from HBM in
+//      a lane-native order (no padding), result kept in the MFMA registers
+//   4. transposed triangle (MFMA): Yr[a] = sum_q Dr[q][a] vr[q] + Ds[q][a] vs[q],
+//      Yt[a] = sum_q B[q][a] vt[q]; the K index of each step is chosen so that
+//      the B operand is exactly the register the pointwise stage produced
+//   5. vertical transpose (VALU): y[c][a] += Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]
+// Output is the E-layout vector [t][a][layer][c] consumed by the atomic-free
+// node-centric summation kernel.
+//
+// Flavours: FP32 (v_mfma_f32_16x16x4f32), FP64 (v_mfma_f64_16x16x4f64) and
+// BF16 operands with FP32 accumulation (v_mfma_f32_16x16x16bf16_1k).  Output
+// row of lane l = 16*(l/16)... see Row<>: FP32/BF16 hold D[4g+r][j], FP64 holds
+// D[g+4r][j] (g = lane/16, j = lane%16, r = 0..3).
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "kernels_mfma.hpp"
+
+namespace pmg {
+
+typedef float f4_t __attribute__((ext_vector_type(4)));
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+template <int P> struct MD {
+  static constexpr int N1 = P + 1, NPT = (P + 1) * (P + 2) / 2, NQT = N1 * N1, NQ = NQT * N1;
+  static constexpr int NT2 = (NQT + 15) / 16;        // q tiles of 16
+  static constexpr int NTF = NQT / 16;               // full q tiles
+  static constexpr int NQR = NQT - 16 * NTF;         // rows of the remainder tile
+  static constexpr int KS = (NPT + 3) / 4;           // K=4 steps over a
+  static constexpr int KS16 = (NPT + 15) / 16;       // K=16 steps over a
+  static constexpr int NAT = (NPT + 15) / 16;        // a tiles
+};
+
+template <bool F64ROW> __device__ __forceinline__ constexpr int row_of(int g, int r) {
+  return F64ROW ? g + 4 * r : 4 * g + r;
+}
+template <int P, bool F64ROW> constexpr int n_steps4() {
+  int n = 0;
+  for (int t = 0; t < MD<P>::NT2; ++t)
+    for (int r = 0; r < 4; ++r)
+      if (16 * t + (F64ROW ? 4 * r : r) < MD<P>::NQT) ++n;
+  return n;
+}
+
+__device__ __forceinline__ f4_t mfma4(float a, float b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ d4_t mfma4(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma16(s4_t a, s4_t b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ short f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return short(u >> 16);
+}
+template <typename TG> __device__ __forceinline__ float gld(const TG* p, size_t i);
+template <> __device__ __forceinline__ float gld<float>(const float* p, size_t i) { return p[i]; }
+template <> __device__ __forceinline__ float gld<bf16_t>(const bf16_t* p, size_t i) {
+  return __uint_as_float(uint32_t(p[i]) << 16);
+}
+
+// XCD-aware block order: consecutive logical blocks land on one XCD (its L2
+// then holds the shared nodes of neighbouring prisms).
+__device__ __forceinline__ int64_t xcd_block(int nblk) {
+  const int b = blockIdx.x;
+  const int per = nblk / 8;
+  if (per * 8 != nblk) return b;
+  return int64_t(b % 8) * per + b / 8;
+}
+
+// offset of G for (batch, k, m, lane, r) in the lane-native layout; -1 if q >= NQT
+template <int P, bool F64ROW>
+__device__ __forceinline__ int64_t gnat_off(int64_t b, int k, int m, int t, int g, int j, int r) {
+  using D = MD<P>;
+  const int64_t blk = ((b * D::N1 + k) * 6 + m) * (16 * D::NQT);
+  if (t < D::NTF) return blk + t * 256 + (g * 16 + j) * 4 + r;
+  const int row = row_of<F64ROW>(g, r);
+  if (row >= D::NQR) return -1;
+  return blk + D::NTF * 256 + row * 16 + j;
+}
+
+// ---------------------------------------------------------------------------
+// Workgroup = N1 waves on one batch of 16 prisms; wave k owns vertical Gauss
+// level k.  Phase 0 stages u in LDS; phase 1 (per wave) runs stages 1-4 for
+// its k; phase 2 (all threads) does the vertical transpose sum over k from
+// LDS and writes the E-layout output with runs of L*(P+1) contiguous values.
+// ---------------------------------------------------------------------------
+template <int P> struct KS_LDS {
+  using D = MD<P>;
+  static constexpr int U_WORDS = D::N1 * D::NPT * 16;           // U[c][a][el]
+  static constexpr int S_WORDS = D::N1 * 2 * D::NAT * 16 * 16;  // S[k][h][a][el]
+  static constexpr int R_WORDS = U_WORDS > S_WORDS ? U_WORDS : S_WORDS;
+};
+
+// geometric factors of one full tile (lane-native: 4 contiguous values per lane)
+template <typename T, typename TG>
+__device__ __forceinline__ void load_full(const TG* __restrict__ G, int64_t blk, int64_t mst, int t, int lane,
+                                          T (&gv)[6][4]) {
+#pragma unroll
+  for (int m = 0; m < 6; ++m)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gv[m][r] = T(gld_any(G, blk + m * mst + t * 256 + lane * 4 + r));
+}
+// geometric factors of the remainder tile (rows < NQR only)
+template <typename T, int NTF, int NQR, bool F64ROW, typename TG>
+__device__ __forceinline__ void load_rem(const TG* __restrict__ G, int64_t blk, int64_t mst, int g, int j,
+                                         T (&gv)[6][4]) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = row_of<F64ROW>(g, r);
+#pragma unroll
+    for (int m = 0; m < 6; ++m)
+      gv[m][r] = row < NQR ? T(gld_any(G, blk + m * mst + NTF * 256 + row * 16 + j)) : T(0);
+  }
+}
+template <typename T, typename ACC>
+__device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds, ACC& db) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const T ur = dr[r], us = ds[r], ut = db[r];
+    dr[r] = gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut;
+    ds[r] = gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut;
+    db[r] = gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut;
+  }
+}
+
+// FP32 / FP64 flavours (K = 4)
+template <int P, typename T, typename TG, typename ACC, bool F64ROW>
+__global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
+                                                         int64_t n_elem, int64_t n_batch,
+                                                         const TG* __restrict__ Gnat, const T* __restrict__ tab2,
+                                                         const T* __restrict__ tab4, VertMats<T> vm,
+                                                         const T* __restrict__ u, T* __restrict__ Y) {
+  using D = MD<P>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NP = NPT * N1, NT2 = D::NT2, KS = D::KS, NAT = D::NAT;
+  constexpr int NS4 = n_steps4<P, F64ROW>();
+  constexpr int NTAB2 = 3 * NT2 * KS * 64, NTAB4 = 3 * NAT * NS4 * 64;
+  constexpr int NTH = 64 * N1;
+  __shared__ T s2[NTAB2];
+  __shared__ T s4[NTAB4];
+  __shared__ T sR[KS_LDS<P>::R_WORDS];
+  __shared__ T sV[2 * N1 * N1];
+  for (int i = threadIdx.x; i < NTAB2; i += NTH) s2[i] = tab2[i];
+  for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
+  for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  // wave-uniform vertical level: its Bz/Dz row stays in scalar registers
+  const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  T bzk[N1], dzk[N1];
+#pragma unroll
+  for (int c = 0; c < N1; ++c) {
+    bzk[c] = vm.Bz[k * N1 + c];
+    dzk[c] = vm.Dz[k * N1 + c];
+  }
+  const int64_t lb = xcd_block(gridDim.x);
+  for (int64_t b = lb; b < n_batch; b += gridDim.x) {
+    __syncthreads();  // previous batch's phase 2 done with sR
+    // phase 0: U[c][a][el] <- u, item (el, a, c) with c fastest
+    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
+      const int el = i / NP, r = i - el * NP, a = r / N1, c = r - a * N1;
+      const int64_t e = b * 16 + el;
+      T v = T(0);
+      if (e < n_elem) {
+        const int te = int(e / L), layer = int(e - int64_t(te) * L);
+        v = u[int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * P + c];
+      }
+      sR[(c * NPT + a) * 16 + el] = v;
+    }
+    __syncthreads();
+    // phase 1, stage 1: W[k][a], Wz[k][a] for a = 4s + g of element j
+    T w[KS], wz[KS];
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const int a = 4 * s + g;
+      T a0 = 0, a1 = 0;
+      if (a < NPT) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) {
+          const T uv = sR[(c * NPT + a) * 16 + j];
+          a0 += bzk[c] * uv;
+          a1 += dzk[c] * uv;
+        }
+      }
+      w[s] = a0;
+      wz[s] = a1;
+    }
+    __syncthreads();  // every wave has read U; sR becomes S
+    ACC yr[NAT], yt[NAT];
+#pragma unroll
+    for (int at = 0; at < NAT; ++at) { yr[at] = ACC{0, 0, 0, 0}; yt[at] = ACC{0, 0, 0, 0}; }
+    const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
+    constexpr int64_t MST = 16 * D::NQT;
+    T ga[6][4];
+#pragma unroll 1
+    for (int t = 0; t < D::NTF; ++t) {
+      load_full<T>(Gnat, blk, MST, t, lane, ga);
+      ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        dr = mfma4(s2[((0 * NT2 + t) * KS + s) * 64 + lane], w[s], dr);
+        ds = mfma4(s2[((1 * NT2 + t) * KS + s) * 64 + lane], w[s], ds);
+        db = mfma4(s2[((2 * NT2 + t) * KS + s) * 64 + lane], wz[s], db);
+      }
+      pointwise<T, ACC>(ga, dr, ds, db);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int st = 4 * t + r;
+#pragma unroll
+        for (int at = 0; at < NAT; ++at) {
+          yr[at] = mfma4(s4[((0 * NAT + at) * NS4 + st) * 64 + lane], dr[r], yr[at]);
+          yr[at] = mfma4(s4[((1 * NAT + at) * NS4 + st) * 64 + lane], ds[r], yr[at]);
+          yt[at] = mfma4(s4[((2 * NAT + at) * NS4 + st) * 64 + lane], db[r], yt[at]);
+        }
+      }
+    }
+    if constexpr (D::NQR > 0) {
+      constexpr int t = D::NTF;
+      load_rem<T, D::NTF, D::NQR, F64ROW>(Gnat, blk, MST, g, j, ga);
+      ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        dr = mfma4(s2[((0 * NT2 + t) * KS + s) * 64 + lane], w[s], dr);
+        ds = mfma4(s2[((1 * NT2 + t) * KS + s) * 64 + lane], w[s], ds);
+        db = mfma4(s2[((2 * NT2 + t) * KS + s) * 64 + lane], wz[s], db);
+      }
+      pointwise<T, ACC>(ga, dr, ds, db);
+      int st = 4 * D::NTF;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        if (row_of<F64ROW>(0, r) < D::NQR) {
+#pragma unroll
+          for (int at = 0; at < NAT; ++at) {
+            yr[at] = mfma4(s4[((0 * NAT + at) * NS4 + st) * 64 + lane], dr[r], yr[at]);
+            yr[at] = mfma4(s4[((1 * NAT + at) * NS4 + st) * 64 + lane], ds[r], yr[at]);
+            yt[at] = mfma4(s4[((2 * NAT + at) * NS4 + st) * 64 + lane], db[r], yt[at]);
+          }
+          ++st;
+        }
+      }
+    }
+    // S[k][h][a][el]: lane holds a = 16 at + row(g, r) of element j
+#pragma unroll
+    for (int at = 0; at < NAT; ++at)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * at + row_of<F64ROW>(g, r);
+        sR[((k * 2 + 0) * NAT * 16 + a) * 16 + j] = yr[at][r];
+        sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
+      }
+    __syncthreads();
+    // phase 2: y[el][c][a] = sum_k Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]; item (a, el, c), c fastest
+    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
+      const int c = i % N1, el = (i / N1) % 16, a = i / (16 * N1);
+      const int64_t e = b * 16 + el;
+      if (e >= n_elem) continue;
+      T y = 0;
+#pragma unroll
+      for (int kk = 0; kk < N1; ++kk)
+        y += sV[kk * N1 + c] * sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el] +
+             sV[N1 * N1 + kk * N1 + c] * sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
+      const int te = int(e / L), layer = int(e - int64_t(te) * L);
+      Y[((size_t(te) * NPT + a) * L + layer) * N1 + c] = y;
+    }
+  }
+}
+
+// BF16 operands, FP32 accumulation (K = 16)
+template <int P, typename TG>
+__global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
+                                                             int64_t n_elem, int64_t n_batch,
+                                                             const TG* __restrict__ Gnat,
+                                                             const s4_t* __restrict__ tab2,
+                                                             const s4_t* __restrict__ tab4, VertMats<float> vm,
+                                                             const float* __restrict__ u, float* __restrict__ Y) {
+  using D = MD<P>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NP = NPT * N1, NT2 = D::NT2, KS16 = D::KS16, NAT = D::NAT;
+  constexpr int NTAB2 = 3 * NT2 * KS16 * 64, NTAB4 = 3 * NAT * NT2 * 64;
+  constexpr int NTH = 64 * N1;
+  __shared__ s4_t s2[NTAB2];
+  __shared__ s4_t s4[NTAB4];
+  __shared__ float sR[KS_LDS<P>::R_WORDS];
+  __shared__ float sV[2 * N1 * N1];
+  for (int i = threadIdx.x; i < NTAB2; i += NTH) s2[i] = tab2[i];
+  for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
+  for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
+  const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
+  const int64_t lb = xcd_block(gridDim.x);
+  for (int64_t b = lb; b < n_batch; b += gridDim.x) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
+      const int el = i / NP, r = i - el * NP, a = r / N1, c = r - a * N1;
+      const int64_t e = b * 16 + el;
+      float v = 0.f;
+      if (e < n_elem) {
+        const int te = int(e / L), layer = int(e - int64_t(te) * L);
+        v = u[int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * P + c];
+      }
+      sR[(c * NPT + a) * 16 + el] = v;
+    }
+    __syncthreads();
+    s4_t w[KS16], wz[KS16];
+#pragma unroll
+    for (int s = 0; s < KS16; ++s)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int a = 16 * s + 4 * g + kk;
+        float a0 = 0.f, a1 = 0.f;
+        if (a < NPT) {
+#pragma unroll
+          for (int c = 0; c < N1; ++c) {
+            const float uv = sR[(c * NPT + a) * 16 + j];
+            a0 += sV[k * N1 + c] * uv;
+            a1 += sV[N1 * N1 + k * N1 + c] * uv;
+          }
+        }
+        w[s][kk] = f2bf(a0);
+        wz[s][kk] = f2bf(a1);
+      }
+    __syncthreads();
+    f4_t yr[NAT], yt[NAT];
+#pragma unroll
+    for (int at = 0; at < NAT; ++at) { yr[at] = f4_t{0, 0, 0, 0}; yt[at] = f4_t{0, 0, 0, 0}; }
+#pragma unroll 1
+    for (int t = 0; t < NT2; ++t) {
+      float gv[6][4];
+      const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
+      const int64_t mst = 16 * D::NQT;
+      if (t < D::NTF) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gv[m][r] = gld<TG>(Gnat, blk + m * mst + t * 256 + lane * 4 + r);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 4 * g + r;
+#pragma unroll
+          for (int m = 0; m < 6; ++m)
+            gv[m][r] = row < D::NQR ? gld<TG>(Gnat, blk + m * mst + D::NTF * 256 + row * 16 + j) : 0.f;
+        }
+      }
+      f4_t dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS16; ++s) {
+        dr = mfma16(s2[((0 * NT2 + t) * KS16 + s) * 64 + lane], w[s], dr);
+        ds = mfma16(s2[((1 * NT2 + t) * KS16 + s) * 64 + lane], w[s], ds);
+        db = mfma16(s2[((2 * NT2 + t) * KS16 + s) * 64 + lane], wz[s], db);
+      }
+      s4_t br, bs, bt;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float ur = dr[r], us = ds[r], ut = db[r];
+        br[r] = f2bf(gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut);
+        bs[r] = f2bf(gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut);
+        bt[r] = f2bf(gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut);
+      }
+#pragma unroll
+      for (int at = 0; at < NAT; ++at) {
+        yr[at] = mfma16(s4[((0 * NAT + at) * NT2 + t) * 64 + lane], br, yr[at]);
+        yr[at] = mfma16(s4[((1 * NAT + at) * NT2 + t) * 64 + lane], bs, yr[at]);
+        yt[at] = mfma16(s4[((2 * NAT + at) * NT2 + t) * 64 + lane], bt, yt[at]);
+      }
+    }
+#pragma unroll
+    for (int at = 0; at < NAT; ++at)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * at + 4 * g + r;
+        sR[((k * 2 + 0) * NAT * 16 + a) * 16 + j] = yr[at][r];
+        sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
+      }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
+      const int c = i % N1, el = (i / N1) % 16, a = i / (16 * N1);
+      const int64_t e = b * 16 + el;
+      if (e >= n_elem) continue;
+      float y = 0.f;
+#pragma unroll
+      for (int kk = 0; kk < N1; ++kk)
+        y += sV[kk * N1 + c] * sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el] +
+             sV[N1 * N1 + kk * N1 + c] * sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
+      const int te = int(e / L), layer = int(e - int64_t(te) * L);
+      Y[((size_t(te) * NPT + a) * L + layer) * N1 + c] = y;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// G re-layout: standard [e][m][k*NQT+q] (FP64) -> lane-native order of a flavour
+// ---------------------------------------------------------------------------
+template <int P, typename TO, bool F64ROW>
+__global__ __launch_bounds__(256) void k_g_native(int64_t n_elem, int64_t n_batch, const double* __restrict__ G,
+                                                  TO* __restrict__ out) {
+  using D = MD<P>;
+  const int64_t per_batch = int64_t(16) * 6 * D::NQ;
+  const int64_t total = n_batch * per_batch;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < total; i += int64_t(gridDim.x) * 256) {
+    const int64_t b = i / per_batch;
+    int64_t rem = i - b * per_batch;
+    const int k = int(rem / (6 * 16 * D::NQT));
+    rem -= int64_t(k) * 6 * 16 * D::NQT;
+    const int m = int(rem / (16 * D::NQT));
+    int w = int(rem - int64_t(m) * 16 * D::NQT);
+    int q, jj;
+    if (w < D::NTF * 256) {
+      const int t = w / 256;
+      const int l = (w % 256) / 4, r = w % 4;
+      jj = l & 15;
+      q = 16 * t + row_of<F64ROW>(l >> 4, r);
+    } else {
+      w -= D::NTF * 256;
+      q = 16 * D::NTF + w / 16;
+      jj = w % 16;
+    }
+    const int64_t e = b * 16 + jj;
+    double v = 0.0;
+    if (e < n_elem) v = G[(e * 6 + m) * D::NQ + int64_t(k) * D::NQT + q];
+    out[i] = cvt_out<TO>(v);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+static int grid_batches(int64_t n_batch) {
+  int64_t blocks = n_batch;
+  if (blocks > 4096) blocks = 4096;
+  blocks = ((blocks + 7) / 8) * 8;  // multiple of the XCD count
+  return int(blocks < 8 ? 8 : blocks);
+}
+
+
+
+template <int P>
+static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
+  const int64_t nb = (n_elem + 15) / 16;
+  const int64_t total = nb * 16 * 6 * MD<P>::NQ;
+  int64_t grid = (total + 255) / 256;
+  if (grid > 65535 * 4) grid = 65535 * 4;
+  if (flavour == MF_F64)
+    hipLaunchKernelGGL((k_g_native<P, double, true>), dim3(grid), dim3(256), 0, st, n_elem, nb, G, (double*)out);
+  else if (flavour == MF_F32)
+    hipLaunchKernelGGL((k_g_native<P, float, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G, (float*)out);
+  else
+    hipLaunchKernelGGL((k_g_native<P, bf16_t, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G, (bf16_t*)out);
+}
+
+void launch_g_native(int P, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
+  switch (P) {
+    case 3: relayout_p<3>(n_elem, G, out, flavour, st); break;
+    case 6: relayout_p<6>(n_elem, G, out, flavour, st); break;
+    case 8: relayout_p<8>(n_elem, G, out, flavour, st); break;
+    default: break;
+  }
+}
+
+template <int P>
+static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
+                      const void* vmats, const void* u, void* Y, hipStream_t st) {
+  const int64_t nb = (lv.n_elem + 15) / 16;
+  const int grid = grid_batches(nb);
+  if (flavour == MF_F64) {
+    if constexpr (P == 8) return;
+    else
+    hipLaunchKernelGGL((k_ax_mfma4<P, double, double, d4_t, true>), dim3(grid), dim3(64 * (P + 1)), 0, st, lv.map2d, lv.L,
+                       int(lv.nz), lv.n_elem, nb, (const double*)Gnat, (const double*)tab2, (const double*)tab4,
+                       *(const VertMats<double>*)vmats, (const double*)u, (double*)Y);
+  } else if (flavour == MF_F32) {
+    hipLaunchKernelGGL((k_ax_mfma4<P, float, float, f4_t, false>), dim3(grid), dim3(64 * (P + 1)), 0, st, lv.map2d, lv.L,
+                       int(lv.nz), lv.n_elem, nb, (const float*)Gnat, (const float*)tab2, (const float*)tab4,
+                       *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
+  } else {
+    hipLaunchKernelGGL((k_ax_mfma_bf16<P, bf16_t>), dim3(grid), dim3(64 * (P + 1)), 0, st, lv.map2d, lv.L, int(lv.nz),
+                       lv.n_elem, nb, (const bf16_t*)Gnat, (const s4_t*)tab2, (const s4_t*)tab4,
+                       *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
+  }
+}
+
+void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
+                    const void* vmats, const void* u, void* Y, hipStream_t st) {
+  switch (lv.P) {
+    case 3: ax_mfma_p<3>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st); break;
+    case 6: ax_mfma_p<6>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st); break;
+    case 8: ax_mfma_p<8>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st); break;
+    default: break;
+  }
+}
+
+}  // namespace pmg

@@ -1,0 +1,40 @@
+// MFMA element operator of the fine levels (see kernels_mfma.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace pmg {
+
+enum MfmaFlavour { MF_F64 = 0, MF_F32 = 1, MF_BF16 = 2 };
+
+// vertical interpolation/derivative matrices at the Gauss points, passed by value
+template <typename T> struct VertMats {
+  T Bz[81];
+  T Dz[81];
+};
+
+template <typename TO> __device__ __forceinline__ TO cvt_out(double v);
+template <> __device__ __forceinline__ double cvt_out<double>(double v) { return v; }
+template <> __device__ __forceinline__ float cvt_out<float>(double v) { return float(v); }
+template <> __device__ __forceinline__ bf16_t cvt_out<bf16_t>(double v) {
+  uint32_t u = __float_as_uint(float(v));
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return bf16_t(u >> 16);
+}
+__device__ __forceinline__ double gld_any(const double* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float gld_any(const float* p, int64_t i) { return p[i]; }
+
+// orders with an MFMA kernel for a flavour
+inline bool mfma_available(int P, int flavour) {
+  if (P == 6 || P == 3) return true;
+  if (P == 8) return flavour != MF_F64;
+  return false;
+}
+void launch_g_native(int P, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st);
+void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
+                    const void* vmats, const void* u, void* Y, hipStream_t st);
+
+}  // namespace pmg

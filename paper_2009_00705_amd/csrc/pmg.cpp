@@ -19,6 +19,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "kernels_mfma.hpp"
 #include "mesh.hpp"
 #include "pmg.h"
 #include "refelem.hpp"
@@ -80,18 +81,26 @@ struct Level {
   bf16_t* G16 = nullptr;
   double *diag = nullptr, *dinv64 = nullptr;
   float* dinv32 = nullptr;
-  double *f64 = nullptr, *u64 = nullptr, *r64 = nullptr;
-  float *f32 = nullptr, *u32 = nullptr, *r32 = nullptr;
+  double *f64 = nullptr, *u64 = nullptr, *r64 = nullptr, *d64 = nullptr;
+  float *f32 = nullptr, *u32 = nullptr, *r32 = nullptr, *d32 = nullptr;
   double *pit64 = nullptr, *piz64 = nullptr;  // transfer to the next coarser level
   float *pit32 = nullptr, *piz32 = nullptr;
   double omega = 0.0;
   double omega_user = 0.0;
   LevelView view{};
+  // MFMA element operator (per flavour MF_F64, MF_F32, MF_BF16)
+  bool mf[3] = {false, false, false};
+  void* gnat[3] = {nullptr, nullptr, nullptr};
+  void* tab2[3] = {nullptr, nullptr, nullptr};
+  void* tab4[3] = {nullptr, nullptr, nullptr};
+  VertMats<double> vm64{};
+  VertMats<float> vm32{};
 
   template <typename T> T* f();
   template <typename T> T* u();
   template <typename T> T* r();
   template <typename T> T* dinv();
+  template <typename T> T* d();
   template <typename T> T* mats();
   template <typename T> T* pit();
   template <typename T> T* piz();
@@ -102,6 +111,8 @@ template <> double* Level::u<double>() { return u64; }
 template <> float* Level::u<float>() { return u32; }
 template <> double* Level::r<double>() { return r64; }
 template <> float* Level::r<float>() { return r32; }
+template <> double* Level::d<double>() { return d64; }
+template <> float* Level::d<float>() { return d32; }
 template <> double* Level::dinv<double>() { return dinv64; }
 template <> float* Level::dinv<float>() { return dinv32; }
 template <> double* Level::mats<double>() { return mats64; }
@@ -138,6 +149,7 @@ struct pmg_ctx {
   double* ctmp64 = nullptr;
   float* ctmp32 = nullptr;
   double cheb_lmin = 0, cheb_lmax = 0;
+  int cheb_k = 0;
   bool coarse_exact = true;
   // solve work (finest level)
   double *s_phiD = nullptr, *s_f = nullptr, *s_u = nullptr, *s_r = nullptr, *s_p = nullptr, *s_q = nullptr,
@@ -213,6 +225,82 @@ static void build_levels(pmg_ctx* c) {
   c->eta_h.assign(size_t(c->lv[0].num.n2d), 0.0);
 }
 
+// MFMA operand tables of one order (see kernels_mfma.hip): row map of the
+// output registers is 4g+r (FP32, BF16) or g+4r (FP64), g = lane/16, j = lane%16.
+static void mfma_tables(const RefElem& re, int flavour, std::vector<double>& t2, std::vector<double>& t4,
+                        std::vector<uint16_t>& b2, std::vector<uint16_t>& b4) {
+  const int NPT = re.np_tri, NQT = re.nq_tri;
+  const int NT2 = (NQT + 15) / 16, KS = (NPT + 3) / 4, KS16 = (NPT + 15) / 16, NAT = (NPT + 15) / 16;
+  const Mat* M[3] = {&re.Dr, &re.Ds, &re.B};
+  auto at = [&](int mt, int q, int a) { return (q < NQT && a < NPT) ? (*M[mt])(q, a) : 0.0; };
+  auto bf = [](double v) {
+    float f = float(v);
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+  };
+  t2.clear(); t4.clear(); b2.clear(); b4.clear();
+  if (flavour == MF_BF16) {
+    for (int mt = 0; mt < 3; ++mt)
+      for (int t = 0; t < NT2; ++t)
+        for (int s = 0; s < KS16; ++s)
+          for (int l = 0; l < 64; ++l)
+            for (int kk = 0; kk < 4; ++kk) b2.push_back(bf(at(mt, 16 * t + (l & 15), 16 * s + 4 * (l >> 4) + kk)));
+    for (int mt = 0; mt < 3; ++mt)
+      for (int a = 0; a < NAT; ++a)
+        for (int t = 0; t < NT2; ++t)
+          for (int l = 0; l < 64; ++l)
+            for (int kk = 0; kk < 4; ++kk) b4.push_back(bf(at(mt, 16 * t + 4 * (l >> 4) + kk, 16 * a + (l & 15))));
+    return;
+  }
+  const bool f64row = flavour == MF_F64;
+  auto row = [&](int g, int r) { return f64row ? g + 4 * r : 4 * g + r; };
+  for (int mt = 0; mt < 3; ++mt)
+    for (int t = 0; t < NT2; ++t)
+      for (int s = 0; s < KS; ++s)
+        for (int l = 0; l < 64; ++l) t2.push_back(at(mt, 16 * t + (l & 15), 4 * s + (l >> 4)));
+  for (int mt = 0; mt < 3; ++mt)
+    for (int a = 0; a < NAT; ++a)
+      for (int t = 0; t < NT2; ++t)
+        for (int r = 0; r < 4; ++r) {
+          if (16 * t + row(0, r) >= NQT) continue;
+          for (int l = 0; l < 64; ++l) t4.push_back(at(mt, 16 * t + row(l >> 4, r), 16 * a + (l & 15)));
+        }
+}
+
+static void upload_mfma(pmg_ctx* c, Level& L) {
+  const RefElem& re = *L.re;
+  for (int i = 0; i < re.n1 * re.n1; ++i) {
+    L.vm64.Bz[i] = re.Bz.v[i];
+    L.vm64.Dz[i] = re.Dz.v[i];
+    L.vm32.Bz[i] = float(re.Bz.v[i]);
+    L.vm32.Dz[i] = float(re.Dz.v[i]);
+  }
+  const int64_t nb = (L.num.n_elem + 15) / 16;
+  const size_t ng = size_t(nb) * 16 * 6 * re.nq;
+  for (int f = 0; f < 3; ++f) {
+    if (!mfma_available(L.P, f)) continue;
+    std::vector<double> t2, t4;
+    std::vector<uint16_t> b2, b4;
+    mfma_tables(re, f, t2, t4, b2, b4);
+    if (f == MF_F64) {
+      L.tab2[f] = c->U(t2);
+      L.tab4[f] = c->U(t4);
+      L.gnat[f] = c->A<double>(ng);
+    } else if (f == MF_F32) {
+      L.tab2[f] = c->U(to_f32(t2));
+      L.tab4[f] = c->U(to_f32(t4));
+      L.gnat[f] = c->A<float>(ng);
+    } else {
+      L.tab2[f] = c->U(b2);
+      L.tab4[f] = c->U(b4);
+      L.gnat[f] = c->A<bf16_t>(ng);
+    }
+    L.mf[f] = true;
+  }
+}
+
 static void upload_levels(pmg_ctx* c) {
   const RefElem& rf = *c->lv[0].re;
   int64_t maxE = 0;
@@ -246,6 +334,10 @@ static void upload_levels(pmg_ctx* c) {
     L.dinv32 = c->A<float>(N);
     L.r64 = c->A<double>(N);
     L.r32 = c->A<float>(N);
+    if (i + 1 < c->nl) {
+      L.d64 = c->A<double>(N);
+      L.d32 = c->A<float>(N);
+    }
     if (i > 0) {
       L.f64 = c->A<double>(N);
       L.u64 = c->A<double>(N);
@@ -253,6 +345,7 @@ static void upload_levels(pmg_ctx* c) {
       L.u32 = c->A<float>(N);
     }
     maxE = std::max(maxE, E * re.np);
+    if (c->opt.kernel_variant == 0) upload_mfma(c, L);
     L.view = LevelView{L.P, L.num.L, L.num.nt, re.np_tri, re.np, re.nq, L.num.n2d, L.num.nz, N, E,
                        L.map2d, L.inc_ptr, L.inc, L.dir2d, L.top_dir};
     if (i + 1 < c->nl) {
@@ -305,8 +398,14 @@ static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
   Level& L = c->lv[i];
   int gs;
   const void* G = gptr<T>(c, L, gs);
-  launch_ax<T>(L.view, L.mats<T>(), G, gs, x, reinterpret_cast<T*>(c->Y), st);
   if (i == 0 && sizeof(T) == 8) c->n_fine_applies++;
+  const int f = sizeof(T) == 8 ? MF_F64 : (gs == G_BF16 ? MF_BF16 : MF_F32);
+  if (L.mf[f]) {
+    const void* vm = sizeof(T) == 8 ? (const void*)&L.vm64 : (const void*)&L.vm32;
+    launch_ax_mfma(L.view, L.gnat[f], f, L.tab2[f], L.tab4[f], vm, x, c->Y, st);
+    return;
+  }
+  launch_ax<T>(L.view, L.mats<T>(), G, gs, x, reinterpret_cast<T*>(c->Y), st);
 }
 
 template <typename T>
@@ -320,6 +419,35 @@ static void jacobi_sweep(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   Level& L = c->lv[i];
   ax_elem<T>(c, i, u, st);
   assemble<T>(c, i, OP_JACOBI, u, f, L.dinv<T>(), nullptr, L.omega, 0.0, st);
+}
+
+// Chebyshev-accelerated Jacobi smoothing (k >= 1 steps) of the defect f - A u on
+// [lambda/ratio, lambda], lambda = 4/(3 omega); from u = 0 when zero_guess.
+template <typename T>
+static void cheb_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess, int k, hipStream_t st) {
+  Level& L = c->lv[i];
+  const int64_t N = L.num.n_dof;
+  const double lmax = 4.0 / (3.0 * L.omega), lmin = lmax / c->opt.smooth_ratio;
+  const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
+  T* r = L.r<T>();
+  T* d = L.d<T>();
+  if (zero_guess) {
+    launch_copy<T>(f, r, N, st);
+    launch_scale_diag<T>(L.dinv<T>(), f, d, 1.0 / theta, N, st);
+    launch_copy<T>(d, u, N, st);
+  } else {
+    ax_elem<T>(c, i, u, st);
+    assemble<T>(c, i, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
+    launch_scale_diag<T>(L.dinv<T>(), r, d, 1.0 / theta, N, st);
+    launch_axpy_t<T>(u, d, 1.0, N, st);
+  }
+  double rho = 1.0 / sigma;
+  for (int j = 1; j < k; ++j) {
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    ax_elem<T>(c, i, d, st);
+    assemble<T>(c, i, OP_CHEB, u, r, L.dinv<T>(), d, rho_new * rho, 2.0 * rho_new / delta, st);
+    rho = rho_new;
+  }
 }
 
 static double read_scal(pmg_ctx* c, int slot, hipStream_t st) {
@@ -353,7 +481,7 @@ static void coarse_solve(pmg_ctx* c, const T* f, T* u, hipStream_t st) {
     return;
   }
   // Jacobi-preconditioned Chebyshev iteration from zero (three-term recurrence)
-  const int k = std::max(1, c->opt.cheb_degree);
+  const int k = std::max(1, c->cheb_k > 0 ? c->cheb_k : c->opt.cheb_degree);
   const double lmin = c->cheb_lmin, lmax = c->cheb_lmax;
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   T* r = L.r<T>();
@@ -397,6 +525,85 @@ static double lambda_max(pmg_ctx* c, int i, hipStream_t st) {
   launch_scale_diag<double>(L.diag, x, y, 1.0, N, st);
   const double xdx = dot_host(c, x, y, N, st);
   return 1.05 * xax / xdx;
+}
+
+// smallest / largest eigenvalue of a symmetric tridiagonal matrix (Sturm bisection)
+static void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e, double& lo, double& hi) {
+  const int m = int(d.size());
+  double a = d[0], b = d[0];
+  for (int i = 0; i < m; ++i) {
+    const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < m ? std::fabs(e[i]) : 0.0);
+    a = std::min(a, d[i] - r);
+    b = std::max(b, d[i] + r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int cnt = 0;
+    double q = d[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < m; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = d[i] - x - e[i - 1] * e[i - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  auto kth = [&](int k) {  // k-th smallest (0-based)
+    double l = a, h = b;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (l + h);
+      if (count_below(mid) > k) h = mid; else l = mid;
+    }
+    return 0.5 * (l + h);
+  };
+  lo = kth(0);
+  hi = kth(m - 1);
+}
+
+// extreme eigenvalues of D^-1 A on level i from m steps of Jacobi-preconditioned
+// CG (Lanczos coefficients), started from the counter-based vector
+static void lanczos_bounds(pmg_ctx* c, int i, int m, double& lmin, double& lmax, hipStream_t st) {
+  Level& L = c->lv[i];
+  const int64_t N = L.num.n_dof;
+  m = int(std::min<int64_t>(m, std::max<int64_t>(L.n_free, 1)));
+  std::vector<double> x0(N);
+  for (int64_t g = 0; g < N; ++g) x0[g] = splitmix_unit(c->opt.seed + 1, uint64_t(g)) - 0.5;
+  double* r = L.r64;
+  double* p = c->s_p;
+  double* z = c->s_z;
+  double* q = c->s_y;
+  HIPCHK(hipMemcpyAsync(q, x0.data(), N * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));
+  launch_mask<double>(L.view, q, r, st);
+  launch_scale_diag<double>(L.dinv64, r, z, 1.0, N, st);
+  launch_copy<double>(z, p, N, st);
+  double rz = dot_host(c, r, z, N, st);
+  const double rz0 = rz;
+  std::vector<double> al, be;
+  for (int it = 0; it < m; ++it) {
+    ax_elem<double>(c, i, p, st);
+    assemble<double>(c, i, OP_STORE_DOT, q, p, nullptr, nullptr, 0, 0, st);
+    launch_finalize(c->partial, c->scal, S_TMP0, FIN_SET, st);
+    const double pq = read_scal(c, S_TMP0, st);
+    if (!(pq > 0)) break;
+    const double alpha = rz / pq;
+    launch_axpy(r, q, -alpha, N, st);
+    launch_scale_diag<double>(L.dinv64, r, z, 1.0, N, st);
+    const double rzn = dot_host(c, r, z, N, st);
+    const double beta = rzn / rz;
+    al.push_back(alpha);
+    be.push_back(beta);
+    rz = rzn;
+    if (!(rz > 1e-28 * rz0)) break;
+    launch_xpay(p, z, beta, N, st);
+  }
+  if (al.empty()) throw Error(PMG_EBREAKDOWN, "Lanczos estimate failed on the coarse level");
+  const int k = int(al.size());
+  std::vector<double> d(k), e(std::max(k - 1, 1), 0.0);
+  for (int t = 0; t < k; ++t) {
+    d[t] = 1.0 / al[t] + (t > 0 ? be[t - 1] / al[t - 1] : 0.0);
+    if (t + 1 < k) e[t] = std::sqrt(be[t]) / al[t];
+  }
+  tridiag_extremes(d, e, lmin, lmax);
 }
 
 // dense inverse of the free-node P=1 matrix (host, from the device G of the level)
@@ -548,6 +755,12 @@ static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
   }
   if (eta != c->eta) HIPCHK(hipMemcpyAsync(c->eta, eta, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(c->eta_h.data(), c->eta, n2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  // lane-native copies of G for the MFMA element operator
+  for (int i = 0; i < c->nl; ++i) {
+    Level& L = c->lv[i];
+    for (int f = 0; f < 3; ++f)
+      if (L.mf[f]) launch_g_native(L.P, L.num.n_elem, L.G64, L.gnat[f], f, st);
+  }
   // Jacobi diagonals
   for (int i = 0; i < c->nl; ++i) {
     Level& L = c->lv[i];
@@ -573,8 +786,23 @@ static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
       c->ctmp64 = c->A<double>(C.num.n_dof);
       c->ctmp32 = c->A<float>(C.num.n_dof);
     }
-    c->cheb_lmax = c->opt.cheb_lmax > 0 ? c->opt.cheb_lmax : lambda_max(c, c->nl - 1, st);
-    c->cheb_lmin = c->opt.cheb_lmin > 0 ? c->opt.cheb_lmin : c->cheb_lmax / std::max(1.0001, c->opt.cheb_ratio);
+    if (c->opt.cheb_lmax > 0 && c->opt.cheb_lmin > 0) {
+      c->cheb_lmax = c->opt.cheb_lmax;
+      c->cheb_lmin = c->opt.cheb_lmin;
+    } else if (c->opt.cheb_ratio > 0) {
+      c->cheb_lmax = c->opt.cheb_lmax > 0 ? c->opt.cheb_lmax : lambda_max(c, c->nl - 1, st);
+      c->cheb_lmin = c->cheb_lmax / std::max(1.0001, c->opt.cheb_ratio);
+    } else {
+      double lo, hi;
+      lanczos_bounds(c, c->nl - 1, 120, lo, hi, st);
+      c->cheb_lmax = c->opt.cheb_lmax > 0 ? c->opt.cheb_lmax : 1.05 * hi;
+      c->cheb_lmin = c->opt.cheb_lmin > 0 ? c->opt.cheb_lmin : 0.9 * lo;
+    }
+    // degree for a 0.1 error reduction over [lmin, lmax] unless given
+    c->cheb_k = c->opt.cheb_degree > 0
+                    ? c->opt.cheb_degree
+                    : std::max(4, std::min(400, int(std::ceil(0.5 * std::sqrt(c->cheb_lmax / c->cheb_lmin) *
+                                                              std::log(20.0)))));
   }
   HIPCHK(hipStreamSynchronize(st));
 }
@@ -591,7 +819,10 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   Level& L = c->lv[i];
   Level& C = c->lv[i + 1];
   const int64_t N = L.num.n_dof;
-  if (c->opt.nu1 >= 1) {
+  const bool cheb = c->opt.smoother == PMG_SMOOTH_CHEBYSHEV;
+  if (c->opt.nu1 >= 1 && cheb) {
+    cheb_smooth<T>(c, i, f, u, true, c->opt.nu1, st);
+  } else if (c->opt.nu1 >= 1) {
     launch_scale_diag<T>(L.dinv<T>(), f, u, L.omega, N, st);
     for (int m = 1; m < c->opt.nu1; ++m) jacobi_sweep<T>(c, i, f, u, st);
   } else {
@@ -605,7 +836,11 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   vcycle<T>(c, i + 1, C.f<T>(), C.u<T>(), st);
   launch_prolong_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), C.u<T>(), reinterpret_cast<T*>(c->Y), st);
   assemble<T>(c, i, OP_AVG_ADD, u, nullptr, nullptr, nullptr, 0, 0, st);
-  for (int m = 0; m < c->opt.nu2; ++m) jacobi_sweep<T>(c, i, f, u, st);
+  if (cheb) {
+    if (c->opt.nu2 >= 1) cheb_smooth<T>(c, i, f, u, false, c->opt.nu2, st);
+  } else {
+    for (int m = 0; m < c->opt.nu2; ++m) jacobi_sweep<T>(c, i, f, u, st);
+  }
 }
 
 // z = M^-1 r at the finest level in the context's precision (r, z FP64)
@@ -827,6 +1062,10 @@ static void check_level(const pmg_ctx* c, int level) {
 
 template <typename T>
 static void smooth_t(pmg_ctx* c, int level, int sweeps, const T* f, T* u, hipStream_t st) {
+  if (c->opt.smoother == PMG_SMOOTH_CHEBYSHEV) {
+    if (sweeps >= 1) cheb_smooth<T>(c, level, f, u, false, sweeps, st);
+    return;
+  }
   for (int m = 0; m < sweeps; ++m) jacobi_sweep<T>(c, level, f, u, st);
 }
 
@@ -853,9 +1092,11 @@ void pmg_options_default(pmg_options* o) {
   o->precision = PMG_FP64;
   o->krylov = PMG_PCG;
   o->coarse = PMG_COARSE_EXACT;
-  o->cheb_degree = 30;
-  o->cheb_ratio = 100.0;
+  o->cheb_degree = 0;
+  o->cheb_ratio = 0.0;
   o->exact_max = 12000;
+  o->smoother = PMG_SMOOTH_JACOBI;
+  o->smooth_ratio = 15.0;
   o->seed = 0;
 }
 
@@ -874,6 +1115,9 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (o->nu1 < 0 || o->nu2 < 0) throw Error(PMG_EINVAL, "negative sweep count");
     if (o->precision < 0 || o->precision > 2) throw Error(PMG_EINVAL, "bad precision");
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
+    if (o->smoother < 0 || o->smoother > 1) throw Error(PMG_EINVAL, "bad smoother");
+    if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
+      throw Error(PMG_EINVAL, "smooth_ratio must exceed 1");
     c = new pmg_ctx();
     c->opt = *o;
     c->host_only = o->host_only != 0;
@@ -1095,6 +1339,16 @@ int pmg_vcycle(pmg_ctx* c, int precision, const void* r, void* z, void* stream) 
       vcycle<float>(c, 0, (const float*)r, (float*)z, S(stream));
     }
   });
+  return PMG_OK;
+}
+
+int pmg_coarse_info(const pmg_ctx* c, int* mode, int* degree, double* lmin, double* lmax, int64_t* n_free) {
+  if (!c) return PMG_EINVAL;
+  if (mode) *mode = c->coarse_exact ? PMG_COARSE_EXACT : PMG_COARSE_CHEBYSHEV;
+  if (degree) *degree = c->coarse_exact ? 0 : c->cheb_k;
+  if (lmin) *lmin = c->cheb_lmin;
+  if (lmax) *lmax = c->cheb_lmax;
+  if (n_free) *n_free = c->lv[c->nl - 1].n_free;
   return PMG_OK;
 }
 

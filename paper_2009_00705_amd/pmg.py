@@ -46,7 +46,8 @@ class Options(C.Structure):
                 ("precision", C.c_int32), ("krylov", C.c_int32), ("dirichlet_tags", C.c_uint32),
                 ("top_neumann", C.c_int32), ("coarse", C.c_int32), ("cheb_degree", C.c_int32),
                 ("cheb_lmin", C.c_double), ("cheb_lmax", C.c_double), ("cheb_ratio", C.c_double),
-                ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32)]
+                ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32),
+                ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double)]
 
 
 class LevelInfo(C.Structure):
@@ -99,6 +100,7 @@ SIGNATURES = {
     "pmg_set_params": (_I, [_VP, _VP, _D, _D]),
     "pmg_solve": (_I, [_VP, _VP, _VP, _VP, _I, _VP, _VP, _D, _D, C.c_int32, C.POINTER(Stats), _VP]),
     "pmg_set_solver": (_I, [_VP, _I, _I]),
+    "pmg_coarse_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_time_kernel": (_I, [_VP, _I, _I, _I, _I, C.POINTER(C.c_double), _VP]),
 }
 KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4}
@@ -156,6 +158,8 @@ def default_options(**kw) -> Options:
             o.precision = PRECISIONS[v]
         elif k == "krylov" and isinstance(v, str):
             o.krylov = KRYLOV[v]
+        elif k == "smoother" and isinstance(v, str):
+            o.smoother = {"jacobi": 0, "chebyshev": 1}[v]
         elif k == "coarse" and isinstance(v, str):
             o.coarse = {"exact": PMG_COARSE_EXACT, "chebyshev": PMG_COARSE_CHEBYSHEV}[v]
         else:
@@ -243,6 +247,14 @@ class Context:
         lo, hi = C.c_double(), C.c_double()
         self._c(lib().pmg_get_params(self.h, om.ctypes.data_as(C.c_void_p), C.byref(lo), C.byref(hi)))
         return om, lo.value, hi.value
+
+    def coarse_info(self) -> dict:
+        mode, deg = C.c_int(), C.c_int()
+        lo, hi = C.c_double(), C.c_double()
+        nf = C.c_int64()
+        self._c(lib().pmg_coarse_info(self.h, C.byref(mode), C.byref(deg), C.byref(lo), C.byref(hi), C.byref(nf)))
+        return {"mode": "exact" if mode.value == 0 else "chebyshev", "degree": deg.value, "lmin": lo.value,
+                "lmax": hi.value, "n_free": nf.value}
 
     def set_params(self, omega=None, cheb_lmin=0.0, cheb_lmax=0.0):
         om = None

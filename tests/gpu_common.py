@@ -39,6 +39,9 @@ def make_pair(mesh, P, eta_kind="wavy", omega=0.3, **kw):
         okw["dirichlet_tags"] = kw["dirichlet_tags"]
     if kw.get("top_neumann"):
         okw["top_neumann"] = True
+    if "smoother" in kw:
+        okw["smoother"] = kw["smoother"]
+        okw["smooth_ratio"] = kw.get("smooth_ratio", 15.0)
     if kw.get("coarse") == "chebyshev":
         okw["coarse"] = "chebyshev"
         okw["cheb"] = (kw["cheb_degree"], kw["cheb_lmin"], kw["cheb_lmax"])

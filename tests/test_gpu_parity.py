@@ -156,3 +156,32 @@ def test_pcg_solve_parity(solve_pair):
     phi2 = torch.zeros_like(phi)
     ctx.solve(phi2, phi_surf=dev(surf_l), rtol=1e-10, imax=300)
     assert torch.equal(phi, phi2)
+
+
+@pytest.fixture(scope="module", params=["box5x5_L3_P6", "cyl_P3"])
+def cheb_pair(request):
+    mk, P = CASES[request.param]
+    h, ctx = make_pair(mk(), P, omega="auto", smoother="chebyshev", nu1=3, nu2=3)
+    yield request.param, h, ctx
+    ctx.close()
+
+
+def test_chebyshev_smoother_vcycle_and_solve(cheb_pair):
+    name, h, ctx = cheb_pair
+    import torch
+    lv = h.levels[0]
+    f = np.where(lv.free, _rand(lv.num.n_dof, 60), 0)
+    u = np.where(lv.free, _rand(lv.num.n_dof, 61), 0)
+    ud = dev(u)
+    ctx.smooth(0, dev(f), ud, sweeps=3)
+    assert rel_err(host(ud), h.smooth(0, u, f, 3)) < 1e-12
+    z = torch.empty(lv.num.n_dof, dtype=torch.float64, device="cuda")
+    ctx.vcycle(dev(f), z)
+    assert rel_err(host(z), h.vcycle(f)) < 1e-11
+    phi_o, surf_l = _dirichlet(h, ctx)
+    ref = K.solve(h, phi_o, method="pcg", rtol=1e-10, imax=300)
+    phi = torch.zeros(lv.num.n_dof, dtype=torch.float64, device="cuda")
+    rc, st = ctx.solve(phi, phi_surf=dev(surf_l), rtol=1e-10, imax=300)
+    assert rc == 0 and st["iters"] == ref.iters
+    np.testing.assert_allclose(st["res_hist"], ref.res_hist, rtol=1e-9, atol=1e-10 * ref.res_hist[0])
+    assert rel_err(host(phi), ref.phi) < 1e-10

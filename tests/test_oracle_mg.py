@@ -148,3 +148,46 @@ def test_convergence_factor_flat_in_element_count():
         r = K.solve(h, phi, rtol=1e-8)
         qs.append(np.exp(np.mean(np.log(r.q))))
     assert max(qs) / min(qs) <= 1.25, qs
+
+
+def test_chebyshev_smoother_is_symmetric_and_beats_jacobi():
+    """Polynomial (Chebyshev-Jacobi) smoothing keeps the V-cycle symmetric and
+    damps the anisotropic prism problem better than damped Jacobi."""
+    import math
+    m = W.box_mesh(8, 4, lx=math.pi / 4, ly=math.pi / 4)       # dx = 0.098, dz = 0.25
+    hj = Hierarchy(m, 4)
+    hc = Hierarchy(m, 4, smoother="chebyshev", nu1=3, nu2=3, omega=[lv.omega for lv in hj.levels[:-1]])
+    lv = hc.levels[0]
+    rng = np.random.default_rng(2)
+    x = np.where(lv.free, rng.standard_normal(lv.num.n_dof), 0)
+    y = np.where(lv.free, rng.standard_normal(lv.num.n_dof), 0)
+    assert abs(hc.vcycle(x) @ y - x @ hc.vcycle(y)) < 1e-10 * np.linalg.norm(x) * np.linalg.norm(y)
+    xyz = M.node_xyz(m, lv.num, np.zeros(lv.num.n2d))
+    phi = W.linear_wave(xyz[:, 0], xyz[:, 1], xyz[:, 2], 1.0)
+    rj = K.solve(hj, phi, rtol=1e-8)
+    rc = K.solve(hc, phi, rtol=1e-8)
+    assert rc.iters < rj.iters
+    np.testing.assert_allclose(rc.phi, rj.phi, atol=1e-7 * np.abs(rj.phi).max())
+
+def test_chebyshev_smoother_closed_form():
+    # one pre-smoothing from zero equals the closed-form polynomial p(D^-1 A) D^-1 f
+    m = W.box_mesh(2, 2)
+    hc = Hierarchy(m, 2, smoother="chebyshev", nu1=3, nu2=3)
+    lv = hc.levels[0]
+    rng = np.random.default_rng(4)
+    f = np.where(lv.free, rng.standard_normal(lv.num.n_dof), 0)
+    u = hc.smooth(0, np.zeros_like(f), f, 3)
+    lmax = 4.0 / (3.0 * lv.omega)
+    lmin = lmax / hc.smooth_ratio
+    free = np.flatnonzero(lv.free)
+    A = lv.op.assembled()[free][:, free].toarray()
+    d = lv.diag[free]
+    S = A / np.sqrt(np.outer(d, d))
+    lam, V = np.linalg.eigh(S)
+    th, de = (lmax + lmin) / 2, (lmax - lmin) / 2
+    c = np.zeros(4)
+    c[3] = 1
+    p = np.polynomial.chebyshev.chebval((th - lam) / de, c) / np.polynomial.chebyshev.chebval(th / de, c)
+    e0 = np.linalg.solve(A, f[free])
+    want = e0 - (V @ (p * (V.T @ (np.sqrt(d) * e0)))) / np.sqrt(d)
+    np.testing.assert_allclose(u[free], want, atol=1e-10 * np.abs(want).max())
