@@ -57,7 +57,11 @@ enum pmg_precision { PMG_FP64 = 0, PMG_MIXED_FP32 = 1, PMG_MIXED_BF16 = 2 };
  * (preconditioned defect correction), stand-alone V-cycles. */
 enum pmg_krylov { PMG_PCG = 0, PMG_FPCG = 1, PMG_PDC = 2, PMG_MG = 3 };
 
-enum pmg_guess { PMG_GUESS_GIVEN = 0, PMG_GUESS_ZERO = 1, PMG_GUESS_LEARNED = 2 };
+/* Initial guess of pmg_solve: the caller's phi, zero, the extrapolation
+ * 2 phi_{n-1} - phi_{n-2} of the two previous solutions plus the learned
+ * correction (falls back to the extrapolation when its residual is not
+ * smaller), or the extrapolation alone. */
+enum pmg_guess { PMG_GUESS_GIVEN = 0, PMG_GUESS_ZERO = 1, PMG_GUESS_LEARNED = 2, PMG_GUESS_EXTRAP = 3 };
 
 /* Coarsest (P = 1) level of Alg. 1: exact solve through a dense inverse of the
  * free-node matrix, or a fixed-degree Jacobi-preconditioned Chebyshev
@@ -237,6 +241,48 @@ enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, 
  * results are discarded. */
 int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps, double* ms_per_launch,
                     void* stream);
+
+/* ---- learned warm start (a small multilayer perceptron, FP32) -------------
+ * The network maps per-node features of the coarsest (P = 1) level to the
+ * correction of the extrapolated guess; pmg_solve prolongates it to the finest
+ * level with the multigrid transfers.  Features of node g = (vertex v,
+ * level z) with gf its finest-level twin and top the finest surface node of
+ * column v: [z/L, x, y scaled to [-1,1], distance to the nearest circle,
+ * p1[gf]-p2[gf], surf[v]-(2 p1[top]-p2[top]), p1[top]-p2[top]]; target
+ * pnow[gf] - (2 p1[gf] - p2[gf]).  Layers: dense y = x W + b (W fan_in x fan_out
+ * row-major), SiLU on hidden layers, linear scalar output; MSE loss; Adam
+ * (0.9, 0.999, 1e-8) with bias correction.  Flat parameter order: W_0, b_0,
+ * W_1, b_1, ...  pmg_net_forward / pmg_net_loss_grad act on raw inputs; the
+ * solve and pmg_net_train use the normalisation (inputs (x - mean) * inv_std,
+ * output times tscale) fitted by pmg_net_train. */
+/* Features (device float [n1][7]) and, if T and pnow are given, targets
+ * (device float [n1]) of the coarsest nodes; surf device [n_surface], p1, p2,
+ * pnow device [n_dof] of the finest level. */
+int pmg_features(pmg_ctx* ctx, const double* surf, const double* p1, const double* p2, const double* pnow,
+                 float* X, float* T, void* stream);
+/* Network with `depth` hidden layers of `width` units on the context's GPU;
+ * weights uniform in +-1/sqrt(fan_in) from the counter generator of `seed`. */
+int pmg_net_create(const pmg_ctx* ctx, int32_t width, int32_t depth, uint64_t seed, pmg_net** out);
+void pmg_net_destroy(pmg_net* net);
+int pmg_net_size(const pmg_net* net, int64_t* n_params, int32_t* d_in, int32_t* width, int32_t* depth);
+/* host copies of the parameters and the normalisation (any pointer may be NULL) */
+int pmg_net_get_params(const pmg_net* net, float* theta, float* mean, float* inv_std, double* tscale);
+int pmg_net_set_params(pmg_net* net, const float* theta, const float* mean, const float* inv_std, double tscale);
+/* raw network output y (device [rows]) of inputs X (device [rows][d_in]) */
+int pmg_net_forward(pmg_net* net, const float* X, int64_t rows, float* y, void* stream);
+/* raw MSE loss of a batch and its gradient (host [n_params], nullable); the
+ * gradient also stays on the device for pmg_net_adam_step */
+int pmg_net_loss_grad(pmg_net* net, const float* X, const float* T, int32_t rows, double* loss, float* grad,
+                      void* stream);
+int pmg_net_adam_step(pmg_net* net, double lr, void* stream);
+/* fit the normalisation to (X, T) (device [rows][d_in], [rows]) and run `steps`
+ * Adam steps on mini-batches drawn with the counter generator; final_loss =
+ * mean normalised loss of the last 20 steps */
+int pmg_net_train(pmg_net* net, const float* X, const float* T, int64_t rows, int32_t steps, int32_t batch,
+                  double lr, uint64_t seed, double* final_loss, void* stream);
+/* versioned binary file with an FNV-1a checksum; load requires equal shapes */
+int pmg_net_save(const pmg_net* net, const char* path);
+int pmg_net_load(pmg_net* net, const char* path);
 
 #ifdef __cplusplus
 }

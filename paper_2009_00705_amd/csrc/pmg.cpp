@@ -10,6 +10,8 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
+#include <fstream>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -20,6 +22,7 @@
 
 #include "kernels.hpp"
 #include "kernels_mfma.hpp"
+#include "mlp.hpp"
 #include "mesh.hpp"
 #include "pmg.h"
 #include "refelem.hpp"
@@ -155,6 +158,7 @@ struct pmg_ctx {
   double *s_phiD = nullptr, *s_f = nullptr, *s_u = nullptr, *s_r = nullptr, *s_p = nullptr, *s_q = nullptr,
          *s_z = nullptr, *s_rold = nullptr, *s_y = nullptr;
   float *s_r32 = nullptr, *s_z32 = nullptr;
+  float* feat_cst = nullptr; // [n1][4] constant features of the coarsest nodes
   int lowp = pmg::G_F32;      // G storage of the float V-cycle
   int n_vcycles = 0, n_fine_applies = 0;
   std::vector<void*> allocs;
@@ -172,6 +176,36 @@ struct pmg_ctx {
   ~pmg_ctx() {
     for (void* p : allocs) (void)hipFree(p);
     if (scal_h) (void)hipHostFree(scal_h);
+  }
+};
+
+struct pmg_net {
+  std::string err;
+  int device = 0;
+  int din = pmg::NET_DIN, width = 0, depth = 0;
+  int64_t np = 0;
+  std::vector<int> fin, fout;
+  std::vector<int64_t> woff, boff;
+  float *theta = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  int t = 0;
+  std::vector<float> mean_h, istd_h;
+  double tscale = 1.0;
+  float *mean = nullptr, *istd = nullptr;
+  int bmax = 0;
+  float *Xb = nullptr, *Tb = nullptr, *dy = nullptr, *dzA = nullptr, *dzB = nullptr, *X1 = nullptr, *Xn = nullptr,
+        *y1 = nullptr;
+  int64_t n1cap = 0;
+  std::vector<float*> Z, H;
+  double *partial = nullptr, *scal = nullptr, *losses = nullptr;
+  int nloss = 0;
+  std::vector<void*> allocs;
+  template <typename T> T* A(size_t n) {
+    T* p = pmg::dalloc<T>(n);
+    allocs.push_back(p);
+    return p;
+  }
+  ~pmg_net() {
+    for (void* p : allocs) (void)hipFree(p);
   }
 };
 
@@ -866,17 +900,143 @@ static void fine_apply(pmg_ctx* c, const double* x, double* y, const double* dot
     assemble<double>(c, 0, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
 }
 
-static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, int guess, const double* const* hist,
-                 double rtol, double atol, int imax, pmg_stats* stats, hipStream_t st) {
+// ---------------------------------------------------------------------------
+// warm-start network
+// ---------------------------------------------------------------------------
+static void net_reserve(pmg_net* n, int B) {
+  if (B <= n->bmax) return;
+  for (float* p : n->Z) (void)p;
+  n->bmax = B;
+  n->Xb = n->A<float>(size_t(B) * n->din);
+  n->Tb = n->A<float>(B);
+  n->dy = n->A<float>(B);
+  n->dzA = n->A<float>(size_t(B) * n->width);
+  n->dzB = n->A<float>(size_t(B) * n->width);
+  n->Z.assign(n->fin.size(), nullptr);
+  n->H.assign(n->fin.size(), nullptr);
+  for (size_t l = 0; l < n->fin.size(); ++l) {
+    n->Z[l] = n->A<float>(size_t(B) * n->fout[l]);
+    n->H[l] = n->A<float>(size_t(B) * n->fout[l]);
+  }
+}
+
+// forward of B rows of X (device, row-major [B][din]); output n->H.back() [B]
+static void net_forward(pmg_net* n, const float* X, int B, hipStream_t st) {
+  net_reserve(n, B);
+  const float* h = X;
+  const int L = int(n->fin.size());
+  for (int l = 0; l < L; ++l) {
+    launch_gemm(B, n->fout[l], n->fin[l], h, n->fin[l], 1, n->theta + n->woff[l], n->fout[l], 1,
+                n->theta + n->boff[l], n->Z[l], n->H[l], n->fout[l], l + 1 < L, st);
+    h = n->H[l];
+  }
+}
+
+// loss and gradient (into n->grad) of B rows; loss sum of squares -> *slot
+static void net_backward(pmg_net* n, const float* X, const float* T, int B, double* loss_slot, hipStream_t st) {
+  net_forward(n, X, B, st);
+  const int L = int(n->fin.size());
+  launch_mse(n->H[L - 1], T, n->dy, B, n->partial, st);
+  launch_red_final(n->partial, MLP_RED, loss_slot, st);
+  const float* dz = n->dy;
+  for (int l = L - 1; l >= 0; --l) {
+    const float* hin = l == 0 ? X : n->H[l - 1];
+    launch_gemm(n->fin[l], n->fout[l], B, hin, 1, n->fin[l], dz, n->fout[l], 1, nullptr, nullptr,
+                n->grad + n->woff[l], n->fout[l], false, st);
+    launch_colsum(dz, B, n->fout[l], n->grad + n->boff[l], st);
+    if (l > 0) {
+      launch_gemm(B, n->fin[l], n->fout[l], dz, n->fout[l], 1, n->theta + n->woff[l], 1, n->fout[l], nullptr,
+                  nullptr, n->dzA, n->fin[l], false, st);
+      launch_silu_back(n->dzA, n->Z[l - 1], n->dzB, int64_t(B) * n->fin[l], st);
+      dz = n->dzB;
+    }
+  }
+}
+
+// constant features of the coarsest nodes: sigma, x and y in [-1,1], distance to the nearest circle
+static void build_feat_cst(pmg_ctx* c) {
+  if (c->feat_cst) return;
+  Level& C = c->lv[c->nl - 1];
+  const int64_t n1 = C.num.n_dof;
+  double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
+  for (int v = 0; v < c->mesh.nv; ++v) {
+    xmin = std::min(xmin, c->mesh.xy[2 * v]);
+    xmax = std::max(xmax, c->mesh.xy[2 * v]);
+    ymin = std::min(ymin, c->mesh.xy[2 * v + 1]);
+    ymax = std::max(ymax, c->mesh.xy[2 * v + 1]);
+  }
+  std::vector<float> f(size_t(n1) * 4);
+  for (int64_t g = 0; g < n1; ++g) {
+    const int64_t v = g / C.num.nz;
+    const int z = int(g - v * C.num.nz);
+    const double x = c->mesh.xy[2 * v], y = c->mesh.xy[2 * v + 1];
+    double dist = 0.0;
+    for (size_t k = 0; k * 3 < c->mesh.circle.size(); ++k) {
+      const double d = std::hypot(x - c->mesh.circle[3 * k], y - c->mesh.circle[3 * k + 1]) - c->mesh.circle[3 * k + 2];
+      dist = (k == 0) ? d : std::min(dist, d);
+    }
+    f[4 * g + 0] = float(double(z) / double(C.num.nz - 1));
+    f[4 * g + 1] = float(2.0 * (x - xmin) / std::max(xmax - xmin, 1e-300) - 1.0);
+    f[4 * g + 2] = float(2.0 * (y - ymin) / std::max(ymax - ymin, 1e-300) - 1.0);
+    f[4 * g + 3] = float(dist);
+  }
+  c->feat_cst = c->U(f);
+}
+
+static void features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* pnow,
+                     float* X, float* T, hipStream_t st) {
+  build_feat_cst(c);
+  Level& C = c->lv[c->nl - 1];
+  Level& F = c->lv[0];
+  launch_features(C.num.n_dof, int(C.num.nz), int(F.num.nz), F.P, c->feat_cst, surf, p1, p2, pnow, X, T, st);
+}
+
+// learned correction of the extrapolation, prolongated to the finest level: out (free nodes)
+static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const double* p1, const double* p2,
+                          double* out, hipStream_t st) {
+  Level& C = c->lv[c->nl - 1];
+  const int64_t n1 = C.num.n_dof;
+  if (n->n1cap < n1) {
+    n->X1 = n->A<float>(size_t(n1) * n->din);
+    n->Xn = n->A<float>(size_t(n1) * n->din);
+    n->y1 = n->A<float>(n1);
+    n->n1cap = n1;
+  }
+  features(c, surf, p1, p2, nullptr, n->X1, nullptr, st);
+  launch_normalize(n->X1, n1, n->din, n->mean, n->istd, n->Xn, st);
+  const int L = int(n->fin.size());
+  const int chunk = 16384;
+  for (int64_t r0 = 0; r0 < n1; r0 += chunk) {
+    const int B = int(std::min<int64_t>(chunk, n1 - r0));
+    net_forward(n, n->Xn + r0 * n->din, B, st);
+    launch_copy<float>(n->H[L - 1], n->y1 + r0, B, st);
+  }
+  // coarsest correction (zero on Dirichlet nodes), prolongated level by level
+  double* cur = c->nl > 1 ? C.u64 : out;
+  launch_scale_out(n->y1, n->tscale, n1, c->s_y, st);
+  launch_mask<double>(C.view, c->s_y, cur, st);
+  for (int i = c->nl - 2; i >= 0; --i) {
+    double* dst = i == 0 ? out : c->lv[i].u64;
+    launch_prolong_elem<double>(c->lv[i].view, c->lv[i + 1].view, c->lv[i].pit64, c->lv[i].piz64, cur, c->Y, st);
+    launch_assemble<double>(c->lv[i].view, OP_AVG_STORE, c->Y, dst, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
+    cur = dst;
+  }
+}
+
+static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, int guess, pmg_net* net,
+                 const double* const* hist, double rtol, double atol, int imax, pmg_stats* stats, hipStream_t st) {
   Level& F = c->lv[0];
   const int64_t N = F.num.n_dof;
-  (void)hist;
+  int fallback = 0;
   if (!surf && !bc) throw Error(PMG_EINVAL, "no Dirichlet data (phi_surf and phi_bc are NULL)");
   if (!bc && c->opt.dirichlet_tags) throw Error(PMG_EINVAL, "lateral Dirichlet tags need phi_bc");
   if (!phi) throw Error(PMG_EINVAL, "phi is NULL");
   if (!(rtol >= 0) || !(atol >= 0) || imax < 0) throw Error(PMG_EINVAL, "bad tolerance");
-  if (guess != PMG_GUESS_GIVEN && guess != PMG_GUESS_ZERO)
-    throw Error(PMG_EINVAL, "guess mode not available");
+  if (guess < PMG_GUESS_GIVEN || guess > PMG_GUESS_EXTRAP) throw Error(PMG_EINVAL, "unknown guess mode");
+  if ((guess == PMG_GUESS_LEARNED || guess == PMG_GUESS_EXTRAP) && (!hist || !hist[0] || !hist[1]))
+    throw Error(PMG_EINVAL, "the learned and extrapolated guesses need the two previous solutions");
+  if (guess == PMG_GUESS_LEARNED && !net) throw Error(PMG_EINVAL, "learned guess without a network");
+  if (guess == PMG_GUESS_LEARNED && !surf) throw Error(PMG_EINVAL, "learned guess needs phi_surf");
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
@@ -898,6 +1058,22 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     launch_finalize(c->partial, c->scal, S_TMP1, FIN_SET, st);
     if (read_scal(c, S_TMP1, st) != 0.0) throw Error(PMG_ENONFINITE, "non-finite initial guess");
     launch_merge_free(F.view, phi, nullptr, c->s_u, st);
+  } else if (guess == PMG_GUESS_EXTRAP || guess == PMG_GUESS_LEARNED) {
+    launch_extrap(hist[0], hist[1], c->s_y, N, st);
+    launch_mask<double>(F.view, c->s_y, c->s_u, st);
+    if (guess == PMG_GUESS_LEARNED) {
+      // candidate = extrapolation + learned correction; keep it only if its residual is smaller
+      learned_guess(c, net, surf, hist[0], hist[1], c->s_q, st);
+      launch_axpy(c->s_q, c->s_u, 1.0, N, st);
+      ax_elem<double>(c, 0, c->s_u, st);
+      assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+      const double r_ex = dot_host(c, c->s_r, c->s_r, N, st);
+      ax_elem<double>(c, 0, c->s_q, st);
+      assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+      const double r_ln = dot_host(c, c->s_r, c->s_r, N, st);
+      if (std::isfinite(r_ln) && r_ln < r_ex) launch_copy<double>(c->s_q, c->s_u, N, st);
+      else fallback = 1;
+    }
   } else {
     launch_fill<double>(c->s_u, 0.0, N, st);
   }
@@ -970,6 +1146,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
   (void)hipEventDestroy(ev0);
   (void)hipEventDestroy(ev1);
   if (status == PMG_OK && hist_r.back() > tol) status = PMG_NOT_CONVERGED;
+  if (status == PMG_OK && fallback) status = PMG_FALLBACK_USED;
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));
     stats->iters = it;
@@ -981,6 +1158,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     stats->t_guess_ms = tg;
     stats->n_vcycles = c->n_vcycles;
     stats->n_fine_applies = c->n_fine_applies;
+    stats->fallback = fallback;
   }
   if (status < 0) throw Error(status, status == PMG_EBREAKDOWN ? "breakdown: p^T A p <= 0 or z^T r <= 0"
                                                                : "non-finite iterate");
@@ -1378,11 +1556,11 @@ int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* 
               const pmg_net* net, const double* const* hist_phi, double rtol, double atol, int32_t imax,
               pmg_stats* stats, void* stream) {
   if (!c) return PMG_EINVAL;
-  (void)net;
   int rc = PMG_OK;
   PMG_TRY(c, {
     need_device(c);
-    rc = solve(c, phi_surf, phi_bc, phi, guess_mode, hist_phi, rtol, atol, imax, stats, S(stream));
+    rc = solve(c, phi_surf, phi_bc, phi, guess_mode, const_cast<pmg_net*>(net), hist_phi, rtol, atol, imax, stats,
+               S(stream));
   });
   return rc;
 }
@@ -1449,6 +1627,266 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
     *ms = double(t) / reps;
   });
   return PMG_OK;
+}
+
+int pmg_features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* pnow, float* X,
+                 float* T, void* stream) {
+  if (!c || !surf || !p1 || !p2 || !X || (T && !pnow)) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    features(c, surf, p1, p2, pnow, X, T, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_net_create(const pmg_ctx* c, int32_t width, int32_t depth, uint64_t seed, pmg_net** out) {
+  if (!c || !out || width < 1 || width > 1024 || depth < 0 || depth > 8) return PMG_EINVAL;
+  pmg_net* n = nullptr;
+  try {
+    if (c->host_only) throw Error(PMG_ESTATE, "host-only context");
+    HIPCHK(hipSetDevice(c->device));
+    n = new pmg_net();
+    n->device = c->device;
+    n->width = width;
+    n->depth = depth;
+    std::vector<int> dims{n->din};
+    for (int l = 0; l < depth; ++l) dims.push_back(width);
+    dims.push_back(1);
+    int64_t o = 0;
+    for (size_t l = 0; l + 1 < dims.size(); ++l) {
+      n->fin.push_back(dims[l]);
+      n->fout.push_back(dims[l + 1]);
+      n->woff.push_back(o);
+      o += int64_t(dims[l]) * dims[l + 1];
+      n->boff.push_back(o);
+      o += dims[l + 1];
+    }
+    n->np = o;
+    // uniform(-1/sqrt(fan_in), 1/sqrt(fan_in)) weights from the counter generator, zero biases
+    std::vector<float> th(n->np, 0.0f);
+    for (size_t l = 0; l < n->fin.size(); ++l) {
+      const double s = 1.0 / std::sqrt(double(n->fin[l]));
+      for (int64_t k = 0; k < int64_t(n->fin[l]) * n->fout[l]; ++k)
+        th[n->woff[l] + k] = float((2.0 * splitmix_unit(seed, uint64_t(n->woff[l] + k)) - 1.0) * s);
+    }
+    n->theta = n->A<float>(n->np);
+    n->grad = n->A<float>(n->np);
+    n->m = n->A<float>(n->np);
+    n->v = n->A<float>(n->np);
+    HIPCHK(hipMemcpy(n->theta, th.data(), n->np * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(n->m, 0, n->np * sizeof(float)));
+    HIPCHK(hipMemset(n->v, 0, n->np * sizeof(float)));
+    n->mean_h.assign(n->din, 0.0f);
+    n->istd_h.assign(n->din, 1.0f);
+    n->mean = n->A<float>(n->din);
+    n->istd = n->A<float>(n->din);
+    HIPCHK(hipMemcpy(n->mean, n->mean_h.data(), n->din * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(n->istd, n->istd_h.data(), n->din * sizeof(float), hipMemcpyHostToDevice));
+    n->partial = n->A<double>(MLP_RED);
+    n->scal = n->A<double>(64);
+    net_reserve(n, 1024);
+    *out = n;
+    return PMG_OK;
+  } catch (const Error& e) {
+    g_err = e.what();
+    delete n;
+    return e.code;
+  } catch (const std::exception& e) {
+    g_err = e.what();
+    delete n;
+    return PMG_EINVAL;
+  }
+}
+
+void pmg_net_destroy(pmg_net* n) {
+  if (!n) return;
+  (void)hipSetDevice(n->device);
+  delete n;
+}
+
+int pmg_net_size(const pmg_net* n, int64_t* n_params, int32_t* d_in, int32_t* width, int32_t* depth) {
+  if (!n) return PMG_EINVAL;
+  if (n_params) *n_params = n->np;
+  if (d_in) *d_in = n->din;
+  if (width) *width = n->width;
+  if (depth) *depth = n->depth;
+  return PMG_OK;
+}
+
+int pmg_net_get_params(const pmg_net* n, float* theta, float* mean, float* inv_std, double* tscale) {
+  if (!n) return PMG_EINVAL;
+  try {
+    HIPCHK(hipSetDevice(n->device));
+    HIPCHK(hipDeviceSynchronize());
+    if (theta) HIPCHK(hipMemcpy(theta, n->theta, n->np * sizeof(float), hipMemcpyDeviceToHost));
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  }
+  if (mean) std::copy(n->mean_h.begin(), n->mean_h.end(), mean);
+  if (inv_std) std::copy(n->istd_h.begin(), n->istd_h.end(), inv_std);
+  if (tscale) *tscale = n->tscale;
+  return PMG_OK;
+}
+
+int pmg_net_set_params(pmg_net* n, const float* theta, const float* mean, const float* inv_std, double tscale) {
+  if (!n) return PMG_EINVAL;
+  try {
+    HIPCHK(hipSetDevice(n->device));
+    if (theta) HIPCHK(hipMemcpy(n->theta, theta, n->np * sizeof(float), hipMemcpyHostToDevice));
+    if (mean) n->mean_h.assign(mean, mean + n->din);
+    if (inv_std) n->istd_h.assign(inv_std, inv_std + n->din);
+    if (tscale > 0) n->tscale = tscale;
+    HIPCHK(hipMemcpy(n->mean, n->mean_h.data(), n->din * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(n->istd, n->istd_h.data(), n->din * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemset(n->m, 0, n->np * sizeof(float)));
+    HIPCHK(hipMemset(n->v, 0, n->np * sizeof(float)));
+    n->t = 0;
+  } catch (const Error& e) {
+    g_err = e.what();
+    return e.code;
+  }
+  return PMG_OK;
+}
+
+int pmg_net_forward(pmg_net* n, const float* X, int64_t rows, float* y, void* stream) {
+  if (!n || !X || !y || rows < 0) return PMG_EINVAL;
+  PMG_TRY(n, {
+    HIPCHK(hipSetDevice(n->device));
+    const int L = int(n->fin.size());
+    for (int64_t r0 = 0; r0 < rows; r0 += 16384) {
+      const int B = int(std::min<int64_t>(16384, rows - r0));
+      net_forward(n, X + r0 * n->din, B, S(stream));
+      launch_copy<float>(n->H[L - 1], y + r0, B, S(stream));
+    }
+  });
+  return PMG_OK;
+}
+
+int pmg_net_loss_grad(pmg_net* n, const float* X, const float* T, int32_t rows, double* loss, float* grad,
+                      void* stream) {
+  if (!n || !X || !T || rows < 1) return PMG_EINVAL;
+  PMG_TRY(n, {
+    HIPCHK(hipSetDevice(n->device));
+    hipStream_t st = S(stream);
+    net_backward(n, X, T, rows, n->scal, st);
+    double l = 0;
+    HIPCHK(hipMemcpyAsync(&l, n->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (grad) HIPCHK(hipMemcpyAsync(grad, n->grad, n->np * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (loss) *loss = l / rows;
+  });
+  return PMG_OK;
+}
+
+int pmg_net_adam_step(pmg_net* n, double lr, void* stream) {
+  if (!n || !(lr > 0)) return PMG_EINVAL;
+  PMG_TRY(n, {
+    HIPCHK(hipSetDevice(n->device));
+    n->t += 1;
+    launch_adam(n->theta, n->grad, n->m, n->v, n->np, lr, n->t, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_net_train(pmg_net* n, const float* X, const float* T, int64_t rows, int32_t steps, int32_t batch,
+                  double lr, uint64_t seed, double* final_loss, void* stream) {
+  if (!n || !X || !T || rows < 1 || steps < 1 || batch < 1 || !(lr > 0)) return PMG_EINVAL;
+  PMG_TRY(n, {
+    HIPCHK(hipSetDevice(n->device));
+    hipStream_t st = S(stream);
+    // normalisation from the training set: inputs to zero mean / unit variance, targets by their rms
+    double* stats = n->scal + 8;
+    launch_colstats(X, rows, n->din, stats, st);
+    launch_colstats(T, rows, 1, stats + 2 * n->din, st);
+    std::vector<double> h(2 * n->din + 2);
+    HIPCHK(hipMemcpyAsync(h.data(), stats, h.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int cc = 0; cc < n->din; ++cc) {
+      const double mu = h[2 * cc], var = std::max(h[2 * cc + 1] - mu * mu, 0.0);
+      n->mean_h[cc] = float(mu);
+      n->istd_h[cc] = float(var > 1e-30 ? 1.0 / std::sqrt(var) : 1.0);
+    }
+    n->tscale = std::sqrt(std::max(h[2 * n->din + 1], 1e-300));
+    HIPCHK(hipMemcpy(n->mean, n->mean_h.data(), n->din * sizeof(float), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(n->istd, n->istd_h.data(), n->din * sizeof(float), hipMemcpyHostToDevice));
+    net_reserve(n, batch);
+    if (n->nloss < steps) {
+      n->losses = n->A<double>(steps);
+      n->nloss = steps;
+    }
+    for (int s = 0; s < steps; ++s) {
+      launch_gather_batch(X, T, rows, n->din, batch, seed, uint64_t(s), n->mean, n->istd, float(1.0 / n->tscale),
+                          n->Xb, n->Tb, st);
+      net_backward(n, n->Xb, n->Tb, batch, n->losses + s, st);
+      n->t += 1;
+      launch_adam(n->theta, n->grad, n->m, n->v, n->np, lr, n->t, st);
+    }
+    std::vector<double> ls(steps);
+    HIPCHK(hipMemcpyAsync(ls.data(), n->losses, steps * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const int tail = std::min(20, steps);
+    double acc = 0;
+    for (int s = steps - tail; s < steps; ++s) acc += ls[s] / batch;
+    if (final_loss) *final_loss = acc / tail;
+  });
+  return PMG_OK;
+}
+
+// file: "PMGNET01", din, width, depth, np, theta[np] (f32), mean[din], inv_std[din], tscale (f64), FNV-1a of all
+int pmg_net_save(const pmg_net* n, const char* path) {
+  if (!n || !path) return PMG_EINVAL;
+  std::vector<float> th(n->np);
+  if (pmg_net_get_params(n, th.data(), nullptr, nullptr, nullptr) != PMG_OK) return PMG_EDEVICE;
+  std::string buf("PMGNET01");
+  auto put = [&](const void* p, size_t k) { buf.append(static_cast<const char*>(p), k); };
+  const int32_t hdr[3] = {n->din, n->width, n->depth};
+  put(hdr, sizeof(hdr));
+  put(&n->np, sizeof(n->np));
+  put(th.data(), th.size() * sizeof(float));
+  put(n->mean_h.data(), n->din * sizeof(float));
+  put(n->istd_h.data(), n->din * sizeof(float));
+  put(&n->tscale, sizeof(double));
+  uint64_t hsh = 1469598103934665603ull;
+  for (unsigned char ch : buf) hsh = (hsh ^ ch) * 1099511628211ull;
+  put(&hsh, sizeof(hsh));
+  std::ofstream f(path, std::ios::binary);
+  if (!f) { g_err = "cannot open file"; return PMG_EINVAL; }
+  f.write(buf.data(), std::streamsize(buf.size()));
+  return f ? PMG_OK : PMG_EINVAL;
+}
+
+int pmg_net_load(pmg_net* n, const char* path) {
+  if (!n || !path) return PMG_EINVAL;
+  std::ifstream f(path, std::ios::binary);
+  if (!f) { g_err = "cannot open file"; return PMG_EINVAL; }
+  std::string buf((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+  const size_t need = 8 + 12 + 8 + n->np * 4 + 2 * size_t(n->din) * 4 + 8 + 8;
+  if (buf.size() != need || buf.compare(0, 8, "PMGNET01") != 0) { g_err = "not a matching network file"; return PMG_EINVAL; }
+  uint64_t hsh = 1469598103934665603ull;
+  for (size_t k = 0; k + 8 < buf.size(); ++k) hsh = (hsh ^ (unsigned char)buf[k]) * 1099511628211ull;
+  uint64_t stored;
+  std::memcpy(&stored, buf.data() + buf.size() - 8, 8);
+  if (stored != hsh) { g_err = "network file checksum mismatch"; return PMG_EINVAL; }
+  int32_t hdr[3];
+  int64_t np;
+  std::memcpy(hdr, buf.data() + 8, 12);
+  std::memcpy(&np, buf.data() + 20, 8);
+  if (hdr[0] != n->din || hdr[1] != n->width || hdr[2] != n->depth || np != n->np) {
+    g_err = "network shape mismatch";
+    return PMG_EINVAL;
+  }
+  const char* p = buf.data() + 28;
+  std::vector<float> th(np), mean(n->din), istd(n->din);
+  std::memcpy(th.data(), p, np * 4);
+  p += np * 4;
+  std::memcpy(mean.data(), p, n->din * 4);
+  p += n->din * 4;
+  std::memcpy(istd.data(), p, n->din * 4);
+  p += n->din * 4;
+  double ts;
+  std::memcpy(&ts, p, 8);
+  return pmg_net_set_params(n, th.data(), mean.data(), istd.data(), ts);
 }
 
 }  // extern "C"

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(HERE, "libpmg.so")
 PMG_OK, PMG_NOT_CONVERGED, PMG_FALLBACK_USED = 0, 1, 2
 PMG_FP64, PMG_MIXED_FP32, PMG_MIXED_BF16 = 0, 1, 2
 PMG_PCG, PMG_FPCG, PMG_PDC, PMG_MG = 0, 1, 2, 3
-PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED = 0, 1, 2
+PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED, PMG_GUESS_EXTRAP = 0, 1, 2, 3
 PMG_COARSE_EXACT, PMG_COARSE_CHEBYSHEV = 0, 1
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FALLBACK_USED", -1: "EINVAL", -2: "ENOMEM",
@@ -102,14 +102,31 @@ SIGNATURES = {
     "pmg_set_solver": (_I, [_VP, _I, _I]),
     "pmg_coarse_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_time_kernel": (_I, [_VP, _I, _I, _I, _I, C.POINTER(C.c_double), _VP]),
+    "pmg_features": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pmg_net_create": (_I, [_VP, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_VP)]),
+    "pmg_net_destroy": (None, [_VP]),
+    "pmg_net_size": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "pmg_net_get_params": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "pmg_net_set_params": (_I, [_VP, _VP, _VP, _VP, _D]),
+    "pmg_net_forward": (_I, [_VP, _VP, C.c_int64, _VP, _VP]),
+    "pmg_net_loss_grad": (_I, [_VP, _VP, _VP, C.c_int32, _VP, _VP, _VP]),
+    "pmg_net_adam_step": (_I, [_VP, _D, _VP]),
+    "pmg_net_train": (_I, [_VP, _VP, _VP, C.c_int64, C.c_int32, C.c_int32, _D, C.c_uint64, _VP, _VP]),
+    "pmg_net_save": (_I, [_VP, C.c_char_p]),
+    "pmg_net_load": (_I, [_VP, C.c_char_p]),
 }
 KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4}
 
 
 def lib():
-    """Load libpmg.so (built in-tree by ``paper_2009_00705_amd.build``)."""
+    """Load libpmg.so (built in-tree by ``paper_2009_00705_amd.build``).
+
+    torch is imported first: its bundled HIP runtime then also serves this
+    library (same soname), so one process never holds two HIP runtimes.
+    """
     global _lib
     if _lib is None:
+        import torch  # noqa: F401  (HIP runtime shared with the library)
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} not built: run `python -m paper_2009_00705_amd.build`")
         L = C.CDLL(LIB_PATH)
@@ -301,11 +318,16 @@ class Context:
                                       C.byref(ms), _stream(stream)))
         return ms.value
 
+    def features(self, surf, p1, p2, X, pnow=None, T=None, stream=None):
+        self._c(lib().pmg_features(self.h, _dptr(surf), _dptr(p1), _dptr(p2), _dptr(pnow), _dptr(X), _dptr(T),
+                                   _stream(stream)))
+
     def solve(self, phi, phi_surf=None, phi_bc=None, guess="zero", rtol=1e-8, atol=0.0, imax=500,
               net=None, hist=None, stream=None):
         """Solve in place into ``phi``; returns (status, stats dict)."""
         import torch
-        gm = {"given": PMG_GUESS_GIVEN, "zero": PMG_GUESS_ZERO, "learned": PMG_GUESS_LEARNED}[guess]
+        gm = {"given": PMG_GUESS_GIVEN, "zero": PMG_GUESS_ZERO, "learned": PMG_GUESS_LEARNED,
+              "extrap": PMG_GUESS_EXTRAP}[guess]
         st = Stats()
         hp = None
         if hist is not None:
@@ -317,3 +339,68 @@ class Context:
                              float(rtol), float(atol), int(imax), C.byref(st), _stream(stream))
         self._c(rc)
         return rc, st.as_dict()
+
+
+class Net:
+    """Owner of one ``pmg_net`` (the warm-start network of a context's GPU)."""
+
+    def __init__(self, ctx: Context, width: int = 160, depth: int = 3, seed: int = 0):
+        h = C.c_void_p()
+        _check(lib().pmg_net_create(ctx.h, width, depth, seed, C.byref(h)))
+        self.h = h
+        np_, din = C.c_int64(), C.c_int32()
+        lib().pmg_net_size(h, C.byref(np_), C.byref(din), None, None)
+        self.n_params, self.d_in, self.width, self.depth = np_.value, din.value, width, depth
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().pmg_net_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _c(self, rc):
+        return _check(rc)
+
+    def get_params(self):
+        th = np.empty(self.n_params, np.float32)
+        mean = np.empty(self.d_in, np.float32)
+        istd = np.empty(self.d_in, np.float32)
+        ts = C.c_double()
+        self._c(lib().pmg_net_get_params(self.h, th.ctypes.data_as(C.c_void_p), mean.ctypes.data_as(C.c_void_p),
+                                         istd.ctypes.data_as(C.c_void_p), C.byref(ts)))
+        return th, mean, istd, ts.value
+
+    def set_params(self, theta=None, mean=None, inv_std=None, tscale=0.0):
+        arrs = [None if a is None else np.ascontiguousarray(a, np.float32) for a in (theta, mean, inv_std)]
+        ptr = [None if a is None else a.ctypes.data_as(C.c_void_p) for a in arrs]
+        self._c(lib().pmg_net_set_params(self.h, *ptr, float(tscale)))
+
+    def forward(self, X, y, stream=None):
+        self._c(lib().pmg_net_forward(self.h, _dptr(X), X.shape[0], _dptr(y), _stream(stream)))
+
+    def loss_grad(self, X, T, stream=None):
+        g = np.empty(self.n_params, np.float32)
+        loss = C.c_double()
+        self._c(lib().pmg_net_loss_grad(self.h, _dptr(X), _dptr(T), X.shape[0], C.byref(loss),
+                                        g.ctypes.data_as(C.c_void_p), _stream(stream)))
+        return loss.value, g
+
+    def adam_step(self, lr, stream=None):
+        self._c(lib().pmg_net_adam_step(self.h, float(lr), _stream(stream)))
+
+    def train(self, X, T, steps=2000, batch=4096, lr=1e-3, seed=7, stream=None):
+        fl = C.c_double()
+        self._c(lib().pmg_net_train(self.h, _dptr(X), _dptr(T), X.shape[0], steps, batch, float(lr), seed,
+                                    C.byref(fl), _stream(stream)))
+        return fl.value
+
+    def save(self, path):
+        self._c(lib().pmg_net_save(self.h, str(path).encode()))
+
+    def load(self, path):
+        self._c(lib().pmg_net_load(self.h, str(path).encode()))

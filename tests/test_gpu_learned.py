@@ -1,0 +1,176 @@
+"""GPU parity of the warm-start network and of the learned guess.
+
+Tolerances: the network runs in FP32; gradients and outputs are compared with
+the FP64 oracle evaluated at the same (FP32-rounded) parameters and inputs:
+1e-4 relative to the largest entry.  Adam is checked against its formula
+applied to the GPU's own gradient (1e-6 relative).
+"""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_2009_00705_amd import workloads as W
+
+from gpu_common import dev, host
+
+pytestmark = pytest.mark.gpu
+
+D, WID, DEP = 7, 32, 2
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2009_00705_amd import pmg
+    c = pmg.Context(W.box_mesh(3, 2), P=4)
+    yield c
+    c.close()
+
+
+def _net(ctx, seed=3):
+    from paper_2009_00705_amd import pmg
+    net = pmg.Net(ctx, width=WID, depth=DEP, seed=seed)
+    th = mlp.init_params(D, WID, DEP, seed=seed).astype(np.float32)
+    th[-1] = 0.1                      # non-zero output bias
+    net.set_params(th)
+    return net, th.astype(np.float64)
+
+
+def _data(n, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((n, D)).astype(np.float32)
+    T = rng.standard_normal(n).astype(np.float32)
+    return X, T
+
+
+def test_net_size_matches_oracle(ctx):
+    from paper_2009_00705_amd import pmg
+    net = pmg.Net(ctx, width=WID, depth=DEP)
+    assert net.n_params == mlp.n_params(D, WID, DEP) and net.d_in == D
+
+
+def test_forward_and_gradient_parity(ctx):
+    import torch
+    net, th = _net(ctx)
+    for n in (1, 37, 256, 1000):
+        X, T = _data(n, n)
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        net.forward(dev(X), y)
+        yo, _ = mlp.forward(th, X.astype(np.float64), D, WID, DEP)
+        assert np.abs(host(y) - yo).max() <= 1e-4 * max(1.0, np.abs(yo).max())
+        loss, g = net.loss_grad(dev(X), dev(T))
+        lo, go = mlp.loss_and_grad(th, X.astype(np.float64), T.astype(np.float64), D, WID, DEP)
+        assert abs(loss - lo) <= 1e-4 * lo
+        assert np.abs(g - go).max() <= 1e-4 * np.abs(go).max(), n
+
+
+def test_adam_step_matches_formula(ctx):
+    net, th = _net(ctx, seed=5)
+    X, T = _data(200, 9)
+    m = np.zeros_like(th)
+    v = np.zeros_like(th)
+    cur = net.get_params()[0].astype(np.float64)
+    for t in range(1, 4):
+        _, g = net.loss_grad(dev(X), dev(T))
+        g = g.astype(np.float64)
+        net.adam_step(1e-3)
+        m = 0.9 * m + 0.1 * g
+        v = 0.999 * v + 0.001 * g * g
+        want = cur - 1e-3 * (m / (1 - 0.9 ** t)) / (np.sqrt(v / (1 - 0.999 ** t)) + 1e-8)
+        got = net.get_params()[0].astype(np.float64)
+        np.testing.assert_allclose(got, want, atol=1e-6 * np.abs(want).max() + 1e-9)
+        cur = got
+
+
+def test_save_load_roundtrip(ctx, tmp_path):
+    from paper_2009_00705_amd import pmg
+    net, _ = _net(ctx)
+    net.set_params(mean=np.arange(D, dtype=np.float32), inv_std=np.ones(D, np.float32) * 2, tscale=3.5)
+    p = tmp_path / "net.bin"
+    net.save(p)
+    other = pmg.Net(ctx, width=WID, depth=DEP, seed=99)
+    other.load(p)
+    a, b = net.get_params(), other.get_params()
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(np.asarray(x), np.asarray(y))
+    raw = bytearray(p.read_bytes())
+    raw[40] ^= 0xFF
+    p.write_bytes(bytes(raw))
+    with pytest.raises(pmg.PmgError):
+        other.load(p)
+
+
+def test_features_match_definition(ctx):
+    import torch
+    info0, info1 = ctx.levels[0], ctx.levels[-1]
+    n0, n1 = info0["n_dof"], info1["n_dof"]
+    rng = np.random.default_rng(0)
+    p1, p2, pn = (rng.standard_normal(n0) for _ in range(3))
+    surf = rng.standard_normal(info0["n_surface"])
+    X = torch.empty((n1, D), dtype=torch.float32, device="cuda")
+    T = torch.empty(n1, dtype=torch.float32, device="cuda")
+    ctx.features(dev(surf), dev(p1), dev(p2), X, pnow=dev(pn), T=T)
+    m = W.box_mesh(3, 2)
+    P, L = 4, 2
+    nz0, nz1 = L * P + 1, L + 1
+    g = np.arange(n1)
+    v, z = g // nz1, g % nz1
+    gf = v * nz0 + z * P
+    top = v * nz0 + nz0 - 1
+    xy = m["xy"][v]
+    want = np.stack([z / L, 2 * xy[:, 0] / (2 * np.pi) - 1, 2 * xy[:, 1] / (2 * np.pi) - 1, np.zeros(n1),
+                     p1[gf] - p2[gf], surf[v] - (2 * p1[top] - p2[top]), p1[top] - p2[top]], axis=1)
+    np.testing.assert_allclose(host(X), want, atol=2e-6 * np.abs(want).max())
+    np.testing.assert_allclose(host(T), pn[gf] - (2 * p1[gf] - p2[gf]), atol=2e-6 * np.abs(pn).max() * 3)
+
+
+def test_learned_guess_on_a_short_history():
+    """Train on a short wave history and check the learned guess: correct
+    solution, initial residual never worse than the extrapolation (fallback),
+    and at most as many iterations as the extrapolated guess."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    mesh = W.box_mesh(4, 2)
+    ctx = pmg.Context(mesh, P=4)
+    wg = W.WaveGroup(n_steps=24)
+    xy = ctx.surface_xy()
+    n0 = ctx.levels[0]["n_dof"]
+    n1 = ctx.levels[-1]["n_dof"]
+    sols, surfs = [], []
+    for n in range(24):
+        eta, phis = wg.surface(xy[:, 0], n)
+        ctx.set_surface(dev(eta))
+        phi = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        guess = "extrap" if n >= 2 else "zero"
+        hist = [sols[-1], sols[-2]] if n >= 2 else None
+        rc, st = ctx.solve(phi, phi_surf=dev(phis), guess=guess, hist=hist, rtol=1e-10)
+        assert rc == 0
+        sols.append(phi)
+        surfs.append(dev(phis))
+    # training set from steps 2..17
+    Xs, Ts = [], []
+    for n in range(2, 18):
+        X = torch.empty((n1, 7), dtype=torch.float32, device="cuda")
+        T = torch.empty(n1, dtype=torch.float32, device="cuda")
+        ctx.features(surfs[n], sols[n - 1], sols[n - 2], X, pnow=sols[n], T=T)
+        Xs.append(X)
+        Ts.append(T)
+    X = torch.cat(Xs).contiguous()
+    T = torch.cat(Ts).contiguous()
+    net = pmg.Net(ctx, width=32, depth=2, seed=1)
+    loss = net.train(X, T, steps=600, batch=256, lr=2e-3)
+    assert np.isfinite(loss) and loss < 1.0
+    for n in range(18, 24):
+        eta, phis = wg.surface(xy[:, 0], n)
+        ctx.set_surface(dev(eta))
+        ref = sols[n]
+        hist = [sols[n - 1], sols[n - 2]]
+        pe = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        _, se = ctx.solve(pe, phi_surf=dev(phis), guess="extrap", hist=hist, rtol=1e-10)
+        pl = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        rc, sl = ctx.solve(pl, phi_surf=dev(phis), guess="learned", hist=hist, net=net, rtol=1e-10)
+        assert rc in (0, 2)
+        assert sl["res_hist"][0] <= se["res_hist"][0] * (1 + 1e-12)
+        assert sl["iters"] <= se["iters"]
+        assert (rc == 2) == bool(sl["fallback"])
+        assert torch.max(torch.abs(pl - ref)).item() <= 1e-8 * torch.max(torch.abs(ref)).item()
+    ctx.close()
