@@ -206,7 +206,9 @@ int pmg_vcycle(pmg_ctx* ctx, int precision, const void* r, void* z, void* stream
 /* Coarse solver in use: mode (pmg_coarse), Chebyshev degree and interval,
  * free unknowns of the coarsest level. */
 int pmg_coarse_info(const pmg_ctx* ctx, int* mode, int* degree, double* lmin, double* lmax, int64_t* n_free);
-/* Smoothing weights and coarse interval in use. */
+/* Smoothing weights and coarse interval in use.  Values set here (> 0) are
+ * kept by later pmg_set_surface calls instead of being re-estimated: the
+ * t = 0 parameters are reused along a time history (Sec. 6, strategy I). */
 int pmg_get_params(const pmg_ctx* ctx, double* omega /*[n_levels]*/, double* cheb_lmin, double* cheb_lmax);
 int pmg_set_params(pmg_ctx* ctx, const double* omega /*[n_levels] or NULL*/, double cheb_lmin, double cheb_lmax);
 

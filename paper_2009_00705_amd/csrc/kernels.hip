@@ -234,6 +234,8 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, 
       out[g] = s;
     } else if (OP == OP_STORE) {
       out[g] = dir ? T(0) : s;
+    } else if (OP == OP_AVG_RAW) {
+      out[g] = s / T((j1 - j0) * (p2 >= 0 ? 2 : 1));
     } else if (OP == OP_AVG_ADD || OP == OP_AVG_STORE) {
       const T m = T((j1 - j0) * (p2 >= 0 ? 2 : 1));
       const T v = dir ? T(0) : s / m;
@@ -281,6 +283,7 @@ void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a
     case OP_AVG_STORE: PMG_ASM(OP_AVG_STORE); break;
     case OP_CHEB: PMG_ASM(OP_CHEB); break;
     case OP_RAW: PMG_ASM(OP_RAW); break;
+    case OP_AVG_RAW: PMG_ASM(OP_AVG_RAW); break;
     default: break;
   }
 #undef PMG_ASM

@@ -45,7 +45,8 @@ enum AsmOp {
   OP_STORE_DOT = 4, // out = mask * sum; partial += a1 . out
   OP_AVG_STORE = 5, // out = mask * sum / multiplicity
   OP_CHEB = 6,      // Chebyshev step on (x=out, r=a1, d=a3): r -= sum; x += d_new ...
-  OP_RAW = 7        // out = sum (no mask)
+  OP_RAW = 7,       // out = sum (no mask)
+  OP_AVG_RAW = 8    // out = sum / multiplicity (no mask)
 };
 template <typename T>
 void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a1, const T* a2,

@@ -245,6 +245,23 @@ void launch_scale_out(const float* y, double s, int64_t n, double* out, hipStrea
   hipLaunchKernelGGL(k_scale_out, dim3(g < 1 ? 1 : g), dim3(256), 0, st, y, s, n, out);
 }
 
+// correction of the extrapolation at the coarsest surface nodes is known exactly:
+// delta = surf[v] - (2 p1[top] - p2[top])
+__global__ void k_corr_surface(int64_t n1, int nz1, int nzf, const double* __restrict__ surf,
+                               const double* __restrict__ p1, const double* __restrict__ p2,
+                               double* __restrict__ delta) {
+  for (int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x; v * nz1 < n1; v += int64_t(gridDim.x) * 256) {
+    const int64_t top = v * nzf + (nzf - 1);
+    delta[v * nz1 + (nz1 - 1)] = surf[v] - (2.0 * p1[top] - p2[top]);
+  }
+}
+void launch_corr_surface(int64_t n1, int nz1, int nzf, const double* surf, const double* p1, const double* p2,
+                         double* delta, hipStream_t st) {
+  int64_t g = (n1 / nz1 + 255) / 256;
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_corr_surface, dim3(g < 1 ? 1 : g), dim3(256), 0, st, n1, nz1, nzf, surf, p1, p2, delta);
+}
+
 // out = 2 p1 - p2
 __global__ void k_extrap(const double* __restrict__ p1, const double* __restrict__ p2, double* __restrict__ out,
                          int64_t n) {

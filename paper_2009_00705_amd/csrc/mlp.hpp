@@ -34,6 +34,8 @@ void launch_colstats(const float* X, int64_t n, int d, double* out, hipStream_t 
 void launch_features(int64_t n1, int nz1, int nzf, int Pf, const float* cst, const double* surf, const double* p1,
                      const double* p2, const double* pnow, float* X, float* T, hipStream_t st);
 void launch_scale_out(const float* y, double s, int64_t n, double* out, hipStream_t st);
+void launch_corr_surface(int64_t n1, int nz1, int nzf, const double* surf, const double* p1, const double* p2,
+                         double* delta, hipStream_t st);
 void launch_extrap(const double* p1, const double* p2, double* out, int64_t n, hipStream_t st);
 
 }  // namespace pmg

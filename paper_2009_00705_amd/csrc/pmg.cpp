@@ -1011,14 +1011,15 @@ static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const doub
     net_forward(n, n->Xn + r0 * n->din, B, st);
     launch_copy<float>(n->H[L - 1], n->y1 + r0, B, st);
   }
-  // coarsest correction (zero on Dirichlet nodes), prolongated level by level
+  // coarsest correction: predicted inside, exact at the surface nodes (new surface data minus its
+  // extrapolation), prolongated level by level without masking; the caller keeps the free part
   double* cur = c->nl > 1 ? C.u64 : out;
-  launch_scale_out(n->y1, n->tscale, n1, c->s_y, st);
-  launch_mask<double>(C.view, c->s_y, cur, st);
+  launch_scale_out(n->y1, n->tscale, n1, cur, st);
+  launch_corr_surface(n1, int(C.num.nz), int(c->lv[0].num.nz), surf, p1, p2, cur, st);
   for (int i = c->nl - 2; i >= 0; --i) {
     double* dst = i == 0 ? out : c->lv[i].u64;
     launch_prolong_elem<double>(c->lv[i].view, c->lv[i + 1].view, c->lv[i].pit64, c->lv[i].piz64, cur, c->Y, st);
-    launch_assemble<double>(c->lv[i].view, OP_AVG_STORE, c->Y, dst, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
+    launch_assemble<double>(c->lv[i].view, OP_AVG_RAW, c->Y, dst, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
     cur = dst;
   }
 }
@@ -1064,7 +1065,8 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     if (guess == PMG_GUESS_LEARNED) {
       // candidate = extrapolation + learned correction; keep it only if its residual is smaller
       learned_guess(c, net, surf, hist[0], hist[1], c->s_q, st);
-      launch_axpy(c->s_q, c->s_u, 1.0, N, st);
+      launch_axpy(c->s_q, c->s_y, 1.0, N, st);            // extrapolation + correction
+      launch_mask<double>(F.view, c->s_q, c->s_q, st);
       ax_elem<double>(c, 0, c->s_u, st);
       assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
       const double r_ex = dot_host(c, c->s_r, c->s_r, N, st);
@@ -1547,8 +1549,10 @@ int pmg_set_params(pmg_ctx* c, const double* omega, double lmin, double lmax) {
       c->lv[i].omega = omega[i];
       c->lv[i].omega_user = omega[i];
     }
-  if (lmax > 0) c->cheb_lmax = lmax;
-  if (lmin > 0) c->cheb_lmin = lmin;
+  // kept by later pmg_set_surface calls (operators of t = 0 reused, as in the paper's strategy I)
+  if (lmax > 0) c->cheb_lmax = c->opt.cheb_lmax = lmax;
+  if (lmin > 0) c->cheb_lmin = c->opt.cheb_lmin = lmin;
+  if (lmin > 0 && lmax > 0 && c->opt.cheb_degree <= 0) c->opt.cheb_degree = c->cheb_k;
   return PMG_OK;
 }
 
