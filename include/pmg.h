@@ -236,11 +236,13 @@ int pmg_set_solver(pmg_ctx* ctx, int precision, int krylov);
 
 /* Kernels that pmg_time_kernel() can time in isolation. */
 enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, PMG_K_RESTRICT = 3,
-                  PMG_K_PROLONG = 4 };
+                  PMG_K_PROLONG = 4, PMG_K_COPY = 5 };
 /* Average duration (ms) of `reps` back-to-back launches of one kernel of
  * level `level` on `stream`, bracketed by hipEvents on that stream (for
  * roofline measurement).  The element operator reads the level's work vector;
- * results are discarded. */
+ * results are discarded.  PMG_K_COPY is a plain device copy of the level's
+ * FP64 vector (n_dof * 8 bytes read and written): the reference point that
+ * scales hardware byte counters. */
 int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps, double* ms_per_launch,
                     void* stream);
 

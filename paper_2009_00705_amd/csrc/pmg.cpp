@@ -1613,6 +1613,7 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
           else launch_prolong_elem<float>(L.view, C.view, L.pit32, L.piz32, C.r32, reinterpret_cast<float*>(c->Y), st);
           break;
         }
+        case PMG_K_COPY: launch_copy<double>(L.r64, c->s_y, L.num.n_dof, st); break;
         default: throw Error(PMG_EINVAL, "unknown kernel");
       }
     };

@@ -115,7 +115,7 @@ SIGNATURES = {
     "pmg_net_save": (_I, [_VP, C.c_char_p]),
     "pmg_net_load": (_I, [_VP, C.c_char_p]),
 }
-KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4}
+KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4, "copy": 5}
 
 
 def lib():
