@@ -905,7 +905,6 @@ static void fine_apply(pmg_ctx* c, const double* x, double* y, const double* dot
 // ---------------------------------------------------------------------------
 static void net_reserve(pmg_net* n, int B) {
   if (B <= n->bmax) return;
-  for (float* p : n->Z) (void)p;
   n->bmax = B;
   n->Xb = n->A<float>(size_t(B) * n->din);
   n->Tb = n->A<float>(B);
