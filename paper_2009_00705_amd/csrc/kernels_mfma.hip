@@ -103,6 +103,64 @@ template <int P> struct KS_LDS {
   static constexpr int R_WORDS = U_WORDS > S_WORDS ? U_WORDS : S_WORDS;
 };
 
+// Stage the 16 prisms' nodal values: U[c][a][el] = u[map2d[t][a] nz + layer P + c].
+// One thread per (a, el) pair: one map read, then the P+1 vertical values of
+// the column issued together (independent loads, a single wait).
+template <int P, typename T>
+__device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L, int nz, int64_t n_elem,
+                                        int64_t b, const T* __restrict__ u, T* __restrict__ sR) {
+  using D = MD<P>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NTH = 64 * N1;
+  for (int pr = threadIdx.x; pr < 16 * NPT; pr += NTH) {
+    const int a = pr >> 4, el = pr & 15;
+    const int64_t e = b * 16 + el;
+    T v[N1];
+    if (e < n_elem) {
+      const int te = int(e / L), layer = int(e - int64_t(te) * L);
+      const T* col = u + int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * P;
+#pragma unroll
+      for (int c = 0; c < N1; ++c) v[c] = col[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < N1; ++c) v[c] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < N1; ++c) sR[(c * NPT + a) * 16 + el] = v[c];
+  }
+}
+
+// Vertical transpose and output: y[c][a] of prism el = sum_k Bz[k][c] Yr[k][a] +
+// Dz[k][c] Yt[k][a], with S[k][h][a][el] in LDS.  One thread per (a, el) pair
+// reads its 2(P+1) partials once and writes the P+1 contiguous outputs of its
+// column slot in the E-layout [t][a][layer][c].
+template <int P, typename T>
+__device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, const T* __restrict__ sR,
+                                             const T* __restrict__ sV, T* __restrict__ Y) {
+  using D = MD<P>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NAT = D::NAT, NTH = 64 * N1;
+  for (int pr = threadIdx.x; pr < 16 * NPT; pr += NTH) {
+    const int a = pr >> 4, el = pr & 15;
+    const int64_t e = b * 16 + el;
+    if (e >= n_elem) continue;
+    T yr[N1], yt[N1];
+#pragma unroll
+    for (int kk = 0; kk < N1; ++kk) {
+      yr[kk] = sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el];
+      yt[kk] = sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
+    }
+    const int te = int(e / L), layer = int(e - int64_t(te) * L);
+    T* out = Y + ((size_t(te) * NPT + a) * L + layer) * N1;
+    // rolled: the coefficients are LDS broadcasts read per c, not 2(P+1)^2 registers
+#pragma unroll 1
+    for (int c = 0; c < N1; ++c) {
+      T y = 0;
+#pragma unroll
+      for (int kk = 0; kk < N1; ++kk) y += sV[kk * N1 + c] * yr[kk] + sV[N1 * N1 + kk * N1 + c] * yt[kk];
+      out[c] = y;
+    }
+  }
+}
+
 // geometric factors of one full tile (lane-native: 4 contiguous values per lane)
 template <typename T, typename TG>
 __device__ __forceinline__ void load_full(const TG* __restrict__ G, int64_t blk, int64_t mst, int t, int lane,
@@ -166,17 +224,8 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma4(const int32_t* __rest
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();  // previous batch's phase 2 done with sR
-    // phase 0: U[c][a][el] <- u, item (el, a, c) with c fastest
-    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
-      const int el = i / NP, r = i - el * NP, a = r / N1, c = r - a * N1;
-      const int64_t e = b * 16 + el;
-      T v = T(0);
-      if (e < n_elem) {
-        const int te = int(e / L), layer = int(e - int64_t(te) * L);
-        v = u[int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * P + c];
-      }
-      sR[(c * NPT + a) * 16 + el] = v;
-    }
+    // phase 0: U[c][a][el] <- u
+    stage_u<P, T>(map2d, L, nz, n_elem, b, u, sR);
     __syncthreads();
     // phase 1, stage 1: W[k][a], Wz[k][a] for a = 4s + g of element j
     T w[KS], wz[KS];
@@ -259,25 +308,14 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma4(const int32_t* __rest
         sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
       }
     __syncthreads();
-    // phase 2: y[el][c][a] = sum_k Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]; item (a, el, c), c fastest
-    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
-      const int c = i % N1, el = (i / N1) % 16, a = i / (16 * N1);
-      const int64_t e = b * 16 + el;
-      if (e >= n_elem) continue;
-      T y = 0;
-#pragma unroll
-      for (int kk = 0; kk < N1; ++kk)
-        y += sV[kk * N1 + c] * sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el] +
-             sV[N1 * N1 + kk * N1 + c] * sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
-      const int te = int(e / L), layer = int(e - int64_t(te) * L);
-      Y[((size_t(te) * NPT + a) * L + layer) * N1 + c] = y;
-    }
+    // phase 2: y[el][c][a] = sum_k Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]
+    vertical_out<P, T>(L, n_elem, b, sR, sV, Y);
   }
 }
 
 // BF16 operands, FP32 accumulation (K = 16)
 template <int P, typename TG>
-__global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
+__global__ __launch_bounds__(64 * (P + 1), P >= 8 ? 3 : 4) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
                                                              int64_t n_elem, int64_t n_batch,
                                                              const TG* __restrict__ Gnat,
                                                              const s4_t* __restrict__ tab2,
@@ -298,16 +336,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma_bf16(const int32_t* __
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();
-    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
-      const int el = i / NP, r = i - el * NP, a = r / N1, c = r - a * N1;
-      const int64_t e = b * 16 + el;
-      float v = 0.f;
-      if (e < n_elem) {
-        const int te = int(e / L), layer = int(e - int64_t(te) * L);
-        v = u[int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * P + c];
-      }
-      sR[(c * NPT + a) * 16 + el] = v;
-    }
+    stage_u<P, float>(map2d, L, nz, n_elem, b, u, sR);
     __syncthreads();
     s4_t w[KS16], wz[KS16];
 #pragma unroll
@@ -381,18 +410,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma_bf16(const int32_t* __
         sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
       }
     __syncthreads();
-    for (int i = threadIdx.x; i < 16 * NP; i += NTH) {
-      const int c = i % N1, el = (i / N1) % 16, a = i / (16 * N1);
-      const int64_t e = b * 16 + el;
-      if (e >= n_elem) continue;
-      float y = 0.f;
-#pragma unroll
-      for (int kk = 0; kk < N1; ++kk)
-        y += sV[kk * N1 + c] * sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el] +
-             sV[N1 * N1 + kk * N1 + c] * sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
-      const int te = int(e / L), layer = int(e - int64_t(te) * L);
-      Y[((size_t(te) * NPT + a) * L + layer) * N1 + c] = y;
-    }
+    vertical_out<P, float>(L, n_elem, b, sR, sV, Y);
   }
 }
 
