@@ -442,6 +442,11 @@ void launch_diag(const LevelView& lv, const double* mats, const double* G64, dou
 // ---------------------------------------------------------------------------
 // transfers: per-element interpolation Pi = Pi_z (x) Pi_tri
 // ---------------------------------------------------------------------------
+// Per-element transfers between consecutive orders, NEB prisms per round.
+// Loads: one thread per (prism, triangle node) pair reads the map once and
+// issues the whole vertical column of the prism at once.
+constexpr int XFER_NEB = 16;
+
 template <int PF, int PC, typename T>
 __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int nzc,
                                                       const int32_t* __restrict__ map2d_c,
@@ -450,33 +455,50 @@ __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int
                                                       const T* __restrict__ uc, T* __restrict__ Yf) {
   constexpr int N1F = PF + 1, NPTF = (PF + 1) * (PF + 2) / 2, NPF = NPTF * N1F;
   constexpr int N1C = PC + 1, NPTC = (PC + 1) * (PC + 2) / 2, NPC = NPTC * N1C;
-  constexpr int NEB = 8;
+  constexpr int NEB = XFER_NEB;
   __shared__ T sUc[NEB * NPC];
   __shared__ T sT1[NEB * N1C * NPTF];
   for (int64_t e0 = int64_t(blockIdx.x) * NEB; e0 < n_elem; e0 += int64_t(gridDim.x) * NEB) {
     const int ne = int(n_elem - e0 < NEB ? n_elem - e0 : NEB);
     __syncthreads();
-    for (int i = threadIdx.x; i < ne * NPC; i += 256) {
-      const int el = i / NPC, r = i - el * NPC, a = r / N1C, c = r - a * N1C;
+    // coarse nodal values U[el][c][a]
+    for (int pr = threadIdx.x; pr < ne * NPTC; pr += 256) {
+      const int el = pr / NPTC, a = pr - el * NPTC;
       const int64_t e = e0 + el;
       const int t = int(e / L), layer = int(e - int64_t(t) * L);
-      sUc[el * NPC + c * NPTC + a] = uc[int64_t(map2d_c[size_t(t) * NPTC + a]) * nzc + layer * PC + c];
+      const T* col = uc + int64_t(map2d_c[size_t(t) * NPTC + a]) * nzc + layer * PC;
+      T v[N1C];
+#pragma unroll
+      for (int c = 0; c < N1C; ++c) v[c] = col[c];
+#pragma unroll
+      for (int c = 0; c < N1C; ++c) sUc[el * NPC + c * NPTC + a] = v[c];
     }
     __syncthreads();
+    // triangle factor: T1[el][c][a] = sum_b Pi_tri[a][b] U[el][c][b]
     for (int i = threadIdx.x; i < ne * N1C * NPTF; i += 256) {
       const int el = i / (N1C * NPTF), r = i - el * N1C * NPTF, c = r / NPTF, a = r - c * NPTF;
       T s = 0;
+#pragma unroll 4
       for (int b = 0; b < NPTC; ++b) s += pit[a * NPTC + b] * sUc[el * NPC + c * NPTC + b];
       sT1[el * N1C * NPTF + c * NPTF + a] = s;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < ne * NPF; i += 256) {
-      const int el = i / NPF, r = i - el * NPF, a = r / N1F, c = r - a * N1F;
-      T s = 0;
-      for (int cc = 0; cc < N1C; ++cc) s += piz[c * N1C + cc] * sT1[el * N1C * NPTF + cc * NPTF + a];
+    // vertical factor and E-layout output: one thread per (prism, fine triangle node)
+    for (int pr = threadIdx.x; pr < ne * NPTF; pr += 256) {
+      const int el = pr / NPTF, a = pr - el * NPTF;
+      T t1[N1C];
+#pragma unroll
+      for (int cc = 0; cc < N1C; ++cc) t1[cc] = sT1[el * N1C * NPTF + cc * NPTF + a];
       const int64_t e = e0 + el;
       const int t = int(e / L), layer = int(e - int64_t(t) * L);
-      Yf[((size_t(t) * NPTF + a) * L + layer) * N1F + c] = s;
+      T* out = Yf + ((size_t(t) * NPTF + a) * L + layer) * N1F;
+#pragma unroll
+      for (int c = 0; c < N1F; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int cc = 0; cc < N1C; ++cc) s += piz[c * N1C + cc] * t1[cc];
+        out[c] = s;
+      }
     }
   }
 }
@@ -491,39 +513,60 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
                                                        const T* __restrict__ rf, T* __restrict__ Yc) {
   constexpr int N1F = PF + 1, NPTF = (PF + 1) * (PF + 2) / 2, NPF = NPTF * N1F;
   constexpr int N1C = PC + 1, NPTC = (PC + 1) * (PC + 2) / 2;
-  constexpr int NEB = 4;
+  constexpr int NEB = XFER_NEB;
   __shared__ T sRf[NEB * NPF];
   __shared__ T sT1[NEB * N1F * NPTC];
   for (int64_t e0 = int64_t(blockIdx.x) * NEB; e0 < n_elem; e0 += int64_t(gridDim.x) * NEB) {
     const int ne = int(n_elem - e0 < NEB ? n_elem - e0 : NEB);
     __syncthreads();
-    for (int i = threadIdx.x; i < ne * NPF; i += 256) {
-      const int el = i / NPF, r = i - el * NPF, a = r / N1F, c = r - a * N1F;
+    // fine values weighted by the inverse multiplicity (the transpose of the averaged
+    // prolongation), zero at Dirichlet nodes
+    for (int pr = threadIdx.x; pr < ne * NPTF; pr += 256) {
+      const int el = pr / NPTF, a = pr - el * NPTF;
       const int64_t e = e0 + el;
       const int t = int(e / L), layer = int(e - int64_t(t) * L);
       const int g2 = map2d_f[size_t(t) * NPTF + a];
-      const int z = layer * PF + c;
-      const bool dir = dir2d_f[g2] || (top_dir && z == nzf - 1);
+      const T* col = rf + int64_t(g2) * nzf + layer * PF;
+      T v[N1F];
+#pragma unroll
+      for (int c = 0; c < N1F; ++c) v[c] = col[c];
+      const bool dcol = dir2d_f[g2] != 0;
       const int cnt = inc_ptr_f[g2 + 1] - inc_ptr_f[g2];
-      const bool iface = (z % PF == 0) && z > 0 && z < nzf - 1;
-      const T m = T(cnt * (iface ? 2 : 1));
-      sRf[el * NPF + c * NPTF + a] = dir ? T(0) : rf[int64_t(g2) * nzf + z] / m;
+      const T inv1 = T(1) / T(cnt), inv2 = T(1) / T(2 * cnt);
+#pragma unroll
+      for (int c = 0; c < N1F; ++c) {
+        const int z = layer * PF + c;
+        const bool dir = dcol || (top_dir && z == nzf - 1);
+        const bool iface = (c == 0 && z > 0) || (c == PF && z < nzf - 1);
+        sRf[el * NPF + c * NPTF + a] = dir ? T(0) : v[c] * (iface ? inv2 : inv1);
+      }
     }
     __syncthreads();
+    // triangle factor: T1[el][c][b] = sum_a Pi_tri[a][b] R[el][c][a]
     for (int i = threadIdx.x; i < ne * N1F * NPTC; i += 256) {
       const int el = i / (N1F * NPTC), r = i - el * N1F * NPTC, c = r / NPTC, b = r - c * NPTC;
       T s = 0;
+#pragma unroll 4
       for (int a = 0; a < NPTF; ++a) s += pit[a * NPTC + b] * sRf[el * NPF + c * NPTF + a];
       sT1[el * N1F * NPTC + c * NPTC + b] = s;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < ne * NPTC * N1C; i += 256) {
-      const int el = i / (NPTC * N1C), r = i - el * NPTC * N1C, b = r / N1C, cc = r - b * N1C;
-      T s = 0;
-      for (int c = 0; c < N1F; ++c) s += piz[c * N1C + cc] * sT1[el * N1F * NPTC + c * NPTC + b];
+    // vertical factor and E-layout output: one thread per (prism, coarse triangle node)
+    for (int pr = threadIdx.x; pr < ne * NPTC; pr += 256) {
+      const int el = pr / NPTC, b = pr - el * NPTC;
+      T t1[N1F];
+#pragma unroll
+      for (int c = 0; c < N1F; ++c) t1[c] = sT1[el * N1F * NPTC + c * NPTC + b];
       const int64_t e = e0 + el;
       const int t = int(e / L), layer = int(e - int64_t(t) * L);
-      Yc[((size_t(t) * NPTC + b) * L + layer) * N1C + cc] = s;
+      T* out = Yc + ((size_t(t) * NPTC + b) * L + layer) * N1C;
+#pragma unroll
+      for (int cc = 0; cc < N1C; ++cc) {
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < N1F; ++c) s += piz[c * N1C + cc] * t1[c];
+        out[cc] = s;
+      }
     }
   }
 }
@@ -533,7 +576,7 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
 template <typename T>
 void launch_prolong_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* uc,
                          T* Yf, hipStream_t st) {
-  const int grid = grid_for(f.n_elem, 8, 262144);
+  const int grid = grid_for(f.n_elem, XFER_NEB, 262144);
 #define PMG_PRO(PFV, PCV)                                                                            \
   if (f.P == PFV && c.P == PCV) {                                                                    \
     hipLaunchKernelGGL((k_prolong_elem<PFV, PCV, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L,   \
@@ -547,7 +590,7 @@ void launch_prolong_elem(const LevelView& f, const LevelView& c, const T* pit, c
 template <typename T>
 void launch_restrict_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* rf,
                           T* Yc, hipStream_t st) {
-  const int grid = grid_for(f.n_elem, 4, 262144);
+  const int grid = grid_for(f.n_elem, XFER_NEB, 262144);
 #define PMG_RES(PFV, PCV)                                                                            \
   if (f.P == PFV && c.P == PCV) {                                                                    \
     hipLaunchKernelGGL((k_restrict_elem<PFV, PCV, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L,  \
@@ -858,4 +901,105 @@ template <typename T> void launch_axpy_t(T* y, const T* x, double a, int64_t n, 
 }
 template void launch_axpy_t<double>(double*, const double*, double, int64_t, hipStream_t);
 template void launch_axpy_t<float>(float*, const float*, double, int64_t, hipStream_t);
+}  // namespace pmg
+
+// ---------------------------------------------------------------------------
+// assembled P = 1 operator (coarse Chebyshev solve): element matrices, CSR
+// values by an ordered per-entry sum, and the fused Chebyshev step
+// ---------------------------------------------------------------------------
+namespace pmg {
+
+// Ae[e][i*6+j] = sum_q sum_ab G_ab[q] D_a[q][i] D_b[q][j]; G standard layout
+// [e][6][8] (rr, rs, rt, ss, st, tt), Dref[a][q][n] the reference derivatives
+__global__ __launch_bounds__(256) void k_p1_elem_mat(int64_t n_elem, const double* __restrict__ G,
+                                                     const double* __restrict__ Dref, double* __restrict__ Ae) {
+  constexpr int NQ = 8, NPE = 6;
+  const int comp[3][3] = {{0, 1, 2}, {1, 3, 4}, {2, 4, 5}};
+  for (int64_t id = int64_t(blockIdx.x) * 256 + threadIdx.x; id < n_elem * 36; id += int64_t(gridDim.x) * 256) {
+    const int64_t e = id / 36;
+    const int ij = int(id - e * 36), i = ij / NPE, j = ij - i * NPE;
+    const double* Ge = G + e * 6 * NQ;
+    double s = 0.0;
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double da = Dref[(a * NQ + q) * NPE + i];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) s += Ge[comp[a][b] * NQ + q] * da * Dref[(b * NQ + q) * NPE + j];
+      }
+    Ae[id] = s;
+  }
+}
+void launch_p1_elem_mat(int64_t n_elem, const double* G, const double* Dref, double* Ae, hipStream_t st) {
+  hipLaunchKernelGGL(k_p1_elem_mat, dim3(grid_for(n_elem * 36)), dim3(256), 0, st, n_elem, G, Dref, Ae);
+}
+
+// val[k] = sum of the element-matrix entries listed for entry k, in list order
+__global__ __launch_bounds__(256) void k_csr_sum(int64_t nnz, const int32_t* __restrict__ cp,
+                                                 const int64_t* __restrict__ cl, const double* __restrict__ Ae,
+                                                 double* __restrict__ v64, float* __restrict__ v32) {
+  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < nnz; k += int64_t(gridDim.x) * 256) {
+    double s = 0.0;
+    for (int m = cp[k]; m < cp[k + 1]; ++m) s += Ae[cl[m]];
+    v64[k] = s;
+    v32[k] = float(s);
+  }
+}
+void launch_csr_sum(int64_t nnz, const int32_t* cp, const int64_t* cl, const double* Ae, double* v64, float* v32,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_csr_sum, dim3(grid_for(nnz)), dim3(256), 0, st, nnz, cp, cl, Ae, v64, v32);
+}
+
+// Chebyshev start from x = 0: r = f, d = D^-1 f / theta, x = d
+template <typename T>
+__global__ __launch_bounds__(256) void k_cheb_start(int64_t n, const T* __restrict__ f, const T* __restrict__ dinv,
+                                                    T* __restrict__ r, T* __restrict__ d, T* __restrict__ x,
+                                                    T inv_theta) {
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
+    const T fv = f[g];
+    const T dv = inv_theta * dinv[g] * fv;
+    r[g] = fv;
+    d[g] = dv;
+    x[g] = dv;
+  }
+}
+// One Chebyshev step on the assembled free-node matrix (rows without entries are
+// Dirichlet rows): r -= A d_old; d_new = c0 d_old + c1 D^-1 r; x += d_new.
+// d is double-buffered because every row reads its neighbours' d_old.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cheb_csr(int64_t n, const int32_t* __restrict__ rp,
+                                                  const int32_t* __restrict__ ci, const T* __restrict__ val,
+                                                  const T* __restrict__ dinv, const T* __restrict__ d_old,
+                                                  T* __restrict__ d_new, T* __restrict__ r, T* __restrict__ x,
+                                                  T c0, T c1) {
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
+    const int j0 = rp[g], j1 = rp[g + 1];
+    if (j0 == j1) {
+      d_new[g] = T(0);
+      continue;
+    }
+    T s = 0;
+    for (int j = j0; j < j1; ++j) s += val[j] * d_old[ci[j]];
+    const T rn = r[g] - s;
+    r[g] = rn;
+    const T dn = c0 * d_old[g] + c1 * dinv[g] * rn;
+    d_new[g] = dn;
+    x[g] += dn;
+  }
+}
+template <typename T>
+void launch_cheb_start(int64_t n, const T* f, const T* dinv, T* r, T* d, T* x, double inv_theta, hipStream_t st) {
+  hipLaunchKernelGGL((k_cheb_start<T>), dim3(grid_for(n)), dim3(256), 0, st, n, f, dinv, r, d, x, T(inv_theta));
+}
+template <typename T>
+void launch_cheb_csr(int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* dinv, const T* d_old,
+                     T* d_new, T* r, T* x, double c0, double c1, hipStream_t st) {
+  hipLaunchKernelGGL((k_cheb_csr<T>), dim3(grid_for(n)), dim3(256), 0, st, n, rp, ci, val, dinv, d_old, d_new, r, x,
+                     T(c0), T(c1));
+}
+template void launch_cheb_start<double>(int64_t, const double*, const double*, double*, double*, double*, double, hipStream_t);
+template void launch_cheb_start<float>(int64_t, const float*, const float*, float*, float*, float*, double, hipStream_t);
+template void launch_cheb_csr<double>(int64_t, const int32_t*, const int32_t*, const double*, const double*, const double*, double*, double*, double*, double, double, hipStream_t);
+template void launch_cheb_csr<float>(int64_t, const int32_t*, const int32_t*, const float*, const float*, const float*, float*, float*, float*, double, double, hipStream_t);
+
 }  // namespace pmg

@@ -73,6 +73,16 @@ template <typename T>
 void launch_coarse_dense(int n, const int32_t* idx, const T* Ainv, const T* x, T* y, T* tmp,
                          int64_t n_dof, hipStream_t st);
 
+// assembled P = 1 operator for the coarse Chebyshev solve
+void launch_p1_elem_mat(int64_t n_elem, const double* G, const double* Dref, double* Ae, hipStream_t st);
+void launch_csr_sum(int64_t nnz, const int32_t* cp, const int64_t* cl, const double* Ae, double* v64, float* v32,
+                    hipStream_t st);
+template <typename T>
+void launch_cheb_start(int64_t n, const T* f, const T* dinv, T* r, T* d, T* x, double inv_theta, hipStream_t st);
+template <typename T>
+void launch_cheb_csr(int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* dinv, const T* d_old,
+                     T* d_new, T* r, T* x, double c0, double c1, hipStream_t st);
+
 // ---- vector kernels
 template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);
 template <typename T> void launch_copy(const T* x, T* y, int64_t n, hipStream_t st);

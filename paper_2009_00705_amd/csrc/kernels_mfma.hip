@@ -20,6 +20,8 @@
 // D[g+4r][j] (g = lane/16, j = lane%16, r = 0..3).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 #include "kernels_mfma.hpp"
 
@@ -451,10 +453,23 @@ __global__ __launch_bounds__(256) void k_g_native(int64_t n_elem, int64_t n_batc
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static int grid_batches(int64_t n_batch) {
-  int64_t blocks = n_batch;
-  if (blocks > 4096) blocks = 4096;
-  blocks = ((blocks + 7) / 8) * 8;  // multiple of the XCD count
+// One resident wave of workgroups: every workgroup stays on its CU and walks
+// batches b, b + grid, ... (the LDS reference tables are loaded once per
+// workgroup).  Occupancy comes from the runtime for the kernel's own LDS and
+// register use; the grid is a multiple of the XCD count.
+static int grid_batches(int64_t n_batch, const void* kernel, int threads) {
+  static int n_cu = 0;
+  if (n_cu == 0) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n_cu < 1)
+      n_cu = 256;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, threads, 0) != hipSuccess || per_cu < 1)
+    per_cu = 1;
+  int64_t blocks = std::min<int64_t>(n_batch, int64_t(per_cu) * n_cu);
+  blocks = ((blocks + 7) / 8) * 8;
   return int(blocks < 8 ? 8 : blocks);
 }
 
@@ -487,19 +502,26 @@ template <int P>
 static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                       const void* vmats, const void* u, void* Y, hipStream_t st) {
   const int64_t nb = (lv.n_elem + 15) / 16;
-  const int grid = grid_batches(nb);
+  const int64_t need = ((nb + 7) / 8) * 8;
+  constexpr int NT = 64 * (P + 1);
   if (flavour == MF_F64) {
-    if constexpr (P == 8) return;
-    else
-    hipLaunchKernelGGL((k_ax_mfma4<P, double, double, d4_t, true>), dim3(grid), dim3(64 * (P + 1)), 0, st, lv.map2d, lv.L,
-                       int(lv.nz), lv.n_elem, nb, (const double*)Gnat, (const double*)tab2, (const double*)tab4,
-                       *(const VertMats<double>*)vmats, (const double*)u, (double*)Y);
+    if constexpr (P != 8) {
+      auto kern = k_ax_mfma4<P, double, double, d4_t, true>;
+      static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
+      hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
+                         lv.n_elem, nb, (const double*)Gnat, (const double*)tab2, (const double*)tab4,
+                         *(const VertMats<double>*)vmats, (const double*)u, (double*)Y);
+    }
   } else if (flavour == MF_F32) {
-    hipLaunchKernelGGL((k_ax_mfma4<P, float, float, f4_t, false>), dim3(grid), dim3(64 * (P + 1)), 0, st, lv.map2d, lv.L,
-                       int(lv.nz), lv.n_elem, nb, (const float*)Gnat, (const float*)tab2, (const float*)tab4,
+    auto kern = k_ax_mfma4<P, float, float, f4_t, false>;
+    static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
+    hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
+                       lv.n_elem, nb, (const float*)Gnat, (const float*)tab2, (const float*)tab4,
                        *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
   } else {
-    hipLaunchKernelGGL((k_ax_mfma_bf16<P, bf16_t>), dim3(grid), dim3(64 * (P + 1)), 0, st, lv.map2d, lv.L, int(lv.nz),
+    auto kern = k_ax_mfma_bf16<P, bf16_t>;
+    static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
+    hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, nb, (const bf16_t*)Gnat, (const s4_t*)tab2, (const s4_t*)tab4,
                        *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
   }

@@ -151,6 +151,16 @@ struct pmg_ctx {
   float* cinv32 = nullptr;
   double* ctmp64 = nullptr;
   float* ctmp32 = nullptr;
+  // assembled free-node P = 1 matrix (coarse Chebyshev): CSR pattern, the element
+  // entries summed into each nonzero, values per precision, second d buffer
+  int64_t csr_nnz = 0;
+  int32_t *csr_rp = nullptr, *csr_ci = nullptr, *csr_cp = nullptr;
+  int64_t* csr_cl = nullptr;
+  double* csr_v64 = nullptr;
+  float* csr_v32 = nullptr;
+  double* p1_dref = nullptr;
+  double* cd64 = nullptr;
+  float* cd32 = nullptr;
   double cheb_lmin = 0, cheb_lmax = 0;
   int cheb_k = 0;
   bool coarse_exact = true;
@@ -395,6 +405,8 @@ static void upload_levels(pmg_ctx* c) {
       L.piz32 = c->U(to_f32(Bz1.v));
     }
   }
+  // also holds the 6x6 element matrices of the P = 1 level (coarse CSR values)
+  maxE = std::max<int64_t>(maxE, c->lv[c->nl - 1].num.n_elem * 36);
   c->Y = c->A<double>(size_t(maxE));
   c->partial = c->A<double>(2 * RED_BLOCKS);
   c->scal = c->A<double>(N_SCAL);
@@ -505,6 +517,12 @@ template <> float* cinv<float>(pmg_ctx* c) { return c->cinv32; }
 template <typename T> static T* ctmp(pmg_ctx* c);
 template <> double* ctmp<double>(pmg_ctx* c) { return c->ctmp64; }
 template <> float* ctmp<float>(pmg_ctx* c) { return c->ctmp32; }
+template <typename T> T* cdbuf(pmg_ctx* c);
+template <> double* cdbuf<double>(pmg_ctx* c) { return c->cd64; }
+template <> float* cdbuf<float>(pmg_ctx* c) { return c->cd32; }
+template <typename T> const T* csr_val(pmg_ctx* c);
+template <> const double* csr_val<double>(pmg_ctx* c) { return c->csr_v64; }
+template <> const float* csr_val<float>(pmg_ctx* c) { return c->csr_v32; }
 
 template <typename T>
 static void coarse_solve(pmg_ctx* c, const T* f, T* u, hipStream_t st) {
@@ -520,16 +538,16 @@ static void coarse_solve(pmg_ctx* c, const T* f, T* u, hipStream_t st) {
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin), sigma = theta / delta;
   T* r = L.r<T>();
   T* d = ctmp<T>(c);
+  T* d2 = cdbuf<T>(c);
   const int64_t N = L.num.n_dof;
-  launch_copy<T>(f, r, N, st);
-  launch_scale_diag<T>(L.dinv<T>(), f, d, 1.0 / theta, N, st);  // d0 = D^-1 r / theta
-  launch_copy<T>(d, u, N, st);                                    // x1 = d0
+  launch_cheb_start<T>(N, f, L.dinv<T>(), r, d, u, 1.0 / theta, st);  // r = f, d0 = D^-1 r / theta, x1 = d0
   double rho = 1.0 / sigma;
   for (int j = 1; j < k; ++j) {
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    ax_elem<T>(c, i, d, st);
-    // r -= A d; d = rho_new rho d + 2 rho_new/delta D^-1 r; x += d
-    assemble<T>(c, i, OP_CHEB, u, r, L.dinv<T>(), d, rho_new * rho, 2.0 * rho_new / delta, st);
+    // r -= A d; d' = rho_new rho d + 2 rho_new/delta D^-1 r; x += d' (one fused kernel)
+    launch_cheb_csr<T>(N, c->csr_rp, c->csr_ci, csr_val<T>(c), L.dinv<T>(), d, d2, r, u, rho_new * rho,
+                       2.0 * rho_new / delta, st);
+    std::swap(d, d2);
     rho = rho_new;
   }
 }
@@ -638,6 +656,86 @@ static void lanczos_bounds(pmg_ctx* c, int i, int m, double& lmin, double& lmax,
     if (t + 1 < k) e[t] = std::sqrt(be[t]) / al[t];
   }
   tridiag_extremes(d, e, lmin, lmax);
+}
+
+// CSR pattern of the free-node P = 1 matrix and, per nonzero, the element-matrix
+// entries (e*36 + i*6 + j) that sum into it, in ascending order; rows of
+// Dirichlet nodes stay empty and Dirichlet columns are left out.  Also uploads
+// the reference derivative matrices D_a[q][n] of the P = 1 prism.
+static void coarse_csr_pattern(pmg_ctx* c) {
+  Level& L = c->lv[c->nl - 1];
+  if (L.P != 1) throw Error(PMG_EINVAL, "coarsest level is not P = 1");
+  const RefElem& re = *L.re;
+  const int64_t E = L.num.n_elem, N = L.num.n_dof;
+  const int np = re.np, nq = re.nq, npt = re.np_tri, nqt = re.nq_tri, n1 = re.n1;
+  std::vector<uint8_t> dir(N);
+  for (int64_t g = 0; g < N; ++g) {
+    const int64_t g2 = g / L.num.nz;
+    const int z = int(g - g2 * L.num.nz);
+    dir[g] = L.dir2d_h[g2] || (L.top_dir && z == L.num.nz - 1);
+  }
+  std::vector<int32_t> map(size_t(E) * np);
+  L.num.gather_map(map.data());
+  // bucket the contributions by row (counting sort), then order each row by column
+  std::vector<int64_t> rcount(N + 1, 0);
+  for (int64_t e = 0; e < E; ++e)
+    for (int i = 0; i < np; ++i) {
+      const int32_t g = map[e * np + i];
+      if (dir[g]) continue;
+      for (int j = 0; j < np; ++j)
+        if (!dir[map[e * np + j]]) rcount[g + 1]++;
+    }
+  for (int64_t g = 0; g < N; ++g) rcount[g + 1] += rcount[g];
+  std::vector<std::pair<int32_t, int64_t>> items(rcount[N]);  // (column, entry id)
+  std::vector<int64_t> fill(rcount.begin(), rcount.end() - 1);
+  for (int64_t e = 0; e < E; ++e)
+    for (int i = 0; i < np; ++i) {
+      const int32_t g = map[e * np + i];
+      if (dir[g]) continue;
+      for (int j = 0; j < np; ++j) {
+        const int32_t h = map[e * np + j];
+        if (!dir[h]) items[fill[g]++] = {h, e * 36 + i * np + j};
+      }
+    }
+  std::vector<int32_t> rp(N + 1, 0), ci, cp{0};
+  std::vector<int64_t> cl;
+  cl.reserve(items.size());
+  for (int64_t g = 0; g < N; ++g) {
+    std::sort(items.begin() + rcount[g], items.begin() + rcount[g + 1]);
+    for (int64_t m = rcount[g]; m < rcount[g + 1]; ++m) {
+      if (m == rcount[g] || items[m].first != items[m - 1].first) {
+        ci.push_back(items[m].first);
+        cp.push_back(cp.back());
+      }
+      cl.push_back(items[m].second);
+      cp.back()++;
+    }
+    rp[g + 1] = int32_t(ci.size());
+  }
+  if (cl.size() > size_t(INT32_MAX)) throw Error(PMG_EINVAL, "coarse matrix too large");
+  c->csr_nnz = int64_t(ci.size());
+  c->csr_rp = c->A<int32_t>(N + 1);
+  c->csr_ci = c->A<int32_t>(ci.size());
+  c->csr_cp = c->A<int32_t>(cp.size());
+  c->csr_cl = c->A<int64_t>(cl.size());
+  c->csr_v64 = c->A<double>(ci.size());
+  c->csr_v32 = c->A<float>(ci.size());
+  HIPCHK(hipMemcpy(c->csr_rp, rp.data(), rp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->csr_ci, ci.data(), ci.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->csr_cp, cp.data(), cp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->csr_cl, cl.data(), cl.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+  std::vector<double> Dp(size_t(3) * nq * np);
+  for (int k = 0; k < n1; ++k)
+    for (int q = 0; q < nqt; ++q)
+      for (int cc = 0; cc < n1; ++cc)
+        for (int aa = 0; aa < npt; ++aa) {
+          const size_t o = size_t(k * nqt + q) * np + cc * npt + aa;
+          Dp[0 * nq * np + o] = re.Bz(k, cc) * re.Dr(q, aa);
+          Dp[1 * nq * np + o] = re.Bz(k, cc) * re.Ds(q, aa);
+          Dp[2 * nq * np + o] = re.Dz(k, cc) * re.B(q, aa);
+        }
+  c->p1_dref = c->A<double>(Dp.size());
+  HIPCHK(hipMemcpy(c->p1_dref, Dp.data(), Dp.size() * sizeof(double), hipMemcpyHostToDevice));
 }
 
 // dense inverse of the free-node P=1 matrix (host, from the device G of the level)
@@ -820,6 +918,13 @@ static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
       c->ctmp64 = c->A<double>(C.num.n_dof);
       c->ctmp32 = c->A<float>(C.num.n_dof);
     }
+    if (!c->cd64) {
+      c->cd64 = c->A<double>(C.num.n_dof);
+      c->cd32 = c->A<float>(C.num.n_dof);
+    }
+    if (!c->csr_rp) coarse_csr_pattern(c);
+    launch_p1_elem_mat(C.num.n_elem, C.G64, c->p1_dref, c->Y, st);
+    launch_csr_sum(c->csr_nnz, c->csr_cp, c->csr_cl, c->Y, c->csr_v64, c->csr_v32, st);
     if (c->opt.cheb_lmax > 0 && c->opt.cheb_lmin > 0) {
       c->cheb_lmax = c->opt.cheb_lmax;
       c->cheb_lmin = c->opt.cheb_lmin;

@@ -185,3 +185,47 @@ def test_chebyshev_smoother_vcycle_and_solve(cheb_pair):
     assert rc == 0 and st["iters"] == ref.iters
     np.testing.assert_allclose(st["res_hist"], ref.res_hist, rtol=1e-9, atol=1e-10 * ref.res_hist[0])
     assert rel_err(host(phi), ref.phi) < 1e-10
+
+
+@pytest.mark.parametrize("case", ["box5x5_L3_P6", "cyl_P3"])
+def test_coarse_chebyshev_parity(case):
+    """Chebyshev coarse solve (assembled P = 1 matrix, fused step) against the
+    oracle's Chebyshev iteration on the same interval and degree: coarse solve
+    and V-cycle to 1e-11, PCG solve with equal iteration counts to 1e-10."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    from oracle.mg import Hierarchy
+    mk, P = CASES[case]
+    mesh = mk()
+    ctx = pmg.Context(mesh, P=P, coarse="chebyshev")
+    xy = ctx.surface_xy()
+    ctx.set_surface(dev(W.surface_elevation_c2(xy[:, 0], xy[:, 1])))
+    info = ctx.coarse_info()
+    assert info["mode"] == "chebyshev" and info["degree"] >= 4
+    assert 0 < info["lmin"] < info["lmax"]
+    om, _, _ = ctx.params()
+    num = M.Numbering(mesh, P)
+    eta_o = W.surface_elevation_c2(*M.unique_xy_2d(mesh, num).T)
+    h = Hierarchy(mesh, P, eta2d=eta_o, omega=list(om), coarse="chebyshev",
+                  cheb=(info["degree"], info["lmin"], info["lmax"]))
+    nc = h.levels[-1].num.n_dof
+    fc = np.where(h.levels[-1].free, _rand(nc, 31), 0.0)
+    uc = torch.zeros(nc, dtype=torch.float64, device="cuda")
+    ctx.coarse_solve(dev(fc), uc)
+    assert rel_err(host(uc), h.coarse_solve(fc)) < 1e-11
+    n0 = h.levels[0].num.n_dof
+    r = np.where(h.levels[0].free, _rand(n0, 32), 0.0)
+    z = torch.zeros(n0, dtype=torch.float64, device="cuda")
+    ctx.vcycle(dev(r), z)
+    assert rel_err(host(z), h.vcycle(r)) < 1e-11
+    phi_o, surf_l = _dirichlet(h, ctx)
+    ref = K.solve(h, phi_o, method="pcg", rtol=1e-10, imax=300)
+    phi = torch.zeros(n0, dtype=torch.float64, device="cuda")
+    rc, st = ctx.solve(phi, phi_surf=dev(surf_l), rtol=1e-10, imax=300)
+    assert rc == 0 and st["iters"] == ref.iters
+    assert rel_err(host(phi), ref.phi) < 1e-10
+    # FP32 coarse solve: same result to single precision
+    u32 = torch.zeros(nc, dtype=torch.float32, device="cuda")
+    ctx.coarse_solve(dev(fc, torch.float32), u32, precision="fp32")
+    assert rel_err(host(u32), h.coarse_solve(fc)) < 1e-4
+    ctx.close()
