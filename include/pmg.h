@@ -50,8 +50,15 @@ enum pmg_status {
 
 /* Arithmetic of the preconditioner (Sec. 1 mentions mixed precision as a way to
  * accelerate multigrid; the outer residual and Krylov recurrences are always
- * FP64). */
-enum pmg_precision { PMG_FP64 = 0, PMG_MIXED_FP32 = 1, PMG_MIXED_BF16 = 2 };
+ * FP64).
+ *   PMG_MIXED_FP32   V-cycle vectors, geometric factors and MFMA operands in FP32
+ *   PMG_MIXED_BF16   FP32 vectors; geometric factors and MFMA operands in BF16,
+ *                    FP32 accumulation
+ *   PMG_MIXED_BF16G  FP32 vectors and FP32 MFMA arithmetic on geometric factors
+ *                    stored in BF16 (half the bytes of FP32 G, FP32 operands)
+ * Vectors of the float V-cycle (pmg_apply, pmg_smooth, ...) are float for all
+ * three. */
+enum pmg_precision { PMG_FP64 = 0, PMG_MIXED_FP32 = 1, PMG_MIXED_BF16 = 2, PMG_MIXED_BF16G = 3 };
 
 /* Outer iteration: Alg. 3 (PCG), flexible PCG (Polak-Ribiere beta), Alg. 2
  * (preconditioned defect correction), stand-alone V-cycles. */

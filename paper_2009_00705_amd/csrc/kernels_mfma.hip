@@ -518,6 +518,12 @@ static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const 
     hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, nb, (const float*)Gnat, (const float*)tab2, (const float*)tab4,
                        *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
+  } else if (flavour == MF_F32G16) {
+    auto kern = k_ax_mfma4<P, float, bf16_t, f4_t, false>;
+    static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
+    hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
+                       lv.n_elem, nb, (const bf16_t*)Gnat, (const float*)tab2, (const float*)tab4,
+                       *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
   } else {
     auto kern = k_ax_mfma_bf16<P, bf16_t>;
     static const int grid = grid_batches(1 << 30, (const void*)kern, NT);

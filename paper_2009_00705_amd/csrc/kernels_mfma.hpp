@@ -8,7 +8,8 @@
 
 namespace pmg {
 
-enum MfmaFlavour { MF_F64 = 0, MF_F32 = 1, MF_BF16 = 2 };
+// MF_F32G16: FP32 MFMA arithmetic reading the BF16 lane-native copy of G
+enum MfmaFlavour { MF_F64 = 0, MF_F32 = 1, MF_BF16 = 2, MF_F32G16 = 3 };
 
 // vertical interpolation/derivative matrices at the Gauss points, passed by value
 template <typename T> struct VertMats {
@@ -26,6 +27,7 @@ template <> __device__ __forceinline__ bf16_t cvt_out<bf16_t>(double v) {
 }
 __device__ __forceinline__ double gld_any(const double* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float gld_any(const float* p, int64_t i) { return p[i]; }
+__device__ __forceinline__ float gld_any(const bf16_t* p, int64_t i) { return __uint_as_float(uint32_t(p[i]) << 16); }
 
 // orders with an MFMA kernel for a flavour
 inline bool mfma_available(int P, int flavour) {

@@ -170,6 +170,7 @@ struct pmg_ctx {
   float *s_r32 = nullptr, *s_z32 = nullptr;
   float* feat_cst = nullptr; // [n1][4] constant features of the coarsest nodes
   int lowp = pmg::G_F32;      // G storage of the float V-cycle
+  bool bf16_ops = false;      // BF16 MFMA operands (PMG_MIXED_BF16) rather than FP32 arithmetic
   int n_vcycles = 0, n_fine_applies = 0;
   std::vector<void*> allocs;
 
@@ -432,6 +433,12 @@ static void upload_levels(pmg_ctx* c) {
 // ---------------------------------------------------------------------------
 // operator building blocks
 // ---------------------------------------------------------------------------
+// precision of the float V-cycle: G storage and MFMA operand type
+static void set_lowp(pmg_ctx* c, int precision) {
+  c->lowp = (precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G) ? G_BF16 : G_F32;
+  c->bf16_ops = precision == PMG_MIXED_BF16;
+}
+
 template <typename T> static const void* gptr(pmg_ctx* c, Level& L, int& gstore);
 template <> const void* gptr<double>(pmg_ctx*, Level& L, int& gs) { gs = G_F64; return L.G64; }
 template <> const void* gptr<float>(pmg_ctx* c, Level& L, int& gs) {
@@ -448,6 +455,11 @@ static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
   const int f = sizeof(T) == 8 ? MF_F64 : (gs == G_BF16 ? MF_BF16 : MF_F32);
   if (L.mf[f]) {
     const void* vm = sizeof(T) == 8 ? (const void*)&L.vm64 : (const void*)&L.vm32;
+    if (f == MF_BF16 && !c->bf16_ops && L.mf[MF_F32]) {
+      // FP32 arithmetic on the BF16 copy of G (FP32 tables)
+      launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_F32G16, L.tab2[MF_F32], L.tab4[MF_F32], vm, x, c->Y, st);
+      return;
+    }
     launch_ax_mfma(L.view, L.gnat[f], f, L.tab2[f], L.tab4[f], vm, x, c->Y, st);
     return;
   }
@@ -990,7 +1002,7 @@ static void precond(pmg_ctx* c, const double* r, double* z, hipStream_t st) {
     vcycle<double>(c, 0, r, z, st);
     return;
   }
-  c->lowp = c->opt.precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+  set_lowp(c, c->opt.precision);
   launch_cast<double, float>(r, c->s_r32, 1.0, N, st);
   vcycle<float>(c, 0, c->s_r32, c->s_z32, st);
   launch_cast<float, double>(c->s_z32, z, 1.0, N, st);
@@ -1397,7 +1409,7 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (m->nv < 3 || m->nt < 1 || !m->xy || !m->tri || m->n_layers < 1 || !(m->depth > 0))
       throw Error(PMG_EINVAL, "bad mesh sizes");
     if (o->nu1 < 0 || o->nu2 < 0) throw Error(PMG_EINVAL, "negative sweep count");
-    if (o->precision < 0 || o->precision > 2) throw Error(PMG_EINVAL, "bad precision");
+    if (o->precision < 0 || o->precision > 3) throw Error(PMG_EINVAL, "bad precision");
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
     if (o->smoother < 0 || o->smoother > 1) throw Error(PMG_EINVAL, "bad smoother");
     if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
@@ -1540,8 +1552,8 @@ int pmg_apply(pmg_ctx* c, int level, int precision, int flags, const void* x, vo
       if (flags & 1) { launch_mask<double>(L.view, xin, L.r64, st); xin = L.r64; }
       ax_elem<double>(c, level, xin, st);
       assemble<double>(c, level, (flags & 1) ? OP_STORE : OP_RAW, (double*)y, nullptr, nullptr, nullptr, 0, 0, st);
-    } else if (precision == PMG_MIXED_FP32 || precision == PMG_MIXED_BF16) {
-      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+    } else if (precision == PMG_MIXED_FP32 || precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G) {
+      set_lowp(c, precision);
       const float* xin = (const float*)x;
       if (flags & 1) { launch_mask<float>(L.view, xin, L.r32, st); xin = L.r32; }
       ax_elem<float>(c, level, xin, st);
@@ -1571,7 +1583,7 @@ int pmg_smooth(pmg_ctx* c, int level, int precision, int sweeps, const void* f, 
     if (level == c->nl - 1) throw Error(PMG_EINVAL, "no smoother on the coarsest level");
     if (precision == PMG_FP64) smooth_t<double>(c, level, sweeps, (const double*)f, (double*)u, S(stream));
     else {
-      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+      set_lowp(c, precision);
       smooth_t<float>(c, level, sweeps, (const float*)f, (float*)u, S(stream));
     }
   });
@@ -1606,7 +1618,7 @@ int pmg_coarse_solve(pmg_ctx* c, int precision, const void* f, void* u, void* st
     need_device(c);
     if (precision == PMG_FP64) coarse_solve<double>(c, (const double*)f, (double*)u, S(stream));
     else {
-      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+      set_lowp(c, precision);
       coarse_solve<float>(c, (const float*)f, (float*)u, S(stream));
     }
   });
@@ -1619,7 +1631,7 @@ int pmg_vcycle(pmg_ctx* c, int precision, const void* r, void* z, void* stream) 
     need_device(c);
     if (precision == PMG_FP64) vcycle<double>(c, 0, (const double*)r, (double*)z, S(stream));
     else {
-      c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+      set_lowp(c, precision);
       vcycle<float>(c, 0, (const float*)r, (float*)z, S(stream));
     }
   });
@@ -1674,7 +1686,7 @@ int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* 
 }
 
 int pmg_set_solver(pmg_ctx* c, int precision, int krylov) {
-  if (!c || precision < 0 || precision > 2 || krylov < 0 || krylov > 3) return PMG_EINVAL;
+  if (!c || precision < 0 || precision > 3 || krylov < 0 || krylov > 3) return PMG_EINVAL;
   c->opt.precision = precision;
   c->opt.krylov = krylov;
   return PMG_OK;
@@ -1688,7 +1700,7 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
     hipStream_t st = S(stream);
     Level& L = c->lv[level];
     const bool f64 = precision == PMG_FP64;
-    c->lowp = precision == PMG_MIXED_BF16 ? G_BF16 : G_F32;
+    set_lowp(c, precision);
     if ((kernel == PMG_K_RESTRICT || kernel == PMG_K_PROLONG) && level + 1 >= c->nl)
       throw Error(PMG_EINVAL, "no coarser level");
     launch_fill<double>(L.r64, 1.0, L.num.n_dof, st);

@@ -52,7 +52,7 @@ def test_operator_fp64_all_levels(pair):
         assert rel_err(host(y), lv.A(x)) < 1e-12, (name, lvl)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2), ("bf16g", 1e-2)])
 def test_operator_low_precision(pair, prec, tol):
     name, h, ctx = pair
     import torch
