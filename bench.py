@@ -39,6 +39,40 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+# dense peaks (TFLOP/s) of the arithmetic each path's element operator runs in
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16g": 157.3, "bf16": 2500.0}
+
+
+def op_flops_per_elem(P):
+    """Algorithmic flops of one prism's operator application: vertical
+    interpolation and derivative (2 x 2 (P+1)^2 Np_tri), triangle contractions
+    at the cubature points (3 x 2 Nq_tri Np_tri (P+1)), the pointwise symmetric
+    3x3 geometric factor (15 per point), and the transposes of both contractions."""
+    n1 = P + 1
+    npt = n1 * (P + 2) // 2
+    nqt = n1 * n1
+    vert = 2 * 2 * n1 * n1 * npt
+    tri = 3 * 2 * nqt * npt * n1
+    return 2 * vert + 2 * tri + 15 * nqt * n1
+
+
+def roofline(bytes_per_launch, flops_per_launch, ms, prec):
+    """Binding roofline of one launch: HBM if moving the algorithmic bytes at
+    8 TB/s takes longer than the flops at the dtype's dense peak, else MFMA."""
+    t_hbm = bytes_per_launch / (HBM_PEAK_GBS * 1e9)
+    t_mma = flops_per_launch / (PEAK_TFLOPS[prec] * 1e12)
+    gbs = bytes_per_launch / (ms * 1e-3) / 1e9
+    tfs = flops_per_launch / (ms * 1e-3) / 1e12
+    if t_hbm >= t_mma:
+        out = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(gbs / HBM_PEAK_GBS, 4)}
+    else:
+        out = {"bound": "mfma", "achieved": round(tfs, 2), "peak": PEAK_TFLOPS[prec], "unit": "TFLOP/s",
+               "frac": round(tfs / PEAK_TFLOPS[prec], 4)}
+    out.update({"hbm_frac": round(gbs / HBM_PEAK_GBS, 4), "mfma_frac": round(tfs / PEAK_TFLOPS[prec], 4)})
+    return out
+
+
 def op_bytes(info0, nt, np_tri, s_g, s_v):
     """Algorithmic bytes of one fine element-operator launch: G + one read of u + the 2D gather map."""
     return info0["n_elem"] * 6 * info0["nq"] * s_g + info0["n_dof"] * s_v + nt * np_tri * 4
@@ -102,20 +136,26 @@ def bench_history(a):
     t0 = time.perf_counter()
     ref, _ = H.solve_sequence(range(0, 300), guess="extrap", rtol=a.rtol)
     log(f"[c5] reference history {time.perf_counter() - t0:.1f}s")
-    X, T = H.training_set(ref, range(2, 200))
-    net = pmg.Net(ctx, width=160, depth=3, seed=6)
-    t0 = time.perf_counter()
-    loss = net.train(X, T, steps=a.train_steps, batch=8192, lr=1e-3, seed=7)
-    torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    log(f"[c5] trained {net.n_params} params on {X.shape[0]} rows in {t_train:.1f}s, loss {loss:.3e}")
+    nets, train = {}, {}
+    for third in (False, True):
+        X, T = H.training_set(ref, range(3 if third else 2, 200), third=third)
+        net = pmg.Net(ctx, width=160, depth=3, seed=6)
+        t0 = time.perf_counter()
+        loss = net.train(X, T, steps=a.train_steps, batch=8192, lr=1e-3, seed=7)
+        torch.cuda.synchronize()
+        key = "learned3" if third else "learned"
+        nets[key] = net
+        train[key] = {"rows": int(X.shape[0]), "loss": loss, "seconds": time.perf_counter() - t0}
+        log(f"[c5] {key}: trained {net.n_params} params on {X.shape[0]} rows in {train[key]['seconds']:.1f}s, "
+            f"loss {loss:.3e}")
+        del X, T
     test = range(200, 300)
-    base = {n: ref[n] for n in (198, 199)}
+    base = {n: ref[n] for n in (197, 198, 199)}
     paths = {}
     for prec in ("fp64", "fp32", "bf16g"):
         ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
-        for guess in ("zero", "prev", "extrap", "learned"):
-            _, st = H.solve_sequence(test, guess=guess, sols=base, net=net, rtol=a.rtol)
+        for guess in ("zero", "prev", "extrap", "extrap3", "learned", "learned3"):
+            _, st = H.solve_sequence(test, guess=guess, sols=base, net=nets.get(guess), rtol=a.rtol)
             paths[f"{prec}+{guess}"] = summarize(st)
             log(f"[c5] {prec}+{guess}: {paths[f'{prec}+{guess}']}")
     best = max(paths, key=lambda k: paths[k]["solves_per_s"])
@@ -128,16 +168,17 @@ def bench_history(a):
            "config": {"workload": f"c5: seeded Delaunay cylinder mesh, {info0['n_elem']} prisms, P={a.P}, "
                                   "300-step focusing group (16 components), train 0-199, test 200-299",
                       "n_dof": info0["n_dof"], "rtol": a.rtol, "smoother": f"{a.smoother} {nu}+{nu}",
-                      "coarse": ctx.coarse_info(), "net_params": net.n_params, "train_loss": loss,
-                      "train_s": t_train, "best": best},
+                      "coarse": ctx.coarse_info(), "net_params": nets["learned"].n_params, "training": train,
+                      "best": best},
            "paths": paths,
-           "speedup_mixed_learned_vs_fp64_prev": max(paths[f"{p}+learned"]["solves_per_s"] for p in ("fp32", "bf16g"))
-           / paths["fp64+prev"]["solves_per_s"],
-           "speedup_mixed_learned_vs_fp64_zero": max(paths[f"{p}+learned"]["solves_per_s"] for p in ("fp32", "bf16g"))
-           / paths["fp64+zero"]["solves_per_s"],
-           "speedup_mixed_learned_vs_fp64_extrap": max(paths[f"{p}+learned"]["solves_per_s"] for p in ("fp32", "bf16g"))
-           / paths["fp64+extrap"]["solves_per_s"],
-           "speedup_learned_vs_extrap_fp64": paths["fp64+learned"]["solves_per_s"] / paths["fp64+extrap"]["solves_per_s"]}
+           "speedup": {f"mixed+{lg} vs fp64+{bg}": round(ml / paths[f"fp64+{bg}"]["solves_per_s"], 4)
+                       for lg in ("learned", "learned3")
+                       for ml in [max(paths[f"{p}+{lg}"]["solves_per_s"] for p in ("fp32", "bf16g"))]
+                       for bg in ("zero", "prev", "extrap", "extrap3")},
+           "speedup_learned_vs_same_base_fp64": {
+               "learned/extrap": round(paths["fp64+learned"]["solves_per_s"] / paths["fp64+extrap"]["solves_per_s"], 4),
+               "learned3/extrap3": round(paths["fp64+learned3"]["solves_per_s"] /
+                                         paths["fp64+extrap3"]["solves_per_s"], 4)}}
     print(json.dumps(out), flush=True)
 
 
@@ -153,6 +194,8 @@ def main():
     ap.add_argument("--coarse-degree", type=int, default=0, help="Chebyshev coarse degree (0: automatic)")
     ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "jacobi"])
     ap.add_argument("--nu", type=int, default=0, help="smoothing degree/sweeps (0: 3 Chebyshev, 2 Jacobi)")
+    ap.add_argument("--smooth-ratio", type=float, default=15.0,
+                    help="Chebyshev smoother interval [lambda/ratio, lambda]")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000)
@@ -178,7 +221,7 @@ def main():
     coarse = "exact" if nc_free <= 12000 else "chebyshev"
     nu = a.nu if a.nu > 0 else (3 if a.smoother == "chebyshev" else 2)
     ctx = pmg.Context(mesh, P=a.P, coarse=coarse, cheb_degree=a.coarse_degree, smoother=a.smoother,
-                      nu1=nu, nu2=nu)
+                      nu1=nu, nu2=nu, smooth_ratio=a.smooth_ratio)
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
@@ -203,7 +246,9 @@ def main():
             s_g = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2}[prec]
             ms = ctx.time_kernel("element_op", 0, prec, reps=a.steps)
             byts = op_bytes(info0, nt, npt, s_g, 8 if prec == "fp64" else 4)
-            res[prec] = {"ms_per_launch": ms, "bytes_per_launch": byts, "GB_per_s": byts / (ms * 1e-3) / 1e9}
+            flops = op_flops_per_elem(a.P) * info0["n_elem"]
+            res[prec] = {"ms_per_launch": ms, "bytes_per_launch": byts, "GB_per_s": byts / (ms * 1e-3) / 1e9,
+                         "flops_per_launch": flops, "roofline": roofline(byts, flops, ms, prec)}
         print(json.dumps(res), flush=True)
         return
 
@@ -241,14 +286,13 @@ def main():
     nt = mesh["tri"].shape[0]
     npt = (a.P + 1) * (a.P + 2) // 2
     byts = op_bytes(info0, nt, npt, s_g, s_v)
-    ach = byts / (ms_k * 1e-3) / 1e9
+    flops = op_flops_per_elem(a.P) * info0["n_elem"]
     byts64 = op_bytes(info0, nt, npt, 8, 8)
-    roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": f"MFMA element operator (P={a.P}), {kprec} geometric factors", "ms_per_launch": ms_k,
-            "bytes_per_launch": byts,
-            "fp64_kernel": {"ms_per_launch": ms_k64, "achieved": round(byts64 / (ms_k64 * 1e-3) / 1e9, 1)},
-            "assemble_ms_per_launch": ms_asm}
+    roof = roofline(byts, flops, ms_k, kprec)
+    roof.update({"traffic": None, "kernel": f"MFMA element operator (P={a.P}), {kprec} path",
+                 "ms_per_launch": ms_k, "bytes_per_launch": byts, "flops_per_launch": flops,
+                 "fp64_kernel": dict(roofline(byts64, flops, ms_k64, "fp64"), ms_per_launch=ms_k64),
+                 "assemble_ms_per_launch": ms_asm})
     prof = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
     if os.path.exists(prof):
         try:
@@ -267,7 +311,8 @@ def main():
            "data": "synthetic", "dof_per_s": res["dof_per_s"],
            "config": {"workload": wl_desc, "P": a.P, "levels": [l["order"] for l in ctx.levels],
                       "n_dof": info0["n_dof"], "n_elem": info0["n_elem"], "rtol": a.rtol,
-                      "smoother": f"{a.smoother} {nu}+{nu}", "coarse": cinfo,
+                      "smoother": f"{a.smoother} {nu}+{nu}" + (f" on [lambda/{a.smooth_ratio:g}, lambda]" if a.smoother == "chebyshev" else ""),
+                      "coarse": cinfo,
                       "guess": "zero", "precision": best, "krylov": res["krylov"]},
            "paths": paths, "roofline": roof}
     if "fp64" in paths and best != "fp64":

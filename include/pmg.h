@@ -67,8 +67,12 @@ enum pmg_krylov { PMG_PCG = 0, PMG_FPCG = 1, PMG_PDC = 2, PMG_MG = 3 };
 /* Initial guess of pmg_solve: the caller's phi, zero, the extrapolation
  * 2 phi_{n-1} - phi_{n-2} of the two previous solutions plus the learned
  * correction (falls back to the extrapolation when its residual is not
- * smaller), or the extrapolation alone. */
-enum pmg_guess { PMG_GUESS_GIVEN = 0, PMG_GUESS_ZERO = 1, PMG_GUESS_LEARNED = 2, PMG_GUESS_EXTRAP = 3 };
+ * smaller), or the extrapolation alone.  The ...3 forms use the third-order
+ * extrapolation 3 phi_{n-1} - 3 phi_{n-2} + phi_{n-3} of three previous
+ * solutions as the base (a network for LEARNED3 is trained on targets and
+ * features relative to that base: pmg_features with p3). */
+enum pmg_guess { PMG_GUESS_GIVEN = 0, PMG_GUESS_ZERO = 1, PMG_GUESS_LEARNED = 2, PMG_GUESS_EXTRAP = 3,
+                 PMG_GUESS_EXTRAP3 = 4, PMG_GUESS_LEARNED3 = 5 };
 
 /* Coarsest (P = 1) level of Alg. 1: exact solve through a dense inverse of the
  * free-node matrix, or a fixed-degree Jacobi-preconditioned Chebyshev
@@ -227,9 +231,10 @@ int pmg_set_params(pmg_ctx* ctx, const double* omega /*[n_levels] or NULL*/, dou
  *  phi_bc:   device [n_dof] values read at every Dirichlet node, or NULL
  *            (required when lateral Dirichlet tags are set);
  *  phi:      device [n_dof]; in: guess (GUESS_GIVEN), out: solution.
- *  net:      learned model for GUESS_LEARNED (else NULL); hist_phi: device
- *            pointers to the two previous solutions [n_dof] (learned/extrapolated
- *            guesses) or NULL.
+ *  net:      learned model for GUESS_LEARNED(3) (else NULL); hist_phi: host
+ *            array of device pointers to the previous solutions [n_dof],
+ *            newest first: two for LEARNED/EXTRAP, three for LEARNED3/EXTRAP3,
+ *            else NULL.
  *  stats:    host, may be NULL.
  * Returns OK, NOT_CONVERGED (phi = last iterate), FALLBACK_USED, or an error
  * (EBREAKDOWN, ENONFINITE, EINVAL, EDEVICE). */
@@ -259,8 +264,9 @@ int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps
  * level with the multigrid transfers.  Features of node g = (vertex v,
  * level z) with gf its finest-level twin and top the finest surface node of
  * column v: [z/L, x, y scaled to [-1,1], distance to the nearest circle,
- * p1[gf]-p2[gf], surf[v]-(2 p1[top]-p2[top]), p1[top]-p2[top]]; target
- * pnow[gf] - (2 p1[gf] - p2[gf]).  Layers: dense y = x W + b (W fan_in x fan_out
+ * p1[gf]-p2[gf], surf[v]-base[top], p1[top]-p2[top]]; target
+ * pnow[gf] - base[gf], with base = 2 p1 - p2, or 3 p1 - 3 p2 + p3 when p3 is
+ * given.  Layers: dense y = x W + b (W fan_in x fan_out
  * row-major), SiLU on hidden layers, linear scalar output; MSE loss; Adam
  * (0.9, 0.999, 1e-8) with bias correction.  Flat parameter order: W_0, b_0,
  * W_1, b_1, ...  pmg_net_forward / pmg_net_loss_grad act on raw inputs; the
@@ -268,9 +274,9 @@ int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps
  * output times tscale) fitted by pmg_net_train. */
 /* Features (device float [n1][7]) and, if T and pnow are given, targets
  * (device float [n1]) of the coarsest nodes; surf device [n_surface], p1, p2,
- * pnow device [n_dof] of the finest level. */
-int pmg_features(pmg_ctx* ctx, const double* surf, const double* p1, const double* p2, const double* pnow,
-                 float* X, float* T, void* stream);
+ * p3 (nullable: second-order base), pnow device [n_dof] of the finest level. */
+int pmg_features(pmg_ctx* ctx, const double* surf, const double* p1, const double* p2, const double* p3,
+                 const double* pnow, float* X, float* T, void* stream);
 /* Network with `depth` hidden layers of `width` units on the context's GPU;
  * weights uniform in +-1/sqrt(fan_in) from the counter generator of `seed`. */
 int pmg_net_create(const pmg_ctx* ctx, int32_t width, int32_t depth, uint64_t seed, pmg_net** out);

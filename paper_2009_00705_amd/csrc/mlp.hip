@@ -205,33 +205,38 @@ void launch_colstats(const float* X, int64_t n, int d, double* out, hipStream_t 
 }
 
 // features of the coarsest (P = 1) nodes, see mlp.hpp
+// base extrapolation of the guess: 2 p1 - p2, or 3 p1 - 3 p2 + p3 when p3 is given
+__device__ __forceinline__ double base_ex(const double* __restrict__ p1, const double* __restrict__ p2,
+                                          const double* __restrict__ p3, int64_t i) {
+  return p3 ? 3.0 * p1[i] - 3.0 * p2[i] + p3[i] : 2.0 * p1[i] - p2[i];
+}
+
 __global__ void k_features(int64_t n1, int nz1, int nzf, int Pf, const float* __restrict__ cst,
                            const double* __restrict__ surf, const double* __restrict__ p1,
-                           const double* __restrict__ p2, const double* __restrict__ pnow,
-                           float* __restrict__ X, float* __restrict__ T) {
+                           const double* __restrict__ p2, const double* __restrict__ p3,
+                           const double* __restrict__ pnow, float* __restrict__ X, float* __restrict__ T) {
   for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n1; g += int64_t(gridDim.x) * 256) {
     const int64_t v = g / nz1;
     const int zl = int(g - v * nz1);
     const int64_t gf = v * nzf + int64_t(zl) * Pf;   // the same point on the finest level
     const int64_t top = v * nzf + (nzf - 1);
-    const double ex = 2.0 * p1[gf] - p2[gf];
     float* x = X + g * NET_DIN;
     x[0] = cst[g * 4 + 0];
     x[1] = cst[g * 4 + 1];
     x[2] = cst[g * 4 + 2];
     x[3] = cst[g * 4 + 3];
     x[4] = float(p1[gf] - p2[gf]);
-    x[5] = float(surf[v] - (2.0 * p1[top] - p2[top]));
+    x[5] = float(surf[v] - base_ex(p1, p2, p3, top));
     x[6] = float(p1[top] - p2[top]);
-    if (T) T[g] = float(pnow[gf] - ex);
+    if (T) T[g] = float(pnow[gf] - base_ex(p1, p2, p3, gf));
   }
 }
 void launch_features(int64_t n1, int nz1, int nzf, int Pf, const float* cst, const double* surf, const double* p1,
-                     const double* p2, const double* pnow, float* X, float* T, hipStream_t st) {
+                     const double* p2, const double* p3, const double* pnow, float* X, float* T, hipStream_t st) {
   int64_t g = (n1 + 255) / 256;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_features, dim3(g < 1 ? 1 : g), dim3(256), 0, st, n1, nz1, nzf, Pf, cst, surf, p1, p2, pnow,
-                     X, T);
+  hipLaunchKernelGGL(k_features, dim3(g < 1 ? 1 : g), dim3(256), 0, st, n1, nz1, nzf, Pf, cst, surf, p1, p2, p3,
+                     pnow, X, T);
 }
 
 // u_coarse (double) = out_scale * y (float) on free nodes of the coarsest level
@@ -245,33 +250,33 @@ void launch_scale_out(const float* y, double s, int64_t n, double* out, hipStrea
   hipLaunchKernelGGL(k_scale_out, dim3(g < 1 ? 1 : g), dim3(256), 0, st, y, s, n, out);
 }
 
-// correction of the extrapolation at the coarsest surface nodes is known exactly:
-// delta = surf[v] - (2 p1[top] - p2[top])
+// correction of the base extrapolation at the coarsest surface nodes is known exactly:
+// delta = surf[v] - base(top)
 __global__ void k_corr_surface(int64_t n1, int nz1, int nzf, const double* __restrict__ surf,
                                const double* __restrict__ p1, const double* __restrict__ p2,
-                               double* __restrict__ delta) {
+                               const double* __restrict__ p3, double* __restrict__ delta) {
   for (int64_t v = int64_t(blockIdx.x) * 256 + threadIdx.x; v * nz1 < n1; v += int64_t(gridDim.x) * 256) {
     const int64_t top = v * nzf + (nzf - 1);
-    delta[v * nz1 + (nz1 - 1)] = surf[v] - (2.0 * p1[top] - p2[top]);
+    delta[v * nz1 + (nz1 - 1)] = surf[v] - base_ex(p1, p2, p3, top);
   }
 }
 void launch_corr_surface(int64_t n1, int nz1, int nzf, const double* surf, const double* p1, const double* p2,
-                         double* delta, hipStream_t st) {
+                         const double* p3, double* delta, hipStream_t st) {
   int64_t g = (n1 / nz1 + 255) / 256;
   if (g > 4096) g = 4096;
-  hipLaunchKernelGGL(k_corr_surface, dim3(g < 1 ? 1 : g), dim3(256), 0, st, n1, nz1, nzf, surf, p1, p2, delta);
+  hipLaunchKernelGGL(k_corr_surface, dim3(g < 1 ? 1 : g), dim3(256), 0, st, n1, nz1, nzf, surf, p1, p2, p3, delta);
 }
 
-// out = 2 p1 - p2
-__global__ void k_extrap(const double* __restrict__ p1, const double* __restrict__ p2, double* __restrict__ out,
-                         int64_t n) {
+// out = 2 p1 - p2, or 3 p1 - 3 p2 + p3 (p3 given)
+__global__ void k_extrap(const double* __restrict__ p1, const double* __restrict__ p2,
+                         const double* __restrict__ p3, double* __restrict__ out, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-    out[i] = 2.0 * p1[i] - p2[i];
+    out[i] = base_ex(p1, p2, p3, i);
 }
-void launch_extrap(const double* p1, const double* p2, double* out, int64_t n, hipStream_t st) {
+void launch_extrap(const double* p1, const double* p2, const double* p3, double* out, int64_t n, hipStream_t st) {
   int64_t g = (n + 255) / 256;
   if (g > 8192) g = 8192;
-  hipLaunchKernelGGL(k_extrap, dim3(g < 1 ? 1 : g), dim3(256), 0, st, p1, p2, out, n);
+  hipLaunchKernelGGL(k_extrap, dim3(g < 1 ? 1 : g), dim3(256), 0, st, p1, p2, p3, out, n);
 }
 
 }  // namespace pmg

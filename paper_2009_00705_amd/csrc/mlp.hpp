@@ -6,9 +6,10 @@
 //   x0..x3 constants: sigma = z / L, x and y scaled to [-1, 1], distance to
 //          the nearest curved boundary circle (0 without one)
 //   x4 = p1[gf] - p2[gf]                       (local rate)
-//   x5 = surf[v] - (2 p1[top] - p2[top])       (new surface data minus its extrapolation)
+//   x5 = surf[v] - base[top]                   (new surface data minus its extrapolation)
 //   x6 = p1[top] - p2[top]                     (surface rate)
-// target T = pnow[gf] - (2 p1[gf] - p2[gf])    (the correction of the extrapolation)
+// target T = pnow[gf] - base[gf]               (the correction of the extrapolation)
+// with base = 2 p1 - p2, or 3 p1 - 3 p2 + p3 when a third previous solution p3 is given
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -32,10 +33,10 @@ void launch_normalize(const float* X, int64_t n, int d, const float* mean, const
                       hipStream_t st);
 void launch_colstats(const float* X, int64_t n, int d, double* out, hipStream_t st);
 void launch_features(int64_t n1, int nz1, int nzf, int Pf, const float* cst, const double* surf, const double* p1,
-                     const double* p2, const double* pnow, float* X, float* T, hipStream_t st);
+                     const double* p2, const double* p3, const double* pnow, float* X, float* T, hipStream_t st);
 void launch_scale_out(const float* y, double s, int64_t n, double* out, hipStream_t st);
 void launch_corr_surface(int64_t n1, int nz1, int nzf, const double* surf, const double* p1, const double* p2,
-                         double* delta, hipStream_t st);
-void launch_extrap(const double* p1, const double* p2, double* out, int64_t n, hipStream_t st);
+                         const double* p3, double* delta, hipStream_t st);
+void launch_extrap(const double* p1, const double* p2, const double* p3, double* out, int64_t n, hipStream_t st);
 
 }  // namespace pmg

@@ -1099,17 +1099,17 @@ static void build_feat_cst(pmg_ctx* c) {
   c->feat_cst = c->U(f);
 }
 
-static void features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* pnow,
-                     float* X, float* T, hipStream_t st) {
+static void features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* p3,
+                     const double* pnow, float* X, float* T, hipStream_t st) {
   build_feat_cst(c);
   Level& C = c->lv[c->nl - 1];
   Level& F = c->lv[0];
-  launch_features(C.num.n_dof, int(C.num.nz), int(F.num.nz), F.P, c->feat_cst, surf, p1, p2, pnow, X, T, st);
+  launch_features(C.num.n_dof, int(C.num.nz), int(F.num.nz), F.P, c->feat_cst, surf, p1, p2, p3, pnow, X, T, st);
 }
 
 // learned correction of the extrapolation, prolongated to the finest level: out (free nodes)
 static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const double* p1, const double* p2,
-                          double* out, hipStream_t st) {
+                          const double* p3, double* out, hipStream_t st) {
   Level& C = c->lv[c->nl - 1];
   const int64_t n1 = C.num.n_dof;
   if (n->n1cap < n1) {
@@ -1118,7 +1118,7 @@ static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const doub
     n->y1 = n->A<float>(n1);
     n->n1cap = n1;
   }
-  features(c, surf, p1, p2, nullptr, n->X1, nullptr, st);
+  features(c, surf, p1, p2, p3, nullptr, n->X1, nullptr, st);
   launch_normalize(n->X1, n1, n->din, n->mean, n->istd, n->Xn, st);
   const int L = int(n->fin.size());
   const int chunk = 16384;
@@ -1131,7 +1131,7 @@ static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const doub
   // extrapolation), prolongated level by level without masking; the caller keeps the free part
   double* cur = c->nl > 1 ? C.u64 : out;
   launch_scale_out(n->y1, n->tscale, n1, cur, st);
-  launch_corr_surface(n1, int(C.num.nz), int(c->lv[0].num.nz), surf, p1, p2, cur, st);
+  launch_corr_surface(n1, int(C.num.nz), int(c->lv[0].num.nz), surf, p1, p2, p3, cur, st);
   for (int i = c->nl - 2; i >= 0; --i) {
     double* dst = i == 0 ? out : c->lv[i].u64;
     launch_prolong_elem<double>(c->lv[i].view, c->lv[i + 1].view, c->lv[i].pit64, c->lv[i].piz64, cur, c->Y, st);
@@ -1149,11 +1149,15 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
   if (!bc && c->opt.dirichlet_tags) throw Error(PMG_EINVAL, "lateral Dirichlet tags need phi_bc");
   if (!phi) throw Error(PMG_EINVAL, "phi is NULL");
   if (!(rtol >= 0) || !(atol >= 0) || imax < 0) throw Error(PMG_EINVAL, "bad tolerance");
-  if (guess < PMG_GUESS_GIVEN || guess > PMG_GUESS_EXTRAP) throw Error(PMG_EINVAL, "unknown guess mode");
-  if ((guess == PMG_GUESS_LEARNED || guess == PMG_GUESS_EXTRAP) && (!hist || !hist[0] || !hist[1]))
-    throw Error(PMG_EINVAL, "the learned and extrapolated guesses need the two previous solutions");
-  if (guess == PMG_GUESS_LEARNED && !net) throw Error(PMG_EINVAL, "learned guess without a network");
-  if (guess == PMG_GUESS_LEARNED && !surf) throw Error(PMG_EINVAL, "learned guess needs phi_surf");
+  if (guess < PMG_GUESS_GIVEN || guess > PMG_GUESS_LEARNED3) throw Error(PMG_EINVAL, "unknown guess mode");
+  const bool third = guess == PMG_GUESS_EXTRAP3 || guess == PMG_GUESS_LEARNED3;
+  const bool learned = guess == PMG_GUESS_LEARNED || guess == PMG_GUESS_LEARNED3;
+  const bool hist_based = learned || guess == PMG_GUESS_EXTRAP || guess == PMG_GUESS_EXTRAP3;
+  if (hist_based && (!hist || !hist[0] || !hist[1] || (third && !hist[2])))
+    throw Error(PMG_EINVAL, third ? "this guess needs the three previous solutions"
+                                  : "the learned and extrapolated guesses need the two previous solutions");
+  if (learned && !net) throw Error(PMG_EINVAL, "learned guess without a network");
+  if (learned && !surf) throw Error(PMG_EINVAL, "learned guess needs phi_surf");
   hipEvent_t ev0, ev1;
   HIPCHK(hipEventCreate(&ev0));
   HIPCHK(hipEventCreate(&ev1));
@@ -1175,12 +1179,13 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     launch_finalize(c->partial, c->scal, S_TMP1, FIN_SET, st);
     if (read_scal(c, S_TMP1, st) != 0.0) throw Error(PMG_ENONFINITE, "non-finite initial guess");
     launch_merge_free(F.view, phi, nullptr, c->s_u, st);
-  } else if (guess == PMG_GUESS_EXTRAP || guess == PMG_GUESS_LEARNED) {
-    launch_extrap(hist[0], hist[1], c->s_y, N, st);
+  } else if (hist_based) {
+    const double* p3 = third ? hist[2] : nullptr;
+    launch_extrap(hist[0], hist[1], p3, c->s_y, N, st);
     launch_mask<double>(F.view, c->s_y, c->s_u, st);
-    if (guess == PMG_GUESS_LEARNED) {
+    if (learned) {
       // candidate = extrapolation + learned correction; keep it only if its residual is smaller
-      learned_guess(c, net, surf, hist[0], hist[1], c->s_q, st);
+      learned_guess(c, net, surf, hist[0], hist[1], p3, c->s_q, st);
       launch_axpy(c->s_q, c->s_y, 1.0, N, st);            // extrapolation + correction
       launch_mask<double>(F.view, c->s_q, c->s_q, st);
       ax_elem<double>(c, 0, c->s_u, st);
@@ -1750,12 +1755,13 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
   return PMG_OK;
 }
 
-int pmg_features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* pnow, float* X,
+int pmg_features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* p3,
+                 const double* pnow, float* X,
                  float* T, void* stream) {
   if (!c || !surf || !p1 || !p2 || !X || (T && !pnow)) return PMG_EINVAL;
   PMG_TRY(c, {
     need_device(c);
-    features(c, surf, p1, p2, pnow, X, T, S(stream));
+    features(c, surf, p1, p2, p3, pnow, X, T, S(stream));
   });
   return PMG_OK;
 }

@@ -61,13 +61,18 @@ class History:
                 mode = "given"
             elif guess in ("extrap", "learned") and (n - 1) in sols and (n - 2) in sols:
                 hist = [sols[n - 1], sols[n - 2]]
+            elif guess in ("extrap3", "learned3") and all((n - k) in sols for k in (1, 2, 3)):
+                hist = [sols[n - 1], sols[n - 2], sols[n - 3]]
+            elif guess in ("extrap3", "learned3") and (n - 1) in sols and (n - 2) in sols:
+                mode, hist = "extrap", [sols[n - 1], sols[n - 2]]
             elif guess != "zero":
                 mode = "given" if (n - 1) in sols else "zero"
                 if mode == "given":
                     phi.copy_(sols[n - 1])
             t.cuda.synchronize()
             t0 = time.perf_counter()
-            rc, st = self.ctx.solve(phi, phi_surf=phis, guess=mode, hist=hist, net=net if mode == "learned" else None,
+            rc, st = self.ctx.solve(phi, phi_surf=phis, guess=mode, hist=hist,
+                                    net=net if mode in ("learned", "learned3") else None,
                                     rtol=rtol, imax=imax)
             t.cuda.synchronize()
             st["wall_ms"] = (time.perf_counter() - t0) * 1e3
@@ -77,15 +82,17 @@ class History:
             sols[n] = phi
         return sols, stats
 
-    def training_set(self, sols, steps):
-        """Features and targets of the coarsest nodes for the given steps (device float32)."""
+    def training_set(self, sols, steps, third=False):
+        """Features and targets of the coarsest nodes for the given steps (device
+        float32), relative to the second- or (third=True) third-order extrapolation."""
         t = self.torch
         Xs, Ts = [], []
         for n in steps:
             _, phis = self.surface(n)
             X = t.empty((self.n1, 7), dtype=t.float32, device="cuda")
             T = t.empty(self.n1, dtype=t.float32, device="cuda")
-            self.ctx.features(phis, sols[n - 1], sols[n - 2], X, pnow=sols[n], T=T)
+            self.ctx.features(phis, sols[n - 1], sols[n - 2], X, pnow=sols[n], T=T,
+                              p3=sols[n - 3] if third else None)
             Xs.append(X)
             Ts.append(T)
         return t.cat(Xs).contiguous(), t.cat(Ts).contiguous()

@@ -19,7 +19,8 @@ LIB_PATH = os.path.join(HERE, "libpmg.so")
 PMG_OK, PMG_NOT_CONVERGED, PMG_FALLBACK_USED = 0, 1, 2
 PMG_FP64, PMG_MIXED_FP32, PMG_MIXED_BF16, PMG_MIXED_BF16G = 0, 1, 2, 3
 PMG_PCG, PMG_FPCG, PMG_PDC, PMG_MG = 0, 1, 2, 3
-PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED, PMG_GUESS_EXTRAP = 0, 1, 2, 3
+PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED, PMG_GUESS_EXTRAP, PMG_GUESS_EXTRAP3, PMG_GUESS_LEARNED3 = \
+    0, 1, 2, 3, 4, 5
 PMG_COARSE_EXACT, PMG_COARSE_CHEBYSHEV = 0, 1
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FALLBACK_USED", -1: "EINVAL", -2: "ENOMEM",
@@ -103,7 +104,7 @@ SIGNATURES = {
     "pmg_set_solver": (_I, [_VP, _I, _I]),
     "pmg_coarse_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_time_kernel": (_I, [_VP, _I, _I, _I, _I, C.POINTER(C.c_double), _VP]),
-    "pmg_features": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pmg_features": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_net_create": (_I, [_VP, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_VP)]),
     "pmg_net_destroy": (None, [_VP]),
     "pmg_net_size": (_I, [_VP, _VP, _VP, _VP, _VP]),
@@ -319,20 +320,20 @@ class Context:
                                       C.byref(ms), _stream(stream)))
         return ms.value
 
-    def features(self, surf, p1, p2, X, pnow=None, T=None, stream=None):
-        self._c(lib().pmg_features(self.h, _dptr(surf), _dptr(p1), _dptr(p2), _dptr(pnow), _dptr(X), _dptr(T),
-                                   _stream(stream)))
+    def features(self, surf, p1, p2, X, pnow=None, T=None, p3=None, stream=None):
+        self._c(lib().pmg_features(self.h, _dptr(surf), _dptr(p1), _dptr(p2), _dptr(p3), _dptr(pnow), _dptr(X),
+                                   _dptr(T), _stream(stream)))
 
     def solve(self, phi, phi_surf=None, phi_bc=None, guess="zero", rtol=1e-8, atol=0.0, imax=500,
               net=None, hist=None, stream=None):
         """Solve in place into ``phi``; returns (status, stats dict)."""
         import torch
         gm = {"given": PMG_GUESS_GIVEN, "zero": PMG_GUESS_ZERO, "learned": PMG_GUESS_LEARNED,
-              "extrap": PMG_GUESS_EXTRAP}[guess]
+              "extrap": PMG_GUESS_EXTRAP, "extrap3": PMG_GUESS_EXTRAP3, "learned3": PMG_GUESS_LEARNED3}[guess]
         st = Stats()
         hp = None
         if hist is not None:
-            arr = (C.c_void_p * 2)(*[t.data_ptr() for t in hist])
+            arr = (C.c_void_p * len(hist))(*[t.data_ptr() for t in hist])
             self._keep.append(arr)
             hp = C.cast(arr, C.c_void_p)
         rc = lib().pmg_solve(self.h, _dptr(phi_surf, torch.float64), _dptr(phi_bc, torch.float64),

@@ -99,16 +99,18 @@ def test_save_load_roundtrip(ctx, tmp_path):
         other.load(p)
 
 
-def test_features_match_definition(ctx):
+@pytest.mark.parametrize("third", [False, True])
+def test_features_match_definition(ctx, third):
     import torch
     info0, info1 = ctx.levels[0], ctx.levels[-1]
     n0, n1 = info0["n_dof"], info1["n_dof"]
     rng = np.random.default_rng(0)
-    p1, p2, pn = (rng.standard_normal(n0) for _ in range(3))
+    p1, p2, pn, p3 = (rng.standard_normal(n0) for _ in range(4))
+    base = 3 * p1 - 3 * p2 + p3 if third else 2 * p1 - p2
     surf = rng.standard_normal(info0["n_surface"])
     X = torch.empty((n1, D), dtype=torch.float32, device="cuda")
     T = torch.empty(n1, dtype=torch.float32, device="cuda")
-    ctx.features(dev(surf), dev(p1), dev(p2), X, pnow=dev(pn), T=T)
+    ctx.features(dev(surf), dev(p1), dev(p2), X, pnow=dev(pn), T=T, p3=dev(p3) if third else None)
     m = W.box_mesh(3, 2)
     P, L = 4, 2
     nz0, nz1 = L * P + 1, L + 1
@@ -118,9 +120,9 @@ def test_features_match_definition(ctx):
     top = v * nz0 + nz0 - 1
     xy = m["xy"][v]
     want = np.stack([z / L, 2 * xy[:, 0] / (2 * np.pi) - 1, 2 * xy[:, 1] / (2 * np.pi) - 1, np.zeros(n1),
-                     p1[gf] - p2[gf], surf[v] - (2 * p1[top] - p2[top]), p1[top] - p2[top]], axis=1)
+                     p1[gf] - p2[gf], surf[v] - base[top], p1[top] - p2[top]], axis=1)
     np.testing.assert_allclose(host(X), want, atol=2e-6 * np.abs(want).max())
-    np.testing.assert_allclose(host(T), pn[gf] - (2 * p1[gf] - p2[gf]), atol=2e-6 * np.abs(pn).max() * 3)
+    np.testing.assert_allclose(host(T), pn[gf] - base[gf], atol=2e-6 * np.abs(pn).max() * 8)
 
 
 def test_learned_guess_on_a_short_history():
@@ -159,6 +161,30 @@ def test_learned_guess_on_a_short_history():
     net = pmg.Net(ctx, width=32, depth=2, seed=1)
     loss = net.train(X, T, steps=600, batch=256, lr=2e-3)
     assert np.isfinite(loss) and loss < 1.0
+    # the same on the third-order base
+    Xs3, Ts3 = [], []
+    for n in range(3, 18):
+        X3 = torch.empty((n1, 7), dtype=torch.float32, device="cuda")
+        T3 = torch.empty(n1, dtype=torch.float32, device="cuda")
+        ctx.features(surfs[n], sols[n - 1], sols[n - 2], X3, pnow=sols[n], T=T3, p3=sols[n - 3])
+        Xs3.append(X3)
+        Ts3.append(T3)
+    net3 = pmg.Net(ctx, width=32, depth=2, seed=1)
+    loss3 = net3.train(torch.cat(Xs3).contiguous(), torch.cat(Ts3).contiguous(), steps=600, batch=256, lr=2e-3)
+    assert np.isfinite(loss3)
+    for n in range(18, 24):
+        eta, phis = wg.surface(xy[:, 0], n)
+        ctx.set_surface(dev(eta))
+        hist3 = [sols[n - 1], sols[n - 2], sols[n - 3]]
+        pe = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        _, se = ctx.solve(pe, phi_surf=dev(phis), guess="extrap3", hist=hist3, rtol=1e-10)
+        pl = torch.zeros(n0, dtype=torch.float64, device="cuda")
+        rc, sl = ctx.solve(pl, phi_surf=dev(phis), guess="learned3", hist=hist3, net=net3, rtol=1e-10)
+        assert rc in (0, 2)
+        assert sl["res_hist"][0] <= se["res_hist"][0] * (1 + 1e-12)
+        assert (rc == 2) == bool(sl["fallback"])
+        assert torch.max(torch.abs(pl - sols[n])).item() <= 1e-8 * torch.max(torch.abs(sols[n])).item()
+        assert torch.max(torch.abs(pe - sols[n])).item() <= 1e-8 * torch.max(torch.abs(sols[n])).item()
     for n in range(18, 24):
         eta, phis = wg.surface(xy[:, 0], n)
         ctx.set_surface(dev(eta))
