@@ -298,8 +298,10 @@ def main():
         try:
             tr = json.load(open(prof))
             key = f"{a.workload}:{kprec}"
-            if key in tr and tr[key].get("src_hash") == _kernel_src_hash():
+            # counters taken on the kernels as they are now (same source hash), else null
+            if key in tr and tr.get("src_hash") == _kernel_src_hash():
                 roof["traffic"] = tr[key]["bytes_per_launch"]
+                roof["traffic_source"] = "profiles/" + tr.get("source", "traffic.json")
         except Exception:
             pass
 
