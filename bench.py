@@ -182,6 +182,115 @@ def bench_history(a):
     print(json.dumps(out), flush=True)
 
 
+def bench_scaling(a):
+    """O(n) series (Sec. 6.3): FP64 PCG with the exact coarse solve on split-quad
+    boxes refined at a fixed element aspect ratio, (N, L) = (4,1) ... (32,8) at
+    P = 6; mean convergence factor q, iterations and time per node."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    from paper_2009_00705_amd import workloads as W
+    log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
+    nu = a.nu if a.nu > 0 else (3 if a.smoother == "chebyshev" else 2)
+    rows = []
+    for nq, L in ((4, 1), (8, 2), (16, 4), (32, 8)):
+        mesh = W.box_mesh(nq, L)
+        ctx = pmg.Context(mesh, P=a.P, coarse="exact", smoother=a.smoother, nu1=nu, nu2=nu)
+        xy = ctx.surface_xy()
+        eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
+        ctx.set_surface(torch.from_numpy(eta).cuda())
+        surf = torch.from_numpy(W.mode_sum(xy[:, 0], xy[:, 1], eta, W.mode_amplitudes(3), W.mode_pairs())).cuda()
+        n = ctx.levels[0]["n_dof"]
+        phi = torch.zeros(n, dtype=torch.float64, device="cuda")
+        for _ in range(a.warmup):
+            phi.zero_()
+            ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            phi.zero_()
+            rc, st = ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        q = st["q"]
+        row = {"N": nq, "L": L, "prisms": ctx.levels[0]["n_elem"], "n_dof": n, "iters": st["iters"],
+               "q_mean": float(np.exp(np.mean(np.log(q)))), "q_max": float(q.max()), "ms_per_solve": dt * 1e3,
+               "ns_per_dof": dt * 1e9 / n, "rel_res": st["rel_res"], "status": int(rc)}
+        rows.append(row)
+        log(f"[scaling] {row}")
+        ctx.close()
+    qs = [r["q_mean"] for r in rows]
+    out = {"metric": "mean convergence factor q and time per node over refinement at a fixed aspect ratio",
+           "value": round(max(qs) / min(qs), 4), "unit": "max q / min q", "n_gpus": 1, "steps": a.steps,
+           "warmup": a.warmup, "ms_per_step": round(rows[-1]["ms_per_solve"], 3), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"box [0,2pi]^2 x [-1,0], (N,L) = (4,1)..(32,8), P={a.P}, FP64 PCG, exact coarse "
+                                  f"solve, {a.smoother} {nu}+{nu}", "rtol": a.rtol},
+           "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
+def bench_cylinder(a):
+    """C4: unstructured cylinder mesh at P = 6.  (i) no-flux cylinder, walls and
+    bottom with the k = 1 linear wave on the surface, every precision; (ii) the
+    uniform flow past the cylinder with Dirichlet surface and walls, against its
+    closed form."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    from paper_2009_00705_amd import workloads as W
+    log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
+    nu = a.nu if a.nu > 0 else 3
+    mesh = W.config_mesh("c4")
+    paths = {}
+    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu)
+    info0 = ctx.levels[0]
+    xy = ctx.surface_xy()
+    ctx.set_surface(torch.zeros(xy.shape[0], dtype=torch.float64, device="cuda"))
+    xyz = ctx.node_xyz(0)
+    field = W.linear_wave(xyz[:, 0], xyz[:, 1], xyz[:, 2], 1.0)
+    top = np.arange(info0["n_dof"]) % (4 * a.P + 1) == 4 * a.P
+    surf = torch.from_numpy(np.ascontiguousarray(field[top])).cuda()
+    phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
+    for prec in [p for p in a.precisions.split(",") if p]:
+        ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
+        for _ in range(a.warmup):
+            phi.zero_()
+            ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(a.steps):
+            phi.zero_()
+            rc, st = ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / a.steps
+        paths[prec] = {"solves_per_s": 1 / dt, "ms_per_solve": dt * 1e3, "dof_per_s": info0["n_dof"] / dt,
+                       "iters": st["iters"], "rel_res": st["rel_res"], "status": int(rc)}
+        log(f"[c4] no-flux cylinder {prec}: {paths[prec]}")
+    cinfo = ctx.coarse_info()
+    ctx.close()
+    # (ii) uniform flow: Dirichlet surface and the four walls, no-flux cylinder and bottom
+    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu, dirichlet_tags=0b11110)
+    ctx.set_surface(torch.zeros(xy.shape[0], dtype=torch.float64, device="cuda"))
+    exact = W.uniform_flow_cylinder(xyz[:, 0], xyz[:, 1])
+    phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
+    rc, st = ctx.solve(phi, phi_bc=torch.from_numpy(exact).cuda(), rtol=1e-12, imax=800)
+    err = float(np.abs(phi.cpu().numpy() - exact).max() / np.abs(exact).max())
+    log(f"[c4] uniform flow past the cylinder: {st['iters']} iterations, max error vs closed form {err:.3e}")
+    ctx.close()
+    best = max(paths, key=lambda k: paths[k]["solves_per_s"])
+    out = {"metric": METRIC, "value": round(paths[best]["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
+           "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(paths[best]["ms_per_solve"], 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[best],
+           "data": "synthetic",
+           "config": {"workload": f"c4: seeded Delaunay cylinder mesh, {info0['n_elem']} prisms, P={a.P}, no-flux "
+                                  "cylinder, k=1 surface data", "n_dof": info0["n_dof"], "rtol": a.rtol,
+                      "coarse": cinfo, "precision": best},
+           "paths": paths,
+           "uniform_flow_check": {"iters": st["iters"], "rel_res": st["rel_res"], "max_rel_error": err}}
+    if "fp64" in paths:
+        out["speedup_vs_fp64"] = paths[best]["solves_per_s"] / paths["fp64"]["solves_per_s"]
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -208,6 +317,10 @@ def main():
         sys.exit(2)
     if a.workload == "c5":
         return bench_history(a)
+    if a.workload == "scaling":
+        return bench_scaling(a)
+    if a.workload == "c4":
+        return bench_cylinder(a)
     import torch
     from paper_2009_00705_amd import pmg
     from paper_2009_00705_amd import workloads as W
