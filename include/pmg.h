@@ -126,17 +126,27 @@ typedef struct pmg_options {
   int32_t smoother;       /* pmg_smoother                                         */
   double smooth_ratio;    /* Chebyshev smoother interval [lambda/ratio, lambda],
                              lambda = 4/(3 omega) of the level                   */
+  int32_t coarsening;     /* pmg_coarsening: order sequence of the levels        */
 } pmg_options;
 
+/* Order sequence of the levels.  BOTH: P, floor(P/2), ..., 1 in every direction
+ * (Sec. 5, Table BTcoarse).  XY_FIRST: the triangle order is coarsened first
+ * with the vertical order kept, then the vertical order, (P,P) -> (P/2,P) ->
+ * ... -> (1,P) -> (1,P/2) -> ... -> (1,1): semi-coarsening for prisms whose
+ * in-plane node spacing is much finer than the vertical one (anisotropic
+ * orders, as the (5,3) -> (3,3) -> (1,1) sequence of Sec. 6.2). */
+enum pmg_coarsening { PMG_COARSEN_BOTH = 0, PMG_COARSEN_XY_FIRST = 1 };
+
 typedef struct pmg_level_info {
-  int32_t order;          /* P_l */
-  int32_t np;             /* nodes per prism (P+1)^2 (P+2)/2 */
-  int32_t nq;             /* cubature points per prism (P+1)^3 */
+  int32_t order;          /* P_l: order on the triangle */
+  int32_t np;             /* nodes per prism (P+1)(P+2)/2 (PZ+1) */
+  int32_t nq;             /* cubature points per prism (P+1)^2 (PZ+1) */
   int32_t n_colours;
   int64_t n_dof;          /* all global nodes of the level */
   int64_t n_free;         /* nodes not on the Dirichlet boundary */
   int64_t n_elem;
   int64_t n_surface;      /* 2D nodes = surface nodes of the level */
+  int32_t order_z;        /* PZ_l: order along the extrusion */
 } pmg_level_info;
 
 typedef struct pmg_stats {

@@ -32,11 +32,14 @@ def edges_of(tri: np.ndarray):
 
 
 class Numbering:
-    """Global numbering of order P on the extruded mesh."""
+    """Global numbering of order P (triangle) and PZ (vertical, default P) on
+    the extruded mesh."""
 
-    def __init__(self, mesh: dict, P: int):
+    def __init__(self, mesh: dict, P: int, PZ: int = None):
+        PZ = P if PZ is None else PZ
         self.P = P
-        re = ref(P)
+        self.PZ = PZ
+        re = ref(P, PZ)
         tri = np.asarray(mesh["tri"], dtype=np.int64)
         self.nv = int(np.asarray(mesh["xy"]).shape[0])
         self.nt = tri.shape[0]
@@ -46,7 +49,7 @@ class Numbering:
         self.ne = edges.shape[0]
         self.nint = (P - 1) * (P - 2) // 2 if P >= 3 else 0
         self.n2d = self.nv + self.ne * max(P - 1, 0) + self.nt * self.nint
-        self.nz = self.L * P + 1
+        self.nz = self.L * PZ + 1
         self.n_dof = self.n2d * self.nz
         self.np_tri = re.np_tri
         self.np = re.np
@@ -77,11 +80,11 @@ class Numbering:
         self.n_elem = E
         layer = np.tile(np.arange(self.L), self.nt)
         t_of_e = np.repeat(np.arange(self.nt), self.L)
-        c = np.repeat(np.arange(P + 1), self.np_tri)        # local node n -> c
-        a = np.tile(np.arange(self.np_tri), P + 1)          # local node n -> a
-        z = layer[:, None] * P + c[None, :]
+        c = np.repeat(np.arange(PZ + 1), self.np_tri)       # local node n -> c
+        a = np.tile(np.arange(self.np_tri), PZ + 1)         # local node n -> a
+        z = layer[:, None] * PZ + c[None, :]
         self.map = m2[t_of_e][:, a] * self.nz + z
-        self.surface_nodes = np.arange(self.n2d) * self.nz + self.L * P
+        self.surface_nodes = np.arange(self.n2d) * self.nz + self.L * PZ
         self.mult = np.bincount(self.map.ravel(), minlength=self.n_dof).astype(np.float64)
 
     def _edge_node(self, va, vb, eid, m):
@@ -188,16 +191,16 @@ def unique_xy_2d(mesh: dict, num: Numbering) -> np.ndarray:
 
 
 def node_xyz(mesh: dict, num: Numbering, eta2d: np.ndarray) -> np.ndarray:
-    """xyz of every global node: z = -h + sigma (eta + h), sigma = z_level / (L P) in LGL spacing."""
-    P, L = num.P, num.L
-    re = ref(P)
+    """xyz of every global node: z = -h + sigma (eta + h), sigma of level layer PZ + c in LGL spacing."""
+    PZ, L = num.PZ, num.L
+    re = ref(num.P, PZ)
     h = float(mesh["depth"])
     xy = unique_xy_2d(mesh, num)
-    # sigma of vertical level zl = layer P + c
+    # sigma of vertical level zl = layer PZ + c
     sig = np.empty(num.nz)
     for layer in range(L):
-        for c in range(P + 1):
-            sig[layer * P + c] = (layer + (1 + re.t[c]) / 2) / L
+        for c in range(PZ + 1):
+            sig[layer * PZ + c] = (layer + (1 + re.t[c]) / 2) / L
     out = np.empty((num.n_dof, 3))
     g2 = np.repeat(np.arange(num.n2d), num.nz)
     zl = np.tile(np.arange(num.nz), num.n2d)

@@ -25,22 +25,35 @@ import scipy.sparse.linalg as spla
 
 from .mesh import Numbering, lateral_dirichlet_2d
 from .operator import LevelGeometry, StiffnessOperator, element_node_xyz
-from .refelem import ref, vandermonde_1d, vandermonde_tri
+from .refelem import order_pair, ref, vandermonde_1d, vandermonde_tri
 
 
-def level_orders(P: int):
-    out = [P]
-    while out[-1] > 1:
-        out.append(max(1, out[-1] // 2))
-    return out
+def level_orders(P: int, coarsening: str = "both"):
+    """Orders of the levels, finest first.  "both": P, floor(P/2), ..., 1 in
+    every direction (Sec. 5).  "xy": the triangle order is coarsened first
+    with the vertical order kept, then the vertical order, (P, P) -> ... ->
+    (1, P) -> (1, floor(P/2)) -> ... -> (1, 1) (semi-coarsening, for prisms
+    whose in-plane node spacing is much finer than the vertical one)."""
+    def seq(p):
+        out = [p]
+        while out[-1] > 1:
+            out.append(max(1, out[-1] // 2))
+        return out
+    if coarsening == "both":
+        return seq(P)
+    if coarsening == "xy":
+        return [(pt, P) for pt in seq(P)] + [(1, pz) for pz in seq(P)[1:]]
+    raise ValueError(coarsening)
 
 
-def element_prolongation(Pf: int, Pc: int) -> np.ndarray:
-    """Pi (Np_f x Np_c): coarse nodal basis evaluated at the fine nodes."""
-    rf, rc = ref(Pf), ref(Pc)
-    Vt, _, _ = vandermonde_tri(rf.r, rf.s, Pc)
+def element_prolongation(Pf, Pc) -> np.ndarray:
+    """Pi (Np_f x Np_c): coarse nodal basis evaluated at the fine nodes,
+    Pi = Pi_z (x) Pi_tri (each factor the identity where that order is kept)."""
+    (ft, fz), (ct, cz) = order_pair(Pf), order_pair(Pc)
+    rf, rc = ref(ft, fz), ref(ct, cz)
+    Vt, _, _ = vandermonde_tri(rf.r, rf.s, ct)
     Pi_tri = Vt @ rc.Vinv
-    V1, _ = vandermonde_1d(rf.t, Pc)
+    V1, _ = vandermonde_1d(rf.t, cz)
     Pi_z = V1 @ rc.V1inv
     return np.kron(Pi_z, Pi_tri)
 
@@ -61,7 +74,7 @@ def splitmix64_unit(n: int, seed: int) -> np.ndarray:
 class Level:
     def __init__(self, mesh, P, Pf, xyz_f, dir2d, top_neumann):
         self.P = P
-        self.num = Numbering(mesh, P)
+        self.num = Numbering(mesh, *order_pair(P))
         self.geo = LevelGeometry(P, Pf, xyz_f)
         self.op = StiffnessOperator(self.num, self.geo)
         n = self.num
@@ -88,10 +101,10 @@ class Hierarchy:
     def __init__(self, mesh: dict, P: int, eta2d=None, nu1=2, nu2=2, omega=None,
                  dirichlet_tags: int = 0, top_neumann: bool = False,
                  coarse: str = "exact", cheb=None, seed: int = 0,
-                 smoother: str = "jacobi", smooth_ratio: float = 15.0):
+                 smoother: str = "jacobi", smooth_ratio: float = 15.0, coarsening: str = "both"):
         self.mesh = mesh
         self.P = P
-        self.orders = level_orders(P)
+        self.orders = level_orders(P, coarsening)
         num_f = Numbering(mesh, P)
         if eta2d is None:
             eta2d = np.zeros(num_f.n2d)
@@ -99,7 +112,7 @@ class Hierarchy:
         xyz_f = element_node_xyz(mesh, num_f, self.eta2d)
         self.levels = []
         for p in self.orders:
-            nl = Numbering(mesh, p)
+            nl = Numbering(mesh, *order_pair(p))
             d2 = lateral_dirichlet_2d(mesh, nl, dirichlet_tags) if dirichlet_tags else None
             self.levels.append(Level(mesh, p, P, xyz_f, d2, top_neumann))
         self.nu1, self.nu2 = nu1, nu2

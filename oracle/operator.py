@@ -16,7 +16,7 @@ from __future__ import annotations
 import numpy as np
 
 from .mesh import Numbering, node_xy_2d
-from .refelem import ref
+from .refelem import order_pair, ref
 
 
 def element_node_xyz(mesh: dict, num_f: Numbering, eta2d: np.ndarray) -> np.ndarray:
@@ -47,8 +47,8 @@ class LevelGeometry:
     tests (volume, physical gradients).
     """
 
-    def __init__(self, Pl: int, Pf: int, xyz_f: np.ndarray):
-        rl = ref(Pl)
+    def __init__(self, Pl, Pf: int, xyz_f: np.ndarray):
+        rl = ref(*order_pair(Pl))
         rf = ref(Pf)
         # fine-order map, differentiated at this level's cubature points
         _, Dr, Ds, Dt = rf.prism_mats(rl.cr, rl.cs, rl.zq)
@@ -84,7 +84,7 @@ class StiffnessOperator:
     def __init__(self, num: Numbering, geo: LevelGeometry):
         self.num = num
         self.geo = geo
-        rl = ref(num.P)
+        rl = ref(num.P, getattr(num, "PZ", num.P))
         self.Dr = np.kron(rl.Bz, rl.Dr)
         self.Ds = np.kron(rl.Bz, rl.Ds)
         self.Dt = np.kron(rl.Dz, rl.B)

@@ -174,23 +174,28 @@ def tri_cubature(P: int):
 # ---------------------------------------------------------------------------
 
 class RefElement:
-    """Reference prism of order P with matrices at its own cubature points."""
+    """Reference prism of order P in the triangle and PZ (default P) along the
+    extrusion, with matrices at its own cubature points: (P+1)^2 collapsed
+    points on the triangle times PZ+1 Gauss points vertically (exact for the
+    stiffness of affine prisms in each direction)."""
 
-    def __init__(self, P: int):
+    def __init__(self, P: int, PZ: int = None):
+        PZ = P if PZ is None else PZ
         self.P = P
-        self.n1 = P + 1
+        self.PZ = PZ
+        self.n1 = PZ + 1
         self.np_tri = (P + 1) * (P + 2) // 2
-        self.np = self.np_tri * (P + 1)
+        self.np = self.np_tri * (PZ + 1)
         self.nq_tri = (P + 1) ** 2
-        self.nq = self.nq_tri * (P + 1)
+        self.nq = self.nq_tri * (PZ + 1)
         self.r, self.s = tri_nodes(P)
-        self.t = lgl_nodes(P)
+        self.t = lgl_nodes(PZ)
         self.V, _, _ = vandermonde_tri(self.r, self.s, P)
         self.Vinv = np.linalg.inv(self.V)
-        self.V1, _ = vandermonde_1d(self.t, P)
+        self.V1, _ = vandermonde_1d(self.t, PZ)
         self.V1inv = np.linalg.inv(self.V1)
         self.cr, self.cs, self.cw = tri_cubature(P)
-        self.zq, self.zw = gauss_legendre(P + 1)
+        self.zq, self.zw = gauss_legendre(PZ + 1)
         self.B, self.Dr, self.Ds = self.tri_eval(self.cr, self.cs)
         self.Bz, self.Dz = self.line_eval(self.zq)
         self.w = np.kron(self.zw, self.cw)  # prism cubature weights
@@ -201,7 +206,7 @@ class RefElement:
         return Vq @ self.Vinv, Vr @ self.Vinv, Vs @ self.Vinv
 
     def line_eval(self, t):
-        Vq, Vt = vandermonde_1d(t, self.P)
+        Vq, Vt = vandermonde_1d(t, self.PZ)
         return Vq @ self.V1inv, Vt @ self.V1inv
 
     def prism_mats(self, cr, cs, zq):
@@ -212,5 +217,12 @@ class RefElement:
 
 
 @lru_cache(maxsize=None)
-def ref(P: int) -> RefElement:
-    return RefElement(P)
+def ref(P: int, PZ: int = None) -> RefElement:
+    return RefElement(P, P if PZ is None else PZ)
+
+
+def order_pair(order):
+    """(triangle order, vertical order) of a level order given as P or (P, PZ)."""
+    if isinstance(order, (tuple, list)):
+        return int(order[0]), int(order[1])
+    return int(order), int(order)

@@ -51,8 +51,8 @@ static inline int grid_for(int64_t n, int per = 256, int cap = 65535 * 4) {
   return int(g);
 }
 
-// position of vertical level z inside a column of L*(P+1) element values;
-// p2 >= 0 when z is an interior layer interface (two element copies)
+// position of vertical level z inside a column of L*(P+1) element values (P the
+// vertical order); p2 >= 0 when z is an interior layer interface (two copies)
 __device__ __forceinline__ void column_pos(int z, int P, int L, int& p1, int& p2) {
   if (z == 0) { p1 = 0; p2 = -1; return; }
   const int layer = (z - 1) / P;
@@ -64,20 +64,21 @@ __device__ __forceinline__ void column_pos(int z, int P, int L, int& p1, int& p2
 // ---------------------------------------------------------------------------
 // generic element operator (all orders, LDS staged)
 // ---------------------------------------------------------------------------
-template <int P> struct Dims {
-  static constexpr int N1 = P + 1, NPT = (P + 1) * (P + 2) / 2, NP = NPT * N1;
-  static constexpr int NQT = N1 * N1, NQ = NQT * N1;
+// PT: triangle order, PZ: vertical order (N1 = PZ + 1 vertical nodes / points)
+template <int PT, int PZ> struct Dims {
+  static constexpr int N1 = PZ + 1, NPT = (PT + 1) * (PT + 2) / 2, NP = NPT * N1;
+  static constexpr int NQT = (PT + 1) * (PT + 1), NQ = NQT * N1;
   static constexpr int NMAT = 3 * NQT * NPT + 2 * N1 * N1;
   static constexpr int PER_EL = (NP > 3 * NQ ? NP : 3 * NQ) + 2 * N1 * NPT;
   static constexpr int NEB = (4096 / PER_EL) < 1 ? 1 : ((4096 / PER_EL) > 64 ? 64 : (4096 / PER_EL));
 };
 
-template <int P, typename T, typename TG>
+template <int PT, int PZ, typename T, typename TG>
 __global__ __launch_bounds__(256) void k_ax(const int32_t* __restrict__ map2d, int L, int nz,
                                             int64_t n_elem, const T* __restrict__ mats,
                                             const TG* __restrict__ G, const T* __restrict__ u,
                                             T* __restrict__ Y) {
-  using D = Dims<P>;
+  using D = Dims<PT, PZ>;
   constexpr int N1 = D::N1, NPT = D::NPT, NP = D::NP, NQT = D::NQT, NQ = D::NQ, NEB = D::NEB;
   constexpr int SA = (NP > 3 * NQ ? NP : 3 * NQ), SB = 2 * N1 * NPT;
   __shared__ T sm_mat[D::NMAT];
@@ -97,7 +98,7 @@ __global__ __launch_bounds__(256) void k_ax(const int32_t* __restrict__ map2d, i
       const int el = i / NP, r = i - el * NP, a = r / N1, c = r - a * N1;
       const int64_t e = e0 + el;
       const int t = int(e / L), layer = int(e - int64_t(t) * L);
-      const int64_t g = int64_t(map2d[size_t(t) * NPT + a]) * nz + layer * P + c;
+      const int64_t g = int64_t(map2d[size_t(t) * NPT + a]) * nz + layer * PZ + c;
       sm_a[el * SA + c * NPT + a] = u[g];
     }
     __syncthreads();
@@ -168,37 +169,30 @@ __global__ __launch_bounds__(256) void k_ax(const int32_t* __restrict__ map2d, i
   }
 }
 
-template <int P, typename T>
+template <int PT, int PZ, typename T>
 static void ax_dispatch_g(const LevelView& lv, const T* mats, const void* G, int gstore, const T* u,
                           T* Y, hipStream_t st) {
-  constexpr int NEB = Dims<P>::NEB;
+  constexpr int NEB = Dims<PT, PZ>::NEB;
   const int64_t nb = (lv.n_elem + NEB - 1) / NEB;
   const int grid = int(nb < 262144 ? nb : 262144);
   if (gstore == G_F64)
-    hipLaunchKernelGGL((k_ax<P, T, double>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
+    hipLaunchKernelGGL((k_ax<PT, PZ, T, double>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, mats, (const double*)G, u, Y);
   else if (gstore == G_F32)
-    hipLaunchKernelGGL((k_ax<P, T, float>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
+    hipLaunchKernelGGL((k_ax<PT, PZ, T, float>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, mats, (const float*)G, u, Y);
   else
-    hipLaunchKernelGGL((k_ax<P, T, bf16_t>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
+    hipLaunchKernelGGL((k_ax<PT, PZ, T, bf16_t>), dim3(grid), dim3(256), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, mats, (const bf16_t*)G, u, Y);
 }
 
 template <typename T>
 void launch_ax(const LevelView& lv, const T* mats, const void* G, int gstore, const T* u, T* Y,
                hipStream_t st) {
-  switch (lv.P) {
-    case 1: ax_dispatch_g<1, T>(lv, mats, G, gstore, u, Y, st); break;
-    case 2: ax_dispatch_g<2, T>(lv, mats, G, gstore, u, Y, st); break;
-    case 3: ax_dispatch_g<3, T>(lv, mats, G, gstore, u, Y, st); break;
-    case 4: ax_dispatch_g<4, T>(lv, mats, G, gstore, u, Y, st); break;
-    case 5: ax_dispatch_g<5, T>(lv, mats, G, gstore, u, Y, st); break;
-    case 6: ax_dispatch_g<6, T>(lv, mats, G, gstore, u, Y, st); break;
-    case 7: ax_dispatch_g<7, T>(lv, mats, G, gstore, u, Y, st); break;
-    case 8: ax_dispatch_g<8, T>(lv, mats, G, gstore, u, Y, st); break;
-    default: break;
-  }
+#define PMG_AX(PTV, PZV) \
+  if (lv.P == PTV && lv.PZ == PZV) return ax_dispatch_g<PTV, PZV, T>(lv, mats, G, gstore, u, Y, st);
+  PMG_ORDERS(PMG_AX)
+#undef PMG_AX
 }
 template void launch_ax<double>(const LevelView&, const double*, const void*, int, const double*, double*, hipStream_t);
 template void launch_ax<float>(const LevelView&, const float*, const void*, int, const float*, float*, hipStream_t);
@@ -272,7 +266,7 @@ void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a
   const int grid = op == OP_STORE_DOT ? RED_BLOCKS : grid_for(lv.n_dof);
 #define PMG_ASM(OPV)                                                                                   \
   hipLaunchKernelGGL((k_assemble<T, OPV>), dim3(grid), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.L,  \
-                     lv.P, lv.inc_ptr, lv.inc, lv.dir2d, lv.top_dir, Y, out, a1, a2, a3, T(omega),    \
+                     lv.PZ, lv.inc_ptr, lv.inc, lv.dir2d, lv.top_dir, Y, out, a1, a2, a3, T(omega),   \
                      T(c1), partial)
   switch (op) {
     case OP_STORE: PMG_ASM(OP_STORE); break;
@@ -294,8 +288,8 @@ template void launch_assemble<float>(const LevelView&, int, const float*, float*
 // ---------------------------------------------------------------------------
 // geometric factors (thread per triangle x triangle cubature point)
 // ---------------------------------------------------------------------------
-template <int PF, int PL>
-__global__ __launch_bounds__(256) void k_geom(int nt, int L, double depth,
+template <int PF>
+__global__ __launch_bounds__(256) void k_geom(int nt, int L, int nqtl, int n1l, double depth,
                                               const double* __restrict__ xyt,
                                               const double* __restrict__ eta,
                                               const int32_t* __restrict__ map2d_f,
@@ -305,8 +299,9 @@ __global__ __launch_bounds__(256) void k_geom(int nt, int L, double depth,
                                               const double* __restrict__ zw, double* __restrict__ G64,
                                               float* __restrict__ G32, bf16_t* __restrict__ G16,
                                               int* __restrict__ bad) {
+  // fine map of order PF, evaluated at the level's nqtl triangle points and n1l vertical points
   constexpr int NPTF = (PF + 1) * (PF + 2) / 2;
-  constexpr int N1L = PL + 1, NQTL = N1L * N1L, NQL = NQTL * N1L;
+  const int NQTL = nqtl, N1L = n1l, NQL = nqtl * n1l;
   const int64_t item = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (item >= int64_t(nt) * NQTL) return;
   const int t = int(item / NQTL), q = int(item - int64_t(t) * NQTL);
@@ -351,92 +346,83 @@ __global__ __launch_bounds__(256) void k_geom(int nt, int L, double depth,
   if (badv) atomicOr(bad, 1);
 }
 
-template <int PF>
-static void geom_pl(int PL, int nt, int L, double depth, const double* xyt, const double* eta,
-                    const int32_t* map2d_f, const double* gm, const double* wq, const double* zq,
-                    const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st) {
-  const int64_t items = int64_t(nt) * (PL + 1) * (PL + 1);
+void launch_geom(const LevelView& fine, const LevelView& lvl, double depth, const double* xyt,
+                 const double* eta, const double* gmats, const double* wq, const double* zq,
+                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st) {
+  const int nqtl = (lvl.P + 1) * (lvl.P + 1), n1l = lvl.PZ + 1;
+  const int64_t items = int64_t(fine.nt) * nqtl;
   const int grid = int((items + 255) / 256);
-#define PMG_GEOM(PLV)                                                                               \
-  hipLaunchKernelGGL((k_geom<PF, PLV>), dim3(grid), dim3(256), 0, st, nt, L, depth, xyt, eta,       \
-                     map2d_f, gm, wq, zq, zw, G64, G32, G16, bad)
-  switch (PL) {
-    case 1: PMG_GEOM(1); break;
-    case 2: PMG_GEOM(2); break;
-    case 3: PMG_GEOM(3); break;
-    case 4: PMG_GEOM(4); break;
-    case 5: PMG_GEOM(5); break;
-    case 6: PMG_GEOM(6); break;
-    case 7: PMG_GEOM(7); break;
-    case 8: PMG_GEOM(8); break;
+#define PMG_GEOM(PFV)                                                                               \
+  case PFV:                                                                                         \
+    hipLaunchKernelGGL((k_geom<PFV>), dim3(grid), dim3(256), 0, st, fine.nt, fine.L, nqtl, n1l, depth, xyt, \
+                       eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad);                     \
+    break;
+  switch (fine.P) {
+    PMG_GEOM(1) PMG_GEOM(2) PMG_GEOM(3) PMG_GEOM(4) PMG_GEOM(5) PMG_GEOM(6) PMG_GEOM(7) PMG_GEOM(8)
     default: break;
   }
 #undef PMG_GEOM
 }
 
-void launch_geom(const LevelView& fine, const LevelView& lvl, double depth, const double* xyt,
-                 const double* eta, const double* gmats, const double* wq, const double* zq,
-                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st) {
-  switch (fine.P) {
-    case 1: geom_pl<1>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    case 2: geom_pl<2>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    case 3: geom_pl<3>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    case 4: geom_pl<4>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    case 5: geom_pl<5>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    case 6: geom_pl<6>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    case 7: geom_pl<7>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    case 8: geom_pl<8>(lvl.P, fine.nt, fine.L, depth, xyt, eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, st); break;
-    default: break;
-  }
-}
-
 // ---------------------------------------------------------------------------
-// diagonal of the element matrices, E-layout (thread per (e, a, c))
+// diagonal of the element matrices, E-layout.  With the tensor structure
+// D_r = B_z (x) Dr, D_s = B_z (x) Ds, D_t = D_z (x) B:
+//   diag[c][a] = sum_k Bz[k][c]^2 S1[k][a] + 2 Bz[k][c] Dz[k][c] S2[k][a] + Dz[k][c]^2 S3[k][a]
+//   S1 = sum_q G_rr Dr^2 + 2 G_rs Dr Ds + G_ss Ds^2,  S2 = sum_q (G_rt Dr + G_st Ds) B,
+//   S3 = sum_q G_tt B^2   (q over the triangle points of vertical point k).
+// One element per block iteration with its G staged in LDS.
 // ---------------------------------------------------------------------------
-template <int P>
-__global__ __launch_bounds__(256) void k_diag(int64_t n_elem, int L, const double* __restrict__ mats,
-                                              const double* __restrict__ G, double* __restrict__ Y) {
-  constexpr int N1 = P + 1, NPT = (P + 1) * (P + 2) / 2, NP = NPT * N1, NQT = N1 * N1, NQ = NQT * N1;
+__global__ __launch_bounds__(256) void k_diag(int64_t n_elem, int L, int npt, int nqt, int n1,
+                                              const double* __restrict__ mats, const double* __restrict__ G,
+                                              double* __restrict__ Y) {
+  extern __shared__ double dsm[];
+  const int nq = nqt * n1;
+  double* sG = dsm;               // [6][nq]
+  double* sS = sG + 6 * nq;       // [3][n1][npt]
   const double* Dr = mats;
-  const double* Ds = Dr + NQT * NPT;
-  const double* Bt = Ds + NQT * NPT;
-  const double* Bz = Bt + NQT * NPT;
-  const double* Dz = Bz + N1 * N1;
-  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n_elem * NP; i += int64_t(gridDim.x) * 256) {
-    const int64_t e = i / NP;
-    const int r = int(i - e * NP), a = r / N1, c = r - a * N1;
-    const double* Ge = G + size_t(e) * 6 * NQ;
-    double d = 0.0;
-    for (int k = 0; k < N1; ++k) {
-      const double bz = Bz[k * N1 + c], dz = Dz[k * N1 + c];
-      for (int q = 0; q < NQT; ++q) {
-        const int p = k * NQT + q;
-        const double dr = bz * Dr[q * NPT + a], ds = bz * Ds[q * NPT + a], dt = dz * Bt[q * NPT + a];
-        d += dr * (Ge[p] * dr + 2.0 * Ge[NQ + p] * ds + 2.0 * Ge[2 * NQ + p] * dt) +
-             ds * (Ge[3 * NQ + p] * ds + 2.0 * Ge[4 * NQ + p] * dt) + dt * Ge[5 * NQ + p] * dt;
+  const double* Ds = Dr + nqt * npt;
+  const double* Bt = Ds + nqt * npt;
+  const double* Bz = Bt + nqt * npt;
+  const double* Dz = Bz + n1 * n1;
+  for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < 6 * nq; i += 256) sG[i] = G[size_t(e) * 6 * nq + i];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n1 * npt; i += 256) {
+      const int k = i / npt, a = i - k * npt;
+      double s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      for (int q = 0; q < nqt; ++q) {
+        const int p = k * nqt + q;
+        const double dr = Dr[q * npt + a], ds = Ds[q * npt + a], b = Bt[q * npt + a];
+        s1 += dr * (sG[p] * dr + 2.0 * sG[nq + p] * ds) + ds * sG[3 * nq + p] * ds;
+        s2 += (sG[2 * nq + p] * dr + sG[4 * nq + p] * ds) * b;
+        s3 += sG[5 * nq + p] * b * b;
       }
+      sS[i] = s1;
+      sS[n1 * npt + i] = s2;
+      sS[2 * n1 * npt + i] = s3;
     }
+    __syncthreads();
     const int t = int(e / L), layer = int(e - int64_t(t) * L);
-    Y[((size_t(t) * NPT + a) * L + layer) * N1 + c] = d;
+    for (int i = threadIdx.x; i < npt * n1; i += 256) {
+      const int a = i / n1, c = i - a * n1;
+      double d = 0.0;
+      for (int k = 0; k < n1; ++k) {
+        const double bz = Bz[k * n1 + c], dz = Dz[k * n1 + c];
+        d += bz * bz * sS[k * npt + a] + 2.0 * bz * dz * sS[n1 * npt + k * npt + a] +
+             dz * dz * sS[2 * n1 * npt + k * npt + a];
+      }
+      Y[((size_t(t) * npt + a) * L + layer) * n1 + c] = d;
+    }
   }
 }
 
 void launch_diag(const LevelView& lv, const double* mats, const double* G64, double* Y, hipStream_t st) {
-  const int64_t n = lv.n_elem * lv.np;
-  const int grid = grid_for(n);
-#define PMG_DIAG(PV) hipLaunchKernelGGL((k_diag<PV>), dim3(grid), dim3(256), 0, st, lv.n_elem, lv.L, mats, G64, Y)
-  switch (lv.P) {
-    case 1: PMG_DIAG(1); break;
-    case 2: PMG_DIAG(2); break;
-    case 3: PMG_DIAG(3); break;
-    case 4: PMG_DIAG(4); break;
-    case 5: PMG_DIAG(5); break;
-    case 6: PMG_DIAG(6); break;
-    case 7: PMG_DIAG(7); break;
-    case 8: PMG_DIAG(8); break;
-    default: break;
-  }
-#undef PMG_DIAG
+  const int npt = lv.np_tri, n1 = lv.PZ + 1, nqt = (lv.P + 1) * (lv.P + 1);
+  const size_t lds = sizeof(double) * (6 * size_t(nqt) * n1 + 3 * size_t(n1) * npt);
+  const int grid = int(lv.n_elem < 65536 ? lv.n_elem : 65536);
+  hipLaunchKernelGGL(k_diag, dim3(grid < 1 ? 1 : grid), dim3(256), lds, st, lv.n_elem, lv.L, npt, nqt, n1, mats,
+                     G64, Y);
 }
 
 // ---------------------------------------------------------------------------
@@ -447,14 +433,14 @@ void launch_diag(const LevelView& lv, const double* mats, const double* G64, dou
 // issues the whole vertical column of the prism at once.
 constexpr int XFER_NEB = 16;
 
-template <int PF, int PC, typename T>
+template <int PFT, int PFZ, int PCT, int PCZ, typename T>
 __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int nzc,
                                                       const int32_t* __restrict__ map2d_c,
                                                       const T* __restrict__ pit,
                                                       const T* __restrict__ piz,
                                                       const T* __restrict__ uc, T* __restrict__ Yf) {
-  constexpr int N1F = PF + 1, NPTF = (PF + 1) * (PF + 2) / 2, NPF = NPTF * N1F;
-  constexpr int N1C = PC + 1, NPTC = (PC + 1) * (PC + 2) / 2, NPC = NPTC * N1C;
+  constexpr int N1F = PFZ + 1, NPTF = (PFT + 1) * (PFT + 2) / 2, NPF = NPTF * N1F;
+  constexpr int N1C = PCZ + 1, NPTC = (PCT + 1) * (PCT + 2) / 2, NPC = NPTC * N1C;
   constexpr int NEB = XFER_NEB;
   __shared__ T sUc[NEB * NPC];
   __shared__ T sT1[NEB * N1C * NPTF];
@@ -466,7 +452,7 @@ __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int
       const int el = pr / NPTC, a = pr - el * NPTC;
       const int64_t e = e0 + el;
       const int t = int(e / L), layer = int(e - int64_t(t) * L);
-      const T* col = uc + int64_t(map2d_c[size_t(t) * NPTC + a]) * nzc + layer * PC;
+      const T* col = uc + int64_t(map2d_c[size_t(t) * NPTC + a]) * nzc + layer * PCZ;
       T v[N1C];
 #pragma unroll
       for (int c = 0; c < N1C; ++c) v[c] = col[c];
@@ -503,7 +489,7 @@ __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int
   }
 }
 
-template <int PF, int PC, typename T>
+template <int PFT, int PFZ, int PCT, int PCZ, typename T>
 __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, int nzf,
                                                        const int32_t* __restrict__ map2d_f,
                                                        const int32_t* __restrict__ inc_ptr_f,
@@ -511,8 +497,8 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
                                                        const T* __restrict__ pit,
                                                        const T* __restrict__ piz,
                                                        const T* __restrict__ rf, T* __restrict__ Yc) {
-  constexpr int N1F = PF + 1, NPTF = (PF + 1) * (PF + 2) / 2, NPF = NPTF * N1F;
-  constexpr int N1C = PC + 1, NPTC = (PC + 1) * (PC + 2) / 2;
+  constexpr int N1F = PFZ + 1, NPTF = (PFT + 1) * (PFT + 2) / 2, NPF = NPTF * N1F;
+  constexpr int N1C = PCZ + 1, NPTC = (PCT + 1) * (PCT + 2) / 2;
   constexpr int NEB = XFER_NEB;
   __shared__ T sRf[NEB * NPF];
   __shared__ T sT1[NEB * N1F * NPTC];
@@ -526,7 +512,7 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
       const int64_t e = e0 + el;
       const int t = int(e / L), layer = int(e - int64_t(t) * L);
       const int g2 = map2d_f[size_t(t) * NPTF + a];
-      const T* col = rf + int64_t(g2) * nzf + layer * PF;
+      const T* col = rf + int64_t(g2) * nzf + layer * PFZ;
       T v[N1F];
 #pragma unroll
       for (int c = 0; c < N1F; ++c) v[c] = col[c];
@@ -535,9 +521,9 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
       const T inv1 = T(1) / T(cnt), inv2 = T(1) / T(2 * cnt);
 #pragma unroll
       for (int c = 0; c < N1F; ++c) {
-        const int z = layer * PF + c;
+        const int z = layer * PFZ + c;
         const bool dir = dcol || (top_dir && z == nzf - 1);
-        const bool iface = (c == 0 && z > 0) || (c == PF && z < nzf - 1);
+        const bool iface = (c == 0 && z > 0) || (c == PFZ && z < nzf - 1);
         sRf[el * NPF + c * NPTF + a] = dir ? T(0) : v[c] * (iface ? inv2 : inv1);
       }
     }
@@ -571,15 +557,14 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
   }
 }
 
-#define PMG_PAIRS(X) X(2, 1) X(3, 1) X(4, 2) X(5, 2) X(6, 3) X(7, 3) X(8, 4)
 
 template <typename T>
 void launch_prolong_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* uc,
                          T* Yf, hipStream_t st) {
   const int grid = grid_for(f.n_elem, XFER_NEB, 262144);
-#define PMG_PRO(PFV, PCV)                                                                            \
-  if (f.P == PFV && c.P == PCV) {                                                                    \
-    hipLaunchKernelGGL((k_prolong_elem<PFV, PCV, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L,   \
+#define PMG_PRO(PFT, PFZ, PCT, PCZ)                                                                  \
+  if (f.P == PFT && f.PZ == PFZ && c.P == PCT && c.PZ == PCZ) {                                       \
+    hipLaunchKernelGGL((k_prolong_elem<PFT, PFZ, PCT, PCZ, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L, \
                        int(c.nz), c.map2d, pit, piz, uc, Yf);                                        \
     return;                                                                                          \
   }
@@ -591,9 +576,9 @@ template <typename T>
 void launch_restrict_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* rf,
                           T* Yc, hipStream_t st) {
   const int grid = grid_for(f.n_elem, XFER_NEB, 262144);
-#define PMG_RES(PFV, PCV)                                                                            \
-  if (f.P == PFV && c.P == PCV) {                                                                    \
-    hipLaunchKernelGGL((k_restrict_elem<PFV, PCV, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L,  \
+#define PMG_RES(PFT, PFZ, PCT, PCZ)                                                                  \
+  if (f.P == PFT && f.PZ == PFZ && c.P == PCT && c.PZ == PCZ) {                                       \
+    hipLaunchKernelGGL((k_restrict_elem<PFT, PFZ, PCT, PCZ, T>), dim3(grid), dim3(256), 0, st, f.n_elem, f.L, \
                        int(f.nz), f.map2d, f.inc_ptr, f.dir2d, f.top_dir, pit, piz, rf, Yc);        \
     return;                                                                                          \
   }

@@ -19,9 +19,22 @@ enum Scal {
   S_DELTA = 0, S_PQ, S_ALPHA, S_RR, S_ZR, S_BETA, S_FF, S_TMP0, S_TMP1, S_ZRO, S_NF, N_SCAL = 16
 };
 
+// (triangle order, vertical order) of the levels the library builds: the
+// isotropic orders and the in-plane-first chains (P, P) -> (P/2, P) -> ... ->
+// (1, P) -> (1, P/2) -> ... -> (1, 1) of every fine order up to 8
+#define PMG_ORDERS(X)                                                                                \
+  X(1, 1) X(2, 2) X(3, 3) X(4, 4) X(5, 5) X(6, 6) X(7, 7) X(8, 8) X(1, 2) X(1, 3) X(1, 4) X(1, 5) \
+  X(1, 6) X(1, 7) X(1, 8) X(2, 4) X(2, 5) X(2, 8) X(3, 6) X(3, 7) X(4, 8)
+// consecutive level pairs (fine PT, PZ, coarse PT, PZ) of both coarsening sequences
+#define PMG_PAIRS(X)                                                                                 \
+  X(2, 2, 1, 1) X(3, 3, 1, 1) X(4, 4, 2, 2) X(5, 5, 2, 2) X(6, 6, 3, 3) X(7, 7, 3, 3) X(8, 8, 4, 4) \
+  X(2, 2, 1, 2) X(1, 2, 1, 1) X(3, 3, 1, 3) X(1, 3, 1, 1) X(4, 4, 2, 4) X(2, 4, 1, 4) X(1, 4, 1, 2) \
+  X(5, 5, 2, 5) X(2, 5, 1, 5) X(1, 5, 1, 2) X(6, 6, 3, 6) X(3, 6, 1, 6) X(1, 6, 1, 3) X(7, 7, 3, 7) \
+  X(3, 7, 1, 7) X(1, 7, 1, 3) X(8, 8, 4, 8) X(4, 8, 2, 8) X(2, 8, 1, 8) X(1, 8, 1, 4)
+
 // Per-level device description.
 struct LevelView {
-  int P, L, nt;
+  int P, PZ, L, nt;        // P: triangle order, PZ: vertical order
   int np_tri, np, nq;
   int64_t n2d, nz, n_dof, n_elem;
   const int32_t* map2d;    // [nt][np_tri]

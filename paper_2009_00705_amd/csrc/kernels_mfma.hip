@@ -31,8 +31,9 @@ typedef float f4_t __attribute__((ext_vector_type(4)));
 typedef double d4_t __attribute__((ext_vector_type(4)));
 typedef short s4_t __attribute__((ext_vector_type(4)));
 
-template <int P> struct MD {
-  static constexpr int N1 = P + 1, NPT = (P + 1) * (P + 2) / 2, NQT = N1 * N1, NQ = NQT * N1;
+// PT: triangle order, PZ: vertical order; N1 = PZ + 1 vertical nodes, Gauss points and waves
+template <int PT, int PZ> struct MD {
+  static constexpr int N1 = PZ + 1, NPT = (PT + 1) * (PT + 2) / 2, NQT = (PT + 1) * (PT + 1), NQ = NQT * N1;
   static constexpr int NT2 = (NQT + 15) / 16;        // q tiles of 16
   static constexpr int NTF = NQT / 16;               // full q tiles
   static constexpr int NQR = NQT - 16 * NTF;         // rows of the remainder tile
@@ -44,11 +45,11 @@ template <int P> struct MD {
 template <bool F64ROW> __device__ __forceinline__ constexpr int row_of(int g, int r) {
   return F64ROW ? g + 4 * r : 4 * g + r;
 }
-template <int P, bool F64ROW> constexpr int n_steps4() {
+template <int PT, int PZ, bool F64ROW> constexpr int n_steps4() {
   int n = 0;
-  for (int t = 0; t < MD<P>::NT2; ++t)
+  for (int t = 0; t < MD<PT, PZ>::NT2; ++t)
     for (int r = 0; r < 4; ++r)
-      if (16 * t + (F64ROW ? 4 * r : r) < MD<P>::NQT) ++n;
+      if (16 * t + (F64ROW ? 4 * r : r) < MD<PT, PZ>::NQT) ++n;
   return n;
 }
 
@@ -82,9 +83,9 @@ __device__ __forceinline__ int64_t xcd_block(int nblk) {
 }
 
 // offset of G for (batch, k, m, lane, r) in the lane-native layout; -1 if q >= NQT
-template <int P, bool F64ROW>
+template <int PT, int PZ, bool F64ROW>
 __device__ __forceinline__ int64_t gnat_off(int64_t b, int k, int m, int t, int g, int j, int r) {
-  using D = MD<P>;
+  using D = MD<PT, PZ>;
   const int64_t blk = ((b * D::N1 + k) * 6 + m) * (16 * D::NQT);
   if (t < D::NTF) return blk + t * 256 + (g * 16 + j) * 4 + r;
   const int row = row_of<F64ROW>(g, r);
@@ -96,22 +97,22 @@ __device__ __forceinline__ int64_t gnat_off(int64_t b, int k, int m, int t, int 
 // Workgroup = N1 waves on one batch of 16 prisms; wave k owns vertical Gauss
 // level k.  Phase 0 stages u in LDS; phase 1 (per wave) runs stages 1-4 for
 // its k; phase 2 (all threads) does the vertical transpose sum over k from
-// LDS and writes the E-layout output with runs of L*(P+1) contiguous values.
+// LDS and writes the E-layout output with runs of L*(PZ+1) contiguous values.
 // ---------------------------------------------------------------------------
-template <int P> struct KS_LDS {
-  using D = MD<P>;
+template <int PT, int PZ> struct KS_LDS {
+  using D = MD<PT, PZ>;
   static constexpr int U_WORDS = D::N1 * D::NPT * 16;           // U[c][a][el]
   static constexpr int S_WORDS = D::N1 * 2 * D::NAT * 16 * 16;  // S[k][h][a][el]
   static constexpr int R_WORDS = U_WORDS > S_WORDS ? U_WORDS : S_WORDS;
 };
 
-// Stage the 16 prisms' nodal values: U[c][a][el] = u[map2d[t][a] nz + layer P + c].
-// One thread per (a, el) pair: one map read, then the P+1 vertical values of
+// Stage the 16 prisms' nodal values: U[c][a][el] = u[map2d[t][a] nz + layer PZ + c].
+// One thread per (a, el) pair: one map read, then the PZ+1 vertical values of
 // the column issued together (independent loads, a single wait).
-template <int P, typename T>
+template <int PT, int PZ, typename T>
 __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L, int nz, int64_t n_elem,
                                         int64_t b, const T* __restrict__ u, T* __restrict__ sR) {
-  using D = MD<P>;
+  using D = MD<PT, PZ>;
   constexpr int N1 = D::N1, NPT = D::NPT, NTH = 64 * N1;
   for (int pr = threadIdx.x; pr < 16 * NPT; pr += NTH) {
     const int a = pr >> 4, el = pr & 15;
@@ -119,7 +120,7 @@ __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L
     T v[N1];
     if (e < n_elem) {
       const int te = int(e / L), layer = int(e - int64_t(te) * L);
-      const T* col = u + int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * P;
+      const T* col = u + int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * PZ;
 #pragma unroll
       for (int c = 0; c < N1; ++c) v[c] = col[c];
     } else {
@@ -133,12 +134,12 @@ __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L
 
 // Vertical transpose and output: y[c][a] of prism el = sum_k Bz[k][c] Yr[k][a] +
 // Dz[k][c] Yt[k][a], with S[k][h][a][el] in LDS.  One thread per (a, el) pair
-// reads its 2(P+1) partials once and writes the P+1 contiguous outputs of its
+// reads its 2(PZ+1) partials once and writes the PZ+1 contiguous outputs of its
 // column slot in the E-layout [t][a][layer][c].
-template <int P, typename T>
+template <int PT, int PZ, typename T>
 __device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, const T* __restrict__ sR,
                                              const T* __restrict__ sV, T* __restrict__ Y) {
-  using D = MD<P>;
+  using D = MD<PT, PZ>;
   constexpr int N1 = D::N1, NPT = D::NPT, NAT = D::NAT, NTH = 64 * N1;
   for (int pr = threadIdx.x; pr < 16 * NPT; pr += NTH) {
     const int a = pr >> 4, el = pr & 15;
@@ -152,7 +153,7 @@ __device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, c
     }
     const int te = int(e / L), layer = int(e - int64_t(te) * L);
     T* out = Y + ((size_t(te) * NPT + a) * L + layer) * N1;
-    // rolled: the coefficients are LDS broadcasts read per c, not 2(P+1)^2 registers
+    // rolled: the coefficients are LDS broadcasts read per c, not 2(PZ+1)^2 registers
 #pragma unroll 1
     for (int c = 0; c < N1; ++c) {
       T y = 0;
@@ -196,20 +197,20 @@ __device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds,
 }
 
 // FP32 / FP64 flavours (K = 4)
-template <int P, typename T, typename TG, typename ACC, bool F64ROW>
-__global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
+template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW>
+__global__ __launch_bounds__(64 * (PZ + 1), sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : 4)) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
                                                          int64_t n_elem, int64_t n_batch,
                                                          const TG* __restrict__ Gnat, const T* __restrict__ tab2,
                                                          const T* __restrict__ tab4, VertMats<T> vm,
                                                          const T* __restrict__ u, T* __restrict__ Y) {
-  using D = MD<P>;
+  using D = MD<PT, PZ>;
   constexpr int N1 = D::N1, NPT = D::NPT, NP = NPT * N1, NT2 = D::NT2, KS = D::KS, NAT = D::NAT;
-  constexpr int NS4 = n_steps4<P, F64ROW>();
+  constexpr int NS4 = n_steps4<PT, PZ, F64ROW>();
   constexpr int NTAB2 = 3 * NT2 * KS * 64, NTAB4 = 3 * NAT * NS4 * 64;
   constexpr int NTH = 64 * N1;
   __shared__ T s2[NTAB2];
   __shared__ T s4[NTAB4];
-  __shared__ T sR[KS_LDS<P>::R_WORDS];
+  __shared__ T sR[KS_LDS<PT, PZ>::R_WORDS];
   __shared__ T sV[2 * N1 * N1];
   for (int i = threadIdx.x; i < NTAB2; i += NTH) s2[i] = tab2[i];
   for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
@@ -227,7 +228,7 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma4(const int32_t* __rest
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();  // previous batch's phase 2 done with sR
     // phase 0: U[c][a][el] <- u
-    stage_u<P, T>(map2d, L, nz, n_elem, b, u, sR);
+    stage_u<PT, PZ, T>(map2d, L, nz, n_elem, b, u, sR);
     __syncthreads();
     // phase 1, stage 1: W[k][a], Wz[k][a] for a = 4s + g of element j
     T w[KS], wz[KS];
@@ -311,25 +312,25 @@ __global__ __launch_bounds__(64 * (P + 1)) void k_ax_mfma4(const int32_t* __rest
       }
     __syncthreads();
     // phase 2: y[el][c][a] = sum_k Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]
-    vertical_out<P, T>(L, n_elem, b, sR, sV, Y);
+    vertical_out<PT, PZ, T>(L, n_elem, b, sR, sV, Y);
   }
 }
 
 // BF16 operands, FP32 accumulation (K = 16)
-template <int P, typename TG>
-__global__ __launch_bounds__(64 * (P + 1), P >= 8 ? 3 : 4) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
+template <int PT, int PZ, typename TG>
+__global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
                                                              int64_t n_elem, int64_t n_batch,
                                                              const TG* __restrict__ Gnat,
                                                              const s4_t* __restrict__ tab2,
                                                              const s4_t* __restrict__ tab4, VertMats<float> vm,
                                                              const float* __restrict__ u, float* __restrict__ Y) {
-  using D = MD<P>;
+  using D = MD<PT, PZ>;
   constexpr int N1 = D::N1, NPT = D::NPT, NP = NPT * N1, NT2 = D::NT2, KS16 = D::KS16, NAT = D::NAT;
   constexpr int NTAB2 = 3 * NT2 * KS16 * 64, NTAB4 = 3 * NAT * NT2 * 64;
   constexpr int NTH = 64 * N1;
   __shared__ s4_t s2[NTAB2];
   __shared__ s4_t s4[NTAB4];
-  __shared__ float sR[KS_LDS<P>::R_WORDS];
+  __shared__ float sR[KS_LDS<PT, PZ>::R_WORDS];
   __shared__ float sV[2 * N1 * N1];
   for (int i = threadIdx.x; i < NTAB2; i += NTH) s2[i] = tab2[i];
   for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
@@ -338,7 +339,7 @@ __global__ __launch_bounds__(64 * (P + 1), P >= 8 ? 3 : 4) void k_ax_mfma_bf16(c
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();
-    stage_u<P, float>(map2d, L, nz, n_elem, b, u, sR);
+    stage_u<PT, PZ, float>(map2d, L, nz, n_elem, b, u, sR);
     __syncthreads();
     s4_t w[KS16], wz[KS16];
 #pragma unroll
@@ -412,17 +413,17 @@ __global__ __launch_bounds__(64 * (P + 1), P >= 8 ? 3 : 4) void k_ax_mfma_bf16(c
         sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
       }
     __syncthreads();
-    vertical_out<P, float>(L, n_elem, b, sR, sV, Y);
+    vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
   }
 }
 
 // ---------------------------------------------------------------------------
 // G re-layout: standard [e][m][k*NQT+q] (FP64) -> lane-native order of a flavour
 // ---------------------------------------------------------------------------
-template <int P, typename TO, bool F64ROW>
+template <int PT, int PZ, typename TO, bool F64ROW>
 __global__ __launch_bounds__(256) void k_g_native(int64_t n_elem, int64_t n_batch, const double* __restrict__ G,
                                                   TO* __restrict__ out) {
-  using D = MD<P>;
+  using D = MD<PT, PZ>;
   const int64_t per_batch = int64_t(16) * 6 * D::NQ;
   const int64_t total = n_batch * per_batch;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < total; i += int64_t(gridDim.x) * 256) {
@@ -475,57 +476,62 @@ static int grid_batches(int64_t n_batch, const void* kernel, int threads) {
 
 
 
-template <int P>
+template <int PT, int PZ>
 static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
   const int64_t nb = (n_elem + 15) / 16;
-  const int64_t total = nb * 16 * 6 * MD<P>::NQ;
+  const int64_t total = nb * 16 * 6 * MD<PT, PZ>::NQ;
   int64_t grid = (total + 255) / 256;
   if (grid > 65535 * 4) grid = 65535 * 4;
   if (flavour == MF_F64)
-    hipLaunchKernelGGL((k_g_native<P, double, true>), dim3(grid), dim3(256), 0, st, n_elem, nb, G, (double*)out);
+    hipLaunchKernelGGL((k_g_native<PT, PZ, double, true>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,
+                       (double*)out);
   else if (flavour == MF_F32)
-    hipLaunchKernelGGL((k_g_native<P, float, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G, (float*)out);
+    hipLaunchKernelGGL((k_g_native<PT, PZ, float, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,
+                       (float*)out);
   else
-    hipLaunchKernelGGL((k_g_native<P, bf16_t, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G, (bf16_t*)out);
+    hipLaunchKernelGGL((k_g_native<PT, PZ, bf16_t, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,
+                       (bf16_t*)out);
 }
 
-void launch_g_native(int P, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
-  switch (P) {
-    case 3: relayout_p<3>(n_elem, G, out, flavour, st); break;
-    case 6: relayout_p<6>(n_elem, G, out, flavour, st); break;
-    case 8: relayout_p<8>(n_elem, G, out, flavour, st); break;
-    default: break;
-  }
+// orders with MFMA kernels: (3,3), (6,6), (3,6) [the in-plane-coarsened level of
+// P = 6] in every flavour, (8,8) without FP64 (its FP64 tables exceed the LDS)
+#define PMG_MFMA_ORDERS(X) X(3, 3) X(6, 6) X(3, 6) X(8, 8)
+
+void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
+#define PMG_REL(PTV, PZV) \
+  if (PT == PTV && PZ == PZV) return relayout_p<PTV, PZV>(n_elem, G, out, flavour, st);
+  PMG_MFMA_ORDERS(PMG_REL)
+#undef PMG_REL
 }
 
-template <int P>
+template <int PT, int PZ>
 static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                       const void* vmats, const void* u, void* Y, hipStream_t st) {
   const int64_t nb = (lv.n_elem + 15) / 16;
   const int64_t need = ((nb + 7) / 8) * 8;
-  constexpr int NT = 64 * (P + 1);
+  constexpr int NT = 64 * (PZ + 1);
   if (flavour == MF_F64) {
-    if constexpr (P != 8) {
-      auto kern = k_ax_mfma4<P, double, double, d4_t, true>;
+    if constexpr (PT != 8) {
+      auto kern = k_ax_mfma4<PT, PZ, double, double, d4_t, true>;
       static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
       hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                          lv.n_elem, nb, (const double*)Gnat, (const double*)tab2, (const double*)tab4,
                          *(const VertMats<double>*)vmats, (const double*)u, (double*)Y);
     }
   } else if (flavour == MF_F32) {
-    auto kern = k_ax_mfma4<P, float, float, f4_t, false>;
+    auto kern = k_ax_mfma4<PT, PZ, float, float, f4_t, false>;
     static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
     hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, nb, (const float*)Gnat, (const float*)tab2, (const float*)tab4,
                        *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
   } else if (flavour == MF_F32G16) {
-    auto kern = k_ax_mfma4<P, float, bf16_t, f4_t, false>;
+    auto kern = k_ax_mfma4<PT, PZ, float, bf16_t, f4_t, false>;
     static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
     hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, nb, (const bf16_t*)Gnat, (const float*)tab2, (const float*)tab4,
                        *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
   } else {
-    auto kern = k_ax_mfma_bf16<P, bf16_t>;
+    auto kern = k_ax_mfma_bf16<PT, PZ, bf16_t>;
     static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
     hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, nb, (const bf16_t*)Gnat, (const s4_t*)tab2, (const s4_t*)tab4,
@@ -535,12 +541,10 @@ static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const 
 
 void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                     const void* vmats, const void* u, void* Y, hipStream_t st) {
-  switch (lv.P) {
-    case 3: ax_mfma_p<3>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st); break;
-    case 6: ax_mfma_p<6>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st); break;
-    case 8: ax_mfma_p<8>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st); break;
-    default: break;
-  }
+#define PMG_AXM(PTV, PZV) \
+  if (lv.P == PTV && lv.PZ == PZV) return ax_mfma_p<PTV, PZV>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st);
+  PMG_MFMA_ORDERS(PMG_AXM)
+#undef PMG_AXM
 }
 
 }  // namespace pmg

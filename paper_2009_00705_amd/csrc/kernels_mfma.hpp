@@ -29,13 +29,13 @@ __device__ __forceinline__ double gld_any(const double* p, int64_t i) { return p
 __device__ __forceinline__ float gld_any(const float* p, int64_t i) { return p[i]; }
 __device__ __forceinline__ float gld_any(const bf16_t* p, int64_t i) { return __uint_as_float(uint32_t(p[i]) << 16); }
 
-// orders with an MFMA kernel for a flavour
-inline bool mfma_available(int P, int flavour) {
-  if (P == 6 || P == 3) return true;
-  if (P == 8) return flavour != MF_F64;
+// (triangle, vertical) orders with an MFMA kernel for a flavour
+inline bool mfma_available(int PT, int PZ, int flavour) {
+  if ((PT == 3 && PZ == 3) || (PT == 6 && PZ == 6) || (PT == 3 && PZ == 6)) return true;
+  if (PT == 8 && PZ == 8) return flavour != MF_F64;
   return false;
 }
-void launch_g_native(int P, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st);
+void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st);
 void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                     const void* vmats, const void* u, void* Y, hipStream_t st);
 

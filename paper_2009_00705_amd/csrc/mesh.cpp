@@ -9,13 +9,14 @@
 
 namespace pmg {
 
-void Numbering::build(const MeshIn& m, int P_) {
+void Numbering::build(const MeshIn& m, int P_, int PZ_) {
   P = P_;
+  PZ = PZ_ < 0 ? P_ : PZ_;
   L = m.L;
   nv = m.nv;
   nt = m.nt;
   np_tri = (P + 1) * (P + 2) / 2;
-  np = np_tri * (P + 1);
+  np = np_tri * (PZ + 1);
   nint = P >= 3 ? (P - 1) * (P - 2) / 2 : 0;
   // unique sorted edges
   std::vector<std::pair<int32_t, int32_t>> ev;
@@ -35,7 +36,7 @@ void Numbering::build(const MeshIn& m, int P_) {
   for (size_t k = 0; k < ev.size(); ++k)
     tri_edge[k] = int32_t(std::lower_bound(uniq.begin(), uniq.end(), ev[k]) - uniq.begin());
   n2d = int64_t(nv) + int64_t(ne) * std::max(P - 1, 0) + int64_t(nt) * nint;
-  nz = int64_t(L) * P + 1;
+  nz = int64_t(L) * PZ + 1;
   n_dof = n2d * nz;
   n_elem = int64_t(nt) * L;
   if (n_dof >= (int64_t(1) << 31) || n_elem * np >= (int64_t(1) << 31))
@@ -76,9 +77,9 @@ void Numbering::gather_map(int32_t* out) const {
   for (int t = 0; t < nt; ++t)
     for (int layer = 0; layer < L; ++layer) {
       int32_t* row = out + (size_t(t) * L + layer) * np;
-      for (int c = 0; c <= P; ++c)
+      for (int c = 0; c <= PZ; ++c)
         for (int a = 0; a < np_tri; ++a)
-          row[c * np_tri + a] = int32_t(int64_t(map2d[size_t(t) * np_tri + a]) * nz + layer * P + c);
+          row[c * np_tri + a] = int32_t(int64_t(map2d[size_t(t) * np_tri + a]) * nz + layer * PZ + c);
     }
 }
 

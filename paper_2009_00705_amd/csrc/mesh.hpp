@@ -28,14 +28,14 @@ struct MeshIn {
 };
 
 struct Numbering {
-  int P = 0, L = 0, nv = 0, nt = 0, ne = 0, nint = 0, np_tri = 0, np = 0;
+  int P = 0, PZ = 0, L = 0, nv = 0, nt = 0, ne = 0, nint = 0, np_tri = 0, np = 0;  // P: triangle, PZ: vertical
   int64_t n2d = 0, nz = 0, n_dof = 0, n_elem = 0;
   std::vector<int32_t> edges;     // ne*2 sorted (min,max)
   std::vector<int32_t> tri_edge;  // nt*3 edge id of (tri[i], tri[(i+1)%3])
   std::vector<int32_t> map2d;     // nt*np_tri local triangle node -> 2D id
   std::vector<int32_t> inc_ptr;   // n2d+1: incidences of each 2D node
   std::vector<int32_t> inc;       // t*np_tri + a, ascending
-  void build(const MeshIn& m, int P);
+  void build(const MeshIn& m, int P, int PZ = -1);
   void gather_map(int32_t* out) const;       // [n_elem][np]
   std::vector<int32_t> colours() const;      // greedy, ascending element order
 };

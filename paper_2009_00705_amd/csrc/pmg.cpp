@@ -67,7 +67,7 @@ static double splitmix_unit(uint64_t seed, uint64_t i) {
 }
 
 struct Level {
-  int P = 0;
+  int P = 0, PZ = 0;  // triangle and vertical order
   std::unique_ptr<RefElem> re;
   Numbering num;
   std::vector<uint8_t> dir2d_h;
@@ -237,17 +237,33 @@ static std::vector<double> pack_mats(const RefElem& re) {
   return m;
 }
 
+// Orders of the levels, finest first (Sec. 5: P, floor(P/2), ..., 1).  With the
+// in-plane-first option the triangle order is coarsened first with the vertical
+// order kept, then the vertical order: (P,P) -> ... -> (1,P) -> (1,P/2) -> ... -> (1,1).
+static std::vector<std::pair<int, int>> level_orders(int P, int coarsening) {
+  std::vector<int> seq{P};
+  while (seq.back() > 1) seq.push_back(std::max(1, seq.back() / 2));
+  std::vector<std::pair<int, int>> out;
+  if (coarsening == PMG_COARSEN_XY_FIRST) {
+    for (int pt : seq) out.emplace_back(pt, P);
+    for (size_t i = 1; i < seq.size(); ++i) out.emplace_back(1, seq[i]);
+  } else {
+    for (int p : seq) out.emplace_back(p, p);
+  }
+  return out;
+}
+
 static void build_levels(pmg_ctx* c) {
   const pmg_options& o = c->opt;
-  std::vector<int> orders{o.P};
-  while (orders.back() > 1) orders.push_back(std::max(1, orders.back() / 2));
+  const std::vector<std::pair<int, int>> orders = level_orders(o.P, o.coarsening);
   c->nl = int(orders.size());
   c->lv.resize(c->nl);
   for (int i = 0; i < c->nl; ++i) {
     Level& L = c->lv[i];
-    L.P = orders[i];
-    L.re.reset(new RefElem(L.P));
-    L.num.build(c->mesh, L.P);
+    L.P = orders[i].first;
+    L.PZ = orders[i].second;
+    L.re.reset(new RefElem(L.P, L.PZ));
+    L.num.build(c->mesh, L.P, L.PZ);
     L.dir2d_h = lateral_dirichlet(c->mesh, L.num, o.dirichlet_tags);
     L.top_dir = o.top_neumann ? 0 : 1;
     int64_t nd = 0;
@@ -325,7 +341,7 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
   const int64_t nb = (L.num.n_elem + 15) / 16;
   const size_t ng = size_t(nb) * 16 * 6 * re.nq;
   for (int f = 0; f < 3; ++f) {
-    if (!mfma_available(L.P, f)) continue;
+    if (!mfma_available(L.P, L.PZ, f)) continue;
     std::vector<double> t2, t4;
     std::vector<uint16_t> b2, b4;
     mfma_tables(re, f, t2, t4, b2, b4);
@@ -391,7 +407,7 @@ static void upload_levels(pmg_ctx* c) {
     }
     maxE = std::max(maxE, E * re.np);
     if (c->opt.kernel_variant == 0) upload_mfma(c, L);
-    L.view = LevelView{L.P, L.num.L, L.num.nt, re.np_tri, re.np, re.nq, L.num.n2d, L.num.nz, N, E,
+    L.view = LevelView{L.P, L.PZ, L.num.L, L.num.nt, re.np_tri, re.np, re.nq, L.num.n2d, L.num.nz, N, E,
                        L.map2d, L.inc_ptr, L.inc, L.dir2d, L.top_dir};
     if (i + 1 < c->nl) {
       const RefElem& rc = *c->lv[i + 1].re;
@@ -676,7 +692,7 @@ static void lanczos_bounds(pmg_ctx* c, int i, int m, double& lmin, double& lmax,
 // the reference derivative matrices D_a[q][n] of the P = 1 prism.
 static void coarse_csr_pattern(pmg_ctx* c) {
   Level& L = c->lv[c->nl - 1];
-  if (L.P != 1) throw Error(PMG_EINVAL, "coarsest level is not P = 1");
+  if (L.P != 1 || L.PZ != 1) throw Error(PMG_EINVAL, "coarsest level is not of order 1");
   const RefElem& re = *L.re;
   const int64_t E = L.num.n_elem, N = L.num.n_dof;
   const int np = re.np, nq = re.nq, npt = re.np_tri, nqt = re.nq_tri, n1 = re.n1;
@@ -903,7 +919,7 @@ static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
   for (int i = 0; i < c->nl; ++i) {
     Level& L = c->lv[i];
     for (int f = 0; f < 3; ++f)
-      if (L.mf[f]) launch_g_native(L.P, L.num.n_elem, L.G64, L.gnat[f], f, st);
+      if (L.mf[f]) launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
   }
   // Jacobi diagonals
   for (int i = 0; i < c->nl; ++i) {
@@ -1104,7 +1120,8 @@ static void features(pmg_ctx* c, const double* surf, const double* p1, const dou
   build_feat_cst(c);
   Level& C = c->lv[c->nl - 1];
   Level& F = c->lv[0];
-  launch_features(C.num.n_dof, int(C.num.nz), int(F.num.nz), F.P, c->feat_cst, surf, p1, p2, p3, pnow, X, T, st);
+  launch_features(C.num.n_dof, int(C.num.nz), int(F.num.nz), F.PZ / C.PZ, c->feat_cst, surf, p1, p2, p3, pnow, X,
+                  T, st);
 }
 
 // learned correction of the extrapolation, prolongated to the finest level: out (free nodes)
@@ -1318,11 +1335,11 @@ static void node_xyz(pmg_ctx* c, int level, double* xyz) {
       eta2[g2] = h;
     }
   const double hd = c->mesh.depth;
-  const int Lr = L.num.L, P = L.P;
+  const int Lr = L.num.L, PZ = L.PZ;
   for (int64_t g2 = 0; g2 < L.num.n2d; ++g2)
     for (int z = 0; z < L.num.nz; ++z) {
-      const int layer = std::min(z / P, Lr - 1);
-      const int cc = z - layer * P;
+      const int layer = std::min(z / PZ, Lr - 1);
+      const int cc = z - layer * PZ;
       const double sig = (layer + 0.5 * (1.0 + rl.t[cc])) / Lr;
       const size_t g = size_t(g2) * L.num.nz + z;
       xyz[3 * g] = xy2[2 * g2];
@@ -1398,6 +1415,7 @@ void pmg_options_default(pmg_options* o) {
   o->exact_max = 12000;
   o->smoother = PMG_SMOOTH_JACOBI;
   o->smooth_ratio = 15.0;
+  o->coarsening = PMG_COARSEN_BOTH;
   o->seed = 0;
 }
 
@@ -1417,6 +1435,7 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (o->precision < 0 || o->precision > 3) throw Error(PMG_EINVAL, "bad precision");
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
     if (o->smoother < 0 || o->smoother > 1) throw Error(PMG_EINVAL, "bad smoother");
+    if (o->coarsening < 0 || o->coarsening > 1) throw Error(PMG_EINVAL, "bad coarsening");
     if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
       throw Error(PMG_EINVAL, "smooth_ratio must exceed 1");
     c = new pmg_ctx();
@@ -1471,6 +1490,7 @@ int pmg_level_info_get(const pmg_ctx* c, int level, pmg_level_info* info) {
     check_level(c, level);
     const Level& L = c->lv[level];
     info->order = L.P;
+    info->order_z = L.PZ;
     info->np = L.re->np;
     info->nq = L.re->nq;
     info->n_dof = L.num.n_dof;

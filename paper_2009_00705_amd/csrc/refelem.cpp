@@ -184,17 +184,18 @@ std::vector<Ijk> tri_lattice(int P) {
   return out;
 }
 
-RefElem::RefElem(int P_) : P(P_) {
-  if (P < 1 || P > 8) throw std::runtime_error("order must be in [1, 8]");
-  n1 = P + 1;
+RefElem::RefElem(int P_, int PZ_) : P(P_), PZ(PZ_ < 0 ? P_ : PZ_) {
+  if (P < 1 || P > 8 || PZ < 1 || PZ > 8) throw std::runtime_error("order must be in [1, 8]");
+  const int m1 = P + 1;  // 1D points of the triangle order
+  n1 = PZ + 1;
   np_tri = (P + 1) * (P + 2) / 2;
   np = np_tri * n1;
-  nq_tri = n1 * n1;
+  nq_tri = m1 * m1;
   nq = nq_tri * n1;
   // triangle nodes from the LGL nodes (closed form of Blyth & Pozrikidis)
-  t = lgl_nodes(P);
-  std::vector<double> v(n1);
-  for (int i = 0; i < n1; ++i) v[i] = 0.5 * (1.0 + t[i]);
+  const std::vector<double> tl = lgl_nodes(P);
+  std::vector<double> v(m1);
+  for (int i = 0; i < m1; ++i) v[i] = 0.5 * (1.0 + tl[i]);
   for (const Ijk& l : tri_lattice(P)) {
     const double x = (1.0 + 2.0 * v[l.i] - v[l.j] - v[l.k]) / 3.0;
     const double y = (1.0 + 2.0 * v[l.j] - v[l.i] - v[l.k]) / 3.0;
@@ -204,15 +205,17 @@ RefElem::RefElem(int P_) : P(P_) {
   Mat V, Vr, Vs;
   pkd_basis(P, r, s, V, Vr, Vs);
   Vinv = inverse(V);
+  // vertical LGL nodes of order PZ
+  t = lgl_nodes(PZ);
   Mat V1, V1x;
-  legendre_basis(P, t, V1, V1x);
+  legendre_basis(PZ, t, V1, V1x);
   V1inv = inverse(V1);
   // collapsed cubature: GL in a, GJ(1,0) in b
   std::vector<double> a, wa, b, wb;
-  gauss_legendre(n1, a, wa);
-  gauss_jacobi10(n1, b, wb);
-  for (int j = 0; j < n1; ++j)
-    for (int i = 0; i < n1; ++i) {
+  gauss_legendre(m1, a, wa);
+  gauss_jacobi10(m1, b, wb);
+  for (int j = 0; j < m1; ++j)
+    for (int i = 0; i < m1; ++i) {
       cr.push_back(0.5 * (1.0 + a[i]) * (1.0 - b[j]) - 1.0);
       cs.push_back(b[j]);
       cw.push_back(0.5 * wa[i] * wb[j]);
@@ -233,7 +236,7 @@ void RefElem::tri_eval(const std::vector<double>& pr, const std::vector<double>&
 
 void RefElem::line_eval(const std::vector<double>& pt, Mat& Bo, Mat& Do) const {
   Mat V, Vx;
-  legendre_basis(P, pt, V, Vx);
+  legendre_basis(PZ, pt, V, Vx);
   Bo = matmul(V, V1inv);
   Do = matmul(Vx, V1inv);
 }

@@ -38,19 +38,21 @@ void pkd_basis(int P, const std::vector<double>& r, const std::vector<double>& s
 struct Ijk { int i, j, k; };
 std::vector<Ijk> tri_lattice(int P);
 
+// Order P on the triangle and PZ (default P) along the extrusion: n1 = PZ + 1
+// vertical nodes and Gauss points, (P+1)^2 triangle cubature points.
 struct RefElem {
-  int P = 0, n1 = 0, np_tri = 0, np = 0, nq_tri = 0, nq = 0;
+  int P = 0, PZ = 0, n1 = 0, np_tri = 0, np = 0, nq_tri = 0, nq = 0;
   std::vector<double> r, s, t;      // triangle nodes (r,s), vertical LGL t
   std::vector<double> cr, cs, cw;   // triangle cubature points / weights
   std::vector<double> zq, zw;       // vertical Gauss points / weights
   Mat Vinv, V1inv;                  // inverse Vandermonde matrices
   Mat B, Dr, Ds;                    // Nq_tri x Np_tri at own cubature
   Mat Bz, Dz;                       // n1 x n1 at own Gauss points
-  explicit RefElem(int P);
+  explicit RefElem(int P, int PZ = -1);
   // Order-P nodal triangle basis (and r,s-derivatives) at arbitrary points.
   void tri_eval(const std::vector<double>& pr, const std::vector<double>& ps,
                 Mat& Bo, Mat& Dro, Mat& Dso) const;
-  // Order-P nodal 1D basis (and derivative) at arbitrary points.
+  // Order-PZ nodal 1D basis (and derivative) at arbitrary points.
   void line_eval(const std::vector<double>& pt, Mat& Bo, Mat& Do) const;
 };
 

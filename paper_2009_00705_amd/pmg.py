@@ -22,6 +22,7 @@ PMG_PCG, PMG_FPCG, PMG_PDC, PMG_MG = 0, 1, 2, 3
 PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED, PMG_GUESS_EXTRAP, PMG_GUESS_EXTRAP3, PMG_GUESS_LEARNED3 = \
     0, 1, 2, 3, 4, 5
 PMG_COARSE_EXACT, PMG_COARSE_CHEBYSHEV = 0, 1
+PMG_COARSEN_BOTH, PMG_COARSEN_XY_FIRST = 0, 1
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FALLBACK_USED", -1: "EINVAL", -2: "ENOMEM",
           -3: "EDEVICE", -4: "EBREAKDOWN", -5: "ENONFINITE", -6: "EMESH", -7: "ESTATE"}
@@ -49,13 +50,14 @@ class Options(C.Structure):
                 ("top_neumann", C.c_int32), ("coarse", C.c_int32), ("cheb_degree", C.c_int32),
                 ("cheb_lmin", C.c_double), ("cheb_lmax", C.c_double), ("cheb_ratio", C.c_double),
                 ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32),
-                ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double)]
+                ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
+                ("coarsening", C.c_int32)]
 
 
 class LevelInfo(C.Structure):
     _fields_ = [("order", C.c_int32), ("np", C.c_int32), ("nq", C.c_int32), ("n_colours", C.c_int32),
                 ("n_dof", C.c_int64), ("n_free", C.c_int64), ("n_elem", C.c_int64),
-                ("n_surface", C.c_int64)]
+                ("n_surface", C.c_int64), ("order_z", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -181,6 +183,8 @@ def default_options(**kw) -> Options:
             o.smoother = {"jacobi": 0, "chebyshev": 1}[v]
         elif k == "coarse" and isinstance(v, str):
             o.coarse = {"exact": PMG_COARSE_EXACT, "chebyshev": PMG_COARSE_CHEBYSHEV}[v]
+        elif k == "coarsening" and isinstance(v, str):
+            o.coarsening = {"both": PMG_COARSEN_BOTH, "xy": PMG_COARSEN_XY_FIRST}[v]
         else:
             setattr(o, k, v)
     return o

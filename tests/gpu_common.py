@@ -42,6 +42,8 @@ def make_pair(mesh, P, eta_kind="wavy", omega=0.3, **kw):
     if "smoother" in kw:
         okw["smoother"] = kw["smoother"]
         okw["smooth_ratio"] = kw.get("smooth_ratio", 15.0)
+    if "coarsening" in kw:
+        okw["coarsening"] = kw["coarsening"]
     if kw.get("coarse") == "chebyshev":
         okw["coarse"] = "chebyshev"
         okw["cheb"] = (kw["cheb_degree"], kw["cheb_lmin"], kw["cheb_lmax"])

@@ -24,12 +24,19 @@ CASES = {
     "cyl_P3": (lambda: W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=3), 3),
     "box2_L1_P8": (lambda: W.box_mesh(2, 1), 8),
 }
+# in-plane-first hierarchies (anisotropic orders, e.g. (6,6) (3,6) (1,6) (1,3) (1,1))
+XY_CASES = {k + "_xy": v for k, v in CASES.items() if k != "c1"}
+ALL = dict(CASES, **XY_CASES)
 
 
-@pytest.fixture(scope="module", params=sorted(CASES))
+def _opts(name):
+    return {"coarsening": "xy"} if name.endswith("_xy") else {}
+
+
+@pytest.fixture(scope="module", params=sorted(ALL))
 def pair(request):
-    mk, P = CASES[request.param]
-    h, ctx = make_pair(mk(), P)
+    mk, P = ALL[request.param]
+    h, ctx = make_pair(mk(), P, **_opts(request.param))
     yield request.param, h, ctx
     ctx.close()
 
@@ -56,12 +63,12 @@ def test_operator_fp64_all_levels(pair):
 def test_operator_low_precision(pair, prec, tol):
     name, h, ctx = pair
     import torch
-    lv = h.levels[0]
-    n = lv.num.n_dof
-    x = _rand(n, 3)
-    y = torch.empty(n, dtype=torch.float32, device="cuda")
-    ctx.apply(0, dev(x, torch.float32), y, prec, masked=True)
-    assert rel_err(host(y), lv.A(x.astype(np.float32).astype(np.float64))) < tol
+    for lvl, lv in enumerate(h.levels):
+        n = lv.num.n_dof
+        x = _rand(n, 3 + lvl)
+        y = torch.empty(n, dtype=torch.float32, device="cuda")
+        ctx.apply(lvl, dev(x, torch.float32), y, prec, masked=True)
+        assert rel_err(host(y), lv.A(x.astype(np.float32).astype(np.float64))) < tol, (name, lvl)
 
 
 def test_diagonal(pair):
@@ -124,10 +131,10 @@ def _dirichlet(h, ctx, k=1.0):
     return phi_o, surf_l
 
 
-@pytest.fixture(scope="module", params=sorted(CASES))
+@pytest.fixture(scope="module", params=sorted(ALL))
 def solve_pair(request):
-    mk, P = CASES[request.param]
-    h, ctx = make_pair(mk(), P, omega="auto")
+    mk, P = ALL[request.param]
+    h, ctx = make_pair(mk(), P, omega="auto", **_opts(request.param))
     yield request.param, h, ctx
     ctx.close()
 

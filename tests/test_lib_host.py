@@ -71,6 +71,26 @@ def test_colours_bit_exact(meshname, P):
 
 
 @pytest.mark.parametrize("meshname", sorted(MESHES))
+@pytest.mark.parametrize("P", [2, 3, 5, 6, 8])
+def test_in_plane_first_levels_bit_exact(meshname, P):
+    """Levels of the in-plane-first sequence (triangle order coarsened first,
+    then the vertical order): orders, sizes and gather maps equal the oracle's
+    numbering of the same (triangle, vertical) orders."""
+    from oracle.mg import level_orders
+    m = MESHES[meshname]()
+    ctx = _host_ctx(m, P, coarsening="xy")
+    orders = level_orders(P, "xy")
+    assert ctx.n_levels == len(orders)
+    for lvl, (pt, pz) in enumerate(orders):
+        num = M.Numbering(m, pt, pz)
+        info = ctx.levels[lvl]
+        assert (info["order"], info["order_z"]) == (pt, pz)
+        assert info["n_dof"] == num.n_dof and info["np"] == num.np and info["n_surface"] == num.n2d
+        np.testing.assert_array_equal(ctx.gather_map(lvl), num.map.astype(np.int32))
+    ctx.close()
+
+
+@pytest.mark.parametrize("meshname", sorted(MESHES))
 def test_surface_xy_and_node_xyz(meshname):
     m = MESHES[meshname]()
     P = 4
