@@ -78,7 +78,7 @@ def op_bytes(info0, nt, np_tri, s_g, s_v):
     return info0["n_elem"] * 6 * info0["nq"] * s_g + info0["n_dof"] * s_v + nt * np_tri * 4
 
 
-def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4):
+def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both"):
     """The oracle's complete FP64 PCG solve on a slice of the workload, scaled to the full mesh.
 
     The slice is the same split-quad box, order, layer count, surface elevation,
@@ -93,7 +93,7 @@ def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16
     num = OM.Numbering(m, P)
     xy = OM.unique_xy_2d(m, num)
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
-    h = mg.Hierarchy(m, P, eta, nu1=nu, nu2=nu, smoother=smoother, coarse="exact")
+    h = mg.Hierarchy(m, P, eta, nu1=nu, nu2=nu, smoother=smoother, coarse="exact", coarsening=coarsening)
     t_setup = time.perf_counter() - t0
     xyz = OM.node_xyz(m, num, eta)
     phi_dir = W.mode_sum(xyz[:, 0], xyz[:, 1], xyz[:, 2], W.mode_amplitudes(3), W.mode_pairs())
@@ -108,7 +108,7 @@ def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16
     except Exception:
         cores = 1
     return {"value": 1.0 / t_full, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle FP64 PCG solve (same smoother, exact coarse solve, rtol 1e-8) on a "
+            "sample": (f"oracle FP64 PCG solve (same smoother and level orders, exact coarse solve, rtol 1e-8) on a "
                        f"{n_side}x{n_side}x{n_layers} slice of the workload ({num.n_elem} prisms, {num.n_dof} "
                        f"nodes): {t_solve:.1f} s for {r.iters} iterations after {t_setup:.1f} s set-up; "
                        f"{t_iter:.2f} s/iteration scaled by {n_elem_full}/{num.n_elem} prisms and "
@@ -125,7 +125,8 @@ def bench_history(a):
     log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
     mesh = W.config_mesh("c5")
     nu = a.nu if a.nu > 0 else 3
-    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu)
+    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu,
+                      coarsening=a.coarsening)
     wave = W.WaveGroup(n_steps=300)
     H = History(ctx, wave)
     H.set_step(0)
@@ -168,6 +169,7 @@ def bench_history(a):
            "config": {"workload": f"c5: seeded Delaunay cylinder mesh, {info0['n_elem']} prisms, P={a.P}, "
                                   "300-step focusing group (16 components), train 0-199, test 200-299",
                       "n_dof": info0["n_dof"], "rtol": a.rtol, "smoother": f"{a.smoother} {nu}+{nu}",
+                      "coarsening": a.coarsening,
                       "coarse": ctx.coarse_info(), "net_params": nets["learned"].n_params, "training": train,
                       "best": best},
            "paths": paths,
@@ -194,7 +196,8 @@ def bench_scaling(a):
     rows = []
     for nq, L in ((4, 1), (8, 2), (16, 4), (32, 8)):
         mesh = W.box_mesh(nq, L)
-        ctx = pmg.Context(mesh, P=a.P, coarse="exact", smoother=a.smoother, nu1=nu, nu2=nu)
+        ctx = pmg.Context(mesh, P=a.P, coarse="exact", smoother=a.smoother, nu1=nu, nu2=nu,
+                          coarsening=a.coarsening)
         xy = ctx.surface_xy()
         eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
         ctx.set_surface(torch.from_numpy(eta).cuda())
@@ -241,7 +244,8 @@ def bench_cylinder(a):
     nu = a.nu if a.nu > 0 else 3
     mesh = W.config_mesh("c4")
     paths = {}
-    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu)
+    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu,
+                      coarsening=a.coarsening)
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     ctx.set_surface(torch.zeros(xy.shape[0], dtype=torch.float64, device="cuda"))
@@ -268,7 +272,8 @@ def bench_cylinder(a):
     cinfo = ctx.coarse_info()
     ctx.close()
     # (ii) uniform flow: Dirichlet surface and the four walls, no-flux cylinder and bottom
-    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu, dirichlet_tags=0b11110)
+    ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu, dirichlet_tags=0b11110,
+                      coarsening=a.coarsening)
     ctx.set_surface(torch.zeros(xy.shape[0], dtype=torch.float64, device="cuda"))
     exact = W.uniform_flow_cylinder(xyz[:, 0], xyz[:, 1])
     phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
@@ -303,6 +308,8 @@ def main():
     ap.add_argument("--coarse-degree", type=int, default=0, help="Chebyshev coarse degree (0: automatic)")
     ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "jacobi"])
     ap.add_argument("--nu", type=int, default=0, help="smoothing degree/sweeps (0: 3 Chebyshev, 2 Jacobi)")
+    ap.add_argument("--coarsening", default="xy", choices=["xy", "both"],
+                    help="level orders: in-plane first (xy) or all directions at once (both)")
     ap.add_argument("--smooth-ratio", type=float, default=15.0,
                     help="Chebyshev smoother interval [lambda/ratio, lambda]")
     ap.add_argument("--no-cpu", action="store_true")
@@ -328,13 +335,13 @@ def main():
     log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
     mesh, wl_desc = workload(a.workload)
     t0 = time.perf_counter()
-    probe = pmg.Context(mesh, P=a.P, host_only=1)
+    probe = pmg.Context(mesh, P=a.P, host_only=1, coarsening=a.coarsening)
     nc_free = probe.levels[-1]["n_free"]
     probe.close()
     coarse = "exact" if nc_free <= 12000 else "chebyshev"
     nu = a.nu if a.nu > 0 else (3 if a.smoother == "chebyshev" else 2)
     ctx = pmg.Context(mesh, P=a.P, coarse=coarse, cheb_degree=a.coarse_degree, smoother=a.smoother,
-                      nu1=nu, nu2=nu, smooth_ratio=a.smooth_ratio)
+                      nu1=nu, nu2=nu, smooth_ratio=a.smooth_ratio, coarsening=a.coarsening)
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
@@ -424,9 +431,10 @@ def main():
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": DTYPES[best],
            "data": "synthetic", "dof_per_s": res["dof_per_s"],
-           "config": {"workload": wl_desc, "P": a.P, "levels": [l["order"] for l in ctx.levels],
+           "config": {"workload": wl_desc, "P": a.P, "levels": [[l["order"], l["order_z"]] for l in ctx.levels],
                       "n_dof": info0["n_dof"], "n_elem": info0["n_elem"], "rtol": a.rtol,
                       "smoother": f"{a.smoother} {nu}+{nu}" + (f" on [lambda/{a.smooth_ratio:g}, lambda]" if a.smoother == "chebyshev" else ""),
+                      "coarsening": a.coarsening,
                       "coarse": cinfo,
                       "guess": "zero", "precision": best, "krylov": res["krylov"]},
            "paths": paths, "roofline": roof}
@@ -434,7 +442,8 @@ def main():
         out["speedup_vs_fp64"] = res["solves_per_s"] / paths["fp64"]["solves_per_s"]
     if not a.no_cpu:
         p64 = paths.get("fp64", res)
-        out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"])
+        out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"],
+                                           coarsening=a.coarsening)
     print(json.dumps(out), flush=True)
 
 
