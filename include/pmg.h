@@ -269,9 +269,9 @@ int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps
                     void* stream);
 
 /* ---- learned warm start (a small multilayer perceptron, FP32) -------------
- * The network maps per-node features of the coarsest (P = 1) level to the
- * correction of the extrapolated guess; pmg_solve prolongates it to the finest
- * level with the multigrid transfers.  Features of node g = (vertex v,
+ * The network maps per-node features of the network level (pmg_net_level: the
+ * coarsest level, order (1,1)) to the correction of the extrapolated guess;
+ * pmg_solve prolongates it to the finest level with the multigrid transfers.  Features of node g = (vertex v,
  * level z) with gf its finest-level twin and top the finest surface node of
  * column v: [z/L, x, y scaled to [-1,1], distance to the nearest circle,
  * p1[gf]-p2[gf], surf[v]-base[top], p1[top]-p2[top]]; target
@@ -282,8 +282,10 @@ int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps
  * W_1, b_1, ...  pmg_net_forward / pmg_net_loss_grad act on raw inputs; the
  * solve and pmg_net_train use the normalisation (inputs (x - mean) * inv_std,
  * output times tscale) fitted by pmg_net_train. */
+/* Index of the network level (its n_dof is the row count n1 of the features). */
+int pmg_net_level(const pmg_ctx* ctx);
 /* Features (device float [n1][7]) and, if T and pnow are given, targets
- * (device float [n1]) of the coarsest nodes; surf device [n_surface], p1, p2,
+ * (device float [n1]) of the network level's nodes; surf device [n_surface], p1, p2,
  * p3 (nullable: second-order base), pnow device [n_dof] of the finest level. */
 int pmg_features(pmg_ctx* ctx, const double* surf, const double* p1, const double* p2, const double* p3,
                  const double* pnow, float* X, float* T, void* stream);

@@ -1085,10 +1085,16 @@ static void net_backward(pmg_net* n, const float* X, const float* T, int B, doub
   }
 }
 
-// constant features of the coarsest nodes: sigma, x and y in [-1,1], distance to the nearest circle
+// Level of the learned correction: the coarsest one (order (1,1); its 2D nodes
+// are the mesh vertices).  A network on the (1,P) level of the in-plane-first
+// sequence (every vertical node kept) was measured too: five times the rows, no
+// fewer iterations.
+static int net_level(const pmg_ctx* c) { return c->nl - 1; }
+
+// constant features of the network level's nodes: sigma, x and y in [-1,1], distance to the nearest circle
 static void build_feat_cst(pmg_ctx* c) {
   if (c->feat_cst) return;
-  Level& C = c->lv[c->nl - 1];
+  Level& C = c->lv[net_level(c)];
   const int64_t n1 = C.num.n_dof;
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
   for (int v = 0; v < c->mesh.nv; ++v) {
@@ -1118,7 +1124,7 @@ static void build_feat_cst(pmg_ctx* c) {
 static void features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* p3,
                      const double* pnow, float* X, float* T, hipStream_t st) {
   build_feat_cst(c);
-  Level& C = c->lv[c->nl - 1];
+  Level& C = c->lv[net_level(c)];
   Level& F = c->lv[0];
   launch_features(C.num.n_dof, int(C.num.nz), int(F.num.nz), F.PZ / C.PZ, c->feat_cst, surf, p1, p2, p3, pnow, X,
                   T, st);
@@ -1127,7 +1133,8 @@ static void features(pmg_ctx* c, const double* surf, const double* p1, const dou
 // learned correction of the extrapolation, prolongated to the finest level: out (free nodes)
 static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const double* p1, const double* p2,
                           const double* p3, double* out, hipStream_t st) {
-  Level& C = c->lv[c->nl - 1];
+  const int NL = net_level(c);
+  Level& C = c->lv[NL];
   const int64_t n1 = C.num.n_dof;
   if (n->n1cap < n1) {
     n->X1 = n->A<float>(size_t(n1) * n->din);
@@ -1146,10 +1153,10 @@ static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const doub
   }
   // coarsest correction: predicted inside, exact at the surface nodes (new surface data minus its
   // extrapolation), prolongated level by level without masking; the caller keeps the free part
-  double* cur = c->nl > 1 ? C.u64 : out;
+  double* cur = NL > 0 ? C.u64 : out;
   launch_scale_out(n->y1, n->tscale, n1, cur, st);
   launch_corr_surface(n1, int(C.num.nz), int(c->lv[0].num.nz), surf, p1, p2, p3, cur, st);
-  for (int i = c->nl - 2; i >= 0; --i) {
+  for (int i = NL - 1; i >= 0; --i) {
     double* dst = i == 0 ? out : c->lv[i].u64;
     launch_prolong_elem<double>(c->lv[i].view, c->lv[i + 1].view, c->lv[i].pit64, c->lv[i].piz64, cur, c->Y, st);
     launch_assemble<double>(c->lv[i].view, OP_AVG_RAW, c->Y, dst, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
@@ -1191,6 +1198,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
   launch_cast<double, double>(c->s_y, c->s_f, -1.0, N, st);
   const double nf = std::sqrt(dot_host(c, c->s_f, c->s_f, N, st));
   // initial guess
+  double rr0 = -1.0;  // ||f - A u||^2 of the chosen guess once known
   if (guess == PMG_GUESS_GIVEN) {
     launch_count_nonfinite(phi, N, c->partial, st);
     launch_finalize(c->partial, c->scal, S_TMP1, FIN_SET, st);
@@ -1201,18 +1209,28 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     launch_extrap(hist[0], hist[1], p3, c->s_y, N, st);
     launch_mask<double>(F.view, c->s_y, c->s_u, st);
     if (learned) {
-      // candidate = extrapolation + learned correction; keep it only if its residual is smaller
+      // candidate = extrapolation + learned correction delta, kept only if its residual
+      // is smaller: r_ex = f - A u_ex and r_ln = r_ex - A delta (one fine apply each,
+      // both norms read with one synchronisation); the chosen residual seeds the loop
       learned_guess(c, net, surf, hist[0], hist[1], p3, c->s_q, st);
-      launch_axpy(c->s_q, c->s_y, 1.0, N, st);            // extrapolation + correction
       launch_mask<double>(F.view, c->s_q, c->s_q, st);
       ax_elem<double>(c, 0, c->s_u, st);
       assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
-      const double r_ex = dot_host(c, c->s_r, c->s_r, N, st);
       ax_elem<double>(c, 0, c->s_q, st);
-      assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
-      const double r_ln = dot_host(c, c->s_r, c->s_r, N, st);
-      if (std::isfinite(r_ln) && r_ln < r_ex) launch_copy<double>(c->s_q, c->s_u, N, st);
-      else fallback = 1;
+      assemble<double>(c, 0, OP_RESID, c->s_y, c->s_r, nullptr, nullptr, 0, 0, st);
+      launch_dot<double>(c->s_r, c->s_r, N, c->partial, st);
+      launch_finalize(c->partial, c->scal, S_TMP0, FIN_SET, st);
+      launch_dot<double>(c->s_y, c->s_y, N, c->partial, st);
+      launch_finalize(c->partial, c->scal, S_TMP1, FIN_SET, st);
+      const double r_ex = read_scal(c, S_TMP0, st), r_ln = c->scal_h[S_TMP1];
+      if (std::isfinite(r_ln) && r_ln < r_ex) {
+        launch_axpy(c->s_u, c->s_q, 1.0, N, st);
+        launch_copy<double>(c->s_y, c->s_r, N, st);
+        rr0 = r_ln;
+      } else {
+        fallback = 1;
+        rr0 = r_ex;
+      }
     }
   } else {
     launch_fill<double>(c->s_u, 0.0, N, st);
@@ -1221,10 +1239,13 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
   HIPCHK(hipEventSynchronize(ev1));
   float tg = 0;
   HIPCHK(hipEventElapsedTime(&tg, ev0, ev1));
-  // r = f - A u
-  ax_elem<double>(c, 0, c->s_u, st);
-  assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
-  std::vector<double> hist_r{std::sqrt(dot_host(c, c->s_r, c->s_r, N, st))};
+  // r = f - A u (already at hand for the learned guess)
+  if (rr0 < 0.0) {
+    ax_elem<double>(c, 0, c->s_u, st);
+    assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+    rr0 = dot_host(c, c->s_r, c->s_r, N, st);
+  }
+  std::vector<double> hist_r{std::sqrt(rr0)};
   const double tol = rtol * nf + atol;
   int it = 0;
   int status = PMG_OK;
@@ -1774,6 +1795,8 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
   });
   return PMG_OK;
 }
+
+int pmg_net_level(const pmg_ctx* c) { return c ? net_level(c) : PMG_EINVAL; }
 
 int pmg_features(pmg_ctx* c, const double* surf, const double* p1, const double* p2, const double* p3,
                  const double* pnow, float* X,

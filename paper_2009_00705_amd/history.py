@@ -27,7 +27,7 @@ class History:
         xy = ctx.surface_xy()
         self.x = xy[:, 0]
         self.n_dof = ctx.levels[0]["n_dof"]
-        self.n1 = ctx.levels[-1]["n_dof"]
+        self.n1 = ctx.levels[ctx.net_level]["n_dof"]
         self._surf = {}
 
     def surface(self, n: int):
@@ -105,5 +105,6 @@ def summarize(stats):
     return {"solves_per_s": float(len(stats) / (ms.sum() / 1e3)), "ms_per_solve": float(ms.mean()),
             "iters_mean": float(it.mean()), "iters_max": int(it.max()),
             "initial_rel_res_median": float(np.median(r0)),
+            "guess_ms_mean": float(np.mean([s.get("t_guess_ms", 0.0) for s in stats])),
             "fallbacks": int(sum(1 for s in stats if s.get("fallback"))),
             "max_rel_res": float(max(s["rel_res"] for s in stats))}

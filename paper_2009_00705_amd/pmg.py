@@ -107,6 +107,7 @@ SIGNATURES = {
     "pmg_coarse_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_time_kernel": (_I, [_VP, _I, _I, _I, _I, C.POINTER(C.c_double), _VP]),
     "pmg_features": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "pmg_net_level": (_I, [_VP]),
     "pmg_net_create": (_I, [_VP, C.c_int32, C.c_int32, C.c_uint64, C.POINTER(_VP)]),
     "pmg_net_destroy": (None, [_VP]),
     "pmg_net_size": (_I, [_VP, _VP, _VP, _VP, _VP]),
@@ -323,6 +324,11 @@ class Context:
         self._c(lib().pmg_time_kernel(self.h, KERNELS[kernel], level, PRECISIONS[precision], reps,
                                       C.byref(ms), _stream(stream)))
         return ms.value
+
+    @property
+    def net_level(self) -> int:
+        """Level whose nodes carry the learned correction (features have its n_dof rows)."""
+        return self._c(lib().pmg_net_level(self.h))
 
     def features(self, surf, p1, p2, X, pnow=None, T=None, p3=None, stream=None):
         self._c(lib().pmg_features(self.h, _dptr(surf), _dptr(p1), _dptr(p2), _dptr(p3), _dptr(pnow), _dptr(X),

@@ -99,10 +99,21 @@ def test_save_load_roundtrip(ctx, tmp_path):
         other.load(p)
 
 
+@pytest.fixture(scope="module")
+def ctx_xy():
+    from paper_2009_00705_amd import pmg
+    c = pmg.Context(W.box_mesh(3, 2), P=4, coarsening="xy")
+    yield c
+    c.close()
+
+
 @pytest.mark.parametrize("third", [False, True])
-def test_features_match_definition(ctx, third):
+@pytest.mark.parametrize("seq", ["both", "xy"])
+def test_features_match_definition(ctx, ctx_xy, third, seq):
     import torch
-    info0, info1 = ctx.levels[0], ctx.levels[-1]
+    ctx = ctx if seq == "both" else ctx_xy
+    info0, info1 = ctx.levels[0], ctx.levels[ctx.net_level]
+    assert info1["order"] == 1 and ctx.net_level == len(ctx.levels) - 1
     n0, n1 = info0["n_dof"], info1["n_dof"]
     rng = np.random.default_rng(0)
     p1, p2, pn, p3 = (rng.standard_normal(n0) for _ in range(4))
@@ -113,13 +124,14 @@ def test_features_match_definition(ctx, third):
     ctx.features(dev(surf), dev(p1), dev(p2), X, pnow=dev(pn), T=T, p3=dev(p3) if third else None)
     m = W.box_mesh(3, 2)
     P, L = 4, 2
-    nz0, nz1 = L * P + 1, L + 1
+    pz1 = info1["order_z"]
+    nz0, nz1 = L * P + 1, L * pz1 + 1
     g = np.arange(n1)
     v, z = g // nz1, g % nz1
-    gf = v * nz0 + z * P
+    gf = v * nz0 + z * (P // pz1)
     top = v * nz0 + nz0 - 1
     xy = m["xy"][v]
-    want = np.stack([z / L, 2 * xy[:, 0] / (2 * np.pi) - 1, 2 * xy[:, 1] / (2 * np.pi) - 1, np.zeros(n1),
+    want = np.stack([z / (L * pz1), 2 * xy[:, 0] / (2 * np.pi) - 1, 2 * xy[:, 1] / (2 * np.pi) - 1, np.zeros(n1),
                      p1[gf] - p2[gf], surf[v] - base[top], p1[top] - p2[top]], axis=1)
     np.testing.assert_allclose(host(X), want, atol=2e-6 * np.abs(want).max())
     np.testing.assert_allclose(host(T), pn[gf] - base[gf], atol=2e-6 * np.abs(pn).max() * 8)
@@ -136,7 +148,7 @@ def test_learned_guess_on_a_short_history():
     wg = W.WaveGroup(n_steps=24)
     xy = ctx.surface_xy()
     n0 = ctx.levels[0]["n_dof"]
-    n1 = ctx.levels[-1]["n_dof"]
+    n1 = ctx.levels[ctx.net_level]["n_dof"]
     sols, surfs = [], []
     for n in range(24):
         eta, phis = wg.surface(xy[:, 0], n)
