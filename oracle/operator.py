@@ -19,24 +19,24 @@ from .mesh import Numbering, node_xy_2d
 from .refelem import order_pair, ref
 
 
-def element_node_xyz(mesh: dict, num_f: Numbering, eta2d: np.ndarray) -> np.ndarray:
-    """Nodal xyz of every prism at the fine order, shape (E, Np, 3)."""
+def element_node_xyz(mesh: dict, num_f: Numbering, eta2d: np.ndarray, elements=None) -> np.ndarray:
+    """Nodal xyz of every prism (or of the listed prisms, in that order) at the
+    fine order, shape (E, Np, 3)."""
     P, L = num_f.P, num_f.L
     re = ref(P)
     h = float(mesh["depth"])
     X2 = node_xy_2d(mesh, num_f)                            # (nt, Np_tri, 2)
     eta_t = np.asarray(eta2d, dtype=np.float64)[num_f.map2d]  # (nt, Np_tri)
-    E = num_f.n_elem
-    out = np.empty((E, re.np, 3))
-    for t in range(num_f.nt):
-        for layer in range(L):
-            e = t * L + layer
-            for c in range(P + 1):
-                sig = (layer + (1 + re.t[c]) / 2) / L
-                sl = slice(c * re.np_tri, (c + 1) * re.np_tri)
-                out[e, sl, 0] = X2[t, :, 0]
-                out[e, sl, 1] = X2[t, :, 1]
-                out[e, sl, 2] = -h + sig * (eta_t[t] + h)
+    els = np.arange(num_f.n_elem) if elements is None else np.asarray(elements)
+    out = np.empty((els.size, re.np, 3))
+    for i, e in enumerate(els):
+        t, layer = divmod(int(e), L)
+        for c in range(P + 1):
+            sig = (layer + (1 + re.t[c]) / 2) / L
+            sl = slice(c * re.np_tri, (c + 1) * re.np_tri)
+            out[i, sl, 0] = X2[t, :, 0]
+            out[i, sl, 1] = X2[t, :, 1]
+            out[i, sl, 2] = -h + sig * (eta_t[t] + h)
     return out
 
 
