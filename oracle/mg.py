@@ -11,7 +11,9 @@
 * Smoother (eq. sec_form): damped Jacobi, S^-1 = omega D^-1, or a
   Chebyshev-accelerated Jacobi polynomial of the same degree as the sweep
   count on [lambda/ratio, lambda] with lambda = 4/(3 omega) (the power
-  estimate of lambda_max(D^-1 A)); both are linear and symmetric.
+  estimate of lambda_max(D^-1 A)); both are linear and symmetric.  Or the
+  overlapping additive Schwarz smoother of eq. Mass (``oracle.schwarz``),
+  damped by omega (default 1), its transpose in post-smoothing.
 * Coarsest level (P = 1): exact solve (dense Cholesky or sparse LU), or a
   fixed-degree Jacobi-preconditioned Chebyshev iteration on a given interval.
 * V-cycle: Alg. 1 with zero initial guess below the top.
@@ -26,6 +28,7 @@ import scipy.sparse.linalg as spla
 from .mesh import Numbering, lateral_dirichlet_2d
 from .operator import LevelGeometry, StiffnessOperator, element_node_xyz
 from .refelem import order_pair, ref, vandermonde_1d, vandermonde_tri
+from .schwarz import Schwarz, overlap_of
 
 
 def level_orders(P: int, coarsening: str = "both"):
@@ -101,7 +104,8 @@ class Hierarchy:
     def __init__(self, mesh: dict, P: int, eta2d=None, nu1=2, nu2=2, omega=None,
                  dirichlet_tags: int = 0, top_neumann: bool = False,
                  coarse: str = "exact", cheb=None, seed: int = 0,
-                 smoother: str = "jacobi", smooth_ratio: float = 15.0, coarsening: str = "both"):
+                 smoother: str = "jacobi", smooth_ratio: float = 15.0, coarsening: str = "both",
+                 overlap: int = 1):
         self.mesh = mesh
         self.P = P
         self.orders = level_orders(P, coarsening)
@@ -118,17 +122,23 @@ class Hierarchy:
         self.nu1, self.nu2 = nu1, nu2
         self.Pi = [element_prolongation(self.orders[i], self.orders[i + 1])
                    for i in range(len(self.orders) - 1)]
-        # smoothing weights
+        if smoother not in ("jacobi", "chebyshev", "schwarz"):
+            raise ValueError(smoother)
+        # smoothing weights (Schwarz: a damping factor, 1 unless given)
         for i, lv in enumerate(self.levels[:-1]):
-            if omega is None:
+            if omega is None and smoother == "schwarz":
+                lv.omega = 1.0
+            elif omega is None:
                 lv.omega = 4.0 / (3.0 * self.lambda_max(i, seed=seed))
             elif np.isscalar(omega):
                 lv.omega = float(omega)
             else:
                 lv.omega = float(omega[i])
-        if smoother not in ("jacobi", "chebyshev"):
-            raise ValueError(smoother)
         self.smoother = smoother
+        self.overlap = int(overlap)
+        if smoother == "schwarz":
+            for lv in self.levels[:-1]:
+                lv.schwarz = Schwarz(lv, *overlap_of(order_pair(lv.P), overlap))
         self.smooth_ratio = float(smooth_ratio)
         self.coarse_mode = coarse
         self.cheb = cheb
@@ -191,8 +201,12 @@ class Hierarchy:
         return np.where(lc.free, rc, 0.0)
 
     # -- Alg. 1
-    def smooth(self, i: int, u: np.ndarray, f: np.ndarray, sweeps: int) -> np.ndarray:
+    def smooth(self, i: int, u: np.ndarray, f: np.ndarray, sweeps: int, post: bool = False) -> np.ndarray:
         lv = self.levels[i]
+        if self.smoother == "schwarz":
+            for _ in range(sweeps):
+                u = u + lv.omega * lv.schwarz.apply(f - lv.A(u), transpose=post)
+            return u
         if self.smoother == "chebyshev":
             if sweeps <= 0:
                 return u
@@ -212,7 +226,7 @@ class Hierarchy:
         rc = self.restrict(i, r)
         uc = self.vcycle(rc, i + 1)
         u = u + self.prolong(i, uc)
-        u = self.smooth(i, u, f, self.nu2)
+        u = self.smooth(i, u, f, self.nu2, post=True)
         return u
 
 
