@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PMG_ABI_VERSION 1
+#define PMG_ABI_VERSION 2
 
 enum pmg_status {
   PMG_OK = 0,
@@ -80,9 +80,18 @@ enum pmg_guess { PMG_GUESS_GIVEN = 0, PMG_GUESS_ZERO = 1, PMG_GUESS_LEARNED = 2,
 enum pmg_coarse { PMG_COARSE_EXACT = 0, PMG_COARSE_CHEBYSHEV = 1 };
 
 /* Smoother of eq. sec_form on every non-coarsest level: damped Jacobi
- * (S^-1 = omega D^-1, nu sweeps) or Chebyshev-accelerated Jacobi (a degree-nu
- * polynomial in D^-1 A, linear and symmetric, so Alg. 3 applies unchanged). */
-enum pmg_smoother { PMG_SMOOTH_JACOBI = 0, PMG_SMOOTH_CHEBYSHEV = 1 };
+ * (S^-1 = omega D^-1, nu sweeps), Chebyshev-accelerated Jacobi (a degree-nu
+ * polynomial in D^-1 A, linear and symmetric, so Alg. 3 applies unchanged), or
+ * the overlapping additive Schwarz preconditioner of Sec. 5.2 (eq. Mass,
+ * eq. weights): S^-1 = W sum_k R_k^T (R_k A R_k^T)^-1 R_k with one subdomain
+ * per prism (the prism's nodes plus the overlap of pmg_options.overlap in the
+ * prisms that touch it, Dirichlet nodes left out) and W the inverse count of
+ * subdomains holding each node; nu sweeps damped by omega (default 1).  Pre-
+ * smoothing uses S^-1, post-smoothing its transpose sum_k R_k^T A_k^-1 R_k W,
+ * so the V-cycle stays symmetric.  The local inverses are dense (FP64, with
+ * FP32 and BF16 copies for the mixed V-cycles) and are rebuilt by every
+ * pmg_set_surface. */
+enum pmg_smoother { PMG_SMOOTH_JACOBI = 0, PMG_SMOOTH_CHEBYSHEV = 1, PMG_SMOOTH_SCHWARZ = 2 };
 
 typedef struct pmg_ctx pmg_ctx;
 typedef struct pmg_net pmg_net;
@@ -127,6 +136,13 @@ typedef struct pmg_options {
   double smooth_ratio;    /* Chebyshev smoother interval [lambda/ratio, lambda],
                              lambda = 4/(3 omega) of the level                   */
   int32_t coarsening;     /* pmg_coarsening: order sequence of the levels        */
+  int32_t overlap;        /* Schwarz overlap: a node of a touching prism joins
+                             subdomain k when it lies within `overlap` lattice
+                             steps in the triangle and along the extrusion of the
+                             entity the two prisms share (0: block Jacobi, 1: one
+                             overlapping node in each direction, Sec. 5.2); -1:
+                             the refined variant of Sec. 6.3, ceil((P_l+1)/2) in
+                             the triangle and ceil((PZ_l+1)/2) vertically      */
 } pmg_options;
 
 /* Order sequence of the levels.  BOTH: P, floor(P/2), ..., 1 in every direction
@@ -252,19 +268,42 @@ int pmg_solve(pmg_ctx* ctx, const double* phi_surf, const double* phi_bc, double
               const pmg_net* net, const double* const* hist_phi, double rtol, double atol, int32_t imax,
               pmg_stats* stats, void* stream);
 
+/* Subdomains of the Schwarz smoother on a non-coarsest level (available in
+ * host-only contexts too).  dt, dz: overlap in lattice steps in the triangle
+ * and along the extrusion; n_sub: subdomains (one per prism); max_size:
+ * largest subdomain; total: sum of the subdomain sizes; inv_entries: entries
+ * of the padded local inverses (each size rounded up to a multiple of 4).
+ * EINVAL when the smoother is not PMG_SMOOTH_SCHWARZ or the level is the
+ * coarsest. */
+typedef struct pmg_schwarz_info {
+  int32_t dt, dz;
+  int64_t n_sub;
+  int32_t max_size;
+  int64_t total;
+  int64_t inv_entries;
+} pmg_schwarz_info;
+int pmg_schwarz_info_get(const pmg_ctx* ctx, int level, pmg_schwarz_info* info);
+/* Free global nodes of every subdomain, ascending (host buffers: ptr
+ * [n_sub+1], nodes [total]; subdomain k is nodes[ptr[k] .. ptr[k+1])).
+ * Bit-exact contract. */
+int pmg_schwarz_nodes(const pmg_ctx* ctx, int level, int32_t* ptr, int32_t* nodes);
+
 /* Change the preconditioner precision and the outer iteration of later solves
  * (pmg_precision, pmg_krylov).  The hierarchy is kept. */
 int pmg_set_solver(pmg_ctx* ctx, int precision, int krylov);
 
 /* Kernels that pmg_time_kernel() can time in isolation. */
 enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, PMG_K_RESTRICT = 3,
-                  PMG_K_PROLONG = 4, PMG_K_COPY = 5 };
+                  PMG_K_PROLONG = 4, PMG_K_COPY = 5, PMG_K_SCHWARZ = 6 };
 /* Average duration (ms) of `reps` back-to-back launches of one kernel of
  * level `level` on `stream`, bracketed by hipEvents on that stream (for
  * roofline measurement).  The element operator reads the level's work vector;
  * results are discarded.  PMG_K_COPY is a plain device copy of the level's
  * FP64 vector (n_dof * 8 bytes read and written): the reference point that
- * scales hardware byte counters. */
+ * scales hardware byte counters.  PMG_K_SCHWARZ is the batched local solve of
+ * the Schwarz smoother (inverse storage: FP64 for PMG_FP64, FP32 for
+ * PMG_MIXED_FP32, BF16 for the BF16 precisions); EINVAL when the smoother is
+ * not PMG_SMOOTH_SCHWARZ or the level is the coarsest. */
 int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps, double* ms_per_launch,
                     void* stream);
 

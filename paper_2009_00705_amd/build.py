@@ -21,7 +21,8 @@ LIB = os.path.join(HERE, "libpmg.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PMG_ARCH", "gfx950")
 
-SOURCES = ["refelem.cpp", "mesh.cpp", "pmg.cpp", "kernels.hip", "kernels_mfma.hip", "mlp.hip"]
+SOURCES = ["refelem.cpp", "mesh.cpp", "schwarz_plan.cpp", "pmg.cpp", "kernels.hip", "kernels_mfma.hip", "mlp.hip",
+           "schwarz.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

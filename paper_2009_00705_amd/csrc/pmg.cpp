@@ -26,6 +26,7 @@
 #include "mesh.hpp"
 #include "pmg.h"
 #include "refelem.hpp"
+#include "schwarz.hpp"
 
 namespace pmg {
 
@@ -98,6 +99,18 @@ struct Level {
   void* tab4[3] = {nullptr, nullptr, nullptr};
   VertMats<double> vm64{};
   VertMats<float> vm32{};
+  // overlapping Schwarz smoother: host plan, device view, local inverses
+  // (FP64 and the FP32 / BF16 copies), weights, subdomain vectors
+  bool has_sz = false;
+  SchwarzPlan sz;
+  SchwarzView szv{};
+  double* sz_inv64 = nullptr;
+  float* sz_inv32 = nullptr;
+  bf16_t* sz_inv16 = nullptr;
+  double *sz_w64 = nullptr, *sz_z64 = nullptr;
+  float *sz_w32 = nullptr, *sz_z32 = nullptr;
+  template <typename T> T* szw();
+  template <typename T> T* szz();
 
   template <typename T> T* f();
   template <typename T> T* u();
@@ -124,6 +137,10 @@ template <> double* Level::pit<double>() { return pit64; }
 template <> float* Level::pit<float>() { return pit32; }
 template <> double* Level::piz<double>() { return piz64; }
 template <> float* Level::piz<float>() { return piz32; }
+template <> double* Level::szw<double>() { return sz_w64; }
+template <> float* Level::szw<float>() { return sz_w32; }
+template <> double* Level::szz<double>() { return sz_z64; }
+template <> float* Level::szz<float>() { return sz_z32; }
 
 }  // namespace pmg
 
@@ -272,6 +289,23 @@ static void build_levels(pmg_ctx* c) {
     L.n_free = L.num.n_dof - nd;
     L.omega_user = (i < 8) ? o.omega[i] : 0.0;
   }
+  if (o.smoother == PMG_SMOOTH_SCHWARZ) {
+    const int nth = int(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+    for (int i = 0; i + 1 < c->nl; ++i) {
+      Level& L = c->lv[i];
+      const int dt = o.overlap < 0 ? (L.P + 2) / 2 : o.overlap;
+      const int dz = o.overlap < 0 ? (L.PZ + 2) / 2 : o.overlap;
+      try {
+        build_schwarz(c->mesh, L.num, L.dir2d_h, L.top_dir, dt, dz, nth, L.sz);
+      } catch (const std::runtime_error& e) {
+        throw Error(PMG_EINVAL, e.what());
+      }
+      int mmax = 0;
+      for (int32_t m : L.sz.msz) mmax = std::max(mmax, m);
+      if (mmax > 8192) throw Error(PMG_EINVAL, "Schwarz subdomain larger than 8192 nodes");
+      L.has_sz = true;
+    }
+  }
   const RefElem& rf = *c->lv[0].re;
   c->xyt_h = triangle_node_xy(c->mesh, rf, c->lv[0].num);
   // check straight/curved triangles are not inverted (flat surface)
@@ -407,6 +441,32 @@ static void upload_levels(pmg_ctx* c) {
     }
     maxE = std::max(maxE, E * re.np);
     if (c->opt.kernel_variant == 0) upload_mfma(c, L);
+    if (L.has_sz) {
+      const SchwarzPlan& P = L.sz;
+      SchwarzView& v = L.szv;
+      v.n_sub = P.n_sub;
+      v.max_n = P.max_n;
+      v.max_m = 0;
+      for (int32_t m : P.msz) v.max_m = std::max(v.max_m, int(m));
+      v.sd_ptr = c->U(P.sd_ptr);
+      v.sd_node = c->U(P.sd_node);
+      v.msz = c->U(P.msz);
+      v.inv_off = c->U(P.inv_off);
+      v.blk_ptr = c->U(P.blk_ptr);
+      v.blk_elem = c->U(P.blk_elem);
+      v.blk_ent = c->U(P.blk_ent);
+      v.ent = c->U(P.ent);
+      v.node_ptr = c->U(P.node_ptr);
+      v.node_pos = c->U(P.node_pos);
+      L.sz_w64 = c->U(P.w);
+      L.sz_w32 = c->U(to_f32(P.w));
+      const size_t ninv = size_t(P.inv_off.back());
+      L.sz_inv64 = c->A<double>(ninv);
+      L.sz_inv32 = c->A<float>(ninv);
+      L.sz_inv16 = c->A<bf16_t>(ninv);
+      L.sz_z64 = c->A<double>(size_t(std::max<int64_t>(1, P.total)));
+      L.sz_z32 = c->A<float>(size_t(std::max<int64_t>(1, P.total)));
+    }
     L.view = LevelView{L.P, L.PZ, L.num.L, L.num.nt, re.np_tri, re.np, re.nq, L.num.n2d, L.num.nz, N, E,
                        L.map2d, L.inc_ptr, L.inc, L.dir2d, L.top_dir};
     if (i + 1 < c->nl) {
@@ -521,6 +581,35 @@ static void cheb_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess, in
     ax_elem<T>(c, i, d, st);
     assemble<T>(c, i, OP_CHEB, u, r, L.dinv<T>(), d, rho_new * rho, 2.0 * rho_new / delta, st);
     rho = rho_new;
+  }
+}
+
+// k sweeps of the Schwarz smoother u <- u + omega S^-1 (f - A u), from u = 0
+// when zero_guess; post: the transpose sum_k R_k^T A_k^-1 R_k W.
+template <typename T>
+static void schwarz_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess, bool post, int k, hipStream_t st) {
+  Level& L = c->lv[i];
+  T* r = L.r<T>();
+  T* z = L.szz<T>();
+  const T* w = L.szw<T>();
+  for (int s = 0; s < k; ++s) {
+    const bool first = zero_guess && s == 0;
+    const T* x = f;
+    if (!first) {
+      ax_elem<T>(c, i, u, st);
+      assemble<T>(c, i, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
+      x = r;
+    }
+    if (sizeof(T) == 8)
+      launch_sd_apply<double, double>(L.szv, L.sz_inv64, (const double*)x, (const double*)(post ? w : nullptr),
+                                      (double*)z, st);
+    else if (c->lowp == G_BF16)
+      launch_sd_apply<float, bf16_t>(L.szv, L.sz_inv16, (const float*)x, (const float*)(post ? w : nullptr),
+                                     (float*)z, st);
+    else
+      launch_sd_apply<float, float>(L.szv, L.sz_inv32, (const float*)x, (const float*)(post ? w : nullptr),
+                                    (float*)z, st);
+    launch_sd_sum<T>(L.szv, L.num.n_dof, z, post ? nullptr : w, T(L.omega), !first, u, st);
   }
 }
 
@@ -888,6 +977,31 @@ static void coarse_exact_setup(pmg_ctx* c, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
+// Schwarz smoother: local matrices R_k A R_k^T from the element matrices of the
+// current geometry, inverted in place (FP64), with FP32 / BF16 copies.  The
+// element matrices live in a scratch buffer freed afterwards.
+// ---------------------------------------------------------------------------
+static void schwarz_setup(pmg_ctx* c, hipStream_t st) {
+  for (int i = 0; i + 1 < c->nl; ++i) {
+    Level& L = c->lv[i];
+    if (!L.has_sz) continue;
+    const size_t nK = size_t(L.num.n_elem) * L.re->np * L.re->np;
+    double* K = nullptr;
+    if (hipMalloc((void**)&K, nK * sizeof(double)) != hipSuccess)
+      throw Error(PMG_ENOMEM, "no device memory for the Schwarz element matrices");
+    HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), st));
+    launch_elem_mats(L.view, L.mats64, L.G64, K, st);
+    launch_sd_assemble(L.szv, L.re->np, K, L.sz_inv64, st);
+    launch_sd_invert(L.szv, L.sz_inv64, L.sz_inv32, L.sz_inv16, c->bad, st);
+    int bad = 0;
+    HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    HIPCHK(hipFree(K));
+    if (bad) throw Error(PMG_EBREAKDOWN, "Schwarz local matrix with a non-positive pivot (singular subdomain?)");
+  }
+}
+
+// ---------------------------------------------------------------------------
 // surface / geometry
 // ---------------------------------------------------------------------------
 static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
@@ -931,8 +1045,10 @@ static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
   }
   for (int i = 0; i + 1 < c->nl; ++i) {
     Level& L = c->lv[i];
-    L.omega = L.omega_user > 0 ? L.omega_user : 4.0 / (3.0 * lambda_max(c, i, st));
+    if (c->opt.smoother == PMG_SMOOTH_SCHWARZ) L.omega = L.omega_user > 0 ? L.omega_user : 1.0;
+    else L.omega = L.omega_user > 0 ? L.omega_user : 4.0 / (3.0 * lambda_max(c, i, st));
   }
+  schwarz_setup(c, st);
   // coarse solver
   Level& C = c->lv[c->nl - 1];
   c->coarse_exact = c->opt.coarse == PMG_COARSE_EXACT;
@@ -987,7 +1103,10 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   Level& C = c->lv[i + 1];
   const int64_t N = L.num.n_dof;
   const bool cheb = c->opt.smoother == PMG_SMOOTH_CHEBYSHEV;
-  if (c->opt.nu1 >= 1 && cheb) {
+  const bool asm_ = c->opt.smoother == PMG_SMOOTH_SCHWARZ;
+  if (c->opt.nu1 >= 1 && asm_) {
+    schwarz_smooth<T>(c, i, f, u, true, false, c->opt.nu1, st);
+  } else if (c->opt.nu1 >= 1 && cheb) {
     cheb_smooth<T>(c, i, f, u, true, c->opt.nu1, st);
   } else if (c->opt.nu1 >= 1) {
     launch_scale_diag<T>(L.dinv<T>(), f, u, L.omega, N, st);
@@ -1003,7 +1122,9 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   vcycle<T>(c, i + 1, C.f<T>(), C.u<T>(), st);
   launch_prolong_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), C.u<T>(), reinterpret_cast<T*>(c->Y), st);
   assemble<T>(c, i, OP_AVG_ADD, u, nullptr, nullptr, nullptr, 0, 0, st);
-  if (cheb) {
+  if (asm_) {
+    schwarz_smooth<T>(c, i, f, u, false, true, c->opt.nu2, st);
+  } else if (cheb) {
     if (c->opt.nu2 >= 1) cheb_smooth<T>(c, i, f, u, false, c->opt.nu2, st);
   } else {
     for (int m = 0; m < c->opt.nu2; ++m) jacobi_sweep<T>(c, i, f, u, st);
@@ -1401,6 +1522,10 @@ static void check_level(const pmg_ctx* c, int level) {
 
 template <typename T>
 static void smooth_t(pmg_ctx* c, int level, int sweeps, const T* f, T* u, hipStream_t st) {
+  if (c->opt.smoother == PMG_SMOOTH_SCHWARZ) {
+    schwarz_smooth<T>(c, level, f, u, false, false, sweeps, st);
+    return;
+  }
   if (c->opt.smoother == PMG_SMOOTH_CHEBYSHEV) {
     if (sweeps >= 1) cheb_smooth<T>(c, level, f, u, false, sweeps, st);
     return;
@@ -1437,6 +1562,7 @@ void pmg_options_default(pmg_options* o) {
   o->smoother = PMG_SMOOTH_JACOBI;
   o->smooth_ratio = 15.0;
   o->coarsening = PMG_COARSEN_BOTH;
+  o->overlap = 1;
   o->seed = 0;
 }
 
@@ -1455,7 +1581,8 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (o->nu1 < 0 || o->nu2 < 0) throw Error(PMG_EINVAL, "negative sweep count");
     if (o->precision < 0 || o->precision > 3) throw Error(PMG_EINVAL, "bad precision");
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
-    if (o->smoother < 0 || o->smoother > 1) throw Error(PMG_EINVAL, "bad smoother");
+    if (o->smoother < 0 || o->smoother > 2) throw Error(PMG_EINVAL, "bad smoother");
+    if (o->smoother == PMG_SMOOTH_SCHWARZ && o->overlap < -1) throw Error(PMG_EINVAL, "bad Schwarz overlap");
     if (o->coarsening < 0 || o->coarsening > 1) throw Error(PMG_EINVAL, "bad coarsening");
     if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
       throw Error(PMG_EINVAL, "smooth_ratio must exceed 1");
@@ -1684,6 +1811,34 @@ int pmg_vcycle(pmg_ctx* c, int precision, const void* r, void* z, void* stream) 
   return PMG_OK;
 }
 
+int pmg_schwarz_info_get(const pmg_ctx* c, int level, pmg_schwarz_info* info) {
+  if (!c || !info) return PMG_EINVAL;
+  PMG_TRY(const_cast<pmg_ctx*>(c), {
+    check_level(c, level);
+    const Level& L = c->lv[level];
+    if (!L.has_sz) throw Error(PMG_EINVAL, "no Schwarz smoother on this level");
+    info->dt = L.sz.dt;
+    info->dz = L.sz.dz;
+    info->n_sub = L.sz.n_sub;
+    info->max_size = L.sz.max_n;
+    info->total = L.sz.total;
+    info->inv_entries = L.sz.inv_off.back();
+  });
+  return PMG_OK;
+}
+
+int pmg_schwarz_nodes(const pmg_ctx* c, int level, int32_t* ptr, int32_t* nodes) {
+  if (!c || !ptr || !nodes) return PMG_EINVAL;
+  PMG_TRY(const_cast<pmg_ctx*>(c), {
+    check_level(c, level);
+    const Level& L = c->lv[level];
+    if (!L.has_sz) throw Error(PMG_EINVAL, "no Schwarz smoother on this level");
+    std::memcpy(ptr, L.sz.sd_ptr.data(), L.sz.sd_ptr.size() * sizeof(int32_t));
+    std::memcpy(nodes, L.sz.sd_node.data(), L.sz.sd_node.size() * sizeof(int32_t));
+  });
+  return PMG_OK;
+}
+
 int pmg_coarse_info(const pmg_ctx* c, int* mode, int* degree, double* lmin, double* lmax, int64_t* n_free) {
   if (!c) return PMG_EINVAL;
   if (mode) *mode = c->coarse_exact ? PMG_COARSE_EXACT : PMG_COARSE_CHEBYSHEV;
@@ -1749,6 +1904,7 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
     set_lowp(c, precision);
     if ((kernel == PMG_K_RESTRICT || kernel == PMG_K_PROLONG) && level + 1 >= c->nl)
       throw Error(PMG_EINVAL, "no coarser level");
+    if (kernel == PMG_K_SCHWARZ && !L.has_sz) throw Error(PMG_EINVAL, "no Schwarz smoother on this level");
     launch_fill<double>(L.r64, 1.0, L.num.n_dof, st);
     launch_fill<float>(L.r32, 1.0f, L.num.n_dof, st);
     auto one = [&]() {
@@ -1776,6 +1932,11 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
           break;
         }
         case PMG_K_COPY: launch_copy<double>(L.r64, c->s_y, L.num.n_dof, st); break;
+        case PMG_K_SCHWARZ:
+          if (f64) launch_sd_apply<double, double>(L.szv, L.sz_inv64, L.r64, nullptr, L.sz_z64, st);
+          else if (c->lowp == G_BF16) launch_sd_apply<float, bf16_t>(L.szv, L.sz_inv16, L.r32, nullptr, L.sz_z32, st);
+          else launch_sd_apply<float, float>(L.szv, L.sz_inv32, L.r32, nullptr, L.sz_z32, st);
+          break;
         default: throw Error(PMG_EINVAL, "unknown kernel");
       }
     };

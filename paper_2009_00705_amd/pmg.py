@@ -51,7 +51,12 @@ class Options(C.Structure):
                 ("cheb_lmin", C.c_double), ("cheb_lmax", C.c_double), ("cheb_ratio", C.c_double),
                 ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32),
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
-                ("coarsening", C.c_int32)]
+                ("coarsening", C.c_int32), ("overlap", C.c_int32)]
+
+
+class SchwarzInfo(C.Structure):
+    _fields_ = [("dt", C.c_int32), ("dz", C.c_int32), ("n_sub", C.c_int64), ("max_size", C.c_int32),
+                ("total", C.c_int64), ("inv_entries", C.c_int64)]
 
 
 class LevelInfo(C.Structure):
@@ -105,6 +110,8 @@ SIGNATURES = {
     "pmg_solve": (_I, [_VP, _VP, _VP, _VP, _I, _VP, _VP, _D, _D, C.c_int32, C.POINTER(Stats), _VP]),
     "pmg_set_solver": (_I, [_VP, _I, _I]),
     "pmg_coarse_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
+    "pmg_schwarz_info_get": (_I, [_VP, _I, C.POINTER(SchwarzInfo)]),
+    "pmg_schwarz_nodes": (_I, [_VP, _I, _VP, _VP]),
     "pmg_time_kernel": (_I, [_VP, _I, _I, _I, _I, C.POINTER(C.c_double), _VP]),
     "pmg_features": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_net_level": (_I, [_VP]),
@@ -120,7 +127,8 @@ SIGNATURES = {
     "pmg_net_save": (_I, [_VP, C.c_char_p]),
     "pmg_net_load": (_I, [_VP, C.c_char_p]),
 }
-KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4, "copy": 5}
+KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4, "copy": 5, "schwarz": 6}
+SMOOTHERS = {"jacobi": 0, "chebyshev": 1, "schwarz": 2}
 
 
 def lib():
@@ -181,7 +189,7 @@ def default_options(**kw) -> Options:
         elif k == "krylov" and isinstance(v, str):
             o.krylov = KRYLOV[v]
         elif k == "smoother" and isinstance(v, str):
-            o.smoother = {"jacobi": 0, "chebyshev": 1}[v]
+            o.smoother = SMOOTHERS[v]
         elif k == "coarse" and isinstance(v, str):
             o.coarse = {"exact": PMG_COARSE_EXACT, "chebyshev": PMG_COARSE_CHEBYSHEV}[v]
         elif k == "coarsening" and isinstance(v, str):
@@ -271,6 +279,20 @@ class Context:
         lo, hi = C.c_double(), C.c_double()
         self._c(lib().pmg_get_params(self.h, om.ctypes.data_as(C.c_void_p), C.byref(lo), C.byref(hi)))
         return om, lo.value, hi.value
+
+    def schwarz_info(self, level: int) -> dict:
+        si = SchwarzInfo()
+        self._c(lib().pmg_schwarz_info_get(self.h, level, C.byref(si)))
+        return {f: getattr(si, f) for f, _ in SchwarzInfo._fields_}
+
+    def schwarz_nodes(self, level: int):
+        """Free global nodes of every Schwarz subdomain of a level (list of arrays)."""
+        info = self.schwarz_info(level)
+        ptr = np.empty(info["n_sub"] + 1, dtype=np.int32)
+        nodes = np.empty(max(1, info["total"]), dtype=np.int32)
+        self._c(lib().pmg_schwarz_nodes(self.h, level, ptr.ctypes.data_as(C.c_void_p),
+                                        nodes.ctypes.data_as(C.c_void_p)))
+        return [nodes[ptr[k]:ptr[k + 1]] for k in range(info["n_sub"])]
 
     def coarse_info(self) -> dict:
         mode, deg = C.c_int(), C.c_int()

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
         assert n in pmg.SIGNATURES, f"binding lacks {n}"
-    assert L.pmg_abi_version() == 1
+    assert L.pmg_abi_version() == 2
 
 
 def _host_ctx(mesh, P, **kw):
@@ -87,6 +87,46 @@ def test_in_plane_first_levels_bit_exact(meshname, P):
         assert (info["order"], info["order_z"]) == (pt, pz)
         assert info["n_dof"] == num.n_dof and info["np"] == num.np and info["n_surface"] == num.n2d
         np.testing.assert_array_equal(ctx.gather_map(lvl), num.map.astype(np.int32))
+    ctx.close()
+
+
+@pytest.mark.parametrize("meshname", sorted(MESHES))
+@pytest.mark.parametrize("P,coarsening,overlap,tags,top_neumann", [
+    (3, "both", 1, 0, 0), (4, "xy", 1, 0b10, 0), (3, "both", 0, 0b10, 1), (4, "both", -1, 0, 0),
+    (3, "xy", 2, 0, 1), (2, "xy", -1, 0b110, 0)])
+def test_schwarz_subdomains_bit_exact(meshname, P, coarsening, overlap, tags, top_neumann):
+    """Subdomains of the Schwarz smoother (library: distance to the shared
+    entity of touching prisms; oracle: brute force over shared nodes) are the
+    same node lists on every non-coarsest level, and the query reports them."""
+    from oracle.mg import level_orders
+    from oracle.refelem import order_pair
+    from oracle.schwarz import overlap_of, subdomains
+    m = MESHES[meshname]()
+    ctx = _host_ctx(m, P, coarsening=coarsening, smoother="schwarz", overlap=overlap, dirichlet_tags=tags,
+                    top_neumann=top_neumann)
+    orders = level_orders(P, coarsening)
+    for lvl, p in enumerate(orders[:-1]):
+        pt, pz = order_pair(p)
+        num = M.Numbering(m, pt, pz)
+        free = np.ones(num.n_dof, dtype=bool)
+        if not top_neumann:
+            free[num.surface_nodes] = False
+        if tags:
+            for g2 in M.lateral_dirichlet_2d(m, num, tags):
+                free[g2 * num.nz:(g2 + 1) * num.nz] = False
+        dt, dz = overlap_of((pt, pz), overlap)
+        want = subdomains(num, free, dt, dz)
+        got = ctx.schwarz_nodes(lvl)
+        info = ctx.schwarz_info(lvl)
+        assert (info["dt"], info["dz"]) == (dt, dz) and info["n_sub"] == num.n_elem
+        assert info["max_size"] == max(w.size for w in want)
+        assert info["total"] == sum(w.size for w in want)
+        assert info["inv_entries"] == sum(((w.size + 3) // 4 * 4) ** 2 for w in want)
+        assert len(got) == len(want)
+        for e in range(num.n_elem):
+            np.testing.assert_array_equal(got[e], want[e].astype(np.int32), err_msg=f"level {lvl} element {e}")
+    with pytest.raises(Exception):
+        ctx.schwarz_info(len(orders) - 1)
     ctx.close()
 
 
