@@ -116,6 +116,24 @@ def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16
             "dof_per_s": n_dof_full / t_full}
 
 
+def schwarz_roofline(ctx, prec, level=0, reps=10):
+    """Roofline of the Schwarz local-solve kernel of a level: per subdomain of n
+    nodes it reads the n x n inverse (8, 4 or 2 bytes an entry), n node ids and
+    n gathered residual values, and writes n corrections."""
+    sizes = np.array([s.size for s in ctx.schwarz_nodes(level)], dtype=np.float64)
+    s_inv = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2}[prec]
+    s_v = 8 if prec == "fp64" else 4
+    byts = float(np.sum(sizes * sizes) * s_inv + np.sum(sizes) * (4 + 2 * s_v))
+    flops = float(2 * np.sum(sizes * sizes))
+    ms = ctx.time_kernel("schwarz", level, prec, reps=reps)
+    r = roofline(byts, flops, ms, prec)
+    info = ctx.schwarz_info(level)
+    r.update({"traffic": None, "kernel": f"Schwarz local solves (level {level}, overlap {info['dt']}), {prec} inverses",
+              "ms_per_launch": ms, "bytes_per_launch": byts, "flops_per_launch": flops,
+              "subdomains": info["n_sub"], "max_size": info["max_size"], "mean_size": float(sizes.mean())})
+    return r
+
+
 def bench_history(a):
     """Learned warm start on the focusing-wave history of the cylinder mesh (C5)."""
     import torch
@@ -306,8 +324,11 @@ def main():
     ap.add_argument("--precisions", default="fp64,fp32,bf16,bf16g")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--coarse-degree", type=int, default=0, help="Chebyshev coarse degree (0: automatic)")
-    ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "jacobi"])
-    ap.add_argument("--nu", type=int, default=0, help="smoothing degree/sweeps (0: 3 Chebyshev, 2 Jacobi)")
+    ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "jacobi", "schwarz"])
+    ap.add_argument("--nu", type=int, default=0,
+                    help="smoothing degree/sweeps (0: 3 Chebyshev, 2 Jacobi, 1 Schwarz)")
+    ap.add_argument("--overlap", type=int, default=1, help="Schwarz overlap (-1: refined)")
+    ap.add_argument("--omega", type=float, default=0.0, help="smoother damping on every level (0: automatic)")
     ap.add_argument("--coarsening", default="xy", choices=["xy", "both"],
                     help="level orders: in-plane first (xy) or all directions at once (both)")
     ap.add_argument("--smooth-ratio", type=float, default=15.0,
@@ -339,9 +360,13 @@ def main():
     nc_free = probe.levels[-1]["n_free"]
     probe.close()
     coarse = "exact" if nc_free <= 12000 else "chebyshev"
-    nu = a.nu if a.nu > 0 else (3 if a.smoother == "chebyshev" else 2)
+    nu = a.nu if a.nu > 0 else {"chebyshev": 3, "jacobi": 2, "schwarz": 1}[a.smoother]
+    # Schwarz: keep only the local-inverse copies the requested precisions read
+    store = ",".join(sorted({"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16g": "bf16"}[p]
+                            for p in a.precisions.split(",") if p))
     ctx = pmg.Context(mesh, P=a.P, coarse=coarse, cheb_degree=a.coarse_degree, smoother=a.smoother,
-                      nu1=nu, nu2=nu, smooth_ratio=a.smooth_ratio, coarsening=a.coarsening)
+                      nu1=nu, nu2=nu, smooth_ratio=a.smooth_ratio, coarsening=a.coarsening, overlap=a.overlap,
+                      schwarz_store=store, **({"omega": [a.omega] * 8} if a.omega > 0 else {}))
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
@@ -413,8 +438,13 @@ def main():
                  "ms_per_launch": ms_k, "bytes_per_launch": byts, "flops_per_launch": flops,
                  "fp64_kernel": dict(roofline(byts64, flops, ms_k64, "fp64"), ms_per_launch=ms_k64),
                  "assemble_ms_per_launch": ms_asm})
+    if a.smoother == "schwarz":
+        # the dominant kernel is then the batched local solve of the finest level
+        roof_op = roof
+        roof = schwarz_roofline(ctx, kprec)
+        roof["element_op"] = roof_op
     prof = os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "traffic.json")
-    if os.path.exists(prof):
+    if a.smoother != "schwarz" and os.path.exists(prof):
         try:
             tr = json.load(open(prof))
             key = f"{a.workload}:{kprec}"
@@ -433,7 +463,7 @@ def main():
            "data": "synthetic", "dof_per_s": res["dof_per_s"],
            "config": {"workload": wl_desc, "P": a.P, "levels": [[l["order"], l["order_z"]] for l in ctx.levels],
                       "n_dof": info0["n_dof"], "n_elem": info0["n_elem"], "rtol": a.rtol,
-                      "smoother": f"{a.smoother} {nu}+{nu}" + (f" on [lambda/{a.smooth_ratio:g}, lambda]" if a.smoother == "chebyshev" else ""),
+                      "smoother": f"{a.smoother} {nu}+{nu}" + (f" on [lambda/{a.smooth_ratio:g}, lambda]" if a.smoother == "chebyshev" else "") + (f", overlap {a.overlap}" if a.smoother == "schwarz" else ""),
                       "coarsening": a.coarsening,
                       "coarse": cinfo,
                       "guess": "zero", "precision": best, "krylov": res["krylov"]},

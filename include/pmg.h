@@ -86,7 +86,7 @@ enum pmg_coarse { PMG_COARSE_EXACT = 0, PMG_COARSE_CHEBYSHEV = 1 };
  * eq. weights): S^-1 = W sum_k R_k^T (R_k A R_k^T)^-1 R_k with one subdomain
  * per prism (the prism's nodes plus the overlap of pmg_options.overlap in the
  * prisms that touch it, Dirichlet nodes left out) and W the inverse count of
- * subdomains holding each node; nu sweeps damped by omega (default 1).  Pre-
+ * subdomains holding each node; nu sweeps damped by omega.  Pre-
  * smoothing uses S^-1, post-smoothing its transpose sum_k R_k^T A_k^-1 R_k W,
  * so the V-cycle stays symmetric.  The local inverses are dense (FP64, with
  * FP32 and BF16 copies for the mixed V-cycles) and are rebuilt by every
@@ -116,7 +116,9 @@ typedef struct pmg_options {
   int32_t P;              /* finest order, 1..8; levels P, floor(P/2), ..., 1    */
   int32_t nu1, nu2;       /* damped-Jacobi pre/post sweeps (Alg. 1)              */
   double omega[8];        /* per level; <= 0: 4/(3*lambda) with lambda = 1.05 x
-                             30-step power estimate of lambda_max(D^-1 A)       */
+                             30-step power estimate of lambda_max(D^-1 A)
+                             (Schwarz: of the spectral radius of S^-1 A, the
+                             2-norm of the last step; the paper's form is 1)   */
   int32_t precision;      /* pmg_precision of the V-cycle                        */
   int32_t krylov;         /* pmg_krylov                                          */
   uint32_t dirichlet_tags;/* bit k set: lateral edges tagged k are Dirichlet      */
@@ -143,6 +145,12 @@ typedef struct pmg_options {
                              overlapping node in each direction, Sec. 5.2); -1:
                              the refined variant of Sec. 6.3, ceil((P_l+1)/2) in
                              the triangle and ceil((PZ_l+1)/2) vertically      */
+  int32_t schwarz_store;  /* Schwarz local inverses kept: bit 0 FP64, bit 1 FP32,
+                             bit 2 BF16 (0: all three).  A smoothing step in a
+                             precision whose copy is not kept fails with EINVAL.
+                             Without FP64 the set-up works in FP64 chunks of
+                             schwarz_chunk entries                             */
+  int64_t schwarz_chunk;  /* entries of an FP64 set-up chunk; <= 0: 2^29 (4 GiB) */
 } pmg_options;
 
 /* Order sequence of the levels.  BOTH: P, floor(P/2), ..., 1 in every direction

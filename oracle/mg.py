@@ -13,7 +13,10 @@
   count on [lambda/ratio, lambda] with lambda = 4/(3 omega) (the power
   estimate of lambda_max(D^-1 A)); both are linear and symmetric.  Or the
   overlapping additive Schwarz smoother of eq. Mass (``oracle.schwarz``),
-  damped by omega (default 1), its transpose in post-smoothing.
+  its transpose in post-smoothing, damped by omega = 4/(3 rho) with rho the
+  power estimate of the spectral radius of S^-1 A (the paper's undamped form
+  is omega = 1; on tall prisms one undamped sweep makes the V-cycle
+  indefinite).
 * Coarsest level (P = 1): exact solve (dense Cholesky or sparse LU), or a
   fixed-degree Jacobi-preconditioned Chebyshev iteration on a given interval.
 * V-cycle: Alg. 1 with zero initial guess below the top.
@@ -124,10 +127,13 @@ class Hierarchy:
                    for i in range(len(self.orders) - 1)]
         if smoother not in ("jacobi", "chebyshev", "schwarz"):
             raise ValueError(smoother)
-        # smoothing weights (Schwarz: a damping factor, 1 unless given)
+        if smoother == "schwarz":
+            for lv in self.levels[:-1]:
+                lv.schwarz = Schwarz(lv, *overlap_of(order_pair(lv.P), overlap))
+        # smoothing weights
         for i, lv in enumerate(self.levels[:-1]):
             if omega is None and smoother == "schwarz":
-                lv.omega = 1.0
+                lv.omega = 4.0 / (3.0 * self.schwarz_rho(i, seed=seed))
             elif omega is None:
                 lv.omega = 4.0 / (3.0 * self.lambda_max(i, seed=seed))
             elif np.isscalar(omega):
@@ -136,9 +142,6 @@ class Hierarchy:
                 lv.omega = float(omega[i])
         self.smoother = smoother
         self.overlap = int(overlap)
-        if smoother == "schwarz":
-            for lv in self.levels[:-1]:
-                lv.schwarz = Schwarz(lv, *overlap_of(order_pair(lv.P), overlap))
         self.smooth_ratio = float(smooth_ratio)
         self.coarse_mode = coarse
         self.cheb = cheb
@@ -154,6 +157,15 @@ class Hierarchy:
         Ax = lv.A(x)
         rq = float(x @ Ax) / float(np.sum(np.where(lv.free, lv.diag, 0.0) * x * x))
         return 1.05 * rq
+
+    # -- spectral radius of S^-1 A for the Schwarz preconditioner (power iteration, 2-norm)
+    def schwarz_rho(self, i: int, steps: int = 30, seed: int = 0) -> float:
+        lv = self.levels[i]
+        x = np.where(lv.free, splitmix64_unit(lv.num.n_dof, seed), 0.0)
+        for _ in range(steps):
+            y = lv.schwarz.apply(lv.A(x))
+            x = y / np.linalg.norm(y)
+        return 1.05 * float(np.linalg.norm(lv.schwarz.apply(lv.A(x))))
 
     def _coarse_setup(self):
         lv = self.levels[-1]

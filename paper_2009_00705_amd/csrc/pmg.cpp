@@ -461,9 +461,10 @@ static void upload_levels(pmg_ctx* c) {
       L.sz_w64 = c->U(P.w);
       L.sz_w32 = c->U(to_f32(P.w));
       const size_t ninv = size_t(P.inv_off.back());
-      L.sz_inv64 = c->A<double>(ninv);
-      L.sz_inv32 = c->A<float>(ninv);
-      L.sz_inv16 = c->A<bf16_t>(ninv);
+      const int keep = c->opt.schwarz_store == 0 ? 7 : c->opt.schwarz_store;
+      if (keep & 1) L.sz_inv64 = c->A<double>(ninv);
+      if (keep & 2) L.sz_inv32 = c->A<float>(ninv);
+      if (keep & 4) L.sz_inv16 = c->A<bf16_t>(ninv);
       L.sz_z64 = c->A<double>(size_t(std::max<int64_t>(1, P.total)));
       L.sz_z32 = c->A<float>(size_t(std::max<int64_t>(1, P.total)));
     }
@@ -584,6 +585,14 @@ static void cheb_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess, in
   }
 }
 
+// inverse storage of a Schwarz application in the V-cycle precision; EINVAL if not kept
+static void need_sz(const Level& L, bool f64, int lowp) {
+  const bool ok = f64 ? L.sz_inv64 != nullptr : (lowp == G_BF16 ? L.sz_inv16 != nullptr : L.sz_inv32 != nullptr);
+  if (!ok)
+    throw Error(PMG_EINVAL, std::string("Schwarz inverses not kept in ") +
+                                (f64 ? "FP64" : (lowp == G_BF16 ? "BF16" : "FP32")) + " (options.schwarz_store)");
+}
+
 // k sweeps of the Schwarz smoother u <- u + omega S^-1 (f - A u), from u = 0
 // when zero_guess; post: the transpose sum_k R_k^T A_k^-1 R_k W.
 template <typename T>
@@ -592,6 +601,7 @@ static void schwarz_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess,
   T* r = L.r<T>();
   T* z = L.szz<T>();
   const T* w = L.szw<T>();
+  need_sz(L, sizeof(T) == 8, c->lowp);
   for (int s = 0; s < k; ++s) {
     const bool first = zero_guess && s == 0;
     const T* x = f;
@@ -694,6 +704,60 @@ static double lambda_max(pmg_ctx* c, int i, hipStream_t st) {
   launch_scale_diag<double>(L.diag, x, y, 1.0, N, st);
   const double xdx = dot_host(c, x, y, N, st);
   return 1.05 * xax / xdx;
+}
+
+// Spectral radius of S^-1 A for the Schwarz preconditioner S^-1 of level i:
+// 30 power steps x <- S^-1 A x / ||S^-1 A x|| from the masked counter-based
+// vector, then 1.05 ||S^-1 A x||.  Vectors in T; the inverse copy is the one
+// a V-cycle in T reads.
+template <typename T>
+static double schwarz_rho_t(pmg_ctx* c, int i, hipStream_t st) {
+  Level& L = c->lv[i];
+  const int64_t N = L.num.n_dof;
+  std::vector<double> x0(N);
+  for (int64_t g = 0; g < N; ++g) x0[g] = splitmix_unit(c->opt.seed, uint64_t(g));
+  T* x = L.r<T>();
+  T* y = L.d<T>();
+  HIPCHK(hipMemcpyAsync(c->s_y, x0.data(), N * sizeof(double), hipMemcpyHostToDevice, st));
+  HIPCHK(hipStreamSynchronize(st));  // x0 is a temporary host buffer
+  launch_cast<double, T>(c->s_y, y, 1.0, N, st);
+  launch_mask<T>(L.view, y, x, st);
+  auto step = [&](T* out) {  // out = S^-1 A x
+    ax_elem<T>(c, i, x, st);
+    assemble<T>(c, i, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+    if (sizeof(T) == 8)
+      launch_sd_apply<double, double>(L.szv, L.sz_inv64, (const double*)y, nullptr, (double*)L.szz<T>(), st);
+    else if (c->lowp == G_BF16)
+      launch_sd_apply<float, bf16_t>(L.szv, L.sz_inv16, (const float*)y, nullptr, (float*)L.szz<T>(), st);
+    else
+      launch_sd_apply<float, float>(L.szv, L.sz_inv32, (const float*)y, nullptr, (float*)L.szz<T>(), st);
+    launch_sd_sum<T>(L.szv, N, L.szz<T>(), L.szw<T>(), T(1), false, out, st);
+  };
+  auto norm = [&](const T* v) {
+    launch_dot<T>(v, v, N, c->partial, st);
+    launch_finalize(c->partial, c->scal, S_TMP0, FIN_SET, st);
+    return std::sqrt(read_scal(c, S_TMP0, st));
+  };
+  for (int it = 0; it < 30; ++it) {
+    step(x);
+    const double nrm = norm(x);
+    if (!(nrm > 0)) throw Error(PMG_EBREAKDOWN, "power iteration collapsed");
+    launch_sd_scale<T>(x, 1.0 / nrm, N, st);
+  }
+  step(y);
+  return 1.05 * norm(y);
+}
+
+static double schwarz_rho(pmg_ctx* c, int i, hipStream_t st) {
+  Level& L = c->lv[i];
+  if (L.sz_inv64) return schwarz_rho_t<double>(c, i, st);
+  const int lowp = c->lowp;
+  const bool ops = c->bf16_ops;
+  set_lowp(c, L.sz_inv32 ? PMG_MIXED_FP32 : PMG_MIXED_BF16G);
+  const double rho = schwarz_rho_t<float>(c, i, st);
+  c->lowp = lowp;
+  c->bf16_ops = ops;
+  return rho;
 }
 
 // smallest / largest eigenvalue of a symmetric tridiagonal matrix (Sturm bisection)
@@ -981,25 +1045,51 @@ static void coarse_exact_setup(pmg_ctx* c, hipStream_t st) {
 // current geometry, inverted in place (FP64), with FP32 / BF16 copies.  The
 // element matrices live in a scratch buffer freed afterwards.
 // ---------------------------------------------------------------------------
+// When the FP64 copy is kept the blocks are built in place; otherwise they are
+// built in FP64 in chunks of at most options.schwarz_chunk entries (one block
+// at least) and converted.
 static void schwarz_setup(pmg_ctx* c, hipStream_t st) {
   for (int i = 0; i + 1 < c->nl; ++i) {
     Level& L = c->lv[i];
     if (!L.has_sz) continue;
     const size_t nK = size_t(L.num.n_elem) * L.re->np * L.re->np;
-    double* K = nullptr;
+    double *K = nullptr, *W = nullptr;
+    const std::vector<int64_t>& off = L.sz.inv_off;
+    const int64_t E = L.sz.n_sub;
     if (hipMalloc((void**)&K, nK * sizeof(double)) != hipSuccess)
       throw Error(PMG_ENOMEM, "no device memory for the Schwarz element matrices");
+    const int64_t chunk = c->opt.schwarz_chunk > 0 ? c->opt.schwarz_chunk : (int64_t(1) << 29);
+    int64_t blk_max = 0;
+    for (int64_t k = 0; k < E; ++k) blk_max = std::max(blk_max, off[k + 1] - off[k]);
+    if (!L.sz_inv64) {
+      const int64_t nw = std::min<int64_t>(off.back(), std::max<int64_t>(chunk, blk_max));
+      if (hipMalloc((void**)&W, size_t(nw) * sizeof(double)) != hipSuccess) {
+        (void)hipFree(K);
+        throw Error(PMG_ENOMEM, "no device memory for the Schwarz set-up");
+      }
+    }
     HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), st));
     launch_elem_mats(L.view, L.mats64, L.G64, K, st);
-    launch_sd_assemble(L.szv, L.re->np, K, L.sz_inv64, st);
-    launch_sd_invert(L.szv, L.sz_inv64, L.sz_inv32, L.sz_inv16, c->bad, st);
+    for (int64_t k0 = 0; k0 < E;) {
+      int64_t k1 = k0 + 1;
+      if (L.sz_inv64) k1 = E;
+      else
+        while (k1 < E && off[k1 + 1] - off[k0] <= chunk) ++k1;
+      double* work = L.sz_inv64 ? L.sz_inv64 : W;
+      const int64_t base = L.sz_inv64 ? 0 : off[k0];
+      launch_sd_assemble(L.szv, k0, k1, base, L.re->np, K, work, st);
+      launch_sd_invert(L.szv, k0, k1, base, work, L.sz_inv64, L.sz_inv32, L.sz_inv16, c->bad, st);
+      k0 = k1;
+    }
     int bad = 0;
     HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     HIPCHK(hipFree(K));
+    if (W) HIPCHK(hipFree(W));
     if (bad) throw Error(PMG_EBREAKDOWN, "Schwarz local matrix with a non-positive pivot (singular subdomain?)");
   }
 }
+
 
 // ---------------------------------------------------------------------------
 // surface / geometry
@@ -1043,12 +1133,12 @@ static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
     launch_dinv<double>(L.view, nullptr, L.diag, L.dinv64, st);
     launch_dinv<float>(L.view, nullptr, L.diag, L.dinv32, st);
   }
+  schwarz_setup(c, st);
   for (int i = 0; i + 1 < c->nl; ++i) {
     Level& L = c->lv[i];
-    if (c->opt.smoother == PMG_SMOOTH_SCHWARZ) L.omega = L.omega_user > 0 ? L.omega_user : 1.0;
-    else L.omega = L.omega_user > 0 ? L.omega_user : 4.0 / (3.0 * lambda_max(c, i, st));
+    const bool sz = c->opt.smoother == PMG_SMOOTH_SCHWARZ;
+    L.omega = L.omega_user > 0 ? L.omega_user : 4.0 / (3.0 * (sz ? schwarz_rho(c, i, st) : lambda_max(c, i, st)));
   }
-  schwarz_setup(c, st);
   // coarse solver
   Level& C = c->lv[c->nl - 1];
   c->coarse_exact = c->opt.coarse == PMG_COARSE_EXACT;
@@ -1583,6 +1673,7 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
     if (o->smoother < 0 || o->smoother > 2) throw Error(PMG_EINVAL, "bad smoother");
     if (o->smoother == PMG_SMOOTH_SCHWARZ && o->overlap < -1) throw Error(PMG_EINVAL, "bad Schwarz overlap");
+    if (o->schwarz_store < 0 || o->schwarz_store > 7) throw Error(PMG_EINVAL, "bad schwarz_store mask");
     if (o->coarsening < 0 || o->coarsening > 1) throw Error(PMG_EINVAL, "bad coarsening");
     if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
       throw Error(PMG_EINVAL, "smooth_ratio must exceed 1");
@@ -1905,6 +1996,7 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
     if ((kernel == PMG_K_RESTRICT || kernel == PMG_K_PROLONG) && level + 1 >= c->nl)
       throw Error(PMG_EINVAL, "no coarser level");
     if (kernel == PMG_K_SCHWARZ && !L.has_sz) throw Error(PMG_EINVAL, "no Schwarz smoother on this level");
+    if (kernel == PMG_K_SCHWARZ) need_sz(L, f64, c->lowp);
     launch_fill<double>(L.r64, 1.0, L.num.n_dof, st);
     launch_fill<float>(L.r32, 1.0f, L.num.n_dof, st);
     auto one = [&]() {

@@ -82,7 +82,8 @@ void launch_elem_mats(const LevelView& lv, const double* mats, const double* G64
 // local matrices: every prism block adds its entries; blocks in ascending
 // prism order (fixed summation order), no two entries of a block collide.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_sd_assemble(int64_t n_sub, const int32_t* __restrict__ sd_ptr,
+__global__ __launch_bounds__(256) void k_sd_assemble(int64_t k0, int64_t k1, int64_t base,
+                                                     const int32_t* __restrict__ sd_ptr,
                                                      const int32_t* __restrict__ msz,
                                                      const int64_t* __restrict__ inv_off,
                                                      const int32_t* __restrict__ blk_ptr,
@@ -90,9 +91,9 @@ __global__ __launch_bounds__(256) void k_sd_assemble(int64_t n_sub, const int32_
                                                      const int32_t* __restrict__ blk_ent,
                                                      const int32_t* __restrict__ ent, int np,
                                                      const double* __restrict__ K, double* __restrict__ A) {
-  for (int64_t k = blockIdx.x; k < n_sub; k += gridDim.x) {
+  for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
     const int m = msz[k], n = sd_ptr[k + 1] - sd_ptr[k];
-    double* Ak = A + inv_off[k];
+    double* Ak = A + (inv_off[k] - base);
     __syncthreads();
     for (int idx = threadIdx.x; idx < m * m; idx += 256) {
       const int i = idx / m, j = idx - i * m;
@@ -112,8 +113,9 @@ __global__ __launch_bounds__(256) void k_sd_assemble(int64_t n_sub, const int32_
   }
 }
 
-void launch_sd_assemble(const SchwarzView& sv, int np, const double* K, double* A, hipStream_t st) {
-  hipLaunchKernelGGL(k_sd_assemble, dim3(grid_of(sv.n_sub)), dim3(256), 0, st, sv.n_sub, sv.sd_ptr, sv.msz,
+void launch_sd_assemble(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t base, int np, const double* K,
+                        double* A, hipStream_t st) {
+  hipLaunchKernelGGL(k_sd_assemble, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.sd_ptr, sv.msz,
                      sv.inv_off, sv.blk_ptr, sv.blk_elem, sv.blk_ent, sv.ent, np, K, A);
 }
 
@@ -125,16 +127,17 @@ void launch_sd_assemble(const SchwarzView& sv, int np, const double* K, double* 
 // ---------------------------------------------------------------------------
 constexpr int GJ_B = 16, GJ_RC = 256;
 
-__global__ __launch_bounds__(256) void k_sd_invert(int64_t n_sub, const int32_t* __restrict__ sd_ptr,
+__global__ __launch_bounds__(256) void k_sd_invert(int64_t k0, int64_t k1, int64_t base,
+                                                   const int32_t* __restrict__ sd_ptr,
                                                    const int32_t* __restrict__ msz,
                                                    const int64_t* __restrict__ inv_off, double* __restrict__ A,
                                                    int* __restrict__ bad) {
   __shared__ double sKK[GJ_B][GJ_B + 1];
   __shared__ double sCol[GJ_RC][GJ_B + 1];
   const int tid = threadIdx.x;
-  for (int64_t k = blockIdx.x; k < n_sub; k += gridDim.x) {
+  for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
     const int m = msz[k], n = sd_ptr[k + 1] - sd_ptr[k];
-    double* Ak = A + inv_off[k];
+    double* Ak = A + (inv_off[k] - base);
     for (int p0 = 0; p0 < n; p0 += GJ_B) {
       const int bb = n - p0 < GJ_B ? n - p0 : GJ_B;
       const int r = tid / GJ_B, c = tid - r * GJ_B;
@@ -231,24 +234,26 @@ __global__ __launch_bounds__(256) void k_sd_invert(int64_t n_sub, const int32_t*
   }
 }
 
-// (A + A^T)/2 on the n x n block and the FP32 / BF16 copies of the whole padded block
-__global__ __launch_bounds__(256) void k_sd_symm(int64_t n_sub, const int32_t* __restrict__ sd_ptr,
+// (A + A^T)/2 on the n x n block, written to the kept copies of the whole
+// padded block (FP64 may be the work block itself)
+__global__ __launch_bounds__(256) void k_sd_symm(int64_t k0, int64_t k1, int64_t base,
+                                                 const int32_t* __restrict__ sd_ptr,
                                                  const int32_t* __restrict__ msz,
-                                                 const int64_t* __restrict__ inv_off, double* __restrict__ A,
+                                                 const int64_t* __restrict__ inv_off, double* A, double* A64,
                                                  float* __restrict__ A32, bf16_t* __restrict__ A16) {
-  for (int64_t k = blockIdx.x; k < n_sub; k += gridDim.x) {
+  for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
     const int m = msz[k], n = sd_ptr[k + 1] - sd_ptr[k];
     const int64_t off = inv_off[k];
-    double* Ak = A + off;
+    double* Ak = A + (off - base);
     __syncthreads();
     for (int idx = threadIdx.x; idx < m * m; idx += 256) {
       const int i = idx / m, j = idx - i * m;
       if (j < i) continue;
       double v = Ak[size_t(i) * m + j];
-      if (j < n) {
-        v = 0.5 * (v + Ak[size_t(j) * m + i]);
-        Ak[size_t(i) * m + j] = v;
-        Ak[size_t(j) * m + i] = v;
+      if (j < n) v = 0.5 * (v + Ak[size_t(j) * m + i]);
+      if (A64) {
+        A64[off + size_t(i) * m + j] = v;
+        A64[off + size_t(j) * m + i] = v;
       }
       if (A32) {
         A32[off + size_t(i) * m + j] = float(v);
@@ -262,11 +267,12 @@ __global__ __launch_bounds__(256) void k_sd_symm(int64_t n_sub, const int32_t* _
   }
 }
 
-void launch_sd_invert(const SchwarzView& sv, double* A, float* A32, bf16_t* A16, int* bad, hipStream_t st) {
-  hipLaunchKernelGGL(k_sd_invert, dim3(grid_of(sv.n_sub)), dim3(256), 0, st, sv.n_sub, sv.sd_ptr, sv.msz, sv.inv_off,
-                     A, bad);
-  hipLaunchKernelGGL(k_sd_symm, dim3(grid_of(sv.n_sub)), dim3(256), 0, st, sv.n_sub, sv.sd_ptr, sv.msz, sv.inv_off, A,
-                     A32, A16);
+void launch_sd_invert(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t base, double* A, double* A64,
+                      float* A32, bf16_t* A16, int* bad, hipStream_t st) {
+  hipLaunchKernelGGL(k_sd_invert, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.sd_ptr, sv.msz,
+                     sv.inv_off, A, bad);
+  hipLaunchKernelGGL(k_sd_symm, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.sd_ptr, sv.msz,
+                     sv.inv_off, A, A64, A32, A16);
 }
 
 // ---------------------------------------------------------------------------
@@ -375,6 +381,19 @@ void launch_sd_sum(const SchwarzView& sv, int64_t n_dof, const T* zS, const T* w
                      sv.node_ptr, sv.node_pos, zS, w, omega, int(accumulate), u);
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_sd_scale(T* __restrict__ x, T s, int64_t n) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) x[i] *= s;
+}
+
+template <typename T>
+void launch_sd_scale(T* x, double s, int64_t n, hipStream_t st) {
+  const int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL((k_sd_scale<T>), dim3(int(nb < 65536 ? (nb < 1 ? 1 : nb) : 65536)), dim3(256), 0, st, x, T(s), n);
+}
+
+template void launch_sd_scale<double>(double*, double, int64_t, hipStream_t);
+template void launch_sd_scale<float>(float*, double, int64_t, hipStream_t);
 template void launch_sd_apply<double, double>(const SchwarzView&, const double*, const double*, const double*,
                                               double*, hipStream_t);
 template void launch_sd_apply<float, float>(const SchwarzView&, const float*, const float*, const float*, float*,

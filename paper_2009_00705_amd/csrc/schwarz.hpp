@@ -54,15 +54,22 @@ struct SchwarzView {
 
 // K[e][i][j]: dense element stiffness matrices (FP64), local nodes c*np_tri + a.
 void launch_elem_mats(const LevelView& lv, const double* mats, const double* G64, double* K, hipStream_t st);
-// A_k = R_k A R_k^T into the padded blocks of A (identity on the padding).
-void launch_sd_assemble(const SchwarzView& sv, int np, const double* K, double* A, hipStream_t st);
-// In-place inversion of every block (blocked Gauss-Jordan, no pivoting: the
-// blocks are SPD), then (A + A^T)/2 and the FP32 / BF16 copies.  *bad is set
-// when a pivot is not positive.
-void launch_sd_invert(const SchwarzView& sv, double* A, float* A32, bf16_t* A16, int* bad, hipStream_t st);
+// A_k = R_k A R_k^T, k in [k0, k1), into the padded blocks of the work array A
+// (block k at inv_off[k] - base; identity on the padding).
+void launch_sd_assemble(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t base, int np, const double* K,
+                        double* A, hipStream_t st);
+// In-place inversion of the work blocks k in [k0, k1) (blocked Gauss-Jordan,
+// no pivoting: the blocks are SPD), then (A + A^T)/2 written to the kept
+// copies A64 / A32 / A16 (nullable; at inv_off[k]; A64 may be A with base 0).
+// *bad is set when a pivot is not positive.
+void launch_sd_invert(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t base, double* A, double* A64,
+                      float* A32, bf16_t* A16, int* bad, hipStream_t st);
 // zS[sd_ptr[k] + i] = sum_j inv_k[i][j] x_j, x_j = r[node_j] (times w[node_j] when w is given).
 template <typename T, typename TI>
 void launch_sd_apply(const SchwarzView& sv, const TI* inv, const T* r, const T* w, T* zS, hipStream_t st);
+// x *= s (n entries).
+template <typename T>
+void launch_sd_scale(T* x, double s, int64_t n, hipStream_t st);
 // u[g] (+)= omega * (w[g] if given) * sum of zS over the positions of g.
 template <typename T>
 void launch_sd_sum(const SchwarzView& sv, int64_t n_dof, const T* zS, const T* w, T omega, bool accumulate, T* u,

@@ -51,7 +51,8 @@ class Options(C.Structure):
                 ("cheb_lmin", C.c_double), ("cheb_lmax", C.c_double), ("cheb_ratio", C.c_double),
                 ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32),
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
-                ("coarsening", C.c_int32), ("overlap", C.c_int32)]
+                ("coarsening", C.c_int32), ("overlap", C.c_int32), ("schwarz_store", C.c_int32),
+                ("schwarz_chunk", C.c_int64)]
 
 
 class SchwarzInfo(C.Structure):
@@ -192,6 +193,8 @@ def default_options(**kw) -> Options:
             o.smoother = SMOOTHERS[v]
         elif k == "coarse" and isinstance(v, str):
             o.coarse = {"exact": PMG_COARSE_EXACT, "chebyshev": PMG_COARSE_CHEBYSHEV}[v]
+        elif k == "schwarz_store" and isinstance(v, str):
+            o.schwarz_store = sum({"fp64": 1, "fp32": 2, "bf16": 4}[x] for x in v.split(",") if x)
         elif k == "coarsening" and isinstance(v, str):
             o.coarsening = {"both": PMG_COARSEN_BOTH, "xy": PMG_COARSEN_XY_FIRST}[v]
         else:

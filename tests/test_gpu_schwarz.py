@@ -35,13 +35,24 @@ CASES = {
 def pair(request):
     mk, P, seq, ov = CASES[request.param]
     print(f"\n[schwarz case {request.param}]", flush=True)
-    h, ctx = make_pair(mk(), P, omega="lib", smoother="schwarz", overlap=ov, coarsening=seq, nu1=1, nu2=1)
+    h, ctx = make_pair(mk(), P, omega="auto", smoother="schwarz", overlap=ov, coarsening=seq, nu1=1, nu2=1)
     yield request.param, h, ctx
     ctx.close()
 
 
 def _rand(n, seed):
     return W.random_vector(n, seed)
+
+
+def test_automatic_damping_matches_oracle():
+    """omega = 4/(3 rho), rho the power estimate of the spectral radius of S^-1 A
+    (same counter-based start vector and steps as the oracle)."""
+    mk, P, seq, ov = CASES["cyl_P3"]
+    h, ctx = make_pair(mk(), P, omega="lib", smoother="schwarz", overlap=ov, coarsening=seq)
+    om, _, _ = ctx.params()
+    for i, lv in enumerate(h.levels[:-1]):
+        assert abs(om[i] - lv.omega) < 1e-9 * lv.omega, (i, om[i], lv.omega)
+    ctx.close()
 
 
 def test_subdomain_sizes_match(pair):
@@ -129,3 +140,35 @@ def test_schwarz_kernel_timing_runs(pair):
     for prec in ("fp64", "fp32", "bf16g"):
         ms = ctx.time_kernel("schwarz", level=0, precision=prec, reps=2)
         assert ms > 0
+
+
+def test_chunked_setup_and_partial_storage_are_bitwise_equal():
+    """Inverses kept only in FP32 and BF16, built in many small FP64 chunks,
+    give bitwise the FP32 / BF16 smoothing of a context that keeps every copy
+    (the per-subdomain arithmetic does not depend on the chunking); a step in
+    a precision whose copy is not kept is refused."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    mesh = W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=3)
+    kw = dict(P=3, smoother="schwarz", overlap=1, nu1=1, nu2=1, omega=[0.8] * 8)
+    full = pmg.Context(mesh, **kw)
+    part = pmg.Context(mesh, schwarz_store="fp32,bf16", schwarz_chunk=5000, **kw)
+    xy = full.surface_xy()
+    eta = dev(W.surface_elevation_c2(xy[:, 0], xy[:, 1]))
+    full.set_surface(eta)
+    part.set_surface(eta)
+    for lvl in range(full.n_levels - 1):
+        n = full.levels[lvl]["n_dof"]
+        mask = torch.from_numpy(full.dirichlet_mask(lvl) == 0).cuda()
+        f = dev(_rand(n, 7 + lvl), torch.float32) * mask
+        for prec in ("fp32", "bf16g"):
+            a = torch.zeros(n, dtype=torch.float32, device="cuda")
+            b = torch.zeros_like(a)
+            full.smooth(lvl, f, a, sweeps=2, precision=prec)
+            part.smooth(lvl, f, b, sweeps=2, precision=prec)
+            assert torch.equal(a, b), (lvl, prec)
+    with pytest.raises(pmg.PmgError):
+        part.smooth(0, dev(np.zeros(full.levels[0]["n_dof"])),
+                    torch.zeros(full.levels[0]["n_dof"], dtype=torch.float64, device="cuda"), sweeps=1)
+    full.close()
+    part.close()
