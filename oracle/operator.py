@@ -112,7 +112,10 @@ class StiffnessOperator:
         D = np.stack([self.Dr, self.Ds, self.Dt], axis=0)   # (3, Nq, Np)
         # physical gradient matrices: Dp[e, c, q, n] = sum_a K[e,q,a,c] D[a,q,n]
         Dp = np.einsum("eqac,aqn->ecqn", K, D)
-        return np.einsum("ecqi,eq,ecqj->eij", Dp, wd, Dp)
+        # sum over (c, q) of Dp[e,c,q,i] wd[e,q] Dp[e,c,q,j], as one product per prism
+        E, _, nq, n = Dp.shape
+        Dpf = Dp.reshape(E, 3 * nq, n)
+        return np.matmul(Dpf.transpose(0, 2, 1), Dpf * np.tile(wd, (1, 3))[:, :, None])
 
     def assembled(self):
         """Global sparse matrix Q^T blockdiag(A_e) Q (scipy CSR)."""
