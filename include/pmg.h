@@ -315,6 +315,56 @@ enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, 
 int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps, double* ms_per_launch,
                     void* stream);
 
+/* ---- free-surface time stepping (eq. FSeta, eq. FSphi; ERK4 as in Sec. 6.1,
+ * Sec. 6.2) ------------------------------------------------------------------
+ * State: eta and the surface potential phi~ at the finest-level surface nodes
+ * (device [n_surface] FP64, the 2D node order of pmg_surface_xy).  Each
+ * right-hand side sets the surface to the stage's eta (pmg_set_surface: an
+ * inverted element gives EMESH), solves the Laplace problem with phi = phi~
+ * at the surface (pmg_solve with the context's precision and outer
+ * iteration), and evaluates
+ *   eta_t  = -grad eta . grad phi~ + w~ (1 + |grad eta|^2)
+ *   phi~_t = -g eta - 1/2 (|grad phi~|^2 - w~^2 (1 + |grad eta|^2)).
+ * grad: x and y derivatives of the order-P interpolant on every triangle
+ * (isoparametric map), averaged over the triangles sharing a node.  w~: the
+ * derivative of phi along the column of the top prism at the surface node,
+ * times 2L / (eta + depth) (d/dz at fixed x, y under the sigma map).
+ * The first call fixes the smoothing weights and the coarse Chebyshev
+ * interval and degree at their current values for all later surfaces (the
+ * parameter part of the paper's strategy I); geometric factors, diagonals and
+ * the coarse operator follow every surface. */
+
+/* (fx, fy) = horizontal gradient of a surface field f (device [n_surface] each). */
+int pmg_surface_grad(pmg_ctx* ctx, const double* f, double* fx, double* fy, void* stream);
+/* w~ of a finest-level field phi (device [n_dof]) under the current surface:
+ * w (device [n_surface]). */
+int pmg_surface_w(pmg_ctx* ctx, const double* phi, double* w, void* stream);
+/* deta = eta_t, dphis = phi~_t at (eta, phis), g the gravitational
+ * acceleration.  phi (device [n_dof]) receives the Laplace solution; with
+ * warm != 0 it is also the initial guess of the solve.  stats (nullable)
+ * receives the solve's statistics.  Returns the solve's status (OK or
+ * NOT_CONVERGED; the right-hand side is evaluated either way) or an error. */
+int pmg_fnpf_rhs(pmg_ctx* ctx, const double* eta, const double* phis, double g, double* phi, int32_t warm,
+                 double rtol, double atol, int32_t imax, double* deta, double* dphis, pmg_stats* stats,
+                 void* stream);
+typedef struct pmg_fnpf_stats {
+  int32_t iters[4];       /* outer iterations of the four stage solves */
+  double rel_res[4];      /* their final relative residuals */
+  double t_step_ms;       /* wall time of the step on the stream (hipEvents) */
+  double t_solve_ms;      /* part spent in the four pmg_solve calls */
+  int32_t status;         /* worst stage status */
+} pmg_fnpf_stats;
+/* One classical fourth-order Runge-Kutta step of (eta, phis) over dt, in
+ * place.  phi carries the Laplace solution from stage to stage: every stage
+ * solve after the first starts from the previous stage's solution, and the
+ * first from phi when warm != 0 (the last stage's solution of the previous
+ * step), else from zero; on return phi holds the last stage's solution.  On
+ * an error eta and phis are left unchanged; NOT_CONVERGED stages are
+ * reported in stats and the step completes.  The context's surface is the
+ * last stage's afterwards. */
+int pmg_fnpf_erk4(pmg_ctx* ctx, double* eta, double* phis, double dt, double g, double* phi, int32_t warm,
+                  double rtol, double atol, int32_t imax, pmg_fnpf_stats* stats, void* stream);
+
 /* ---- learned warm start (a small multilayer perceptron, FP32) -------------
  * The network maps per-node features of the network level (pmg_net_level: the
  * coarsest level, order (1,1)) to the correction of the extrapolated guess;

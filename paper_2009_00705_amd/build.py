@@ -22,6 +22,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PMG_ARCH", "gfx950")
 
 SOURCES = ["refelem.cpp", "mesh.cpp", "schwarz_plan.cpp", "pmg.cpp", "kernels.hip", "kernels_mfma.hip", "mlp.hip",
+           "fnpf.hip",
            "schwarz.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

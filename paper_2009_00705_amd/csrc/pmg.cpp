@@ -27,6 +27,7 @@
 #include "pmg.h"
 #include "refelem.hpp"
 #include "schwarz.hpp"
+#include "fnpf.hpp"
 
 namespace pmg {
 
@@ -189,6 +190,11 @@ struct pmg_ctx {
   int lowp = pmg::G_F32;      // G storage of the float V-cycle
   bool bf16_ops = false;      // BF16 MFMA operands (PMG_MIXED_BF16) rather than FP32 arithmetic
   int n_vcycles = 0, n_fine_applies = 0;
+  // free-surface time stepping: nodal triangle derivatives, top-node column
+  // derivative, stage buffers ([eta | phi~] pairs), gradients and w~
+  double *fn_Dr = nullptr, *fn_Ds = nullptr, *fn_dtop = nullptr;
+  double *fn_y0 = nullptr, *fn_ys = nullptr, *fn_acc = nullptr, *fn_k = nullptr, *fn_gr = nullptr,
+         *fn_w = nullptr;
   std::vector<void*> allocs;
 
   template <typename T> T* A(size_t n) {
@@ -1962,6 +1968,160 @@ int pmg_set_params(pmg_ctx* c, const double* omega, double lmin, double lmax) {
   if (lmin > 0) c->cheb_lmin = c->opt.cheb_lmin = lmin;
   if (lmin > 0 && lmax > 0 && c->opt.cheb_degree <= 0) c->opt.cheb_degree = c->cheb_k;
   return PMG_OK;
+}
+
+// ---------------------------------------------------------------------------
+// free-surface time stepping (eq. FSeta, eq. FSphi) around the Laplace solve
+// ---------------------------------------------------------------------------
+static void fnpf_alloc(pmg_ctx* c) {
+  if (c->fn_Dr) return;
+  const RefElem& re = *c->lv[0].re;
+  Mat B, Dr, Ds, B1, D1;
+  re.tri_eval(re.r, re.s, B, Dr, Ds);
+  re.line_eval(re.t, B1, D1);
+  std::vector<double> dtop(size_t(re.n1));
+  for (int k = 0; k < re.n1; ++k) dtop[size_t(k)] = D1(re.n1 - 1, k);
+  c->fn_Dr = c->U(Dr.v);
+  c->fn_Ds = c->U(Ds.v);
+  c->fn_dtop = c->U(dtop);
+  const size_t n2 = size_t(c->lv[0].num.n2d);
+  c->fn_y0 = c->A<double>(2 * n2);
+  c->fn_ys = c->A<double>(2 * n2);
+  c->fn_acc = c->A<double>(2 * n2);
+  c->fn_k = c->A<double>(2 * n2);
+  c->fn_gr = c->A<double>(4 * n2);
+  c->fn_w = c->A<double>(n2);
+}
+
+// (fx, fy) of a surface field: element derivatives averaged over triangles
+static void surface_grad(pmg_ctx* c, const double* f, double* fx, double* fy, hipStream_t st) {
+  const Level& F = c->lv[0];
+  launch_surf_grad_elem(F.num.nt, F.re->np_tri, F.map2d, c->fn_Dr, c->fn_Ds, c->xyt, f, c->Y, st);
+  launch_surf_avg(F.num.n2d, F.inc_ptr, F.inc, c->Y, fx, fy, st);
+}
+
+static void surface_w(pmg_ctx* c, const double* phi, const double* eta, double* w, hipStream_t st) {
+  const Level& F = c->lv[0];
+  launch_surf_w(F.num.n2d, F.num.nz, F.num.L, F.PZ, c->mesh.depth, c->fn_dtop, phi, eta, w, st);
+}
+
+// The smoothing weights and the coarse interval and degree keep their current
+// values for later surfaces (the parameter part of strategy I of Sec. 6).
+static void fnpf_freeze(pmg_ctx* c) {
+  for (int i = 0; i + 1 < c->nl; ++i)
+    if (!(c->lv[i].omega_user > 0)) c->lv[i].omega_user = c->lv[i].omega;
+  if (!c->coarse_exact) {
+    if (!(c->opt.cheb_lmax > 0)) c->opt.cheb_lmax = c->cheb_lmax;
+    if (!(c->opt.cheb_lmin > 0)) c->opt.cheb_lmin = c->cheb_lmin;
+    if (c->opt.cheb_degree <= 0) c->opt.cheb_degree = c->cheb_k;
+  }
+}
+
+// deta, dphis at the state (eta, phis): surface geometry, Laplace solve (from
+// phi when warm, else from zero), w~, gradients, eq. FSeta / eq. FSphi.
+static int fnpf_rhs(pmg_ctx* c, const double* eta, const double* phis, double g, double* phi, bool warm,
+                    double rtol, double atol, int imax, double* deta, double* dphis, pmg_stats* stats,
+                    hipStream_t st) {
+  const int64_t n2 = c->lv[0].num.n2d;
+  set_surface(c, eta, st);
+  pmg_stats local;
+  const int rc = solve(c, phis, nullptr, phi, warm ? PMG_GUESS_GIVEN : PMG_GUESS_ZERO, nullptr, nullptr, rtol, atol,
+                       imax, stats ? stats : &local, st);
+  if (rc != PMG_OK && rc != PMG_NOT_CONVERGED) return rc;
+  double* ex = c->fn_gr;
+  double* ey = ex + n2;
+  double* px = ey + n2;
+  double* py = px + n2;
+  surface_w(c, phi, eta, c->fn_w, st);
+  surface_grad(c, eta, ex, ey, st);
+  surface_grad(c, phis, px, py, st);
+  launch_fnpf_rhs(n2, g, eta, ex, ey, px, py, c->fn_w, deta, dphis, st);
+  return rc;
+}
+
+int pmg_surface_grad(pmg_ctx* c, const double* f, double* fx, double* fy, void* stream) {
+  if (!c || !f || !fx || !fy) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    fnpf_alloc(c);
+    surface_grad(c, f, fx, fy, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_surface_w(pmg_ctx* c, const double* phi, double* w, void* stream) {
+  if (!c || !phi || !w) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    fnpf_alloc(c);
+    surface_w(c, phi, c->eta, w, S(stream));
+  });
+  return PMG_OK;
+}
+
+int pmg_fnpf_rhs(pmg_ctx* c, const double* eta, const double* phis, double g, double* phi, int32_t warm,
+                 double rtol, double atol, int32_t imax, double* deta, double* dphis, pmg_stats* stats,
+                 void* stream) {
+  if (!c || !eta || !phis || !phi || !deta || !dphis) return PMG_EINVAL;
+  int rc = PMG_OK;
+  PMG_TRY(c, {
+    need_device(c);
+    fnpf_alloc(c);
+    fnpf_freeze(c);
+    rc = fnpf_rhs(c, eta, phis, g, phi, warm != 0, rtol, atol, imax, deta, dphis, stats, S(stream));
+  });
+  return rc;
+}
+
+int pmg_fnpf_erk4(pmg_ctx* c, double* eta, double* phis, double dt, double g, double* phi, int32_t warm,
+                  double rtol, double atol, int32_t imax, pmg_fnpf_stats* fs, void* stream) {
+  if (!c || !eta || !phis || !phi || !(dt > 0)) return PMG_EINVAL;
+  int rc = PMG_OK;
+  PMG_TRY(c, {
+    need_device(c);
+    fnpf_alloc(c);
+    fnpf_freeze(c);
+    hipStream_t st = S(stream);
+    const int64_t n2 = c->lv[0].num.n2d;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, st));
+    HIPCHK(hipMemcpyAsync(c->fn_y0, eta, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(c->fn_y0 + n2, phis, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    // classical Runge-Kutta: stage s evaluates at y0 + a_s dt k_{s-1}; weights b = (1, 2, 2, 1)/6
+    const double a[4] = {0.0, 0.5, 0.5, 1.0}, b[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
+    pmg_fnpf_stats loc{};
+    for (int s = 0; s < 4 && rc >= 0; ++s) {
+      const double* y = s == 0 ? c->fn_y0 : c->fn_ys;
+      pmg_stats ps;
+      const int r = fnpf_rhs(c, y, y + n2, g, phi, warm != 0 || s > 0, rtol, atol, imax, c->fn_k, c->fn_k + n2,
+                             &ps, st);
+      if (r < 0) { rc = r; break; }
+      if (r != PMG_OK) rc = r;
+      loc.iters[s] = ps.iters;
+      loc.rel_res[s] = ps.rel_res;
+      loc.t_solve_ms += ps.t_solve_ms;
+      // next stage state (unused after the last stage) and the weighted sum
+      launch_rk_stage(2 * n2, c->fn_y0, c->fn_k, s < 3 ? a[s + 1] * dt : 0.0, s < 3 ? c->fn_ys : nullptr, b[s] * dt,
+                      s == 0, c->fn_acc, st);
+    }
+    if (rc >= 0) {
+      launch_rk_stage(2 * n2, c->fn_y0, c->fn_acc, 1.0, c->fn_ys, 0.0, false, c->fn_k, st);
+      HIPCHK(hipMemcpyAsync(eta, c->fn_ys, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+      HIPCHK(hipMemcpyAsync(phis, c->fn_ys + n2, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    }
+    HIPCHK(hipEventRecord(e1, st));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    loc.t_step_ms = ms;
+    loc.status = rc;
+    if (fs) *fs = loc;
+  });
+  return rc;
 }
 
 int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* phi, int guess_mode,

@@ -55,6 +55,15 @@ class Options(C.Structure):
                 ("schwarz_chunk", C.c_int64)]
 
 
+class FnpfStats(C.Structure):
+    _fields_ = [("iters", C.c_int32 * 4), ("rel_res", C.c_double * 4), ("t_step_ms", C.c_double),
+                ("t_solve_ms", C.c_double), ("status", C.c_int32)]
+
+    def as_dict(self):
+        return dict(iters=list(self.iters), rel_res=list(self.rel_res), t_step_ms=self.t_step_ms,
+                    t_solve_ms=self.t_solve_ms, status=self.status)
+
+
 class SchwarzInfo(C.Structure):
     _fields_ = [("dt", C.c_int32), ("dz", C.c_int32), ("n_sub", C.c_int64), ("max_size", C.c_int32),
                 ("total", C.c_int64), ("inv_entries", C.c_int64)]
@@ -112,6 +121,10 @@ SIGNATURES = {
     "pmg_set_solver": (_I, [_VP, _I, _I]),
     "pmg_coarse_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_schwarz_info_get": (_I, [_VP, _I, C.POINTER(SchwarzInfo)]),
+    "pmg_surface_grad": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "pmg_surface_w": (_I, [_VP, _VP, _VP, _VP]),
+    "pmg_fnpf_rhs": (_I, [_VP, _VP, _VP, _D, _VP, C.c_int32, _D, _D, C.c_int32, _VP, _VP, C.POINTER(Stats), _VP]),
+    "pmg_fnpf_erk4": (_I, [_VP, _VP, _VP, _D, _D, _VP, C.c_int32, _D, _D, C.c_int32, C.POINTER(FnpfStats), _VP]),
     "pmg_schwarz_nodes": (_I, [_VP, _I, _VP, _VP]),
     "pmg_time_kernel": (_I, [_VP, _I, _I, _I, _I, C.POINTER(C.c_double), _VP]),
     "pmg_features": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
@@ -374,6 +387,45 @@ class Context:
         rc = lib().pmg_solve(self.h, _dptr(phi_surf, torch.float64), _dptr(phi_bc, torch.float64),
                              _dptr(phi, torch.float64), gm, net.h if net is not None else None, hp,
                              float(rtol), float(atol), int(imax), C.byref(st), _stream(stream))
+        self._c(rc)
+        return rc, st.as_dict()
+
+
+    # ---- free-surface time stepping
+    def surface_grad(self, f, stream=None):
+        """(f_x, f_y) of a surface field (device FP64 tensors)."""
+        import torch
+        fx = torch.empty_like(f)
+        fy = torch.empty_like(f)
+        self._c(lib().pmg_surface_grad(self.h, _dptr(f, torch.float64), _dptr(fx), _dptr(fy), _stream(stream)))
+        return fx, fy
+
+    def surface_w(self, phi, stream=None):
+        """w~ = d phi / dz at the surface nodes under the current surface."""
+        import torch
+        w = torch.empty(self.levels[0]["n_surface"], dtype=torch.float64, device=phi.device)
+        self._c(lib().pmg_surface_w(self.h, _dptr(phi, torch.float64), _dptr(w), _stream(stream)))
+        return w
+
+    def fnpf_rhs(self, eta, phis, phi, g=9.81, warm=False, rtol=1e-10, atol=0.0, imax=500, stream=None):
+        """(eta_t, phi~_t, status, stats) at the state (eta, phi~); phi receives the Laplace solution."""
+        import torch
+        deta = torch.empty_like(eta)
+        dphis = torch.empty_like(phis)
+        st = Stats()
+        rc = lib().pmg_fnpf_rhs(self.h, _dptr(eta, torch.float64), _dptr(phis, torch.float64), float(g),
+                                _dptr(phi, torch.float64), int(bool(warm)), float(rtol), float(atol), int(imax),
+                                _dptr(deta), _dptr(dphis), C.byref(st), _stream(stream))
+        self._c(rc)
+        return deta, dphis, rc, st.as_dict()
+
+    def fnpf_erk4(self, eta, phis, phi, dt, g=9.81, warm=True, rtol=1e-8, atol=0.0, imax=500, stream=None):
+        """One ERK4 step of (eta, phi~) in place; returns (status, stats dict)."""
+        import torch
+        st = FnpfStats()
+        rc = lib().pmg_fnpf_erk4(self.h, _dptr(eta, torch.float64), _dptr(phis, torch.float64), float(dt), float(g),
+                                 _dptr(phi, torch.float64), int(bool(warm)), float(rtol), float(atol), int(imax),
+                                 C.byref(st), _stream(stream))
         self._c(rc)
         return rc, st.as_dict()
 
