@@ -134,6 +134,61 @@ def schwarz_roofline(ctx, prec, level=0, reps=10):
     return r
 
 
+def bench_erk4(a):
+    """Free-surface time stepping on the c3 mesh: a standing wave
+    eta = eps cos(2x) cos(y), phi~ = 0 (k = sqrt 5, steepness k eps = 0.1),
+    ERK4 with dt = T/32, four Laplace solves per step, each stage solve
+    starting from the previous stage's solution."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
+    mesh, wl_desc = workload("c3")
+    probe = pmg.Context(mesh, P=a.P, host_only=1, coarsening=a.coarsening)
+    coarse = "exact" if probe.levels[-1]["n_free"] <= 12000 else "chebyshev"
+    probe.close()
+    nu = a.nu if a.nu > 0 else 3
+    ctx = pmg.Context(mesh, P=a.P, coarse=coarse, smoother="chebyshev", nu1=nu, nu2=nu, coarsening=a.coarsening)
+    info0 = ctx.levels[0]
+    xy = ctx.surface_xy()
+    g, h = 9.81, 1.0
+    k = math.sqrt(5.0)
+    eps = 0.1 / k
+    om = math.sqrt(g * k * math.tanh(k * h))
+    dt = (2 * math.pi / om) / 32
+    eta0 = torch.from_numpy(eps * np.cos(2 * xy[:, 0]) * np.cos(xy[:, 1])).cuda()
+    paths = {}
+    for prec in [p for p in a.precisions.split(",") if p]:
+        ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
+        eta, phis = eta0.clone(), torch.zeros_like(eta0)
+        phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
+        for i in range(a.warmup):
+            ctx.fnpf_erk4(eta, phis, phi, dt, g=g, warm=i > 0, rtol=a.rtol)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        its, solve_ms = [], 0.0
+        for i in range(a.steps):
+            rc, st = ctx.fnpf_erk4(eta, phis, phi, dt, g=g, warm=a.warmup > 0 or i > 0, rtol=a.rtol)
+            its += st["iters"]
+            solve_ms += st["t_solve_ms"]
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t1) * 1e3 / a.steps
+        paths[prec] = {"ms_per_step": ms, "steps_per_s": 1e3 / ms, "stage_iters_mean": float(np.mean(its)),
+                       "stage_iters": its, "solve_share": solve_ms / (ms * a.steps),
+                       "eta_max": float(eta.abs().max())}
+        log(f"[erk4] {prec}: {ms:.1f} ms/step, stage iterations {its}")
+    best = max(paths, key=lambda p: paths[p]["steps_per_s"])
+    out = {"metric": "erk4_steps_per_s", "value": round(paths[best]["steps_per_s"], 4), "unit": "steps/s",
+           "n_gpus": 1, "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(paths[best]["ms_per_step"], 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": DTYPES[best],
+           "data": "synthetic",
+           "config": {"workload": "erk4 on " + wl_desc + f"; standing wave eps cos(2x) cos(y), k eps = 0.1, "
+                                  f"dt = T/32 = {dt:.4f} s, 4 stage solves per step, warm stage starts",
+                      "P": a.P, "n_dof": info0["n_dof"], "rtol": a.rtol, "smoother": f"chebyshev {nu}+{nu}",
+                      "coarsening": a.coarsening, "precision": best},
+           "paths": paths}
+    print(json.dumps(out), flush=True)
+
+
 def bench_history(a):
     """Learned warm start on the focusing-wave history of the cylinder mesh (C5)."""
     import torch
@@ -349,6 +404,8 @@ def main():
         return bench_scaling(a)
     if a.workload == "c4":
         return bench_cylinder(a)
+    if a.workload == "erk4":
+        return bench_erk4(a)
     import torch
     from paper_2009_00705_amd import pmg
     from paper_2009_00705_amd import workloads as W

@@ -355,10 +355,13 @@ typedef struct pmg_fnpf_stats {
   int32_t status;         /* worst stage status */
 } pmg_fnpf_stats;
 /* One classical fourth-order Runge-Kutta step of (eta, phis) over dt, in
- * place.  phi carries the Laplace solution from stage to stage: every stage
- * solve after the first starts from the previous stage's solution, and the
- * first from phi when warm != 0 (the last stage's solution of the previous
- * step), else from zero; on return phi holds the last stage's solution.  On
+ * place.  phi carries the Laplace solution from stage to stage.  Stage solves
+ * start from a prediction linear in time over steps of dt/2: the first from
+ * phi when warm != 0 (the last stage's solution of the previous step), else
+ * from zero; the second (t + dt/2) from 2 phi(t) - phi(t - dt/2) when the
+ * previous call was a step of the same dt (its third stage), else from
+ * phi(t); the third from the second's solution; the fourth (t + dt) from
+ * 2 phi(t + dt/2) - phi(t).  On return phi holds the last stage's solution.  On
  * an error eta and phis are left unchanged; NOT_CONVERGED stages are
  * reported in stats and the step completes.  The context's surface is the
  * last stage's afterwards. */

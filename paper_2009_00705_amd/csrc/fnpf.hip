@@ -101,6 +101,17 @@ void launch_fnpf_rhs(int64_t n2d, double g, const double* eta, const double* ex,
   hipLaunchKernelGGL(k_fnpf_rhs, dim3(blocks(n2d)), dim3(256), 0, st, n2d, g, eta, ex, ey, px, py, w, deta, dphis);
 }
 
+__global__ __launch_bounds__(256) void k_lin_extrap(int64_t n, const double* a, const double* b, double* out) {
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
+    const double v = 2.0 * a[i] - b[i];
+    out[i] = v;
+  }
+}
+
+void launch_lin_extrap(int64_t n, const double* a, const double* b, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_lin_extrap, dim3(blocks(n)), dim3(256), 0, st, n, a, b, out);
+}
+
 __global__ __launch_bounds__(256) void k_rk_stage(int64_t n, const double* __restrict__ y0,
                                                   const double* __restrict__ k, double a, double* __restrict__ ys,
                                                   double b, int first, double* __restrict__ acc) {

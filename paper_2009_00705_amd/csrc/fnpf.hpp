@@ -23,6 +23,8 @@ void launch_surf_w(int64_t n2d, int64_t nz, int L, int PZ, double depth, const d
 // eq. FSeta and eq. FSphi pointwise.
 void launch_fnpf_rhs(int64_t n2d, double g, const double* eta, const double* ex, const double* ey, const double* px,
                      const double* py, const double* w, double* deta, double* dphis, hipStream_t st);
+// out = 2 a - b (n entries; out may be a or b).
+void launch_lin_extrap(int64_t n, const double* a, const double* b, double* out, hipStream_t st);
 // ys = y0 + a k; acc = (first ? 0 : acc) + b k (n entries).
 void launch_rk_stage(int64_t n, const double* y0, const double* k, double a, double* ys, double b, bool first,
                      double* acc, hipStream_t st);

@@ -195,6 +195,10 @@ struct pmg_ctx {
   double *fn_Dr = nullptr, *fn_Ds = nullptr, *fn_dtop = nullptr;
   double *fn_y0 = nullptr, *fn_ys = nullptr, *fn_acc = nullptr, *fn_k = nullptr, *fn_gr = nullptr,
          *fn_w = nullptr;
+  // stage solutions kept for the stage predictor: t_n (stage 1), t_n + dt/2
+  // (stage 3) and the previous step's t_n - dt/2; fn_dt: that step's dt (0: none)
+  double *fn_p1 = nullptr, *fn_p3 = nullptr, *fn_p3prev = nullptr;
+  double fn_dt = 0.0;
   std::vector<void*> allocs;
 
   template <typename T> T* A(size_t n) {
@@ -1991,6 +1995,10 @@ static void fnpf_alloc(pmg_ctx* c) {
   c->fn_k = c->A<double>(2 * n2);
   c->fn_gr = c->A<double>(4 * n2);
   c->fn_w = c->A<double>(n2);
+  const size_t N = size_t(c->lv[0].num.n_dof);
+  c->fn_p1 = c->A<double>(N);
+  c->fn_p3 = c->A<double>(N);
+  c->fn_p3prev = c->A<double>(N);
 }
 
 // (fx, fy) of a surface field: element derivatives averaged over triangles
@@ -2091,14 +2099,23 @@ int pmg_fnpf_erk4(pmg_ctx* c, double* eta, double* phis, double dt, double g, do
     HIPCHK(hipMemcpyAsync(c->fn_y0 + n2, phis, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
     // classical Runge-Kutta: stage s evaluates at y0 + a_s dt k_{s-1}; weights b = (1, 2, 2, 1)/6
     const double a[4] = {0.0, 0.5, 0.5, 1.0}, b[4] = {1.0 / 6, 2.0 / 6, 2.0 / 6, 1.0 / 6};
+    const int64_t N = c->lv[0].num.n_dof;
+    const bool have_prev = warm != 0 && c->fn_dt == dt;
     pmg_fnpf_stats loc{};
     for (int s = 0; s < 4 && rc >= 0; ++s) {
       const double* y = s == 0 ? c->fn_y0 : c->fn_ys;
+      // stage predictor (linear in time over steps of dt/2): stage 2 (t + dt/2)
+      // from t and t - dt/2, stage 4 (t + dt) from t + dt/2 and t; stage 3 (t +
+      // dt/2) starts from stage 2's solution, stage 1 from phi
+      if (s == 1 && have_prev) launch_lin_extrap(N, c->fn_p1, c->fn_p3prev, phi, st);
+      if (s == 3) launch_lin_extrap(N, c->fn_p3, c->fn_p1, phi, st);
       pmg_stats ps;
       const int r = fnpf_rhs(c, y, y + n2, g, phi, warm != 0 || s > 0, rtol, atol, imax, c->fn_k, c->fn_k + n2,
                              &ps, st);
       if (r < 0) { rc = r; break; }
       if (r != PMG_OK) rc = r;
+      if (s == 0) launch_copy<double>(phi, c->fn_p1, N, st);
+      if (s == 2) launch_copy<double>(phi, c->fn_p3, N, st);
       loc.iters[s] = ps.iters;
       loc.rel_res[s] = ps.rel_res;
       loc.t_solve_ms += ps.t_solve_ms;
@@ -2107,6 +2124,8 @@ int pmg_fnpf_erk4(pmg_ctx* c, double* eta, double* phis, double dt, double g, do
                       s == 0, c->fn_acc, st);
     }
     if (rc >= 0) {
+      std::swap(c->fn_p3, c->fn_p3prev);
+      c->fn_dt = dt;
       launch_rk_stage(2 * n2, c->fn_y0, c->fn_acc, 1.0, c->fn_ys, 0.0, false, c->fn_k, st);
       HIPCHK(hipMemcpyAsync(eta, c->fn_ys, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
       HIPCHK(hipMemcpyAsync(phis, c->fn_ys + n2, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
