@@ -20,6 +20,11 @@
 * Coarsest level (P = 1): exact solve (dense Cholesky or sparse LU), or a
   fixed-degree Jacobi-preconditioned Chebyshev iteration on a given interval.
 * V-cycle: Alg. 1 with zero initial guess below the top.
+* Operator reuse across surfaces (Sec. 6, Fig. simstrats): "none" rebuilds
+  every level from each new surface (strategy III); "t0" keeps the
+  preconditioner and moves only the finest level's operator (strategy I);
+  "lin" puts the coarse levels on the flat surface eta = 0 once and moves the
+  finest level with its diagonal (strategy II).  Weights stay as they are.
 Dirichlet nodes carry homogeneous corrections on every level.
 """
 from __future__ import annotations
@@ -111,6 +116,8 @@ class Hierarchy:
                  overlap: int = 1):
         self.mesh = mesh
         self.P = P
+        self.dirichlet_tags, self.top_neumann = dirichlet_tags, top_neumann
+        self.reuse = "none"
         self.orders = level_orders(P, coarsening)
         num_f = Numbering(mesh, P)
         if eta2d is None:
@@ -146,6 +153,43 @@ class Hierarchy:
         self.coarse_mode = coarse
         self.cheb = cheb
         self._coarse_setup()
+
+    # -- operator reuse across surfaces
+    def _rebuild(self, i, xyz_f):
+        old = self.levels[i]
+        nl = Numbering(self.mesh, *order_pair(old.P))
+        d2 = lateral_dirichlet_2d(self.mesh, nl, self.dirichlet_tags) if self.dirichlet_tags else None
+        lv = Level(self.mesh, old.P, self.P, xyz_f, d2, self.top_neumann)
+        lv.omega = old.omega
+        if self.smoother == "schwarz" and i < len(self.levels) - 1:
+            lv.schwarz = Schwarz(lv, *overlap_of(order_pair(lv.P), self.overlap))
+        self.levels[i] = lv
+
+    def set_reuse(self, mode: str):
+        if mode not in ("none", "t0", "lin"):
+            raise ValueError(mode)
+        if mode == "lin":
+            num_f = Numbering(self.mesh, self.P)
+            xyz0 = element_node_xyz(self.mesh, num_f, np.zeros(num_f.n2d))
+            for i in range(1, len(self.levels)):
+                self._rebuild(i, xyz0)
+            self._coarse_setup()
+        self.reuse = mode
+
+    def set_surface(self, eta2d):
+        self.eta2d = np.asarray(eta2d, dtype=np.float64)
+        num_f = Numbering(self.mesh, self.P)
+        xyz_f = element_node_xyz(self.mesh, num_f, self.eta2d)
+        if self.reuse == "none":
+            for i in range(len(self.levels)):
+                self._rebuild(i, xyz_f)
+            self._coarse_setup()
+        elif self.reuse == "t0":
+            lv = self.levels[0]
+            lv.geo = LevelGeometry(lv.P, self.P, xyz_f)
+            lv.op = StiffnessOperator(lv.num, lv.geo)
+        else:
+            self._rebuild(0, xyz_f)
 
     # -- eigenvalue estimate of D^-1 A (power iteration, Rayleigh quotient in the D inner product)
     def lambda_max(self, i: int, steps: int = 30, seed: int = 0) -> float:
