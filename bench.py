@@ -156,6 +156,8 @@ def bench_erk4(a):
     om = math.sqrt(g * k * math.tanh(k * h))
     dt = (2 * math.pi / om) / 32
     eta0 = torch.from_numpy(eps * np.cos(2 * xy[:, 0]) * np.cos(xy[:, 1])).cuda()
+    ctx.set_surface(eta0)
+    ctx.set_reuse(a.reuse)
     paths = {}
     for prec in [p for p in a.precisions.split(",") if p]:
         ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
@@ -184,7 +186,7 @@ def bench_erk4(a):
            "config": {"workload": "erk4 on " + wl_desc + f"; standing wave eps cos(2x) cos(y), k eps = 0.1, "
                                   f"dt = T/32 = {dt:.4f} s, 4 stage solves per step, warm stage starts",
                       "P": a.P, "n_dof": info0["n_dof"], "rtol": a.rtol, "smoother": f"chebyshev {nu}+{nu}",
-                      "coarsening": a.coarsening, "precision": best},
+                      "coarsening": a.coarsening, "precision": best, "reuse": a.reuse},
            "paths": paths}
     print(json.dumps(out), flush=True)
 
@@ -384,6 +386,8 @@ def main():
                     help="smoothing degree/sweeps (0: 3 Chebyshev, 2 Jacobi, 1 Schwarz)")
     ap.add_argument("--overlap", type=int, default=1, help="Schwarz overlap (-1: refined)")
     ap.add_argument("--omega", type=float, default=0.0, help="smoother damping on every level (0: automatic)")
+    ap.add_argument("--reuse", default="none", choices=["none", "t0", "lin"],
+                    help="operator reuse across surfaces (erk4 workload): strategy III, I or II")
     ap.add_argument("--coarsening", default="xy", choices=["xy", "both"],
                     help="level orders: in-plane first (xy) or all directions at once (both)")
     ap.add_argument("--smooth-ratio", type=float, default=15.0,

@@ -296,6 +296,25 @@ int pmg_schwarz_info_get(const pmg_ctx* ctx, int level, pmg_schwarz_info* info);
  * Bit-exact contract. */
 int pmg_schwarz_nodes(const pmg_ctx* ctx, int level, int32_t* ptr, int32_t* nodes);
 
+/* Operator reuse across surfaces (Sec. 6, Fig. simstrats).
+ * NONE: every pmg_set_surface rebuilds the operators of all levels from the
+ *   new surface (NONLIN on every level: the paper's strategy III).
+ * T0: the preconditioner of the surface current at this call is kept (the
+ *   paper's strategy I: S^-1 and the coarse operators of t = 0).  Later
+ *   pmg_set_surface calls update only the finest level's FP64 geometric
+ *   factors, which the outer iteration (and the FP64 V-cycle's finest level)
+ *   applies; coarse operators, diagonals, Schwarz inverses, the coarse solve
+ *   and the finest level's FP32 / BF16 factors of the mixed V-cycle stay.
+ * LIN: the coarse levels are rebuilt once on the flat surface eta = 0 (the
+ *   linear formulation on every level but the finest: the paper's strategy
+ *   II) and kept; the finest level, its smoother data included, follows every
+ *   surface.
+ * T0 and LIN fix the smoothing weights and the coarse Chebyshev interval and
+ * degree at their current values (pmg_set_params changes them).  EINVAL for
+ * an unknown mode. */
+enum pmg_reuse { PMG_REUSE_NONE = 0, PMG_REUSE_T0 = 1, PMG_REUSE_LIN = 2 };
+int pmg_set_reuse(pmg_ctx* ctx, int mode, void* stream);
+
 /* Change the preconditioner precision and the outer iteration of later solves
  * (pmg_precision, pmg_krylov).  The hierarchy is kept. */
 int pmg_set_solver(pmg_ctx* ctx, int precision, int krylov);

@@ -199,6 +199,9 @@ struct pmg_ctx {
   // (stage 3) and the previous step's t_n - dt/2; fn_dt: that step's dt (0: none)
   double *fn_p1 = nullptr, *fn_p3 = nullptr, *fn_p3prev = nullptr;
   double fn_dt = 0.0;
+  // operator reuse across surfaces (pmg_reuse); eta_flat: zeros for the LIN levels
+  int reuse = PMG_REUSE_NONE;
+  double* eta_flat = nullptr;
   std::vector<void*> allocs;
 
   template <typename T> T* A(size_t n) {
@@ -1058,8 +1061,8 @@ static void coarse_exact_setup(pmg_ctx* c, hipStream_t st) {
 // When the FP64 copy is kept the blocks are built in place; otherwise they are
 // built in FP64 in chunks of at most options.schwarz_chunk entries (one block
 // at least) and converted.
-static void schwarz_setup(pmg_ctx* c, hipStream_t st) {
-  for (int i = 0; i + 1 < c->nl; ++i) {
+static void schwarz_setup(pmg_ctx* c, hipStream_t st, int i0 = 0) {
+  for (int i = i0; i + 1 < c->nl; ++i) {
     Level& L = c->lv[i];
     if (!L.has_sz) continue;
     const size_t nK = size_t(L.num.n_elem) * L.re->np * L.re->np;
@@ -1104,7 +1107,69 @@ static void schwarz_setup(pmg_ctx* c, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // surface / geometry
 // ---------------------------------------------------------------------------
+static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st);
+
+// Diagonal (and its inverses) of one level from its current G64.
+static void level_diag(pmg_ctx* c, Level& L, hipStream_t st) {
+  launch_diag(L.view, L.mats64, L.G64, c->Y, st);
+  launch_assemble<double>(L.view, OP_RAW, c->Y, L.diag, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
+  launch_dinv<double>(L.view, nullptr, L.diag, L.dinv64, st);
+  launch_dinv<float>(L.view, nullptr, L.diag, L.dinv32, st);
+}
+
+// Geometry of level i for surface eta (G64, and the FP32/BF16 copies when
+// lowp), with the native copies of the flavours listed in `flavours` (bitmask).
+// Returns nonzero if an element is inverted.
+static int level_geom(pmg_ctx* c, int i, const double* eta, bool lowp, int flavours, hipStream_t st) {
+  Level& F = c->lv[0];
+  Level& L = c->lv[i];
+  HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), st));
+  launch_geom(F.view, L.view, c->mesh.depth, c->xyt, eta, L.gmats, L.wq, L.zq, L.zw, L.G64, lowp ? L.G32 : nullptr,
+              lowp ? L.G16 : nullptr, c->bad, st);
+  int bad = 0;
+  HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (bad) return bad;
+  for (int f = 0; f < 3; ++f)
+    if (L.mf[f] && ((flavours >> f) & 1)) launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
+  return 0;
+}
+
+// Under a reuse mode only the finest level follows the surface: its G64 (the
+// operator of the outer iteration) always; under LIN also its low-precision
+// copies, diagonals and Schwarz inverses.
 static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
+  if (c->reuse == PMG_REUSE_NONE) {
+    set_surface_all(c, eta, st);
+    return;
+  }
+  const bool lin = c->reuse == PMG_REUSE_LIN;
+  const int64_t n2 = c->lv[0].num.n2d;
+  if (level_geom(c, 0, eta, lin, lin ? 7 : 1 << MF_F64, st)) {
+    (void)level_geom(c, 0, c->eta, lin, lin ? 7 : 1 << MF_F64, st);  // restore the previous surface
+    throw Error(PMG_EMESH, "non-positive Jacobian for the given surface (eta <= -depth?)");
+  }
+  if (eta != c->eta) HIPCHK(hipMemcpyAsync(c->eta, eta, n2 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(c->eta_h.data(), c->eta, n2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (lin) {
+    level_diag(c, c->lv[0], st);
+    if (c->lv[0].has_sz) {
+      // Schwarz inverses of the finest level only
+      std::vector<bool> keep(size_t(c->nl));
+      for (int i = 1; i < c->nl; ++i) {
+        keep[size_t(i)] = c->lv[i].has_sz;
+        c->lv[i].has_sz = false;
+      }
+      schwarz_setup(c, st);
+      for (int i = 1; i < c->nl; ++i) c->lv[i].has_sz = keep[size_t(i)];
+    }
+  }
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+static void coarse_setup(pmg_ctx* c, hipStream_t st);
+
+static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st) {
   Level& F = c->lv[0];
   const int64_t n2 = F.num.n2d;
   HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), st));
@@ -1149,7 +1214,12 @@ static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
     const bool sz = c->opt.smoother == PMG_SMOOTH_SCHWARZ;
     L.omega = L.omega_user > 0 ? L.omega_user : 4.0 / (3.0 * (sz ? schwarz_rho(c, i, st) : lambda_max(c, i, st)));
   }
-  // coarse solver
+  coarse_setup(c, st);
+  HIPCHK(hipStreamSynchronize(st));
+}
+
+// coarse solver of the current coarsest-level operator
+static void coarse_setup(pmg_ctx* c, hipStream_t st) {
   Level& C = c->lv[c->nl - 1];
   c->coarse_exact = c->opt.coarse == PMG_COARSE_EXACT;
   if (c->coarse_exact && C.n_free > c->opt.exact_max)
@@ -2141,6 +2211,33 @@ int pmg_fnpf_erk4(pmg_ctx* c, double* eta, double* phis, double dt, double g, do
     if (fs) *fs = loc;
   });
   return rc;
+}
+
+int pmg_set_reuse(pmg_ctx* c, int mode, void* stream) {
+  if (!c || mode < PMG_REUSE_NONE || mode > PMG_REUSE_LIN) return PMG_EINVAL;
+  PMG_TRY(c, {
+    need_device(c);
+    hipStream_t st = S(stream);
+    if (mode != PMG_REUSE_NONE) {
+      fnpf_freeze(c);
+      if (mode == PMG_REUSE_LIN) {
+        const int64_t n2 = c->lv[0].num.n2d;
+        if (!c->eta_flat) {
+          c->eta_flat = c->A<double>(size_t(n2));
+          HIPCHK(hipMemsetAsync(c->eta_flat, 0, n2 * sizeof(double), st));
+        }
+        for (int i = 1; i < c->nl; ++i) {
+          if (level_geom(c, i, c->eta_flat, true, 7, st)) throw Error(PMG_EMESH, "inverted element at eta = 0");
+          level_diag(c, c->lv[i], st);
+        }
+        schwarz_setup(c, st, 1);
+        coarse_setup(c, st);
+        HIPCHK(hipStreamSynchronize(st));
+      }
+    }
+    c->reuse = mode;
+  });
+  return PMG_OK;
 }
 
 int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* phi, int guess_mode,

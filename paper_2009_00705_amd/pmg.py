@@ -122,6 +122,7 @@ SIGNATURES = {
     "pmg_coarse_info": (_I, [_VP, _VP, _VP, _VP, _VP, _VP]),
     "pmg_schwarz_info_get": (_I, [_VP, _I, C.POINTER(SchwarzInfo)]),
     "pmg_surface_grad": (_I, [_VP, _VP, _VP, _VP, _VP]),
+    "pmg_set_reuse": (_I, [_VP, _I, _VP]),
     "pmg_surface_w": (_I, [_VP, _VP, _VP, _VP]),
     "pmg_fnpf_rhs": (_I, [_VP, _VP, _VP, _D, _VP, C.c_int32, _D, _D, C.c_int32, _VP, _VP, C.POINTER(Stats), _VP]),
     "pmg_fnpf_erk4": (_I, [_VP, _VP, _VP, _D, _D, _VP, C.c_int32, _D, _D, C.c_int32, C.POINTER(FnpfStats), _VP]),
@@ -352,6 +353,10 @@ class Context:
 
     def vcycle(self, r, z, precision="fp64", stream=None):
         self._c(lib().pmg_vcycle(self.h, PRECISIONS[precision], _dptr(r), _dptr(z), _stream(stream)))
+
+    def set_reuse(self, mode="none", stream=None):
+        """Operator reuse across surfaces: "none" (strategy III), "t0" (I), "lin" (II)."""
+        self._c(lib().pmg_set_reuse(self.h, {"none": 0, "t0": 1, "lin": 2}[mode], _stream(stream)))
 
     def set_solver(self, precision="fp64", krylov="pcg"):
         self._c(lib().pmg_set_solver(self.h, PRECISIONS[precision], KRYLOV[krylov]))
