@@ -56,9 +56,16 @@ enum pmg_status {
  *                    FP32 accumulation
  *   PMG_MIXED_BF16G  FP32 vectors and FP32 MFMA arithmetic on geometric factors
  *                    stored in BF16 (half the bytes of FP32 G, FP32 operands)
+ *   PMG_MIXED_BF16X3 as BF16G, but every product of the element operator's
+ *                    contractions is a_hi b_hi + a_hi b_lo + a_lo b_hi of BF16
+ *                    parts (x_hi = bf16(x), x_lo = bf16(x - x_hi)) on BF16 MFMA
+ *                    with FP32 accumulation: about 16 significant bits at BF16
+ *                    matrix-core rates (orders (3,3), (6,6), (3,6); other
+ *                    orders run as BF16G)
  * Vectors of the float V-cycle (pmg_apply, pmg_smooth, ...) are float for all
- * three. */
-enum pmg_precision { PMG_FP64 = 0, PMG_MIXED_FP32 = 1, PMG_MIXED_BF16 = 2, PMG_MIXED_BF16G = 3 };
+ * four. */
+enum pmg_precision { PMG_FP64 = 0, PMG_MIXED_FP32 = 1, PMG_MIXED_BF16 = 2, PMG_MIXED_BF16G = 3,
+                     PMG_MIXED_BF16X3 = 4 };
 
 /* Outer iteration: Alg. 3 (PCG), flexible PCG (Polak-Ribiere beta), Alg. 2
  * (preconditioned defect correction), stand-alone V-cycles. */

@@ -12,7 +12,7 @@ typedef uint16_t bf16_t;  // bfloat16 storage (upper half of an IEEE float)
 enum GStore { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
 
 // Reduction buffer: fixed grid so the summation order never changes.
-constexpr int RED_BLOCKS = 512;
+constexpr int RED_BLOCKS = 4096;
 
 // Scalar slots of the Krylov loop (device double array of size N_SCAL).
 enum Scal {

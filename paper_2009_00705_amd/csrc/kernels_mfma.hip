@@ -417,6 +417,153 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
   }
 }
 
+// Split-BF16 products (FP32 accumulation): every operand x = x_hi + x_lo with
+// x_hi = bf16(x), x_lo = bf16(x - x_hi); a product keeps the three terms
+// a_hi b_hi + a_hi b_lo + a_lo b_hi (about 16 significant bits, against 8 for
+// one BF16 product), three BF16 MFMAs in place of one FP32 MFMA of four times
+// the cost per K.  Tables: hi and lo copies of the BF16-layout tables, both in
+// LDS (two workgroups per CU; reading the lo copies through the caches
+// instead, for three, was slower).  Measured at P = 6 this is slower than FP32
+// MFMA on the same BF16 G: the extra MFMAs and the hi/lo splits cost more
+// than the FP32 matrix-core time they replace.
+__device__ __forceinline__ void split_bf(float x, short& hi, short& lo) {
+  hi = f2bf(x);
+  lo = f2bf(x - __uint_as_float(uint32_t(uint16_t(hi)) << 16));
+}
+
+template <int PT, int PZ>
+__global__ __launch_bounds__(64 * (PZ + 1), 2) void k_ax_mfma_bf16x3(const int32_t* __restrict__ map2d, int L,
+                                                                     int nz, int64_t n_elem, int64_t n_batch,
+                                                                     const bf16_t* __restrict__ Gnat,
+                                                                     const s4_t* __restrict__ tab2,
+                                                                     const s4_t* __restrict__ tab4,
+                                                                     const s4_t* __restrict__ tab2lo,
+                                                                     const s4_t* __restrict__ tab4lo,
+                                                                     VertMats<float> vm, const float* __restrict__ u,
+                                                                     float* __restrict__ Y) {
+  using D = MD<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NT2 = D::NT2, KS16 = D::KS16, NAT = D::NAT;
+  constexpr int NTAB2 = 3 * NT2 * KS16 * 64, NTAB4 = 3 * NAT * NT2 * 64;
+  constexpr int NTH = 64 * N1;
+  __shared__ s4_t s2[NTAB2];
+  __shared__ s4_t s2l[NTAB2];
+  __shared__ s4_t s4[NTAB4];
+  __shared__ s4_t s4l[NTAB4];
+  __shared__ float sR[KS_LDS<PT, PZ>::R_WORDS];
+  __shared__ float sV[2 * N1 * N1];
+  for (int i = threadIdx.x; i < NTAB2; i += NTH) { s2[i] = tab2[i]; s2l[i] = tab2lo[i]; }
+  for (int i = threadIdx.x; i < NTAB4; i += NTH) { s4[i] = tab4[i]; s4l[i] = tab4lo[i]; }
+  for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
+  const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
+  const int64_t lb = xcd_block(gridDim.x);
+  for (int64_t b = lb; b < n_batch; b += gridDim.x) {
+    __syncthreads();
+    stage_u<PT, PZ, float>(map2d, L, nz, n_elem, b, u, sR);
+    __syncthreads();
+    s4_t wh[KS16], wl[KS16], zh[KS16], zl[KS16];
+#pragma unroll
+    for (int s = 0; s < KS16; ++s)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int a = 16 * s + 4 * g + kk;
+        float a0 = 0.f, a1 = 0.f;
+        if (a < NPT) {
+#pragma unroll
+          for (int c = 0; c < N1; ++c) {
+            const float uv = sR[(c * NPT + a) * 16 + j];
+            a0 += sV[k * N1 + c] * uv;
+            a1 += sV[N1 * N1 + k * N1 + c] * uv;
+          }
+        }
+        short h0, l0, h1, l1;
+        split_bf(a0, h0, l0);
+        split_bf(a1, h1, l1);
+        wh[s][kk] = h0;
+        wl[s][kk] = l0;
+        zh[s][kk] = h1;
+        zl[s][kk] = l1;
+      }
+    __syncthreads();
+    f4_t yr[NAT], yt[NAT];
+#pragma unroll
+    for (int at = 0; at < NAT; ++at) { yr[at] = f4_t{0, 0, 0, 0}; yt[at] = f4_t{0, 0, 0, 0}; }
+#pragma unroll 1
+    for (int t = 0; t < NT2; ++t) {
+      float gv[6][4];
+      const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
+      const int64_t mst = 16 * D::NQT;
+      if (t < D::NTF) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gv[m][r] = gld<bf16_t>(Gnat, blk + m * mst + t * 256 + lane * 4 + r);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 4 * g + r;
+#pragma unroll
+          for (int m = 0; m < 6; ++m)
+            gv[m][r] = row < D::NQR ? gld<bf16_t>(Gnat, blk + m * mst + D::NTF * 256 + row * 16 + j) : 0.f;
+        }
+      }
+      f4_t dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS16; ++s) {
+        const int i0 = ((0 * NT2 + t) * KS16 + s) * 64 + lane, i1 = ((1 * NT2 + t) * KS16 + s) * 64 + lane,
+                  i2 = ((2 * NT2 + t) * KS16 + s) * 64 + lane;
+        dr = mfma16(s2[i0], wh[s], dr);
+        ds = mfma16(s2[i1], wh[s], ds);
+        db = mfma16(s2[i2], zh[s], db);
+        dr = mfma16(s2[i0], wl[s], dr);
+        ds = mfma16(s2[i1], wl[s], ds);
+        db = mfma16(s2[i2], zl[s], db);
+        dr = mfma16(s2l[i0], wh[s], dr);
+        ds = mfma16(s2l[i1], wh[s], ds);
+        db = mfma16(s2l[i2], zh[s], db);
+      }
+      s4_t rh, rl, sh, sl, th, tl;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float ur = dr[r], us = ds[r], ut = db[r];
+        short h, l;
+        split_bf(gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut, h, l);
+        rh[r] = h;
+        rl[r] = l;
+        split_bf(gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut, h, l);
+        sh[r] = h;
+        sl[r] = l;
+        split_bf(gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut, h, l);
+        th[r] = h;
+        tl[r] = l;
+      }
+#pragma unroll
+      for (int at = 0; at < NAT; ++at) {
+        const int i0 = ((0 * NAT + at) * NT2 + t) * 64 + lane, i1 = ((1 * NAT + at) * NT2 + t) * 64 + lane,
+                  i2 = ((2 * NAT + at) * NT2 + t) * 64 + lane;
+        yr[at] = mfma16(s4[i0], rh, yr[at]);
+        yr[at] = mfma16(s4[i1], sh, yr[at]);
+        yt[at] = mfma16(s4[i2], th, yt[at]);
+        yr[at] = mfma16(s4[i0], rl, yr[at]);
+        yr[at] = mfma16(s4[i1], sl, yr[at]);
+        yt[at] = mfma16(s4[i2], tl, yt[at]);
+        yr[at] = mfma16(s4l[i0], rh, yr[at]);
+        yr[at] = mfma16(s4l[i1], sh, yr[at]);
+        yt[at] = mfma16(s4l[i2], th, yt[at]);
+      }
+    }
+#pragma unroll
+    for (int at = 0; at < NAT; ++at)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * at + 4 * g + r;
+        sR[((k * 2 + 0) * NAT * 16 + a) * 16 + j] = yr[at][r];
+        sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
+      }
+    __syncthreads();
+    vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // G re-layout: standard [e][m][k*NQT+q] (FP64) -> lane-native order of a flavour
 // ---------------------------------------------------------------------------
@@ -506,7 +653,8 @@ void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out,
 
 template <int PT, int PZ>
 static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
-                      const void* vmats, const void* u, void* Y, hipStream_t st) {
+                      const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo = nullptr,
+                      const void* tab4lo = nullptr) {
   const int64_t nb = (lv.n_elem + 15) / 16;
   const int64_t need = ((nb + 7) / 8) * 8;
   constexpr int NT = 64 * (PZ + 1);
@@ -530,6 +678,15 @@ static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const 
     hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                        lv.n_elem, nb, (const bf16_t*)Gnat, (const float*)tab2, (const float*)tab4,
                        *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
+  } else if (flavour == MF_BF16X3) {
+    if constexpr (PT != 8) {
+      auto kern = k_ax_mfma_bf16x3<PT, PZ>;
+      static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
+      hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
+                         lv.n_elem, nb, (const bf16_t*)Gnat, (const s4_t*)tab2, (const s4_t*)tab4,
+                         (const s4_t*)tab2lo, (const s4_t*)tab4lo, *(const VertMats<float>*)vmats,
+                         (const float*)u, (float*)Y);
+    }
   } else {
     auto kern = k_ax_mfma_bf16<PT, PZ, bf16_t>;
     static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
@@ -540,9 +697,11 @@ static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const 
 }
 
 void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
-                    const void* vmats, const void* u, void* Y, hipStream_t st) {
-#define PMG_AXM(PTV, PZV) \
-  if (lv.P == PTV && lv.PZ == PZV) return ax_mfma_p<PTV, PZV>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st);
+                    const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo,
+                    const void* tab4lo) {
+#define PMG_AXM(PTV, PZV)                                                                                      \
+  if (lv.P == PTV && lv.PZ == PZV)                                                                             \
+    return ax_mfma_p<PTV, PZV>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st, tab2lo, tab4lo);
   PMG_MFMA_ORDERS(PMG_AXM)
 #undef PMG_AXM
 }

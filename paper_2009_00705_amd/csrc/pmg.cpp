@@ -98,6 +98,9 @@ struct Level {
   void* gnat[3] = {nullptr, nullptr, nullptr};
   void* tab2[3] = {nullptr, nullptr, nullptr};
   void* tab4[3] = {nullptr, nullptr, nullptr};
+  // lo parts of the BF16 tables (split-BF16 products, MF_BF16X3)
+  void *tab2lo = nullptr, *tab4lo = nullptr;
+  bool mfx3 = false;
   VertMats<double> vm64{};
   VertMats<float> vm32{};
   // overlapping Schwarz smoother: host plan, device view, local inverses
@@ -189,6 +192,7 @@ struct pmg_ctx {
   float* feat_cst = nullptr; // [n1][4] constant features of the coarsest nodes
   int lowp = pmg::G_F32;      // G storage of the float V-cycle
   bool bf16_ops = false;      // BF16 MFMA operands (PMG_MIXED_BF16) rather than FP32 arithmetic
+  bool bf16x3 = false;        // split-BF16 MFMA products (PMG_MIXED_BF16X3)
   int n_vcycles = 0, n_fine_applies = 0;
   // free-surface time stepping: nodal triangle derivatives, top-node column
   // derivative, stage buffers ([eta | phi~] pairs), gradients and w~
@@ -336,7 +340,8 @@ static void build_levels(pmg_ctx* c) {
 // MFMA operand tables of one order (see kernels_mfma.hip): row map of the
 // output registers is 4g+r (FP32, BF16) or g+4r (FP64), g = lane/16, j = lane%16.
 static void mfma_tables(const RefElem& re, int flavour, std::vector<double>& t2, std::vector<double>& t4,
-                        std::vector<uint16_t>& b2, std::vector<uint16_t>& b4) {
+                        std::vector<uint16_t>& b2, std::vector<uint16_t>& b4, std::vector<uint16_t>* b2lo = nullptr,
+                        std::vector<uint16_t>* b4lo = nullptr) {
   const int NPT = re.np_tri, NQT = re.nq_tri;
   const int NT2 = (NQT + 15) / 16, KS = (NPT + 3) / 4, KS16 = (NPT + 15) / 16, NAT = (NPT + 15) / 16;
   const Mat* M[3] = {&re.Dr, &re.Ds, &re.B};
@@ -348,7 +353,29 @@ static void mfma_tables(const RefElem& re, int flavour, std::vector<double>& t2,
     u += 0x7FFFu + ((u >> 16) & 1u);
     return uint16_t(u >> 16);
   };
+  // lo part of a value: bf16 of (v - hi), hi = bf16(v)
+  auto bflo = [&](double v) {
+    const uint16_t h = bf(v);
+    const uint32_t hb = uint32_t(h) << 16;
+    float hf;
+    std::memcpy(&hf, &hb, 4);
+    return bf(double(float(v) - hf));
+  };
   t2.clear(); t4.clear(); b2.clear(); b4.clear();
+  if (flavour == MF_BF16 && b2lo && b4lo) {
+    b2lo->clear();
+    b4lo->clear();
+    for (int mt = 0; mt < 3; ++mt)
+      for (int t = 0; t < NT2; ++t)
+        for (int s = 0; s < KS16; ++s)
+          for (int l = 0; l < 64; ++l)
+            for (int kk = 0; kk < 4; ++kk) b2lo->push_back(bflo(at(mt, 16 * t + (l & 15), 16 * s + 4 * (l >> 4) + kk)));
+    for (int mt = 0; mt < 3; ++mt)
+      for (int a = 0; a < NAT; ++a)
+        for (int t = 0; t < NT2; ++t)
+          for (int l = 0; l < 64; ++l)
+            for (int kk = 0; kk < 4; ++kk) b4lo->push_back(bflo(at(mt, 16 * t + 4 * (l >> 4) + kk, 16 * a + (l & 15))));
+  }
   if (flavour == MF_BF16) {
     for (int mt = 0; mt < 3; ++mt)
       for (int t = 0; t < NT2; ++t)
@@ -390,8 +417,13 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
   for (int f = 0; f < 3; ++f) {
     if (!mfma_available(L.P, L.PZ, f)) continue;
     std::vector<double> t2, t4;
-    std::vector<uint16_t> b2, b4;
-    mfma_tables(re, f, t2, t4, b2, b4);
+    std::vector<uint16_t> b2, b4, b2lo, b4lo;
+    mfma_tables(re, f, t2, t4, b2, b4, &b2lo, &b4lo);
+    if (f == MF_BF16 && mfma_available(L.P, L.PZ, MF_BF16X3)) {
+      L.tab2lo = c->U(b2lo);
+      L.tab4lo = c->U(b4lo);
+      L.mfx3 = true;
+    }
     if (f == MF_F64) {
       L.tab2[f] = c->U(t2);
       L.tab4[f] = c->U(t4);
@@ -525,8 +557,10 @@ static void upload_levels(pmg_ctx* c) {
 // ---------------------------------------------------------------------------
 // precision of the float V-cycle: G storage and MFMA operand type
 static void set_lowp(pmg_ctx* c, int precision) {
-  c->lowp = (precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G) ? G_BF16 : G_F32;
+  c->lowp = (precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G || precision == PMG_MIXED_BF16X3) ? G_BF16
+                                                                                                           : G_F32;
   c->bf16_ops = precision == PMG_MIXED_BF16;
+  c->bf16x3 = precision == PMG_MIXED_BF16X3;
 }
 
 template <typename T> static const void* gptr(pmg_ctx* c, Level& L, int& gstore);
@@ -545,6 +579,11 @@ static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
   const int f = sizeof(T) == 8 ? MF_F64 : (gs == G_BF16 ? MF_BF16 : MF_F32);
   if (L.mf[f]) {
     const void* vm = sizeof(T) == 8 ? (const void*)&L.vm64 : (const void*)&L.vm32;
+    if (f == MF_BF16 && c->bf16x3 && L.mfx3) {
+      launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X3, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
+                     L.tab2lo, L.tab4lo);
+      return;
+    }
     if (f == MF_BF16 && !c->bf16_ops && L.mf[MF_F32]) {
       // FP32 arithmetic on the BF16 copy of G (FP32 tables)
       launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_F32G16, L.tab2[MF_F32], L.tab4[MF_F32], vm, x, c->Y, st);
@@ -1749,7 +1788,7 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (m->nv < 3 || m->nt < 1 || !m->xy || !m->tri || m->n_layers < 1 || !(m->depth > 0))
       throw Error(PMG_EINVAL, "bad mesh sizes");
     if (o->nu1 < 0 || o->nu2 < 0) throw Error(PMG_EINVAL, "negative sweep count");
-    if (o->precision < 0 || o->precision > 3) throw Error(PMG_EINVAL, "bad precision");
+    if (o->precision < 0 || o->precision > 4) throw Error(PMG_EINVAL, "bad precision");
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
     if (o->smoother < 0 || o->smoother > 2) throw Error(PMG_EINVAL, "bad smoother");
     if (o->smoother == PMG_SMOOTH_SCHWARZ && o->overlap < -1) throw Error(PMG_EINVAL, "bad Schwarz overlap");
@@ -1896,7 +1935,8 @@ int pmg_apply(pmg_ctx* c, int level, int precision, int flags, const void* x, vo
       if (flags & 1) { launch_mask<double>(L.view, xin, L.r64, st); xin = L.r64; }
       ax_elem<double>(c, level, xin, st);
       assemble<double>(c, level, (flags & 1) ? OP_STORE : OP_RAW, (double*)y, nullptr, nullptr, nullptr, 0, 0, st);
-    } else if (precision == PMG_MIXED_FP32 || precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G) {
+    } else if (precision == PMG_MIXED_FP32 || precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G ||
+               precision == PMG_MIXED_BF16X3) {
       set_lowp(c, precision);
       const float* xin = (const float*)x;
       if (flags & 1) { launch_mask<float>(L.view, xin, L.r32, st); xin = L.r32; }
@@ -2254,7 +2294,7 @@ int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* 
 }
 
 int pmg_set_solver(pmg_ctx* c, int precision, int krylov) {
-  if (!c || precision < 0 || precision > 3 || krylov < 0 || krylov > 3) return PMG_EINVAL;
+  if (!c || precision < 0 || precision > 4 || krylov < 0 || krylov > 3) return PMG_EINVAL;
   c->opt.precision = precision;
   c->opt.krylov = krylov;
   return PMG_OK;

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmg.so")
 
 PMG_OK, PMG_NOT_CONVERGED, PMG_FALLBACK_USED = 0, 1, 2
-PMG_FP64, PMG_MIXED_FP32, PMG_MIXED_BF16, PMG_MIXED_BF16G = 0, 1, 2, 3
+PMG_FP64, PMG_MIXED_FP32, PMG_MIXED_BF16, PMG_MIXED_BF16G, PMG_MIXED_BF16X3 = 0, 1, 2, 3, 4
 PMG_PCG, PMG_FPCG, PMG_PDC, PMG_MG = 0, 1, 2, 3
 PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED, PMG_GUESS_EXTRAP, PMG_GUESS_EXTRAP3, PMG_GUESS_LEARNED3 = \
     0, 1, 2, 3, 4, 5
@@ -27,7 +27,8 @@ PMG_COARSEN_BOTH, PMG_COARSEN_XY_FIRST = 0, 1
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FALLBACK_USED", -1: "EINVAL", -2: "ENOMEM",
           -3: "EDEVICE", -4: "EBREAKDOWN", -5: "ENONFINITE", -6: "EMESH", -7: "ESTATE"}
 STATUS_CODES = {v: k for k, v in STATUS.items()}
-PRECISIONS = {"fp64": PMG_FP64, "fp32": PMG_MIXED_FP32, "bf16": PMG_MIXED_BF16, "bf16g": PMG_MIXED_BF16G}
+PRECISIONS = {"fp64": PMG_FP64, "fp32": PMG_MIXED_FP32, "bf16": PMG_MIXED_BF16, "bf16g": PMG_MIXED_BF16G,
+              "bf16x3": PMG_MIXED_BF16X3}
 KRYLOV = {"pcg": PMG_PCG, "fpcg": PMG_FPCG, "pdc": PMG_PDC, "mg": PMG_MG}
 
 

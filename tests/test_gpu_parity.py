@@ -59,7 +59,7 @@ def test_operator_fp64_all_levels(pair):
         assert rel_err(host(y), lv.A(x)) < 1e-12, (name, lvl)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2), ("bf16g", 1e-2)])
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-5), ("bf16", 1e-2), ("bf16g", 1e-2), ("bf16x3", 1e-2)])
 def test_operator_low_precision(pair, prec, tol):
     name, h, ctx = pair
     import torch
@@ -69,6 +69,22 @@ def test_operator_low_precision(pair, prec, tol):
         y = torch.empty(n, dtype=torch.float32, device="cuda")
         ctx.apply(lvl, dev(x, torch.float32), y, prec, masked=True)
         assert rel_err(host(y), lv.A(x.astype(np.float32).astype(np.float64))) < tol, (name, lvl)
+
+
+def test_split_bf16_products_match_fp32_products(pair):
+    """bf16x3 and bf16g read the same BF16 geometric factors; their products
+    differ only by the split's rounding (about 2^-16 relative), far below the
+    2^-9 of a single BF16 product: 1e-4."""
+    name, h, ctx = pair
+    import torch
+    for lvl, lv in enumerate(h.levels):
+        n = lv.num.n_dof
+        x = dev(_rand(n, 7 + lvl), torch.float32)
+        y3 = torch.empty(n, dtype=torch.float32, device="cuda")
+        yg = torch.empty_like(y3)
+        ctx.apply(lvl, x, y3, "bf16x3", masked=True)
+        ctx.apply(lvl, x, yg, "bf16g", masked=True)
+        assert rel_err(host(y3), host(yg)) < 1e-4, (name, lvl)
 
 
 def test_diagonal(pair):
