@@ -52,8 +52,68 @@ __global__ __launch_bounds__(256) void k_gemm(int M, int N, int K, const float* 
   }
 }
 
+// Row-contiguous A (sak = 1), K a multiple of 16: one wave per 16 x 64 block
+// of C (four MFMA chains sharing the A operand).  Every lane loads four
+// consecutive k of its A row at once; step s of a group of four uses k =
+// k0 + 4 g + s in lane group g for both operands (the sum over k does not
+// depend on the order in which its terms are grouped).
+template <int ACT>
+__global__ __launch_bounds__(256) void k_gemm_rc(int M, int N, int K, const float* __restrict__ A, int64_t sai,
+                                                 const float* __restrict__ B, int64_t sbk, int64_t sbj,
+                                                 const float* __restrict__ bias, float* __restrict__ Z,
+                                                 float* __restrict__ Cm, int64_t ldc) {
+  const int tiles_n = (N + 63) / 64;
+  const int64_t tile = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t ntile = int64_t((M + 15) / 16) * tiles_n;
+  if (tile >= ntile) return;
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  const int i0 = int(tile / tiles_n) * 16, j0 = int(tile % tiles_n) * 64;
+  f4m_t acc[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) acc[n] = f4m_t{0.f, 0.f, 0.f, 0.f};
+  const int ia = i0 + j;
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    const int kb = k0 + 4 * g;
+    float4 a4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (ia < M) a4 = *reinterpret_cast<const float4*>(A + int64_t(ia) * sai + kb);
+    const float av[4] = {a4.x, a4.y, a4.z, a4.w};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const int jb = j0 + 16 * n + j;
+        const float b = jb < N ? B[int64_t(kb + s) * sbk + int64_t(jb) * sbj] : 0.f;
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[s], b, acc[n], 0, 0, 0);
+      }
+    }
+  }
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const int jb = j0 + 16 * n + j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = i0 + 4 * g + r;
+      if (i < M && jb < N) {
+        float c = acc[n][r] + (bias ? bias[jb] : 0.f);
+        if (Z) Z[int64_t(i) * ldc + jb] = c;
+        if (ACT == 1) c = silu_f(c);
+        Cm[int64_t(i) * ldc + jb] = c;
+      }
+    }
+  }
+}
+
 void launch_gemm(int M, int N, int K, const float* A, int64_t sai, int64_t sak, const float* B, int64_t sbk,
                  int64_t sbj, const float* bias, float* Z, float* C, int64_t ldc, bool silu, hipStream_t st) {
+  if (sak == 1 && K % 16 == 0 && sai % 4 == 0 && (reinterpret_cast<uintptr_t>(A) & 15) == 0) {
+    const int64_t nt = int64_t((M + 15) / 16) * ((N + 63) / 64);
+    const int grid = int((nt + 3) / 4);
+    if (silu)
+      hipLaunchKernelGGL(k_gemm_rc<1>, dim3(grid), dim3(256), 0, st, M, N, K, A, sai, B, sbk, sbj, bias, Z, C, ldc);
+    else
+      hipLaunchKernelGGL(k_gemm_rc<0>, dim3(grid), dim3(256), 0, st, M, N, K, A, sai, B, sbk, sbj, bias, Z, C, ldc);
+    return;
+  }
   const int64_t ntile = int64_t((M + 15) / 16) * ((N + 15) / 16);
   const int grid = int((ntile + 3) / 4);
   if (silu)

@@ -1482,16 +1482,23 @@ static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const doub
     launch_copy<float>(n->H[L - 1], n->y1 + r0, B, st);
   }
   // coarsest correction: predicted inside, exact at the surface nodes (new surface data minus its
-  // extrapolation), prolongated level by level without masking; the caller keeps the free part
-  double* cur = NL > 0 ? C.u64 : out;
-  launch_scale_out(n->y1, n->tscale, n1, cur, st);
-  launch_corr_surface(n1, int(C.num.nz), int(c->lv[0].num.nz), surf, p1, p2, p3, cur, st);
+  // extrapolation), prolongated level by level without masking, in FP32 (it is a starting
+  // guess; its residual is formed in FP64 by the caller, who keeps the free part)
+  double* c64 = NL > 0 ? C.u64 : out;
+  launch_scale_out(n->y1, n->tscale, n1, c64, st);
+  launch_corr_surface(n1, int(C.num.nz), int(c->lv[0].num.nz), surf, p1, p2, p3, c64, st);
+  if (NL == 0) return;
+  launch_cast<double, float>(c64, C.u32, 1.0, n1, st);
+  const float* cur = C.u32;
   for (int i = NL - 1; i >= 0; --i) {
-    double* dst = i == 0 ? out : c->lv[i].u64;
-    launch_prolong_elem<double>(c->lv[i].view, c->lv[i + 1].view, c->lv[i].pit64, c->lv[i].piz64, cur, c->Y, st);
-    launch_assemble<double>(c->lv[i].view, OP_AVG_RAW, c->Y, dst, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
+    float* dst = i == 0 ? c->s_z32 : c->lv[i].u32;
+    launch_prolong_elem<float>(c->lv[i].view, c->lv[i + 1].view, c->lv[i].pit32, c->lv[i].piz32, cur,
+                               reinterpret_cast<float*>(c->Y), st);
+    launch_assemble<float>(c->lv[i].view, OP_AVG_RAW, reinterpret_cast<const float*>(c->Y), dst, nullptr, nullptr,
+                           nullptr, 0, 0, nullptr, st);
     cur = dst;
   }
+  launch_cast<float, double>(c->s_z32, out, 1.0, c->lv[0].num.n_dof, st);
 }
 
 static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, int guess, pmg_net* net,
