@@ -196,9 +196,11 @@ __device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds,
   }
 }
 
-// FP32 / FP64 flavours (K = 4)
-template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW>
-__global__ __launch_bounds__(64 * (PZ + 1), sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : 4)) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
+// FP32 / FP64 flavours (K = 4).  GT: the reference tables are read through the
+// caches instead of LDS (FP64 at P = 8, whose tables and staging buffer do not
+// fit in the LDS together); one workgroup per CU then.
+template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW, bool GT = false>
+__global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : 4))) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
                                                          int64_t n_elem, int64_t n_batch,
                                                          const TG* __restrict__ Gnat, const T* __restrict__ tab2,
                                                          const T* __restrict__ tab4, VertMats<T> vm,
@@ -208,12 +210,16 @@ __global__ __launch_bounds__(64 * (PZ + 1), sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : 
   constexpr int NS4 = n_steps4<PT, PZ, F64ROW>();
   constexpr int NTAB2 = 3 * NT2 * KS * 64, NTAB4 = 3 * NAT * NS4 * 64;
   constexpr int NTH = 64 * N1;
-  __shared__ T s2[NTAB2];
-  __shared__ T s4[NTAB4];
+  __shared__ T s2buf[GT ? 1 : NTAB2];
+  __shared__ T s4buf[GT ? 1 : NTAB4];
   __shared__ T sR[KS_LDS<PT, PZ>::R_WORDS];
   __shared__ T sV[2 * N1 * N1];
-  for (int i = threadIdx.x; i < NTAB2; i += NTH) s2[i] = tab2[i];
-  for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
+  const T* __restrict__ s2 = GT ? tab2 : s2buf;
+  const T* __restrict__ s4 = GT ? tab4 : s4buf;
+  if constexpr (!GT) {
+    for (int i = threadIdx.x; i < NTAB2; i += NTH) s2buf[i] = tab2[i];
+    for (int i = threadIdx.x; i < NTAB4; i += NTH) s4buf[i] = tab4[i];
+  }
   for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
   const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
   // wave-uniform vertical level: its Bz/Dz row stays in scalar registers
@@ -641,7 +647,8 @@ static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, 
 }
 
 // orders with MFMA kernels: (3,3), (6,6), (3,6) [the in-plane-coarsened level of
-// P = 6] in every flavour, (8,8) without FP64 (its FP64 tables exceed the LDS)
+// P = 6] in every flavour, (8,8) in every flavour but split-BF16 (its FP64 tables
+// are read through the caches)
 #define PMG_MFMA_ORDERS(X) X(3, 3) X(6, 6) X(3, 6) X(8, 8)
 
 void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
@@ -659,8 +666,8 @@ static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const 
   const int64_t need = ((nb + 7) / 8) * 8;
   constexpr int NT = 64 * (PZ + 1);
   if (flavour == MF_F64) {
-    if constexpr (PT != 8) {
-      auto kern = k_ax_mfma4<PT, PZ, double, double, d4_t, true>;
+    {
+      auto kern = k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8>;
       static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
       hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
                          lv.n_elem, nb, (const double*)Gnat, (const double*)tab2, (const double*)tab4,

@@ -34,7 +34,7 @@ __device__ __forceinline__ float gld_any(const bf16_t* p, int64_t i) { return __
 // (triangle, vertical) orders with an MFMA kernel for a flavour
 inline bool mfma_available(int PT, int PZ, int flavour) {
   if ((PT == 3 && PZ == 3) || (PT == 6 && PZ == 6) || (PT == 3 && PZ == 6)) return true;
-  if (PT == 8 && PZ == 8) return flavour != MF_F64 && flavour != MF_BF16X3;  // LDS
+  if (PT == 8 && PZ == 8) return flavour != MF_BF16X3;  // LDS
   return false;
 }
 void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st);
