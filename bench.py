@@ -26,7 +26,8 @@ import numpy as np
 
 HBM_PEAK_GBS = 8000.0
 # arithmetic of each path: FP64 outer iteration, preconditioner in the second type
-DTYPES = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16", "bf16g": "f64+f32", "bf16x3": "f64+bf16x3"}
+DTYPES = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16", "bf16g": "f64+f32", "bf16x3": "f64+bf16x3",
+          "bf16x2": "f64+bf16x2"}
 METRIC = "Laplace solves/s and DOF/s to 1e-8 rel residual at P=6 (mixed/learned vs FP64)"
 
 
@@ -40,7 +41,7 @@ def workload(name):
 
 
 # dense peaks (TFLOP/s) of the arithmetic each path's element operator runs in
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16g": 157.3, "bf16": 2500.0, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16g": 157.3, "bf16": 2500.0, "bf16x3": 2500.0, "bf16x2": 2500.0}
 
 
 def op_flops_per_elem(P):
@@ -121,7 +122,7 @@ def schwarz_roofline(ctx, prec, level=0, reps=10):
     nodes it reads the n x n inverse (8, 4 or 2 bytes an entry), n node ids and
     n gathered residual values, and writes n corrections."""
     sizes = np.array([s.size for s in ctx.schwarz_nodes(level)], dtype=np.float64)
-    s_inv = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2}[prec]
+    s_inv = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2, "bf16x2": 2}[prec]
     s_v = 8 if prec == "fp64" else 4
     byts = float(np.sum(sizes * sizes) * s_inv + np.sum(sizes) * (4 + 2 * s_v))
     flops = float(2 * np.sum(sizes * sizes))
@@ -378,7 +379,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3")
     ap.add_argument("--P", type=int, default=6)
-    ap.add_argument("--precisions", default="fp64,fp32,bf16,bf16g")
+    ap.add_argument("--precisions", default="fp64,fp32,bf16,bf16g,bf16x3")
     ap.add_argument("--rtol", type=float, default=1e-8)
     ap.add_argument("--coarse-degree", type=int, default=0, help="Chebyshev coarse degree (0: automatic)")
     ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "jacobi", "schwarz"])
@@ -423,7 +424,8 @@ def main():
     coarse = "exact" if nc_free <= 12000 else "chebyshev"
     nu = a.nu if a.nu > 0 else {"chebyshev": 3, "jacobi": 2, "schwarz": 1}[a.smoother]
     # Schwarz: keep only the local-inverse copies the requested precisions read
-    store = ",".join(sorted({{"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16g": "bf16", "bf16x3": "bf16"}[p]
+    store = ",".join(sorted({{"fp64": "fp64", "fp32": "fp32", "bf16": "bf16", "bf16g": "bf16", "bf16x3": "bf16",
+                              "bf16x2": "bf16"}[p]
                              for p in a.precisions.split(",") if p}))
     ctx = pmg.Context(mesh, P=a.P, coarse=coarse, cheb_degree=a.coarse_degree, smoother=a.smoother,
                       nu1=nu, nu2=nu, smooth_ratio=a.smooth_ratio, coarsening=a.coarsening, overlap=a.overlap,
@@ -449,7 +451,7 @@ def main():
         res = {"workload": wl_desc, "copy_bytes": 2 * 8 * info0["n_dof"]}
         res["copy_ms"] = ctx.time_kernel("copy", 0, "fp64", reps=a.steps)
         for prec in [p for p in a.precisions.split(",") if p]:
-            s_g = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2}[prec]
+            s_g = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2, "bf16x2": 2}[prec]
             ms = ctx.time_kernel("element_op", 0, prec, reps=a.steps)
             byts = op_bytes(info0, nt, npt, s_g, 8 if prec == "fp64" else 4)
             flops = op_flops_per_elem(a.P) * info0["n_elem"]
@@ -484,7 +486,7 @@ def main():
     best = max(paths, key=lambda k: paths[k]["solves_per_s"] if paths[k]["rel_res"] <= a.rtol * 1.0001 else -1)
     # dominant kernel: fine-level element operator in the best path's V-cycle precision
     kprec = best
-    s_g = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2}[kprec]
+    s_g = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2, "bf16x2": 2}[kprec]
     s_v = 8 if kprec == "fp64" else 4
     ms_k = ctx.time_kernel("element_op", 0, kprec, reps=20)
     ms_k64 = ctx.time_kernel("element_op", 0, "fp64", reps=20)

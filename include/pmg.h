@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PMG_ABI_VERSION 2
+#define PMG_ABI_VERSION 3
 
 enum pmg_status {
   PMG_OK = 0,
@@ -60,12 +60,18 @@ enum pmg_status {
  *                    contractions is a_hi b_hi + a_hi b_lo + a_lo b_hi of BF16
  *                    parts (x_hi = bf16(x), x_lo = bf16(x - x_hi)) on BF16 MFMA
  *                    with FP32 accumulation: about 16 significant bits at BF16
- *                    matrix-core rates (orders (3,3), (6,6), (3,6); other
- *                    orders run as BF16G)
+ *                    matrix-core rates (levels of in-plane order 6; the
+ *                    other levels run as BF16G)
+ *   PMG_MIXED_BF16X2 as BF16X3 with the reference matrices rounded to BF16
+ *                    (a_lo = 0): the element operator is that of slightly
+ *                    perturbed reference matrices, still symmetric, applied
+ *                    with vectors kept to about 16 bits; two BF16 MFMAs per
+ *                    product (levels of in-plane order 6; the other levels
+ *                    run as BF16G)
  * Vectors of the float V-cycle (pmg_apply, pmg_smooth, ...) are float for all
- * four. */
+ * five. */
 enum pmg_precision { PMG_FP64 = 0, PMG_MIXED_FP32 = 1, PMG_MIXED_BF16 = 2, PMG_MIXED_BF16G = 3,
-                     PMG_MIXED_BF16X3 = 4 };
+                     PMG_MIXED_BF16X3 = 4, PMG_MIXED_BF16X2 = 5 };
 
 /* Outer iteration: Alg. 3 (PCG), flexible PCG (Polak-Ribiere beta), Alg. 2
  * (preconditioned defect correction), stand-alone V-cycles. */
@@ -158,7 +164,21 @@ typedef struct pmg_options {
                              Without FP64 the set-up works in FP64 chunks of
                              schwarz_chunk entries                             */
   int64_t schwarz_chunk;  /* entries of an FP64 set-up chunk; <= 0: 2^29 (4 GiB) */
+  int32_t geometry;       /* pmg_geometry of the MFMA element operators          */
 } pmg_options;
+
+/* Geometric factors read by the MFMA element operators.  STORED: the six
+ * factors of G = w det(J) J^-1 J^-T (the metric of the weak form, Sec. 3.1) at
+ * every cubature point of every prism, streamed from memory.  COLUMN
+ * (default): the prisms of a column are the sigma-transform of one triangle
+ * (eq. jacobian: z = -h + s (eta + h), s affine in each layer), so G at
+ * vertical point k of layer l is
+ * zw_k (B0, B1, s B2, B3, s B4, s^2 B5 + B6) with seven factors B per
+ * triangle cubature point shared by the column; the kernels read those and form
+ * G in registers, in the precision of their arithmetic (FP64, FP32).  The BF16
+ * and BF16G precisions keep their stored BF16 factors (BF16X3 and BF16X2 on
+ * the levels without their split kernels too). */
+enum pmg_geometry { PMG_GEOM_STORED = 0, PMG_GEOM_COLUMN = 1 };
 
 /* Order sequence of the levels.  BOTH: P, floor(P/2), ..., 1 in every direction
  * (Sec. 5, Table BTcoarse).  XY_FIRST: the triangle order is coarsened first

@@ -298,7 +298,8 @@ __global__ __launch_bounds__(256) void k_geom(int nt, int L, int nqtl, int n1l, 
                                               const double* __restrict__ zq,
                                               const double* __restrict__ zw, double* __restrict__ G64,
                                               float* __restrict__ G32, bf16_t* __restrict__ G16,
-                                              int* __restrict__ bad) {
+                                              int* __restrict__ bad, double* __restrict__ geo64,
+                                              float* __restrict__ geo32) {
   // fine map of order PF, evaluated at the level's nqtl triangle points and n1l vertical points
   constexpr int NPTF = (PF + 1) * (PF + 2) / 2;
   const int NQTL = nqtl, N1L = n1l, NQL = nqtl * n1l;
@@ -320,6 +321,28 @@ __global__ __launch_bounds__(256) void k_geom(int nt, int L, int nqtl, int n1l, 
   const double Krx = ys / j2, Kry = -xs / j2, Ksx = -yr / j2, Ksy = xr / j2;
   const double zt = (eq + depth) / (2.0 * L);
   int badv = (j2 <= 0.0 || zt <= 0.0 || !(j2 == j2) || !(zt == zt)) ? 1 : 0;
+  if (geo64 || geo32) {
+    // column factors: every (layer, k) of this column shares x_r .. y_s, eta and its
+    // gradient; z_t = (eta + h) / 2L is the same in every layer and
+    // grad t = -s grad(eta) / z_t + e_z / z_t
+    const double c0 = wq[q] * j2;
+    const double ex = er * Krx + es * Ksx, ey = er * Kry + es * Ksy;
+    double bq[8];
+    bq[0] = c0 * zt * (Krx * Krx + Kry * Kry);
+    bq[1] = c0 * zt * (Krx * Ksx + Kry * Ksy);
+    bq[2] = -c0 * (Krx * ex + Kry * ey);
+    bq[3] = c0 * zt * (Ksx * Ksx + Ksy * Ksy);
+    bq[4] = -c0 * (Ksx * ex + Ksy * ey);
+    bq[5] = c0 * (ex * ex + ey * ey) / zt;
+    bq[6] = c0 / zt;
+    bq[7] = 0.0;
+    const size_t o = (size_t(t) * NQTL + q) * 8;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      if (geo64) geo64[o + m] = bq[m];
+      if (geo32) geo32[o + m] = float(bq[m]);
+    }
+  }
   for (int layer = 0; layer < L; ++layer) {
     const size_t e = size_t(t) * L + layer;
     for (int k = 0; k < N1L; ++k) {
@@ -348,14 +371,15 @@ __global__ __launch_bounds__(256) void k_geom(int nt, int L, int nqtl, int n1l, 
 
 void launch_geom(const LevelView& fine, const LevelView& lvl, double depth, const double* xyt,
                  const double* eta, const double* gmats, const double* wq, const double* zq,
-                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st) {
+                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st,
+                 double* geo64, float* geo32) {
   const int nqtl = (lvl.P + 1) * (lvl.P + 1), n1l = lvl.PZ + 1;
   const int64_t items = int64_t(fine.nt) * nqtl;
   const int grid = int((items + 255) / 256);
 #define PMG_GEOM(PFV)                                                                               \
   case PFV:                                                                                         \
     hipLaunchKernelGGL((k_geom<PFV>), dim3(grid), dim3(256), 0, st, fine.nt, fine.L, nqtl, n1l, depth, xyt, \
-                       eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad);                     \
+                       eta, fine.map2d, gmats, wq, zq, zw, G64, G32, G16, bad, geo64, geo32);       \
     break;
   switch (fine.P) {
     PMG_GEOM(1) PMG_GEOM(2) PMG_GEOM(3) PMG_GEOM(4) PMG_GEOM(5) PMG_GEOM(6) PMG_GEOM(7) PMG_GEOM(8)
@@ -444,6 +468,10 @@ __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int
   constexpr int NEB = XFER_NEB;
   __shared__ T sUc[NEB * NPC];
   __shared__ T sT1[NEB * N1C * NPTF];
+  __shared__ T sPt[NPTF * NPTC];
+  __shared__ T sPz[N1F * N1C];
+  for (int i = threadIdx.x; i < NPTF * NPTC; i += 256) sPt[i] = pit[i];
+  for (int i = threadIdx.x; i < N1F * N1C; i += 256) sPz[i] = piz[i];
   for (int64_t e0 = int64_t(blockIdx.x) * NEB; e0 < n_elem; e0 += int64_t(gridDim.x) * NEB) {
     const int ne = int(n_elem - e0 < NEB ? n_elem - e0 : NEB);
     __syncthreads();
@@ -465,7 +493,7 @@ __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int
       const int el = i / (N1C * NPTF), r = i - el * N1C * NPTF, c = r / NPTF, a = r - c * NPTF;
       T s = 0;
 #pragma unroll 4
-      for (int b = 0; b < NPTC; ++b) s += pit[a * NPTC + b] * sUc[el * NPC + c * NPTC + b];
+      for (int b = 0; b < NPTC; ++b) s += sPt[a * NPTC + b] * sUc[el * NPC + c * NPTC + b];
       sT1[el * N1C * NPTF + c * NPTF + a] = s;
     }
     __syncthreads();
@@ -482,7 +510,7 @@ __global__ __launch_bounds__(256) void k_prolong_elem(int64_t n_elem, int L, int
       for (int c = 0; c < N1F; ++c) {
         T s = 0;
 #pragma unroll
-        for (int cc = 0; cc < N1C; ++cc) s += piz[c * N1C + cc] * t1[cc];
+        for (int cc = 0; cc < N1C; ++cc) s += sPz[c * N1C + cc] * t1[cc];
         out[c] = s;
       }
     }
@@ -502,6 +530,10 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
   constexpr int NEB = XFER_NEB;
   __shared__ T sRf[NEB * NPF];
   __shared__ T sT1[NEB * N1F * NPTC];
+  __shared__ T sPt[NPTF * NPTC];
+  __shared__ T sPz[N1F * N1C];
+  for (int i = threadIdx.x; i < NPTF * NPTC; i += 256) sPt[i] = pit[i];
+  for (int i = threadIdx.x; i < N1F * N1C; i += 256) sPz[i] = piz[i];
   for (int64_t e0 = int64_t(blockIdx.x) * NEB; e0 < n_elem; e0 += int64_t(gridDim.x) * NEB) {
     const int ne = int(n_elem - e0 < NEB ? n_elem - e0 : NEB);
     __syncthreads();
@@ -533,7 +565,7 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
       const int el = i / (N1F * NPTC), r = i - el * N1F * NPTC, c = r / NPTC, b = r - c * NPTC;
       T s = 0;
 #pragma unroll 4
-      for (int a = 0; a < NPTF; ++a) s += pit[a * NPTC + b] * sRf[el * NPF + c * NPTF + a];
+      for (int a = 0; a < NPTF; ++a) s += sPt[a * NPTC + b] * sRf[el * NPF + c * NPTF + a];
       sT1[el * N1F * NPTC + c * NPTC + b] = s;
     }
     __syncthreads();
@@ -550,7 +582,7 @@ __global__ __launch_bounds__(256) void k_restrict_elem(int64_t n_elem, int L, in
       for (int cc = 0; cc < N1C; ++cc) {
         T s = 0;
 #pragma unroll
-        for (int c = 0; c < N1F; ++c) s += piz[c * N1C + cc] * t1[c];
+        for (int c = 0; c < N1F; ++c) s += sPz[c * N1C + cc] * t1[c];
         out[cc] = s;
       }
     }
@@ -706,8 +738,9 @@ __global__ __launch_bounds__(256) void k_finalize(const double* __restrict__ par
       scal[S_BETA] = sa / scal[S_DELTA];
       scal[S_DELTA] = sa;
     } else if (op == FIN_BETA_PR) {
+      // Polak-Ribiere: z.(r_new - r_old) = -alpha z.q, since r_new = r_old - alpha q
       scal[S_ZR] = sa;
-      scal[S_BETA] = (sa - sb) / scal[S_DELTA];
+      scal[S_BETA] = -scal[S_ALPHA] * sb / scal[S_DELTA];
       scal[S_DELTA] = sa;
     } else if (op == FIN_DELTA) {
       scal[S_DELTA] = sa;
@@ -920,19 +953,26 @@ void launch_p1_elem_mat(int64_t n_elem, const double* G, const double* Dref, dou
 }
 
 // val[k] = sum of the element-matrix entries listed for entry k, in list order
-__global__ __launch_bounds__(256) void k_csr_sum(int64_t nnz, const int32_t* __restrict__ cp,
-                                                 const int64_t* __restrict__ cl, const double* __restrict__ Ae,
-                                                 double* __restrict__ v64, float* __restrict__ v32) {
-  for (int64_t k = int64_t(blockIdx.x) * 256 + threadIdx.x; k < nnz; k += int64_t(gridDim.x) * 256) {
+// ELL slot (k, g) holds the k-th nonzero of row g (CSR position rp[g] + k), the
+// sum of its element entries in ascending order; slots past the row's end hold 0.
+__global__ __launch_bounds__(256) void k_ell_sum(int64_t n, int w, const int32_t* __restrict__ rp,
+                                                 const int32_t* __restrict__ cp, const int64_t* __restrict__ cl,
+                                                 const double* __restrict__ Ae, double* __restrict__ v64,
+                                                 float* __restrict__ v32) {
+  const int64_t total = n * w;
+  for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < total; i += int64_t(gridDim.x) * 256) {
+    const int64_t k = i / n, g = i - k * n;
+    const int64_t j = rp[g] + k;
     double s = 0.0;
-    for (int m = cp[k]; m < cp[k + 1]; ++m) s += Ae[cl[m]];
-    v64[k] = s;
-    v32[k] = float(s);
+    if (j < rp[g + 1])
+      for (int m = cp[j]; m < cp[j + 1]; ++m) s += Ae[cl[m]];
+    v64[i] = s;
+    v32[i] = float(s);
   }
 }
-void launch_csr_sum(int64_t nnz, const int32_t* cp, const int64_t* cl, const double* Ae, double* v64, float* v32,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_csr_sum, dim3(grid_for(nnz)), dim3(256), 0, st, nnz, cp, cl, Ae, v64, v32);
+void launch_ell_sum(int64_t n, int w, const int32_t* rp, const int32_t* cp, const int64_t* cl, const double* Ae,
+                    double* v64, float* v32, hipStream_t st) {
+  hipLaunchKernelGGL(k_ell_sum, dim3(grid_for(n * w)), dim3(256), 0, st, n, w, rp, cp, cl, Ae, v64, v32);
 }
 
 // Chebyshev start from x = 0: r = f, d = D^-1 f / theta, x = d
@@ -948,23 +988,26 @@ __global__ __launch_bounds__(256) void k_cheb_start(int64_t n, const T* __restri
     x[g] = dv;
   }
 }
-// One Chebyshev step on the assembled free-node matrix (rows without entries are
-// Dirichlet rows): r -= A d_old; d_new = c0 d_old + c1 D^-1 r; x += d_new.
+// One Chebyshev step on the assembled free-node matrix in ELL layout (slot
+// (k, g) at k n + g, so a wave reads each slot column with unit stride; padding
+// slots have column g and value 0; a Dirichlet row has column -1 in slot 0):
+// r -= A d_old; d_new = c0 d_old + c1 D^-1 r; x += d_new.
 // d is double-buffered because every row reads its neighbours' d_old.
 template <typename T>
-__global__ __launch_bounds__(256) void k_cheb_csr(int64_t n, const int32_t* __restrict__ rp,
-                                                  const int32_t* __restrict__ ci, const T* __restrict__ val,
-                                                  const T* __restrict__ dinv, const T* __restrict__ d_old,
-                                                  T* __restrict__ d_new, T* __restrict__ r, T* __restrict__ x,
-                                                  T c0, T c1) {
+__global__ __launch_bounds__(256) void k_cheb_ell(int64_t n, int w, const int32_t* __restrict__ ci,
+                                                  const T* __restrict__ val, const T* __restrict__ dinv,
+                                                  const T* __restrict__ d_old, T* __restrict__ d_new,
+                                                  T* __restrict__ r, T* __restrict__ x, T c0, T c1) {
   for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
-    const int j0 = rp[g], j1 = rp[g + 1];
-    if (j0 == j1) {
+    if (ci[g] < 0) {
       d_new[g] = T(0);
       continue;
     }
     T s = 0;
-    for (int j = j0; j < j1; ++j) s += val[j] * d_old[ci[j]];
+    for (int k = 0; k < w; ++k) {
+      const int64_t j = int64_t(k) * n + g;
+      s += val[j] * d_old[ci[j]];
+    }
     const T rn = r[g] - s;
     r[g] = rn;
     const T dn = c0 * d_old[g] + c1 * dinv[g] * rn;
@@ -977,14 +1020,14 @@ void launch_cheb_start(int64_t n, const T* f, const T* dinv, T* r, T* d, T* x, d
   hipLaunchKernelGGL((k_cheb_start<T>), dim3(grid_for(n)), dim3(256), 0, st, n, f, dinv, r, d, x, T(inv_theta));
 }
 template <typename T>
-void launch_cheb_csr(int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* dinv, const T* d_old,
-                     T* d_new, T* r, T* x, double c0, double c1, hipStream_t st) {
-  hipLaunchKernelGGL((k_cheb_csr<T>), dim3(grid_for(n)), dim3(256), 0, st, n, rp, ci, val, dinv, d_old, d_new, r, x,
+void launch_cheb_ell(int64_t n, int w, const int32_t* ci, const T* val, const T* dinv, const T* d_old, T* d_new,
+                     T* r, T* x, double c0, double c1, hipStream_t st) {
+  hipLaunchKernelGGL((k_cheb_ell<T>), dim3(grid_for(n)), dim3(256), 0, st, n, w, ci, val, dinv, d_old, d_new, r, x,
                      T(c0), T(c1));
 }
 template void launch_cheb_start<double>(int64_t, const double*, const double*, double*, double*, double*, double, hipStream_t);
 template void launch_cheb_start<float>(int64_t, const float*, const float*, float*, float*, float*, double, hipStream_t);
-template void launch_cheb_csr<double>(int64_t, const int32_t*, const int32_t*, const double*, const double*, const double*, double*, double*, double*, double, double, hipStream_t);
-template void launch_cheb_csr<float>(int64_t, const int32_t*, const int32_t*, const float*, const float*, const float*, float*, float*, float*, double, double, hipStream_t);
+template void launch_cheb_ell<double>(int64_t, int, const int32_t*, const double*, const double*, const double*, double*, double*, double*, double, double, hipStream_t);
+template void launch_cheb_ell<float>(int64_t, int, const int32_t*, const float*, const float*, const float*, float*, float*, float*, double, double, hipStream_t);
 
 }  // namespace pmg

@@ -66,9 +66,15 @@ void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a
                      T* a3, double omega, double c1, double* partial, hipStream_t st);
 
 // ---- geometric factors at level cubature from the fine isoparametric map
+// G64/G32/G16: G[e][m][k*nqt+q] (any may be null).  geo64/geo32 (may be null):
+// the column factors geo[t][q][0..7] of the sigma-transformed prism, from
+// which G at vertical Gauss point k of layer l follows as
+//   G = zw_k (B0, B1, s B2, B3, s B4, s^2 B5 + B6),  s = (l + (1+zq_k)/2) / L
+// (slot 7 is zero).
 void launch_geom(const LevelView& fine, const LevelView& lvl, double depth, const double* xyt,
                  const double* eta, const double* gmats, const double* wq, const double* zq,
-                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st);
+                 const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st,
+                 double* geo64 = nullptr, float* geo32 = nullptr);
 
 // ---- diagonal of the element matrices (E-layout), FP64
 void launch_diag(const LevelView& lv, const double* mats, const double* G64, double* Y, hipStream_t st);
@@ -88,13 +94,15 @@ void launch_coarse_dense(int n, const int32_t* idx, const T* Ainv, const T* x, T
 
 // assembled P = 1 operator for the coarse Chebyshev solve
 void launch_p1_elem_mat(int64_t n_elem, const double* G, const double* Dref, double* Ae, hipStream_t st);
-void launch_csr_sum(int64_t nnz, const int32_t* cp, const int64_t* cl, const double* Ae, double* v64, float* v32,
-                    hipStream_t st);
+// ELL values (n rows, w slots, slot-major) of the CSR pattern rp whose nonzero j
+// sums the element entries Ae[cl[cp[j] .. cp[j+1])]
+void launch_ell_sum(int64_t n, int w, const int32_t* rp, const int32_t* cp, const int64_t* cl, const double* Ae,
+                    double* v64, float* v32, hipStream_t st);
 template <typename T>
 void launch_cheb_start(int64_t n, const T* f, const T* dinv, T* r, T* d, T* x, double inv_theta, hipStream_t st);
 template <typename T>
-void launch_cheb_csr(int64_t n, const int32_t* rp, const int32_t* ci, const T* val, const T* dinv, const T* d_old,
-                     T* d_new, T* r, T* x, double c0, double c1, hipStream_t st);
+void launch_cheb_ell(int64_t n, int w, const int32_t* ci, const T* val, const T* dinv, const T* d_old, T* d_new,
+                     T* r, T* x, double c0, double c1, hipStream_t st);
 
 // ---- vector kernels
 template <typename T> void launch_fill(T* x, T v, int64_t n, hipStream_t st);

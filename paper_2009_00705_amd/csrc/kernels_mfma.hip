@@ -185,6 +185,65 @@ __device__ __forceinline__ void load_rem(const TG* __restrict__ G, int64_t blk, 
       gv[m][r] = row < NQR ? T(gld_any(G, blk + m * mst + NTF * 256 + row * 16 + j)) : T(0);
   }
 }
+// Geometric factors of q tile t computed from the column factors (see
+// launch_geom): lane rows q = 16 t + row(g, r) of triangle tri; p = zw_k,
+// ps = zw_k s, ps2 = zw_k s^2 for the lane's layer.  Rows past the last q, and
+// lanes past the last element (tri < 0), get 0.
+__device__ __forceinline__ void load8(const double* p, double (&b)[8]) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const double2 v = reinterpret_cast<const double2*>(p)[i];
+    b[2 * i] = v.x;
+    b[2 * i + 1] = v.y;
+  }
+}
+__device__ __forceinline__ void load8(const float* p, float (&b)[8]) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const float4 v = reinterpret_cast<const float4*>(p)[i];
+    b[4 * i] = v.x;
+    b[4 * i + 1] = v.y;
+    b[4 * i + 2] = v.z;
+    b[4 * i + 3] = v.w;
+  }
+}
+template <typename T, int PT, int PZ, bool F64ROW>
+__device__ __forceinline__ void load_geo(const T* __restrict__ geo, int64_t tri, int t, int g, T p, T ps, T ps2,
+                                         T (&gv)[6][4]) {
+  using D = MD<PT, PZ>;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int q = 16 * t + row_of<F64ROW>(g, r);
+    T bq[8];
+    if (tri >= 0 && q < D::NQT) {
+      load8(geo + (tri * D::NQT + q) * 8, bq);
+    } else {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) bq[m] = T(0);
+    }
+    gv[0][r] = p * bq[0];
+    gv[1][r] = p * bq[1];
+    gv[2][r] = ps * bq[2];
+    gv[3][r] = p * bq[3];
+    gv[4][r] = ps * bq[4];
+    gv[5][r] = ps2 * bq[5] + p * bq[6];
+  }
+}
+// per-lane constants of load_geo for element e = 16 b + j at vertical Gauss point k
+template <typename T>
+__device__ __forceinline__ void geo_lane(int64_t e, int64_t n_elem, int L, T zw, T zh, int64_t& tri, T& p, T& ps,
+                                         T& ps2) {
+  tri = -1;
+  p = ps = ps2 = T(0);
+  if (e < n_elem) {
+    tri = e / L;
+    const T sg = (T(int(e - tri * L)) + zh) / T(L);
+    p = zw;
+    ps = zw * sg;
+    ps2 = ps * sg;
+  }
+}
+
 template <typename T, typename ACC>
 __device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds, ACC& db) {
 #pragma unroll
@@ -199,7 +258,9 @@ __device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds,
 // FP32 / FP64 flavours (K = 4).  GT: the reference tables are read through the
 // caches instead of LDS (FP64 at P = 8, whose tables and staging buffer do not
 // fit in the LDS together); one workgroup per CU then.
-template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW, bool GT = false>
+// GEO: G from the column factors (Gnat is then geo[t][q][8] of type T) instead
+// of the stored lane-native G.
+template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW, bool GT = false, bool GEO = false>
 __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : 4))) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
                                                          int64_t n_elem, int64_t n_batch,
                                                          const TG* __restrict__ Gnat, const T* __restrict__ tab2,
@@ -259,10 +320,14 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     for (int at = 0; at < NAT; ++at) { yr[at] = ACC{0, 0, 0, 0}; yt[at] = ACC{0, 0, 0, 0}; }
     const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
     constexpr int64_t MST = 16 * D::NQT;
+    int64_t tri;
+    T gp, gps, gps2;
+    if constexpr (GEO) geo_lane<T>(b * 16 + j, n_elem, L, vm.zw[k], vm.zh[k], tri, gp, gps, gps2);
     T ga[6][4];
 #pragma unroll 1
     for (int t = 0; t < D::NTF; ++t) {
-      load_full<T>(Gnat, blk, MST, t, lane, ga);
+      if constexpr (GEO) load_geo<T, PT, PZ, F64ROW>((const T*)Gnat, tri, t, g, gp, gps, gps2, ga);
+      else load_full<T>(Gnat, blk, MST, t, lane, ga);
       ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
@@ -284,7 +349,8 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     }
     if constexpr (D::NQR > 0) {
       constexpr int t = D::NTF;
-      load_rem<T, D::NTF, D::NQR, F64ROW>(Gnat, blk, MST, g, j, ga);
+      if constexpr (GEO) load_geo<T, PT, PZ, F64ROW>((const T*)Gnat, tri, D::NTF, g, gp, gps, gps2, ga);
+      else load_rem<T, D::NTF, D::NQR, F64ROW>(Gnat, blk, MST, g, j, ga);
       ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
@@ -423,24 +489,58 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
   }
 }
 
+// BF16 G of q tile t for lane (g, j), rows 4g+r (r = 0..3), packed two per word
+// (low half = even r): one 8-byte load per factor on full tiles; rows past the
+// last q of the remainder tile read as 0.
+template <int PT, int PZ>
+__device__ __forceinline__ void load_g_bf16(const bf16_t* __restrict__ Gnat, int64_t blk, int64_t mst, int t,
+                                            int lane, int g, int j, uint32_t (&gw)[6][2]) {
+  using D = MD<PT, PZ>;
+  if (t < D::NTF) {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      const uint2 v = *reinterpret_cast<const uint2*>(Gnat + blk + m * mst + t * 256 + lane * 4);
+      gw[m][0] = v.x;
+      gw[m][1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 6; ++m) {
+      uint32_t h[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * g + r;
+        h[r] = row < D::NQR ? uint32_t(Gnat[blk + m * mst + D::NTF * 256 + row * 16 + j]) : 0u;
+      }
+      gw[m][0] = h[0] | (h[1] << 16);
+      gw[m][1] = h[2] | (h[3] << 16);
+    }
+  }
+}
+
 // Split-BF16 products (FP32 accumulation): every operand x = x_hi + x_lo with
-// x_hi = bf16(x), x_lo = bf16(x - x_hi); a product keeps the three terms
-// a_hi b_hi + a_hi b_lo + a_lo b_hi (about 16 significant bits, against 8 for
-// one BF16 product), three BF16 MFMAs in place of one FP32 MFMA of four times
-// the cost per K.  Tables: hi and lo copies of the BF16-layout tables, both in
-// LDS (two workgroups per CU; reading the lo copies through the caches
-// instead, for three, was slower).  Measured at P = 6 this is slower than FP32
-// MFMA on the same BF16 G: the extra MFMAs and the hi/lo splits cost more
-// than the FP32 matrix-core time they replace.
+// x_hi = bf16(x), x_lo = bf16(x - x_hi).
+// LO: a product keeps the three terms a_hi b_hi + a_hi b_lo + a_lo b_hi (about
+//   16 significant bits, against 8 for one BF16 product), three BF16 MFMAs in
+//   place of one FP32 MFMA of four times the cost per K.  Tables: hi and lo
+//   copies of the BF16-layout tables, both in LDS.  Measured at P = 6 this is
+//   slower than FP32 MFMA on the same BF16 G: the extra MFMAs, the LDS of the
+//   lo tables and the hi/lo splits cost more than the matrix-core time saved.
+// !LO: the reference tables are rounded to BF16 once (a fixed, symmetric
+//   perturbation of the reference matrices, as G's rounding is of the
+//   geometry) and only the vectors are split: a_hi b_hi + a_hi b_lo, two BF16
+//   MFMAs, the LDS of the plain BF16 kernel.
 __device__ __forceinline__ void split_bf(float x, short& hi, short& lo) {
   hi = f2bf(x);
   lo = f2bf(x - __uint_as_float(uint32_t(uint16_t(hi)) << 16));
 }
 
-template <int PT, int PZ>
-__global__ __launch_bounds__(64 * (PZ + 1), 2) void k_ax_mfma_bf16x3(const int32_t* __restrict__ map2d, int L,
+// GEO: G in FP32 from the FP32 column factors (Gsrc = geo[t][q][8]) instead of
+// the stored lane-native BF16 G (Gsrc = Gnat).
+template <int PT, int PZ, bool LO, bool GEO = false>
+__global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_mfma_bf16x3(const int32_t* __restrict__ map2d, int L,
                                                                      int nz, int64_t n_elem, int64_t n_batch,
-                                                                     const bf16_t* __restrict__ Gnat,
+                                                                     const void* __restrict__ Gsrc,
                                                                      const s4_t* __restrict__ tab2,
                                                                      const s4_t* __restrict__ tab4,
                                                                      const s4_t* __restrict__ tab2lo,
@@ -452,18 +552,36 @@ __global__ __launch_bounds__(64 * (PZ + 1), 2) void k_ax_mfma_bf16x3(const int32
   constexpr int NTAB2 = 3 * NT2 * KS16 * 64, NTAB4 = 3 * NAT * NT2 * 64;
   constexpr int NTH = 64 * N1;
   __shared__ s4_t s2[NTAB2];
-  __shared__ s4_t s2l[NTAB2];
+  __shared__ s4_t s2l[LO ? NTAB2 : 1];
   __shared__ s4_t s4[NTAB4];
-  __shared__ s4_t s4l[NTAB4];
+  __shared__ s4_t s4l[LO ? NTAB4 : 1];
   __shared__ float sR[KS_LDS<PT, PZ>::R_WORDS];
   __shared__ float sV[2 * N1 * N1];
-  for (int i = threadIdx.x; i < NTAB2; i += NTH) { s2[i] = tab2[i]; s2l[i] = tab2lo[i]; }
-  for (int i = threadIdx.x; i < NTAB4; i += NTH) { s4[i] = tab4[i]; s4l[i] = tab4lo[i]; }
+  for (int i = threadIdx.x; i < NTAB2; i += NTH) {
+    s2[i] = tab2[i];
+    if constexpr (LO) s2l[i] = tab2lo[i];
+  }
+  for (int i = threadIdx.x; i < NTAB4; i += NTH) {
+    s4[i] = tab4[i];
+    if constexpr (LO) s4l[i] = tab4lo[i];
+  }
   for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
   const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
+  const bf16_t* __restrict__ Gnat = static_cast<const bf16_t*>(Gsrc);
+  const float* __restrict__ geo = static_cast<const float*>(Gsrc);
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();
+    // stored G: tile t as raw BF16 pairs, loaded one tile ahead (the first under
+    // the staging of u and stage 1): a tile's words are in flight during the
+    // previous tile's MFMAs
+    const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
+    constexpr int64_t mst = 16 * D::NQT;
+    uint32_t gw[6][2];
+    int64_t tri;
+    float gp, gps, gps2;
+    if constexpr (GEO) geo_lane<float>(b * 16 + j, n_elem, L, vm.zw[k], vm.zh[k], tri, gp, gps, gps2);
+    else load_g_bf16<PT, PZ>(Gnat, blk, mst, 0, lane, g, j, gw);
     stage_u<PT, PZ, float>(map2d, L, nz, n_elem, b, u, sR);
     __syncthreads();
     s4_t wh[KS16], wl[KS16], zh[KS16], zl[KS16];
@@ -495,22 +613,14 @@ __global__ __launch_bounds__(64 * (PZ + 1), 2) void k_ax_mfma_bf16x3(const int32
     for (int at = 0; at < NAT; ++at) { yr[at] = f4_t{0, 0, 0, 0}; yt[at] = f4_t{0, 0, 0, 0}; }
 #pragma unroll 1
     for (int t = 0; t < NT2; ++t) {
-      float gv[6][4];
-      const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
-      const int64_t mst = 16 * D::NQT;
-      if (t < D::NTF) {
-#pragma unroll
-        for (int m = 0; m < 6; ++m)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) gv[m][r] = gld<bf16_t>(Gnat, blk + m * mst + t * 256 + lane * 4 + r);
+      uint32_t gc[6][2];
+      float gg[6][4];
+      if constexpr (GEO) {
+        load_geo<float, PT, PZ, false>(geo, tri, t, g, gp, gps, gps2, gg);
       } else {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 4 * g + r;
-#pragma unroll
-          for (int m = 0; m < 6; ++m)
-            gv[m][r] = row < D::NQR ? gld<bf16_t>(Gnat, blk + m * mst + D::NTF * 256 + row * 16 + j) : 0.f;
-        }
+        for (int m = 0; m < 6; ++m) { gc[m][0] = gw[m][0]; gc[m][1] = gw[m][1]; }
+        if (t + 1 < NT2) load_g_bf16<PT, PZ>(Gnat, blk, mst, t + 1, lane, g, j, gw);
       }
       f4_t dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
 #pragma unroll
@@ -523,14 +633,26 @@ __global__ __launch_bounds__(64 * (PZ + 1), 2) void k_ax_mfma_bf16x3(const int32
         dr = mfma16(s2[i0], wl[s], dr);
         ds = mfma16(s2[i1], wl[s], ds);
         db = mfma16(s2[i2], zl[s], db);
-        dr = mfma16(s2l[i0], wh[s], dr);
-        ds = mfma16(s2l[i1], wh[s], ds);
-        db = mfma16(s2l[i2], zh[s], db);
+        if constexpr (LO) {
+          dr = mfma16(s2l[i0], wh[s], dr);
+          ds = mfma16(s2l[i1], wh[s], ds);
+          db = mfma16(s2l[i2], zh[s], db);
+        }
       }
       s4_t rh, rl, sh, sl, th, tl;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float ur = dr[r], us = ds[r], ut = db[r];
+        float gv[6][4];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          if constexpr (GEO) {
+            gv[m][r] = gg[m][r];
+          } else {
+            const uint32_t wv = gc[m][r >> 1];
+            gv[m][r] = __uint_as_float((r & 1) ? (wv & 0xFFFF0000u) : (wv << 16));
+          }
+        }
         short h, l;
         split_bf(gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut, h, l);
         rh[r] = h;
@@ -552,9 +674,11 @@ __global__ __launch_bounds__(64 * (PZ + 1), 2) void k_ax_mfma_bf16x3(const int32
         yr[at] = mfma16(s4[i0], rl, yr[at]);
         yr[at] = mfma16(s4[i1], sl, yr[at]);
         yt[at] = mfma16(s4[i2], tl, yt[at]);
-        yr[at] = mfma16(s4l[i0], rh, yr[at]);
-        yr[at] = mfma16(s4l[i1], sh, yr[at]);
-        yt[at] = mfma16(s4l[i2], th, yt[at]);
+        if constexpr (LO) {
+          yr[at] = mfma16(s4l[i0], rh, yr[at]);
+          yr[at] = mfma16(s4l[i1], sh, yr[at]);
+          yt[at] = mfma16(s4l[i2], th, yt[at]);
+        }
       }
     }
 #pragma unroll
@@ -646,10 +770,10 @@ static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, 
                        (bf16_t*)out);
 }
 
-// orders with MFMA kernels: (3,3), (6,6), (3,6) [the in-plane-coarsened level of
-// P = 6] in every flavour, (8,8) in every flavour but split-BF16 (its FP64 tables
-// are read through the caches)
-#define PMG_MFMA_ORDERS(X) X(3, 3) X(6, 6) X(3, 6) X(8, 8)
+// orders with MFMA kernels: (3,3), (6,6), (3,6), (4,8), (2,8) [the in-plane-
+// coarsened levels of P = 6 and P = 8] in every flavour, (8,8) in every flavour
+// but split-BF16 (its FP64 tables are read through the caches)
+#define PMG_MFMA_ORDERS(X) X(3, 3) X(6, 6) X(3, 6) X(8, 8) X(4, 8) X(2, 8)
 
 void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
 #define PMG_REL(PTV, PZV) \
@@ -658,57 +782,77 @@ void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out,
 #undef PMG_REL
 }
 
+// one launch of kernel kern over the batches, its resident-grid size cached per
+// instantiation (KEY)
+template <typename KEY, typename K, typename... A>
+static void launch_batches(K kern, int NT, int64_t need, hipStream_t st, A... args) {
+  static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
+  hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, args...);
+}
+template <int PT, int PZ, int FL, bool GEO> struct KeyOf {};
+
 template <int PT, int PZ>
 static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
-                      const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo = nullptr,
-                      const void* tab4lo = nullptr) {
+                      const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo,
+                      const void* tab4lo, const void* geo) {
   const int64_t nb = (lv.n_elem + 15) / 16;
   const int64_t need = ((nb + 7) / 8) * 8;
   constexpr int NT = 64 * (PZ + 1);
+  const VertMats<double>& v64 = *(const VertMats<double>*)vmats;
+  const VertMats<float>& v32 = *(const VertMats<float>*)vmats;
+#define PMG_ARGS(TG, TT, VM) lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb, (const TG*)G, (const TT*)tab2, (const TT*)tab4, \
+    VM, (const TT*)u, (TT*)Y
   if (flavour == MF_F64) {
-    {
-      auto kern = k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8>;
-      static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
-      hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
-                         lv.n_elem, nb, (const double*)Gnat, (const double*)tab2, (const double*)tab4,
-                         *(const VertMats<double>*)vmats, (const double*)u, (double*)Y);
-    }
+    const void* G = geo ? geo : Gnat;
+    if (geo)
+      launch_batches<KeyOf<PT, PZ, MF_F64, true>>(k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8, true>, NT,
+                                                  need, st, PMG_ARGS(double, double, v64));
+    else
+      launch_batches<KeyOf<PT, PZ, MF_F64, false>>(k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8>, NT,
+                                                   need, st, PMG_ARGS(double, double, v64));
   } else if (flavour == MF_F32) {
-    auto kern = k_ax_mfma4<PT, PZ, float, float, f4_t, false>;
-    static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
-    hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
-                       lv.n_elem, nb, (const float*)Gnat, (const float*)tab2, (const float*)tab4,
-                       *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
+    const void* G = geo ? geo : Gnat;
+    if (geo)
+      launch_batches<KeyOf<PT, PZ, MF_F32, true>>(k_ax_mfma4<PT, PZ, float, float, f4_t, false, false, true>, NT,
+                                                  need, st, PMG_ARGS(float, float, v32));
+    else
+      launch_batches<KeyOf<PT, PZ, MF_F32, false>>(k_ax_mfma4<PT, PZ, float, float, f4_t, false>, NT, need, st,
+                                                   PMG_ARGS(float, float, v32));
   } else if (flavour == MF_F32G16) {
-    auto kern = k_ax_mfma4<PT, PZ, float, bf16_t, f4_t, false>;
-    static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
-    hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
-                       lv.n_elem, nb, (const bf16_t*)Gnat, (const float*)tab2, (const float*)tab4,
-                       *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
-  } else if (flavour == MF_BF16X3) {
-    if constexpr (PT != 8) {
-      auto kern = k_ax_mfma_bf16x3<PT, PZ>;
-      static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
-      hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
-                         lv.n_elem, nb, (const bf16_t*)Gnat, (const s4_t*)tab2, (const s4_t*)tab4,
-                         (const s4_t*)tab2lo, (const s4_t*)tab4lo, *(const VertMats<float>*)vmats,
-                         (const float*)u, (float*)Y);
+    const void* G = Gnat;
+    launch_batches<KeyOf<PT, PZ, MF_F32G16, false>>(k_ax_mfma4<PT, PZ, float, bf16_t, f4_t, false>, NT, need, st,
+                                                    PMG_ARGS(bf16_t, float, v32));
+  } else if (flavour == MF_BF16X3 || flavour == MF_BF16X2) {
+    if constexpr (PT == 6) {
+      const void* G = geo ? geo : Gnat;
+      const void* lo2 = flavour == MF_BF16X3 ? tab2lo : nullptr;
+      const void* lo4 = flavour == MF_BF16X3 ? tab4lo : nullptr;
+#define PMG_X(LO, GE)                                                                                         \
+  launch_batches<KeyOf<PT, PZ, LO ? MF_BF16X3 : MF_BF16X2, GE>>(                                              \
+      k_ax_mfma_bf16x3<PT, PZ, LO, GE>, NT, need, st, lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb, G,           \
+      (const s4_t*)tab2, (const s4_t*)tab4, (const s4_t*)lo2, (const s4_t*)lo4, v32, (const float*)u, (float*)Y)
+      if (flavour == MF_BF16X3) {
+        if (geo) PMG_X(true, true); else PMG_X(true, false);
+      } else {
+        if (geo) PMG_X(false, true); else PMG_X(false, false);
+      }
+#undef PMG_X
     }
   } else {
-    auto kern = k_ax_mfma_bf16<PT, PZ, bf16_t>;
-    static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
-    hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, lv.map2d, lv.L, int(lv.nz),
-                       lv.n_elem, nb, (const bf16_t*)Gnat, (const s4_t*)tab2, (const s4_t*)tab4,
-                       *(const VertMats<float>*)vmats, (const float*)u, (float*)Y);
+    launch_batches<KeyOf<PT, PZ, MF_BF16, false>>(k_ax_mfma_bf16<PT, PZ, bf16_t>, NT, need, st, lv.map2d, lv.L,
+                                                  int(lv.nz), lv.n_elem, nb, (const bf16_t*)Gnat,
+                                                  (const s4_t*)tab2, (const s4_t*)tab4, v32, (const float*)u,
+                                                  (float*)Y);
   }
+#undef PMG_ARGS
 }
 
 void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                     const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo,
-                    const void* tab4lo) {
+                    const void* tab4lo, const void* geo) {
 #define PMG_AXM(PTV, PZV)                                                                                      \
   if (lv.P == PTV && lv.PZ == PZV)                                                                             \
-    return ax_mfma_p<PTV, PZV>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st, tab2lo, tab4lo);
+    return ax_mfma_p<PTV, PZV>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st, tab2lo, tab4lo, geo);
   PMG_MFMA_ORDERS(PMG_AXM)
 #undef PMG_AXM
 }

@@ -10,13 +10,16 @@ namespace pmg {
 
 // MF_F32G16: FP32 MFMA arithmetic reading the BF16 lane-native copy of G;
 // MF_BF16X3: split-BF16 products (three BF16 MFMAs each) on the BF16 copy of G
-// and the hi / lo BF16 tables
-enum MfmaFlavour { MF_F64 = 0, MF_F32 = 1, MF_BF16 = 2, MF_F32G16 = 3, MF_BF16X3 = 4 };
+// and the hi / lo BF16 tables; MF_BF16X2: split vectors on the BF16 tables (two)
+enum MfmaFlavour { MF_F64 = 0, MF_F32 = 1, MF_BF16 = 2, MF_F32G16 = 3, MF_BF16X3 = 4, MF_BF16X2 = 5 };
 
-// vertical interpolation/derivative matrices at the Gauss points, passed by value
+// vertical interpolation/derivative matrices at the Gauss points, and the Gauss
+// weights zw and positions zh = (1 + zq) / 2 in [0, 1], passed by value
 template <typename T> struct VertMats {
   T Bz[81];
   T Dz[81];
+  T zw[9];
+  T zh[9];
 };
 
 template <typename TO> __device__ __forceinline__ TO cvt_out(double v);
@@ -33,14 +36,21 @@ __device__ __forceinline__ float gld_any(const bf16_t* p, int64_t i) { return __
 
 // (triangle, vertical) orders with an MFMA kernel for a flavour
 inline bool mfma_available(int PT, int PZ, int flavour) {
-  if ((PT == 3 && PZ == 3) || (PT == 6 && PZ == 6) || (PT == 3 && PZ == 6)) return true;
-  if (PT == 8 && PZ == 8) return flavour != MF_BF16X3;  // LDS
-  return false;
+  const bool order = (PT == 3 && PZ == 3) || (PT == 6 && PZ == 6) || (PT == 3 && PZ == 6) ||
+                     (PT == 4 && PZ == 8) || (PT == 2 && PZ == 8) || (PT == 8 && PZ == 8);
+  // split-BF16 kernels at in-plane order 6 only: at lower orders the K = 16 steps
+  // pad the few triangle nodes and FP32 MFMA is faster; at 8 the tables do not fit
+  if (flavour == MF_BF16X3 || flavour == MF_BF16X2) return order && PT == 6;
+  return order;
 }
 void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st);
-// tab2lo / tab4lo: the lo tables of MF_BF16X3 (unused by the other flavours)
+// tab2lo / tab4lo: the lo tables of MF_BF16X3 (unused by the other flavours).
+// geo (optional): column factors of the level (FP64 for MF_F64, FP32 for MF_F32
+// and the split-BF16 flavours; ignored by MF_BF16 and MF_F32G16, which read
+// their stored BF16 G), from which the kernel computes G in place of reading
+// Gnat.
 void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                     const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo = nullptr,
-                    const void* tab4lo = nullptr);
+                    const void* tab4lo = nullptr, const void* geo = nullptr);
 
 }  // namespace pmg

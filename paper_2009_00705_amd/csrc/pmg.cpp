@@ -101,6 +101,9 @@ struct Level {
   // lo parts of the BF16 tables (split-BF16 products, MF_BF16X3)
   void *tab2lo = nullptr, *tab4lo = nullptr;
   bool mfx3 = false;
+  // column factors geo[t][q][8] of the MFMA operators (PMG_GEOM_COLUMN)
+  double* geo64 = nullptr;
+  float* geo32 = nullptr;
   VertMats<double> vm64{};
   VertMats<float> vm32{};
   // overlapping Schwarz smoother: host plan, device view, local inverses
@@ -172,13 +175,15 @@ struct pmg_ctx {
   float* cinv32 = nullptr;
   double* ctmp64 = nullptr;
   float* ctmp32 = nullptr;
-  // assembled free-node P = 1 matrix (coarse Chebyshev): CSR pattern, the element
-  // entries summed into each nonzero, values per precision, second d buffer
-  int64_t csr_nnz = 0;
-  int32_t *csr_rp = nullptr, *csr_ci = nullptr, *csr_cp = nullptr;
+  // assembled free-node P = 1 matrix (coarse Chebyshev): CSR pattern and the
+  // element entries summed into each nonzero; the ELL copy (ell_w slots per row)
+  // the Chebyshev steps read, with values per precision; second d buffer
+  int32_t *csr_rp = nullptr, *csr_cp = nullptr;
   int64_t* csr_cl = nullptr;
-  double* csr_v64 = nullptr;
-  float* csr_v32 = nullptr;
+  int ell_w = 0;
+  int32_t* ell_ci = nullptr;
+  double* ell_v64 = nullptr;
+  float* ell_v32 = nullptr;
   double* p1_dref = nullptr;
   double* cd64 = nullptr;
   float* cd32 = nullptr;
@@ -187,12 +192,13 @@ struct pmg_ctx {
   bool coarse_exact = true;
   // solve work (finest level)
   double *s_phiD = nullptr, *s_f = nullptr, *s_u = nullptr, *s_r = nullptr, *s_p = nullptr, *s_q = nullptr,
-         *s_z = nullptr, *s_rold = nullptr, *s_y = nullptr;
+         *s_z = nullptr, *s_y = nullptr;
   float *s_r32 = nullptr, *s_z32 = nullptr;
   float* feat_cst = nullptr; // [n1][4] constant features of the coarsest nodes
   int lowp = pmg::G_F32;      // G storage of the float V-cycle
   bool bf16_ops = false;      // BF16 MFMA operands (PMG_MIXED_BF16) rather than FP32 arithmetic
   bool bf16x3 = false;        // split-BF16 MFMA products (PMG_MIXED_BF16X3)
+  bool bf16x2 = false;        // split vectors on BF16 tables (PMG_MIXED_BF16X2)
   int n_vcycles = 0, n_fine_applies = 0;
   // free-surface time stepping: nodal triangle derivatives, top-node column
   // derivative, stage buffers ([eta | phi~] pairs), gradients and w~
@@ -412,6 +418,12 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
     L.vm32.Bz[i] = float(re.Bz.v[i]);
     L.vm32.Dz[i] = float(re.Dz.v[i]);
   }
+  for (int k = 0; k < re.n1; ++k) {
+    L.vm64.zw[k] = re.zw[k];
+    L.vm64.zh[k] = 0.5 * (1.0 + re.zq[k]);
+    L.vm32.zw[k] = float(L.vm64.zw[k]);
+    L.vm32.zh[k] = float(L.vm64.zh[k]);
+  }
   const int64_t nb = (L.num.n_elem + 15) / 16;
   const size_t ng = size_t(nb) * 16 * 6 * re.nq;
   for (int f = 0; f < 3; ++f) {
@@ -438,6 +450,11 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
       L.gnat[f] = c->A<bf16_t>(ng);
     }
     L.mf[f] = true;
+  }
+  if (c->opt.geometry == PMG_GEOM_COLUMN && (L.mf[MF_F64] || L.mf[MF_F32])) {
+    const size_t n = size_t(c->mesh.nt) * re.nq_tri * 8;
+    L.geo64 = c->A<double>(n);
+    L.geo32 = c->A<float>(n);
   }
 }
 
@@ -546,7 +563,6 @@ static void upload_levels(pmg_ctx* c) {
   c->s_p = c->A<double>(N);
   c->s_q = c->A<double>(N);
   c->s_z = c->A<double>(N);
-  c->s_rold = c->A<double>(N);
   c->s_y = c->A<double>(N);
   c->s_r32 = c->A<float>(N);
   c->s_z32 = c->A<float>(N);
@@ -557,10 +573,13 @@ static void upload_levels(pmg_ctx* c) {
 // ---------------------------------------------------------------------------
 // precision of the float V-cycle: G storage and MFMA operand type
 static void set_lowp(pmg_ctx* c, int precision) {
-  c->lowp = (precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G || precision == PMG_MIXED_BF16X3) ? G_BF16
-                                                                                                           : G_F32;
+  c->lowp = (precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G || precision == PMG_MIXED_BF16X3 ||
+             precision == PMG_MIXED_BF16X2)
+                ? G_BF16
+                : G_F32;
   c->bf16_ops = precision == PMG_MIXED_BF16;
   c->bf16x3 = precision == PMG_MIXED_BF16X3;
+  c->bf16x2 = precision == PMG_MIXED_BF16X2;
 }
 
 template <typename T> static const void* gptr(pmg_ctx* c, Level& L, int& gstore);
@@ -579,17 +598,28 @@ static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
   const int f = sizeof(T) == 8 ? MF_F64 : (gs == G_BF16 ? MF_BF16 : MF_F32);
   if (L.mf[f]) {
     const void* vm = sizeof(T) == 8 ? (const void*)&L.vm64 : (const void*)&L.vm32;
+    // column factors in the precision of the kernel's arithmetic (not for BF16 operands)
+    const bool col = c->opt.geometry == PMG_GEOM_COLUMN && L.geo64;
+    const void* geo = !col ? nullptr : (sizeof(T) == 8 ? (const void*)L.geo64 : (const void*)L.geo32);
     if (f == MF_BF16 && c->bf16x3 && L.mfx3) {
       launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X3, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
-                     L.tab2lo, L.tab4lo);
+                     L.tab2lo, L.tab4lo, geo);
+      return;
+    }
+    if (f == MF_BF16 && c->bf16x2 && mfma_available(L.P, L.PZ, MF_BF16X2)) {
+      launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X2, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
+                     nullptr, nullptr, geo);
       return;
     }
     if (f == MF_BF16 && !c->bf16_ops && L.mf[MF_F32]) {
-      // FP32 arithmetic on the BF16 copy of G (FP32 tables)
+      // FP32 arithmetic on the stored BF16 copy of G (FP32 tables); at in-plane
+      // order 3 this is faster than forming G from the column factors, whose
+      // kernel holds more registers
       launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_F32G16, L.tab2[MF_F32], L.tab4[MF_F32], vm, x, c->Y, st);
       return;
     }
-    launch_ax_mfma(L.view, L.gnat[f], f, L.tab2[f], L.tab4[f], vm, x, c->Y, st);
+    launch_ax_mfma(L.view, L.gnat[f], f, L.tab2[f], L.tab4[f], vm, x, c->Y, st, nullptr, nullptr,
+                   f == MF_BF16 ? nullptr : geo);
     return;
   }
   launch_ax<T>(L.view, L.mats<T>(), G, gs, x, reinterpret_cast<T*>(c->Y), st);
@@ -699,9 +729,9 @@ template <> float* ctmp<float>(pmg_ctx* c) { return c->ctmp32; }
 template <typename T> T* cdbuf(pmg_ctx* c);
 template <> double* cdbuf<double>(pmg_ctx* c) { return c->cd64; }
 template <> float* cdbuf<float>(pmg_ctx* c) { return c->cd32; }
-template <typename T> const T* csr_val(pmg_ctx* c);
-template <> const double* csr_val<double>(pmg_ctx* c) { return c->csr_v64; }
-template <> const float* csr_val<float>(pmg_ctx* c) { return c->csr_v32; }
+template <typename T> const T* ell_val(pmg_ctx* c);
+template <> const double* ell_val<double>(pmg_ctx* c) { return c->ell_v64; }
+template <> const float* ell_val<float>(pmg_ctx* c) { return c->ell_v32; }
 
 template <typename T>
 static void coarse_solve(pmg_ctx* c, const T* f, T* u, hipStream_t st) {
@@ -724,7 +754,7 @@ static void coarse_solve(pmg_ctx* c, const T* f, T* u, hipStream_t st) {
   for (int j = 1; j < k; ++j) {
     const double rho_new = 1.0 / (2.0 * sigma - rho);
     // r -= A d; d' = rho_new rho d + 2 rho_new/delta D^-1 r; x += d' (one fused kernel)
-    launch_cheb_csr<T>(N, c->csr_rp, c->csr_ci, csr_val<T>(c), L.dinv<T>(), d, d2, r, u, rho_new * rho,
+    launch_cheb_ell<T>(N, c->ell_w, c->ell_ci, ell_val<T>(c), L.dinv<T>(), d, d2, r, u, rho_new * rho,
                        2.0 * rho_new / delta, st);
     std::swap(d, d2);
     rho = rho_new;
@@ -946,15 +976,25 @@ static void coarse_csr_pattern(pmg_ctx* c) {
     rp[g + 1] = int32_t(ci.size());
   }
   if (cl.size() > size_t(INT32_MAX)) throw Error(PMG_EINVAL, "coarse matrix too large");
-  c->csr_nnz = int64_t(ci.size());
+  // ELL columns: slot-major, padding slots point at the row itself, Dirichlet rows
+  // carry -1 in slot 0
+  int w = 1;
+  for (int64_t g = 0; g < N; ++g) w = std::max(w, rp[g + 1] - rp[g]);
+  std::vector<int32_t> eci(size_t(w) * N);
+  for (int64_t g = 0; g < N; ++g) {
+    const int len = rp[g + 1] - rp[g];
+    for (int k = 0; k < w; ++k) eci[size_t(k) * N + g] = k < len ? ci[rp[g] + k] : int32_t(g);
+    if (len == 0) eci[g] = -1;
+  }
+  c->ell_w = w;
   c->csr_rp = c->A<int32_t>(N + 1);
-  c->csr_ci = c->A<int32_t>(ci.size());
   c->csr_cp = c->A<int32_t>(cp.size());
   c->csr_cl = c->A<int64_t>(cl.size());
-  c->csr_v64 = c->A<double>(ci.size());
-  c->csr_v32 = c->A<float>(ci.size());
+  c->ell_ci = c->A<int32_t>(eci.size());
+  c->ell_v64 = c->A<double>(eci.size());
+  c->ell_v32 = c->A<float>(eci.size());
   HIPCHK(hipMemcpy(c->csr_rp, rp.data(), rp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->csr_ci, ci.data(), ci.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->ell_ci, eci.data(), eci.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->csr_cp, cp.data(), cp.size() * sizeof(int32_t), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->csr_cl, cl.data(), cl.size() * sizeof(int64_t), hipMemcpyHostToDevice));
   std::vector<double> Dp(size_t(3) * nq * np);
@@ -1164,7 +1204,7 @@ static int level_geom(pmg_ctx* c, int i, const double* eta, bool lowp, int flavo
   Level& L = c->lv[i];
   HIPCHK(hipMemsetAsync(c->bad, 0, sizeof(int), st));
   launch_geom(F.view, L.view, c->mesh.depth, c->xyt, eta, L.gmats, L.wq, L.zq, L.zw, L.G64, lowp ? L.G32 : nullptr,
-              lowp ? L.G16 : nullptr, c->bad, st);
+              lowp ? L.G16 : nullptr, c->bad, st, L.geo64, lowp ? L.geo32 : nullptr);
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
@@ -1215,7 +1255,7 @@ static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st) {
   for (int i = 0; i < c->nl; ++i) {
     Level& L = c->lv[i];
     launch_geom(F.view, L.view, c->mesh.depth, c->xyt, eta, L.gmats, L.wq, L.zq, L.zw, L.G64, L.G32, L.G16,
-                c->bad, st);
+                c->bad, st, L.geo64, L.geo32);
   }
   int bad = 0;
   HIPCHK(hipMemcpyAsync(&bad, c->bad, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -1226,7 +1266,7 @@ static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st) {
     for (int i = 0; i < c->nl; ++i) {
       Level& L = c->lv[i];
       launch_geom(F.view, L.view, c->mesh.depth, c->xyt, c->eta, L.gmats, L.wq, L.zq, L.zw, L.G64, L.G32,
-                  L.G16, c->bad, st);
+                  L.G16, c->bad, st, L.geo64, L.geo32);
     }
     HIPCHK(hipStreamSynchronize(st));
     throw Error(PMG_EMESH, "non-positive Jacobian for the given surface (eta <= -depth?)");
@@ -1277,7 +1317,7 @@ static void coarse_setup(pmg_ctx* c, hipStream_t st) {
     }
     if (!c->csr_rp) coarse_csr_pattern(c);
     launch_p1_elem_mat(C.num.n_elem, C.G64, c->p1_dref, c->Y, st);
-    launch_csr_sum(c->csr_nnz, c->csr_cp, c->csr_cl, c->Y, c->csr_v64, c->csr_v32, st);
+    launch_ell_sum(C.num.n_dof, c->ell_w, c->csr_rp, c->csr_cp, c->csr_cl, c->Y, c->ell_v64, c->ell_v32, st);
     if (c->opt.cheb_lmax > 0 && c->opt.cheb_lmin > 0) {
       c->cheb_lmax = c->opt.cheb_lmax;
       c->cheb_lmin = c->opt.cheb_lmin;
@@ -1597,7 +1637,6 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     while (it < imax && hist_r.back() > tol) {
       fine_apply(c, c->s_p, c->s_q, c->s_p, st);
       launch_finalize(c->partial, c->scal, 0, FIN_ALPHA, st);
-      if (kry == PMG_FPCG) launch_copy<double>(c->s_r, c->s_rold, N, st);
       launch_cg_update(c->s_u, c->s_r, c->s_p, c->s_q, c->scal, c->partial, N, st);
       launch_finalize(c->partial, c->scal, S_RR, FIN_SET, st);
       HIPCHK(hipMemcpyAsync(c->scal_h, c->scal, N_SCAL * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -1613,7 +1652,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
         launch_dot<double>(c->s_z, c->s_r, N, c->partial, st);
         launch_finalize(c->partial, c->scal, 0, FIN_BETA_FR, st);
       } else {
-        launch_dot2(c->s_z, c->s_r, c->s_rold, N, c->partial, st);
+        launch_dot2(c->s_z, c->s_r, c->s_q, N, c->partial, st);
         launch_finalize(c->partial, c->scal, 0, FIN_BETA_PR, st);
       }
       launch_cg_dir(c->s_p, c->s_z, c->scal, N, st);
@@ -1780,6 +1819,7 @@ void pmg_options_default(pmg_options* o) {
   o->coarsening = PMG_COARSEN_BOTH;
   o->overlap = 1;
   o->seed = 0;
+  o->geometry = PMG_GEOM_COLUMN;
 }
 
 int pmg_abi_version(void) { return PMG_ABI_VERSION; }
@@ -1795,12 +1835,13 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (m->nv < 3 || m->nt < 1 || !m->xy || !m->tri || m->n_layers < 1 || !(m->depth > 0))
       throw Error(PMG_EINVAL, "bad mesh sizes");
     if (o->nu1 < 0 || o->nu2 < 0) throw Error(PMG_EINVAL, "negative sweep count");
-    if (o->precision < 0 || o->precision > 4) throw Error(PMG_EINVAL, "bad precision");
+    if (o->precision < 0 || o->precision > 5) throw Error(PMG_EINVAL, "bad precision");
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");
     if (o->smoother < 0 || o->smoother > 2) throw Error(PMG_EINVAL, "bad smoother");
     if (o->smoother == PMG_SMOOTH_SCHWARZ && o->overlap < -1) throw Error(PMG_EINVAL, "bad Schwarz overlap");
     if (o->schwarz_store < 0 || o->schwarz_store > 7) throw Error(PMG_EINVAL, "bad schwarz_store mask");
     if (o->coarsening < 0 || o->coarsening > 1) throw Error(PMG_EINVAL, "bad coarsening");
+    if (o->geometry < 0 || o->geometry > 1) throw Error(PMG_EINVAL, "bad geometry mode");
     if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
       throw Error(PMG_EINVAL, "smooth_ratio must exceed 1");
     c = new pmg_ctx();
@@ -1943,7 +1984,7 @@ int pmg_apply(pmg_ctx* c, int level, int precision, int flags, const void* x, vo
       ax_elem<double>(c, level, xin, st);
       assemble<double>(c, level, (flags & 1) ? OP_STORE : OP_RAW, (double*)y, nullptr, nullptr, nullptr, 0, 0, st);
     } else if (precision == PMG_MIXED_FP32 || precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G ||
-               precision == PMG_MIXED_BF16X3) {
+               precision == PMG_MIXED_BF16X3 || precision == PMG_MIXED_BF16X2) {
       set_lowp(c, precision);
       const float* xin = (const float*)x;
       if (flags & 1) { launch_mask<float>(L.view, xin, L.r32, st); xin = L.r32; }
@@ -2301,7 +2342,7 @@ int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* 
 }
 
 int pmg_set_solver(pmg_ctx* c, int precision, int krylov) {
-  if (!c || precision < 0 || precision > 4 || krylov < 0 || krylov > 3) return PMG_EINVAL;
+  if (!c || precision < 0 || precision > 5 || krylov < 0 || krylov > 3) return PMG_EINVAL;
   c->opt.precision = precision;
   c->opt.krylov = krylov;
   return PMG_OK;
@@ -2333,7 +2374,7 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
           break;
         case PMG_K_GEOMETRY:
           launch_geom(c->lv[0].view, L.view, c->mesh.depth, c->xyt, c->eta, L.gmats, L.wq, L.zq, L.zw, L.G64,
-                      L.G32, L.G16, c->bad, st);
+                      L.G32, L.G16, c->bad, st, L.geo64, L.geo32);
           break;
         case PMG_K_RESTRICT:
           if (f64) launch_restrict_elem<double>(L.view, c->lv[level + 1].view, L.pit64, L.piz64, L.r64, c->Y, st);

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmg.so")
 
 PMG_OK, PMG_NOT_CONVERGED, PMG_FALLBACK_USED = 0, 1, 2
-PMG_FP64, PMG_MIXED_FP32, PMG_MIXED_BF16, PMG_MIXED_BF16G, PMG_MIXED_BF16X3 = 0, 1, 2, 3, 4
+PMG_FP64, PMG_MIXED_FP32, PMG_MIXED_BF16, PMG_MIXED_BF16G, PMG_MIXED_BF16X3, PMG_MIXED_BF16X2 = 0, 1, 2, 3, 4, 5
 PMG_PCG, PMG_FPCG, PMG_PDC, PMG_MG = 0, 1, 2, 3
 PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED, PMG_GUESS_EXTRAP, PMG_GUESS_EXTRAP3, PMG_GUESS_LEARNED3 = \
     0, 1, 2, 3, 4, 5
@@ -28,7 +28,7 @@ STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FALLBACK_USED", -1: "EINVAL", -2: "EN
           -3: "EDEVICE", -4: "EBREAKDOWN", -5: "ENONFINITE", -6: "EMESH", -7: "ESTATE"}
 STATUS_CODES = {v: k for k, v in STATUS.items()}
 PRECISIONS = {"fp64": PMG_FP64, "fp32": PMG_MIXED_FP32, "bf16": PMG_MIXED_BF16, "bf16g": PMG_MIXED_BF16G,
-              "bf16x3": PMG_MIXED_BF16X3}
+              "bf16x3": PMG_MIXED_BF16X3, "bf16x2": PMG_MIXED_BF16X2}
 KRYLOV = {"pcg": PMG_PCG, "fpcg": PMG_FPCG, "pdc": PMG_PDC, "mg": PMG_MG}
 
 
@@ -53,7 +53,7 @@ class Options(C.Structure):
                 ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32),
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
                 ("coarsening", C.c_int32), ("overlap", C.c_int32), ("schwarz_store", C.c_int32),
-                ("schwarz_chunk", C.c_int64)]
+                ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32)]
 
 
 class FnpfStats(C.Structure):
@@ -212,6 +212,8 @@ def default_options(**kw) -> Options:
             o.schwarz_store = sum({"fp64": 1, "fp32": 2, "bf16": 4}[x] for x in v.split(",") if x)
         elif k == "coarsening" and isinstance(v, str):
             o.coarsening = {"both": PMG_COARSEN_BOTH, "xy": PMG_COARSEN_XY_FIRST}[v]
+        elif k == "geometry" and isinstance(v, str):
+            o.geometry = {"stored": 0, "column": 1}[v]
         else:
             setattr(o, k, v)
     return o
