@@ -229,7 +229,7 @@ def bench_history(a):
     test = range(200, 300)
     base = {n: ref[n] for n in (197, 198, 199)}
     paths = {}
-    for prec in ("fp64", "fp32", "bf16g"):
+    for prec in ("fp64", "fp32", "bf16g", "bf16x3"):
         ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
         for guess in ("zero", "prev", "extrap", "extrap3", "learned", "learned3"):
             _, st = H.solve_sequence(test, guess=guess, sols=base, net=nets.get(guess), rtol=a.rtol)
@@ -251,7 +251,7 @@ def bench_history(a):
            "paths": paths,
            "speedup": {f"mixed+{lg} vs fp64+{bg}": round(ml / paths[f"fp64+{bg}"]["solves_per_s"], 4)
                        for lg in ("learned", "learned3")
-                       for ml in [max(paths[f"{p}+{lg}"]["solves_per_s"] for p in ("fp32", "bf16g"))]
+                       for ml in [max(paths[f"{p}+{lg}"]["solves_per_s"] for p in ("fp32", "bf16g", "bf16x3"))]
                        for bg in ("zero", "prev", "extrap", "extrap3")},
            "speedup_learned_vs_same_base_fp64": {
                "learned/extrap": round(paths["fp64+learned"]["solves_per_s"] / paths["fp64+extrap"]["solves_per_s"], 4),

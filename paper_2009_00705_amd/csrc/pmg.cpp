@@ -426,6 +426,8 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
   }
   const int64_t nb = (L.num.n_elem + 15) / 16;
   const size_t ng = size_t(nb) * 16 * 6 * re.nq;
+  // with column factors the FP64 and FP32 kernels read no stored G: no native copy
+  const bool col = c->opt.geometry == PMG_GEOM_COLUMN;
   for (int f = 0; f < 3; ++f) {
     if (!mfma_available(L.P, L.PZ, f)) continue;
     std::vector<double> t2, t4;
@@ -439,11 +441,11 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
     if (f == MF_F64) {
       L.tab2[f] = c->U(t2);
       L.tab4[f] = c->U(t4);
-      L.gnat[f] = c->A<double>(ng);
+      if (!col) L.gnat[f] = c->A<double>(ng);
     } else if (f == MF_F32) {
       L.tab2[f] = c->U(to_f32(t2));
       L.tab4[f] = c->U(to_f32(t4));
-      L.gnat[f] = c->A<float>(ng);
+      if (!col) L.gnat[f] = c->A<float>(ng);
     } else {
       L.tab2[f] = c->U(b2);
       L.tab4[f] = c->U(b4);
@@ -1210,7 +1212,8 @@ static int level_geom(pmg_ctx* c, int i, const double* eta, bool lowp, int flavo
   HIPCHK(hipStreamSynchronize(st));
   if (bad) return bad;
   for (int f = 0; f < 3; ++f)
-    if (L.mf[f] && ((flavours >> f) & 1)) launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
+    if (L.mf[f] && L.gnat[f] && ((flavours >> f) & 1))
+      launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
   return 0;
 }
 
@@ -1277,7 +1280,7 @@ static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st) {
   for (int i = 0; i < c->nl; ++i) {
     Level& L = c->lv[i];
     for (int f = 0; f < 3; ++f)
-      if (L.mf[f]) launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
+      if (L.mf[f] && L.gnat[f]) launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
   }
   // Jacobi diagonals
   for (int i = 0; i < c->nl; ++i) {
