@@ -74,9 +74,21 @@ def roofline(bytes_per_launch, flops_per_launch, ms, prec):
     return out
 
 
-def op_bytes(info0, nt, np_tri, s_g, s_v):
-    """Algorithmic bytes of one fine element-operator launch: G + one read of u + the 2D gather map."""
-    return info0["n_elem"] * 6 * info0["nq"] * s_g + info0["n_dof"] * s_v + nt * np_tri * 4
+# paths whose fine MFMA operator forms G from the column factors (geometry "column",
+# the library's default); bf16 and bf16g stream their stored BF16 G
+COLUMN_PATHS = ("fp64", "fp32", "bf16x3", "bf16x2")
+
+
+def op_bytes(info0, nt, np_tri, prec, P):
+    """Algorithmic bytes of one fine element-operator launch: the geometry (stored G,
+    6 factors per cubature point, or 7 column factors per triangle cubature point),
+    one read of u, one write of the element results, and the 2D gather map."""
+    s_v = 8 if prec == "fp64" else 4
+    if prec in COLUMN_PATHS:
+        geo = nt * (P + 1) ** 2 * 7 * (8 if prec == "fp64" else 4)
+    else:
+        geo = info0["n_elem"] * 6 * info0["nq"] * {"fp32": 4}.get(prec, 2)
+    return geo + info0["n_dof"] * s_v + info0["n_elem"] * info0["np"] * s_v + nt * np_tri * 4
 
 
 def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both"):
@@ -451,9 +463,8 @@ def main():
         res = {"workload": wl_desc, "copy_bytes": 2 * 8 * info0["n_dof"]}
         res["copy_ms"] = ctx.time_kernel("copy", 0, "fp64", reps=a.steps)
         for prec in [p for p in a.precisions.split(",") if p]:
-            s_g = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2, "bf16x2": 2}[prec]
             ms = ctx.time_kernel("element_op", 0, prec, reps=a.steps)
-            byts = op_bytes(info0, nt, npt, s_g, 8 if prec == "fp64" else 4)
+            byts = op_bytes(info0, nt, npt, prec, a.P)
             flops = op_flops_per_elem(a.P) * info0["n_elem"]
             res[prec] = {"ms_per_launch": ms, "bytes_per_launch": byts, "GB_per_s": byts / (ms * 1e-3) / 1e9,
                          "flops_per_launch": flops, "roofline": roofline(byts, flops, ms, prec)}
@@ -486,16 +497,14 @@ def main():
     best = max(paths, key=lambda k: paths[k]["solves_per_s"] if paths[k]["rel_res"] <= a.rtol * 1.0001 else -1)
     # dominant kernel: fine-level element operator in the best path's V-cycle precision
     kprec = best
-    s_g = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2, "bf16x2": 2}[kprec]
-    s_v = 8 if kprec == "fp64" else 4
     ms_k = ctx.time_kernel("element_op", 0, kprec, reps=20)
     ms_k64 = ctx.time_kernel("element_op", 0, "fp64", reps=20)
     ms_asm = ctx.time_kernel("assemble", 0, kprec, reps=20)
     nt = mesh["tri"].shape[0]
     npt = (a.P + 1) * (a.P + 2) // 2
-    byts = op_bytes(info0, nt, npt, s_g, s_v)
+    byts = op_bytes(info0, nt, npt, kprec, a.P)
     flops = op_flops_per_elem(a.P) * info0["n_elem"]
-    byts64 = op_bytes(info0, nt, npt, 8, 8)
+    byts64 = op_bytes(info0, nt, npt, "fp64", a.P)
     roof = roofline(byts, flops, ms_k, kprec)
     roof.update({"traffic": None, "kernel": f"MFMA element operator (P={a.P}), {kprec} path",
                  "ms_per_launch": ms_k, "bytes_per_launch": byts, "flops_per_launch": flops,
