@@ -343,7 +343,7 @@ __global__ __launch_bounds__(256) void k_geom(int nt, int L, int nqtl, int n1l, 
       if (geo32) geo32[o + m] = float(bq[m]);
     }
   }
-  for (int layer = 0; layer < L; ++layer) {
+  for (int layer = 0; layer < ((G64 || G32 || G16) ? L : 0); ++layer) {
     const size_t e = size_t(t) * L + layer;
     for (int k = 0; k < N1L; ++k) {
       const double sig = (layer + 0.5 * (1.0 + zq[k])) / L;
@@ -439,6 +439,66 @@ __global__ __launch_bounds__(256) void k_diag(int64_t n_elem, int L, int npt, in
       Y[((size_t(t) * npt + a) * L + layer) * n1 + c] = d;
     }
   }
+}
+
+// Diagonal from the column factors geo[t][q][8] (see launch_geom).  The four
+// triangle sums T1 = sum_q B0 Dr^2 + 2 B1 Dr Ds + B3 Ds^2, T2 = sum_q (B2 Dr + B4 Ds) B,
+// T5 = sum_q B5 B^2 and T6 = sum_q B6 B^2 are shared by every layer and vertical
+// point of the column, so that, with s_k the sigma of Gauss point k in layer l,
+//   diag[c][a] = sum_k zw_k (Bz^2 T1 + 2 Bz Dz s_k T2 + Dz^2 (s_k^2 T5 + T6)).
+// One triangle column per block iteration.
+__global__ __launch_bounds__(256) void k_diag_col(int nt, int L, int npt, int nqt, int n1,
+                                                  const double* __restrict__ mats, const double* __restrict__ zq,
+                                                  const double* __restrict__ zw, const double* __restrict__ geo,
+                                                  double* __restrict__ Y) {
+  extern __shared__ double dsm[];
+  double* sB = dsm;              // [nqt][8]
+  double* sT = sB + nqt * 8;     // [4][npt]
+  const double* Dr = mats;
+  const double* Ds = Dr + nqt * npt;
+  const double* Bt = Ds + nqt * npt;
+  const double* Bz = Bt + nqt * npt;
+  const double* Dz = Bz + n1 * n1;
+  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < nqt * 8; i += 256) sB[i] = geo[size_t(t) * nqt * 8 + i];
+    __syncthreads();
+    for (int a = threadIdx.x; a < npt; a += 256) {
+      double t1 = 0.0, t2 = 0.0, t5 = 0.0, t6 = 0.0;
+      for (int q = 0; q < nqt; ++q) {
+        const double* g = sB + q * 8;
+        const double dr = Dr[q * npt + a], ds = Ds[q * npt + a], b = Bt[q * npt + a];
+        t1 += dr * (g[0] * dr + 2.0 * g[1] * ds) + ds * g[3] * ds;
+        t2 += (g[2] * dr + g[4] * ds) * b;
+        t5 += g[5] * b * b;
+        t6 += g[6] * b * b;
+      }
+      sT[a] = t1;
+      sT[npt + a] = t2;
+      sT[2 * npt + a] = t5;
+      sT[3 * npt + a] = t6;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < L * npt * n1; i += 256) {
+      const int layer = i / (npt * n1), r = i - layer * npt * n1, a = r / n1, c = r - a * n1;
+      double d = 0.0;
+      for (int k = 0; k < n1; ++k) {
+        const double s = (layer + 0.5 * (1.0 + zq[k])) / L;
+        const double bz = Bz[k * n1 + c], dz = Dz[k * n1 + c];
+        d += zw[k] * (bz * bz * sT[a] + 2.0 * bz * dz * s * sT[npt + a] + dz * dz * (s * s * sT[2 * npt + a] + sT[3 * npt + a]));
+      }
+      Y[((size_t(t) * npt + a) * L + layer) * n1 + c] = d;
+    }
+  }
+}
+
+void launch_diag_col(const LevelView& lv, const double* mats, const double* zq, const double* zw, const double* geo,
+                     double* Y, hipStream_t st) {
+  const int npt = lv.np_tri, n1 = lv.PZ + 1, nqt = (lv.P + 1) * (lv.P + 1);
+  const size_t lds = sizeof(double) * (8 * size_t(nqt) + 4 * size_t(npt));
+  const int grid = int(lv.nt < 65536 ? lv.nt : 65536);
+  hipLaunchKernelGGL(k_diag_col, dim3(grid < 1 ? 1 : grid), dim3(256), lds, st, lv.nt, lv.L, npt, nqt, n1, mats, zq,
+                     zw, geo, Y);
 }
 
 void launch_diag(const LevelView& lv, const double* mats, const double* G64, double* Y, hipStream_t st) {

@@ -76,8 +76,11 @@ void launch_geom(const LevelView& fine, const LevelView& lvl, double depth, cons
                  const double* zw, double* G64, float* G32, bf16_t* G16, int* bad, hipStream_t st,
                  double* geo64 = nullptr, float* geo32 = nullptr);
 
-// ---- diagonal of the element matrices (E-layout), FP64
+// ---- diagonal of the element matrices (E-layout), FP64: from the standard G, or
+// from the column factors of launch_geom (zq, zw: vertical Gauss rule)
 void launch_diag(const LevelView& lv, const double* mats, const double* G64, double* Y, hipStream_t st);
+void launch_diag_col(const LevelView& lv, const double* mats, const double* zq, const double* zw, const double* geo,
+                     double* Y, hipStream_t st);
 
 // ---- transfers between level f and the next coarser level c (E-layout output)
 template <typename T>

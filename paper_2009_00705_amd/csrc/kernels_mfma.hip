@@ -697,9 +697,12 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
 // ---------------------------------------------------------------------------
 // G re-layout: standard [e][m][k*NQT+q] (FP64) -> lane-native order of a flavour
 // ---------------------------------------------------------------------------
-template <int PT, int PZ, typename TO, bool F64ROW>
+// COL: G formed from the column factors geo[t][q][8] (L layers, vertical Gauss
+// points zq, weights zw; see launch_geom) instead of read from the standard G.
+template <int PT, int PZ, typename TO, bool F64ROW, bool COL = false>
 __global__ __launch_bounds__(256) void k_g_native(int64_t n_elem, int64_t n_batch, const double* __restrict__ G,
-                                                  TO* __restrict__ out) {
+                                                  TO* __restrict__ out, int L, const double* __restrict__ geo,
+                                                  const double* __restrict__ zq, const double* __restrict__ zw) {
   using D = MD<PT, PZ>;
   const int64_t per_batch = int64_t(16) * 6 * D::NQ;
   const int64_t total = n_batch * per_batch;
@@ -723,7 +726,17 @@ __global__ __launch_bounds__(256) void k_g_native(int64_t n_elem, int64_t n_batc
     }
     const int64_t e = b * 16 + jj;
     double v = 0.0;
-    if (e < n_elem) v = G[(e * 6 + m) * D::NQ + int64_t(k) * D::NQT + q];
+    if (e < n_elem) {
+      if constexpr (COL) {
+        const int64_t tri = e / L;
+        const double sg = (double(e - tri * L) + 0.5 * (1.0 + zq[k])) / L;
+        const double* bq = geo + (tri * D::NQT + q) * 8;
+        const double f[6] = {bq[0], bq[1], sg * bq[2], bq[3], sg * bq[4], sg * sg * bq[5] + bq[6]};
+        v = zw[k] * f[m];
+      } else {
+        v = G[(e * 6 + m) * D::NQ + int64_t(k) * D::NQT + q];
+      }
+    }
     out[i] = cvt_out<TO>(v);
   }
 }
@@ -754,30 +767,34 @@ static int grid_batches(int64_t n_batch, const void* kernel, int threads) {
 
 
 template <int PT, int PZ>
-static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
+static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st, const double* geo,
+                       int L, const double* zq, const double* zw) {
   const int64_t nb = (n_elem + 15) / 16;
   const int64_t total = nb * 16 * 6 * MD<PT, PZ>::NQ;
   int64_t grid = (total + 255) / 256;
   if (grid > 65535 * 4) grid = 65535 * 4;
-  if (flavour == MF_F64)
-    hipLaunchKernelGGL((k_g_native<PT, PZ, double, true>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,
-                       (double*)out);
-  else if (flavour == MF_F32)
-    hipLaunchKernelGGL((k_g_native<PT, PZ, float, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,
-                       (float*)out);
-  else
-    hipLaunchKernelGGL((k_g_native<PT, PZ, bf16_t, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,
-                       (bf16_t*)out);
+#define PMG_GN(TO, ROW)                                                                                    \
+  if (geo)                                                                                                 \
+    hipLaunchKernelGGL((k_g_native<PT, PZ, TO, ROW, true>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,    \
+                       (TO*)out, L, geo, zq, zw);                                                          \
+  else                                                                                                     \
+    hipLaunchKernelGGL((k_g_native<PT, PZ, TO, ROW, false>), dim3(grid), dim3(256), 0, st, n_elem, nb, G,   \
+                       (TO*)out, L, geo, zq, zw)
+  if (flavour == MF_F64) PMG_GN(double, true);
+  else if (flavour == MF_F32) PMG_GN(float, false);
+  else PMG_GN(bf16_t, false);
+#undef PMG_GN
 }
 
 // orders with MFMA kernels: (3,3), (6,6), (3,6), (4,8), (2,8) [the in-plane-
-// coarsened levels of P = 6 and P = 8] in every flavour, (8,8) in every flavour
-// but split-BF16 (its FP64 tables are read through the caches)
+// coarsened levels of P = 6 and P = 8] and (8,8) (its FP64 tables are read
+// through the caches); split-BF16 kernels at in-plane order 6 only
 #define PMG_MFMA_ORDERS(X) X(3, 3) X(6, 6) X(3, 6) X(8, 8) X(4, 8) X(2, 8)
 
-void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st) {
+void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st,
+                     const double* geo, int L, const double* zq, const double* zw) {
 #define PMG_REL(PTV, PZV) \
-  if (PT == PTV && PZ == PZV) return relayout_p<PTV, PZV>(n_elem, G, out, flavour, st);
+  if (PT == PTV && PZ == PZV) return relayout_p<PTV, PZV>(n_elem, G, out, flavour, st, geo, L, zq, zw);
   PMG_MFMA_ORDERS(PMG_REL)
 #undef PMG_REL
 }

@@ -43,7 +43,12 @@ inline bool mfma_available(int PT, int PZ, int flavour) {
   if (flavour == MF_BF16X3 || flavour == MF_BF16X2) return order && PT == 6;
   return order;
 }
-void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st);
+// lane-native copy of G for a flavour, from the standard FP64 G, or (geo given)
+// formed from the FP64 column factors of an L-layer column with vertical Gauss
+// points zq and weights zw (device arrays)
+void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st,
+                     const double* geo = nullptr, int L = 1, const double* zq = nullptr,
+                     const double* zw = nullptr);
 // tab2lo / tab4lo: the lo tables of MF_BF16X3 (unused by the other flavours).
 // geo (optional): column factors of the level (FP64 for MF_F64, FP32 for MF_F32
 // and the split-BF16 flavours; ignored by MF_BF16 and MF_F32G16, which read

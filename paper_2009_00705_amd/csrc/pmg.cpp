@@ -485,9 +485,15 @@ static void upload_levels(pmg_ctx* c) {
     L.zq = c->U(re.zq);
     L.zw = c->U(re.zw);
     const int64_t E = L.num.n_elem, N = L.num.n_dof;
-    L.G64 = c->A<double>(size_t(E) * 6 * re.nq);
-    L.G32 = c->A<float>(size_t(E) * 6 * re.nq);
-    L.G16 = c->A<bf16_t>(size_t(E) * 6 * re.nq);
+    // stored G: every level without an MFMA operator on column factors, and every
+    // level under the Schwarz smoother (its element matrices read G)
+    const bool col_only = c->opt.geometry == PMG_GEOM_COLUMN && c->opt.kernel_variant == 0 &&
+                          c->opt.smoother != PMG_SMOOTH_SCHWARZ && mfma_available(L.P, L.PZ, MF_F64);
+    if (!col_only) {
+      L.G64 = c->A<double>(size_t(E) * 6 * re.nq);
+      L.G32 = c->A<float>(size_t(E) * 6 * re.nq);
+      L.G16 = c->A<bf16_t>(size_t(E) * 6 * re.nq);
+    }
     L.diag = c->A<double>(N);
     L.dinv64 = c->A<double>(N);
     L.dinv32 = c->A<float>(N);
@@ -1190,9 +1196,18 @@ static void schwarz_setup(pmg_ctx* c, hipStream_t st, int i0 = 0) {
 // ---------------------------------------------------------------------------
 static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st);
 
-// Diagonal (and its inverses) of one level from its current G64.
+// Lane-native copy of G for flavour f: from the stored G64, or formed from the
+// FP64 column factors when the level keeps no stored G.
+static void native_g(pmg_ctx* c, Level& L, int f, hipStream_t st) {
+  launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st, L.G64 ? nullptr : L.geo64, L.view.L, L.zq,
+                  L.zw);
+}
+
+// Diagonal (and its inverses) of one level from its current G64, or from its
+// column factors when it keeps no stored G.
 static void level_diag(pmg_ctx* c, Level& L, hipStream_t st) {
-  launch_diag(L.view, L.mats64, L.G64, c->Y, st);
+  if (L.G64) launch_diag(L.view, L.mats64, L.G64, c->Y, st);
+  else launch_diag_col(L.view, L.mats64, L.zq, L.zw, L.geo64, c->Y, st);
   launch_assemble<double>(L.view, OP_RAW, c->Y, L.diag, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
   launch_dinv<double>(L.view, nullptr, L.diag, L.dinv64, st);
   launch_dinv<float>(L.view, nullptr, L.diag, L.dinv32, st);
@@ -1212,8 +1227,7 @@ static int level_geom(pmg_ctx* c, int i, const double* eta, bool lowp, int flavo
   HIPCHK(hipStreamSynchronize(st));
   if (bad) return bad;
   for (int f = 0; f < 3; ++f)
-    if (L.mf[f] && L.gnat[f] && ((flavours >> f) & 1))
-      launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
+    if (L.mf[f] && L.gnat[f] && ((flavours >> f) & 1)) native_g(c, L, f, st);
   return 0;
 }
 
@@ -1280,16 +1294,10 @@ static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st) {
   for (int i = 0; i < c->nl; ++i) {
     Level& L = c->lv[i];
     for (int f = 0; f < 3; ++f)
-      if (L.mf[f] && L.gnat[f]) launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st);
+      if (L.mf[f] && L.gnat[f]) native_g(c, L, f, st);
   }
   // Jacobi diagonals
-  for (int i = 0; i < c->nl; ++i) {
-    Level& L = c->lv[i];
-    launch_diag(L.view, L.mats64, L.G64, c->Y, st);
-    launch_assemble<double>(L.view, OP_RAW, c->Y, L.diag, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
-    launch_dinv<double>(L.view, nullptr, L.diag, L.dinv64, st);
-    launch_dinv<float>(L.view, nullptr, L.diag, L.dinv32, st);
-  }
+  for (int i = 0; i < c->nl; ++i) level_diag(c, c->lv[i], st);
   schwarz_setup(c, st);
   for (int i = 0; i + 1 < c->nl; ++i) {
     Level& L = c->lv[i];
