@@ -1053,20 +1053,34 @@ __global__ __launch_bounds__(256) void k_cheb_start(int64_t n, const T* __restri
 // slots have column g and value 0; a Dirichlet row has column -1 in slot 0):
 // r -= A d_old; d_new = c0 d_old + c1 D^-1 r; x += d_new.
 // d is double-buffered because every row reads its neighbours' d_old.
+// ELL_LANES lanes share a row (slots k = part, part + ELL_LANES, ...), their
+// partial sums joined by shuffles: four times the waves of one lane per row for
+// the same rows, which the 83k-row coarse problem needs to hide its latency.
+constexpr int ELL_LANES = 4;
 template <typename T>
 __global__ __launch_bounds__(256) void k_cheb_ell(int64_t n, int w, const int32_t* __restrict__ ci,
                                                   const T* __restrict__ val, const T* __restrict__ dinv,
                                                   const T* __restrict__ d_old, T* __restrict__ d_new,
                                                   T* __restrict__ r, T* __restrict__ x, T c0, T c1) {
-  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n; g += int64_t(gridDim.x) * 256) {
-    if (ci[g] < 0) {
+  const int part = threadIdx.x % ELL_LANES;
+  const int64_t rows_per_grid = int64_t(gridDim.x) * (256 / ELL_LANES);
+  // every lane of a row group runs the same trip count (the shuffles need all of them)
+  for (int64_t g0 = int64_t(blockIdx.x) * (256 / ELL_LANES); g0 < n; g0 += rows_per_grid) {
+    const int64_t g = g0 + threadIdx.x / ELL_LANES;
+    const bool row = g < n;
+    const bool dir = row && ci[g] < 0;
+    T s = 0;
+    if (row && !dir)
+      for (int k = part; k < w; k += ELL_LANES) {
+        const int64_t j = int64_t(k) * n + g;
+        s += val[j] * d_old[ci[j]];
+      }
+#pragma unroll
+    for (int o = 1; o < ELL_LANES; o <<= 1) s += __shfl_xor(s, o, ELL_LANES);
+    if (!row || part != 0) continue;
+    if (dir) {
       d_new[g] = T(0);
       continue;
-    }
-    T s = 0;
-    for (int k = 0; k < w; ++k) {
-      const int64_t j = int64_t(k) * n + g;
-      s += val[j] * d_old[ci[j]];
     }
     const T rn = r[g] - s;
     r[g] = rn;
@@ -1082,8 +1096,8 @@ void launch_cheb_start(int64_t n, const T* f, const T* dinv, T* r, T* d, T* x, d
 template <typename T>
 void launch_cheb_ell(int64_t n, int w, const int32_t* ci, const T* val, const T* dinv, const T* d_old, T* d_new,
                      T* r, T* x, double c0, double c1, hipStream_t st) {
-  hipLaunchKernelGGL((k_cheb_ell<T>), dim3(grid_for(n)), dim3(256), 0, st, n, w, ci, val, dinv, d_old, d_new, r, x,
-                     T(c0), T(c1));
+  hipLaunchKernelGGL((k_cheb_ell<T>), dim3(grid_for(n * ELL_LANES)), dim3(256), 0, st, n, w, ci, val, dinv, d_old,
+                     d_new, r, x, T(c0), T(c1));
 }
 template void launch_cheb_start<double>(int64_t, const double*, const double*, double*, double*, double*, double, hipStream_t);
 template void launch_cheb_start<float>(int64_t, const float*, const float*, float*, float*, float*, double, hipStream_t);

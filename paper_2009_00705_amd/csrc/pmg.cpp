@@ -657,9 +657,7 @@ static void cheb_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess, in
   T* r = L.r<T>();
   T* d = L.d<T>();
   if (zero_guess) {
-    launch_copy<T>(f, r, N, st);
-    launch_scale_diag<T>(L.dinv<T>(), f, d, 1.0 / theta, N, st);
-    launch_copy<T>(d, u, N, st);
+    launch_cheb_start<T>(N, f, L.dinv<T>(), r, d, u, 1.0 / theta, st);  // r = f, d = D^-1 f / theta, u = d
   } else {
     ax_elem<T>(c, i, u, st);
     assemble<T>(c, i, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
