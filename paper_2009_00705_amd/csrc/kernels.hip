@@ -208,7 +208,7 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, 
                                                   const T* __restrict__ Y, T* __restrict__ out,
                                                   const T* __restrict__ a1, const T* __restrict__ a2,
                                                   T* __restrict__ a3, T omega, T c1,
-                                                  double* __restrict__ partial) {
+                                                  double* __restrict__ partial, T* __restrict__ a4) {
   const int colen = L * (P + 1);
   double acc = 0.0;
   for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n_dof; g += int64_t(gridDim.x) * 256) {
@@ -242,6 +242,13 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, 
       const T v = dir ? T(0) : s;
       out[g] = v;
       acc += double(a1[g]) * double(v);
+    } else if (OP == OP_CHEB0) {
+      // r = f - A x, d = c1 D^-1 r, x += d (D^-1 is zero at Dirichlet nodes)
+      const T rn = dir ? T(0) : a1[g] - s;
+      a4[g] = rn;
+      const T dn = c1 * a2[g] * rn;
+      a3[g] = dn;
+      out[g] += dn;
     } else if (OP == OP_CHEB) {
       // x = out, r = a1 (in/out through a3 alias), d = a3
       if (!dir) {
@@ -262,12 +269,12 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, 
 
 template <typename T>
 void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a1, const T* a2, T* a3,
-                     double omega, double c1, double* partial, hipStream_t st) {
+                     double omega, double c1, double* partial, hipStream_t st, T* a4) {
   const int grid = op == OP_STORE_DOT ? RED_BLOCKS : grid_for(lv.n_dof);
 #define PMG_ASM(OPV)                                                                                   \
   hipLaunchKernelGGL((k_assemble<T, OPV>), dim3(grid), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.L,  \
                      lv.PZ, lv.inc_ptr, lv.inc, lv.dir2d, lv.top_dir, Y, out, a1, a2, a3, T(omega),   \
-                     T(c1), partial)
+                     T(c1), partial, a4)
   switch (op) {
     case OP_STORE: PMG_ASM(OP_STORE); break;
     case OP_AVG_ADD: PMG_ASM(OP_AVG_ADD); break;
@@ -278,12 +285,13 @@ void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a
     case OP_CHEB: PMG_ASM(OP_CHEB); break;
     case OP_RAW: PMG_ASM(OP_RAW); break;
     case OP_AVG_RAW: PMG_ASM(OP_AVG_RAW); break;
+    case OP_CHEB0: PMG_ASM(OP_CHEB0); break;
     default: break;
   }
 #undef PMG_ASM
 }
-template void launch_assemble<double>(const LevelView&, int, const double*, double*, const double*, const double*, double*, double, double, double*, hipStream_t);
-template void launch_assemble<float>(const LevelView&, int, const float*, float*, const float*, const float*, float*, double, double, double*, hipStream_t);
+template void launch_assemble<double>(const LevelView&, int, const double*, double*, const double*, const double*, double*, double, double, double*, hipStream_t, double*);
+template void launch_assemble<float>(const LevelView&, int, const float*, float*, const float*, const float*, float*, double, double, double*, hipStream_t, float*);
 
 // ---------------------------------------------------------------------------
 // geometric factors (thread per triangle x triangle cubature point)
@@ -815,30 +823,35 @@ void launch_finalize(const double* partial, double* scal, int slot, int op, hipS
 __global__ __launch_bounds__(256) void k_cg_update(double* __restrict__ u, double* __restrict__ r,
                                                    const double* __restrict__ p, const double* __restrict__ q,
                                                    const double* __restrict__ scal, double* __restrict__ partial,
-                                                   int64_t n) {
+                                                   int64_t n, float* __restrict__ r32) {
   const double alpha = scal[S_ALPHA];
   double acc = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
     u[i] += alpha * p[i];
     const double rn = r[i] - alpha * q[i];
     r[i] = rn;
+    if (r32) r32[i] = float(rn);
     acc += rn * rn;
   }
   const double b = block_sum256(acc);
   if (threadIdx.x == 0) partial[blockIdx.x] = b;
 }
 void launch_cg_update(double* u, double* r, const double* p, const double* q, const double* scal,
-                      double* partial, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_update, dim3(RED_BLOCKS), dim3(256), 0, st, u, r, p, q, scal, partial, n);
+                      double* partial, int64_t n, hipStream_t st, float* r32) {
+  hipLaunchKernelGGL(k_cg_update, dim3(RED_BLOCKS), dim3(256), 0, st, u, r, p, q, scal, partial, n, r32);
 }
-__global__ void k_cg_dir(double* __restrict__ p, const double* __restrict__ z, const double* __restrict__ scal,
+template <typename TZ>
+__global__ void k_cg_dir(double* __restrict__ p, const TZ* __restrict__ z, const double* __restrict__ scal,
                          int64_t n) {
   const double beta = scal[S_BETA];
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256)
-    p[i] = z[i] + beta * p[i];
+    p[i] = double(z[i]) + beta * p[i];
 }
 void launch_cg_dir(double* p, const double* z, const double* scal, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(k_cg_dir, dim3(grid_for(n)), dim3(256), 0, st, p, z, scal, n);
+  hipLaunchKernelGGL(k_cg_dir<double>, dim3(grid_for(n)), dim3(256), 0, st, p, z, scal, n);
+}
+void launch_cg_dir(double* p, const float* z, const double* scal, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_cg_dir<float>, dim3(grid_for(n)), dim3(256), 0, st, p, z, scal, n);
 }
 __global__ void k_axpy(double* __restrict__ y, const double* __restrict__ x, double a, int64_t n) {
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) y[i] += a * x[i];
@@ -918,13 +931,15 @@ template void launch_dinv<float>(const LevelView&, const float*, const double*, 
 }  // namespace pmg
 
 namespace pmg {
-__global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ x, const double* __restrict__ y1,
+template <typename TX>
+__global__ __launch_bounds__(256) void k_dot2(const TX* __restrict__ x, const double* __restrict__ y1,
                                               const double* __restrict__ y2, int64_t n,
                                               double* __restrict__ partial) {
   double a = 0.0, b = 0.0;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < n; i += int64_t(gridDim.x) * 256) {
-    a += x[i] * y1[i];
-    b += x[i] * y2[i];
+    const double xi = double(x[i]);
+    a += xi * y1[i];
+    b += xi * y2[i];
   }
   const double sa = block_sum256(a);
   const double sb = block_sum256(b);
@@ -935,7 +950,11 @@ __global__ __launch_bounds__(256) void k_dot2(const double* __restrict__ x, cons
 }
 void launch_dot2(const double* x, const double* y1, const double* y2, int64_t n, double* partial,
                  hipStream_t st) {
-  hipLaunchKernelGGL(k_dot2, dim3(RED_BLOCKS), dim3(256), 0, st, x, y1, y2, n, partial);
+  hipLaunchKernelGGL(k_dot2<double>, dim3(RED_BLOCKS), dim3(256), 0, st, x, y1, y2, n, partial);
+}
+void launch_dot2(const float* x, const double* y1, const double* y2, int64_t n, double* partial,
+                 hipStream_t st) {
+  hipLaunchKernelGGL(k_dot2<float>, dim3(RED_BLOCKS), dim3(256), 0, st, x, y1, y2, n, partial);
 }
 }  // namespace pmg
 

@@ -59,11 +59,12 @@ enum AsmOp {
   OP_AVG_STORE = 5, // out = mask * sum / multiplicity
   OP_CHEB = 6,      // Chebyshev step on (x=out, r=a1, d=a3): r -= sum; x += d_new ...
   OP_RAW = 7,       // out = sum (no mask)
-  OP_AVG_RAW = 8    // out = sum / multiplicity (no mask)
+  OP_AVG_RAW = 8,   // out = sum / multiplicity (no mask)
+  OP_CHEB0 = 9      // first Chebyshev step from x = out: a4 = r = mask (a1 - sum), a3 = d = c1 a2 r, x += d
 };
 template <typename T>
 void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a1, const T* a2,
-                     T* a3, double omega, double c1, double* partial, hipStream_t st);
+                     T* a3, double omega, double c1, double* partial, hipStream_t st, T* a4 = nullptr);
 
 // ---- geometric factors at level cubature from the fine isoparametric map
 // G64/G32/G16: G[e][m][k*nqt+q] (any may be null).  geo64/geo32 (may be null):
@@ -125,11 +126,13 @@ enum FinOp { FIN_SET = 0, FIN_ALPHA = 1, FIN_BETA_FR = 2, FIN_BETA_PR = 3, FIN_D
 void launch_finalize(const double* partial, double* scal, int slot, int op, hipStream_t st);
 
 // PCG vector updates (FP64)
-// u += alpha p; r -= alpha q; partial = ||r||^2    (alpha = scal[S_ALPHA])
+// u += alpha p; r -= alpha q; partial = ||r||^2    (alpha = scal[S_ALPHA]);
+// r32 (optional) = float(r), the input of a low-precision V-cycle
 void launch_cg_update(double* u, double* r, const double* p, const double* q, const double* scal,
-                      double* partial, int64_t n, hipStream_t st);
-// p = z + beta p (beta = scal[S_BETA])
+                      double* partial, int64_t n, hipStream_t st, float* r32 = nullptr);
+// p = z + beta p (beta = scal[S_BETA]); z FP64 or the FP32 V-cycle output
 void launch_cg_dir(double* p, const double* z, const double* scal, int64_t n, hipStream_t st);
+void launch_cg_dir(double* p, const float* z, const double* scal, int64_t n, hipStream_t st);
 // u += z ; partial of nothing
 void launch_axpy(double* y, const double* x, double a, int64_t n, hipStream_t st);
 // r = f - y (masked by a2 != 0 when mask given) ; partial ||r||^2
@@ -141,8 +144,10 @@ void launch_lift(const LevelView& lv, const double* surf, const double* bc, doub
 // out = where(free, a, b)
 void launch_merge_free(const LevelView& lv, const double* a, const double* b, double* out,
                        hipStream_t st);
-// partial[0..RED_BLOCKS) = x.y1, partial[RED_BLOCKS..) = x.y2
+// partial[0..RED_BLOCKS) = x.y1, partial[RED_BLOCKS..) = x.y2 (x FP64 or FP32, in FP64)
 void launch_dot2(const double* x, const double* y1, const double* y2, int64_t n, double* partial,
+                 hipStream_t st);
+void launch_dot2(const float* x, const double* y1, const double* y2, int64_t n, double* partial,
                  hipStream_t st);
 // y += a x
 template <typename T> void launch_axpy_t(T* y, const T* x, double a, int64_t n, hipStream_t st);

@@ -659,10 +659,10 @@ static void cheb_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess, in
   if (zero_guess) {
     launch_cheb_start<T>(N, f, L.dinv<T>(), r, d, u, 1.0 / theta, st);  // r = f, d = D^-1 f / theta, u = d
   } else {
+    // r = f - A u, d = D^-1 r / theta, u += d (one fused summation)
     ax_elem<T>(c, i, u, st);
-    assemble<T>(c, i, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
-    launch_scale_diag<T>(L.dinv<T>(), r, d, 1.0 / theta, N, st);
-    launch_axpy_t<T>(u, d, 1.0, N, st);
+    launch_assemble<T>(L.view, OP_CHEB0, reinterpret_cast<const T*>(c->Y), u, f, L.dinv<T>(), d, 0.0, 1.0 / theta,
+                       c->partial, st, r);
   }
   double rho = 1.0 / sigma;
   for (int j = 1; j < k; ++j) {
@@ -1643,10 +1643,13 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
       launch_dot<double>(c->s_z, c->s_r, N, c->partial, st);
       launch_finalize(c->partial, c->scal, 0, FIN_DELTA, st);
     }
+    // low-precision V-cycle: the update also writes r in FP32 (the V-cycle input)
+    // and the beta dot and the direction read its FP32 output directly
+    const bool lowp = c->opt.precision != PMG_FP64;
     while (it < imax && hist_r.back() > tol) {
       fine_apply(c, c->s_p, c->s_q, c->s_p, st);
       launch_finalize(c->partial, c->scal, 0, FIN_ALPHA, st);
-      launch_cg_update(c->s_u, c->s_r, c->s_p, c->s_q, c->scal, c->partial, N, st);
+      launch_cg_update(c->s_u, c->s_r, c->s_p, c->s_q, c->scal, c->partial, N, st, lowp ? c->s_r32 : nullptr);
       launch_finalize(c->partial, c->scal, S_RR, FIN_SET, st);
       HIPCHK(hipMemcpyAsync(c->scal_h, c->scal, N_SCAL * sizeof(double), hipMemcpyDeviceToHost, st));
       HIPCHK(hipStreamSynchronize(st));
@@ -1656,6 +1659,16 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
       hist_r.push_back(std::sqrt(rr));
       ++it;
       if (hist_r.back() <= tol || it >= imax) break;
+      if (lowp) {
+        // z = M r with r already in FP32; z stays FP32 (widened where read)
+        c->n_vcycles++;
+        set_lowp(c, c->opt.precision);
+        vcycle<float>(c, 0, c->s_r32, c->s_z32, st);
+        launch_dot2(c->s_z32, c->s_r, c->s_q, N, c->partial, st);
+        launch_finalize(c->partial, c->scal, 0, kry == PMG_PCG ? FIN_BETA_FR : FIN_BETA_PR, st);
+        launch_cg_dir(c->s_p, c->s_z32, c->scal, N, st);
+        continue;
+      }
       precond(c, c->s_r, c->s_z, st);
       if (kry == PMG_PCG) {
         launch_dot<double>(c->s_z, c->s_r, N, c->partial, st);
