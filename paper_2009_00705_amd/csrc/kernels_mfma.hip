@@ -261,7 +261,7 @@ __device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds,
 // GEO: G from the column factors (Gnat is then geo[t][q][8] of type T) instead
 // of the stored lane-native G.
 template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW, bool GT = false, bool GEO = false>
-__global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : 4))) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
+__global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : ((GEO && PT <= 3) ? 6 : 4)))) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
                                                          int64_t n_elem, int64_t n_batch,
                                                          const TG* __restrict__ Gnat, const T* __restrict__ tab2,
                                                          const T* __restrict__ tab4, VertMats<T> vm,
