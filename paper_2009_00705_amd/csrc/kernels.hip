@@ -6,7 +6,9 @@
 //    of triangle t is contiguous (L*(P+1) values) and the node-centric sum
 //    reads it with unit stride.
 //  * G: [e][6][Nq] with components (rr, rs, rt, ss, st, tt) and cubature index
-//    k*Nq_tri + q.
+//    k*Nq_tri + q (levels that keep it stored).
+//  * Column factors: [t][q][8], seven factors per triangle cubature point from
+//    which G of every layer and vertical point of the column follows (k_geom).
 //  * Reference matrices ("mats"): [Dr | Ds | B] (Nq_tri x Np_tri each, row
 //    major) followed by [Bz | Dz] ((P+1) x (P+1) each).
 #include <hip/hip_runtime.h>

@@ -5,8 +5,10 @@
 //   1. vertical (VALU): W[k][a] = sum_c Bz[k][c] u[c][a],  Wz with Dz
 //   2. triangle (MFMA): [ur|us|ut][q] = [Dr|Ds|B][q][a] x [W|W|Wz][a]
 //      (A operand = reference matrix tile from LDS, B operand = W in registers)
-//   3. pointwise (VALU): (vr, vs, vt) = G (ur, us, ut), G streamed from HBM in
-//      a lane-native order (no padding), result kept in the MFMA registers
+//   3. pointwise (VALU): (vr, vs, vt) = G (ur, us, ut), G formed in registers
+//      from the column factors of the prism's triangle (the sigma-transform
+//      shares them along the column; see launch_geom) or streamed from a stored
+//      lane-native copy (no padding); the result stays in the MFMA registers
 //   4. transposed triangle (MFMA): Yr[a] = sum_q Dr[q][a] vr[q] + Ds[q][a] vs[q],
 //      Yt[a] = sum_q B[q][a] vt[q]; the K index of each step is chosen so that
 //      the B operand is exactly the register the pointwise stage produced
@@ -14,10 +16,11 @@
 // Output is the E-layout vector [t][a][layer][c] consumed by the atomic-free
 // node-centric summation kernel.
 //
-// Flavours: FP32 (v_mfma_f32_16x16x4f32), FP64 (v_mfma_f64_16x16x4f64) and
-// BF16 operands with FP32 accumulation (v_mfma_f32_16x16x16bf16_1k).  Output
-// row of lane l = 16*(l/16)... see Row<>: FP32/BF16 hold D[4g+r][j], FP64 holds
-// D[g+4r][j] (g = lane/16, j = lane%16, r = 0..3).
+// Flavours: FP32 (v_mfma_f32_16x16x4f32), FP64 (v_mfma_f64_16x16x4f64), BF16
+// operands with FP32 accumulation (v_mfma_f32_16x16x16bf16_1k), and split-BF16
+// products on the same BF16 instruction.  Output registers: FP32/BF16 hold
+// D[4g+r][j], FP64 holds D[g+4r][j] (g = lane/16, j = lane%16, r = 0..3; see
+// row_of).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -523,9 +526,10 @@ __device__ __forceinline__ void load_g_bf16(const bf16_t* __restrict__ Gnat, int
 // LO: a product keeps the three terms a_hi b_hi + a_hi b_lo + a_lo b_hi (about
 //   16 significant bits, against 8 for one BF16 product), three BF16 MFMAs in
 //   place of one FP32 MFMA of four times the cost per K.  Tables: hi and lo
-//   copies of the BF16-layout tables, both in LDS.  Measured at P = 6 this is
-//   slower than FP32 MFMA on the same BF16 G: the extra MFMAs, the LDS of the
-//   lo tables and the hi/lo splits cost more than the matrix-core time saved.
+//   copies of the BF16-layout tables, both in LDS (78 KB at P = 6, two
+//   workgroups per CU within 128 VGPRs).  At P = 6 it is the fastest FP32-
+//   accurate operator: its matrix-core time is a fraction of the FP32 MFMA's,
+//   and the kernel is bound by memory latency and barriers instead.
 // !LO: the reference tables are rounded to BF16 once (a fixed, symmetric
 //   perturbation of the reference matrices, as G's rounding is of the
 //   geometry) and only the vectors are split: a_hi b_hi + a_hi b_lo, two BF16
