@@ -285,3 +285,34 @@ def test_column_geometry_matches_stored_factors(case):
             assert rel_err(host(ys["column"]), host(ys["stored"])) < tol, (case, lvl, prec)
     for c in ctxs.values():
         c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16x3"])
+def test_stored_geometry_solves_match_column_solves(prec):
+    """The whole solve (FP64 outer iteration, V-cycle in each precision) with
+    stored G and with the column factors: FP64 iteration counts and residual
+    histories agree to 1e-10, the mixed ones to the rounding of their
+    geometric factors (iteration counts within one, potentials within 1e-8 of
+    each other at rtol 1e-10)."""
+    import torch
+    from gpu_common import surface_eta
+    from paper_2009_00705_amd import pmg
+    mk, P = CASES["box5x5_L3_P6"]
+    mesh = mk()
+    out = {}
+    for g in ("stored", "column"):
+        ctx = pmg.Context(mesh, P=P, geometry=g, coarsening="xy", smoother="chebyshev", nu1=3, nu2=3)
+        xy = ctx.surface_xy()
+        ctx.set_surface(dev(surface_eta(xy, "wavy")))
+        ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
+        phi = torch.zeros(ctx.levels[0]["n_dof"], dtype=torch.float64, device="cuda")
+        rc, st = ctx.solve(phi, phi_surf=dev(np.cos(xy[:, 0]) * np.cos(xy[:, 1])), rtol=1e-10, imax=300)
+        assert rc == 0, (g, prec)
+        out[g] = (st, host(phi))
+        ctx.close()
+    (ss, ps), (sc, pc) = out["stored"], out["column"]
+    # the mixed V-cycles differ by their factors' rounding (BF16-stored G for bf16x3)
+    assert abs(ss["iters"] - sc["iters"]) <= (0 if prec == "fp64" else 1)
+    if prec == "fp64":
+        np.testing.assert_allclose(sc["res_hist"], ss["res_hist"], rtol=1e-9, atol=1e-10 * ss["res_hist"][0])
+    assert rel_err(pc, ps) < (1e-10 if prec == "fp64" else 1e-8)
