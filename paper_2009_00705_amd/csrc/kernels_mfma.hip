@@ -355,11 +355,36 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
       if constexpr (GEO) load_geo<T, PT, PZ, F64ROW>((const T*)Gnat, tri, D::NTF, g, gp, gps, gps2, ga);
       else load_rem<T, D::NTF, D::NQR, F64ROW>(Gnat, blk, MST, g, j, ga);
       ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
+      if constexpr (D::NQR == 1) {
+        // one valid row (q = 16 NTF, held by lanes g = 0 in register 0): three dot
+        // products over a on VALU instead of 3 KS MFMAs of which 15/16 rows are
+        // padding.  Lane (g, j) holds W at a = 4 s + g; the row's coefficients are
+        // the table entries of lane 16 g (row 0 of the tile, column 4 s + g).
+        T pr = 0, ps = 0, pb = 0;
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        dr = mfma4(s2[((0 * NT2 + t) * KS + s) * 64 + lane], w[s], dr);
-        ds = mfma4(s2[((1 * NT2 + t) * KS + s) * 64 + lane], w[s], ds);
-        db = mfma4(s2[((2 * NT2 + t) * KS + s) * 64 + lane], wz[s], db);
+        for (int s = 0; s < KS; ++s) {
+          pr += s2[((0 * NT2 + t) * KS + s) * 64 + 16 * g] * w[s];
+          ps += s2[((1 * NT2 + t) * KS + s) * 64 + 16 * g] * w[s];
+          pb += s2[((2 * NT2 + t) * KS + s) * 64 + 16 * g] * wz[s];
+        }
+#pragma unroll
+        for (int o = 16; o < 64; o <<= 1) {
+          pr += __shfl_xor(pr, o);
+          ps += __shfl_xor(ps, o);
+          pb += __shfl_xor(pb, o);
+        }
+        if (g == 0) {
+          dr[0] = pr;
+          ds[0] = ps;
+          db[0] = pb;
+        }
+      } else {
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          dr = mfma4(s2[((0 * NT2 + t) * KS + s) * 64 + lane], w[s], dr);
+          ds = mfma4(s2[((1 * NT2 + t) * KS + s) * 64 + lane], w[s], ds);
+          db = mfma4(s2[((2 * NT2 + t) * KS + s) * 64 + lane], wz[s], db);
+        }
       }
       pointwise<T, ACC>(ga, dr, ds, db);
       int st = 4 * D::NTF;
