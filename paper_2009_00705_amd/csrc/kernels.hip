@@ -456,48 +456,56 @@ __global__ __launch_bounds__(256) void k_diag(int64_t n_elem, int L, int npt, in
 // T5 = sum_q B5 B^2 and T6 = sum_q B6 B^2 are shared by every layer and vertical
 // point of the column, so that, with s_k the sigma of Gauss point k in layer l,
 //   diag[c][a] = sum_k zw_k (Bz^2 T1 + 2 Bz Dz s_k T2 + Dz^2 (s_k^2 T5 + T6)).
-// One triangle column per block iteration.
+// DIAG_TB triangle columns per block iteration (one thread per (column, node a)
+// for the triangle sums).
+constexpr int DIAG_TB = 8;
 __global__ __launch_bounds__(256) void k_diag_col(int nt, int L, int npt, int nqt, int n1,
                                                   const double* __restrict__ mats, const double* __restrict__ zq,
                                                   const double* __restrict__ zw, const double* __restrict__ geo,
                                                   double* __restrict__ Y) {
   extern __shared__ double dsm[];
-  double* sB = dsm;              // [nqt][8]
-  double* sT = sB + nqt * 8;     // [4][npt]
+  double* sB = dsm;                         // [DIAG_TB][nqt][8]
+  double* sT = sB + DIAG_TB * nqt * 8;      // [DIAG_TB][4][npt]
   const double* Dr = mats;
   const double* Ds = Dr + nqt * npt;
   const double* Bt = Ds + nqt * npt;
   const double* Bz = Bt + nqt * npt;
   const double* Dz = Bz + n1 * n1;
-  for (int t = blockIdx.x; t < nt; t += gridDim.x) {
+  for (int t0 = blockIdx.x * DIAG_TB; t0 < nt; t0 += gridDim.x * DIAG_TB) {
+    const int nb = nt - t0 < DIAG_TB ? nt - t0 : DIAG_TB;
     __syncthreads();
-    for (int i = threadIdx.x; i < nqt * 8; i += 256) sB[i] = geo[size_t(t) * nqt * 8 + i];
+    for (int i = threadIdx.x; i < nb * nqt * 8; i += 256) sB[i] = geo[size_t(t0) * nqt * 8 + i];
     __syncthreads();
-    for (int a = threadIdx.x; a < npt; a += 256) {
+    for (int i = threadIdx.x; i < nb * npt; i += 256) {
+      const int tl = i / npt, a = i - tl * npt;
       double t1 = 0.0, t2 = 0.0, t5 = 0.0, t6 = 0.0;
       for (int q = 0; q < nqt; ++q) {
-        const double* g = sB + q * 8;
+        const double* g = sB + (tl * nqt + q) * 8;
         const double dr = Dr[q * npt + a], ds = Ds[q * npt + a], b = Bt[q * npt + a];
         t1 += dr * (g[0] * dr + 2.0 * g[1] * ds) + ds * g[3] * ds;
         t2 += (g[2] * dr + g[4] * ds) * b;
         t5 += g[5] * b * b;
         t6 += g[6] * b * b;
       }
-      sT[a] = t1;
-      sT[npt + a] = t2;
-      sT[2 * npt + a] = t5;
-      sT[3 * npt + a] = t6;
+      double* T = sT + tl * 4 * npt;
+      T[a] = t1;
+      T[npt + a] = t2;
+      T[2 * npt + a] = t5;
+      T[3 * npt + a] = t6;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < L * npt * n1; i += 256) {
-      const int layer = i / (npt * n1), r = i - layer * npt * n1, a = r / n1, c = r - a * n1;
+    const int per = L * npt * n1;
+    for (int i = threadIdx.x; i < nb * per; i += 256) {
+      const int tl = i / per, rr = i - tl * per;
+      const int layer = rr / (npt * n1), r = rr - layer * npt * n1, a = r / n1, c = r - a * n1;
+      const double* T = sT + tl * 4 * npt;
       double d = 0.0;
       for (int k = 0; k < n1; ++k) {
         const double s = (layer + 0.5 * (1.0 + zq[k])) / L;
         const double bz = Bz[k * n1 + c], dz = Dz[k * n1 + c];
-        d += zw[k] * (bz * bz * sT[a] + 2.0 * bz * dz * s * sT[npt + a] + dz * dz * (s * s * sT[2 * npt + a] + sT[3 * npt + a]));
+        d += zw[k] * (bz * bz * T[a] + 2.0 * bz * dz * s * T[npt + a] + dz * dz * (s * s * T[2 * npt + a] + T[3 * npt + a]));
       }
-      Y[((size_t(t) * npt + a) * L + layer) * n1 + c] = d;
+      Y[((size_t(t0 + tl) * npt + a) * L + layer) * n1 + c] = d;
     }
   }
 }
@@ -505,8 +513,9 @@ __global__ __launch_bounds__(256) void k_diag_col(int nt, int L, int npt, int nq
 void launch_diag_col(const LevelView& lv, const double* mats, const double* zq, const double* zw, const double* geo,
                      double* Y, hipStream_t st) {
   const int npt = lv.np_tri, n1 = lv.PZ + 1, nqt = (lv.P + 1) * (lv.P + 1);
-  const size_t lds = sizeof(double) * (8 * size_t(nqt) + 4 * size_t(npt));
-  const int grid = int(lv.nt < 65536 ? lv.nt : 65536);
+  const size_t lds = sizeof(double) * DIAG_TB * (8 * size_t(nqt) + 4 * size_t(npt));
+  const int nblk = (lv.nt + DIAG_TB - 1) / DIAG_TB;
+  const int grid = nblk < 65536 ? nblk : 65536;
   hipLaunchKernelGGL(k_diag_col, dim3(grid < 1 ? 1 : grid), dim3(256), lds, st, lv.nt, lv.L, npt, nqt, n1, mats, zq,
                      zw, geo, Y);
 }

@@ -733,15 +733,17 @@ __global__ __launch_bounds__(256) void k_g_native(int64_t n_elem, int64_t n_batc
                                                   TO* __restrict__ out, int L, const double* __restrict__ geo,
                                                   const double* __restrict__ zq, const double* __restrict__ zw) {
   using D = MD<PT, PZ>;
-  const int64_t per_batch = int64_t(16) * 6 * D::NQ;
+  // one thread per (batch, k, slot w of a factor's 16 NQT block) writes all six
+  // factors of its cubature point (they are 16 NQT apart)
+  constexpr int64_t MST = int64_t(16) * D::NQT;
+  const int64_t per_batch = D::N1 * MST;
   const int64_t total = n_batch * per_batch;
   for (int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x; i < total; i += int64_t(gridDim.x) * 256) {
     const int64_t b = i / per_batch;
-    int64_t rem = i - b * per_batch;
-    const int k = int(rem / (6 * 16 * D::NQT));
-    rem -= int64_t(k) * 6 * 16 * D::NQT;
-    const int m = int(rem / (16 * D::NQT));
-    int w = int(rem - int64_t(m) * 16 * D::NQT);
+    const int64_t rem = i - b * per_batch;
+    const int k = int(rem / MST);
+    int w = int(rem - int64_t(k) * MST);
+    const int64_t o = (b * D::N1 + k) * 6 * MST + w;
     int q, jj;
     if (w < D::NTF * 256) {
       const int t = w / 256;
@@ -754,19 +756,25 @@ __global__ __launch_bounds__(256) void k_g_native(int64_t n_elem, int64_t n_batc
       jj = w % 16;
     }
     const int64_t e = b * 16 + jj;
-    double v = 0.0;
+    double v[6] = {0, 0, 0, 0, 0, 0};
     if (e < n_elem) {
       if constexpr (COL) {
         const int64_t tri = e / L;
-        const double sg = (double(e - tri * L) + 0.5 * (1.0 + zq[k])) / L;
+        const double sg = (double(e - tri * L) + 0.5 * (1.0 + zq[k])) / L, wk = zw[k];
         const double* bq = geo + (tri * D::NQT + q) * 8;
-        const double f[6] = {bq[0], bq[1], sg * bq[2], bq[3], sg * bq[4], sg * sg * bq[5] + bq[6]};
-        v = zw[k] * f[m];
+        v[0] = wk * bq[0];
+        v[1] = wk * bq[1];
+        v[2] = wk * (sg * bq[2]);
+        v[3] = wk * bq[3];
+        v[4] = wk * (sg * bq[4]);
+        v[5] = wk * (sg * sg * bq[5] + bq[6]);
       } else {
-        v = G[(e * 6 + m) * D::NQ + int64_t(k) * D::NQT + q];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) v[m] = G[(e * 6 + m) * D::NQ + int64_t(k) * D::NQT + q];
       }
     }
-    out[i] = cvt_out<TO>(v);
+#pragma unroll
+    for (int m = 0; m < 6; ++m) out[o + m * MST] = cvt_out<TO>(v[m]);
   }
 }
 
@@ -799,7 +807,7 @@ template <int PT, int PZ>
 static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st, const double* geo,
                        int L, const double* zq, const double* zw) {
   const int64_t nb = (n_elem + 15) / 16;
-  const int64_t total = nb * 16 * 6 * MD<PT, PZ>::NQ;
+  const int64_t total = nb * 16 * MD<PT, PZ>::NQ;
   int64_t grid = (total + 255) / 256;
   if (grid > 65535 * 4) grid = 65535 * 4;
 #define PMG_GN(TO, ROW)                                                                                    \

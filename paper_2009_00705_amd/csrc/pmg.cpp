@@ -96,6 +96,8 @@ struct Level {
   // MFMA element operator (per flavour MF_F64, MF_F32, MF_BF16)
   bool mf[3] = {false, false, false};
   void* gnat[3] = {nullptr, nullptr, nullptr};
+  // gnat[f] no longer matches the level's geometry: rebuilt before its next use
+  bool nat_stale[3] = {false, false, false};
   void* tab2[3] = {nullptr, nullptr, nullptr};
   void* tab4[3] = {nullptr, nullptr, nullptr};
   // lo parts of the BF16 tables (split-BF16 products, MF_BF16X3)
@@ -597,6 +599,20 @@ template <> const void* gptr<float>(pmg_ctx* c, Level& L, int& gs) {
   return c->lowp == G_BF16 ? (const void*)L.G16 : (const void*)L.G32;
 }
 
+// Lane-native copy of G for flavour f: from the stored G64, or formed from the
+// FP64 column factors when the level keeps no stored G.  The copies are built
+// lazily: a surface change marks them stale, and a kernel that reads one
+// rebuilds it first (paths that never read a flavour never pay for it).
+static void native_g(pmg_ctx* c, Level& L, int f, hipStream_t st) {
+  launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st, L.G64 ? nullptr : L.geo64, L.view.L, L.zq,
+                  L.zw);
+}
+static void ensure_native(pmg_ctx* c, Level& L, int f, hipStream_t st) {
+  if (!L.nat_stale[f]) return;
+  native_g(c, L, f, st);
+  L.nat_stale[f] = false;
+}
+
 template <typename T>
 static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
   Level& L = c->lv[i];
@@ -610,11 +626,13 @@ static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
     const bool col = c->opt.geometry == PMG_GEOM_COLUMN && L.geo64;
     const void* geo = !col ? nullptr : (sizeof(T) == 8 ? (const void*)L.geo64 : (const void*)L.geo32);
     if (f == MF_BF16 && c->bf16x3 && L.mfx3) {
+      if (!geo) ensure_native(c, L, MF_BF16, st);
       launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X3, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
                      L.tab2lo, L.tab4lo, geo);
       return;
     }
     if (f == MF_BF16 && c->bf16x2 && mfma_available(L.P, L.PZ, MF_BF16X2)) {
+      if (!geo) ensure_native(c, L, MF_BF16, st);
       launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X2, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
                      nullptr, nullptr, geo);
       return;
@@ -623,9 +641,11 @@ static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
       // FP32 arithmetic on the stored BF16 copy of G (FP32 tables); at in-plane
       // order 3 this is faster than forming G from the column factors, whose
       // kernel holds more registers
+      ensure_native(c, L, MF_BF16, st);
       launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_F32G16, L.tab2[MF_F32], L.tab4[MF_F32], vm, x, c->Y, st);
       return;
     }
+    if (f == MF_BF16 || !geo) ensure_native(c, L, f, st);
     launch_ax_mfma(L.view, L.gnat[f], f, L.tab2[f], L.tab4[f], vm, x, c->Y, st, nullptr, nullptr,
                    f == MF_BF16 ? nullptr : geo);
     return;
@@ -1194,13 +1214,6 @@ static void schwarz_setup(pmg_ctx* c, hipStream_t st, int i0 = 0) {
 // ---------------------------------------------------------------------------
 static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st);
 
-// Lane-native copy of G for flavour f: from the stored G64, or formed from the
-// FP64 column factors when the level keeps no stored G.
-static void native_g(pmg_ctx* c, Level& L, int f, hipStream_t st) {
-  launch_g_native(L.P, L.PZ, L.num.n_elem, L.G64, L.gnat[f], f, st, L.G64 ? nullptr : L.geo64, L.view.L, L.zq,
-                  L.zw);
-}
-
 // Diagonal (and its inverses) of one level from its current G64, or from its
 // column factors when it keeps no stored G.
 static void level_diag(pmg_ctx* c, Level& L, hipStream_t st) {
@@ -1225,7 +1238,7 @@ static int level_geom(pmg_ctx* c, int i, const double* eta, bool lowp, int flavo
   HIPCHK(hipStreamSynchronize(st));
   if (bad) return bad;
   for (int f = 0; f < 3; ++f)
-    if (L.mf[f] && L.gnat[f] && ((flavours >> f) & 1)) native_g(c, L, f, st);
+    if (L.mf[f] && L.gnat[f] && ((flavours >> f) & 1)) L.nat_stale[f] = true;
   return 0;
 }
 
@@ -1292,7 +1305,7 @@ static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st) {
   for (int i = 0; i < c->nl; ++i) {
     Level& L = c->lv[i];
     for (int f = 0; f < 3; ++f)
-      if (L.mf[f] && L.gnat[f]) native_g(c, L, f, st);
+      if (L.mf[f] && L.gnat[f]) L.nat_stale[f] = true;
   }
   // Jacobi diagonals
   for (int i = 0; i < c->nl; ++i) level_diag(c, c->lv[i], st);
@@ -2330,6 +2343,9 @@ int pmg_set_reuse(pmg_ctx* c, int mode, void* stream) {
     hipStream_t st = S(stream);
     if (mode != PMG_REUSE_NONE) {
       fnpf_freeze(c);
+      // the kept preconditioner includes the native copies of the current surface
+      for (int i = 0; i < c->nl; ++i)
+        for (int f = 0; f < 3; ++f) ensure_native(c, c->lv[i], f, st);
       if (mode == PMG_REUSE_LIN) {
         const int64_t n2 = c->lv[0].num.n2d;
         if (!c->eta_flat) {
