@@ -455,11 +455,6 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
     }
     L.mf[f] = true;
   }
-  if (c->opt.geometry == PMG_GEOM_COLUMN && (L.mf[MF_F64] || L.mf[MF_F32])) {
-    const size_t n = size_t(c->mesh.nt) * re.nq_tri * 8;
-    L.geo64 = c->A<double>(n);
-    L.geo32 = c->A<float>(n);
-  }
 }
 
 static void upload_levels(pmg_ctx* c) {
@@ -495,6 +490,12 @@ static void upload_levels(pmg_ctx* c) {
       L.G64 = c->A<double>(size_t(E) * 6 * re.nq);
       L.G32 = c->A<float>(size_t(E) * 6 * re.nq);
       L.G16 = c->A<bf16_t>(size_t(E) * 6 * re.nq);
+    }
+    // column factors of every level (the MFMA operators and the diagonal read them)
+    if (c->opt.geometry == PMG_GEOM_COLUMN) {
+      const size_t n = size_t(c->mesh.nt) * re.nq_tri * 8;
+      L.geo64 = c->A<double>(n);
+      L.geo32 = c->A<float>(n);
     }
     L.diag = c->A<double>(N);
     L.dinv64 = c->A<double>(N);
@@ -1214,11 +1215,11 @@ static void schwarz_setup(pmg_ctx* c, hipStream_t st, int i0 = 0) {
 // ---------------------------------------------------------------------------
 static void set_surface_all(pmg_ctx* c, const double* eta, hipStream_t st);
 
-// Diagonal (and its inverses) of one level from its current G64, or from its
-// column factors when it keeps no stored G.
+// Diagonal (and its inverses) of one level from its column factors, or from its
+// stored G64 without them.
 static void level_diag(pmg_ctx* c, Level& L, hipStream_t st) {
-  if (L.G64) launch_diag(L.view, L.mats64, L.G64, c->Y, st);
-  else launch_diag_col(L.view, L.mats64, L.zq, L.zw, L.geo64, c->Y, st);
+  if (L.geo64) launch_diag_col(L.view, L.mats64, L.zq, L.zw, L.geo64, c->Y, st);
+  else launch_diag(L.view, L.mats64, L.G64, c->Y, st);
   launch_assemble<double>(L.view, OP_RAW, c->Y, L.diag, nullptr, nullptr, nullptr, 0, 0, nullptr, st);
   launch_dinv<double>(L.view, nullptr, L.diag, L.dinv64, st);
   launch_dinv<float>(L.view, nullptr, L.diag, L.dinv32, st);
