@@ -416,107 +416,6 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
   }
 }
 
-// BF16 operands, FP32 accumulation (K = 16)
-template <int PT, int PZ, typename TG>
-__global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
-                                                             int64_t n_elem, int64_t n_batch,
-                                                             const TG* __restrict__ Gnat,
-                                                             const s4_t* __restrict__ tab2,
-                                                             const s4_t* __restrict__ tab4, VertMats<float> vm,
-                                                             const float* __restrict__ u, float* __restrict__ Y) {
-  using D = MD<PT, PZ>;
-  constexpr int N1 = D::N1, NPT = D::NPT, NP = NPT * N1, NT2 = D::NT2, KS16 = D::KS16, NAT = D::NAT;
-  constexpr int NTAB2 = 3 * NT2 * KS16 * 64, NTAB4 = 3 * NAT * NT2 * 64;
-  constexpr int NTH = 64 * N1;
-  __shared__ s4_t s2[NTAB2];
-  __shared__ s4_t s4[NTAB4];
-  __shared__ float sR[KS_LDS<PT, PZ>::R_WORDS];
-  __shared__ float sV[2 * N1 * N1];
-  for (int i = threadIdx.x; i < NTAB2; i += NTH) s2[i] = tab2[i];
-  for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
-  for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
-  const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
-  const int64_t lb = xcd_block(gridDim.x);
-  for (int64_t b = lb; b < n_batch; b += gridDim.x) {
-    __syncthreads();
-    stage_u<PT, PZ, float>(map2d, L, nz, n_elem, b, u, sR);
-    __syncthreads();
-    s4_t w[KS16], wz[KS16];
-#pragma unroll
-    for (int s = 0; s < KS16; ++s)
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int a = 16 * s + 4 * g + kk;
-        float a0 = 0.f, a1 = 0.f;
-        if (a < NPT) {
-#pragma unroll
-          for (int c = 0; c < N1; ++c) {
-            const float uv = sR[(c * NPT + a) * 16 + j];
-            a0 += sV[k * N1 + c] * uv;
-            a1 += sV[N1 * N1 + k * N1 + c] * uv;
-          }
-        }
-        w[s][kk] = f2bf(a0);
-        wz[s][kk] = f2bf(a1);
-      }
-    __syncthreads();
-    f4_t yr[NAT], yt[NAT];
-#pragma unroll
-    for (int at = 0; at < NAT; ++at) { yr[at] = f4_t{0, 0, 0, 0}; yt[at] = f4_t{0, 0, 0, 0}; }
-#pragma unroll 1
-    for (int t = 0; t < NT2; ++t) {
-      float gv[6][4];
-      const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
-      const int64_t mst = 16 * D::NQT;
-      if (t < D::NTF) {
-#pragma unroll
-        for (int m = 0; m < 6; ++m)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) gv[m][r] = gld<TG>(Gnat, blk + m * mst + t * 256 + lane * 4 + r);
-      } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int row = 4 * g + r;
-#pragma unroll
-          for (int m = 0; m < 6; ++m)
-            gv[m][r] = row < D::NQR ? gld<TG>(Gnat, blk + m * mst + D::NTF * 256 + row * 16 + j) : 0.f;
-        }
-      }
-      f4_t dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < KS16; ++s) {
-        dr = mfma16(s2[((0 * NT2 + t) * KS16 + s) * 64 + lane], w[s], dr);
-        ds = mfma16(s2[((1 * NT2 + t) * KS16 + s) * 64 + lane], w[s], ds);
-        db = mfma16(s2[((2 * NT2 + t) * KS16 + s) * 64 + lane], wz[s], db);
-      }
-      s4_t br, bs, bt;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float ur = dr[r], us = ds[r], ut = db[r];
-        br[r] = f2bf(gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut);
-        bs[r] = f2bf(gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut);
-        bt[r] = f2bf(gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut);
-      }
-#pragma unroll
-      for (int at = 0; at < NAT; ++at) {
-        yr[at] = mfma16(s4[((0 * NAT + at) * NT2 + t) * 64 + lane], br, yr[at]);
-        yr[at] = mfma16(s4[((1 * NAT + at) * NT2 + t) * 64 + lane], bs, yr[at]);
-        yt[at] = mfma16(s4[((2 * NAT + at) * NT2 + t) * 64 + lane], bt, yt[at]);
-      }
-    }
-#pragma unroll
-    for (int at = 0; at < NAT; ++at)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int a = 16 * at + 4 * g + r;
-        sR[((k * 2 + 0) * NAT * 16 + a) * 16 + j] = yr[at][r];
-        sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
-      }
-    __syncthreads();
-    vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
-  }
-}
-
 // BF16 G of q tile t for lane (g, j), rows 4g+r (r = 0..3), packed two per word
 // (low half = even r): one 8-byte load per factor on full tiles; rows past the
 // last q of the remainder tile read as 0.
@@ -543,6 +442,128 @@ __device__ __forceinline__ void load_g_bf16(const bf16_t* __restrict__ Gnat, int
       gw[m][0] = h[0] | (h[1] << 16);
       gw[m][1] = h[2] | (h[3] << 16);
     }
+  }
+}
+
+// BF16 operands, FP32 accumulation (K = 16)
+template <int PT, int PZ, typename TG>
+__global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
+                                                             int64_t n_elem, int64_t n_batch,
+                                                             const TG* __restrict__ Gnat,
+                                                             const s4_t* __restrict__ tab2,
+                                                             const s4_t* __restrict__ tab4, VertMats<float> vm,
+                                                             const float* __restrict__ u, float* __restrict__ Y) {
+  using D = MD<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NP = NPT * N1, NT2 = D::NT2, KS16 = D::KS16, NAT = D::NAT;
+  constexpr int NTAB2 = 3 * NT2 * KS16 * 64, NTAB4 = 3 * NAT * NT2 * 64;
+  constexpr int NTH = 64 * N1;
+  __shared__ s4_t s2[NTAB2];
+  __shared__ s4_t s4[NTAB4];
+  __shared__ float sR[KS_LDS<PT, PZ>::R_WORDS];
+  __shared__ float sV[2 * N1 * N1];
+  for (int i = threadIdx.x; i < NTAB2; i += NTH) s2[i] = tab2[i];
+  for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
+  for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
+  const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
+  const int64_t lb = xcd_block(gridDim.x);
+  for (int64_t b = lb; b < n_batch; b += gridDim.x) {
+    __syncthreads();
+    // G of tile t as raw BF16 pairs (PF: one tile ahead, the first under the
+    // staging of u and stage 1, as in the split-BF16 kernel; measured faster at
+    // P = 6 only: 190 -> 180 us, while the smaller and the P = 8 orders lost)
+    constexpr bool PF = PT == 6;
+    const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
+    constexpr int64_t mst = 16 * D::NQT;
+    uint32_t gw[6][2];
+    if constexpr (PF) load_g_bf16<PT, PZ>(Gnat, blk, mst, 0, lane, g, j, gw);
+    stage_u<PT, PZ, float>(map2d, L, nz, n_elem, b, u, sR);
+    __syncthreads();
+    s4_t w[KS16], wz[KS16];
+#pragma unroll
+    for (int s = 0; s < KS16; ++s)
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) {
+        const int a = 16 * s + 4 * g + kk;
+        float a0 = 0.f, a1 = 0.f;
+        if (a < NPT) {
+#pragma unroll
+          for (int c = 0; c < N1; ++c) {
+            const float uv = sR[(c * NPT + a) * 16 + j];
+            a0 += sV[k * N1 + c] * uv;
+            a1 += sV[N1 * N1 + k * N1 + c] * uv;
+          }
+        }
+        w[s][kk] = f2bf(a0);
+        wz[s][kk] = f2bf(a1);
+      }
+    __syncthreads();
+    f4_t yr[NAT], yt[NAT];
+#pragma unroll
+    for (int at = 0; at < NAT; ++at) { yr[at] = f4_t{0, 0, 0, 0}; yt[at] = f4_t{0, 0, 0, 0}; }
+#pragma unroll 1
+    for (int t = 0; t < NT2; ++t) {
+      uint32_t gc[6][2];
+      float gd[6][4];
+      if constexpr (PF) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) { gc[m][0] = gw[m][0]; gc[m][1] = gw[m][1]; }
+        if (t + 1 < NT2) load_g_bf16<PT, PZ>(Gnat, blk, mst, t + 1, lane, g, j, gw);
+      } else if (t < D::NTF) {
+#pragma unroll
+        for (int m = 0; m < 6; ++m)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) gd[m][r] = gld<TG>(Gnat, blk + m * mst + t * 256 + lane * 4 + r);
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 4 * g + r;
+#pragma unroll
+          for (int m = 0; m < 6; ++m)
+            gd[m][r] = row < D::NQR ? gld<TG>(Gnat, blk + m * mst + D::NTF * 256 + row * 16 + j) : 0.f;
+        }
+      }
+      f4_t dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS16; ++s) {
+        dr = mfma16(s2[((0 * NT2 + t) * KS16 + s) * 64 + lane], w[s], dr);
+        ds = mfma16(s2[((1 * NT2 + t) * KS16 + s) * 64 + lane], w[s], ds);
+        db = mfma16(s2[((2 * NT2 + t) * KS16 + s) * 64 + lane], wz[s], db);
+      }
+      s4_t br, bs, bt;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float ur = dr[r], us = ds[r], ut = db[r];
+        float gv[6][4];
+#pragma unroll
+        for (int m = 0; m < 6; ++m) {
+          if constexpr (PF) {
+            const uint32_t wv = gc[m][r >> 1];
+            gv[m][r] = __uint_as_float((r & 1) ? (wv & 0xFFFF0000u) : (wv << 16));
+          } else {
+            gv[m][r] = gd[m][r];
+          }
+        }
+        br[r] = f2bf(gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut);
+        bs[r] = f2bf(gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut);
+        bt[r] = f2bf(gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut);
+      }
+#pragma unroll
+      for (int at = 0; at < NAT; ++at) {
+        yr[at] = mfma16(s4[((0 * NAT + at) * NT2 + t) * 64 + lane], br, yr[at]);
+        yr[at] = mfma16(s4[((1 * NAT + at) * NT2 + t) * 64 + lane], bs, yr[at]);
+        yt[at] = mfma16(s4[((2 * NAT + at) * NT2 + t) * 64 + lane], bt, yt[at]);
+      }
+    }
+#pragma unroll
+    for (int at = 0; at < NAT; ++at)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int a = 16 * at + 4 * g + r;
+        sR[((k * 2 + 0) * NAT * 16 + a) * 16 + j] = yr[at][r];
+        sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
+      }
+    __syncthreads();
+    vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
   }
 }
 
