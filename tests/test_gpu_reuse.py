@@ -61,3 +61,40 @@ def test_reuse_mode_parity(case, mode):
     assert rc == 0 and st["iters"] == ref.iters, (st["iters"], ref.iters)
     assert rel_err(host(phi), ref.phi) < 1e-10
     ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["bf16g", "fp32", "bf16x3", "bf16"])
+def test_t0_keeps_the_finest_low_precision_operator(prec):
+    """Strategy I keeps the finest level's low-precision factors of the surface
+    current when the mode is set (the native BF16 copies are built lazily, so
+    setting the mode must build the pending ones first), while its FP64
+    factors follow every surface: after a surface change the low-precision
+    operator is bitwise the one of a context left at the first surface, and
+    the FP64 operator that of a context set to the new one."""
+    import torch
+    from gpu_common import surface_eta
+    from paper_2009_00705_amd import pmg
+    mk, P, kw = CASES["box5x5_L3_P6_xy"]
+    mesh = mk()
+    a, b, c = (pmg.Context(mesh, P=P, **kw) for _ in range(3))
+    xy = a.surface_xy()
+    eta1, eta2 = dev(surface_eta(xy, "wavy")), dev(_eta2(xy))
+    a.set_surface(eta1)
+    b.set_surface(eta1)
+    c.set_surface(eta2)
+    a.set_reuse("t0")
+    a.set_surface(eta2)
+    n = a.levels[0]["n_dof"]
+    x32 = dev(W.random_vector(n, 21), torch.float32)
+    ya, yb = (torch.empty(n, dtype=torch.float32, device="cuda") for _ in range(2))
+    a.apply(0, x32, ya, prec)
+    b.apply(0, x32, yb, prec)
+    torch.cuda.synchronize()
+    assert torch.equal(ya, yb), prec
+    x64 = dev(W.random_vector(n, 22))
+    za, zc = (torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(2))
+    a.apply(0, x64, za, "fp64")
+    c.apply(0, x64, zc, "fp64")
+    assert rel_err(host(za), host(zc)) < 1e-13
+    for ctx in (a, b, c):
+        ctx.close()
