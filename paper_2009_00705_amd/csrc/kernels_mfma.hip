@@ -70,6 +70,26 @@ __device__ __forceinline__ short f2bf(float f) {
   u += 0x7FFFu + ((u >> 16) & 1u);
   return short(u >> 16);
 }
+// Packed rounding to BF16 (nearest even) on the gfx950 conversion unit: one
+// v_cvt_pk_bf16_f32 per pair, low half = first value.  Same result as f2bf for
+// every finite input; used where the rounding sits in the kernels' inner loops.
+typedef __bf16 bf2_t __attribute__((ext_vector_type(2)));
+typedef float fv2_t __attribute__((ext_vector_type(2)));
+typedef uint32_t u2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf2(float x0, float x1) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector(fv2_t{x0, x1}, bf2_t));
+}
+__device__ __forceinline__ s4_t bf4(const float (&x)[4]) {
+  return __builtin_bit_cast(s4_t, u2_t{bf2(x[0], x[1]), bf2(x[2], x[3])});
+}
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi), four values at once
+__device__ __forceinline__ void split4(const float (&x)[4], s4_t& hi, s4_t& lo) {
+  const uint32_t h01 = bf2(x[0], x[1]), h23 = bf2(x[2], x[3]);
+  const float d[4] = {x[0] - __uint_as_float(h01 << 16), x[1] - __uint_as_float(h01 & 0xFFFF0000u),
+                      x[2] - __uint_as_float(h23 << 16), x[3] - __uint_as_float(h23 & 0xFFFF0000u)};
+  hi = __builtin_bit_cast(s4_t, u2_t{h01, h23});
+  lo = bf4(d);
+}
 template <typename TG> __device__ __forceinline__ float gld(const TG* p, size_t i);
 template <> __device__ __forceinline__ float gld<float>(const float* p, size_t i) { return p[i]; }
 template <> __device__ __forceinline__ float gld<bf16_t>(const bf16_t* p, size_t i) {
@@ -190,8 +210,10 @@ __device__ __forceinline__ void load_rem(const TG* __restrict__ G, int64_t blk, 
 }
 // Geometric factors of q tile t computed from the column factors (see
 // launch_geom): lane rows q = 16 t + row(g, r) of triangle tri; p = zw_k,
-// ps = zw_k s, ps2 = zw_k s^2 for the lane's layer.  Rows past the last q, and
-// lanes past the last element (tri < 0), get 0.
+// ps = zw_k s, ps2 = zw_k s^2 for the lane's layer.  Every load is in bounds
+// and unpredicated: rows past the last q read the last row (the operand tables
+// are zero there, so those rows of the products are exactly zero), and lanes
+// past the last element (tri < 0, p = ps = ps2 = 0) read triangle 0 and get 0.
 __device__ __forceinline__ void load8(const double* p, double (&b)[8]) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
@@ -214,16 +236,12 @@ template <typename T, int PT, int PZ, bool F64ROW>
 __device__ __forceinline__ void load_geo(const T* __restrict__ geo, int64_t tri, int t, int g, T p, T ps, T ps2,
                                          T (&gv)[6][4]) {
   using D = MD<PT, PZ>;
+  const int64_t tc = tri >= 0 ? tri : 0;
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int q = 16 * t + row_of<F64ROW>(g, r);
     T bq[8];
-    if (tri >= 0 && q < D::NQT) {
-      load8(geo + (tri * D::NQT + q) * 8, bq);
-    } else {
-#pragma unroll
-      for (int m = 0; m < 8; ++m) bq[m] = T(0);
-    }
+    load8(geo + (tc * D::NQT + (q < D::NQT ? q : D::NQT - 1)) * 8, bq);
     gv[0][r] = p * bq[0];
     gv[1][r] = p * bq[1];
     gv[2][r] = ps * bq[2];
@@ -480,22 +498,25 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
     __syncthreads();
     s4_t w[KS16], wz[KS16];
 #pragma unroll
-    for (int s = 0; s < KS16; ++s)
+    for (int s = 0; s < KS16; ++s) {
+      float a0[4], a1[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int a = 16 * s + 4 * g + kk;
-        float a0 = 0.f, a1 = 0.f;
+        a0[kk] = 0.f;
+        a1[kk] = 0.f;
         if (a < NPT) {
 #pragma unroll
           for (int c = 0; c < N1; ++c) {
             const float uv = sR[(c * NPT + a) * 16 + j];
-            a0 += sV[k * N1 + c] * uv;
-            a1 += sV[N1 * N1 + k * N1 + c] * uv;
+            a0[kk] += sV[k * N1 + c] * uv;
+            a1[kk] += sV[N1 * N1 + k * N1 + c] * uv;
           }
         }
-        w[s][kk] = f2bf(a0);
-        wz[s][kk] = f2bf(a1);
       }
+      w[s] = bf4(a0);
+      wz[s] = bf4(a1);
+    }
     __syncthreads();
     f4_t yr[NAT], yt[NAT];
 #pragma unroll
@@ -529,7 +550,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
         ds = mfma16(s2[((1 * NT2 + t) * KS16 + s) * 64 + lane], w[s], ds);
         db = mfma16(s2[((2 * NT2 + t) * KS16 + s) * 64 + lane], wz[s], db);
       }
-      s4_t br, bs, bt;
+      float pr[4], ps[4], pt[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float ur = dr[r], us = ds[r], ut = db[r];
@@ -543,10 +564,11 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
             gv[m][r] = gd[m][r];
           }
         }
-        br[r] = f2bf(gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut);
-        bs[r] = f2bf(gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut);
-        bt[r] = f2bf(gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut);
+        pr[r] = gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut;
+        ps[r] = gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut;
+        pt[r] = gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut;
       }
+      const s4_t br = bf4(pr), bs = bf4(ps), bt = bf4(pt);
 #pragma unroll
       for (int at = 0; at < NAT; ++at) {
         yr[at] = mfma16(s4[((0 * NAT + at) * NT2 + t) * 64 + lane], br, yr[at]);
@@ -580,11 +602,6 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
 //   perturbation of the reference matrices, as G's rounding is of the
 //   geometry) and only the vectors are split: a_hi b_hi + a_hi b_lo, two BF16
 //   MFMAs, the LDS of the plain BF16 kernel.
-__device__ __forceinline__ void split_bf(float x, short& hi, short& lo) {
-  hi = f2bf(x);
-  lo = f2bf(x - __uint_as_float(uint32_t(uint16_t(hi)) << 16));
-}
-
 // GEO: G in FP32 from the FP32 column factors (Gsrc = geo[t][q][8]) instead of
 // the stored lane-native BF16 G (Gsrc = Gnat).
 template <int PT, int PZ, bool LO, bool GEO = false>
@@ -636,27 +653,25 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
     __syncthreads();
     s4_t wh[KS16], wl[KS16], zh[KS16], zl[KS16];
 #pragma unroll
-    for (int s = 0; s < KS16; ++s)
+    for (int s = 0; s < KS16; ++s) {
+      float a0[4], a1[4];
 #pragma unroll
       for (int kk = 0; kk < 4; ++kk) {
         const int a = 16 * s + 4 * g + kk;
-        float a0 = 0.f, a1 = 0.f;
+        a0[kk] = 0.f;
+        a1[kk] = 0.f;
         if (a < NPT) {
 #pragma unroll
           for (int c = 0; c < N1; ++c) {
             const float uv = sR[(c * NPT + a) * 16 + j];
-            a0 += sV[k * N1 + c] * uv;
-            a1 += sV[N1 * N1 + k * N1 + c] * uv;
+            a0[kk] += sV[k * N1 + c] * uv;
+            a1[kk] += sV[N1 * N1 + k * N1 + c] * uv;
           }
         }
-        short h0, l0, h1, l1;
-        split_bf(a0, h0, l0);
-        split_bf(a1, h1, l1);
-        wh[s][kk] = h0;
-        wl[s][kk] = l0;
-        zh[s][kk] = h1;
-        zl[s][kk] = l1;
       }
+      split4(a0, wh[s], wl[s]);
+      split4(a1, zh[s], zl[s]);
+    }
     __syncthreads();
     f4_t yr[NAT], yt[NAT];
 #pragma unroll
@@ -689,7 +704,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
           db = mfma16(s2l[i2], zh[s], db);
         }
       }
-      s4_t rh, rl, sh, sl, th, tl;
+      float pr[4], ps[4], pt[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float ur = dr[r], us = ds[r], ut = db[r];
@@ -703,17 +718,14 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
             gv[m][r] = __uint_as_float((r & 1) ? (wv & 0xFFFF0000u) : (wv << 16));
           }
         }
-        short h, l;
-        split_bf(gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut, h, l);
-        rh[r] = h;
-        rl[r] = l;
-        split_bf(gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut, h, l);
-        sh[r] = h;
-        sl[r] = l;
-        split_bf(gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut, h, l);
-        th[r] = h;
-        tl[r] = l;
+        pr[r] = gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut;
+        ps[r] = gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut;
+        pt[r] = gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut;
       }
+      s4_t rh, rl, sh, sl, th, tl;
+      split4(pr, rh, rl);
+      split4(ps, sh, sl);
+      split4(pt, th, tl);
 #pragma unroll
       for (int at = 0; at < NAT; ++at) {
         const int i0 = ((0 * NAT + at) * NT2 + t) * 64 + lane, i1 = ((1 * NAT + at) * NT2 + t) * 64 + lane,
