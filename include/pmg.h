@@ -121,7 +121,7 @@ typedef struct pmg_mesh {
   int32_t ncurved;
   const int32_t* curved_edge;/* [ncurved][2] vertex pairs on a circle (nullable) */
   const double* circle;      /* [ncurved][3] cx, cy, R (nullable)               */
-  int32_t n_layers;
+  int32_t n_layers;          /* >= 1; nt * n_layers < 2^31 prisms (PMG_EINVAL otherwise) */
   double depth;
 } pmg_mesh;
 

@@ -129,9 +129,49 @@ template <int PT, int PZ> struct KS_LDS {
   static constexpr int R_WORDS = U_WORDS > S_WORDS ? U_WORDS : S_WORDS;
 };
 
+// (triangle, layer) of prism e = 16 b + j of a batch; te = -1 past the last
+// prism.  Every thread with lane % 16 == j stages and writes this slot (the
+// workgroup is a multiple of 16 threads), so one 32-bit division per batch
+// serves stage_u, geo_lane and vertical_out (launch_ax_mfma requires fewer
+// than 2^31 prisms).
+struct ColSlot {
+  int te, layer;
+};
+__device__ __forceinline__ ColSlot col_slot(int64_t b, int j, int64_t n_elem, int L) {
+  const int64_t e = b * 16 + j;
+  if (e >= n_elem) return ColSlot{-1, 0};
+  const uint32_t eu = uint32_t(e), te = eu / uint32_t(L);
+  return ColSlot{int(te), int(eu - te * uint32_t(L))};
+}
+
 // Stage the 16 prisms' nodal values: U[c][a][el] = u[map2d[t][a] nz + layer PZ + c].
 // One thread per (a, el) pair: one map read, then the PZ+1 vertical values of
-// the column issued together (independent loads, a single wait).
+// the column issued together (independent loads, a single wait).  cs: the
+// thread's column slot (el = lane % 16).
+template <int PT, int PZ, typename T>
+__device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int nz, ColSlot cs,
+                                        const T* __restrict__ u, T* __restrict__ sR) {
+  using D = MD<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NTH = 64 * N1;
+  static_assert(NTH % 16 == 0, "pr & 15 must be the lane's slot");
+  for (int pr = threadIdx.x; pr < 16 * NPT; pr += NTH) {
+    const int a = pr >> 4, el = pr & 15;
+    T v[N1];
+    if (cs.te >= 0) {
+      const T* col = u + int64_t(map2d[size_t(cs.te) * NPT + a]) * nz + cs.layer * PZ;
+#pragma unroll
+      for (int c = 0; c < N1; ++c) v[c] = col[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < N1; ++c) v[c] = T(0);
+    }
+#pragma unroll
+    for (int c = 0; c < N1; ++c) sR[(c * NPT + a) * 16 + el] = v[c];
+  }
+}
+// Per-use form for the BF16 and split-BF16 kernels: the slot is derived where it
+// is used, so it is not held across the batch (at their 128-VGPR cap that costs
+// more than the repeated division: 189 -> 208 us for the split kernel at c3).
 template <int PT, int PZ, typename T>
 __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L, int nz, int64_t n_elem,
                                         int64_t b, const T* __restrict__ u, T* __restrict__ sR) {
@@ -159,6 +199,31 @@ __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L
 // Dz[k][c] Yt[k][a], with S[k][h][a][el] in LDS.  One thread per (a, el) pair
 // reads its 2(PZ+1) partials once and writes the PZ+1 contiguous outputs of its
 // column slot in the E-layout [t][a][layer][c].
+template <int PT, int PZ, typename T>
+__device__ __forceinline__ void vertical_out(int L, ColSlot cs, const T* __restrict__ sR,
+                                             const T* __restrict__ sV, T* __restrict__ Y) {
+  using D = MD<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NAT = D::NAT, NTH = 64 * N1;
+  if (cs.te < 0) return;
+  for (int pr = threadIdx.x; pr < 16 * NPT; pr += NTH) {
+    const int a = pr >> 4, el = pr & 15;
+    T yr[N1], yt[N1];
+#pragma unroll
+    for (int kk = 0; kk < N1; ++kk) {
+      yr[kk] = sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el];
+      yt[kk] = sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
+    }
+    T* out = Y + ((size_t(cs.te) * NPT + a) * L + cs.layer) * N1;
+    // rolled: the coefficients are LDS broadcasts read per c, not 2(PZ+1)^2 registers
+#pragma unroll 1
+    for (int c = 0; c < N1; ++c) {
+      T y = 0;
+#pragma unroll
+      for (int kk = 0; kk < N1; ++kk) y += sV[kk * N1 + c] * yr[kk] + sV[N1 * N1 + kk * N1 + c] * yt[kk];
+      out[c] = y;
+    }
+  }
+}
 template <int PT, int PZ, typename T>
 __device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, const T* __restrict__ sR,
                                              const T* __restrict__ sV, T* __restrict__ Y) {
@@ -250,7 +315,19 @@ __device__ __forceinline__ void load_geo(const T* __restrict__ geo, int64_t tri,
     gv[5][r] = ps2 * bq[5] + p * bq[6];
   }
 }
-// per-lane constants of load_geo for element e = 16 b + j at vertical Gauss point k
+// per-lane constants of load_geo for the lane's column slot at vertical Gauss point k
+template <typename T>
+__device__ __forceinline__ void geo_lane(ColSlot cs, int L, T zw, T zh, int64_t& tri, T& p, T& ps, T& ps2) {
+  tri = -1;
+  p = ps = ps2 = T(0);
+  if (cs.te >= 0) {
+    tri = cs.te;
+    const T sg = (T(cs.layer) + zh) / T(L);
+    p = zw;
+    ps = zw * sg;
+    ps2 = ps * sg;
+  }
+}
 template <typename T>
 __device__ __forceinline__ void geo_lane(int64_t e, int64_t n_elem, int L, T zw, T zh, int64_t& tri, T& p, T& ps,
                                          T& ps2) {
@@ -316,7 +393,8 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();  // previous batch's phase 2 done with sR
     // phase 0: U[c][a][el] <- u
-    stage_u<PT, PZ, T>(map2d, L, nz, n_elem, b, u, sR);
+    const ColSlot cs = col_slot(b, j, n_elem, L);
+    stage_u<PT, PZ, T>(map2d, nz, cs, u, sR);
     __syncthreads();
     // phase 1, stage 1: W[k][a], Wz[k][a] for a = 4s + g of element j
     T w[KS], wz[KS];
@@ -343,7 +421,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     constexpr int64_t MST = 16 * D::NQT;
     int64_t tri;
     T gp, gps, gps2;
-    if constexpr (GEO) geo_lane<T>(b * 16 + j, n_elem, L, vm.zw[k], vm.zh[k], tri, gp, gps, gps2);
+    if constexpr (GEO) geo_lane<T>(cs, L, vm.zw[k], vm.zh[k], tri, gp, gps, gps2);
     T ga[6][4];
 #pragma unroll 1
     for (int t = 0; t < D::NTF; ++t) {
@@ -430,7 +508,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
       }
     __syncthreads();
     // phase 2: y[el][c][a] = sum_k Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]
-    vertical_out<PT, PZ, T>(L, n_elem, b, sR, sV, Y);
+    vertical_out<PT, PZ, T>(L, cs, sR, sV, Y);
   }
 }
 

@@ -1870,6 +1870,7 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (o->P < 1 || o->P > 8) throw Error(PMG_EINVAL, "P must be in 1..8");
     if (m->nv < 3 || m->nt < 1 || !m->xy || !m->tri || m->n_layers < 1 || !(m->depth > 0))
       throw Error(PMG_EINVAL, "bad mesh sizes");
+    if (int64_t(m->nt) * m->n_layers >= (int64_t(1) << 31)) throw Error(PMG_EINVAL, "2^31 or more prisms");
     if (o->nu1 < 0 || o->nu2 < 0) throw Error(PMG_EINVAL, "negative sweep count");
     if (o->precision < 0 || o->precision > 5) throw Error(PMG_EINVAL, "bad precision");
     if (o->krylov < 0 || o->krylov > 3) throw Error(PMG_EINVAL, "bad krylov method");

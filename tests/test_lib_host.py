@@ -159,6 +159,11 @@ def test_create_rejects_bad_input():
     with pytest.raises(pmg.PmgError) as e:
         pmg.Context(m, P=9, host_only=1)
     assert e.value.code == -1
+    big = dict(m)
+    big["n_layers"] = (1 << 31) // len(m["tri"]) + 1   # 2^31 or more prisms
+    with pytest.raises(pmg.PmgError) as e:
+        pmg.Context(big, P=2, host_only=1)
+    assert e.value.code == -1
     bad = dict(m)
     bad["tri"] = m["tri"][:, [0, 2, 1]]       # clockwise triangles
     with pytest.raises(pmg.PmgError) as e:
