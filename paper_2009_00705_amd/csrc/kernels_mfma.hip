@@ -675,7 +675,8 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
 //   copies of the BF16-layout tables, both in LDS (78 KB at P = 6, two
 //   workgroups per CU within 128 VGPRs).  At P = 6 it is the fastest FP32-
 //   accurate operator: its matrix-core time is a fraction of the FP32 MFMA's,
-//   and the kernel is bound by memory latency and barriers instead.
+//   and the kernel is bound by vector-ALU issue instead (hi/lo splits,
+//   pointwise products, the vertical contractions), not by memory.
 // !LO: the reference tables are rounded to BF16 once (a fixed, symmetric
 //   perturbation of the reference matrices, as G's rounding is of the
 //   geometry) and only the vectors are split: a_hi b_hi + a_hi b_lo, two BF16
