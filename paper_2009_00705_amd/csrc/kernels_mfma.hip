@@ -132,8 +132,8 @@ template <int PT, int PZ> struct KS_LDS {
 // (triangle, layer) of prism e = 16 b + j of a batch; te = -1 past the last
 // prism.  Every thread with lane % 16 == j stages and writes this slot (the
 // workgroup is a multiple of 16 threads), so one 32-bit division per batch
-// serves stage_u, geo_lane and vertical_out (launch_ax_mfma requires fewer
-// than 2^31 prisms).
+// serves stage_u, geo_lane and vertical_out (pmg_create rejects meshes of
+// 2^31 or more prisms).
 struct ColSlot {
   int te, layer;
 };
