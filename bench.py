@@ -91,13 +91,9 @@ def op_bytes(info0, nt, np_tri, prec, P):
     return geo + info0["n_dof"] * s_v + info0["n_elem"] * info0["np"] * s_v + nt * np_tri * 4
 
 
-def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both"):
-    """The oracle's complete FP64 PCG solve on a slice of the workload, scaled to the full mesh.
-
-    The slice is the same split-quad box, order, layer count, surface elevation,
-    Dirichlet data, smoother and stop test at n_side x n_side quads; its time per
-    iteration is scaled by the prism count and by the FP64 GPU iteration count.
-    """
+def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening):
+    """One oracle FP64 PCG solve (rtol 1e-8) of an n_side x n_side x n_layers slice
+    of the box workload: (set-up s, solve s, iterations, prisms, nodes)."""
     import oracle.mesh as OM
     from oracle import krylov, mg
     from paper_2009_00705_amd import workloads as W
@@ -112,21 +108,60 @@ def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16
     phi_dir = W.mode_sum(xyz[:, 0], xyz[:, 1], xyz[:, 2], W.mode_amplitudes(3), W.mode_pairs())
     t0 = time.perf_counter()
     r = krylov.solve(h, phi_dir, method="pcg", rtol=1e-8, imax=300)
-    t_solve = time.perf_counter() - t0
-    t_iter = t_solve / max(r.iters, 1)
-    t_full = t_iter * (n_elem_full / num.n_elem) * iters_full
+    return t_setup, time.perf_counter() - t0, max(r.iters, 1), num.n_elem, num.n_dof
+
+
+def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both"):
+    """The oracle's complete FP64 PCG solve on slices of the workload, scaled to the full mesh.
+
+    The slices are the same split-quad box, order, layer count, surface
+    elevation, Dirichlet data, smoother and stop test at n_side x n_side quads
+    (and at half that side, to show how far the time per prism and iteration
+    is from constant); the larger slice's time per iteration is scaled by the
+    prism count and by the FP64 GPU iteration count.  Run with all the cores
+    this process may use (os.sched_getaffinity) and again with one BLAS thread.
+    """
+    cores = len(os.sched_getaffinity(0))
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():      # the host's CPU share, where it is set
+        cores = max(1, min(cores, int(os.environ["OMP_NUM_THREADS"])))
     try:
-        from threadpoolctl import threadpool_info
-        cores = max([1] + [int(i.get("num_threads", 1)) for i in threadpool_info()])
-    except Exception:
-        cores = 1
-    return {"value": 1.0 / t_full, "unit": "solves/s", "cores": cores, "kind": "oracle",
-            "sample": (f"oracle FP64 PCG solve (same smoother and level orders, exact coarse solve, rtol 1e-8) on a "
-                       f"{n_side}x{n_side}x{n_layers} slice of the workload ({num.n_elem} prisms, {num.n_dof} "
-                       f"nodes): {t_solve:.1f} s for {r.iters} iterations after {t_setup:.1f} s set-up; "
-                       f"{t_iter:.2f} s/iteration scaled by {n_elem_full}/{num.n_elem} prisms and "
-                       f"{iters_full} iterations"),
-            "dof_per_s": n_dof_full / t_full}
+        from threadpoolctl import threadpool_limits
+    except Exception:                      # pragma: no cover - threadpoolctl ships with scipy's stack
+        threadpool_limits = None
+    runs = {}
+    for label, nthreads in (("all", cores), ("one", 1)):
+        lim = threadpool_limits(limits=nthreads) if threadpool_limits else None
+        try:
+            small = _oracle_slice_solve(P, nu, smoother, n_side // 2, n_layers, coarsening) if label == "all" else None
+            big = _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening)
+        finally:
+            if lim is not None:
+                lim.unregister()
+        runs[label] = (small, big)
+    res = {}
+    for label, (small, big) in runs.items():
+        t_setup, t_solve, iters, ne, nd = big
+        t_iter = t_solve / iters
+        t_full = t_iter * (n_elem_full / ne) * iters_full
+        per_big = t_iter / ne
+        txt = (f"{n_side}x{n_side}x{n_layers} slice ({ne} prisms, {nd} nodes): {t_solve:.1f} s for {iters} "
+               f"iterations after {t_setup:.1f} s set-up; {t_iter:.2f} s/iteration scaled by {n_elem_full}/{ne} "
+               f"prisms and {iters_full} iterations")
+        res[label] = {"t_full": t_full, "sample": txt, "growth": None}
+        if small is not None:
+            per_small = small[1] / small[2] / small[3]
+            res[label]["growth"] = per_big / per_small
+            res[label]["sample"] += (f"; time per prism-iteration {per_big * 1e6:.0f} us against "
+                                     f"{per_small * 1e6:.0f} us on the {n_side // 2}x{n_side // 2}x{n_layers} "
+                                     f"slice ({small[3]} prisms), ratio {per_big / per_small:.2f}")
+    a, o = res["all"], res["one"]
+    return {"value": 1.0 / a["t_full"], "unit": "solves/s", "cores": cores, "kind": "oracle",
+            "sample": ("oracle FP64 PCG solve (same smoother and level orders, exact coarse solve, rtol 1e-8) "
+                       f"with {cores} threads on a " + a["sample"]),
+            "dof_per_s": n_dof_full / a["t_full"],
+            "one_core": {"value": 1.0 / o["t_full"], "unit": "solves/s", "cores": 1,
+                         "dof_per_s": n_dof_full / o["t_full"], "sample": "one BLAS thread, " + o["sample"]},
+            "slice_growth": round(a["growth"], 3)}
 
 
 def schwarz_roofline(ctx, prec, level=0, reps=10):
@@ -202,6 +237,122 @@ def bench_erk4(a):
                       "coarsening": a.coarsening, "precision": best, "reuse": a.reuse},
            "paths": paths}
     print(json.dumps(out), flush=True)
+
+
+def c2_fp64_row(a, log, steps=10, warmup=2):
+    """The FP64 GPU configuration (32x32 split-quad box x 4 layers = 8192 prisms,
+    P = 6, levels 6 -> 3 -> 1, exact coarse solve, eta = 0.1 sin x cos y, field
+    cosh(k(z+1))/cosh(k) cos(kx) with k = 1 and 2 on the surface): plain FP64
+    PCG solves/s, DOF/s, iterations and mean convergence factor, plus the FP64
+    element operator's launch time and algorithmic GB/s (its 8192 prisms' column
+    factors and vectors stay in the 256 MB last-level cache, so this is not an
+    HBM figure)."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    from paper_2009_00705_amd import workloads as W
+    mesh = W.config_mesh("c2")
+    ctx = pmg.Context(mesh, P=6, coarse="exact", smoother="chebyshev", nu1=3, nu2=3, coarsening="both")
+    info0 = ctx.levels[0]
+    xy = ctx.surface_xy()
+    eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
+    ctx.set_surface(torch.from_numpy(eta).cuda())
+    xyz = ctx.node_xyz(0)
+    nz = 4 * 6 + 1
+    top = np.arange(info0["n_dof"]) % nz == nz - 1
+    ctx.set_solver("fp64", "pcg")
+    rows = {}
+    phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
+    for k in (1, 2):
+        surf = torch.from_numpy(np.ascontiguousarray(W.linear_wave(xyz[:, 0], xyz[:, 1], xyz[:, 2], float(k))[top]))
+        surf = surf.cuda()
+        for _ in range(warmup):
+            phi.zero_()
+            ctx.solve(phi, phi_surf=surf, rtol=1e-8, imax=500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            phi.zero_()
+            rc, st = ctx.solve(phi, phi_surf=surf, rtol=1e-8, imax=500)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        exact = W.linear_wave(xyz[:, 0], xyz[:, 1], xyz[:, 2], float(k))
+        err = float(np.abs(phi.cpu().numpy() - exact).max() / np.abs(exact).max())
+        q = st["q"]
+        rows[f"k={k}"] = {"solves_per_s": 1.0 / dt, "ms_per_solve": dt * 1e3, "dof_per_s": info0["n_dof"] / dt,
+                          "iters": st["iters"], "q_mean": float(np.exp(np.mean(np.log(q)))) if q.size else None,
+                          "rel_res": st["rel_res"], "max_error_vs_exact_field": err, "status": int(rc)}
+        log(f"[c2] fp64 k={k}: {dt * 1e3:.2f} ms/solve, {st['iters']} its")
+    nt = mesh["tri"].shape[0]
+    ms = ctx.time_kernel("element_op", 0, "fp64", reps=50)
+    byts = op_bytes(info0, nt, 28, "fp64", 6)
+    ctx.close()
+    return {"workload": "c2: 32x32 split-quad box, 2048 triangles x 4 layers = 8192 prisms, P=6, levels 6 -> 3 -> 1, "
+                        "exact coarse solve, FP64 PCG, Chebyshev 3+3, rtol 1e-8",
+            "n_dof": info0["n_dof"], "paths": rows,
+            "element_op": {"ms_per_launch": ms, "bytes_per_launch": byts, "GB_per_s": byts / (ms * 1e-3) / 1e9,
+                           "note": "column factors and vectors resident in the last-level cache"}}
+
+
+def learned_leg(a, log, train_steps=1500):
+    """Learned half of the metric on the focusing-wave history of the cylinder
+    mesh (48,060 prisms, P = 6): steps 0-199 are solved (split-BF16 V-cycle,
+    extrapolated guess) to build the training set, a 160-wide, 3-hidden-layer
+    network is trained on the GPU against the third-order extrapolation, and
+    the 100 test steps 200-299 are solved with each guess.  The 2x target is
+    stated against plain FP64 p-multigrid with the same non-learned guess (the
+    previous step); the zero-guess ratio is shown too.  Per-step time =
+    guess (features, network, fallback check) + solve; set_surface excluded."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    from paper_2009_00705_amd import workloads as W
+    from paper_2009_00705_amd.history import History, summarize
+    mesh = W.config_mesh("c5")
+    ctx = pmg.Context(mesh, P=6, coarse="chebyshev", smoother="chebyshev", nu1=3, nu2=3, coarsening="xy")
+    H = History(ctx, W.WaveGroup(n_steps=300))
+    H.set_step(0)
+    om, lo, hi = ctx.params()
+    ctx.set_params(om, lo, hi)               # t = 0 smoothing weights and coarse interval reused
+    info0 = ctx.levels[0]
+    t0 = time.perf_counter()
+    ctx.set_solver("bf16x3", "fpcg")
+    ref, _ = H.solve_sequence(range(0, 200), guess="extrap", rtol=a.rtol)
+    t_hist = time.perf_counter() - t0
+    X, T = H.training_set(ref, range(3, 200), third=True)
+    net = pmg.Net(ctx, width=160, depth=3, seed=6)
+    t0 = time.perf_counter()
+    loss = net.train(X, T, steps=train_steps, batch=8192, lr=1e-3, seed=7)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rows = int(X.shape[0])
+    del X, T
+    log(f"[learned] history 0-199 in {t_hist:.1f}s, trained {net.n_params} params on {rows} rows in "
+        f"{t_train:.1f}s (loss {loss:.3e})")
+    test = range(200, 300)
+    base = {n: ref[n] for n in (197, 198, 199)}
+    paths = {}
+    for prec, guess in (("fp64", "zero"), ("fp64", "prev"), ("fp64", "extrap3"), ("fp64", "learned3"),
+                        ("bf16x3", "prev"), ("bf16x3", "extrap3"), ("bf16x3", "learned3")):
+        ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
+        _, st = H.solve_sequence(test, guess=guess, sols=base, net=net if guess == "learned3" else None,
+                                 rtol=a.rtol)
+        paths[f"{prec}+{guess}"] = summarize(st)
+        log(f"[learned] {prec}+{guess}: {paths[f'{prec}+{guess}']}")
+    n_params = net.n_params
+    net.close()
+    ctx.close()
+    sp = lambda k: paths[k]["solves_per_s"]
+    best = max((k for k in paths if not k.startswith("fp64")), key=sp)
+    return {"workload": f"c5: seeded Delaunay cylinder mesh, {info0['n_elem']} prisms, P=6, {info0['n_dof']} nodes, "
+                        "300-step focusing group (16 components); train on steps 3-199, test on 200-299",
+            "metric": "Laplace solves/s over the 100 test steps (guess + solve), rtol 1e-8",
+            "value": round(sp(best), 3), "unit": "solves/s", "best": best,
+            "vs_fp64_same_guess": round(sp(best) / sp("fp64+prev"), 4),
+            "vs_fp64_zero_guess": round(sp(best) / sp("fp64+zero"), 4),
+            "learned_vs_extrap3_bf16x3": round(sp("bf16x3+learned3") / sp("bf16x3+extrap3"), 4),
+            "learned_vs_extrap3_fp64": round(sp("fp64+learned3") / sp("fp64+extrap3"), 4),
+            "training": {"rows": rows, "steps": train_steps, "batch": 8192, "loss": loss, "seconds": t_train,
+                         "params": n_params},
+            "paths": paths}
 
 
 def bench_history(a):
@@ -406,6 +557,8 @@ def main():
     ap.add_argument("--smooth-ratio", type=float, default=15.0,
                     help="Chebyshev smoother interval [lambda/ratio, lambda]")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg (c5 history)")
+    ap.add_argument("--no-c2", action="store_true", help="skip the FP64 c2 row")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--kernel-only", action="store_true",
@@ -542,6 +695,10 @@ def main():
            "paths": paths, "roofline": roof}
     if "fp64" in paths and best != "fp64":
         out["speedup_vs_fp64"] = res["solves_per_s"] / paths["fp64"]["solves_per_s"]
+    if a.workload == "c3" and a.P == 6 and not a.no_c2:
+        out["c2_fp64"] = c2_fp64_row(a, log)
+    if a.workload == "c3" and a.P == 6 and not a.no_learned:
+        out["learned"] = learned_leg(a, log)
     if not a.no_cpu:
         p64 = paths.get("fp64", res)
         out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"],

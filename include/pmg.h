@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PMG_ABI_VERSION 3
+#define PMG_ABI_VERSION 4
 
 enum pmg_status {
   PMG_OK = 0,
@@ -126,7 +126,7 @@ typedef struct pmg_mesh {
 } pmg_mesh;
 
 typedef struct pmg_options {
-  int32_t P;              /* finest order, 1..8; levels P, floor(P/2), ..., 1    */
+  int32_t P;              /* finest triangle order, 1..8 (vertical order: PZ)   */
   int32_t nu1, nu2;       /* damped-Jacobi pre/post sweeps (Alg. 1)              */
   double omega[8];        /* per level; <= 0: 4/(3*lambda) with lambda = 1.05 x
                              30-step power estimate of lambda_max(D^-1 A)
@@ -165,6 +165,15 @@ typedef struct pmg_options {
                              schwarz_chunk entries                             */
   int64_t schwarz_chunk;  /* entries of an FP64 set-up chunk; <= 0: 2^29 (4 GiB) */
   int32_t geometry;       /* pmg_geometry of the MFMA element operators          */
+  int32_t PZ;             /* finest vertical order, 1..8; <= 0: P.  The geometry
+                             is the isoparametric map of triangle order P on
+                             every level (the sigma map is affine along the
+                             extrusion inside a layer, so PZ does not change it).
+                             Level orders must be among those the library builds
+                             (pmg_create fails with PMG_EINVAL otherwise): any
+                             isotropic P; with PZ != P the EQUAL sequences of
+                             (4,2), (5,3), (6,4), (2,4), (3,6), (4,8) and the
+                             XY_FIRST sequences of (3,6), (2,4), (4,8)           */
 } pmg_options;
 
 /* Geometric factors read by the MFMA element operators.  STORED: the six
@@ -180,13 +189,17 @@ typedef struct pmg_options {
  * the levels without their split kernels too). */
 enum pmg_geometry { PMG_GEOM_STORED = 0, PMG_GEOM_COLUMN = 1 };
 
-/* Order sequence of the levels.  BOTH: P, floor(P/2), ..., 1 in every direction
- * (Sec. 5, Table BTcoarse).  XY_FIRST: the triangle order is coarsened first
- * with the vertical order kept, then the vertical order, (P,P) -> (P/2,P) ->
- * ... -> (1,P) -> (1,P/2) -> ... -> (1,1): semi-coarsening for prisms whose
- * in-plane node spacing is much finer than the vertical one (anisotropic
- * orders, as the (5,3) -> (3,3) -> (1,1) sequence of Sec. 6.2). */
-enum pmg_coarsening { PMG_COARSEN_BOTH = 0, PMG_COARSEN_XY_FIRST = 1 };
+/* Order sequence of the levels, from the finest (P, PZ); each coarsening step
+ * takes an order p to max(1, floor(p/2)).  BOTH: both orders together (Sec. 5,
+ * Table BTcoarse: 6 -> 3 -> 1).  XY_FIRST: the triangle order is coarsened
+ * first with the vertical order kept, then the vertical order, (P,PZ) ->
+ * (P/2,PZ) -> ... -> (1,PZ) -> (1,PZ/2) -> ... -> (1,1): in-plane
+ * semi-coarsening for prisms whose in-plane node spacing is much finer than
+ * the vertical one.  EQUAL: semi-coarsening of the direction of higher order,
+ * each step to max(lower order, floor(higher/2)), until the two agree, then
+ * both together (Sec. 6.2, Table BTcoarse3D: (5,3) -> (3,3) -> (1,1); with
+ * PZ > P the vertical order goes first). */
+enum pmg_coarsening { PMG_COARSEN_BOTH = 0, PMG_COARSEN_XY_FIRST = 1, PMG_COARSEN_EQUAL = 2 };
 
 typedef struct pmg_level_info {
   int32_t order;          /* P_l: order on the triangle */

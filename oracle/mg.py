@@ -39,21 +39,49 @@ from .refelem import order_pair, ref, vandermonde_1d, vandermonde_tri
 from .schwarz import Schwarz, overlap_of
 
 
-def level_orders(P: int, coarsening: str = "both"):
-    """Orders of the levels, finest first.  "both": P, floor(P/2), ..., 1 in
-    every direction (Sec. 5).  "xy": the triangle order is coarsened first
-    with the vertical order kept, then the vertical order, (P, P) -> ... ->
-    (1, P) -> (1, floor(P/2)) -> ... -> (1, 1) (semi-coarsening, for prisms
-    whose in-plane node spacing is much finer than the vertical one)."""
+def level_orders(P: int, coarsening: str = "both", PZ: int = None):
+    """Orders of the levels, finest first, for the finest triangle order P and
+    vertical order PZ (default P); a level is (triangle order, vertical order),
+    or the plain int P for the isotropic all-direction sequence.
+
+    "both": both orders halve together, max(1, floor(p/2)) (Sec. 5, Table
+    BTcoarse: 6 -> 3 -> 1).  "xy": the triangle order is coarsened first with
+    the vertical order kept, then the vertical order, (P, PZ) -> ... -> (1, PZ)
+    -> (1, floor(PZ/2)) -> ... -> (1, 1) (in-plane semi-coarsening, for prisms
+    whose in-plane node spacing is much finer than the vertical one).
+    "equal": semi-coarsening of the direction of higher order until the two
+    orders agree, each step to max(lower order, floor(higher/2)), then both
+    together (Sec. 6.2 and Table BTcoarse3D: (5, 3) -> (3, 3) -> (1, 1); with
+    PZ > P the vertical order is the one coarsened first)."""
+    PZ = P if PZ is None else int(PZ)
+    half = lambda p: max(1, p // 2)
+
     def seq(p):
         out = [p]
         while out[-1] > 1:
-            out.append(max(1, out[-1] // 2))
+            out.append(half(out[-1]))
         return out
     if coarsening == "both":
-        return seq(P)
+        if PZ == P:
+            return seq(P)
+        out = [(P, PZ)]
+        while out[-1] != (1, 1):
+            out.append((half(out[-1][0]), half(out[-1][1])))
+        return out
     if coarsening == "xy":
-        return [(pt, P) for pt in seq(P)] + [(1, pz) for pz in seq(P)[1:]]
+        return [(pt, PZ) for pt in seq(P)] + [(1, pz) for pz in seq(PZ)[1:]]
+    if coarsening == "equal":
+        out = [(P, PZ)]
+        pt, pz = P, PZ
+        while pt != pz:
+            if pt > pz:
+                pt = max(pz, half(pt))
+            else:
+                pz = max(pt, half(pz))
+            out.append((pt, pz))
+        for p in seq(pt)[1:]:
+            out.append((p, p))
+        return out
     raise ValueError(coarsening)
 
 
@@ -113,12 +141,17 @@ class Hierarchy:
                  dirichlet_tags: int = 0, top_neumann: bool = False,
                  coarse: str = "exact", cheb=None, seed: int = 0,
                  smoother: str = "jacobi", smooth_ratio: float = 15.0, coarsening: str = "both",
-                 overlap: int = 1):
+                 overlap: int = 1, PZ: int = None):
         self.mesh = mesh
+        # P: triangle order of the finest level, which is also the order of the
+        # isoparametric map every level's geometry comes from (the sigma map is
+        # affine along the extrusion inside a layer, so the map's vertical order
+        # does not change it); PZ: vertical order of the finest level
         self.P = P
+        self.PZ = P if PZ is None else int(PZ)
         self.dirichlet_tags, self.top_neumann = dirichlet_tags, top_neumann
         self.reuse = "none"
-        self.orders = level_orders(P, coarsening)
+        self.orders = level_orders(P, coarsening, self.PZ)
         num_f = Numbering(mesh, P)
         if eta2d is None:
             eta2d = np.zeros(num_f.n2d)

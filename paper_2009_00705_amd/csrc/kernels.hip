@@ -196,6 +196,20 @@ void launch_ax(const LevelView& lv, const T* mats, const void* G, int gstore, co
   PMG_ORDERS(PMG_AX)
 #undef PMG_AX
 }
+bool order_supported(int PT, int PZ) {
+#define PMG_OS(PTV, PZV) \
+  if (PT == PTV && PZ == PZV) return true;
+  PMG_ORDERS(PMG_OS)
+#undef PMG_OS
+  return false;
+}
+bool pair_supported(int PFT, int PFZ, int PCT, int PCZ) {
+#define PMG_PS(A, B, C, D) \
+  if (PFT == A && PFZ == B && PCT == C && PCZ == D) return true;
+  PMG_PAIRS(PMG_PS)
+#undef PMG_PS
+  return false;
+}
 template void launch_ax<double>(const LevelView&, const double*, const void*, int, const double*, double*, hipStream_t);
 template void launch_ax<float>(const LevelView&, const float*, const void*, int, const float*, float*, hipStream_t);
 

@@ -20,17 +20,25 @@ enum Scal {
 };
 
 // (triangle order, vertical order) of the levels the library builds: the
-// isotropic orders and the in-plane-first chains (P, P) -> (P/2, P) -> ... ->
-// (1, P) -> (1, P/2) -> ... -> (1, 1) of every fine order up to 8
+// isotropic orders, the in-plane-first chains (P, P) -> (P/2, P) -> ... ->
+// (1, P) -> (1, P/2) -> ... -> (1, 1) of every fine order up to 8, and the
+// anisotropic finest levels of the equal-order chains (4,2), (5,3), (6,4)
 #define PMG_ORDERS(X)                                                                                \
   X(1, 1) X(2, 2) X(3, 3) X(4, 4) X(5, 5) X(6, 6) X(7, 7) X(8, 8) X(1, 2) X(1, 3) X(1, 4) X(1, 5) \
-  X(1, 6) X(1, 7) X(1, 8) X(2, 4) X(2, 5) X(2, 8) X(3, 6) X(3, 7) X(4, 8)
-// consecutive level pairs (fine PT, PZ, coarse PT, PZ) of both coarsening sequences
+  X(1, 6) X(1, 7) X(1, 8) X(2, 4) X(2, 5) X(2, 8) X(3, 6) X(3, 7) X(4, 8) X(4, 2) X(5, 3) X(6, 4)
+// consecutive level pairs (fine PT, PZ, coarse PT, PZ) of the coarsening sequences:
+// all directions, in-plane first, and equal-order (semi-coarsening of the
+// higher order until the two agree, then both)
 #define PMG_PAIRS(X)                                                                                 \
   X(2, 2, 1, 1) X(3, 3, 1, 1) X(4, 4, 2, 2) X(5, 5, 2, 2) X(6, 6, 3, 3) X(7, 7, 3, 3) X(8, 8, 4, 4) \
   X(2, 2, 1, 2) X(1, 2, 1, 1) X(3, 3, 1, 3) X(1, 3, 1, 1) X(4, 4, 2, 4) X(2, 4, 1, 4) X(1, 4, 1, 2) \
   X(5, 5, 2, 5) X(2, 5, 1, 5) X(1, 5, 1, 2) X(6, 6, 3, 6) X(3, 6, 1, 6) X(1, 6, 1, 3) X(7, 7, 3, 7) \
-  X(3, 7, 1, 7) X(1, 7, 1, 3) X(8, 8, 4, 8) X(4, 8, 2, 8) X(2, 8, 1, 8) X(1, 8, 1, 4)
+  X(3, 7, 1, 7) X(1, 7, 1, 3) X(8, 8, 4, 8) X(4, 8, 2, 8) X(2, 8, 1, 8) X(1, 8, 1, 4)               \
+  X(4, 2, 2, 2) X(5, 3, 3, 3) X(6, 4, 4, 4) X(2, 4, 2, 2) X(3, 6, 3, 3) X(4, 8, 4, 4)
+
+// whether the element kernels exist for a level order / the transfers for a pair
+bool order_supported(int PT, int PZ);
+bool pair_supported(int PFT, int PFZ, int PCT, int PCZ);
 
 // Per-level device description.
 struct LevelView {

@@ -279,25 +279,42 @@ static std::vector<double> pack_mats(const RefElem& re) {
   return m;
 }
 
-// Orders of the levels, finest first (Sec. 5: P, floor(P/2), ..., 1).  With the
-// in-plane-first option the triangle order is coarsened first with the vertical
-// order kept, then the vertical order: (P,P) -> ... -> (1,P) -> (1,P/2) -> ... -> (1,1).
-static std::vector<std::pair<int, int>> level_orders(int P, int coarsening) {
-  std::vector<int> seq{P};
-  while (seq.back() > 1) seq.push_back(std::max(1, seq.back() / 2));
-  std::vector<std::pair<int, int>> out;
+// Orders of the levels, finest first, from the finest (P, PZ); a coarsening
+// step takes an order p to max(1, floor(p/2)) (Sec. 5).  BOTH: both orders
+// together.  XY_FIRST: the triangle order first with the vertical order kept,
+// then the vertical order: (P,PZ) -> ... -> (1,PZ) -> (1,PZ/2) -> ... -> (1,1).
+// EQUAL: the higher order alone, to max(lower, floor(higher/2)), until the two
+// agree, then both (Sec. 6.2, Table BTcoarse3D: (5,3) -> (3,3) -> (1,1)).
+static std::vector<std::pair<int, int>> level_orders(int P, int PZ, int coarsening) {
+  auto half = [](int p) { return std::max(1, p / 2); };
+  std::vector<std::pair<int, int>> out{{P, PZ}};
   if (coarsening == PMG_COARSEN_XY_FIRST) {
-    for (int pt : seq) out.emplace_back(pt, P);
-    for (size_t i = 1; i < seq.size(); ++i) out.emplace_back(1, seq[i]);
+    for (int pt = P; pt > 1;) out.emplace_back(pt = half(pt), PZ);
+    for (int pz = PZ; pz > 1;) out.emplace_back(1, pz = half(pz));
+  } else if (coarsening == PMG_COARSEN_EQUAL) {
+    int pt = P, pz = PZ;
+    while (pt != pz) {
+      if (pt > pz) pt = std::max(pz, half(pt)); else pz = std::max(pt, half(pz));
+      out.emplace_back(pt, pz);
+    }
+    while (pt > 1) { pt = pz = half(pt); out.emplace_back(pt, pz); }
   } else {
-    for (int p : seq) out.emplace_back(p, p);
+    int pt = P, pz = PZ;
+    while (pt > 1 || pz > 1) { pt = half(pt); pz = half(pz); out.emplace_back(pt, pz); }
   }
   return out;
 }
 
 static void build_levels(pmg_ctx* c) {
   const pmg_options& o = c->opt;
-  const std::vector<std::pair<int, int>> orders = level_orders(o.P, o.coarsening);
+  const std::vector<std::pair<int, int>> orders = level_orders(o.P, o.PZ > 0 ? o.PZ : o.P, o.coarsening);
+  for (size_t i = 0; i < orders.size(); ++i) {
+    const auto& a = orders[i];
+    if (!order_supported(a.first, a.second) ||
+        (i + 1 < orders.size() && !pair_supported(a.first, a.second, orders[i + 1].first, orders[i + 1].second)))
+      throw Error(PMG_EINVAL, "level orders (" + std::to_string(a.first) + "," + std::to_string(a.second) +
+                                  ") of this coarsening sequence are not built by the library");
+  }
   c->nl = int(orders.size());
   c->lv.resize(c->nl);
   for (int i = 0; i < c->nl; ++i) {
@@ -1856,6 +1873,7 @@ void pmg_options_default(pmg_options* o) {
   o->overlap = 1;
   o->seed = 0;
   o->geometry = PMG_GEOM_COLUMN;
+  o->PZ = 0;
 }
 
 int pmg_abi_version(void) { return PMG_ABI_VERSION; }
@@ -1877,7 +1895,8 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (o->smoother < 0 || o->smoother > 2) throw Error(PMG_EINVAL, "bad smoother");
     if (o->smoother == PMG_SMOOTH_SCHWARZ && o->overlap < -1) throw Error(PMG_EINVAL, "bad Schwarz overlap");
     if (o->schwarz_store < 0 || o->schwarz_store > 7) throw Error(PMG_EINVAL, "bad schwarz_store mask");
-    if (o->coarsening < 0 || o->coarsening > 1) throw Error(PMG_EINVAL, "bad coarsening");
+    if (o->coarsening < 0 || o->coarsening > 2) throw Error(PMG_EINVAL, "bad coarsening");
+    if (o->PZ > 8) throw Error(PMG_EINVAL, "PZ must be in 1..8 (or <= 0 for P)");
     if (o->geometry < 0 || o->geometry > 1) throw Error(PMG_EINVAL, "bad geometry mode");
     if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
       throw Error(PMG_EINVAL, "smooth_ratio must exceed 1");

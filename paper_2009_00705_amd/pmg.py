@@ -22,7 +22,7 @@ PMG_PCG, PMG_FPCG, PMG_PDC, PMG_MG = 0, 1, 2, 3
 PMG_GUESS_GIVEN, PMG_GUESS_ZERO, PMG_GUESS_LEARNED, PMG_GUESS_EXTRAP, PMG_GUESS_EXTRAP3, PMG_GUESS_LEARNED3 = \
     0, 1, 2, 3, 4, 5
 PMG_COARSE_EXACT, PMG_COARSE_CHEBYSHEV = 0, 1
-PMG_COARSEN_BOTH, PMG_COARSEN_XY_FIRST = 0, 1
+PMG_COARSEN_BOTH, PMG_COARSEN_XY_FIRST, PMG_COARSEN_EQUAL = 0, 1, 2
 
 STATUS = {0: "OK", 1: "NOT_CONVERGED", 2: "FALLBACK_USED", -1: "EINVAL", -2: "ENOMEM",
           -3: "EDEVICE", -4: "EBREAKDOWN", -5: "ENONFINITE", -6: "EMESH", -7: "ESTATE"}
@@ -53,7 +53,7 @@ class Options(C.Structure):
                 ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32),
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
                 ("coarsening", C.c_int32), ("overlap", C.c_int32), ("schwarz_store", C.c_int32),
-                ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32)]
+                ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32), ("PZ", C.c_int32)]
 
 
 class FnpfStats(C.Structure):
@@ -211,7 +211,7 @@ def default_options(**kw) -> Options:
         elif k == "schwarz_store" and isinstance(v, str):
             o.schwarz_store = sum({"fp64": 1, "fp32": 2, "bf16": 4}[x] for x in v.split(",") if x)
         elif k == "coarsening" and isinstance(v, str):
-            o.coarsening = {"both": PMG_COARSEN_BOTH, "xy": PMG_COARSEN_XY_FIRST}[v]
+            o.coarsening = {"both": PMG_COARSEN_BOTH, "xy": PMG_COARSEN_XY_FIRST, "equal": PMG_COARSEN_EQUAL}[v]
         elif k == "geometry" and isinstance(v, str):
             o.geometry = {"stored": 0, "column": 1}[v]
         else:

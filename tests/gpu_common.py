@@ -44,6 +44,8 @@ def make_pair(mesh, P, eta_kind="wavy", omega=0.3, **kw):
         okw["smooth_ratio"] = kw.get("smooth_ratio", 15.0)
     if "coarsening" in kw:
         okw["coarsening"] = kw["coarsening"]
+    if "PZ" in kw:
+        okw["PZ"] = kw["PZ"]
     if "overlap" in kw:
         okw["overlap"] = kw["overlap"]
     if kw.get("coarse") == "chebyshev":

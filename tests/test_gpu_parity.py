@@ -28,10 +28,19 @@ CASES = {
 }
 # in-plane-first hierarchies (anisotropic orders, e.g. (6,6) (3,6) (1,6) (1,3) (1,1))
 XY_CASES = {k + "_xy": v for k, v in CASES.items() if k != "c1"}
-ALL = dict(CASES, **XY_CASES)
+# anisotropic finest levels with the equal-order sequence (Sec. 6.2, Table
+# BTcoarse3D): (5,3) (3,3) (1,1), and vertical-first (3,6) (3,3) (1,1)
+EQ_CASES = {
+    "box5x5_L3_P5_eq53": (lambda: W.box_mesh(5, 3), 5),
+    "cyl_P3_eq36": (CASES["cyl_P3"][0], 3),
+}
+EQ_PZ = {"box5x5_L3_P5_eq53": 3, "cyl_P3_eq36": 6}
+ALL = dict(CASES, **XY_CASES, **EQ_CASES)
 
 
 def _opts(name):
+    if name in EQ_PZ:
+        return {"coarsening": "equal", "PZ": EQ_PZ[name]}
     return {"coarsening": "xy"} if name.endswith("_xy") else {}
 
 

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
         assert n in pmg.SIGNATURES, f"binding lacks {n}"
-    assert L.pmg_abi_version() == 3
+    assert L.pmg_abi_version() == 4
 
 
 def _host_ctx(mesh, P, **kw):
@@ -88,6 +88,37 @@ def test_in_plane_first_levels_bit_exact(meshname, P):
         assert info["n_dof"] == num.n_dof and info["np"] == num.np and info["n_surface"] == num.n2d
         np.testing.assert_array_equal(ctx.gather_map(lvl), num.map.astype(np.int32))
     ctx.close()
+
+
+@pytest.mark.parametrize("meshname", sorted(MESHES))
+@pytest.mark.parametrize("P,PZ,coarsening", [(5, 3, "equal"), (4, 2, "equal"), (6, 4, "equal"), (3, 6, "equal"),
+                                             (2, 4, "equal"), (4, 8, "equal"), (6, 6, "equal"), (3, 6, "xy"),
+                                             (4, 4, "both")])
+def test_anisotropic_finest_levels_bit_exact(meshname, P, PZ, coarsening):
+    """Finest vertical order PZ (pmg_options.PZ) with the equal-order sequence
+    (Sec. 6.2, Table BTcoarse3D) or the others: orders, sizes and gather maps of
+    every level equal the oracle's numbering of the same orders."""
+    from oracle.mg import level_orders
+    m = MESHES[meshname]()
+    ctx = _host_ctx(m, P, PZ=PZ, coarsening=coarsening)
+    orders = [o if isinstance(o, tuple) else (o, o) for o in level_orders(P, coarsening, PZ)]
+    assert ctx.n_levels == len(orders)
+    for lvl, (pt, pz) in enumerate(orders):
+        num = M.Numbering(m, pt, pz)
+        info = ctx.levels[lvl]
+        assert (info["order"], info["order_z"]) == (pt, pz)
+        assert info["n_dof"] == num.n_dof and info["np"] == num.np and info["n_surface"] == num.n2d
+        np.testing.assert_array_equal(ctx.gather_map(lvl), num.map.astype(np.int32))
+    ctx.close()
+
+
+def test_unbuilt_order_sequences_are_rejected():
+    from paper_2009_00705_amd import pmg
+    m = W.box_mesh(2, 1)
+    for kw in (dict(P=5, PZ=3, coarsening="xy"), dict(P=7, PZ=2, coarsening="equal"), dict(P=3, PZ=9)):
+        with pytest.raises(pmg.PmgError) as e:
+            pmg.Context(m, host_only=1, **kw)
+        assert e.value.code == -1, kw
 
 
 @pytest.mark.parametrize("meshname", sorted(MESHES))

@@ -1,5 +1,5 @@
 """Pins of the oracle's anisotropic orders (triangle order P, vertical order PZ)
-and of the in-plane-first coarsening sequence.
+and of the in-plane-first and equal-order (semi-coarsening) sequences.
 
 The paper's 3D test coarsens (5,3) -> (3,3) -> (1,1) (Sec. 6.2, Table
 BTcoarse3D): prisms may carry different orders in the plane and along the
@@ -37,6 +37,95 @@ def test_in_plane_first_sequence():
     assert level_orders(3, "xy") == [(3, 3), (1, 3), (1, 1)]
     assert level_orders(1, "xy") == [(1, 1)]
     assert level_orders(6, "both") == [6, 3, 1]
+
+
+def test_equal_order_sequence():
+    """Semi-coarsening of the higher-order direction until the orders agree, then
+    both together (Sec. 6.2, Table BTcoarse3D); the finest pairs of the scaling
+    study (Sec. 6.3) and a vertical-first case (vertical order above the
+    triangle order)."""
+    assert level_orders(5, "equal", 3) == [(5, 3), (3, 3), (1, 1)]
+    assert level_orders(2, "equal", 2) == [(2, 2), (1, 1)]
+    assert level_orders(4, "equal", 2) == [(4, 2), (2, 2), (1, 1)]
+    assert level_orders(6, "equal", 4) == [(6, 4), (4, 4), (2, 2), (1, 1)]
+    assert level_orders(9, "equal", 7) == [(9, 7), (7, 7), (3, 3), (1, 1)]
+    assert level_orders(8, "equal", 2) == [(8, 2), (4, 2), (2, 2), (1, 1)]
+    assert level_orders(3, "equal", 6) == [(3, 6), (3, 3), (1, 1)]
+    assert level_orders(6, "equal") == [(6, 6), (3, 3), (1, 1)]
+    assert level_orders(5, "both", 3) == [(5, 3), (2, 1), (1, 1)]
+    assert level_orders(5, "xy", 3) == [(5, 3), (2, 3), (1, 3), (1, 1)]
+    # every step lowers an order to no less than its floor half and never raises one
+    for P in range(1, 9):
+        for PZ in range(1, 9):
+            seq = level_orders(P, "equal", PZ)
+            assert seq[0] == (P, PZ) and seq[-1] == (1, 1)
+            for (a, b), (c, d) in zip(seq, seq[1:]):
+                assert c <= a and d <= b and (c, d) != (a, b) and c >= max(1, a // 2) and d >= max(1, b // 2)
+
+
+@pytest.fixture(scope="module")
+def fpso_like():
+    """(5, 3) -> (3, 3) -> (1, 1) on a curved 2 x 2 x 2 box: the order pairs of the
+    paper's 3D case."""
+    m = W.box_mesh(2, 2)
+    num = M.Numbering(m, 5)
+    eta = 0.05 * np.sin(M.unique_xy_2d(m, num)[:, 0])
+    return m, Hierarchy(m, 5, eta2d=eta, nu1=3, nu2=3, smoother="chebyshev", coarsening="equal", PZ=3)
+
+
+def test_anisotropic_finest_level_is_the_fine_space(fpso_like):
+    """The finest level carries triangle order 5 and vertical order 3: node and
+    cubature counts, the isoparametric geometry of the order-5 map (its volume
+    equals that of the same map at (5, 5): the sigma map is affine along the
+    extrusion, so the vertical order does not change it), and the weak
+    Laplacian of linear fields vanishing at nodes away from the boundary."""
+    m, h = fpso_like
+    assert [(lv.num.P, lv.num.PZ) for lv in h.levels] == [(5, 3), (3, 3), (1, 1)]
+    lv = h.levels[0]
+    assert lv.num.n_dof == (2 * 5 + 1) ** 2 * (2 * 3 + 1)
+    iso = Hierarchy(m, 5, eta2d=h.eta2d, omega=0.3, coarsening="both")
+    assert abs(lv.geo.wdet.sum() - iso.levels[0].geo.wdet.sum()) < 1e-12 * lv.geo.wdet.sum()
+    xyz = M.node_xyz(m, lv.num, h.eta2d)
+    lin = 0.7 + 0.3 * xyz[:, 0] - 0.2 * xyz[:, 1] + 0.5 * xyz[:, 2]
+    y = lv.op.apply(lin)
+    z = np.arange(lv.num.n_dof) % lv.num.nz
+    x, yy = xyz[:, 0], xyz[:, 1]
+    inner = (x > 1e-9) & (x < 2 * np.pi - 1e-9) & (yy > 1e-9) & (yy < 2 * np.pi - 1e-9) & (z > 0) & \
+            (z < lv.num.nz - 1)
+    assert inner.any() and np.abs(y[inner]).max() < 1e-10 * np.abs(lv.diag).max()
+
+
+def test_equal_order_transfers_reproduce_coarse_polynomials():
+    """Flat box: fields of the coarse space prolongate to their fine interpolant
+    on both steps of (5, 3) -> (3, 3) -> (1, 1); P 1 = 1; R = P^T."""
+    m = W.box_mesh(2, 2)
+    h = Hierarchy(m, 5, omega=0.3, coarsening="equal", PZ=3, top_neumann=True, coarse="chebyshev",
+                  cheb=(2, 0.1, 2.0))
+    rng = np.random.default_rng(5)
+    for i in range(len(h.levels) - 1):
+        lf, lc = h.levels[i], h.levels[i + 1]
+        ct, cz = lc.num.P, lc.num.PZ
+        xf = M.node_xyz(m, lf.num, np.zeros(lf.num.n2d))
+        xc = M.node_xyz(m, lc.num, np.zeros(lc.num.n2d))
+        f = lambda X: (0.2 + 0.1 * X[:, 0] - 0.3 * X[:, 1]) ** ct * (X[:, 2] + 0.4) ** cz
+        np.testing.assert_allclose(h.prolong(i, f(xc)), f(xf), atol=1e-12)
+        np.testing.assert_allclose(h.prolong(i, np.ones(lc.num.n_dof)), 1.0, atol=1e-14)
+        x = rng.standard_normal(lc.num.n_dof)
+        y = rng.standard_normal(lf.num.n_dof)
+        assert abs(h.prolong(i, x) @ y - x @ h.restrict(i, y)) < 1e-12 * np.abs(x).sum() * np.abs(y).max()
+
+
+def test_equal_order_solve_equals_direct(fpso_like):
+    """PCG with (5, 3) -> (3, 3) -> (1, 1) V-cycles reaches the direct solution
+    of the (5, 3) problem, with a V-cycle contraction well below one."""
+    m, h = fpso_like
+    xyz = M.node_xyz(m, h.levels[0].num, h.eta2d)
+    phi = W.linear_wave(xyz[:, 0], xyz[:, 1], xyz[:, 2], 1.0)
+    ref = K.direct_solve(h, phi)
+    r = K.solve(h, phi, method="pcg", rtol=1e-11, imax=100)
+    assert np.abs(r.phi - ref).max() < 1e-9 * np.abs(ref).max()
+    q = r.res_hist[1:] / r.res_hist[:-1]
+    assert np.exp(np.mean(np.log(q))) < 0.3, q
 
 
 @pytest.mark.parametrize("P,PZ", [(3, 6), (1, 6), (2, 8), (6, 2)])

@@ -9,12 +9,19 @@ from paper_2009_00705_amd import workloads as W
 
 
 def test_level_orders_match_paper_table():
-    # Table BTcoarse (Sec. 6.1): P = 6 coarsens 6 -> 3 -> 1
+    # Table BTcoarse (Sec. 6.1): P = 6 coarsens 6 -> 3 -> 1; Table BTcoarse3D
+    # (Sec. 6.2): (5, 3) -> (3, 3) -> (1, 1)
+    pair = lambda txt: tuple(int(v) for v in txt.split(","))
     with open("tests/golden/coarsening_tables.txt") as fh:
         rows = [l for l in fh if l.strip() and not l.startswith("#")]
+    assert len(rows) == 2
     for row in rows:
-        P, rest = row.split(":")
-        assert level_orders(int(P)) == [int(v) for v in rest.split()]
+        head, rest = row.split(":")
+        seq, fine = head.split()
+        P, PZ = pair(fine)
+        want = [pair(v) for v in rest.split()]
+        got = [o if isinstance(o, tuple) else (o, o) for o in level_orders(P, seq, PZ)]
+        assert got == want, (row, got)
     assert level_orders(4) == [4, 2, 1]
     assert level_orders(8) == [8, 4, 2, 1]
 
