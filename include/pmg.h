@@ -458,6 +458,18 @@ int pmg_net_get_params(const pmg_net* net, float* theta, float* mean, float* inv
 int pmg_net_set_params(pmg_net* net, const float* theta, const float* mean, const float* inv_std, double tscale);
 /* raw network output y (device [rows]) of inputs X (device [rows][d_in]) */
 int pmg_net_forward(pmg_net* net, const float* X, int64_t rows, float* y, void* stream);
+/* pmg_net_forward for callers that cannot allocate device memory at the call
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and the same output, bit for bit, with the
+ * hidden activations in a fixed 8 MiB array per GPU (rows in chunks of 4096,
+ * two 4096 x 256 FP32 halves) instead of buffers the network allocates on
+ * first use.  Calls no hipMalloc/hipFree.  Networks whose hidden width exceeds
+ * 256 are rejected with PMG_EINVAL (message in pmg_global_error).  X (device
+ * [rows][d_in]) and y (device [rows]) are the caller's; rows = 0 does nothing.
+ * Every call on one GPU shares that GPU's array and keeps the previous call's
+ * contents: calls that overlap on one GPU (other streams, other threads, other
+ * networks) race and must be serialised by the caller. */
+int pmg_net_forward_noalloc(pmg_net* net, const float* X, int64_t rows, float* y, void* stream);
 /* raw MSE loss of a batch and its gradient (host [n_params], nullable); the
  * gradient also stays on the device for pmg_net_adam_step */
 int pmg_net_loss_grad(pmg_net* net, const float* X, const float* T, int32_t rows, double* loss, float* grad,

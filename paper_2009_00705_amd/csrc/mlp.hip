@@ -4,10 +4,40 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "mlp.hpp"
 
 namespace pmg {
+
+// Hidden activations of the allocation-free forward: two halves of
+// NET_NOALLOC_ROWS x NET_NOALLOC_WIDTH floats.  In host code this name is a
+// stand-in, not a device address; kernels receive the address returned by
+// net_scratch_ptr.  Every call on one GPU shares that GPU's copy, so calls that
+// overlap on a GPU race.
+static __device__ __align__(256) float scratch[2 * NET_NOALLOC_ROWS * NET_NOALLOC_WIDTH];
+
+float* net_scratch_ptr(int device, hipError_t* err) {
+  constexpr int MAX_DEV = 64;
+  static std::mutex mu;
+  static float* ptr[MAX_DEV] = {};
+  *err = hipSuccess;
+  if (device < 0 || device >= MAX_DEV) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    ptr[device] = static_cast<float*>(p);
+  }
+  return ptr[device];
+}
 
 typedef float f4m_t __attribute__((ext_vector_type(4)));
 

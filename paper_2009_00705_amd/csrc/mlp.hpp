@@ -20,6 +20,18 @@ namespace pmg {
 constexpr int NET_DIN = 7;
 constexpr int MLP_RED = 256;
 
+// Allocation-free forward: rows go through the network in chunks of at most
+// NET_NOALLOC_ROWS, their hidden activations ping-ponging between two
+// [NET_NOALLOC_ROWS][NET_NOALLOC_WIDTH] FP32 halves of a file-scope device
+// array (8 MiB per GPU, held until the process ends).  Networks wider than
+// NET_NOALLOC_WIDTH are rejected by that entry point.
+constexpr int NET_NOALLOC_ROWS = 4096;
+constexpr int NET_NOALLOC_WIDTH = 256;
+// Device address of this GPU's activation array (the current device's copy),
+// looked up once per device with hipGetSymbolAddress; null (with the HIP error
+// in *err) if the lookup fails.
+float* net_scratch_ptr(int device, hipError_t* err);
+
 void launch_gemm(int M, int N, int K, const float* A, int64_t sai, int64_t sak, const float* B, int64_t sbk,
                  int64_t sbj, const float* bias, float* Z, float* C, int64_t ldc, bool silu, hipStream_t st);
 void launch_silu_back(const float* dH, const float* Z, float* dZ, int64_t n, hipStream_t st);

@@ -251,6 +251,7 @@ struct pmg_net {
   std::vector<float*> Z, H;
   double *partial = nullptr, *scal = nullptr, *losses = nullptr;
   int nloss = 0;
+  float* scratch = nullptr;  // this GPU's activation array of the allocation-free forward
   std::vector<void*> allocs;
   template <typename T> T* A(size_t n) {
     T* p = pmg::dalloc<T>(n);
@@ -2531,6 +2532,9 @@ int pmg_net_create(const pmg_ctx* c, int32_t width, int32_t depth, uint64_t seed
     n->partial = n->A<double>(MLP_RED);
     n->scal = n->A<double>(64);
     net_reserve(n, 1024);
+    hipError_t se;
+    n->scratch = net_scratch_ptr(n->device, &se);
+    if (!n->scratch) throw Error(PMG_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(se));
     *out = n;
     return PMG_OK;
   } catch (const Error& e) {
@@ -2604,6 +2608,34 @@ int pmg_net_forward(pmg_net* n, const float* X, int64_t rows, float* y, void* st
       const int B = int(std::min<int64_t>(16384, rows - r0));
       net_forward(n, X + r0 * n->din, B, S(stream));
       launch_copy<float>(n->H[L - 1], y + r0, B, S(stream));
+    }
+  });
+  return PMG_OK;
+}
+
+int pmg_net_forward_noalloc(pmg_net* n, const float* X, int64_t rows, float* y, void* stream) {
+  if (!n || rows < 0) return PMG_EINVAL;
+  if (rows == 0) return PMG_OK;
+  if (!X || !y) return PMG_EINVAL;
+  PMG_TRY(n, {
+    HIPCHK(hipSetDevice(n->device));
+    if (n->width > NET_NOALLOC_WIDTH)
+      throw Error(PMG_EINVAL, "pmg_net_forward_noalloc: hidden width " + std::to_string(n->width) +
+                                  " exceeds the allocation-free limit of " + std::to_string(NET_NOALLOC_WIDTH));
+    if (!n->scratch) throw Error(PMG_ESTATE, "pmg_net_forward_noalloc: activation array not set up");
+    hipStream_t st = S(stream);
+    const int L = int(n->fin.size());
+    float* half[2] = {n->scratch, n->scratch + size_t(NET_NOALLOC_ROWS) * NET_NOALLOC_WIDTH};
+    for (int64_t r0 = 0; r0 < rows; r0 += NET_NOALLOC_ROWS) {
+      const int B = int(std::min<int64_t>(NET_NOALLOC_ROWS, rows - r0));
+      const float* h = X + r0 * n->din;
+      for (int l = 0; l < L; ++l) {
+        // hidden layers write alternate halves; the scalar output layer writes y directly
+        float* out = l + 1 < L ? half[l & 1] : y + r0;
+        launch_gemm(B, n->fout[l], n->fin[l], h, n->fin[l], 1, n->theta + n->woff[l], n->fout[l], 1,
+                    n->theta + n->boff[l], nullptr, out, n->fout[l], l + 1 < L, st);
+        h = out;
+      }
     }
   });
   return PMG_OK;

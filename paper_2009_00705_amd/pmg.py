@@ -137,6 +137,7 @@ SIGNATURES = {
     "pmg_net_get_params": (_I, [_VP, _VP, _VP, _VP, _VP]),
     "pmg_net_set_params": (_I, [_VP, _VP, _VP, _VP, _D]),
     "pmg_net_forward": (_I, [_VP, _VP, C.c_int64, _VP, _VP]),
+    "pmg_net_forward_noalloc": (_I, [_VP, _VP, C.c_int64, _VP, _VP]),
     "pmg_net_loss_grad": (_I, [_VP, _VP, _VP, C.c_int32, _VP, _VP, _VP]),
     "pmg_net_adam_step": (_I, [_VP, _D, _VP]),
     "pmg_net_train": (_I, [_VP, _VP, _VP, C.c_int64, C.c_int32, C.c_int32, _D, C.c_uint64, _VP, _VP]),
@@ -479,6 +480,9 @@ class Net:
 
     def forward(self, X, y, stream=None):
         self._c(lib().pmg_net_forward(self.h, _dptr(X), X.shape[0], _dptr(y), _stream(stream)))
+
+    def forward_noalloc(self, X, y, stream=None):
+        self._c(lib().pmg_net_forward_noalloc(self.h, _dptr(X), X.shape[0], _dptr(y), _stream(stream)))
 
     def loss_grad(self, X, T, stream=None):
         g = np.empty(self.n_params, np.float32)
