@@ -111,6 +111,26 @@ def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening):
     return t_setup, time.perf_counter() - t0, max(r.iters, 1), num.n_elem, num.n_dof
 
 
+def apply_bytes(info0, nt, np_tri, prec, P):
+    """Algorithmic bytes of one fine operator apply y = A x: the geometry (7
+    column factors per triangle cubature point, or the stored BF16 G of the bf16
+    and bf16g paths), one read of x and one write of y, the 2D gather map."""
+    s_v = 8 if prec == "fp64" else 4
+    if prec in COLUMN_PATHS:
+        geo = nt * (P + 1) ** 2 * 7 * (8 if prec == "fp64" else 4)
+    else:
+        geo = info0["n_elem"] * 6 * info0["nq"] * 2
+    return geo + 2 * info0["n_dof"] * s_v + nt * np_tri * 4
+
+
+def cheb_bytes(info0, nt, np_tri, prec, P):
+    """Algorithmic bytes of one Chebyshev smoothing step (r -= A d; d = w d + c
+    D^-1 r; x += d): the apply's geometry and map, reads of d, r, D^-1 and x,
+    writes of r, d and x."""
+    s_v = 8 if prec == "fp64" else 4
+    return apply_bytes(info0, nt, np_tri, prec, P) - 2 * info0["n_dof"] * s_v + 7 * info0["n_dof"] * s_v
+
+
 def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both"):
     """The oracle's complete FP64 PCG solve on slices of the workload, scaled to the full mesh.
 
@@ -337,11 +357,17 @@ def learned_leg(a, log, train_steps=1500):
                                  rtol=a.rtol)
         paths[f"{prec}+{guess}"] = summarize(st)
         log(f"[learned] {prec}+{guess}: {paths[f'{prec}+{guess}']}")
+    # where the guess weighs more: a looser tolerance (fewer iterations to save from)
+    ctx.set_solver("bf16x3", "fpcg")
+    for guess in ("extrap3", "learned3"):
+        _, st = H.solve_sequence(test, guess=guess, sols=base, net=net if guess == "learned3" else None, rtol=1e-6)
+        paths[f"bf16x3+{guess}@1e-6"] = summarize(st)
+        log(f"[learned] bf16x3+{guess} at rtol 1e-6: {paths[f'bf16x3+{guess}@1e-6']}")
     n_params = net.n_params
     net.close()
     ctx.close()
     sp = lambda k: paths[k]["solves_per_s"]
-    best = max((k for k in paths if not k.startswith("fp64")), key=sp)
+    best = max((k for k in paths if not k.startswith("fp64") and "@" not in k), key=sp)
     return {"workload": f"c5: seeded Delaunay cylinder mesh, {info0['n_elem']} prisms, P=6, {info0['n_dof']} nodes, "
                         "300-step focusing group (16 components); train on steps 3-199, test on 200-299",
             "metric": "Laplace solves/s over the 100 test steps (guess + solve), rtol 1e-8",
@@ -350,6 +376,7 @@ def learned_leg(a, log, train_steps=1500):
             "vs_fp64_zero_guess": round(sp(best) / sp("fp64+zero"), 4),
             "learned_vs_extrap3_bf16x3": round(sp("bf16x3+learned3") / sp("bf16x3+extrap3"), 4),
             "learned_vs_extrap3_fp64": round(sp("fp64+learned3") / sp("fp64+extrap3"), 4),
+            "learned_vs_extrap3_bf16x3_rtol_1e-6": round(sp("bf16x3+learned3@1e-6") / sp("bf16x3+extrap3@1e-6"), 4),
             "training": {"rows": rows, "steps": train_steps, "batch": 8192, "loss": loss, "seconds": t_train,
                          "params": n_params},
             "paths": paths}
@@ -616,11 +643,16 @@ def main():
         res = {"workload": wl_desc, "copy_bytes": 2 * 8 * info0["n_dof"]}
         res["copy_ms"] = ctx.time_kernel("copy", 0, "fp64", reps=a.steps)
         for prec in [p for p in a.precisions.split(",") if p]:
-            ms = ctx.time_kernel("element_op", 0, prec, reps=a.steps)
-            byts = op_bytes(info0, nt, npt, prec, a.P)
             flops = op_flops_per_elem(a.P) * info0["n_elem"]
-            res[prec] = {"ms_per_launch": ms, "bytes_per_launch": byts, "GB_per_s": byts / (ms * 1e-3) / 1e9,
-                         "flops_per_launch": flops, "roofline": roofline(byts, flops, ms, prec)}
+            byts = apply_bytes(info0, nt, npt, prec, a.P)
+            t_f = ctx.time_kernel("colsum_op", 0, prec, reps=a.steps)
+            t_s = ctx.time_kernel("col_sum_store", 0, prec, reps=a.steps)
+            ms = ctx.time_kernel("element_op", 0, prec, reps=a.steps)
+            res[prec] = {"ms_element_kernel": t_f, "ms_node_kernel": t_s, "bytes_per_apply": byts,
+                         "GB_per_s": byts / ((t_f + t_s) * 1e-3) / 1e9, "flops_per_apply": flops,
+                         "roofline": roofline(byts, flops, t_f + t_s, prec),
+                         "unfused_element_op_ms": ms,
+                         "unfused_element_op_bytes": op_bytes(info0, nt, npt, prec, a.P)}
         print(json.dumps(res), flush=True)
         return
 
@@ -648,21 +680,49 @@ def main():
         log(f"[bench] {prec}: {dt*1e3:.2f} ms/solve, {st['iters']} its, rel_res {st['rel_res']:.2e}")
 
     best = max(paths, key=lambda k: paths[k]["solves_per_s"] if paths[k]["rel_res"] <= a.rtol * 1.0001 else -1)
-    # dominant kernel: fine-level element operator in the best path's V-cycle precision
+    # dominant kernel: the fine-level operator apply in the best path's V-cycle
+    # precision, as the solve runs it (the element operator with the direct-
+    # stiffness sum inside, plus the kernel finishing the triangle-boundary
+    # nodes), timed as one unit; algorithmic bytes of one apply: geometry, one
+    # read of x, one write of y, the 2D map
     kprec = best
-    ms_k = ctx.time_kernel("element_op", 0, kprec, reps=20)
-    ms_k64 = ctx.time_kernel("element_op", 0, "fp64", reps=20)
-    ms_asm = ctx.time_kernel("assemble", 0, kprec, reps=20)
     nt = mesh["tri"].shape[0]
     npt = (a.P + 1) * (a.P + 2) // 2
-    byts = op_bytes(info0, nt, npt, kprec, a.P)
     flops = op_flops_per_elem(a.P) * info0["n_elem"]
-    byts64 = op_bytes(info0, nt, npt, "fp64", a.P)
-    roof = roofline(byts, flops, ms_k, kprec)
-    roof.update({"traffic": None, "kernel": f"MFMA element operator (P={a.P}), {kprec} path",
-                 "ms_per_launch": ms_k, "bytes_per_launch": byts, "flops_per_launch": flops,
-                 "fp64_kernel": dict(roofline(byts64, flops, ms_k64, "fp64"), ms_per_launch=ms_k64),
-                 "assemble_ms_per_launch": ms_asm})
+    fused = True
+    try:
+        t_f = ctx.time_kernel("colsum_op", 0, kprec, reps=20)
+        t_s = ctx.time_kernel("col_sum_store", 0, kprec, reps=20)
+        t_f64 = ctx.time_kernel("colsum_op", 0, "fp64", reps=20) + ctx.time_kernel("col_sum_store", 0, "fp64", reps=20)
+        t_cf = t_f
+        t_cs = ctx.time_kernel("col_sum_cheb", 0, kprec, reps=20)
+    except Exception:
+        fused = False
+    t_e = ctx.time_kernel("element_op", 0, kprec, reps=20)       # element-layout output (unfused path)
+    t_asm = ctx.time_kernel("assemble", 0, kprec, reps=20)        # its node-centric summation
+    t_e64 = ctx.time_kernel("element_op", 0, "fp64", reps=20)
+    byts = apply_bytes(info0, nt, npt, kprec, a.P)
+    byts64 = apply_bytes(info0, nt, npt, "fp64", a.P)
+    if fused:
+        ms_k, ms_k64 = t_f + t_s, t_f64
+        roof = roofline(byts, flops, ms_k, kprec)
+        roof.update({"traffic": None,
+                     "kernel": f"fine operator apply y = A x (P={a.P}), {kprec} path: element operator writing "
+                               "column sums + node sum",
+                     "ms_per_launch": ms_k, "ms_element_kernel": t_f, "ms_node_kernel": t_s,
+                     "bytes_per_launch": byts, "flops_per_launch": flops,
+                     "fp64_apply": dict(roofline(byts64, flops, ms_k64, "fp64"), ms_per_launch=ms_k64),
+                     "chebyshev_step": {"ms_element_kernel": t_cf, "ms_node_kernel": t_cs,
+                                        "bytes": cheb_bytes(info0, nt, npt, kprec, a.P),
+                                        "GB_per_s": cheb_bytes(info0, nt, npt, kprec, a.P) / ((t_cf + t_cs) * 1e-3)
+                                        / 1e9},
+                     "unfused": {"ms_element_op": t_e, "ms_node_sum": t_asm, "ms_element_op_fp64": t_e64}})
+    else:
+        roof = roofline(byts, flops, t_e + t_asm, kprec)
+        roof.update({"traffic": None, "kernel": f"fine operator apply (P={a.P}), {kprec} path: element operator "
+                                                "+ node-centric sum", "ms_per_launch": t_e + t_asm,
+                     "bytes_per_launch": byts, "flops_per_launch": flops,
+                     "unfused": {"ms_element_op": t_e, "ms_node_sum": t_asm, "ms_element_op_fp64": t_e64}})
     if a.smoother == "schwarz":
         # the dominant kernel is then the batched local solve of the finest level
         roof_op = roof

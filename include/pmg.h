@@ -174,6 +174,18 @@ typedef struct pmg_options {
                              isotropic P; with PZ != P the EQUAL sequences of
                              (4,2), (5,3), (6,4), (2,4), (3,6), (4,8) and the
                              XY_FIRST sequences of (3,6), (2,4), (4,8)           */
+  int32_t fused_sum;      /* 1 (default): where the MFMA element operator can
+                             (layer counts dividing 16, orders up to 16 (node,
+                             prism) pairs per thread, column-factor geometry
+                             for FP64/FP32), it sums each triangle column's
+                             layers itself and writes one value per
+                             (triangle, node, z); a node kernel then adds the
+                             triangles sharing each vertex or edge node and
+                             applies the step's epilogue (the direct-stiffness
+                             sum of Sec. 3.1).  0: element results through the
+                             element layout and the node-centric sum kernel.
+                             Both use no atomics and a fixed order (bitwise
+                             reproducible); they differ by rounding           */
 } pmg_options;
 
 /* Geometric factors read by the MFMA element operators.  STORED: the six
@@ -361,7 +373,8 @@ int pmg_set_solver(pmg_ctx* ctx, int precision, int krylov);
 
 /* Kernels that pmg_time_kernel() can time in isolation. */
 enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, PMG_K_RESTRICT = 3,
-                  PMG_K_PROLONG = 4, PMG_K_COPY = 5, PMG_K_SCHWARZ = 6 };
+                  PMG_K_PROLONG = 4, PMG_K_COPY = 5, PMG_K_SCHWARZ = 6, PMG_K_COLSUM_OP = 7,
+                  PMG_K_COL_SUM_STORE = 8, PMG_K_COL_SUM_CHEB = 9 };
 /* Average duration (ms) of `reps` back-to-back launches of one kernel of
  * level `level` on `stream`, bracketed by hipEvents on that stream (for
  * roofline measurement).  The element operator reads the level's work vector;
@@ -370,7 +383,11 @@ enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, 
  * scales hardware byte counters.  PMG_K_SCHWARZ is the batched local solve of
  * the Schwarz smoother (inverse storage: FP64 for PMG_FP64, FP32 for
  * PMG_MIXED_FP32, BF16 for the BF16 precisions); EINVAL when the smoother is
- * not PMG_SMOOTH_SCHWARZ or the level is the coarsest. */
+ * not PMG_SMOOTH_SCHWARZ or the level is the coarsest.  PMG_K_COLSUM_OP: the
+ * element operator writing column sums (pmg_options.fused_sum); PMG_K_COL_SUM_STORE
+ * / PMG_K_COL_SUM_CHEB: the node kernel that sums them, with the epilogue
+ * y = A x or a Chebyshev smoothing step (r -= A d; d = w d + c D^-1 r;
+ * x += d); EINVAL where the level has no column-sum path. */
 int pmg_time_kernel(pmg_ctx* ctx, int kernel, int level, int precision, int reps, double* ms_per_launch,
                     void* stream);
 

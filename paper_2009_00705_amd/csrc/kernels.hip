@@ -15,6 +15,7 @@
 
 #include <cmath>
 
+#include "epilogue.hpp"
 #include "kernels.hpp"
 
 namespace pmg {
@@ -240,41 +241,14 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, 
       s += col[p1];
       if (p2 >= 0) s += col[p2];
     }
-    if (OP == OP_RAW) {
-      out[g] = s;
-    } else if (OP == OP_STORE) {
-      out[g] = dir ? T(0) : s;
-    } else if (OP == OP_AVG_RAW) {
+    if constexpr (OP == OP_AVG_RAW) {
       out[g] = s / T((j1 - j0) * (p2 >= 0 ? 2 : 1));
-    } else if (OP == OP_AVG_ADD || OP == OP_AVG_STORE) {
+    } else if constexpr (OP == OP_AVG_ADD || OP == OP_AVG_STORE) {
       const T m = T((j1 - j0) * (p2 >= 0 ? 2 : 1));
       const T v = dir ? T(0) : s / m;
       if (OP == OP_AVG_ADD) out[g] += v; else out[g] = v;
-    } else if (OP == OP_RESID) {
-      out[g] = dir ? T(0) : a1[g] - s;
-    } else if (OP == OP_JACOBI) {
-      if (!dir) out[g] += omega * a2[g] * (a1[g] - s);
-    } else if (OP == OP_STORE_DOT) {
-      const T v = dir ? T(0) : s;
-      out[g] = v;
-      acc += double(a1[g]) * double(v);
-    } else if (OP == OP_CHEB0) {
-      // r = f - A x, d = c1 D^-1 r, x += d (D^-1 is zero at Dirichlet nodes)
-      const T rn = dir ? T(0) : a1[g] - s;
-      a4[g] = rn;
-      const T dn = c1 * a2[g] * rn;
-      a3[g] = dn;
-      out[g] += dn;
-    } else if (OP == OP_CHEB) {
-      // x = out, r = a1 (in/out through a3 alias), d = a3
-      if (!dir) {
-        T* r = const_cast<T*>(a1);
-        const T rn = r[g] - s;
-        r[g] = rn;
-        const T dn = omega * a3[g] + c1 * a2[g] * rn;
-        a3[g] = dn;
-        out[g] += dn;
-      }
+    } else {
+      node_epilogue<T, OP>(g, dir, s, out, a1, a2, a3, a4, omega, c1, acc);
     }
   }
   if (OP == OP_STORE_DOT) {
@@ -308,6 +282,70 @@ void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a
 }
 template void launch_assemble<double>(const LevelView&, int, const double*, double*, const double*, const double*, double*, double, double, double*, hipStream_t, double*);
 template void launch_assemble<float>(const LevelView&, int, const float*, float*, const float*, const float*, float*, double, double, double*, hipStream_t, float*);
+
+// ---------------------------------------------------------------------------
+// Node sum from column sums (see launch_col_sum in kernels.hpp).  Thread per
+// global node g = n nz + z: a triangle-interior node (n >= n_bnd) reads its one
+// value, cv[g - n_bnd nz], in global order; a vertex or edge node adds the
+// column sums cv_b[(t 3P + s) nz + z] of the triangles holding it (ascending
+// triangle order).  Then the node epilogue.  z is fastest across a wave, so
+// every read is a contiguous run.
+// ---------------------------------------------------------------------------
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_col_sum(int64_t n_dof, uint32_t nz, int64_t n_bnd,
+                                                 const T* __restrict__ cv, const T* __restrict__ cv_b,
+                                                 const int32_t* __restrict__ sh_ptr,
+                                                 const int32_t* __restrict__ sh_idx,
+                                                 const uint8_t* __restrict__ dir2d, int top_dir,
+                                                 T* __restrict__ out, const T* __restrict__ a1,
+                                                 const T* __restrict__ a2, T* __restrict__ a3, T omega, T c1,
+                                                 double* __restrict__ partial, T* __restrict__ a4) {
+  double acc = 0.0;
+  const int64_t g_bnd = n_bnd * int64_t(nz);
+  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n_dof; g += int64_t(gridDim.x) * 256) {
+    const uint32_t gu = uint32_t(g), n2 = gu / nz, z = gu - n2 * nz;  // n_dof < 2^32 (colsum levels)
+    T s;
+    if (g >= g_bnd) {
+      s = cv[g - g_bnd];
+    } else {
+      s = 0;
+      const int j1 = sh_ptr[n2 + 1];
+      for (int j = sh_ptr[n2]; j < j1; ++j) s += cv_b[size_t(sh_idx[j]) * nz + z];
+    }
+    const bool dir = dir2d[n2] || (top_dir && z == nz - 1);
+    node_epilogue<T, OP>(g, dir, s, out, a1, a2, a3, a4, omega, c1, acc);
+  }
+  if constexpr (OP == OP_STORE_DOT) {
+    const double b = block_sum256(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+  }
+}
+
+template <typename T>
+void launch_col_sum(const LevelView& lv, int op, const T* cv, T* out, const T* a1, const T* a2, T* a3,
+                    double omega, double c1, double* partial, hipStream_t st, T* a4) {
+  const int grid = op == OP_STORE_DOT ? RED_BLOCKS : grid_for(lv.n_dof);
+  const T* cv_b = cv + int64_t(lv.nt) * lv.nint * lv.nz;
+#define PMG_CS(OPV)                                                                                     \
+  hipLaunchKernelGGL((k_col_sum<T, OPV>), dim3(grid), dim3(256), 0, st, lv.n_dof, uint32_t(lv.nz), lv.n_bnd, \
+                     cv, cv_b, lv.sh_ptr, lv.sh_idx, lv.dir2d, lv.top_dir, out, a1, a2, a3, T(omega), T(c1), \
+                     partial, a4)
+  switch (op) {
+    case OP_STORE: PMG_CS(OP_STORE); break;
+    case OP_RESID: PMG_CS(OP_RESID); break;
+    case OP_JACOBI: PMG_CS(OP_JACOBI); break;
+    case OP_STORE_DOT: PMG_CS(OP_STORE_DOT); break;
+    case OP_CHEB: PMG_CS(OP_CHEB); break;
+    case OP_RAW: PMG_CS(OP_RAW); break;
+    case OP_CHEB0: PMG_CS(OP_CHEB0); break;
+    default: break;
+  }
+#undef PMG_CS
+}
+template void launch_col_sum<double>(const LevelView&, int, const double*, double*, const double*, const double*,
+                                     double*, double, double, double*, hipStream_t, double*);
+template void launch_col_sum<float>(const LevelView&, int, const float*, float*, const float*, const float*,
+                                    float*, double, double, double*, hipStream_t, float*);
 
 // ---------------------------------------------------------------------------
 // geometric factors (thread per triangle x triangle cubature point)

@@ -40,23 +40,6 @@ enum Scal {
 bool order_supported(int PT, int PZ);
 bool pair_supported(int PFT, int PFZ, int PCT, int PCZ);
 
-// Per-level device description.
-struct LevelView {
-  int P, PZ, L, nt;        // P: triangle order, PZ: vertical order
-  int np_tri, np, nq;
-  int64_t n2d, nz, n_dof, n_elem;
-  const int32_t* map2d;    // [nt][np_tri]
-  const int32_t* inc_ptr;  // [n2d+1]
-  const int32_t* inc;      // [nnz] = t*np_tri + a
-  const uint8_t* dir2d;    // [n2d] lateral Dirichlet columns
-  int top_dir;             // surface nodes are Dirichlet
-};
-
-// ---- element operator: Y_E = blockdiag(A_e) Q u (E-layout [t][a][layer][c])
-template <typename T>
-void launch_ax(const LevelView& lv, const T* mats, const void* G, int gstore, const T* u, T* Y,
-               hipStream_t st);
-
 // ---- direct-stiffness sum of an E-layout vector (atomic-free, node-centric)
 enum AsmOp {
   OP_STORE = 0,     // out = mask * sum
@@ -70,6 +53,48 @@ enum AsmOp {
   OP_AVG_RAW = 8,   // out = sum / multiplicity (no mask)
   OP_CHEB0 = 9      // first Chebyshev step from x = out: a4 = r = mask (a1 - sum), a3 = d = c1 a2 r, x += d
 };
+
+// Per-level device description.
+struct LevelView {
+  int P, PZ, L, nt;        // P: triangle order, PZ: vertical order
+  int np_tri, np, nq;
+  int64_t n2d, nz, n_dof, n_elem;
+  const int32_t* map2d;    // [nt][np_tri]
+  const int32_t* inc_ptr;  // [n2d+1]
+  const int32_t* inc;      // [nnz] = t*np_tri + a
+  const uint8_t* dir2d;    // [n2d] lateral Dirichlet columns
+  int top_dir;             // surface nodes are Dirichlet
+  // Column-sum layout (launch_col_sum): 2D ids below n_bnd are vertices and
+  // edge nodes (on triangle boundaries), those from n_bnd on are triangle
+  // interiors, nint per triangle in triangle order.  sh_ptr/sh_idx: for every
+  // 2D node below n_bnd the boundary slots t*3P + s of the triangles holding
+  // it, in ascending triangle order.  colsum: this level's numbering has that
+  // form and L divides 16 (the MFMA operators can write column sums).
+  int64_t n_bnd;
+  int nint;
+  const int32_t* sh_ptr;   // [n_bnd+1]
+  const int32_t* sh_idx;   // [sh_ptr[n_bnd]] = t*3P + s
+  int colsum;
+};
+
+// Direct-stiffness sum from column sums.  A batch of 16 prisms holds 16/L whole
+// triangle columns (L divides 16), so the element operator sums each column's
+// layers itself and writes one value per (triangle, local node, z): at the
+// nint interior nodes of triangle t to cv[(t nint + rank) nz + z] (the 2D node
+// n_bnd + t nint + rank, so this part of cv is in global-vector order), at the
+// 3P boundary nodes to cv[nt nint nz + (t 3P + s) nz + z] (s: tri_slot).  The
+// node kernel then reads an interior node's value directly and sums a boundary
+// node's slots over the triangles holding it (ascending triangle order), and
+// applies the node epilogue op.  No atomics; every sum has a fixed order.
+template <typename T>
+void launch_col_sum(const LevelView& lv, int op, const T* cv, T* out, const T* a1, const T* a2, T* a3,
+                    double omega, double c1, double* partial, hipStream_t st, T* a4 = nullptr);
+
+// ---- element operator: Y_E = blockdiag(A_e) Q u (E-layout [t][a][layer][c])
+template <typename T>
+void launch_ax(const LevelView& lv, const T* mats, const void* G, int gstore, const T* u, T* Y,
+               hipStream_t st);
+
 template <typename T>
 void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a1, const T* a2,
                      T* a3, double omega, double c1, double* partial, hipStream_t st, T* a4 = nullptr);

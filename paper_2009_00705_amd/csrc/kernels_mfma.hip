@@ -25,6 +25,7 @@
 
 #include <algorithm>
 
+#include "epilogue.hpp"
 #include "kernels.hpp"
 #include "kernels_mfma.hpp"
 
@@ -182,7 +183,8 @@ __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L
     const int64_t e = b * 16 + el;
     T v[N1];
     if (e < n_elem) {
-      const int te = int(e / L), layer = int(e - int64_t(te) * L);
+      const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
+      const int te = int(tu), layer = int(eu - tu * uint32_t(L));
       const T* col = u + int64_t(map2d[size_t(te) * NPT + a]) * nz + layer * PZ;
 #pragma unroll
       for (int c = 0; c < N1; ++c) v[c] = col[c];
@@ -239,7 +241,8 @@ __device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, c
       yr[kk] = sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el];
       yt[kk] = sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
     }
-    const int te = int(e / L), layer = int(e - int64_t(te) * L);
+    const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
+    const int te = int(tu), layer = int(eu - tu * uint32_t(L));
     T* out = Y + ((size_t(te) * NPT + a) * L + layer) * N1;
     // rolled: the coefficients are LDS broadcasts read per c, not 2(PZ+1)^2 registers
 #pragma unroll 1
@@ -250,6 +253,54 @@ __device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, c
       out[c] = y;
     }
   }
+}
+
+// Phase 2 writing column sums (CS; 16 % L == 0, so the batch holds 16/L whole
+// columns and prism el + 1 is the layer above el).  Thread (a, el) reads its
+// partials from S, then (once every thread holds its own) writes y[c] of prism
+// el to LDS as Ycol[el][a][c]; it then writes the column values z = layer PZ +
+// c, c = (layer > 0) .. PZ, of its (triangle, node a), the top one adding the
+// bottom value of the layer above: for a node inside the triangle to
+// Y[(te NINT + rank) nz + z], for a node on the triangle's boundary to
+// Y[nt NINT nz + (te 3P + s) nz + z] (layout of launch_col_sum).  Only stores
+// leave the workgroup: nothing in this phase waits on global memory.
+template <int PT, int PZ, typename T>
+__device__ __forceinline__ void vertical_colsum(int te, int layer, int L, int nz, int64_t bnd_off,
+                                                T* __restrict__ sR, const T* __restrict__ sV, T* __restrict__ Y) {
+  using D = MD<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NAT = D::NAT, NTH = 64 * N1, NINT = (PT - 1) * (PT - 2) / 2;
+  static_assert(16 * NPT <= NTH, "one (node, prism) pair per thread");
+  static_assert(16 * NPT * N1 <= KS_LDS<PT, PZ>::R_WORDS, "Ycol fits in the staging buffer");
+  const int pr = threadIdx.x, a = pr >> 4, el = pr & 15;
+  const bool act = pr < 16 * NPT;
+  T yr[N1], yt[N1];
+  if (act) {
+#pragma unroll
+    for (int kk = 0; kk < N1; ++kk) {
+      yr[kk] = sR[((kk * 2 + 0) * NAT * 16 + a) * 16 + el];
+      yt[kk] = sR[((kk * 2 + 1) * NAT * 16 + a) * 16 + el];
+    }
+  }
+  __syncthreads();  // every thread holds its partials; sR becomes Ycol
+  T* ycol = sR + (el * NPT + a) * N1;
+  if (act) {
+#pragma unroll 1
+    for (int c = 0; c < N1; ++c) {
+      T v = 0;
+#pragma unroll
+      for (int kk = 0; kk < N1; ++kk) v += sV[kk * N1 + c] * yr[kk] + sV[N1 * N1 + kk * N1 + c] * yt[kk];
+      ycol[c] = v;
+    }
+  }
+  __syncthreads();
+  if (!act || te < 0) return;
+  const bool above = layer + 1 < L;
+  const T top = above ? sR[((el + 1) * NPT + a) * N1] : T(0);
+  const int code = tri_code<PT>(a);
+  T* dst = (code >= 0 ? Y + bnd_off + (size_t(te) * (3 * PT) + code) * nz
+                      : Y + (size_t(te) * NINT + (-1 - code)) * nz) + layer * PZ;
+#pragma unroll 1
+  for (int c = layer > 0 ? 1 : 0; c < N1; ++c) dst[c] = c == PZ && above ? ycol[c] + top : ycol[c];
 }
 
 // geometric factors of one full tile (lane-native: 4 contiguous values per lane)
@@ -297,7 +348,9 @@ __device__ __forceinline__ void load8(const float* p, float (&b)[8]) {
     b[4 * i + 3] = v.w;
   }
 }
-template <typename T, int PT, int PZ, bool F64ROW>
+// ONE: the Gauss weight zw_k is carried by the vertical transpose (its rows of
+// Bz and Dz scaled by zw_k), so G is formed without it (p = 1).
+template <typename T, int PT, int PZ, bool F64ROW, bool ONE = false>
 __device__ __forceinline__ void load_geo(const T* __restrict__ geo, int64_t tri, int t, int g, T p, T ps, T ps2,
                                          T (&gv)[6][4]) {
   using D = MD<PT, PZ>;
@@ -307,12 +360,19 @@ __device__ __forceinline__ void load_geo(const T* __restrict__ geo, int64_t tri,
     const int q = 16 * t + row_of<F64ROW>(g, r);
     T bq[8];
     load8(geo + (tc * D::NQT + (q < D::NQT ? q : D::NQT - 1)) * 8, bq);
-    gv[0][r] = p * bq[0];
-    gv[1][r] = p * bq[1];
+    if constexpr (ONE) {
+      gv[0][r] = bq[0];
+      gv[1][r] = bq[1];
+      gv[3][r] = bq[3];
+      gv[5][r] = ps2 * bq[5] + bq[6];
+    } else {
+      gv[0][r] = p * bq[0];
+      gv[1][r] = p * bq[1];
+      gv[3][r] = p * bq[3];
+      gv[5][r] = ps2 * bq[5] + p * bq[6];
+    }
     gv[2][r] = ps * bq[2];
-    gv[3][r] = p * bq[3];
     gv[4][r] = ps * bq[4];
-    gv[5][r] = ps2 * bq[5] + p * bq[6];
   }
 }
 // per-lane constants of load_geo for the lane's column slot at vertical Gauss point k
@@ -334,8 +394,9 @@ __device__ __forceinline__ void geo_lane(int64_t e, int64_t n_elem, int L, T zw,
   tri = -1;
   p = ps = ps2 = T(0);
   if (e < n_elem) {
-    tri = e / L;
-    const T sg = (T(int(e - tri * L)) + zh) / T(L);
+    const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
+    tri = tu;
+    const T sg = (T(int(eu - tu * uint32_t(L))) + zh) / T(L);
     p = zw;
     ps = zw * sg;
     ps2 = ps * sg;
@@ -358,7 +419,9 @@ __device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds,
 // fit in the LDS together); one workgroup per CU then.
 // GEO: G from the column factors (Gnat is then geo[t][q][8] of type T) instead
 // of the stored lane-native G.
-template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW, bool GT = false, bool GEO = false>
+// CS: phase 2 writes column sums (vertical_colsum) instead of the E-layout output.
+template <int PT, int PZ, typename T, typename TG, typename ACC, bool F64ROW, bool GT = false, bool GEO = false,
+          bool CS = false>
 __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >= 8 ? 3 : ((GEO && PT <= 3) ? 6 : 4)))) void k_ax_mfma4(const int32_t* __restrict__ map2d, int L, int nz,
                                                          int64_t n_elem, int64_t n_batch,
                                                          const TG* __restrict__ Gnat, const T* __restrict__ tab2,
@@ -379,7 +442,13 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     for (int i = threadIdx.x; i < NTAB2; i += NTH) s2buf[i] = tab2[i];
     for (int i = threadIdx.x; i < NTAB4; i += NTH) s4buf[i] = tab4[i];
   }
-  for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
+  // vertical transpose coefficients; with the column factors (GEO) row k carries
+  // the Gauss weight zw_k, which G then leaves out
+  for (int i = threadIdx.x; i < N1 * N1; i += NTH) {
+    const T w = GEO ? vm.zw[i / N1] : T(1);
+    sV[i] = vm.Bz[i] * w;
+    sV[N1 * N1 + i] = vm.Dz[i] * w;
+  }
   const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
   // wave-uniform vertical level: its Bz/Dz row stays in scalar registers
   const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -389,6 +458,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     bzk[c] = vm.Bz[k * N1 + c];
     dzk[c] = vm.Dz[k * N1 + c];
   }
+  const int64_t bnd_off = CS ? int64_t(n_elem / L) * ((PT - 1) * (PT - 2) / 2) * nz : 0;
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();  // previous batch's phase 2 done with sR
@@ -421,11 +491,11 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     constexpr int64_t MST = 16 * D::NQT;
     int64_t tri;
     T gp, gps, gps2;
-    if constexpr (GEO) geo_lane<T>(cs, L, vm.zw[k], vm.zh[k], tri, gp, gps, gps2);
+    if constexpr (GEO) geo_lane<T>(cs, L, T(1), vm.zh[k], tri, gp, gps, gps2);
     T ga[6][4];
 #pragma unroll 1
     for (int t = 0; t < D::NTF; ++t) {
-      if constexpr (GEO) load_geo<T, PT, PZ, F64ROW>((const T*)Gnat, tri, t, g, gp, gps, gps2, ga);
+      if constexpr (GEO) load_geo<T, PT, PZ, F64ROW, true>((const T*)Gnat, tri, t, g, gp, gps, gps2, ga);
       else load_full<T>(Gnat, blk, MST, t, lane, ga);
       ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
 #pragma unroll
@@ -448,7 +518,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     }
     if constexpr (D::NQR > 0) {
       constexpr int t = D::NTF;
-      if constexpr (GEO) load_geo<T, PT, PZ, F64ROW>((const T*)Gnat, tri, D::NTF, g, gp, gps, gps2, ga);
+      if constexpr (GEO) load_geo<T, PT, PZ, F64ROW, true>((const T*)Gnat, tri, D::NTF, g, gp, gps, gps2, ga);
       else load_rem<T, D::NTF, D::NQR, F64ROW>(Gnat, blk, MST, g, j, ga);
       ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
       if constexpr (D::NQR == 1) {
@@ -508,7 +578,8 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
       }
     __syncthreads();
     // phase 2: y[el][c][a] = sum_k Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]
-    vertical_out<PT, PZ, T>(L, cs, sR, sV, Y);
+    if constexpr (CS) vertical_colsum<PT, PZ, T>(cs.te, cs.layer, L, nz, bnd_off, sR, sV, Y);
+    else vertical_out<PT, PZ, T>(L, cs, sR, sV, Y);
   }
 }
 
@@ -542,7 +613,7 @@ __device__ __forceinline__ void load_g_bf16(const bf16_t* __restrict__ Gnat, int
 }
 
 // BF16 operands, FP32 accumulation (K = 16)
-template <int PT, int PZ, typename TG>
+template <int PT, int PZ, typename TG, bool CS = false>
 __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16(const int32_t* __restrict__ map2d, int L, int nz,
                                                              int64_t n_elem, int64_t n_batch,
                                                              const TG* __restrict__ Gnat,
@@ -561,6 +632,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
   for (int i = threadIdx.x; i < NTAB4; i += NTH) s4[i] = tab4[i];
   for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
   const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
+  const int64_t bnd_off = CS ? int64_t(n_elem / L) * ((PT - 1) * (PT - 2) / 2) * nz : 0;
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();
@@ -663,7 +735,14 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
         sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
       }
     __syncthreads();
-    vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
+    if constexpr (CS) {
+      const int64_t e = b * 16 + (threadIdx.x & 15);
+      const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
+      vertical_colsum<PT, PZ, float>(e < n_elem ? int(tu) : -1, int(eu - tu * uint32_t(L)), L, nz, bnd_off, sR, sV,
+                                     Y);
+    } else {
+      vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
+    }
   }
 }
 
@@ -683,7 +762,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
 //   MFMAs, the LDS of the plain BF16 kernel.
 // GEO: G in FP32 from the FP32 column factors (Gsrc = geo[t][q][8]) instead of
 // the stored lane-native BF16 G (Gsrc = Gnat).
-template <int PT, int PZ, bool LO, bool GEO = false>
+template <int PT, int PZ, bool LO, bool GEO = false, bool CS = false>
 __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_mfma_bf16x3(const int32_t* __restrict__ map2d, int L,
                                                                      int nz, int64_t n_elem, int64_t n_batch,
                                                                      const void* __restrict__ Gsrc,
@@ -703,6 +782,9 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
   __shared__ s4_t s4l[LO ? NTAB4 : 1];
   __shared__ float sR[KS_LDS<PT, PZ>::R_WORDS];
   __shared__ float sV[2 * N1 * N1];
+  // vertical transpose coefficients with the Gauss weight zw_k in row k (GEO:
+  // G is then formed without it); stage 1 reads the plain sV
+  __shared__ float sVw[GEO ? 2 * N1 * N1 : 1];
   for (int i = threadIdx.x; i < NTAB2; i += NTH) {
     s2[i] = tab2[i];
     if constexpr (LO) s2l[i] = tab2lo[i];
@@ -711,10 +793,19 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
     s4[i] = tab4[i];
     if constexpr (LO) s4l[i] = tab4lo[i];
   }
-  for (int i = threadIdx.x; i < N1 * N1; i += NTH) { sV[i] = vm.Bz[i]; sV[N1 * N1 + i] = vm.Dz[i]; }
+  for (int i = threadIdx.x; i < N1 * N1; i += NTH) {
+    sV[i] = vm.Bz[i];
+    sV[N1 * N1 + i] = vm.Dz[i];
+    if constexpr (GEO) {
+      sVw[i] = vm.Bz[i] * vm.zw[i / N1];
+      sVw[N1 * N1 + i] = vm.Dz[i] * vm.zw[i / N1];
+    }
+  }
+  const float* __restrict__ sVo = GEO ? sVw : sV;  // coefficients of the vertical transpose
   const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
   const bf16_t* __restrict__ Gnat = static_cast<const bf16_t*>(Gsrc);
   const float* __restrict__ geo = static_cast<const float*>(Gsrc);
+  const int64_t bnd_off = CS ? int64_t(n_elem / L) * ((PT - 1) * (PT - 2) / 2) * nz : 0;
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();
@@ -726,7 +817,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
     uint32_t gw[6][2];
     int64_t tri;
     float gp, gps, gps2;
-    if constexpr (GEO) geo_lane<float>(b * 16 + j, n_elem, L, vm.zw[k], vm.zh[k], tri, gp, gps, gps2);
+    if constexpr (GEO) geo_lane<float>(b * 16 + j, n_elem, L, 1.0f, vm.zh[k], tri, gp, gps, gps2);
     else load_g_bf16<PT, PZ>(Gnat, blk, mst, 0, lane, g, j, gw);
     stage_u<PT, PZ, float>(map2d, L, nz, n_elem, b, u, sR);
     __syncthreads();
@@ -760,7 +851,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
       uint32_t gc[6][2];
       float gg[6][4];
       if constexpr (GEO) {
-        load_geo<float, PT, PZ, false>(geo, tri, t, g, gp, gps, gps2, gg);
+        load_geo<float, PT, PZ, false, true>(geo, tri, t, g, gp, gps, gps2, gg);
       } else {
 #pragma unroll
         for (int m = 0; m < 6; ++m) { gc[m][0] = gw[m][0]; gc[m][1] = gw[m][1]; }
@@ -831,7 +922,14 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
         sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
       }
     __syncthreads();
-    vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
+    if constexpr (CS) {
+      const int64_t e = b * 16 + (threadIdx.x & 15);
+      const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
+      vertical_colsum<PT, PZ, float>(e < n_elem ? int(tu) : -1, int(eu - tu * uint32_t(L)), L, nz, bnd_off, sR,
+                                     sVo, Y);
+    } else {
+      vertical_out<PT, PZ, float>(L, n_elem, b, sR, sVo, Y);
+    }
   }
 }
 
@@ -955,72 +1053,110 @@ static void launch_batches(K kern, int NT, int64_t need, hipStream_t st, A... ar
   static const int grid = grid_batches(1 << 30, (const void*)kern, NT);
   hipLaunchKernelGGL(kern, dim3(std::min<int64_t>(grid, need)), dim3(NT), 0, st, args...);
 }
-template <int PT, int PZ, int FL, bool GEO> struct KeyOf {};
+template <int PT, int PZ, int FL, bool GEO, bool CS = false> struct KeyOf {};
 
 template <int PT, int PZ>
-static void ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
+static bool ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                       const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo,
-                      const void* tab4lo, const void* geo) {
+                      const void* tab4lo, const void* geo, bool colsum) {
   const int64_t nb = (lv.n_elem + 15) / 16;
   const int64_t need = ((nb + 7) / 8) * 8;
   constexpr int NT = 64 * (PZ + 1);
+  // the column-sum phase 2 keeps one (node, prism) pair per thread
+  constexpr bool CSOK = 16 * MD<PT, PZ>::NPT <= NT;
+  if (colsum && (!CSOK || !lv.colsum)) return false;
   const VertMats<double>& v64 = *(const VertMats<double>*)vmats;
   const VertMats<float>& v32 = *(const VertMats<float>*)vmats;
-#define PMG_ARGS(TG, TT, VM) lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb, (const TG*)G, (const TT*)tab2, (const TT*)tab4, \
-    VM, (const TT*)u, (TT*)Y
+#define PMG_ARGS(TG, TT, VM) lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb, (const TG*)G, (const TT*)tab2, \
+    (const TT*)tab4, VM, (const TT*)u, (TT*)Y
+// launch with column sums (C = true) or the element layout
+#define PMG_CSW(LAUNCH)                  \
+  if (colsum) {                          \
+    if constexpr (CSOK) LAUNCH(true);    \
+  } else {                               \
+    LAUNCH(false);                       \
+  }                                      \
+  return true;
   if (flavour == MF_F64) {
     const void* G = geo ? geo : Gnat;
-    if (geo)
-      launch_batches<KeyOf<PT, PZ, MF_F64, true>>(k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8, true>, NT,
-                                                  need, st, PMG_ARGS(double, double, v64));
-    else
-      launch_batches<KeyOf<PT, PZ, MF_F64, false>>(k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8>, NT,
-                                                   need, st, PMG_ARGS(double, double, v64));
+    if (geo) {
+#define PMG_L(C)                                                                                              \
+  launch_batches<KeyOf<PT, PZ, MF_F64, true, C>>(k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8, true, C>, \
+                                                 NT, need, st, PMG_ARGS(double, double, v64))
+      PMG_CSW(PMG_L)
+#undef PMG_L
+    }
+    if (colsum) return false;
+    launch_batches<KeyOf<PT, PZ, MF_F64, false>>(k_ax_mfma4<PT, PZ, double, double, d4_t, true, PT == 8>, NT,
+                                                 need, st, PMG_ARGS(double, double, v64));
+    return true;
   } else if (flavour == MF_F32) {
     const void* G = geo ? geo : Gnat;
-    if (geo)
-      launch_batches<KeyOf<PT, PZ, MF_F32, true>>(k_ax_mfma4<PT, PZ, float, float, f4_t, false, false, true>, NT,
-                                                  need, st, PMG_ARGS(float, float, v32));
-    else
-      launch_batches<KeyOf<PT, PZ, MF_F32, false>>(k_ax_mfma4<PT, PZ, float, float, f4_t, false>, NT, need, st,
-                                                   PMG_ARGS(float, float, v32));
+    if (geo) {
+#define PMG_L(C)                                                                                             \
+  launch_batches<KeyOf<PT, PZ, MF_F32, true, C>>(k_ax_mfma4<PT, PZ, float, float, f4_t, false, false, true, C>, \
+                                                 NT, need, st, PMG_ARGS(float, float, v32))
+      PMG_CSW(PMG_L)
+#undef PMG_L
+    }
+    if (colsum) return false;
+    launch_batches<KeyOf<PT, PZ, MF_F32, false>>(k_ax_mfma4<PT, PZ, float, float, f4_t, false>, NT, need, st,
+                                                 PMG_ARGS(float, float, v32));
+    return true;
   } else if (flavour == MF_F32G16) {
     const void* G = Gnat;
-    launch_batches<KeyOf<PT, PZ, MF_F32G16, false>>(k_ax_mfma4<PT, PZ, float, bf16_t, f4_t, false>, NT, need, st,
-                                                    PMG_ARGS(bf16_t, float, v32));
+#define PMG_L(C)                                                                                              \
+  launch_batches<KeyOf<PT, PZ, MF_F32G16, false, C>>(                                                         \
+      k_ax_mfma4<PT, PZ, float, bf16_t, f4_t, false, false, false, C>, NT, need, st, PMG_ARGS(bf16_t, float, v32))
+    PMG_CSW(PMG_L)
+#undef PMG_L
   } else if (flavour == MF_BF16X3 || flavour == MF_BF16X2) {
     if constexpr (PT == 6) {
       const void* G = geo ? geo : Gnat;
       const void* lo2 = flavour == MF_BF16X3 ? tab2lo : nullptr;
       const void* lo4 = flavour == MF_BF16X3 ? tab4lo : nullptr;
-#define PMG_X(LO, GE)                                                                                         \
-  launch_batches<KeyOf<PT, PZ, LO ? MF_BF16X3 : MF_BF16X2, GE>>(                                              \
-      k_ax_mfma_bf16x3<PT, PZ, LO, GE>, NT, need, st, lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb, G,           \
-      (const s4_t*)tab2, (const s4_t*)tab4, (const s4_t*)lo2, (const s4_t*)lo4, v32, (const float*)u, (float*)Y)
+#define PMG_X(LO, GE, C)                                                                                      \
+  launch_batches<KeyOf<PT, PZ, LO ? MF_BF16X3 : MF_BF16X2, GE, C>>(                                           \
+      k_ax_mfma_bf16x3<PT, PZ, LO, GE, C>, NT, need, st, lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb, G,        \
+      (const s4_t*)tab2, (const s4_t*)tab4, (const s4_t*)lo2, (const s4_t*)lo4, v32, (const float*)u,         \
+      (float*)Y)
+      if (flavour == MF_BF16X3 && geo) {
+#define PMG_L(C) PMG_X(true, true, C)
+        PMG_CSW(PMG_L)
+#undef PMG_L
+      }
+      if (colsum) return false;
       if (flavour == MF_BF16X3) {
-        if (geo) PMG_X(true, true); else PMG_X(true, false);
+        PMG_X(true, false, false);
       } else {
-        if (geo) PMG_X(false, true); else PMG_X(false, false);
+        if (geo) PMG_X(false, true, false); else PMG_X(false, false, false);
       }
 #undef PMG_X
+      return true;
     }
+    return false;
   } else {
-    launch_batches<KeyOf<PT, PZ, MF_BF16, false>>(k_ax_mfma_bf16<PT, PZ, bf16_t>, NT, need, st, lv.map2d, lv.L,
-                                                  int(lv.nz), lv.n_elem, nb, (const bf16_t*)Gnat,
-                                                  (const s4_t*)tab2, (const s4_t*)tab4, v32, (const float*)u,
-                                                  (float*)Y);
+#define PMG_L(C)                                                                                              \
+  launch_batches<KeyOf<PT, PZ, MF_BF16, false, C>>(                                                           \
+      k_ax_mfma_bf16<PT, PZ, bf16_t, C>, NT, need, st, lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb,             \
+      (const bf16_t*)Gnat, (const s4_t*)tab2, (const s4_t*)tab4, v32, (const float*)u, (float*)Y)
+    PMG_CSW(PMG_L)
+#undef PMG_L
   }
+#undef PMG_CSW
 #undef PMG_ARGS
+  return false;
 }
 
-void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
+bool launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                     const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo,
-                    const void* tab4lo, const void* geo) {
+                    const void* tab4lo, const void* geo, bool colsum) {
 #define PMG_AXM(PTV, PZV)                                                                                      \
   if (lv.P == PTV && lv.PZ == PZV)                                                                             \
-    return ax_mfma_p<PTV, PZV>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st, tab2lo, tab4lo, geo);
+    return ax_mfma_p<PTV, PZV>(lv, Gnat, flavour, tab2, tab4, vmats, u, Y, st, tab2lo, tab4lo, geo, colsum);
   PMG_MFMA_ORDERS(PMG_AXM)
 #undef PMG_AXM
+  return false;
 }
 
 }  // namespace pmg

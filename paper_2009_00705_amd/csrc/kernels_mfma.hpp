@@ -54,8 +54,12 @@ void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out,
 // and the split-BF16 flavours; ignored by MF_BF16 and MF_F32G16, which read
 // their stored BF16 G), from which the kernel computes G in place of reading
 // Gnat.
-void launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
+// colsum: write column sums (the layout of launch_col_sum) instead of the
+// element layout; returns false, launching nothing, when the level has no
+// such kernel (the level's colsum flag, orders with more (node, prism) pairs
+// per batch than threads, stored-G FP64/FP32, MF_BF16X2); otherwise true.
+bool launch_ax_mfma(const LevelView& lv, const void* Gnat, int flavour, const void* tab2, const void* tab4,
                     const void* vmats, const void* u, void* Y, hipStream_t st, const void* tab2lo = nullptr,
-                    const void* tab4lo = nullptr, const void* geo = nullptr);
+                    const void* tab4lo = nullptr, const void* geo = nullptr, bool colsum = false);
 
 }  // namespace pmg

@@ -27,6 +27,7 @@
 #include "pmg.h"
 #include "refelem.hpp"
 #include "schwarz.hpp"
+#include "epilogue.hpp"
 #include "fnpf.hpp"
 
 namespace pmg {
@@ -77,6 +78,9 @@ struct Level {
   int top_dir = 1;
   // device
   int32_t *map2d = nullptr, *inc_ptr = nullptr, *inc = nullptr;
+  int32_t *sh_ptr = nullptr, *sh_idx = nullptr;  // boundary nodes of the column-sum path
+  int64_t n_bnd = 0;
+  int nint = 0, colsum = 0;
   uint8_t* dir2d = nullptr;
   double* mats64 = nullptr;
   float* mats32 = nullptr;
@@ -559,8 +563,42 @@ static void upload_levels(pmg_ctx* c) {
       L.sz_z64 = c->A<double>(size_t(std::max<int64_t>(1, P.total)));
       L.sz_z32 = c->A<float>(size_t(std::max<int64_t>(1, P.total)));
     }
+    {
+      // column-sum layout: 2D ids below n_bnd are the vertices and edge nodes,
+      // then nint interior nodes per triangle in triangle order; the boundary
+      // slots t*3P + s of every node below n_bnd, in ascending triangle order
+      const int P3 = 3 * L.P, npt = L.num.np_tri;
+      L.nint = (L.P - 1) * (L.P - 2) / 2;
+      L.n_bnd = int64_t(L.num.nv) + int64_t(L.num.ne) * (L.P - 1);
+      bool ok = L.n_bnd + int64_t(L.num.nt) * L.nint == L.num.n2d && 16 % L.num.L == 0 &&
+                L.num.n_dof < (int64_t(1) << 32);
+      std::vector<int32_t> ptr(size_t(L.n_bnd) + 1, 0);
+      for (int t = 0; t < L.num.nt && ok; ++t)
+        for (int a = 0; a < npt; ++a) {
+          const int code = tri_code_of(a, L.P);
+          const int64_t n = L.num.map2d[size_t(t) * npt + a];
+          if (code >= 0) {
+            if (n >= L.n_bnd) ok = false; else ptr[size_t(n) + 1]++;
+          } else if (n != L.n_bnd + int64_t(t) * L.nint + (-1 - code)) {
+            ok = false;
+          }
+        }
+      if (ok) {
+        for (size_t n = 0; n < size_t(L.n_bnd); ++n) ptr[n + 1] += ptr[n];
+        std::vector<int32_t> idx(size_t(ptr.back())), fill(ptr.begin(), ptr.end() - 1);
+        for (int t = 0; t < L.num.nt; ++t)
+          for (int a = 0; a < npt; ++a) {
+            const int code = tri_code_of(a, L.P);
+            if (code >= 0) idx[size_t(fill[size_t(L.num.map2d[size_t(t) * npt + a])]++)] = t * P3 + code;
+          }
+        L.sh_ptr = c->U(ptr);
+        L.sh_idx = c->U(idx);
+      }
+      L.colsum = ok ? 1 : 0;
+    }
     L.view = LevelView{L.P, L.PZ, L.num.L, L.num.nt, re.np_tri, re.np, re.nq, L.num.n2d, L.num.nz, N, E,
-                       L.map2d, L.inc_ptr, L.inc, L.dir2d, L.top_dir};
+                       L.map2d, L.inc_ptr, L.inc, L.dir2d, L.top_dir, L.n_bnd, L.nint, L.sh_ptr, L.sh_idx,
+                       L.colsum};
     if (i + 1 < c->nl) {
       const RefElem& rc = *c->lv[i + 1].re;
       // coarse nodal basis at the fine nodes
@@ -574,8 +612,11 @@ static void upload_levels(pmg_ctx* c) {
       L.piz32 = c->U(to_f32(Bz1.v));
     }
   }
-  // also holds the 6x6 element matrices of the P = 1 level (coarse CSR values)
+  // also holds the 6x6 element matrices of the P = 1 level (coarse CSR values) and
+  // the boundary column sums [nt][3P][nz] of the fused summation
   maxE = std::max<int64_t>(maxE, c->lv[c->nl - 1].num.n_elem * 36);
+  for (int i = 0; i < c->nl; ++i)
+    maxE = std::max<int64_t>(maxE, int64_t(c->lv[i].num.nt) * c->lv[i].num.np_tri * c->lv[i].num.nz);
   c->Y = c->A<double>(size_t(maxE));
   c->partial = c->A<double>(2 * RED_BLOCKS);
   c->scal = c->A<double>(N_SCAL);
@@ -632,13 +673,16 @@ static void ensure_native(pmg_ctx* c, Level& L, int f, hipStream_t st) {
   L.nat_stale[f] = false;
 }
 
+// Element operator of level i on x into c->Y: the element layout (for the
+// node-centric sum), or with colsum the column sums of launch_col_sum; returns
+// false, launching nothing, where the level has no column-sum kernel.
 template <typename T>
-static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
+static bool ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st, bool colsum = false) {
   Level& L = c->lv[i];
   int gs;
   const void* G = gptr<T>(c, L, gs);
-  if (i == 0 && sizeof(T) == 8) c->n_fine_applies++;
   const int f = sizeof(T) == 8 ? MF_F64 : (gs == G_BF16 ? MF_BF16 : MF_F32);
+  bool ok = false;
   if (L.mf[f]) {
     const void* vm = sizeof(T) == 8 ? (const void*)&L.vm64 : (const void*)&L.vm32;
     // column factors in the precision of the kernel's arithmetic (not for BF16 operands)
@@ -646,30 +690,30 @@ static void ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st) {
     const void* geo = !col ? nullptr : (sizeof(T) == 8 ? (const void*)L.geo64 : (const void*)L.geo32);
     if (f == MF_BF16 && c->bf16x3 && L.mfx3) {
       if (!geo) ensure_native(c, L, MF_BF16, st);
-      launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X3, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
-                     L.tab2lo, L.tab4lo, geo);
-      return;
-    }
-    if (f == MF_BF16 && c->bf16x2 && mfma_available(L.P, L.PZ, MF_BF16X2)) {
+      ok = launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X3, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
+                          L.tab2lo, L.tab4lo, geo, colsum);
+    } else if (f == MF_BF16 && c->bf16x2 && mfma_available(L.P, L.PZ, MF_BF16X2)) {
       if (!geo) ensure_native(c, L, MF_BF16, st);
-      launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X2, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
-                     nullptr, nullptr, geo);
-      return;
-    }
-    if (f == MF_BF16 && !c->bf16_ops && L.mf[MF_F32]) {
+      ok = launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X2, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
+                          nullptr, nullptr, geo, colsum);
+    } else if (f == MF_BF16 && !c->bf16_ops && L.mf[MF_F32]) {
       // FP32 arithmetic on the stored BF16 copy of G (FP32 tables); at in-plane
       // order 3 this is faster than forming G from the column factors, whose
       // kernel holds more registers
       ensure_native(c, L, MF_BF16, st);
-      launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_F32G16, L.tab2[MF_F32], L.tab4[MF_F32], vm, x, c->Y, st);
-      return;
+      ok = launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_F32G16, L.tab2[MF_F32], L.tab4[MF_F32], vm, x, c->Y, st,
+                          nullptr, nullptr, nullptr, colsum);
+    } else {
+      if (f == MF_BF16 || !geo) ensure_native(c, L, f, st);
+      ok = launch_ax_mfma(L.view, L.gnat[f], f, L.tab2[f], L.tab4[f], vm, x, c->Y, st, nullptr, nullptr,
+                          f == MF_BF16 ? nullptr : geo, colsum);
     }
-    if (f == MF_BF16 || !geo) ensure_native(c, L, f, st);
-    launch_ax_mfma(L.view, L.gnat[f], f, L.tab2[f], L.tab4[f], vm, x, c->Y, st, nullptr, nullptr,
-                   f == MF_BF16 ? nullptr : geo);
-    return;
+  } else if (!colsum) {
+    launch_ax<T>(L.view, L.mats<T>(), G, gs, x, reinterpret_cast<T*>(c->Y), st);
+    ok = true;
   }
-  launch_ax<T>(L.view, L.mats<T>(), G, gs, x, reinterpret_cast<T*>(c->Y), st);
+  if (ok && i == 0 && sizeof(T) == 8) c->n_fine_applies++;
+  return ok;
 }
 
 template <typename T>
@@ -678,11 +722,27 @@ static void assemble(pmg_ctx* c, int i, int op, T* out, const T* a1, const T* a2
   launch_assemble<T>(c->lv[i].view, op, reinterpret_cast<const T*>(c->Y), out, a1, a2, a3, w, c1, c->partial, st);
 }
 
+// out (+)= epilogue op of (A x) on level i (see AsmOp): where the level's MFMA
+// operator writes column sums (16 % L == 0), the operator and the node kernel
+// of launch_col_sum; otherwise the element layout and the node-centric sum.
+// Both add every node's contributions in a fixed order without atomics.
+template <typename T>
+static void apply_op(pmg_ctx* c, int i, const T* x, int op, T* out, const T* a1, const T* a2, T* a3, double w,
+                     double c1, hipStream_t st, T* a4 = nullptr) {
+  Level& L = c->lv[i];
+  const bool avg = op == OP_AVG_ADD || op == OP_AVG_STORE || op == OP_AVG_RAW;
+  if (c->opt.fused_sum && !avg && ax_elem<T>(c, i, x, st, true)) {
+    launch_col_sum<T>(L.view, op, reinterpret_cast<const T*>(c->Y), out, a1, a2, a3, w, c1, c->partial, st, a4);
+    return;
+  }
+  ax_elem<T>(c, i, x, st);
+  launch_assemble<T>(L.view, op, reinterpret_cast<const T*>(c->Y), out, a1, a2, a3, w, c1, c->partial, st, a4);
+}
+
 template <typename T>
 static void jacobi_sweep(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   Level& L = c->lv[i];
-  ax_elem<T>(c, i, u, st);
-  assemble<T>(c, i, OP_JACOBI, u, f, L.dinv<T>(), nullptr, L.omega, 0.0, st);
+  apply_op<T>(c, i, u, OP_JACOBI, u, f, L.dinv<T>(), nullptr, L.omega, 0.0, st);
 }
 
 // Chebyshev-accelerated Jacobi smoothing (k >= 1 steps) of the defect f - A u on
@@ -699,15 +759,12 @@ static void cheb_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess, in
     launch_cheb_start<T>(N, f, L.dinv<T>(), r, d, u, 1.0 / theta, st);  // r = f, d = D^-1 f / theta, u = d
   } else {
     // r = f - A u, d = D^-1 r / theta, u += d (one fused summation)
-    ax_elem<T>(c, i, u, st);
-    launch_assemble<T>(L.view, OP_CHEB0, reinterpret_cast<const T*>(c->Y), u, f, L.dinv<T>(), d, 0.0, 1.0 / theta,
-                       c->partial, st, r);
+    apply_op<T>(c, i, u, OP_CHEB0, u, f, L.dinv<T>(), d, 0.0, 1.0 / theta, st, r);
   }
   double rho = 1.0 / sigma;
   for (int j = 1; j < k; ++j) {
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    ax_elem<T>(c, i, d, st);
-    assemble<T>(c, i, OP_CHEB, u, r, L.dinv<T>(), d, rho_new * rho, 2.0 * rho_new / delta, st);
+    apply_op<T>(c, i, d, OP_CHEB, u, r, L.dinv<T>(), d, rho_new * rho, 2.0 * rho_new / delta, st);
     rho = rho_new;
   }
 }
@@ -733,8 +790,7 @@ static void schwarz_smooth(pmg_ctx* c, int i, const T* f, T* u, bool zero_guess,
     const bool first = zero_guess && s == 0;
     const T* x = f;
     if (!first) {
-      ax_elem<T>(c, i, u, st);
-      assemble<T>(c, i, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
+      apply_op<T>(c, i, u, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
       x = r;
     }
     if (sizeof(T) == 8)
@@ -1405,8 +1461,7 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
     launch_fill<T>(u, T(0), N, st);
   }
   T* r = L.r<T>();
-  ax_elem<T>(c, i, u, st);
-  assemble<T>(c, i, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
+  apply_op<T>(c, i, u, OP_RESID, r, f, nullptr, nullptr, 0, 0, st);
   launch_restrict_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), r, reinterpret_cast<T*>(c->Y), st);
   assemble<T>(c, i + 1, OP_STORE, C.f<T>(), nullptr, nullptr, nullptr, 0, 0, st);
   vcycle<T>(c, i + 1, C.f<T>(), C.u<T>(), st);
@@ -1437,11 +1492,10 @@ static void precond(pmg_ctx* c, const double* r, double* z, hipStream_t st) {
 
 // y = A_FF x (FP64, finest), partial of p.y when dot_with != nullptr
 static void fine_apply(pmg_ctx* c, const double* x, double* y, const double* dot_with, hipStream_t st) {
-  ax_elem<double>(c, 0, x, st);
   if (dot_with)
-    assemble<double>(c, 0, OP_STORE_DOT, y, dot_with, nullptr, nullptr, 0, 0, st);
+    apply_op<double>(c, 0, x, OP_STORE_DOT, y, dot_with, nullptr, nullptr, 0, 0, st);
   else
-    assemble<double>(c, 0, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+    apply_op<double>(c, 0, x, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -1632,10 +1686,8 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
       // both norms read with one synchronisation); the chosen residual seeds the loop
       learned_guess(c, net, surf, hist[0], hist[1], p3, c->s_q, st);
       launch_mask<double>(F.view, c->s_q, c->s_q, st);
-      ax_elem<double>(c, 0, c->s_u, st);
-      assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
-      ax_elem<double>(c, 0, c->s_q, st);
-      assemble<double>(c, 0, OP_RESID, c->s_y, c->s_r, nullptr, nullptr, 0, 0, st);
+      apply_op<double>(c, 0, c->s_u, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+      apply_op<double>(c, 0, c->s_q, OP_RESID, c->s_y, c->s_r, nullptr, nullptr, 0, 0, st);
       launch_dot<double>(c->s_r, c->s_r, N, c->partial, st);
       launch_finalize(c->partial, c->scal, S_TMP0, FIN_SET, st);
       launch_dot<double>(c->s_y, c->s_y, N, c->partial, st);
@@ -1659,8 +1711,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
   HIPCHK(hipEventElapsedTime(&tg, ev0, ev1));
   // r = f - A u (already at hand for the learned guess)
   if (rr0 < 0.0) {
-    ax_elem<double>(c, 0, c->s_u, st);
-    assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+    apply_op<double>(c, 0, c->s_u, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
     rr0 = dot_host(c, c->s_r, c->s_r, N, st);
   }
   std::vector<double> hist_r{std::sqrt(rr0)};
@@ -1715,8 +1766,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     while (it < imax && hist_r.back() > tol) {
       precond(c, c->s_r, c->s_z, st);
       launch_axpy(c->s_u, c->s_z, 1.0, N, st);
-      ax_elem<double>(c, 0, c->s_u, st);
-      assemble<double>(c, 0, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
+      apply_op<double>(c, 0, c->s_u, OP_RESID, c->s_r, c->s_f, nullptr, nullptr, 0, 0, st);
       const double rr = dot_host(c, c->s_r, c->s_r, N, st);
       if (!std::isfinite(rr)) { status = PMG_ENONFINITE; break; }
       hist_r.push_back(std::sqrt(rr));
@@ -1727,8 +1777,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
   }
   // phi = phi_D + u; true relative residual in FP64
   launch_merge_free(F.view, c->s_u, c->s_phiD, phi, st);
-  ax_elem<double>(c, 0, c->s_u, st);
-  assemble<double>(c, 0, OP_RESID, c->s_y, c->s_f, nullptr, nullptr, 0, 0, st);
+  apply_op<double>(c, 0, c->s_u, OP_RESID, c->s_y, c->s_f, nullptr, nullptr, 0, 0, st);
   const double rtrue = std::sqrt(dot_host(c, c->s_y, c->s_y, N, st));
   HIPCHK(hipEventRecord(ev1, st));
   HIPCHK(hipEventSynchronize(ev1));
@@ -1875,6 +1924,7 @@ void pmg_options_default(pmg_options* o) {
   o->seed = 0;
   o->geometry = PMG_GEOM_COLUMN;
   o->PZ = 0;
+  o->fused_sum = 1;
 }
 
 int pmg_abi_version(void) { return PMG_ABI_VERSION; }
@@ -2038,15 +2088,15 @@ int pmg_apply(pmg_ctx* c, int level, int precision, int flags, const void* x, vo
     if (precision == PMG_FP64) {
       const double* xin = (const double*)x;
       if (flags & 1) { launch_mask<double>(L.view, xin, L.r64, st); xin = L.r64; }
-      ax_elem<double>(c, level, xin, st);
-      assemble<double>(c, level, (flags & 1) ? OP_STORE : OP_RAW, (double*)y, nullptr, nullptr, nullptr, 0, 0, st);
+      apply_op<double>(c, level, xin, (flags & 1) ? OP_STORE : OP_RAW, (double*)y, nullptr, nullptr, nullptr, 0, 0,
+                       st);
     } else if (precision == PMG_MIXED_FP32 || precision == PMG_MIXED_BF16 || precision == PMG_MIXED_BF16G ||
                precision == PMG_MIXED_BF16X3 || precision == PMG_MIXED_BF16X2) {
       set_lowp(c, precision);
       const float* xin = (const float*)x;
       if (flags & 1) { launch_mask<float>(L.view, xin, L.r32, st); xin = L.r32; }
-      ax_elem<float>(c, level, xin, st);
-      assemble<float>(c, level, (flags & 1) ? OP_STORE : OP_RAW, (float*)y, nullptr, nullptr, nullptr, 0, 0, st);
+      apply_op<float>(c, level, xin, (flags & 1) ? OP_STORE : OP_RAW, (float*)y, nullptr, nullptr, nullptr, 0, 0,
+                      st);
     } else {
       throw Error(PMG_EINVAL, "bad precision");
     }
@@ -2448,6 +2498,23 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
           break;
         }
         case PMG_K_COPY: launch_copy<double>(L.r64, c->s_y, L.num.n_dof, st); break;
+        case PMG_K_COLSUM_OP: {
+          const bool ok = f64 ? ax_elem<double>(c, level, L.r64, st, true) : ax_elem<float>(c, level, L.r32, st, true);
+          if (!ok) throw Error(PMG_EINVAL, "no column-sum element operator on this level");
+          break;
+        }
+        case PMG_K_COL_SUM_STORE: case PMG_K_COL_SUM_CHEB: {
+          // x = s_y / s_z32, r = r, d = the level's direction vector (column sums read from c->Y)
+          if (!L.colsum) throw Error(PMG_EINVAL, "no column-sum layout on this level");
+          const int op = kernel == PMG_K_COL_SUM_STORE ? OP_STORE : OP_CHEB;
+          if (f64)
+            launch_col_sum<double>(L.view, op, c->Y, c->s_y, L.r64, L.dinv64, L.d64 ? L.d64 : c->s_q, 0.5, 0.1,
+                                   c->partial, st);
+          else
+            launch_col_sum<float>(L.view, op, reinterpret_cast<const float*>(c->Y), c->s_z32, L.r32, L.dinv32,
+                                  L.d32 ? L.d32 : L.r32, 0.5, 0.1, c->partial, st);
+          break;
+        }
         case PMG_K_SCHWARZ:
           if (f64) launch_sd_apply<double, double>(L.szv, L.sz_inv64, L.r64, nullptr, L.sz_z64, st);
           else if (c->lowp == G_BF16) launch_sd_apply<float, bf16_t>(L.szv, L.sz_inv16, L.r32, nullptr, L.sz_z32, st);

@@ -53,7 +53,8 @@ class Options(C.Structure):
                 ("exact_max", C.c_int32), ("seed", C.c_uint64), ("host_only", C.c_int32),
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
                 ("coarsening", C.c_int32), ("overlap", C.c_int32), ("schwarz_store", C.c_int32),
-                ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32), ("PZ", C.c_int32)]
+                ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32), ("PZ", C.c_int32),
+                ("fused_sum", C.c_int32)]
 
 
 class FnpfStats(C.Structure):
@@ -144,7 +145,8 @@ SIGNATURES = {
     "pmg_net_save": (_I, [_VP, C.c_char_p]),
     "pmg_net_load": (_I, [_VP, C.c_char_p]),
 }
-KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4, "copy": 5, "schwarz": 6}
+KERNELS = {"element_op": 0, "assemble": 1, "geometry": 2, "restrict": 3, "prolong": 4, "copy": 5, "schwarz": 6,
+           "colsum_op": 7, "col_sum_store": 8, "col_sum_cheb": 9}
 SMOOTHERS = {"jacobi": 0, "chebyshev": 1, "schwarz": 2}
 
 

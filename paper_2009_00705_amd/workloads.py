@@ -269,8 +269,21 @@ def config_mesh(name: str) -> dict:
     if name == "c3":
         return box_mesh(128, 4)
     if name in ("c4", "c5"):
-        return cylinder_mesh()
+        return frozen_cylinder_mesh()
     raise KeyError(name)
+
+
+def frozen_cylinder_mesh() -> dict:
+    """The default cylinder_mesh() as written to fixtures/cyl_mesh.npz by
+    fixtures/make_cyl_mesh.py (plain arrays, no pickles), so that the
+    unstructured workloads keep one numbering whatever Delaunay implementation
+    the running machine has."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "fixtures", "cyl_mesh.npz")
+    with np.load(path, allow_pickle=False) as f:
+        return dict(xy=f["xy"].astype(np.float64), tri=f["tri"].astype(np.int32),
+                    edge_tag=f["edge_tag"].astype(np.int32), curved_edge=f["curved_edge"].astype(np.int32),
+                    circle=f["circle"].astype(np.float64), n_layers=int(f["n_layers"]), depth=float(f["depth"]))
 
 
 def random_vector(n: int, seed: int, dtype=np.float64) -> np.ndarray:

@@ -25,6 +25,10 @@ CASES = {
     "box5x5_L3_P6": (lambda: W.box_mesh(5, 3), 6),        # several blocks + ragged tail
     "cyl_P3": (lambda: W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=3), 3),
     "box2_L1_P8": (lambda: W.box_mesh(2, 1), 8),
+    # four layers: batches of 16 prisms hold whole columns, so the MFMA levels
+    # sum their columns inside the element operator (pmg_options.fused_sum)
+    "box5x5_L4_P6": (lambda: W.box_mesh(5, 4), 6),
+    "cyl_L4_P3": (lambda: W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=4), 3),
 }
 # in-plane-first hierarchies (anisotropic orders, e.g. (6,6) (3,6) (1,6) (1,3) (1,1))
 XY_CASES = {k + "_xy": v for k, v in CASES.items() if k != "c1"}
@@ -400,3 +404,82 @@ def test_stored_geometry_solves_match_column_solves(prec):
     if prec == "fp64":
         np.testing.assert_allclose(sc["res_hist"], ss["res_hist"], rtol=1e-9, atol=1e-10 * ss["res_hist"][0])
     assert rel_err(pc, ps) < (1e-10 if prec == "fp64" else 1e-8)
+
+
+@pytest.fixture(scope="module", params=["box5x5_L4_P6", "box5x5_L4_P6_xy", "cyl_L4_P3_xy", "c1"])
+def fused_pair(request):
+    """The same hierarchy with the direct-stiffness sum inside the element
+    operators (default) and through the element-layout buffer and node-centric
+    sum kernel (fused_sum = 0)."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    from gpu_common import surface_eta
+    mk, P = ALL[request.param]
+    mesh = mk()
+    ctxs = []
+    for fused in (1, 0):
+        c = pmg.Context(mesh, P=P, fused_sum=fused, omega=[0.3] * 8, **_opts(request.param))
+        c.set_surface(dev(surface_eta(c.surface_xy(), "wavy")))
+        ctxs.append(c)
+    torch.cuda.synchronize()
+    yield request.param, ctxs[0], ctxs[1]
+    for c in ctxs:
+        c.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "bf16g", "bf16x3"])
+def test_fused_sum_equals_node_sum(fused_pair, prec):
+    """y = A x on every level: the fused summation and the node-centric one add
+    the same contributions in different orders (FP64 1e-13, FP32 2e-6 of the
+    output's max), both masked and bitwise reproducible."""
+    import torch
+    name, cf, cu = fused_pair
+    dt = torch.float64 if prec == "fp64" else torch.float32
+    for lvl, info in enumerate(cf.levels):
+        n = info["n_dof"]
+        x = dev(_rand(n, 90 + lvl), dt)
+        yf = torch.empty(n, dtype=dt, device="cuda")
+        yf2 = torch.empty_like(yf)
+        yu = torch.empty_like(yf)
+        cf.apply(lvl, x, yf, prec, masked=True)
+        cf.apply(lvl, x, yf2, prec, masked=True)
+        cu.apply(lvl, x, yu, prec, masked=True)
+        assert torch.equal(yf, yf2), (name, lvl, prec)
+        assert rel_err(host(yf), host(yu)) < (1e-13 if prec == "fp64" else 2e-6), (name, lvl, prec)
+
+
+def test_fused_sum_smoother_vcycle_and_solve(fused_pair):
+    """Chebyshev smoothing, V-cycle and PCG solve with the fused summation match
+    the node-centric summation (the FP64 Chebyshev steps, residual and the
+    outer iteration's q = A p with its dot product all take the fused path)."""
+    import torch
+    name, cf, cu = fused_pair
+    lv0 = cf.levels[0]
+    n = lv0["n_dof"]
+    nz = n // lv0["n_surface"]
+    top = np.arange(n) % nz == nz - 1
+    mask = ~top
+    f = np.where(mask, _rand(n, 61), 0.0)
+    outs = []
+    for c in (cf, cu):
+        c.set_solver("fp64", "pcg")
+        u = torch.zeros(n, dtype=torch.float64, device="cuda")
+        c.smooth(0, dev(f), u, sweeps=3)
+        z = torch.empty(n, dtype=torch.float64, device="cuda")
+        c.vcycle(dev(f), z)
+        outs.append((host(u), host(z)))
+    assert rel_err(outs[0][0], outs[1][0]) < 1e-12 and rel_err(outs[0][1], outs[1][1]) < 1e-11, name
+    xyz = cf.node_xyz(0)
+    surf = dev(np.ascontiguousarray(W.linear_wave(xyz[:, 0], xyz[:, 1], xyz[:, 2], 1.0)[top]))
+    sols = []
+    for c in (cf, cu):
+        for prec in ("fp64", "bf16x3"):
+            c.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
+            phi = torch.zeros(n, dtype=torch.float64, device="cuda")
+            rc, st = c.solve(phi, phi_surf=surf, rtol=1e-10, imax=300)
+            assert rc == 0 and st["rel_res"] <= 1e-10, (name, prec, rc, st["rel_res"])
+            sols.append((prec, st["iters"], host(phi)))
+    for k in range(2):
+        (_, it_f, pf), (_, it_u, pu) = sols[k], sols[k + 2]
+        assert abs(it_f - it_u) <= 1, (name, sols[k][0], it_f, it_u)
+        assert rel_err(pf, pu) < 1e-9, (name, sols[k][0])

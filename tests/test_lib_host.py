@@ -205,3 +205,30 @@ def test_create_rejects_bad_input():
     with pytest.raises(pmg.PmgError) as e:   # device call on a host-only context
         ctx._c(pmg.lib().pmg_set_surface(ctx.h, ctypes.c_void_p(1), None))
     assert e.value.code == -7
+
+
+def test_frozen_cylinder_mesh():
+    """The unstructured workloads read the cylinder mesh from the committed
+    fixture: 12015 counter-clockwise triangles in [-4, 4]^2, none inside the
+    cylinder of radius 0.5, curved edges with both ends on that circle, and
+    every boundary edge tagged; the library numbers it like the oracle."""
+    m = W.config_mesh("c4")
+    xy, tri = m["xy"], m["tri"]
+    assert tri.shape == (12015, 3) and m["n_layers"] == 4 and m["depth"] == 1.0
+    p0, p1, p2 = xy[tri[:, 0]], xy[tri[:, 1]], xy[tri[:, 2]]
+    area2 = (p1[:, 0] - p0[:, 0]) * (p2[:, 1] - p0[:, 1]) - (p1[:, 1] - p0[:, 1]) * (p2[:, 0] - p0[:, 0])
+    assert area2.min() > 0
+    cen = (p0 + p1 + p2) / 3
+    assert np.hypot(cen[:, 0], cen[:, 1]).min() > 0.5 and np.abs(xy).max() <= 4.0 + 1e-12
+    ends = xy[m["curved_edge"].ravel()]
+    assert len(ends) > 0 and np.abs(np.hypot(ends[:, 0], ends[:, 1]) - 0.5).max() < 1e-12
+    # boundary edges (held by one triangle) carry a tag, interior edges none
+    from collections import Counter
+    cnt = Counter(tuple(sorted((int(t[i]), int(t[(i + 1) % 3])))) for t in tri for i in range(3))
+    for t, tags in zip(tri, m["edge_tag"]):
+        for i in range(3):
+            e = tuple(sorted((int(t[i]), int(t[(i + 1) % 3]))))
+            assert (tags[i] != 0) == (cnt[e] == 1)
+    ctx = _host_ctx(m, 1)
+    np.testing.assert_array_equal(ctx.gather_map(0), M.Numbering(m, 1).map.astype(np.int32))
+    ctx.close()
