@@ -31,6 +31,13 @@ DTYPES = {"fp64": "f64", "fp32": "f64+f32", "bf16": "f64+bf16", "bf16g": "f64+f3
 METRIC = "Laplace solves/s and DOF/s to 1e-8 rel residual at P=6 (mixed/learned vs FP64)"
 
 
+def smoother_kw(a):
+    """Smoother options shared by every workload of one run: the Chebyshev
+    interval [lambda/ratio, lambda] and the summation mode."""
+    kw = {"smooth_ratio": a.smooth_ratio, "fused_sum": 1 if a.fused_sum else 0}
+    return kw
+
+
 def workload(name):
     from paper_2009_00705_amd import workloads as W
     if name == "c3":
@@ -91,7 +98,7 @@ def op_bytes(info0, nt, np_tri, prec, P):
     return geo + info0["n_dof"] * s_v + info0["n_elem"] * info0["np"] * s_v + nt * np_tri * 4
 
 
-def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening):
+def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening, smooth_ratio=8.0):
     """One oracle FP64 PCG solve (rtol 1e-8) of an n_side x n_side x n_layers slice
     of the box workload: (set-up s, solve s, iterations, prisms, nodes)."""
     import oracle.mesh as OM
@@ -102,7 +109,8 @@ def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening):
     num = OM.Numbering(m, P)
     xy = OM.unique_xy_2d(m, num)
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
-    h = mg.Hierarchy(m, P, eta, nu1=nu, nu2=nu, smoother=smoother, coarse="exact", coarsening=coarsening)
+    h = mg.Hierarchy(m, P, eta, nu1=nu, nu2=nu, smoother=smoother, coarse="exact", coarsening=coarsening,
+                     smooth_ratio=smooth_ratio)
     t_setup = time.perf_counter() - t0
     xyz = OM.node_xyz(m, num, eta)
     phi_dir = W.mode_sum(xyz[:, 0], xyz[:, 1], xyz[:, 2], W.mode_amplitudes(3), W.mode_pairs())
@@ -131,7 +139,8 @@ def cheb_bytes(info0, nt, np_tri, prec, P):
     return apply_bytes(info0, nt, np_tri, prec, P) - 2 * info0["n_dof"] * s_v + 7 * info0["n_dof"] * s_v
 
 
-def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both"):
+def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both",
+                 smooth_ratio=8.0):
     """The oracle's complete FP64 PCG solve on slices of the workload, scaled to the full mesh.
 
     The slices are the same split-quad box, order, layer count, surface
@@ -152,8 +161,9 @@ def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16
     for label, nthreads in (("all", cores), ("one", 1)):
         lim = threadpool_limits(limits=nthreads) if threadpool_limits else None
         try:
-            small = _oracle_slice_solve(P, nu, smoother, n_side // 2, n_layers, coarsening) if label == "all" else None
-            big = _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening)
+            small = (_oracle_slice_solve(P, nu, smoother, n_side // 2, n_layers, coarsening, smooth_ratio)
+                     if label == "all" else None)
+            big = _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening, smooth_ratio)
         finally:
             if lim is not None:
                 lim.unregister()
@@ -215,7 +225,8 @@ def bench_erk4(a):
     coarse = "exact" if probe.levels[-1]["n_free"] <= 12000 else "chebyshev"
     probe.close()
     nu = a.nu if a.nu > 0 else 3
-    ctx = pmg.Context(mesh, P=a.P, coarse=coarse, smoother="chebyshev", nu1=nu, nu2=nu, coarsening=a.coarsening)
+    ctx = pmg.Context(mesh, P=a.P, coarse=coarse, smoother="chebyshev", nu1=nu, nu2=nu, coarsening=a.coarsening,
+                      **smoother_kw(a))
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     g, h = 9.81, 1.0
@@ -271,7 +282,8 @@ def c2_fp64_row(a, log, steps=10, warmup=2):
     from paper_2009_00705_amd import pmg
     from paper_2009_00705_amd import workloads as W
     mesh = W.config_mesh("c2")
-    ctx = pmg.Context(mesh, P=6, coarse="exact", smoother="chebyshev", nu1=3, nu2=3, coarsening="both")
+    ctx = pmg.Context(mesh, P=6, coarse="exact", smoother="chebyshev", nu1=3, nu2=3, coarsening="both",
+                      **smoother_kw(a))
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
@@ -327,7 +339,8 @@ def learned_leg(a, log, train_steps=1500):
     from paper_2009_00705_amd import workloads as W
     from paper_2009_00705_amd.history import History, summarize
     mesh = W.config_mesh("c5")
-    ctx = pmg.Context(mesh, P=6, coarse="chebyshev", smoother="chebyshev", nu1=3, nu2=3, coarsening="xy")
+    ctx = pmg.Context(mesh, P=6, coarse="chebyshev", smoother="chebyshev", nu1=3, nu2=3, coarsening="xy",
+                      **smoother_kw(a))
     H = History(ctx, W.WaveGroup(n_steps=300))
     H.set_step(0)
     om, lo, hi = ctx.params()
@@ -392,7 +405,7 @@ def bench_history(a):
     mesh = W.config_mesh("c5")
     nu = a.nu if a.nu > 0 else 3
     ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu,
-                      coarsening=a.coarsening)
+                      coarsening=a.coarsening, **smoother_kw(a))
     wave = W.WaveGroup(n_steps=300)
     H = History(ctx, wave)
     H.set_step(0)
@@ -463,7 +476,7 @@ def bench_scaling(a):
     for nq, L in ((4, 1), (8, 2), (16, 4), (32, 8)):
         mesh = W.box_mesh(nq, L)
         ctx = pmg.Context(mesh, P=a.P, coarse="exact", smoother=a.smoother, nu1=nu, nu2=nu,
-                          coarsening=a.coarsening)
+                          coarsening=a.coarsening, **smoother_kw(a))
         xy = ctx.surface_xy()
         eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
         ctx.set_surface(torch.from_numpy(eta).cuda())
@@ -511,7 +524,7 @@ def bench_cylinder(a):
     mesh = W.config_mesh("c4")
     paths = {}
     ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu,
-                      coarsening=a.coarsening)
+                      coarsening=a.coarsening, **smoother_kw(a))
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
     ctx.set_surface(torch.zeros(xy.shape[0], dtype=torch.float64, device="cuda"))
@@ -539,7 +552,7 @@ def bench_cylinder(a):
     ctx.close()
     # (ii) uniform flow: Dirichlet surface and the four walls, no-flux cylinder and bottom
     ctx = pmg.Context(mesh, P=a.P, coarse="chebyshev", smoother=a.smoother, nu1=nu, nu2=nu, dirichlet_tags=0b11110,
-                      coarsening=a.coarsening)
+                      coarsening=a.coarsening, **smoother_kw(a))
     ctx.set_surface(torch.zeros(xy.shape[0], dtype=torch.float64, device="cuda"))
     exact = W.uniform_flow_cylinder(xyz[:, 0], xyz[:, 1])
     phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
@@ -581,7 +594,10 @@ def main():
                     help="operator reuse across surfaces (erk4 workload): strategy III, I or II")
     ap.add_argument("--coarsening", default="xy", choices=["xy", "both"],
                     help="level orders: in-plane first (xy) or all directions at once (both)")
-    ap.add_argument("--smooth-ratio", type=float, default=15.0,
+    ap.add_argument("--fused-sum", action="store_true",
+                    help="column sums from the element operators and the node kernel over them, instead of the "
+                         "element layout and the node-centric summation")
+    ap.add_argument("--smooth-ratio", type=float, default=8.0,
                     help="Chebyshev smoother interval [lambda/ratio, lambda]")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg (c5 history)")
@@ -620,7 +636,7 @@ def main():
                               "bf16x2": "bf16"}[p]
                              for p in a.precisions.split(",") if p}))
     ctx = pmg.Context(mesh, P=a.P, coarse=coarse, cheb_degree=a.coarse_degree, smoother=a.smoother,
-                      nu1=nu, nu2=nu, smooth_ratio=a.smooth_ratio, coarsening=a.coarsening, overlap=a.overlap,
+                      nu1=nu, nu2=nu, coarsening=a.coarsening, overlap=a.overlap, **smoother_kw(a),
                       schwarz_store=store, **({"omega": [a.omega] * 8} if a.omega > 0 else {}))
     info0 = ctx.levels[0]
     xy = ctx.surface_xy()
@@ -645,14 +661,15 @@ def main():
         for prec in [p for p in a.precisions.split(",") if p]:
             flops = op_flops_per_elem(a.P) * info0["n_elem"]
             byts = apply_bytes(info0, nt, npt, prec, a.P)
+            t_e = ctx.time_kernel("element_op", 0, prec, reps=a.steps)
+            t_a = ctx.time_kernel("assemble", 0, prec, reps=a.steps)
             t_f = ctx.time_kernel("colsum_op", 0, prec, reps=a.steps)
             t_s = ctx.time_kernel("col_sum_store", 0, prec, reps=a.steps)
-            ms = ctx.time_kernel("element_op", 0, prec, reps=a.steps)
-            res[prec] = {"ms_element_kernel": t_f, "ms_node_kernel": t_s, "bytes_per_apply": byts,
-                         "GB_per_s": byts / ((t_f + t_s) * 1e-3) / 1e9, "flops_per_apply": flops,
-                         "roofline": roofline(byts, flops, t_f + t_s, prec),
-                         "unfused_element_op_ms": ms,
-                         "unfused_element_op_bytes": op_bytes(info0, nt, npt, prec, a.P)}
+            res[prec] = {"ms_element_op": t_e, "ms_node_sum": t_a, "bytes_per_apply": byts,
+                         "GB_per_s": byts / ((t_e + t_a) * 1e-3) / 1e9, "flops_per_apply": flops,
+                         "roofline": roofline(byts, flops, t_e + t_a, prec),
+                         "column_sum_form": {"ms_element_kernel": t_f, "ms_node_kernel": t_s,
+                                             "roofline": roofline(byts, flops, t_f + t_s, prec)}}
         print(json.dumps(res), flush=True)
         return
 
@@ -689,40 +706,34 @@ def main():
     nt = mesh["tri"].shape[0]
     npt = (a.P + 1) * (a.P + 2) // 2
     flops = op_flops_per_elem(a.P) * info0["n_elem"]
-    fused = True
-    try:
-        t_f = ctx.time_kernel("colsum_op", 0, kprec, reps=20)
-        t_s = ctx.time_kernel("col_sum_store", 0, kprec, reps=20)
-        t_f64 = ctx.time_kernel("colsum_op", 0, "fp64", reps=20) + ctx.time_kernel("col_sum_store", 0, "fp64", reps=20)
-        t_cf = t_f
-        t_cs = ctx.time_kernel("col_sum_cheb", 0, kprec, reps=20)
-    except Exception:
-        fused = False
-    t_e = ctx.time_kernel("element_op", 0, kprec, reps=20)       # element-layout output (unfused path)
-    t_asm = ctx.time_kernel("assemble", 0, kprec, reps=20)        # its node-centric summation
+    # the apply as the solve runs it: element operator + summation (element layout
+    # and node-centric sum by default; column sums and their node kernel with
+    # --fused-sum), and the other form for comparison
+    t_e = ctx.time_kernel("element_op", 0, kprec, reps=20)
+    t_asm = ctx.time_kernel("assemble", 0, kprec, reps=20)
     t_e64 = ctx.time_kernel("element_op", 0, "fp64", reps=20)
+    t_asm64 = ctx.time_kernel("assemble", 0, "fp64", reps=20)
+    try:
+        t_c = ctx.time_kernel("colsum_op", 0, kprec, reps=20)
+        t_cs = ctx.time_kernel("col_sum_store", 0, kprec, reps=20)
+        t_cc = ctx.time_kernel("col_sum_cheb", 0, kprec, reps=20)
+        colsum = {"ms_element_kernel": t_c, "ms_node_kernel_store": t_cs, "ms_node_kernel_cheb": t_cc}
+    except Exception:
+        colsum = None
     byts = apply_bytes(info0, nt, npt, kprec, a.P)
     byts64 = apply_bytes(info0, nt, npt, "fp64", a.P)
-    if fused:
-        ms_k, ms_k64 = t_f + t_s, t_f64
-        roof = roofline(byts, flops, ms_k, kprec)
-        roof.update({"traffic": None,
-                     "kernel": f"fine operator apply y = A x (P={a.P}), {kprec} path: element operator writing "
-                               "column sums + node sum",
-                     "ms_per_launch": ms_k, "ms_element_kernel": t_f, "ms_node_kernel": t_s,
-                     "bytes_per_launch": byts, "flops_per_launch": flops,
-                     "fp64_apply": dict(roofline(byts64, flops, ms_k64, "fp64"), ms_per_launch=ms_k64),
-                     "chebyshev_step": {"ms_element_kernel": t_cf, "ms_node_kernel": t_cs,
-                                        "bytes": cheb_bytes(info0, nt, npt, kprec, a.P),
-                                        "GB_per_s": cheb_bytes(info0, nt, npt, kprec, a.P) / ((t_cf + t_cs) * 1e-3)
-                                        / 1e9},
-                     "unfused": {"ms_element_op": t_e, "ms_node_sum": t_asm, "ms_element_op_fp64": t_e64}})
+    if a.fused_sum and colsum:
+        ms_k, parts = t_c + t_cs, {"ms_element_kernel": t_c, "ms_node_kernel": t_cs}
+        how = "element operator writing column sums + node kernel"
     else:
-        roof = roofline(byts, flops, t_e + t_asm, kprec)
-        roof.update({"traffic": None, "kernel": f"fine operator apply (P={a.P}), {kprec} path: element operator "
-                                                "+ node-centric sum", "ms_per_launch": t_e + t_asm,
-                     "bytes_per_launch": byts, "flops_per_launch": flops,
-                     "unfused": {"ms_element_op": t_e, "ms_node_sum": t_asm, "ms_element_op_fp64": t_e64}})
+        ms_k, parts = t_e + t_asm, {"ms_element_kernel": t_e, "ms_node_kernel": t_asm}
+        how = "element operator (element layout) + node-centric sum"
+    roof = roofline(byts, flops, ms_k, kprec)
+    roof.update({"traffic": None, "kernel": f"fine operator apply y = A x (P={a.P}), {kprec} path: {how}",
+                 "ms_per_launch": ms_k, **parts, "bytes_per_launch": byts, "flops_per_launch": flops,
+                 "fp64_apply": dict(roofline(byts64, flops, t_e64 + t_asm64, "fp64"), ms_per_launch=t_e64 + t_asm64),
+                 "element_kernel_alone": dict(roofline(byts, flops, t_e, kprec), ms_per_launch=t_e),
+                 "column_sum_form": colsum})
     if a.smoother == "schwarz":
         # the dominant kernel is then the batched local solve of the finest level
         roof_op = roof
@@ -762,7 +773,7 @@ def main():
     if not a.no_cpu:
         p64 = paths.get("fp64", res)
         out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"],
-                                           coarsening=a.coarsening)
+                                           coarsening=a.coarsening, smooth_ratio=a.smooth_ratio)
     print(json.dumps(out), flush=True)
 
 

@@ -121,7 +121,8 @@ typedef struct pmg_mesh {
   int32_t ncurved;
   const int32_t* curved_edge;/* [ncurved][2] vertex pairs on a circle (nullable) */
   const double* circle;      /* [ncurved][3] cx, cy, R (nullable)               */
-  int32_t n_layers;          /* >= 1; nt * n_layers < 2^31 prisms (PMG_EINVAL otherwise) */
+  int32_t n_layers;          /* >= 1; nt * n_layers < 2^31 prisms and fewer than 2^32 nodes on
+                                the finest level (PMG_EINVAL otherwise) */
   double depth;
 } pmg_mesh;
 
@@ -174,18 +175,19 @@ typedef struct pmg_options {
                              isotropic P; with PZ != P the EQUAL sequences of
                              (4,2), (5,3), (6,4), (2,4), (3,6), (4,8) and the
                              XY_FIRST sequences of (3,6), (2,4), (4,8)           */
-  int32_t fused_sum;      /* 1 (default): where the MFMA element operator can
-                             (layer counts dividing 16, orders up to 16 (node,
-                             prism) pairs per thread, column-factor geometry
-                             for FP64/FP32), it sums each triangle column's
-                             layers itself and writes one value per
-                             (triangle, node, z); a node kernel then adds the
-                             triangles sharing each vertex or edge node and
-                             applies the step's epilogue (the direct-stiffness
-                             sum of Sec. 3.1).  0: element results through the
-                             element layout and the node-centric sum kernel.
-                             Both use no atomics and a fixed order (bitwise
-                             reproducible); they differ by rounding           */
+  int32_t fused_sum;      /* 1: where the MFMA element operator can (layer
+                             counts dividing 16, orders up to 16 (node, prism)
+                             pairs per thread, column-factor geometry for
+                             FP64/FP32), it sums each triangle column's layers
+                             itself and writes one value per (triangle, node,
+                             z); a node kernel then adds the triangles sharing
+                             each vertex or edge node and applies the step's
+                             epilogue (the direct-stiffness sum of Sec. 3.1).
+                             0 (default, as fast on the benchmark meshes):
+                             element results through the element layout and
+                             the node-centric sum kernel.  Both use no atomics
+                             and a fixed order (bitwise reproducible); they
+                             differ by rounding                               */
 } pmg_options;
 
 /* Geometric factors read by the MFMA element operators.  STORED: the six

@@ -1,9 +1,10 @@
 // Node epilogues of the direct-stiffness sum (Sec. 3.1: the global operator is
 // the sum over elements of the element contributions at each global node).
-// One definition serves the node-centric summation kernel (k_assemble), the
-// element operators that sum their own columns (vertical_fused) and the kernel
-// that finishes the nodes several triangle columns share (k_shared_sum), so all
-// three apply the same arithmetic to a node's sum s.
+// One definition serves the node-centric summation kernel (k_assemble) and the
+// node kernel of the column-sum layout (k_col_sum), so both apply the same
+// arithmetic to a node's sum s.  The vectors an epilogue reads are loaded by
+// node_in before the node's gather starts (their reads are then in flight
+// together with it); node_epilogue computes and stores.
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -21,37 +22,49 @@ namespace pmg {
 //   OP_STORE_DOT out = mask s; acc += a1 out
 //   OP_CHEB0     a4 = r = mask (a1 - s); a3 = d = c1 a2 r; out += d
 //   OP_CHEB      r = a1 (in/out): r -= s; d = a3 = omega d + c1 a2 r; out += d
+template <typename T> struct NodeIn {
+  T a1, a2, a3, o;
+};
 template <typename T, int OP>
-__device__ __forceinline__ void node_epilogue(int64_t g, bool dir, T s, T* __restrict__ out,
-                                              const T* __restrict__ a1, const T* __restrict__ a2,
-                                              T* __restrict__ a3, T* __restrict__ a4, T omega, T c1,
-                                              double& acc) {
+__device__ __forceinline__ NodeIn<T> node_in(uint64_t g, const T* __restrict__ out, const T* __restrict__ a1,
+                                             const T* __restrict__ a2, const T* __restrict__ a3) {
+  NodeIn<T> v{T(0), T(0), T(0), T(0)};
+  if constexpr (OP == OP_RESID || OP == OP_STORE_DOT || OP == OP_JACOBI || OP == OP_CHEB0 || OP == OP_CHEB)
+    v.a1 = a1[g];
+  if constexpr (OP == OP_JACOBI || OP == OP_CHEB0 || OP == OP_CHEB) v.a2 = a2[g];
+  if constexpr (OP == OP_JACOBI || OP == OP_CHEB0 || OP == OP_CHEB || OP == OP_AVG_ADD) v.o = out[g];
+  if constexpr (OP == OP_CHEB) v.a3 = a3[g];
+  return v;
+}
+template <typename T, int OP>
+__device__ __forceinline__ void node_epilogue(uint64_t g, bool dir, T s, const NodeIn<T>& in, T* __restrict__ out,
+                                              T* __restrict__ r, T* __restrict__ a3, T* __restrict__ a4, T omega,
+                                              T c1, double& acc) {
   if constexpr (OP == OP_RAW) {
     out[g] = s;
   } else if constexpr (OP == OP_STORE) {
     out[g] = dir ? T(0) : s;
   } else if constexpr (OP == OP_RESID) {
-    out[g] = dir ? T(0) : a1[g] - s;
+    out[g] = dir ? T(0) : in.a1 - s;
   } else if constexpr (OP == OP_JACOBI) {
-    if (!dir) out[g] += omega * a2[g] * (a1[g] - s);
+    if (!dir) out[g] = in.o + omega * in.a2 * (in.a1 - s);
   } else if constexpr (OP == OP_STORE_DOT) {
     const T v = dir ? T(0) : s;
     out[g] = v;
-    acc += double(a1[g]) * double(v);
+    acc += double(in.a1) * double(v);
   } else if constexpr (OP == OP_CHEB0) {
-    const T rn = dir ? T(0) : a1[g] - s;
+    const T rn = dir ? T(0) : in.a1 - s;
     a4[g] = rn;
-    const T dn = c1 * a2[g] * rn;
+    const T dn = c1 * in.a2 * rn;
     a3[g] = dn;
-    out[g] += dn;
+    out[g] = in.o + dn;
   } else if constexpr (OP == OP_CHEB) {
     if (!dir) {
-      T* r = const_cast<T*>(a1);
-      const T rn = r[g] - s;
+      const T rn = in.a1 - s;
       r[g] = rn;
-      const T dn = omega * a3[g] + c1 * a2[g] * rn;
+      const T dn = omega * in.a3 + c1 * in.a2 * rn;
       a3[g] = dn;
-      out[g] += dn;
+      out[g] = in.o + dn;
     }
   }
 }

@@ -217,8 +217,15 @@ template void launch_ax<float>(const LevelView&, const float*, const void*, int,
 // ---------------------------------------------------------------------------
 // node-centric direct-stiffness sum with fused epilogues
 // ---------------------------------------------------------------------------
+// Thread per global node g = n nz + z (32-bit: every level has fewer than 2^32
+// nodes, pmg_create).  The node's epilogue inputs and the element values of its
+// first two incidences are read first, with no read waiting on another beyond
+// the incidence ids; nodes of more triangle columns (triangle vertices) read
+// the next ASM_UNROLL together the same way, and any further ones in a loop.
+// The sum runs in ascending incidence order.
+constexpr int ASM_UNROLL = 6;
 template <typename T, int OP>
-__global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, int P,
+__global__ __launch_bounds__(256) void k_assemble(uint32_t n_dof, uint32_t nz, int L, int P,
                                                   const int32_t* __restrict__ inc_ptr,
                                                   const int32_t* __restrict__ inc,
                                                   const uint8_t* __restrict__ dir2d, int top_dir,
@@ -226,29 +233,58 @@ __global__ __launch_bounds__(256) void k_assemble(int64_t n_dof, int nz, int L, 
                                                   const T* __restrict__ a1, const T* __restrict__ a2,
                                                   T* __restrict__ a3, T omega, T c1,
                                                   double* __restrict__ partial, T* __restrict__ a4) {
-  const int colen = L * (P + 1);
+  const uint32_t colen = uint32_t(L * (P + 1));
   double acc = 0.0;
-  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n_dof; g += int64_t(gridDim.x) * 256) {
-    const int64_t g2 = g / nz;
-    const int z = int(g - g2 * nz);
+  for (uint64_t gl = uint64_t(blockIdx.x) * 256 + threadIdx.x; gl < n_dof; gl += uint64_t(gridDim.x) * 256) {
+    const uint32_t g = uint32_t(gl), g2 = g / nz, z = g - g2 * nz;
+    const int j0 = inc_ptr[g2], n = inc_ptr[g2 + 1] - j0;
     const bool dir = dir2d[g2] || (top_dir && z == nz - 1);
+    const NodeIn<T> in = node_in<T, OP>(g, out, a1, a2, a3);
     int p1, p2;
-    column_pos(z, P, L, p1, p2);
-    T s = 0;
-    const int j0 = inc_ptr[g2], j1 = inc_ptr[g2 + 1];
-    for (int j = j0; j < j1; ++j) {
-      const T* col = Y + size_t(inc[j]) * colen;
-      s += col[p1];
-      if (p2 >= 0) s += col[p2];
+    column_pos(int(z), P, L, p1, p2);
+    // p2 read as p1 off an interface (same line, not added); every node has n >= 1
+    const int q2 = p2 >= 0 ? p2 : p1;
+    T s;
+    {
+      const T* ca = Y + size_t(uint32_t(inc[j0])) * colen;
+      const T* cb = Y + size_t(uint32_t(inc[j0 + (n > 1 ? 1 : 0)])) * colen;
+      const T xa = ca[p1], ya = ca[q2], xb = cb[p1], yb = cb[q2];
+      s = xa;
+      if (p2 >= 0) s += ya;
+      if (n > 1) {
+        s += xb;
+        if (p2 >= 0) s += yb;
+      }
+    }
+    if (n > 2) {  // vertex columns: the next ASM_UNROLL incidences at once, clamped in bounds
+      T x[ASM_UNROLL], y[ASM_UNROLL];
+#pragma unroll
+      for (int u = 0; u < ASM_UNROLL; ++u) {
+        const T* col = Y + size_t(uint32_t(inc[j0 + 2 + (u < n - 3 ? u : n - 3)])) * colen;
+        x[u] = col[p1];
+        y[u] = col[q2];
+      }
+#pragma unroll
+      for (int u = 0; u < ASM_UNROLL; ++u) {
+        if (u + 2 < n) {
+          s += x[u];
+          if (p2 >= 0) s += y[u];
+        }
+      }
+      for (int j = j0 + 2 + ASM_UNROLL; j < j0 + n; ++j) {
+        const T* col = Y + size_t(uint32_t(inc[j])) * colen;
+        s += col[p1];
+        if (p2 >= 0) s += col[p2];
+      }
     }
     if constexpr (OP == OP_AVG_RAW) {
-      out[g] = s / T((j1 - j0) * (p2 >= 0 ? 2 : 1));
+      out[g] = s / T(n * (p2 >= 0 ? 2 : 1));
     } else if constexpr (OP == OP_AVG_ADD || OP == OP_AVG_STORE) {
-      const T m = T((j1 - j0) * (p2 >= 0 ? 2 : 1));
+      const T m = T(n * (p2 >= 0 ? 2 : 1));
       const T v = dir ? T(0) : s / m;
-      if (OP == OP_AVG_ADD) out[g] += v; else out[g] = v;
+      if (OP == OP_AVG_ADD) out[g] = in.o + v; else out[g] = v;
     } else {
-      node_epilogue<T, OP>(g, dir, s, out, a1, a2, a3, a4, omega, c1, acc);
+      node_epilogue<T, OP>(g, dir, s, in, out, const_cast<T*>(a1), a3, a4, omega, c1, acc);
     }
   }
   if (OP == OP_STORE_DOT) {
@@ -262,7 +298,8 @@ void launch_assemble(const LevelView& lv, int op, const T* Y, T* out, const T* a
                      double omega, double c1, double* partial, hipStream_t st, T* a4) {
   const int grid = op == OP_STORE_DOT ? RED_BLOCKS : grid_for(lv.n_dof);
 #define PMG_ASM(OPV)                                                                                   \
-  hipLaunchKernelGGL((k_assemble<T, OPV>), dim3(grid), dim3(256), 0, st, lv.n_dof, int(lv.nz), lv.L,  \
+  hipLaunchKernelGGL((k_assemble<T, OPV>), dim3(grid), dim3(256), 0, st, uint32_t(lv.n_dof),           \
+                     uint32_t(lv.nz), lv.L,                                                           \
                      lv.PZ, lv.inc_ptr, lv.inc, lv.dir2d, lv.top_dir, Y, out, a1, a2, a3, T(omega),   \
                      T(c1), partial, a4)
   switch (op) {
@@ -302,10 +339,11 @@ __global__ __launch_bounds__(256) void k_col_sum(int64_t n_dof, uint32_t nz, int
                                                  double* __restrict__ partial, T* __restrict__ a4) {
   double acc = 0.0;
   const int64_t g_bnd = n_bnd * int64_t(nz);
-  for (int64_t g = int64_t(blockIdx.x) * 256 + threadIdx.x; g < n_dof; g += int64_t(gridDim.x) * 256) {
-    const uint32_t gu = uint32_t(g), n2 = gu / nz, z = gu - n2 * nz;  // n_dof < 2^32 (colsum levels)
+  for (uint64_t gl = uint64_t(blockIdx.x) * 256 + threadIdx.x; gl < n_dof; gl += uint64_t(gridDim.x) * 256) {
+    const uint32_t g = uint32_t(gl), n2 = g / nz, z = g - n2 * nz;  // n_dof < 2^32 (pmg_create)
+    const NodeIn<T> in = node_in<T, OP>(g, out, a1, a2, a3);
     T s;
-    if (g >= g_bnd) {
+    if (int64_t(g) >= g_bnd) {
       s = cv[g - g_bnd];
     } else {
       s = 0;
@@ -313,7 +351,7 @@ __global__ __launch_bounds__(256) void k_col_sum(int64_t n_dof, uint32_t nz, int
       for (int j = sh_ptr[n2]; j < j1; ++j) s += cv_b[size_t(sh_idx[j]) * nz + z];
     }
     const bool dir = dir2d[n2] || (top_dir && z == nz - 1);
-    node_epilogue<T, OP>(g, dir, s, out, a1, a2, a3, a4, omega, c1, acc);
+    node_epilogue<T, OP>(g, dir, s, in, out, const_cast<T*>(a1), a3, a4, omega, c1, acc);
   }
   if constexpr (OP == OP_STORE_DOT) {
     const double b = block_sum256(acc);

@@ -749,42 +749,71 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
 // Split-BF16 products (FP32 accumulation): every operand x = x_hi + x_lo with
 // x_hi = bf16(x), x_lo = bf16(x - x_hi).
 // LO: a product keeps the three terms a_hi b_hi + a_hi b_lo + a_lo b_hi (about
-//   16 significant bits, against 8 for one BF16 product), three BF16 MFMAs in
-//   place of one FP32 MFMA of four times the cost per K.  Tables: hi and lo
-//   copies of the BF16-layout tables, both in LDS (78 KB at P = 6, two
-//   workgroups per CU within 128 VGPRs).  At P = 6 it is the fastest FP32-
-//   accurate operator: its matrix-core time is a fraction of the FP32 MFMA's,
-//   and the kernel is bound by vector-ALU issue instead (hi/lo splits,
-//   pointwise products, the vertical contractions), not by memory.
+//   16 significant bits, against 8 for one BF16 product).  Tables: hi and lo
+//   copies, both in LDS (79 KB at P = 6, two workgroups per CU within 128
+//   VGPRs).
 // !LO: the reference tables are rounded to BF16 once (a fixed, symmetric
 //   perturbation of the reference matrices, as G's rounding is of the
-//   geometry) and only the vectors are split: a_hi b_hi + a_hi b_lo, two BF16
-//   MFMAs, the LDS of the plain BF16 kernel.
+//   geometry) and only the vectors are split: a_hi b_hi + a_hi b_lo.
+// Stage 2 runs on the K = 32 BF16 MFMA of gfx950 (v_mfma_f32_16x16x32_bf16):
+// one step covers the 28 triangle nodes of P = 6, half the instructions of two
+// K = 16 steps.  K slots: lane group g = lane / 16 holds slots 8g .. 8g+7, and
+// slot e of group g is node a = 16 (e / 4) + 4 (e % 4) + g, so that stage 1
+// reads 64 consecutive LDS words per instruction.  Stage 4 stays on K = 16 per
+// q tile, its B operand being the registers the pointwise stage produced (a
+// K = 32 form over q tile pairs halves those instructions too but holds two
+// tiles' values at once and measured slower at 128 VGPRs).
+// Phase 2 reads the vertical coefficients from the kernel arguments (scalar
+// registers), and the partial results from S[k][h][a][el] with rows of 20
+// words (conflict-free stores from the MFMA output layout).
 // GEO: G in FP32 from the FP32 column factors (Gsrc = geo[t][q][8]) instead of
 // the stored lane-native BF16 G (Gsrc = Gnat).
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef short s8_t __attribute__((ext_vector_type(8)));
+__device__ __forceinline__ f4_t mfma32(s8_t a, s8_t b, f4_t c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, a), __builtin_bit_cast(bf8_t, b), c, 0, 0,
+                                                 0);
+}
+__device__ __forceinline__ void split8(const float (&x)[8], s8_t& hi, s8_t& lo) {
+  const float x0[4] = {x[0], x[1], x[2], x[3]}, x1[4] = {x[4], x[5], x[6], x[7]};
+  s4_t h0, l0, h1, l1;
+  split4(x0, h0, l0);
+  split4(x1, h1, l1);
+  hi = __builtin_shufflevector(h0, h1, 0, 1, 2, 3, 4, 5, 6, 7);
+  lo = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+}
+template <int PT, int PZ> struct X3 {
+  using D = MD<PT, PZ>;
+  static constexpr int SROW = 20;                          // words per row of S
+  static constexpr int S_WORDS = D::N1 * 2 * D::NPT * SROW;
+  static constexpr int U_WORDS = D::N1 * D::NPT * 16;
+  static constexpr int C_WORDS = 16 * D::NPT * D::N1;      // Ycol of the column-sum phase 2
+  static constexpr int R_WORDS = S_WORDS > U_WORDS ? (S_WORDS > C_WORDS ? S_WORDS : C_WORDS)
+                                                   : (U_WORDS > C_WORDS ? U_WORDS : C_WORDS);
+  static constexpr int NTAB2 = 3 * D::NT2 * 64, NTAB4 = 3 * D::NAT * D::NT2 * 64;
+};
+__device__ __forceinline__ int x3_srow(int k, int h, int a, int NPT) { return ((k * 2 + h) * NPT + a) * 20; }
+
 template <int PT, int PZ, bool LO, bool GEO = false, bool CS = false>
 __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_mfma_bf16x3(const int32_t* __restrict__ map2d, int L,
                                                                      int nz, int64_t n_elem, int64_t n_batch,
                                                                      const void* __restrict__ Gsrc,
-                                                                     const s4_t* __restrict__ tab2,
+                                                                     const s8_t* __restrict__ tab2,
                                                                      const s4_t* __restrict__ tab4,
-                                                                     const s4_t* __restrict__ tab2lo,
+                                                                     const s8_t* __restrict__ tab2lo,
                                                                      const s4_t* __restrict__ tab4lo,
                                                                      VertMats<float> vm, const float* __restrict__ u,
                                                                      float* __restrict__ Y) {
   using D = MD<PT, PZ>;
-  constexpr int N1 = D::N1, NPT = D::NPT, NT2 = D::NT2, KS16 = D::KS16, NAT = D::NAT;
-  constexpr int NTAB2 = 3 * NT2 * KS16 * 64, NTAB4 = 3 * NAT * NT2 * 64;
-  constexpr int NTH = 64 * N1;
-  __shared__ s4_t s2[NTAB2];
-  __shared__ s4_t s2l[LO ? NTAB2 : 1];
+  using XS = X3<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NT2 = D::NT2, NAT = D::NAT;
+  constexpr int NTAB2 = XS::NTAB2, NTAB4 = XS::NTAB4, NTH = 64 * N1;
+  static_assert(NPT <= 32, "one K = 32 step over the triangle nodes");
+  __shared__ s8_t s2[NTAB2];
+  __shared__ s8_t s2l[LO ? NTAB2 : 1];
   __shared__ s4_t s4[NTAB4];
   __shared__ s4_t s4l[LO ? NTAB4 : 1];
-  __shared__ float sR[KS_LDS<PT, PZ>::R_WORDS];
-  __shared__ float sV[2 * N1 * N1];
-  // vertical transpose coefficients with the Gauss weight zw_k in row k (GEO:
-  // G is then formed without it); stage 1 reads the plain sV
-  __shared__ float sVw[GEO ? 2 * N1 * N1 : 1];
+  __shared__ float sR[XS::R_WORDS];
   for (int i = threadIdx.x; i < NTAB2; i += NTH) {
     s2[i] = tab2[i];
     if constexpr (LO) s2l[i] = tab2lo[i];
@@ -793,25 +822,24 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
     s4[i] = tab4[i];
     if constexpr (LO) s4l[i] = tab4lo[i];
   }
-  for (int i = threadIdx.x; i < N1 * N1; i += NTH) {
-    sV[i] = vm.Bz[i];
-    sV[N1 * N1 + i] = vm.Dz[i];
-    if constexpr (GEO) {
-      sVw[i] = vm.Bz[i] * vm.zw[i / N1];
-      sVw[N1 * N1 + i] = vm.Dz[i] * vm.zw[i / N1];
-    }
-  }
-  const float* __restrict__ sVo = GEO ? sVw : sV;  // coefficients of the vertical transpose
-  const int lane = threadIdx.x & 63, k = threadIdx.x >> 6, g = lane >> 4, j = lane & 15;
+  // wave-uniform Gauss level: the stage-1 coefficients are scalar loads
+  const int k = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
   const bf16_t* __restrict__ Gnat = static_cast<const bf16_t*>(Gsrc);
   const float* __restrict__ geo = static_cast<const float*>(Gsrc);
+  // vertical transpose coefficients (kernel arguments, uniform index: scalar
+  // loads); with GEO the Gauss weight zw_k rides on them (rows of Bz and Dz
+  // scaled by zw_k) and G is formed without it
+  auto vB = [&](int i) {
+    if constexpr (GEO) return vm.Bzw[i]; else return vm.Bz[i];
+  };
+  auto vD = [&](int i) {
+    if constexpr (GEO) return vm.Dzw[i]; else return vm.Dz[i];
+  };
   const int64_t bnd_off = CS ? int64_t(n_elem / L) * ((PT - 1) * (PT - 2) / 2) * nz : 0;
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();
-    // stored G: tile t as raw BF16 pairs, loaded one tile ahead (the first under
-    // the staging of u and stage 1): a tile's words are in flight during the
-    // previous tile's MFMAs
     const int64_t blk = ((b * N1 + k) * 6) * (16 * D::NQT);
     constexpr int64_t mst = 16 * D::NQT;
     uint32_t gw[6][2];
@@ -821,26 +849,26 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
     else load_g_bf16<PT, PZ>(Gnat, blk, mst, 0, lane, g, j, gw);
     stage_u<PT, PZ, float>(map2d, L, nz, n_elem, b, u, sR);
     __syncthreads();
-    s4_t wh[KS16], wl[KS16], zh[KS16], zl[KS16];
+    // stage 1: the lane's eight node slots a = 16 s + 4 kk + g
+    s8_t wh, wl, zh, zl;
+    {
+      float w0[8], w1[8];
 #pragma unroll
-    for (int s = 0; s < KS16; ++s) {
-      float a0[4], a1[4];
-#pragma unroll
-      for (int kk = 0; kk < 4; ++kk) {
-        const int a = 16 * s + 4 * g + kk;
-        a0[kk] = 0.f;
-        a1[kk] = 0.f;
+      for (int e = 0; e < 8; ++e) {
+        const int a = 16 * (e >> 2) + 4 * (e & 3) + g;
+        w0[e] = 0.f;
+        w1[e] = 0.f;
         if (a < NPT) {
 #pragma unroll
           for (int c = 0; c < N1; ++c) {
             const float uv = sR[(c * NPT + a) * 16 + j];
-            a0[kk] += sV[k * N1 + c] * uv;
-            a1[kk] += sV[N1 * N1 + k * N1 + c] * uv;
+            w0[e] = __builtin_fmaf(vm.Bz[k * N1 + c], uv, w0[e]);
+            w1[e] = __builtin_fmaf(vm.Dz[k * N1 + c], uv, w1[e]);
           }
         }
       }
-      split4(a0, wh[s], wl[s]);
-      split4(a1, zh[s], zl[s]);
+      split8(w0, wh, wl);
+      split8(w1, zh, zl);
     }
     __syncthreads();
     f4_t yr[NAT], yt[NAT];
@@ -857,40 +885,35 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
         for (int m = 0; m < 6; ++m) { gc[m][0] = gw[m][0]; gc[m][1] = gw[m][1]; }
         if (t + 1 < NT2) load_g_bf16<PT, PZ>(Gnat, blk, mst, t + 1, lane, g, j, gw);
       }
-      f4_t dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
-#pragma unroll
-      for (int s = 0; s < KS16; ++s) {
-        const int i0 = ((0 * NT2 + t) * KS16 + s) * 64 + lane, i1 = ((1 * NT2 + t) * KS16 + s) * 64 + lane,
-                  i2 = ((2 * NT2 + t) * KS16 + s) * 64 + lane;
-        dr = mfma16(s2[i0], wh[s], dr);
-        ds = mfma16(s2[i1], wh[s], ds);
-        db = mfma16(s2[i2], zh[s], db);
-        dr = mfma16(s2[i0], wl[s], dr);
-        ds = mfma16(s2[i1], wl[s], ds);
-        db = mfma16(s2[i2], zl[s], db);
-        if constexpr (LO) {
-          dr = mfma16(s2l[i0], wh[s], dr);
-          ds = mfma16(s2l[i1], wh[s], ds);
-          db = mfma16(s2l[i2], zh[s], db);
-        }
+      const int i0 = (0 * NT2 + t) * 64 + lane, i1 = (1 * NT2 + t) * 64 + lane, i2 = (2 * NT2 + t) * 64 + lane;
+      f4_t dr = mfma32(s2[i0], wh, f4_t{0, 0, 0, 0});
+      f4_t ds = mfma32(s2[i1], wh, f4_t{0, 0, 0, 0});
+      f4_t db = mfma32(s2[i2], zh, f4_t{0, 0, 0, 0});
+      dr = mfma32(s2[i0], wl, dr);
+      ds = mfma32(s2[i1], wl, ds);
+      db = mfma32(s2[i2], zl, db);
+      if constexpr (LO) {
+        dr = mfma32(s2l[i0], wh, dr);
+        ds = mfma32(s2l[i1], wh, ds);
+        db = mfma32(s2l[i2], zh, db);
       }
       float pr[4], ps[4], pt[4];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const float ur = dr[r], us = ds[r], ut = db[r];
-        float gv[6][4];
+        float gv[6];
 #pragma unroll
         for (int m = 0; m < 6; ++m) {
           if constexpr (GEO) {
-            gv[m][r] = gg[m][r];
+            gv[m] = gg[m][r];
           } else {
             const uint32_t wv = gc[m][r >> 1];
-            gv[m][r] = __uint_as_float((r & 1) ? (wv & 0xFFFF0000u) : (wv << 16));
+            gv[m] = __uint_as_float((r & 1) ? (wv & 0xFFFF0000u) : (wv << 16));
           }
         }
-        pr[r] = gv[0][r] * ur + gv[1][r] * us + gv[2][r] * ut;
-        ps[r] = gv[1][r] * ur + gv[3][r] * us + gv[4][r] * ut;
-        pt[r] = gv[2][r] * ur + gv[4][r] * us + gv[5][r] * ut;
+        pr[r] = gv[0] * ur + gv[1] * us + gv[2] * ut;
+        ps[r] = gv[1] * ur + gv[3] * us + gv[4] * ut;
+        pt[r] = gv[2] * ur + gv[4] * us + gv[5] * ut;
       }
       s4_t rh, rl, sh, sl, th, tl;
       split4(pr, rh, rl);
@@ -898,37 +921,93 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
       split4(pt, th, tl);
 #pragma unroll
       for (int at = 0; at < NAT; ++at) {
-        const int i0 = ((0 * NAT + at) * NT2 + t) * 64 + lane, i1 = ((1 * NAT + at) * NT2 + t) * 64 + lane,
-                  i2 = ((2 * NAT + at) * NT2 + t) * 64 + lane;
-        yr[at] = mfma16(s4[i0], rh, yr[at]);
-        yr[at] = mfma16(s4[i1], sh, yr[at]);
-        yt[at] = mfma16(s4[i2], th, yt[at]);
-        yr[at] = mfma16(s4[i0], rl, yr[at]);
-        yr[at] = mfma16(s4[i1], sl, yr[at]);
-        yt[at] = mfma16(s4[i2], tl, yt[at]);
+        const int k0 = ((0 * NAT + at) * NT2 + t) * 64 + lane, k1 = ((1 * NAT + at) * NT2 + t) * 64 + lane,
+                  k2 = ((2 * NAT + at) * NT2 + t) * 64 + lane;
+        yr[at] = mfma16(s4[k0], rh, yr[at]);
+        yr[at] = mfma16(s4[k1], sh, yr[at]);
+        yt[at] = mfma16(s4[k2], th, yt[at]);
+        yr[at] = mfma16(s4[k0], rl, yr[at]);
+        yr[at] = mfma16(s4[k1], sl, yr[at]);
+        yt[at] = mfma16(s4[k2], tl, yt[at]);
         if constexpr (LO) {
-          yr[at] = mfma16(s4l[i0], rh, yr[at]);
-          yr[at] = mfma16(s4l[i1], sh, yr[at]);
-          yt[at] = mfma16(s4l[i2], th, yt[at]);
+          yr[at] = mfma16(s4l[k0], rh, yr[at]);
+          yr[at] = mfma16(s4l[k1], sh, yr[at]);
+          yt[at] = mfma16(s4l[k2], th, yt[at]);
         }
       }
     }
+    // partials to S[k][h][a][el] (rows a >= NPT hold no node)
 #pragma unroll
     for (int at = 0; at < NAT; ++at)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int a = 16 * at + 4 * g + r;
-        sR[((k * 2 + 0) * NAT * 16 + a) * 16 + j] = yr[at][r];
-        sR[((k * 2 + 1) * NAT * 16 + a) * 16 + j] = yt[at][r];
+        if (a < NPT) {
+          sR[x3_srow(k, 0, a, NPT) + j] = yr[at][r];
+          sR[x3_srow(k, 1, a, NPT) + j] = yt[at][r];
+        }
       }
     __syncthreads();
+    // phase 2: thread (a, el) sums over the Gauss levels for its PZ+1 outputs
+    static_assert(16 * NPT <= NTH, "one (node, prism) pair per thread");
+    const int pr2 = threadIdx.x, a2 = pr2 >> 4, el = pr2 & 15;
+    const bool act = pr2 < 16 * NPT;
+    const int64_t e = b * 16 + el;
+    const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
+    const int te = e < n_elem ? int(tu) : -1, layer = int(eu - tu * uint32_t(L));
+    float yv[N1], zv[N1];
+    if (act) {
+#pragma unroll
+      for (int kk = 0; kk < N1; ++kk) {
+        yv[kk] = sR[x3_srow(kk, 0, a2, NPT) + el];
+        zv[kk] = sR[x3_srow(kk, 1, a2, NPT) + el];
+      }
+    }
     if constexpr (CS) {
-      const int64_t e = b * 16 + (threadIdx.x & 15);
-      const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
-      vertical_colsum<PT, PZ, float>(e < n_elem ? int(tu) : -1, int(eu - tu * uint32_t(L)), L, nz, bnd_off, sR,
-                                     sVo, Y);
+      // column sums (16 % L == 0: whole columns per batch, prism el + 1 is the
+      // layer above el): y[c] of prism el to Ycol[el][a][c], then the column
+      // values z = layer PZ + c, c = (layer > 0) .. PZ, of (triangle, node a),
+      // the top one adding the bottom value of the layer above, to the layout
+      // of launch_col_sum
+      constexpr int NINT = (PT - 1) * (PT - 2) / 2;
+      __syncthreads();  // every thread holds its partials; sR becomes Ycol
+      float* ycol = sR + (el * NPT + a2) * N1;
+      if (act) {
+#pragma unroll 1
+        for (int c = 0; c < N1; ++c) {
+          float y = 0.f;
+#pragma unroll
+          for (int kk = 0; kk < N1; ++kk) {
+            y = __builtin_fmaf(vB(kk * N1 + c), yv[kk], y);
+            y = __builtin_fmaf(vD(kk * N1 + c), zv[kk], y);
+          }
+          ycol[c] = y;
+        }
+      }
+      __syncthreads();
+      if (act && te >= 0) {
+        const bool above = layer + 1 < L;
+        const float top = above ? sR[((el + 1) * NPT + a2) * N1] : 0.f;
+        const int code = tri_code<PT>(a2);
+        float* dst = (code >= 0 ? Y + bnd_off + (size_t(te) * (3 * PT) + code) * nz
+                                : Y + (size_t(te) * NINT + (-1 - code)) * nz) + layer * PZ;
+#pragma unroll 1
+        for (int c = layer > 0 ? 1 : 0; c < N1; ++c) dst[c] = c == PZ && above ? ycol[c] + top : ycol[c];
+      }
     } else {
-      vertical_out<PT, PZ, float>(L, n_elem, b, sR, sVo, Y);
+      if (act && te >= 0) {
+        float* out = Y + ((size_t(te) * NPT + a2) * L + layer) * N1;
+#pragma unroll 1
+        for (int c = 0; c < N1; ++c) {
+          float y = 0.f;
+#pragma unroll
+          for (int kk = 0; kk < N1; ++kk) {
+            y = __builtin_fmaf(vB(kk * N1 + c), yv[kk], y);
+            y = __builtin_fmaf(vD(kk * N1 + c), zv[kk], y);
+          }
+          out[c] = y;
+        }
+      }
     }
   }
 }
@@ -1118,7 +1197,7 @@ static bool ax_mfma_p(const LevelView& lv, const void* Gnat, int flavour, const 
 #define PMG_X(LO, GE, C)                                                                                      \
   launch_batches<KeyOf<PT, PZ, LO ? MF_BF16X3 : MF_BF16X2, GE, C>>(                                           \
       k_ax_mfma_bf16x3<PT, PZ, LO, GE, C>, NT, need, st, lv.map2d, lv.L, int(lv.nz), lv.n_elem, nb, G,        \
-      (const s4_t*)tab2, (const s4_t*)tab4, (const s4_t*)lo2, (const s4_t*)lo4, v32, (const float*)u,         \
+      (const s8_t*)tab2, (const s4_t*)tab4, (const s8_t*)lo2, (const s4_t*)lo4, v32, (const float*)u,         \
       (float*)Y)
       if (flavour == MF_BF16X3 && geo) {
 #define PMG_L(C) PMG_X(true, true, C)

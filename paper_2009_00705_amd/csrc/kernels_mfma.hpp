@@ -13,11 +13,14 @@ namespace pmg {
 // and the hi / lo BF16 tables; MF_BF16X2: split vectors on the BF16 tables (two)
 enum MfmaFlavour { MF_F64 = 0, MF_F32 = 1, MF_BF16 = 2, MF_F32G16 = 3, MF_BF16X3 = 4, MF_BF16X2 = 5 };
 
-// vertical interpolation/derivative matrices at the Gauss points, and the Gauss
-// weights zw and positions zh = (1 + zq) / 2 in [0, 1], passed by value
+// vertical interpolation/derivative matrices at the Gauss points (Bz[k][c],
+// Dz[k][c]), the same with row k scaled by the Gauss weight zw_k (Bzw, Dzw),
+// and the weights zw and positions zh = (1 + zq) / 2 in [0, 1], passed by value
 template <typename T> struct VertMats {
   T Bz[81];
   T Dz[81];
+  T Bzw[81];
+  T Dzw[81];
   T zw[9];
   T zh[9];
 };

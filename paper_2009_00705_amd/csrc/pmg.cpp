@@ -105,7 +105,7 @@ struct Level {
   void* tab2[3] = {nullptr, nullptr, nullptr};
   void* tab4[3] = {nullptr, nullptr, nullptr};
   // lo parts of the BF16 tables (split-BF16 products, MF_BF16X3)
-  void *tab2lo = nullptr, *tab4lo = nullptr;
+  void *tab2x = nullptr, *tab4x = nullptr, *tab2lo = nullptr, *tab4lo = nullptr;  // split-BF16 tables
   bool mfx3 = false;
   // column factors geo[t][q][8] of the MFMA operators (PMG_GEOM_COLUMN)
   double* geo64 = nullptr;
@@ -328,6 +328,8 @@ static void build_levels(pmg_ctx* c) {
     L.PZ = orders[i].second;
     L.re.reset(new RefElem(L.P, L.PZ));
     L.num.build(c->mesh, L.P, L.PZ);
+    // node kernels index a level's nodes with 32-bit integers
+    if (L.num.n_dof >= (int64_t(1) << 32)) throw Error(PMG_EINVAL, "a level with 2^32 or more nodes");
     L.dir2d_h = lateral_dirichlet(c->mesh, L.num, o.dirichlet_tags);
     L.top_dir = o.top_neumann ? 0 : 1;
     int64_t nd = 0;
@@ -370,8 +372,7 @@ static void build_levels(pmg_ctx* c) {
 // MFMA operand tables of one order (see kernels_mfma.hip): row map of the
 // output registers is 4g+r (FP32, BF16) or g+4r (FP64), g = lane/16, j = lane%16.
 static void mfma_tables(const RefElem& re, int flavour, std::vector<double>& t2, std::vector<double>& t4,
-                        std::vector<uint16_t>& b2, std::vector<uint16_t>& b4, std::vector<uint16_t>* b2lo = nullptr,
-                        std::vector<uint16_t>* b4lo = nullptr) {
+                        std::vector<uint16_t>& b2, std::vector<uint16_t>& b4) {
   const int NPT = re.np_tri, NQT = re.nq_tri;
   const int NT2 = (NQT + 15) / 16, KS = (NPT + 3) / 4, KS16 = (NPT + 15) / 16, NAT = (NPT + 15) / 16;
   const Mat* M[3] = {&re.Dr, &re.Ds, &re.B};
@@ -383,29 +384,7 @@ static void mfma_tables(const RefElem& re, int flavour, std::vector<double>& t2,
     u += 0x7FFFu + ((u >> 16) & 1u);
     return uint16_t(u >> 16);
   };
-  // lo part of a value: bf16 of (v - hi), hi = bf16(v)
-  auto bflo = [&](double v) {
-    const uint16_t h = bf(v);
-    const uint32_t hb = uint32_t(h) << 16;
-    float hf;
-    std::memcpy(&hf, &hb, 4);
-    return bf(double(float(v) - hf));
-  };
   t2.clear(); t4.clear(); b2.clear(); b4.clear();
-  if (flavour == MF_BF16 && b2lo && b4lo) {
-    b2lo->clear();
-    b4lo->clear();
-    for (int mt = 0; mt < 3; ++mt)
-      for (int t = 0; t < NT2; ++t)
-        for (int s = 0; s < KS16; ++s)
-          for (int l = 0; l < 64; ++l)
-            for (int kk = 0; kk < 4; ++kk) b2lo->push_back(bflo(at(mt, 16 * t + (l & 15), 16 * s + 4 * (l >> 4) + kk)));
-    for (int mt = 0; mt < 3; ++mt)
-      for (int a = 0; a < NAT; ++a)
-        for (int t = 0; t < NT2; ++t)
-          for (int l = 0; l < 64; ++l)
-            for (int kk = 0; kk < 4; ++kk) b4lo->push_back(bflo(at(mt, 16 * t + 4 * (l >> 4) + kk, 16 * a + (l & 15))));
-  }
   if (flavour == MF_BF16) {
     for (int mt = 0; mt < 3; ++mt)
       for (int t = 0; t < NT2; ++t)
@@ -434,6 +413,46 @@ static void mfma_tables(const RefElem& re, int flavour, std::vector<double>& t2,
         }
 }
 
+// Operand tables of the split-BF16 operator (see kernels_mfma.hip), hi =
+// bf16(v) and lo = bf16(v - hi) copies: stage 2 (K = 32, 8 values per lane)
+// [m][q tile t][lane][e] = M_m[16 t + lane % 16][a], a = 16 (e / 4) + 4 (e % 4)
+// + lane / 16; stage 4 (K = 16, 4 values per lane) [m][a tile][t][lane][kk] =
+// M_m[16 t + 4 (lane / 16) + kk][16 a_tile + lane % 16]; zero outside the
+// NQT x NPT matrices.
+static void split_tables(const RefElem& re, std::vector<uint16_t>& h2, std::vector<uint16_t>& h4,
+                         std::vector<uint16_t>& l2, std::vector<uint16_t>& l4) {
+  const int NPT = re.np_tri, NQT = re.nq_tri;
+  const int NT2 = (NQT + 15) / 16, NAT = (NPT + 15) / 16;
+  const Mat* M[3] = {&re.Dr, &re.Ds, &re.B};
+  auto at = [&](int mt, int q, int a) { return (q < NQT && a < NPT) ? (*M[mt])(q, a) : 0.0; };
+  auto bf = [](float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return uint16_t(u >> 16);
+  };
+  auto push = [&](double v, std::vector<uint16_t>& hi, std::vector<uint16_t>& lo) {
+    const float f = float(v);
+    const uint16_t h = bf(f);
+    const uint32_t hb = uint32_t(h) << 16;
+    float hf;
+    std::memcpy(&hf, &hb, 4);
+    hi.push_back(h);
+    lo.push_back(bf(f - hf));
+  };
+  h2.clear(); h4.clear(); l2.clear(); l4.clear();
+  for (int mt = 0; mt < 3; ++mt)
+    for (int t = 0; t < NT2; ++t)
+      for (int l = 0; l < 64; ++l)
+        for (int e = 0; e < 8; ++e)
+          push(at(mt, 16 * t + (l & 15), 16 * (e >> 2) + 4 * (e & 3) + (l >> 4)), h2, l2);
+  for (int mt = 0; mt < 3; ++mt)
+    for (int a = 0; a < NAT; ++a)
+      for (int t = 0; t < NT2; ++t)
+        for (int l = 0; l < 64; ++l)
+          for (int kk = 0; kk < 4; ++kk) push(at(mt, 16 * t + 4 * (l >> 4) + kk, 16 * a + (l & 15)), h4, l4);
+}
+
 static void upload_mfma(pmg_ctx* c, Level& L) {
   const RefElem& re = *L.re;
   for (int i = 0; i < re.n1 * re.n1; ++i) {
@@ -441,6 +460,13 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
     L.vm64.Dz[i] = re.Dz.v[i];
     L.vm32.Bz[i] = float(re.Bz.v[i]);
     L.vm32.Dz[i] = float(re.Dz.v[i]);
+  }
+  for (int i = 0; i < re.n1 * re.n1; ++i) {
+    const double w = re.zw[i / re.n1];
+    L.vm64.Bzw[i] = re.Bz.v[i] * w;
+    L.vm64.Dzw[i] = re.Dz.v[i] * w;
+    L.vm32.Bzw[i] = float(L.vm64.Bzw[i]);
+    L.vm32.Dzw[i] = float(L.vm64.Dzw[i]);
   }
   for (int k = 0; k < re.n1; ++k) {
     L.vm64.zw[k] = re.zw[k];
@@ -455,11 +481,15 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
   for (int f = 0; f < 3; ++f) {
     if (!mfma_available(L.P, L.PZ, f)) continue;
     std::vector<double> t2, t4;
-    std::vector<uint16_t> b2, b4, b2lo, b4lo;
-    mfma_tables(re, f, t2, t4, b2, b4, &b2lo, &b4lo);
+    std::vector<uint16_t> b2, b4;
+    mfma_tables(re, f, t2, t4, b2, b4);
     if (f == MF_BF16 && mfma_available(L.P, L.PZ, MF_BF16X3)) {
-      L.tab2lo = c->U(b2lo);
-      L.tab4lo = c->U(b4lo);
+      std::vector<uint16_t> h2, h4, l2, l4;
+      split_tables(re, h2, h4, l2, l4);
+      L.tab2x = c->U(h2);
+      L.tab4x = c->U(h4);
+      L.tab2lo = c->U(l2);
+      L.tab4lo = c->U(l4);
       L.mfx3 = true;
     }
     if (f == MF_F64) {
@@ -516,8 +546,12 @@ static void upload_levels(pmg_ctx* c) {
     // column factors of every level (the MFMA operators and the diagonal read them)
     if (c->opt.geometry == PMG_GEOM_COLUMN) {
       const size_t n = size_t(c->mesh.nt) * re.nq_tri * 8;
-      L.geo64 = c->A<double>(n);
-      L.geo32 = c->A<float>(n);
+      // padded with 16 zero records: the MFMA operators read whole 16-row tiles of
+      // cubature points, past a triangle's last point into the next one's
+      L.geo64 = c->A<double>(n + 128);
+      L.geo32 = c->A<float>(n + 128);
+      HIPCHK(hipMemset(L.geo64 + n, 0, 128 * sizeof(double)));
+      HIPCHK(hipMemset(L.geo32 + n, 0, 128 * sizeof(float)));
     }
     L.diag = c->A<double>(N);
     L.dinv64 = c->A<double>(N);
@@ -690,12 +724,12 @@ static bool ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st, bool colsum =
     const void* geo = !col ? nullptr : (sizeof(T) == 8 ? (const void*)L.geo64 : (const void*)L.geo32);
     if (f == MF_BF16 && c->bf16x3 && L.mfx3) {
       if (!geo) ensure_native(c, L, MF_BF16, st);
-      ok = launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X3, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
-                          L.tab2lo, L.tab4lo, geo, colsum);
-    } else if (f == MF_BF16 && c->bf16x2 && mfma_available(L.P, L.PZ, MF_BF16X2)) {
+      ok = launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X3, L.tab2x, L.tab4x, vm, x, c->Y, st, L.tab2lo,
+                          L.tab4lo, geo, colsum);
+    } else if (f == MF_BF16 && c->bf16x2 && L.mfx3) {
       if (!geo) ensure_native(c, L, MF_BF16, st);
-      ok = launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X2, L.tab2[MF_BF16], L.tab4[MF_BF16], vm, x, c->Y, st,
-                          nullptr, nullptr, geo, colsum);
+      ok = launch_ax_mfma(L.view, L.gnat[MF_BF16], MF_BF16X2, L.tab2x, L.tab4x, vm, x, c->Y, st, nullptr, nullptr,
+                          geo, colsum);
     } else if (f == MF_BF16 && !c->bf16_ops && L.mf[MF_F32]) {
       // FP32 arithmetic on the stored BF16 copy of G (FP32 tables); at in-plane
       // order 3 this is faster than forming G from the column factors, whose
@@ -1924,7 +1958,7 @@ void pmg_options_default(pmg_options* o) {
   o->seed = 0;
   o->geometry = PMG_GEOM_COLUMN;
   o->PZ = 0;
-  o->fused_sum = 1;
+  o->fused_sum = 0;
 }
 
 int pmg_abi_version(void) { return PMG_ABI_VERSION; }

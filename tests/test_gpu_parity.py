@@ -25,8 +25,9 @@ CASES = {
     "box5x5_L3_P6": (lambda: W.box_mesh(5, 3), 6),        # several blocks + ragged tail
     "cyl_P3": (lambda: W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=3), 3),
     "box2_L1_P8": (lambda: W.box_mesh(2, 1), 8),
-    # four layers: batches of 16 prisms hold whole columns, so the MFMA levels
-    # sum their columns inside the element operator (pmg_options.fused_sum)
+    # four layers: batches of 16 prisms hold whole columns; these cases run
+    # with pmg_options.fused_sum = 1 (the MFMA levels write column sums and a
+    # node kernel finishes them), so every check below covers that path too
     "box5x5_L4_P6": (lambda: W.box_mesh(5, 4), 6),
     "cyl_L4_P3": (lambda: W.cylinder_mesh(spacing=0.45, half=2.0, radius=0.5, n_layers=4), 3),
 }
@@ -43,9 +44,12 @@ ALL = dict(CASES, **XY_CASES, **EQ_CASES)
 
 
 def _opts(name):
+    o = {"fused_sum": 1} if "_L4_" in name else {}
     if name in EQ_PZ:
-        return {"coarsening": "equal", "PZ": EQ_PZ[name]}
-    return {"coarsening": "xy"} if name.endswith("_xy") else {}
+        o.update({"coarsening": "equal", "PZ": EQ_PZ[name]})
+    elif name.endswith("_xy"):
+        o["coarsening"] = "xy"
+    return o
 
 
 @pytest.fixture(scope="module", params=sorted(ALL))
@@ -418,7 +422,8 @@ def fused_pair(request):
     mesh = mk()
     ctxs = []
     for fused in (1, 0):
-        c = pmg.Context(mesh, P=P, fused_sum=fused, omega=[0.3] * 8, **_opts(request.param))
+        opts = dict(_opts(request.param), fused_sum=fused)
+        c = pmg.Context(mesh, P=P, omega=[0.3] * 8, **opts)
         c.set_surface(dev(surface_eta(c.surface_xy(), "wavy")))
         ctxs.append(c)
     torch.cuda.synchronize()
