@@ -460,11 +460,40 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
   }
   const int64_t bnd_off = CS ? int64_t(n_elem / L) * ((PT - 1) * (PT - 2) / 2) * nz : 0;
   const int64_t lb = xcd_block(gridDim.x);
+  // PF: one (node, prism) pair of the staging per thread; its column values for
+  // the next batch are loaded while this batch computes (map entry at the top
+  // of the batch, values after stage 1), hiding the gather's two dependent
+  // memory latencies
+  constexpr bool PF = 16 * NPT <= NTH;
+  const int pa = threadIdx.x >> 4;
+  T pf[N1];
+  int32_t pidx = 0;
+  if constexpr (PF) {
+    const ColSlot c0 = col_slot(lb, j, n_elem, L);
+    if (pa < NPT && lb < n_batch && c0.te >= 0) {
+      const T* col = u + int64_t(map2d[size_t(c0.te) * NPT + pa]) * nz + c0.layer * PZ;
+#pragma unroll
+      for (int c = 0; c < N1; ++c) pf[c] = col[c];
+    } else {
+#pragma unroll
+      for (int c = 0; c < N1; ++c) pf[c] = T(0);
+    }
+  }
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
     __syncthreads();  // previous batch's phase 2 done with sR
     // phase 0: U[c][a][el] <- u
     const ColSlot cs = col_slot(b, j, n_elem, L);
-    stage_u<PT, PZ, T>(map2d, nz, cs, u, sR);
+    ColSlot cn{-1, 0};
+    if constexpr (PF) {
+      if (pa < NPT) {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) sR[(c * NPT + pa) * 16 + j] = pf[c];
+      }
+      cn = col_slot(b + gridDim.x, j, n_elem, L);
+      if (pa < NPT && b + gridDim.x < n_batch && cn.te >= 0) pidx = map2d[size_t(cn.te) * NPT + pa];
+    } else {
+      stage_u<PT, PZ, T>(map2d, nz, cs, u, sR);
+    }
     __syncthreads();
     // phase 1, stage 1: W[k][a], Wz[k][a] for a = 4s + g of element j
     T w[KS], wz[KS];
@@ -482,6 +511,16 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
       }
       w[s] = a0;
       wz[s] = a1;
+    }
+    if constexpr (PF) {
+      if (pa < NPT && b + gridDim.x < n_batch && cn.te >= 0) {
+        const T* col = u + int64_t(pidx) * nz + cn.layer * PZ;
+#pragma unroll
+        for (int c = 0; c < N1; ++c) pf[c] = col[c];
+      } else {
+#pragma unroll
+        for (int c = 0; c < N1; ++c) pf[c] = T(0);
+      }
     }
     __syncthreads();  // every wave has read U; sR becomes S
     ACC yr[NAT], yt[NAT];
