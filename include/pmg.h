@@ -382,7 +382,9 @@ enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, 
  * roofline measurement).  The element operator reads the level's work vector;
  * results are discarded.  PMG_K_COPY is a plain device copy of the level's
  * FP64 vector (n_dof * 8 bytes read and written): the reference point that
- * scales hardware byte counters.  PMG_K_SCHWARZ is the batched local solve of
+ * scales hardware byte counters.  PMG_K_PROLONG is the prolongation from
+ * level + 1 to `level` as the V-cycle runs it (node-wise where the level pair
+ * keeps one order, else element-wise with its averaging sum).  PMG_K_SCHWARZ is the batched local solve of
  * the Schwarz smoother (inverse storage: FP64 for PMG_FP64, FP32 for
  * PMG_MIXED_FP32, BF16 for the BF16 precisions); EINVAL when the smoother is
  * not PMG_SMOOTH_SCHWARZ or the level is the coarsest.  PMG_K_COLSUM_OP: the

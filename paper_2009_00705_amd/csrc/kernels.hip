@@ -773,6 +773,127 @@ void launch_prolong_elem(const LevelView& f, const LevelView& c, const T* pit, c
 #undef PMG_PRO
 }
 
+// Node-wise prolongation for level pairs where one factor of the transfer is
+// the identity (the in-plane-first sequence: the vertical order kept while the
+// triangle order halves, then the triangle order kept).  The coarse space is
+// continuous and nested in the fine one, so every element holding a fine node
+// interpolates the same value there: the element average of the element-wise
+// path equals the value from any one element, here the first incidence of the
+// node's column (the node's triangle t and local node a) in the layer holding
+// it.  One thread per (fine 2D node, layer): the incidence and the coarse map
+// are read once, then the PZ+1 (PZ for layers above the first, whose bottom
+// node the layer below writes) nodes of the layer are formed from independent
+// loads, and the result goes straight to the nodes (OP: OP_AVG_ADD out +=
+// mask v, OP_AVG_STORE out = mask v, OP_AVG_RAW out = v).  Consecutive threads
+// take the layers of one column, so a wave writes runs of whole columns.
+template <int PFT, int PFZ, int PCT, int PCZ, typename T, int OP>
+__global__ __launch_bounds__(256) void k_prolong_node(uint32_t n_col, uint32_t nz, int L,
+                                                      const int32_t* __restrict__ inc_ptr,
+                                                      const int32_t* __restrict__ inc,
+                                                      const uint8_t* __restrict__ dir2d, int top_dir, int nzc,
+                                                      const int32_t* __restrict__ map2d_c,
+                                                      const T* __restrict__ pit, const T* __restrict__ piz,
+                                                      const T* __restrict__ uc, T* __restrict__ out) {
+  constexpr int N1F = PFZ + 1, NPTF = (PFT + 1) * (PFT + 2) / 2;
+  constexpr int N1C = PCZ + 1, NPTC = (PCT + 1) * (PCT + 2) / 2;
+  static_assert(PFT == PCT || PFZ == PCZ, "one factor of the transfer is the identity");
+  __shared__ T sPt[NPTF * NPTC];
+  __shared__ T sPz[N1F * N1C];
+  for (int i = threadIdx.x; i < NPTF * NPTC; i += 256) sPt[i] = pit[i];
+  for (int i = threadIdx.x; i < N1F * N1C; i += 256) sPz[i] = piz[i];
+  __syncthreads();
+  for (uint64_t il = uint64_t(blockIdx.x) * 256 + threadIdx.x; il < n_col; il += uint64_t(gridDim.x) * 256) {
+    const uint32_t item = uint32_t(il), n2 = item / uint32_t(L);
+    const int layer = int(item - n2 * uint32_t(L));
+    const uint32_t id = uint32_t(inc[inc_ptr[n2]]), t = id / NPTF, a = id - t * NPTF;
+    const bool dcol = OP != OP_AVG_RAW && dir2d[n2];
+    const int c0 = layer > 0 ? 1 : 0;
+    T v[N1F];
+    if constexpr (PFZ == PCZ) {
+      // vertical factor the identity: at each level c, sum over the coarse triangle nodes
+      int64_t base[NPTC];
+#pragma unroll
+      for (int b = 0; b < NPTC; ++b) base[b] = int64_t(map2d_c[size_t(t) * NPTC + b]) * nzc + layer * PCZ;
+      T w[NPTC];
+#pragma unroll
+      for (int b = 0; b < NPTC; ++b) w[b] = sPt[a * NPTC + b];
+#pragma unroll
+      for (int c = 0; c < N1F; ++c) {
+        T x[NPTC];
+#pragma unroll
+        for (int b = 0; b < NPTC; ++b) x[b] = uc[base[b] + c];
+        T s = 0;
+#pragma unroll
+        for (int b = 0; b < NPTC; ++b) s += w[b] * x[b];
+        v[c] = s;
+      }
+    } else {
+      // triangle factor the identity: the coarse column of node a, vertical factor
+      const T* col = uc + int64_t(map2d_c[size_t(t) * NPTC + a]) * nzc + layer * PCZ;
+      T x[N1C];
+#pragma unroll
+      for (int cc = 0; cc < N1C; ++cc) x[cc] = col[cc];
+#pragma unroll
+      for (int c = 0; c < N1F; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int cc = 0; cc < N1C; ++cc) s += sPz[c * N1C + cc] * x[cc];
+        v[c] = s;
+      }
+    }
+    T* o = out + size_t(n2) * nz + layer * PFZ;
+#pragma unroll
+    for (int c = 0; c < N1F; ++c) {
+      if (c < c0) continue;
+      if constexpr (OP == OP_AVG_RAW) {
+        o[c] = v[c];
+      } else {
+        const bool dir = dcol || (top_dir && layer == L - 1 && c == PFZ);
+        if constexpr (OP == OP_AVG_ADD) {
+          if (!dir) o[c] += v[c];
+        } else {
+          o[c] = dir ? T(0) : v[c];
+        }
+      }
+    }
+  }
+}
+
+template <typename T>
+bool launch_prolong_node(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* uc, T* out,
+                         int op, hipStream_t st) {
+  if (!(f.P == c.P || f.PZ == c.PZ)) return false;
+  const int64_t n_col = f.n2d * f.L;
+  const int grid = grid_for(n_col);
+#define PMG_PRN(PFT, PFZ, PCT, PCZ)                                                                           \
+  if constexpr (PFT == PCT || PFZ == PCZ) {                                                                    \
+    if (f.P == PFT && f.PZ == PFZ && c.P == PCT && c.PZ == PCZ) {                                              \
+      if (op == OP_AVG_ADD)                                                                                    \
+        hipLaunchKernelGGL((k_prolong_node<PFT, PFZ, PCT, PCZ, T, OP_AVG_ADD>), dim3(grid), dim3(256), 0, st,  \
+                           uint32_t(n_col), uint32_t(f.nz), f.L, f.inc_ptr, f.inc, f.dir2d, f.top_dir,       \
+                           int(c.nz), c.map2d, pit, piz, uc, out);                                             \
+      else if (op == OP_AVG_STORE)                                                                             \
+        hipLaunchKernelGGL((k_prolong_node<PFT, PFZ, PCT, PCZ, T, OP_AVG_STORE>), dim3(grid), dim3(256), 0,    \
+                           st, uint32_t(n_col), uint32_t(f.nz), f.L, f.inc_ptr, f.inc, f.dir2d, f.top_dir,   \
+                           int(c.nz), c.map2d, pit, piz, uc, out);                                             \
+      else if (op == OP_AVG_RAW)                                                                               \
+        hipLaunchKernelGGL((k_prolong_node<PFT, PFZ, PCT, PCZ, T, OP_AVG_RAW>), dim3(grid), dim3(256), 0, st,  \
+                           uint32_t(n_col), uint32_t(f.nz), f.L, f.inc_ptr, f.inc, f.dir2d, f.top_dir,       \
+                           int(c.nz), c.map2d, pit, piz, uc, out);                                             \
+      else                                                                                                     \
+        return false;                                                                                          \
+      return true;                                                                                             \
+    }                                                                                                          \
+  }
+  PMG_PAIRS(PMG_PRN)
+#undef PMG_PRN
+  return false;
+}
+template bool launch_prolong_node<double>(const LevelView&, const LevelView&, const double*, const double*,
+                                          const double*, double*, int, hipStream_t);
+template bool launch_prolong_node<float>(const LevelView&, const LevelView&, const float*, const float*,
+                                         const float*, float*, int, hipStream_t);
+
 template <typename T>
 void launch_restrict_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* rf,
                           T* Yc, hipStream_t st) {

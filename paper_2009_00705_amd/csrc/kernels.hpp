@@ -123,6 +123,12 @@ void launch_prolong_elem(const LevelView& f, const LevelView& c, const T* pit, c
 template <typename T>
 void launch_restrict_elem(const LevelView& f, const LevelView& c, const T* pit, const T* piz,
                           const T* rf, T* Yc, hipStream_t st);
+// Node-wise prolongation straight to the fine nodes (op: OP_AVG_ADD, OP_AVG_STORE
+// or OP_AVG_RAW on the prolongated value) for level pairs where the triangle or
+// the vertical order is kept; returns false, launching nothing, otherwise.
+template <typename T>
+bool launch_prolong_node(const LevelView& f, const LevelView& c, const T* pit, const T* piz, const T* uc, T* out,
+                         int op, hipStream_t st);
 
 // ---- coarse exact solve: y[idx[i]] = sum_j Ainv[i][j] x[idx[j]], y zero elsewhere
 template <typename T>

@@ -756,6 +756,18 @@ static void assemble(pmg_ctx* c, int i, int op, T* out, const T* a1, const T* a2
   launch_assemble<T>(c->lv[i].view, op, reinterpret_cast<const T*>(c->Y), out, a1, a2, a3, w, c1, c->partial, st);
 }
 
+// Prolongation from level i+1 to level i, then op (OP_AVG_ADD, OP_AVG_STORE or
+// OP_AVG_RAW) at the fine nodes: node-wise where one factor of the transfer is
+// the identity, else element-wise with the averaging sum.
+template <typename T>
+static void prolong_add(pmg_ctx* c, int i, const T* uc, T* out, int op, hipStream_t st) {
+  Level& L = c->lv[i];
+  Level& C = c->lv[i + 1];
+  if (launch_prolong_node<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), uc, out, op, st)) return;
+  launch_prolong_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), uc, reinterpret_cast<T*>(c->Y), st);
+  assemble<T>(c, i, op, out, nullptr, nullptr, nullptr, 0, 0, st);
+}
+
 // out (+)= epilogue op of (A x) on level i (see AsmOp): where the level's MFMA
 // operator writes column sums (16 % L == 0), the operator and the node kernel
 // of launch_col_sum; otherwise the element layout and the node-centric sum.
@@ -1499,8 +1511,7 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   launch_restrict_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), r, reinterpret_cast<T*>(c->Y), st);
   assemble<T>(c, i + 1, OP_STORE, C.f<T>(), nullptr, nullptr, nullptr, 0, 0, st);
   vcycle<T>(c, i + 1, C.f<T>(), C.u<T>(), st);
-  launch_prolong_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), C.u<T>(), reinterpret_cast<T*>(c->Y), st);
-  assemble<T>(c, i, OP_AVG_ADD, u, nullptr, nullptr, nullptr, 0, 0, st);
+  prolong_add<T>(c, i, C.u<T>(), u, OP_AVG_ADD, st);
   if (asm_) {
     schwarz_smooth<T>(c, i, f, u, false, true, c->opt.nu2, st);
   } else if (cheb) {
@@ -1661,10 +1672,7 @@ static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const doub
   const float* cur = C.u32;
   for (int i = NL - 1; i >= 0; --i) {
     float* dst = i == 0 ? c->s_z32 : c->lv[i].u32;
-    launch_prolong_elem<float>(c->lv[i].view, c->lv[i + 1].view, c->lv[i].pit32, c->lv[i].piz32, cur,
-                               reinterpret_cast<float*>(c->Y), st);
-    launch_assemble<float>(c->lv[i].view, OP_AVG_RAW, reinterpret_cast<const float*>(c->Y), dst, nullptr, nullptr,
-                           nullptr, 0, 0, nullptr, st);
+    prolong_add<float>(c, i, cur, dst, OP_AVG_RAW, st);
     cur = dst;
   }
   launch_cast<float, double>(c->s_z32, out, 1.0, c->lv[0].num.n_dof, st);
@@ -1930,8 +1938,7 @@ static void transfer_t(pmg_ctx* c, int level, bool prolong, const T* x, T* y, hi
   Level& L = c->lv[level];
   Level& C = c->lv[level + 1];
   if (prolong) {
-    launch_prolong_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), x, reinterpret_cast<T*>(c->Y), st);
-    assemble<T>(c, level, OP_AVG_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
+    prolong_add<T>(c, level, x, y, OP_AVG_STORE, st);
   } else {
     launch_restrict_elem<T>(L.view, C.view, L.pit<T>(), L.piz<T>(), x, reinterpret_cast<T*>(c->Y), st);
     assemble<T>(c, level + 1, OP_STORE, y, nullptr, nullptr, nullptr, 0, 0, st);
@@ -2527,8 +2534,8 @@ int pmg_time_kernel(pmg_ctx* c, int kernel, int level, int precision, int reps, 
           break;
         case PMG_K_PROLONG: {
           Level& C = c->lv[level + 1];
-          if (f64) launch_prolong_elem<double>(L.view, C.view, L.pit64, L.piz64, C.r64, c->Y, st);
-          else launch_prolong_elem<float>(L.view, C.view, L.pit32, L.piz32, C.r32, reinterpret_cast<float*>(c->Y), st);
+          if (f64) prolong_add<double>(c, level, C.r64, c->s_y, OP_AVG_STORE, st);
+          else prolong_add<float>(c, level, C.r32, reinterpret_cast<float*>(c->s_y), OP_AVG_STORE, st);
           break;
         }
         case PMG_K_COPY: launch_copy<double>(L.r64, c->s_y, L.num.n_dof, st); break;
