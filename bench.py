@@ -32,9 +32,9 @@ METRIC = "Laplace solves/s and DOF/s to 1e-8 rel residual at P=6 (mixed/learned 
 
 
 def smoother_kw(a):
-    """Smoother options shared by every workload of one run: the Chebyshev
-    interval [lambda/ratio, lambda] and the summation mode."""
-    kw = {"smooth_ratio": a.smooth_ratio, "fused_sum": 1 if a.fused_sum else 0}
+    """Options shared by every workload of one run: the Chebyshev interval
+    [lambda/ratio, lambda], the summation mode and the V-cycle graphs."""
+    kw = {"smooth_ratio": a.smooth_ratio, "fused_sum": 1 if a.fused_sum else 0, "graphs": 1 if a.graphs else 0}
     return kw
 
 
@@ -599,6 +599,7 @@ def main():
                          "element layout and the node-centric summation")
     ap.add_argument("--smooth-ratio", type=float, default=8.0,
                     help="Chebyshev smoother interval [lambda/ratio, lambda]")
+    ap.add_argument("--graphs", action="store_true", help="replay the solve's V-cycle from a captured HIP graph")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg (c5 history)")
     ap.add_argument("--no-c2", action="store_true", help="skip the FP64 c2 row")
@@ -611,6 +612,10 @@ def main():
         print(json.dumps({"error": "pmg runs on one GPU: --gpus must be 1 "
                           "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
+    import torch
+    # every solve on a side stream of default priority (the library captures
+    # V-cycle graphs, with --graphs, only on a stream of the caller's)
+    torch.cuda.set_stream(torch.cuda.Stream())
     if a.workload == "c5":
         return bench_history(a)
     if a.workload == "scaling":

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PMG_ABI_VERSION 4
+#define PMG_ABI_VERSION 5
 
 enum pmg_status {
   PMG_OK = 0,
@@ -188,6 +188,18 @@ typedef struct pmg_options {
                              the node-centric sum kernel.  Both use no atomics
                              and a fixed order (bitwise reproducible); they
                              differ by rounding                               */
+  int32_t graphs;         /* 1: inside pmg_solve the preconditioner's V-cycle
+                             (its kernels and arguments fixed while the context
+                             is unchanged) is captured once as a HIP graph on
+                             the caller's stream and replayed: the first
+                             V-cycle after a change of the context (surface,
+                             parameters, solver, reuse mode, stream) runs
+                             eagerly, the next is captured.  Results are
+                             bitwise those of the eager V-cycle.  Never on the
+                             null stream.  0 (default): always eager; on the
+                             benchmark meshes the GPU never waits for the
+                             host's launches, so replay gains nothing there,
+                             and each capture costs a V-cycle's launches    */
 } pmg_options;
 
 /* Geometric factors read by the MFMA element operators.  STORED: the six
@@ -238,6 +250,7 @@ typedef struct pmg_stats {
   int32_t fallback;       /* 1 if a learned guess was rejected */
   int32_t n_vcycles;      /* preconditioner applications */
   int32_t n_fine_applies; /* FP64 fine-operator applications */
+  int32_t n_graph_vcycles;/* V-cycles replayed from a captured graph (pmg_options.graphs) */
 } pmg_stats;
 
 /* Fill `opt` with defaults: P=6, nu1=nu2=2, auto omega, FP64, PCG, exact

@@ -205,7 +205,7 @@ struct pmg_ctx {
   bool bf16_ops = false;      // BF16 MFMA operands (PMG_MIXED_BF16) rather than FP32 arithmetic
   bool bf16x3 = false;        // split-BF16 MFMA products (PMG_MIXED_BF16X3)
   bool bf16x2 = false;        // split vectors on BF16 tables (PMG_MIXED_BF16X2)
-  int n_vcycles = 0, n_fine_applies = 0;
+  int n_vcycles = 0, n_fine_applies = 0, n_graph_vcycles = 0;
   // free-surface time stepping: nodal triangle derivatives, top-node column
   // derivative, stage buffers ([eta | phi~] pairs), gradients and w~
   double *fn_Dr = nullptr, *fn_Ds = nullptr, *fn_dtop = nullptr;
@@ -230,7 +230,19 @@ struct pmg_ctx {
     allocs.push_back(p);
     return p;
   }
+  // V-cycle graphs (pmg_options.graphs), one per V-cycle precision (0: FP64, 1: low):
+  // gen counts changes of the context; a graph is valid for the gen, stream and
+  // low-precision mode it was captured at; warm: gen of the last eager V-cycle
+  uint64_t gen = 1;
+  struct VGraph {
+    hipGraphExec_t exec = nullptr;
+    uint64_t gen = 0, warm = 0;
+    hipStream_t st = nullptr;
+    int lowp = -1;
+  } vg[2];
   ~pmg_ctx() {
+    for (auto& g : vg)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
     for (void* p : allocs) (void)hipFree(p);
     if (scal_h) (void)hipHostFree(scal_h);
   }
@@ -1367,6 +1379,7 @@ static int level_geom(pmg_ctx* c, int i, const double* eta, bool lowp, int flavo
 // operator of the outer iteration) always; under LIN also its low-precision
 // copies, diagonals and Schwarz inverses.
 static void set_surface(pmg_ctx* c, const double* eta, hipStream_t st) {
+  c->gen++;  // V-cycle graphs of the previous state are stale
   if (c->reuse == PMG_REUSE_NONE) {
     set_surface_all(c, eta, st);
     return;
@@ -1521,17 +1534,67 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   }
 }
 
-// z = M^-1 r at the finest level in the context's precision (r, z FP64)
+// One finest-level V-cycle of the solve, f -> u, replayed from a captured HIP
+// graph where pmg_options.graphs allows: the kernels and their arguments of a
+// V-cycle depend only on the context's state and the (fixed) vectors, so a
+// graph captured after one eager V-cycle at the current state (lazily built
+// operand copies then exist) reproduces it exactly.  Captures never run on
+// the null stream.
+template <typename T>
+static void solve_vcycle(pmg_ctx* c, const T* f, T* u, hipStream_t st) {
+  pmg_ctx::VGraph& g = c->vg[sizeof(T) == 8 ? 0 : 1];
+  const int lowp = sizeof(T) == 8 ? -1 : c->lowp;
+  if (!c->opt.graphs || st == nullptr) {
+    vcycle<T>(c, 0, f, u, st);
+    return;
+  }
+  if (g.exec && g.gen == c->gen && g.st == st && g.lowp == lowp) {
+    HIPCHK(hipGraphLaunch(g.exec, st));
+    c->n_graph_vcycles++;
+    return;
+  }
+  if (g.warm != c->gen) {
+    vcycle<T>(c, 0, f, u, st);
+    g.warm = c->gen;
+    return;
+  }
+  if (g.exec) {
+    HIPCHK(hipGraphExecDestroy(g.exec));
+    g.exec = nullptr;
+  }
+  hipGraph_t graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  try {
+    vcycle<T>(c, 0, f, u, st);
+  } catch (...) {  // leave the caller's stream out of capture mode
+    hipGraph_t partial = nullptr;
+    (void)hipStreamEndCapture(st, &partial);
+    if (partial) (void)hipGraphDestroy(partial);
+    throw;
+  }
+  HIPCHK(hipStreamEndCapture(st, &graph));
+  const hipError_t e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPCHK(e);
+  g.gen = c->gen;
+  g.st = st;
+  g.lowp = lowp;
+  HIPCHK(hipGraphLaunch(g.exec, st));
+  c->n_graph_vcycles++;
+}
+
+// z = M^-1 r at the finest level in the context's precision (r, z FP64: the
+// solve's own vectors, fixed for the context, so its V-cycle may be a graph)
 static void precond(pmg_ctx* c, const double* r, double* z, hipStream_t st) {
   c->n_vcycles++;
   const int64_t N = c->lv[0].num.n_dof;
   if (c->opt.precision == PMG_FP64) {
-    vcycle<double>(c, 0, r, z, st);
+    solve_vcycle<double>(c, r, z, st);
     return;
   }
   set_lowp(c, c->opt.precision);
   launch_cast<double, float>(r, c->s_r32, 1.0, N, st);
-  vcycle<float>(c, 0, c->s_r32, c->s_z32, st);
+  solve_vcycle<float>(c, c->s_r32, c->s_z32, st);
   launch_cast<float, double>(c->s_z32, z, 1.0, N, st);
 }
 
@@ -1702,6 +1765,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
   HIPCHK(hipEventRecord(ev0, st));
   c->n_vcycles = 0;
   c->n_fine_applies = 0;
+  c->n_graph_vcycles = 0;
   // non-finite boundary data
   launch_count_nonfinite(bc ? bc : surf, bc ? N : F.num.n2d, c->partial, st);
   launch_finalize(c->partial, c->scal, S_TMP1, FIN_SET, st);
@@ -1788,7 +1852,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
         // z = M r with r already in FP32; z stays FP32 (widened where read)
         c->n_vcycles++;
         set_lowp(c, c->opt.precision);
-        vcycle<float>(c, 0, c->s_r32, c->s_z32, st);
+        solve_vcycle<float>(c, c->s_r32, c->s_z32, st);
         launch_dot2(c->s_z32, c->s_r, c->s_q, N, c->partial, st);
         launch_finalize(c->partial, c->scal, 0, kry == PMG_PCG ? FIN_BETA_FR : FIN_BETA_PR, st);
         launch_cg_dir(c->s_p, c->s_z32, c->scal, N, st);
@@ -1840,6 +1904,7 @@ static int solve(pmg_ctx* c, const double* surf, const double* bc, double* phi, 
     stats->t_guess_ms = tg;
     stats->n_vcycles = c->n_vcycles;
     stats->n_fine_applies = c->n_fine_applies;
+    stats->n_graph_vcycles = c->n_graph_vcycles;
     stats->fallback = fallback;
   }
   if (status < 0) throw Error(status, status == PMG_EBREAKDOWN ? "breakdown: p^T A p <= 0 or z^T r <= 0"
@@ -1966,6 +2031,7 @@ void pmg_options_default(pmg_options* o) {
   o->geometry = PMG_GEOM_COLUMN;
   o->PZ = 0;
   o->fused_sum = 0;
+  o->graphs = 0;
 }
 
 int pmg_abi_version(void) { return PMG_ABI_VERSION; }
@@ -2267,6 +2333,7 @@ int pmg_get_params(const pmg_ctx* c, double* omega, double* lmin, double* lmax) 
 
 int pmg_set_params(pmg_ctx* c, const double* omega, double lmin, double lmax) {
   if (!c) return PMG_EINVAL;
+  c->gen++;
   if (omega)
     for (int i = 0; i + 1 < c->nl; ++i) {
       if (!(omega[i] > 0)) return PMG_EINVAL;
@@ -2451,6 +2518,7 @@ int pmg_fnpf_erk4(pmg_ctx* c, double* eta, double* phis, double dt, double g, do
 
 int pmg_set_reuse(pmg_ctx* c, int mode, void* stream) {
   if (!c || mode < PMG_REUSE_NONE || mode > PMG_REUSE_LIN) return PMG_EINVAL;
+  c->gen++;
   PMG_TRY(c, {
     need_device(c);
     hipStream_t st = S(stream);
@@ -2494,6 +2562,7 @@ int pmg_solve(pmg_ctx* c, const double* phi_surf, const double* phi_bc, double* 
 
 int pmg_set_solver(pmg_ctx* c, int precision, int krylov) {
   if (!c || precision < 0 || precision > 5 || krylov < 0 || krylov > 3) return PMG_EINVAL;
+  c->gen++;
   c->opt.precision = precision;
   c->opt.krylov = krylov;
   return PMG_OK;

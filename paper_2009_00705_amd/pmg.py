@@ -54,7 +54,7 @@ class Options(C.Structure):
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
                 ("coarsening", C.c_int32), ("overlap", C.c_int32), ("schwarz_store", C.c_int32),
                 ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32), ("PZ", C.c_int32),
-                ("fused_sum", C.c_int32)]
+                ("fused_sum", C.c_int32), ("graphs", C.c_int32)]
 
 
 class FnpfStats(C.Structure):
@@ -81,14 +81,14 @@ class Stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("n_hist", C.c_int32), ("rel_res", C.c_double),
                 ("norm_f", C.c_double), ("res_hist", C.c_double * 512), ("t_solve_ms", C.c_double),
                 ("t_guess_ms", C.c_double), ("fallback", C.c_int32), ("n_vcycles", C.c_int32),
-                ("n_fine_applies", C.c_int32)]
+                ("n_fine_applies", C.c_int32), ("n_graph_vcycles", C.c_int32)]
 
     def as_dict(self):
         h = np.array(self.res_hist[: self.n_hist])
         return dict(iters=self.iters, rel_res=self.rel_res, norm_f=self.norm_f, res_hist=h,
                     q=h[1:] / h[:-1] if h.size > 1 else np.zeros(0), t_solve_ms=self.t_solve_ms,
                     t_guess_ms=self.t_guess_ms, fallback=self.fallback, n_vcycles=self.n_vcycles,
-                    n_fine_applies=self.n_fine_applies)
+                    n_fine_applies=self.n_fine_applies, n_graph_vcycles=self.n_graph_vcycles)
 
 
 _lib = None

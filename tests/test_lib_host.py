@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
         assert n in pmg.SIGNATURES, f"binding lacks {n}"
-    assert L.pmg_abi_version() == 4
+    assert L.pmg_abi_version() == 5
 
 
 def _host_ctx(mesh, P, **kw):
