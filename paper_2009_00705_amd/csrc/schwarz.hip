@@ -279,7 +279,11 @@ void launch_sd_invert(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t bas
 // application: one workgroup per subdomain.  The local vector x is gathered
 // into LDS; lane l owns rows VR*l .. VR*l+VR-1 and streams the (symmetric)
 // inverse column by column, one 8-byte load per column (VR = 8/sizeof(TI)),
-// so a wave reads 512 contiguous bytes per column.
+// so a wave reads 512 contiguous bytes per column.  When the row vectors fill
+// at most half the workgroup (BF16 inverses: up to 128 vectors = 512 rows), the
+// columns are split in two halves, one per half of the workgroup, and the two
+// partial sums are added in a fixed order through LDS: every thread streams,
+// twice the loads are in flight.
 // ---------------------------------------------------------------------------
 template <typename TI> struct Vec8;
 template <> struct Vec8<double> { typedef double type; static constexpr int VR = 1; };
@@ -298,6 +302,33 @@ __device__ __forceinline__ void unpack(const uint2& v, T* o) {
   o[3] = __uint_as_float(v.y & 0xFFFF0000u);
 }
 
+// acc[0..VR) += sum over columns j in [j0, j1) of A[j][rows of vector l] x[j]
+template <typename T, typename V, int VR>
+__device__ __forceinline__ void sd_columns(const V* __restrict__ Ak, int mv, int l, int j0, int j1,
+                                           const T* __restrict__ sx, T (&acc)[VR]) {
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+    V a[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) a[h] = Ak[size_t(j + h) * mv + l];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+      T e[VR];
+      unpack<T>(a[h], e);
+      const T x = sx[j + h];
+#pragma unroll
+      for (int v = 0; v < VR; ++v) acc[v] += e[v] * x;
+    }
+  }
+  for (; j < j1; ++j) {
+    T e[VR];
+    unpack<T>(Ak[size_t(j) * mv + l], e);
+    const T x = sx[j];
+#pragma unroll
+    for (int v = 0; v < VR; ++v) acc[v] += e[v] * x;
+  }
+}
+
 template <typename T, typename TI>
 __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, const int32_t* __restrict__ sd_ptr,
                                                   const int32_t* __restrict__ sd_node,
@@ -309,6 +340,7 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, const int32_t* 
   constexpr int VR = Vec8<TI>::VR;
   extern __shared__ unsigned char smraw[];
   T* sx = reinterpret_cast<T*>(smraw);
+  __shared__ T spart[128 * VR];  // second half's partial sums (split columns)
   const int tid = threadIdx.x;
   for (int64_t k = blockIdx.x; k < n_sub; k += gridDim.x) {
     const int32_t b = sd_ptr[k];
@@ -322,34 +354,33 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, const int32_t* 
     const V* Ak = reinterpret_cast<const V*>(inv + inv_off[k]);
     const int mv = m / VR;        // vectors per column
     const int nv = (n + VR - 1) / VR;
-    for (int l = tid; l < nv; l += 256) {
+    if (nv <= 128) {
+      // split columns: threads 0..127 take [0, n/2), threads 128..255 take [n/2, n)
+      const int half = tid >> 7, l = tid & 127, jm = n >> 1;
       T acc[VR];
 #pragma unroll
       for (int v = 0; v < VR; ++v) acc[v] = T(0);
-      int j = 0;
-      for (; j + 4 <= n; j += 4) {
-        V a[4];
+      if (l < nv) sd_columns<T, V, VR>(Ak, mv, l, half ? jm : 0, half ? n : jm, sx, acc);
+      if (half && l < nv) {
 #pragma unroll
-        for (int h = 0; h < 4; ++h) a[h] = Ak[size_t(j + h) * mv + l];
-#pragma unroll
-        for (int h = 0; h < 4; ++h) {
-          T e[VR];
-          unpack<T>(a[h], e);
-          const T x = sx[j + h];
-#pragma unroll
-          for (int v = 0; v < VR; ++v) acc[v] += e[v] * x;
-        }
+        for (int v = 0; v < VR; ++v) spart[l * VR + v] = acc[v];
       }
-      for (; j < n; ++j) {
-        T e[VR];
-        unpack<T>(Ak[size_t(j) * mv + l], e);
-        const T x = sx[j];
+      __syncthreads();
+      if (!half && l < nv) {
 #pragma unroll
-        for (int v = 0; v < VR; ++v) acc[v] += e[v] * x;
+        for (int v = 0; v < VR; ++v)
+          if (VR * l + v < n) zS[b + VR * l + v] = acc[v] + spart[l * VR + v];
       }
+    } else {
+      for (int l = tid; l < nv; l += 256) {
+        T acc[VR];
 #pragma unroll
-      for (int v = 0; v < VR; ++v)
-        if (VR * l + v < n) zS[b + VR * l + v] = acc[v];
+        for (int v = 0; v < VR; ++v) acc[v] = T(0);
+        sd_columns<T, V, VR>(Ak, mv, l, 0, n, sx, acc);
+#pragma unroll
+        for (int v = 0; v < VR; ++v)
+          if (VR * l + v < n) zS[b + VR * l + v] = acc[v];
+      }
     }
   }
 }
