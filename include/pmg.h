@@ -162,7 +162,7 @@ typedef struct pmg_options {
   int32_t schwarz_store;  /* Schwarz local inverses kept: bit 0 FP64, bit 1 FP32,
                              bit 2 BF16 (0: all three).  A smoothing step in a
                              precision whose copy is not kept fails with EINVAL.
-                             Without FP64 the set-up works in FP64 chunks of
+                             The set-up works in FP64 chunks of
                              schwarz_chunk entries                             */
   int64_t schwarz_chunk;  /* entries of an FP64 set-up chunk; <= 0: 2^29 (4 GiB) */
   int32_t geometry;       /* pmg_geometry of the MFMA element operators          */
@@ -347,7 +347,8 @@ int pmg_solve(pmg_ctx* ctx, const double* phi_surf, const double* phi_bc, double
  * host-only contexts too).  dt, dz: overlap in lattice steps in the triangle
  * and along the extrusion; n_sub: subdomains (one per prism); max_size:
  * largest subdomain; total: sum of the subdomain sizes; inv_entries: entries
- * of the padded local inverses (each size rounded up to a multiple of 4).
+ * of the kept local inverses in one precision (each stored as the 32 x 32
+ * tiles of its upper block triangle, ceil(n/32) (ceil(n/32) + 1) / 2 tiles).
  * EINVAL when the smoother is not PMG_SMOOTH_SCHWARZ or the level is the
  * coarsest. */
 typedef struct pmg_schwarz_info {

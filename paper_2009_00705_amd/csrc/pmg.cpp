@@ -593,6 +593,7 @@ static void upload_levels(pmg_ctx* c) {
       v.sd_node = c->U(P.sd_node);
       v.msz = c->U(P.msz);
       v.inv_off = c->U(P.inv_off);
+      v.tile_off = c->U(P.tile_off);
       v.blk_ptr = c->U(P.blk_ptr);
       v.blk_elem = c->U(P.blk_elem);
       v.blk_ent = c->U(P.blk_ent);
@@ -601,8 +602,16 @@ static void upload_levels(pmg_ctx* c) {
       v.node_pos = c->U(P.node_pos);
       L.sz_w64 = c->U(P.w);
       L.sz_w32 = c->U(to_f32(P.w));
-      const size_t ninv = size_t(P.inv_off.back());
+      const size_t ninv = size_t(P.tile_off.back());
       const int keep = c->opt.schwarz_store == 0 ? 7 : c->opt.schwarz_store;
+      int lds_max = 0;
+      HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
+      const size_t lds = std::max({(keep & 1) ? sd_apply_lds(P.max_n, 8, 8) : size_t(0),
+                                   (keep & 2) ? sd_apply_lds(P.max_n, 4, 4) : size_t(0),
+                                   (keep & 4) ? sd_apply_lds(P.max_n, 4, 2) : size_t(0)});
+      if (lds > size_t(lds_max))
+        throw Error(PMG_EINVAL, "Schwarz subdomains too large for the local solve (" + std::to_string(P.max_n) +
+                                    " nodes)");
       if (keep & 1) L.sz_inv64 = c->A<double>(ninv);
       if (keep & 2) L.sz_inv32 = c->A<float>(ninv);
       if (keep & 4) L.sz_inv16 = c->A<bf16_t>(ninv);
@@ -1296,9 +1305,9 @@ static void coarse_exact_setup(pmg_ctx* c, hipStream_t st) {
 // current geometry, inverted in place (FP64), with FP32 / BF16 copies.  The
 // element matrices live in a scratch buffer freed afterwards.
 // ---------------------------------------------------------------------------
-// When the FP64 copy is kept the blocks are built in place; otherwise they are
-// built in FP64 in chunks of at most options.schwarz_chunk entries (one block
-// at least) and converted.
+// The blocks are built and inverted in FP64 in chunks of at most
+// options.schwarz_chunk entries (one block at least), then written to the kept
+// copies as packed tiles.
 static void schwarz_setup(pmg_ctx* c, hipStream_t st, int i0 = 0) {
   for (int i = i0; i + 1 < c->nl; ++i) {
     Level& L = c->lv[i];
@@ -1312,7 +1321,7 @@ static void schwarz_setup(pmg_ctx* c, hipStream_t st, int i0 = 0) {
     const int64_t chunk = c->opt.schwarz_chunk > 0 ? c->opt.schwarz_chunk : (int64_t(1) << 29);
     int64_t blk_max = 0;
     for (int64_t k = 0; k < E; ++k) blk_max = std::max(blk_max, off[k + 1] - off[k]);
-    if (!L.sz_inv64) {
+    {
       const int64_t nw = std::min<int64_t>(off.back(), std::max<int64_t>(chunk, blk_max));
       if (hipMalloc((void**)&W, size_t(nw) * sizeof(double)) != hipSuccess) {
         (void)hipFree(K);
@@ -1323,13 +1332,10 @@ static void schwarz_setup(pmg_ctx* c, hipStream_t st, int i0 = 0) {
     launch_elem_mats(L.view, L.mats64, L.G64, K, st);
     for (int64_t k0 = 0; k0 < E;) {
       int64_t k1 = k0 + 1;
-      if (L.sz_inv64) k1 = E;
-      else
-        while (k1 < E && off[k1 + 1] - off[k0] <= chunk) ++k1;
-      double* work = L.sz_inv64 ? L.sz_inv64 : W;
-      const int64_t base = L.sz_inv64 ? 0 : off[k0];
-      launch_sd_assemble(L.szv, k0, k1, base, L.re->np, K, work, st);
-      launch_sd_invert(L.szv, k0, k1, base, work, L.sz_inv64, L.sz_inv32, L.sz_inv16, c->bad, st);
+      while (k1 < E && off[k1 + 1] - off[k0] <= chunk) ++k1;
+      const int64_t base = off[k0];
+      launch_sd_assemble(L.szv, k0, k1, base, L.re->np, K, W, st);
+      launch_sd_invert(L.szv, k0, k1, base, W, L.sz_inv64, L.sz_inv32, L.sz_inv16, c->bad, st);
       k0 = k1;
     }
     int bad = 0;
@@ -2295,7 +2301,7 @@ int pmg_schwarz_info_get(const pmg_ctx* c, int level, pmg_schwarz_info* info) {
     info->n_sub = L.sz.n_sub;
     info->max_size = L.sz.max_n;
     info->total = L.sz.total;
-    info->inv_entries = L.sz.inv_off.back();
+    info->inv_entries = L.sz.tile_off.back();
   });
   return PMG_OK;
 }

@@ -234,36 +234,30 @@ __global__ __launch_bounds__(256) void k_sd_invert(int64_t k0, int64_t k1, int64
   }
 }
 
-// (A + A^T)/2 on the n x n block, written to the kept copies of the whole
-// padded block (FP64 may be the work block itself)
+// (A + A^T)/2 on the n x n block, written as the packed upper block-triangle
+// tiles of the kept copies (zero outside n x n)
 __global__ __launch_bounds__(256) void k_sd_symm(int64_t k0, int64_t k1, int64_t base,
                                                  const int32_t* __restrict__ sd_ptr,
                                                  const int32_t* __restrict__ msz,
-                                                 const int64_t* __restrict__ inv_off, double* A, double* A64,
-                                                 float* __restrict__ A32, bf16_t* __restrict__ A16) {
+                                                 const int64_t* __restrict__ inv_off,
+                                                 const int64_t* __restrict__ tile_off, const double* __restrict__ A,
+                                                 double* __restrict__ A64, float* __restrict__ A32,
+                                                 bf16_t* __restrict__ A16) {
   for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
     const int m = msz[k], n = sd_ptr[k + 1] - sd_ptr[k];
-    const int64_t off = inv_off[k];
-    double* Ak = A + (off - base);
-    __syncthreads();
-    for (int idx = threadIdx.x; idx < m * m; idx += 256) {
-      const int i = idx / m, j = idx - i * m;
-      if (j < i) continue;
-      double v = Ak[size_t(i) * m + j];
-      if (j < n) v = 0.5 * (v + Ak[size_t(j) * m + i]);
-      if (A64) {
-        A64[off + size_t(i) * m + j] = v;
-        A64[off + size_t(j) * m + i] = v;
-      }
-      if (A32) {
-        A32[off + size_t(i) * m + j] = float(v);
-        A32[off + size_t(j) * m + i] = float(v);
-      }
-      if (A16) {
-        A16[off + size_t(i) * m + j] = sz_f32_to_bf16(float(v));
-        A16[off + size_t(j) * m + i] = sz_f32_to_bf16(float(v));
-      }
-    }
+    const int nt = (n + SZ_TS - 1) / SZ_TS;
+    const double* Ak = A + (inv_off[k] - base);
+    int64_t off = tile_off[k];
+    for (int J = 0; J < nt; ++J)
+      for (int I = 0; I <= J; ++I, off += SZ_TS * SZ_TS)
+        for (int e = threadIdx.x; e < SZ_TS * SZ_TS; e += 256) {
+          const int i = I * SZ_TS + (e / SZ_TS), j = J * SZ_TS + (e % SZ_TS);
+          const int lo = i < j ? i : j, hi = i < j ? j : i;
+          const double v = hi < n ? 0.5 * (Ak[size_t(lo) * m + hi] + Ak[size_t(hi) * m + lo]) : 0.0;
+          if (A64) A64[off + e] = v;
+          if (A32) A32[off + e] = float(v);
+          if (A16) A16[off + e] = sz_f32_to_bf16(float(v));
+        }
   }
 }
 
@@ -272,123 +266,192 @@ void launch_sd_invert(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t bas
   hipLaunchKernelGGL(k_sd_invert, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.sd_ptr, sv.msz,
                      sv.inv_off, A, bad);
   hipLaunchKernelGGL(k_sd_symm, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.sd_ptr, sv.msz,
-                     sv.inv_off, A, A64, A32, A16);
+                     sv.inv_off, sv.tile_off, A, A64, A32, A16);
 }
 
 // ---------------------------------------------------------------------------
-// application: one workgroup per subdomain.  The local vector x is gathered
-// into LDS; lane l owns rows VR*l .. VR*l+VR-1 and streams the (symmetric)
-// inverse column by column, one 8-byte load per column (VR = 8/sizeof(TI)),
-// so a wave reads 512 contiguous bytes per column.  When the row vectors fill
-// at most half the workgroup (BF16 inverses: up to 128 vectors = 512 rows), the
-// columns are split in two halves, one per half of the workgroup, and the two
-// partial sums are added in a fixed order through LDS: every thread streams,
-// twice the loads are in flight.
+// application: one workgroup per subdomain, z = inv x with inv stored as the
+// tiles (I, J), I <= J, of its upper block triangle.  A tile off the diagonal
+// serves twice: z_I += A_IJ x_J (row pass) and z_J += A_IJ^T x_I (column
+// pass); a diagonal tile (stored whole) only in the row pass.  Each wave takes
+// a contiguous run of the tiles in their storage order (J-major), so x_J sits
+// in registers and z_J accumulates in registers until the column ends.  A tile
+// is read from HBM once, with 16-byte loads (the next tile's are issued before
+// the current one is used), and staged in the wave's own LDS slice (rows
+// padded by 16 bytes: both passes read it without bank conflicts).  Lane l
+// takes row l mod 32 over the column half l / 32 in the row pass and column
+// l mod 32 over the row half l / 32 in the column pass; one cross-half
+// exchange completes both sums.  z_I goes to the wave's own LDS accumulator;
+// the four accumulators are added in a fixed order at the end.
 // ---------------------------------------------------------------------------
-template <typename TI> struct Vec8;
-template <> struct Vec8<double> { typedef double type; static constexpr int VR = 1; };
-template <> struct Vec8<float> { typedef float2 type; static constexpr int VR = 2; };
-template <> struct Vec8<bf16_t> { typedef uint2 type; static constexpr int VR = 4; };
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-template <typename T>
-__device__ __forceinline__ void unpack(const double& v, T* o) { o[0] = T(v); }
-template <typename T>
-__device__ __forceinline__ void unpack(const float2& v, T* o) { o[0] = v.x; o[1] = v.y; }
-template <typename T>
-__device__ __forceinline__ void unpack(const uint2& v, T* o) {
-  o[0] = __uint_as_float(v.x << 16);
-  o[1] = __uint_as_float(v.x & 0xFFFF0000u);
-  o[2] = __uint_as_float(v.y << 16);
-  o[3] = __uint_as_float(v.y & 0xFFFF0000u);
-}
-
-// acc[0..VR) += sum over columns j in [j0, j1) of A[j][rows of vector l] x[j]
-template <typename T, typename V, int VR>
-__device__ __forceinline__ void sd_columns(const V* __restrict__ Ak, int mv, int l, int j0, int j1,
-                                           const T* __restrict__ sx, T (&acc)[VR]) {
-  int j = j0;
-  for (; j + 4 <= j1; j += 4) {
-    V a[4];
+// Entries of a staged tile: get(p, i) one entry, row(p, o) the 16 entries at
+// p (16-byte aligned) read as 16-byte words.
+template <typename TI> struct TileT;
+template <> struct TileT<double> {
+  static __device__ __forceinline__ double get(const double* p, int i) { return p[i]; }
+  static __device__ __forceinline__ void row(const double* p, double (&o)[16]) {
+    const u32x4* q = reinterpret_cast<const u32x4*>(p);
 #pragma unroll
-    for (int h = 0; h < 4; ++h) a[h] = Ak[size_t(j + h) * mv + l];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      T e[VR];
-      unpack<T>(a[h], e);
-      const T x = sx[j + h];
-#pragma unroll
-      for (int v = 0; v < VR; ++v) acc[v] += e[v] * x;
+    for (int h = 0; h < 8; ++h) {
+      const u32x4 v = q[h];
+      o[2 * h] = __hiloint2double(int(v.y), int(v.x));
+      o[2 * h + 1] = __hiloint2double(int(v.w), int(v.z));
     }
   }
-  for (; j < j1; ++j) {
-    T e[VR];
-    unpack<T>(Ak[size_t(j) * mv + l], e);
-    const T x = sx[j];
+};
+template <> struct TileT<float> {
+  static __device__ __forceinline__ float get(const float* p, int i) { return p[i]; }
+  static __device__ __forceinline__ void row(const float* p, float (&o)[16]) {
+    const u32x4* q = reinterpret_cast<const u32x4*>(p);
 #pragma unroll
-    for (int v = 0; v < VR; ++v) acc[v] += e[v] * x;
+    for (int h = 0; h < 4; ++h) {
+      const u32x4 v = q[h];
+      o[4 * h] = __uint_as_float(v.x);
+      o[4 * h + 1] = __uint_as_float(v.y);
+      o[4 * h + 2] = __uint_as_float(v.z);
+      o[4 * h + 3] = __uint_as_float(v.w);
+    }
   }
+};
+template <> struct TileT<bf16_t> {
+  static __device__ __forceinline__ float get(const bf16_t* p, int i) { return __uint_as_float(uint32_t(p[i]) << 16); }
+  static __device__ __forceinline__ void row(const bf16_t* p, float (&o)[16]) {
+    const u32x4* q = reinterpret_cast<const u32x4*>(p);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const u32x4 v = q[h];
+      const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        o[8 * h + 2 * c] = __uint_as_float(wd[c] << 16);
+        o[8 * h + 2 * c + 1] = __uint_as_float(wd[c] & 0xFFFF0000u);
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 template <typename T, typename TI>
-__global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, const int32_t* __restrict__ sd_ptr,
+__global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const int32_t* __restrict__ sd_ptr,
                                                   const int32_t* __restrict__ sd_node,
-                                                  const int32_t* __restrict__ msz,
-                                                  const int64_t* __restrict__ inv_off, const TI* __restrict__ inv,
+                                                  const int64_t* __restrict__ tile_off, const TI* __restrict__ inv,
                                                   const T* __restrict__ r, const T* __restrict__ w,
                                                   T* __restrict__ zS) {
-  typedef typename Vec8<TI>::type V;
-  constexpr int VR = Vec8<TI>::VR;
-  extern __shared__ unsigned char smraw[];
-  T* sx = reinterpret_cast<T*>(smraw);
-  __shared__ T spart[128 * VR];  // second half's partial sums (split columns)
-  const int tid = threadIdx.x;
+  constexpr int TS = SZ_TS;
+  constexpr int EC = 16 / int(sizeof(TI));   // entries per 16-byte chunk
+  constexpr int NCH = int(sizeof(TI));       // 16-byte chunks per lane and tile (TS*TS/64 entries)
+  constexpr int RS = TS + EC;                // padded LDS row (entries)
+  static_assert(TS * TS * int(sizeof(TI)) == 64 * 16 * NCH, "tile = 64 lanes x NCH chunks");
+  extern __shared__ __align__(16) unsigned char smraw[];
+  T* sx = reinterpret_cast<T*>(smraw);                       // [ntm*TS]
+  T* zacc = sx + size_t(ntm) * TS;                           // [4][ntm*TS]
+  TI* stile = reinterpret_cast<TI*>(zacc + 4 * size_t(ntm) * TS);  // [4][TS*RS]
+  const int tid = threadIdx.x, l = tid & 63, lr = l & 31, lh = l >> 5;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: the tile loop is scalar
+  T* zw = zacc + size_t(wv) * ntm * TS;
+  TI* st = stile + wv * TS * RS;
   for (int64_t k = blockIdx.x; k < n_sub; k += gridDim.x) {
     const int32_t b = sd_ptr[k];
-    const int n = sd_ptr[k + 1] - b, m = msz[k];
+    const int n = sd_ptr[k + 1] - b, nt = (n + TS - 1) / TS, np = nt * TS;
     __syncthreads();
-    for (int j = tid; j < n; j += 256) {
-      const int32_t g = sd_node[b + j];
-      sx[j] = w ? r[g] * w[g] : r[g];
+    for (int j = tid; j < np; j += 256) {
+      T x = T(0);
+      if (j < n) {
+        const int32_t g = sd_node[b + j];
+        x = w ? r[g] * w[g] : r[g];
+      }
+      sx[j] = x;
+    }
+    for (int j = tid; j < 4 * np; j += 256) zacc[(j / np) * ntm * TS + j % np] = T(0);
+    __syncthreads();
+    const int ntl = nt * (nt + 1) / 2;
+    const int t0 = ntl * wv / 4, t1 = ntl * (wv + 1) / 4;
+    if (t0 < t1) {
+      const u32x4* At = reinterpret_cast<const u32x4*>(inv + tile_off[k]);
+      int J = 0;
+      while ((J + 1) * (J + 2) / 2 <= t0) ++J;
+      int I = t0 - J * (J + 1) / 2;
+      u32x4 a[NCH];
+#pragma unroll
+      for (int h = 0; h < NCH; ++h) a[h] = At[size_t(t0) * 64 * NCH + h * 64 + l];
+      T xj[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) xj[i] = sx[J * TS + lh * 16 + i];
+      T zj = T(0);
+      for (int t = t0; t < t1; ++t) {
+        wave_sync();
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) {
+          const int e = (h * 64 + l) * EC;  // first entry of the chunk
+          *reinterpret_cast<u32x4*>(st + (e / TS) * RS + e % TS) = a[h];
+        }
+        if (t + 1 < t1) {
+#pragma unroll
+          for (int h = 0; h < NCH; ++h) a[h] = At[size_t(t + 1) * 64 * NCH + h * 64 + l];
+        }
+        wave_sync();
+        // row pass: row lr, columns lh*16 .. lh*16+15
+        T pr = T(0);
+        {
+          T e[16];
+          TileT<TI>::row(st + lr * RS + lh * 16, e);
+#pragma unroll
+          for (int i = 0; i < 16; ++i) pr += e[i] * xj[i];
+        }
+        const bool diag = I == J;
+        T pc = T(0);
+        if (!diag) {
+          // column pass: column lr, rows lh*16 .. lh*16+15
+          const TI* col = st + lh * 16 * RS + lr;
+          const T* xi = sx + I * TS + lh * 16;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) pc += T(TileT<TI>::get(col, i * RS)) * xi[i];
+        }
+        // lanes < 32 complete row sums, lanes >= 32 column sums
+        const T o = __shfl_xor((lh == 0 && !diag) ? pc : pr, 32);
+        // at the diagonal the upper lanes hand over the column's z_J (same rows)
+        const T oz = diag ? __shfl_xor(zj, 32) : T(0);
+        if (lh == 0) {
+          zw[I * TS + lr] += (pr + o) + oz;
+        } else if (!diag) {
+          zj += pc + o;
+        }
+        if (diag) {
+          // next column
+          ++J;
+          I = 0;
+          zj = T(0);
+          if (t + 1 < t1) {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) xj[i] = sx[J * TS + lh * 16 + i];
+          }
+        } else {
+          ++I;
+        }
+      }
+      // run ended inside a column: flush the upper lanes' z_J
+      if (I != 0 && lh == 1) zw[J * TS + lr] += zj;
     }
     __syncthreads();
-    const V* Ak = reinterpret_cast<const V*>(inv + inv_off[k]);
-    const int mv = m / VR;        // vectors per column
-    const int nv = (n + VR - 1) / VR;
-    if (nv <= 128) {
-      // split columns: threads 0..127 take [0, n/2), threads 128..255 take [n/2, n)
-      const int half = tid >> 7, l = tid & 127, jm = n >> 1;
-      T acc[VR];
-#pragma unroll
-      for (int v = 0; v < VR; ++v) acc[v] = T(0);
-      if (l < nv) sd_columns<T, V, VR>(Ak, mv, l, half ? jm : 0, half ? n : jm, sx, acc);
-      if (half && l < nv) {
-#pragma unroll
-        for (int v = 0; v < VR; ++v) spart[l * VR + v] = acc[v];
-      }
-      __syncthreads();
-      if (!half && l < nv) {
-#pragma unroll
-        for (int v = 0; v < VR; ++v)
-          if (VR * l + v < n) zS[b + VR * l + v] = acc[v] + spart[l * VR + v];
-      }
-    } else {
-      for (int l = tid; l < nv; l += 256) {
-        T acc[VR];
-#pragma unroll
-        for (int v = 0; v < VR; ++v) acc[v] = T(0);
-        sd_columns<T, V, VR>(Ak, mv, l, 0, n, sx, acc);
-#pragma unroll
-        for (int v = 0; v < VR; ++v)
-          if (VR * l + v < n) zS[b + VR * l + v] = acc[v];
-      }
+    for (int i = tid; i < n; i += 256) {
+      const size_t q = size_t(ntm) * TS;
+      zS[b + i] = ((zacc[i] + zacc[q + i]) + zacc[2 * q + i]) + zacc[3 * q + i];
     }
   }
 }
 
 template <typename T, typename TI>
 void launch_sd_apply(const SchwarzView& sv, const TI* inv, const T* r, const T* w, T* zS, hipStream_t st) {
-  hipLaunchKernelGGL((k_sd_apply<T, TI>), dim3(grid_of(sv.n_sub)), dim3(256), sizeof(T) * size_t(sv.max_m), st,
-                     sv.n_sub, sv.sd_ptr, sv.sd_node, sv.msz, sv.inv_off, inv, r, w, zS);
+  const int ntm = (sv.max_n + SZ_TS - 1) / SZ_TS;
+  hipLaunchKernelGGL((k_sd_apply<T, TI>), dim3(grid_of(sv.n_sub)), dim3(256), sd_apply_lds(sv.max_n, sizeof(T), sizeof(TI)), st,
+                     sv.n_sub, ntm, sv.sd_ptr, sv.sd_node, sv.tile_off, inv, r, w, zS);
 }
 
 template <typename T>

@@ -18,6 +18,24 @@
 
 namespace pmg {
 
+// The kept local inverses are symmetric: each is stored as the SZ_TS x SZ_TS
+// tiles (I, J), I <= J, of its upper block triangle, tile J(J+1)/2 + I at
+// SZ_TS^2 (J(J+1)/2 + I), row-major inside the tile; entries past the
+// subdomain size are zero.  About 57% of the full square at the sizes of the
+// c3 finest level (428 nodes on average).
+constexpr int SZ_TS = 32;
+inline int64_t sz_tiles(int n) {
+  const int64_t t = (n + SZ_TS - 1) / SZ_TS;
+  return t * (t + 1) / 2 * SZ_TS * SZ_TS;
+}
+
+// LDS bytes of the local solve on subdomains of up to max_n nodes, for
+// compute values of ts bytes and stored entries of tis bytes.
+inline size_t sd_apply_lds(int max_n, size_t ts, size_t tis) {
+  const size_t ntm = size_t(max_n + SZ_TS - 1) / SZ_TS;
+  return ts * 5 * ntm * SZ_TS + 4 * tis * SZ_TS * (SZ_TS + 16 / tis);
+}
+
 // Host plan of one level's subdomains.
 struct SchwarzPlan {
   int dt = 0, dz = 0;
@@ -27,7 +45,8 @@ struct SchwarzPlan {
   std::vector<int32_t> sd_ptr;   // [n_sub+1] into sd_node
   std::vector<int32_t> sd_node;  // sorted free global nodes of every subdomain
   std::vector<int32_t> msz;      // padded size of every local matrix (multiple of 4)
-  std::vector<int64_t> inv_off;  // [n_sub+1] entry offsets of the padded msz x msz blocks
+  std::vector<int64_t> inv_off;  // [n_sub+1] entry offsets of the padded msz x msz blocks (set-up work)
+  std::vector<int64_t> tile_off; // [n_sub+1] entry offsets of the kept inverses (packed tiles, sz_tiles)
   std::vector<int32_t> blk_ptr;  // [n_sub+1] element blocks of every subdomain
   std::vector<int32_t> blk_elem; // prism of every block
   std::vector<int32_t> blk_ent;  // [n_blk+1] into ent
@@ -47,7 +66,7 @@ struct SchwarzView {
   int64_t n_sub = 0;
   int max_n = 0, max_m = 0;
   const int32_t *sd_ptr = nullptr, *sd_node = nullptr, *msz = nullptr;
-  const int64_t* inv_off = nullptr;
+  const int64_t *inv_off = nullptr, *tile_off = nullptr;
   const int32_t *blk_ptr = nullptr, *blk_elem = nullptr, *blk_ent = nullptr, *ent = nullptr;
   const int32_t *node_ptr = nullptr, *node_pos = nullptr;
 };
@@ -59,12 +78,13 @@ void launch_elem_mats(const LevelView& lv, const double* mats, const double* G64
 void launch_sd_assemble(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t base, int np, const double* K,
                         double* A, hipStream_t st);
 // In-place inversion of the work blocks k in [k0, k1) (blocked Gauss-Jordan,
-// no pivoting: the blocks are SPD), then (A + A^T)/2 written to the kept
-// copies A64 / A32 / A16 (nullable; at inv_off[k]; A64 may be A with base 0).
-// *bad is set when a pivot is not positive.
+// no pivoting: the blocks are SPD), then (A + A^T)/2 written as packed tiles
+// to the kept copies A64 / A32 / A16 (nullable; at tile_off[k]).  *bad is set
+// when a pivot is not positive.
 void launch_sd_invert(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t base, double* A, double* A64,
                       float* A32, bf16_t* A16, int* bad, hipStream_t st);
-// zS[sd_ptr[k] + i] = sum_j inv_k[i][j] x_j, x_j = r[node_j] (times w[node_j] when w is given).
+// zS[sd_ptr[k] + i] = sum_j inv_k[i][j] x_j, x_j = r[node_j] (times w[node_j] when w is given),
+// inv_k the packed tiles at tile_off[k].
 template <typename T, typename TI>
 void launch_sd_apply(const SchwarzView& sv, const TI* inv, const T* r, const T* w, T* zS, hipStream_t st);
 // x *= s (n entries).

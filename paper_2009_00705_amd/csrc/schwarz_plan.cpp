@@ -146,6 +146,7 @@ void build_schwarz(const MeshIn& m, const Numbering& num, const std::vector<uint
   o.sd_ptr.assign(size_t(E) + 1, 0);
   o.msz.assign(size_t(E), 0);
   o.inv_off.assign(size_t(E) + 1, 0);
+  o.tile_off.assign(size_t(E) + 1, 0);
   o.blk_ptr.assign(size_t(E) + 1, 0);
   int64_t tot = 0, nblk = 0, nent = 0;
   for (int64_t k = 0; k < E; ++k) {
@@ -161,6 +162,7 @@ void build_schwarz(const MeshIn& m, const Numbering& num, const std::vector<uint
     const int ms = (n + 3) & ~3;
     o.msz[size_t(k)] = ms;
     o.inv_off[size_t(k) + 1] = o.inv_off[size_t(k)] + int64_t(ms) * ms;
+    o.tile_off[size_t(k) + 1] = o.tile_off[size_t(k)] + sz_tiles(n);
     o.blk_ptr[size_t(k) + 1] = int32_t(nblk);
   }
   o.total = tot;

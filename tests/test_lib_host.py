@@ -152,7 +152,8 @@ def test_schwarz_subdomains_bit_exact(meshname, P, coarsening, overlap, tags, to
         assert (info["dt"], info["dz"]) == (dt, dz) and info["n_sub"] == num.n_elem
         assert info["max_size"] == max(w.size for w in want)
         assert info["total"] == sum(w.size for w in want)
-        assert info["inv_entries"] == sum(((w.size + 3) // 4 * 4) ** 2 for w in want)
+        nt = [(w.size + 31) // 32 for w in want]
+        assert info["inv_entries"] == sum(t * (t + 1) // 2 * 1024 for t in nt)
         assert len(got) == len(want)
         for e in range(num.n_elem):
             np.testing.assert_array_equal(got[e], want[e].astype(np.int32), err_msg=f"level {lvl} element {e}")
