@@ -3,6 +3,8 @@
 // (batched dense matrix-vector product, node-centric weighted sum).
 #include "schwarz.hpp"
 
+#include <stdexcept>
+
 namespace pmg {
 
 namespace {
@@ -15,20 +17,31 @@ __device__ __forceinline__ bf16_t sz_f32_to_bf16(float f) {
 
 int grid_of(int64_t n) { return int(n < 65536 ? (n < 1 ? 1 : n) : 65536); }
 
+// orders this wave's LDS accesses (no workgroup barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
 // element matrices: K[i][j] = sum_q sum_ab D_a(q, i) G_ab(q) D_b(q, j), the
-// reference gradients of the prism basis being products of the triangle
-// tables (Dr, Ds, B at the triangle points) and the vertical ones (Bz, Dz).
-// Upper triangle computed, mirrored.
+// reference gradients of the prism basis being products of triangle tables
+// (Dr, Ds, Bt at the triangle points) and vertical ones (Bz, Dz): x = Dr Bz,
+// y = Ds Bz, z = Bt Dz.  Sum-factorised: one thread per triangle-node pair
+// (ai <= aj) of one element forms, per vertical point k, the four in-plane
+// sums S_BB, S_BD, S_DB, S_DD over the triangle points and spreads them to
+// every vertical pair (ci, cj) through Bz / Dz.  Exactly symmetric output.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_elem_mats(int64_t n_elem, int npt, int nqt, int n1, int tab_lds,
+template <int N1>
+__global__ __launch_bounds__(256) void k_elem_mats(int64_t n_elem, int npt, int nqt, int epb, int tab_lds,
                                                    const double* __restrict__ mats, const double* __restrict__ G,
                                                    double* __restrict__ K) {
   extern __shared__ double sm[];
-  const int nq = nqt * n1, np = npt * n1;
-  const int ntab = tab_lds ? 3 * nqt * npt + 2 * n1 * n1 : 0;
+  const int nq = nqt * N1, np = npt * N1, npair = npt * (npt + 1) / 2;
+  const int ntab = tab_lds ? 3 * nqt * npt + 2 * N1 * N1 : 0;
   double* sT = sm;
   double* sG = sm + ntab;
   for (int i = threadIdx.x; i < ntab; i += 256) sT[i] = mats[i];
@@ -36,46 +49,83 @@ __global__ __launch_bounds__(256) void k_elem_mats(int64_t n_elem, int npt, int 
   const double* Ds = Dr + nqt * npt;
   const double* Bt = Ds + nqt * npt;
   const double* Bz = Bt + nqt * npt;
-  const double* Dz = Bz + n1 * n1;
-  const int npair = np * (np + 1) / 2;
-  for (int64_t e = blockIdx.x; e < n_elem; e += gridDim.x) {
+  const double* Dz = Bz + N1 * N1;
+  for (int64_t e0 = int64_t(blockIdx.x) * epb; e0 < n_elem; e0 += int64_t(gridDim.x) * epb) {
+    const int ne = int(n_elem - e0 < epb ? n_elem - e0 : epb);
     __syncthreads();
-    for (int i = threadIdx.x; i < 6 * nq; i += 256) sG[i] = G[size_t(e) * 6 * nq + i];
+    for (int i = threadIdx.x; i < ne * 6 * nq; i += 256) sG[i] = G[size_t(e0) * 6 * nq + i];
     __syncthreads();
-    double* Ke = K + size_t(e) * np * np;
-    for (int idx = threadIdx.x; idx < npair; idx += 256) {
-      // idx = j (j + 1) / 2 + i, i <= j
-      int j = int((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-      while (j * (j + 1) / 2 > idx) --j;
-      while ((j + 1) * (j + 2) / 2 <= idx) ++j;
-      const int i = idx - j * (j + 1) / 2;
-      const int ci = i / npt, ai = i - ci * npt, cj = j / npt, aj = j - cj * npt;
-      double s = 0.0;
-      for (int k = 0; k < n1; ++k) {
-        const double bzi = Bz[k * n1 + ci], dzi = Dz[k * n1 + ci];
-        const double bzj = Bz[k * n1 + cj], dzj = Dz[k * n1 + cj];
-        const double* g = sG + k * nqt;
+    for (int w = threadIdx.x; w < ne * npair; w += 256) {
+      const int le = w / npair, pr = w - le * npair;
+      int aj = int((sqrt(8.0 * pr + 1.0) - 1.0) * 0.5);
+      while (aj * (aj + 1) / 2 > pr) --aj;
+      while ((aj + 1) * (aj + 2) / 2 <= pr) ++aj;
+      const int ai = pr - aj * (aj + 1) / 2;
+      const double* g = sG + le * 6 * nq;
+      double acc[N1][N1];
+      #pragma unroll
+      for (int ci = 0; ci < N1; ++ci)
+        #pragma unroll
+        for (int cj = 0; cj < N1; ++cj) acc[ci][cj] = 0.0;
+#pragma unroll 1
+      for (int k = 0; k < N1; ++k) {
+        double sbb = 0.0, sbd = 0.0, sdb = 0.0, sdd = 0.0;
+        const double* gk = g + k * nqt;
         for (int q = 0; q < nqt; ++q) {
-          const double xi = Dr[q * npt + ai] * bzi, yi = Ds[q * npt + ai] * bzi, zi = Bt[q * npt + ai] * dzi;
-          const double xj = Dr[q * npt + aj] * bzj, yj = Ds[q * npt + aj] * bzj, zj = Bt[q * npt + aj] * dzj;
-          s += g[q] * xi * xj + g[nq + q] * (xi * yj + yi * xj) + g[2 * nq + q] * (xi * zj + zi * xj) +
-               g[3 * nq + q] * yi * yj + g[4 * nq + q] * (yi * zj + zi * yj) + g[5 * nq + q] * zi * zj;
+          const double ri = Dr[q * npt + ai], si = Ds[q * npt + ai], ti = Bt[q * npt + ai];
+          const double rj = Dr[q * npt + aj], sj = Ds[q * npt + aj], tj = Bt[q * npt + aj];
+          const double g0 = gk[q], g1 = gk[nq + q], g2 = gk[2 * nq + q];
+          const double g3 = gk[3 * nq + q], g4 = gk[4 * nq + q], g5 = gk[5 * nq + q];
+          sbb += g0 * ri * rj + g1 * (ri * sj + si * rj) + g3 * si * sj;
+          sbd += tj * (g2 * ri + g4 * si);
+          sdb += ti * (g2 * rj + g4 * sj);
+          sdd += g5 * ti * tj;
+        }
+        #pragma unroll
+        for (int cj = 0; cj < N1; ++cj) {
+          const double vb = Bz[k * N1 + cj] * sbb + Dz[k * N1 + cj] * sbd;
+          const double vd = Bz[k * N1 + cj] * sdb + Dz[k * N1 + cj] * sdd;
+          #pragma unroll
+          for (int ci = 0; ci < N1; ++ci) acc[ci][cj] += Bz[k * N1 + ci] * vb + Dz[k * N1 + ci] * vd;
         }
       }
-      Ke[size_t(i) * np + j] = s;
-      Ke[size_t(j) * np + i] = s;
+      double* Ke = K + size_t(e0 + le) * np * np;
+      #pragma unroll
+      for (int ci = 0; ci < N1; ++ci)
+        #pragma unroll
+        for (int cj = 0; cj < N1; ++cj) {
+          if (ai == aj && cj < ci) continue;  // diagonal triangle block: its upper half, mirrored
+          const int i = ci * npt + ai, j = cj * npt + aj;
+          Ke[size_t(i) * np + j] = acc[ci][cj];
+          Ke[size_t(j) * np + i] = acc[ci][cj];
+        }
     }
   }
 }
 
 void launch_elem_mats(const LevelView& lv, const double* mats, const double* G64, double* K, hipStream_t st) {
   const int npt = lv.np_tri, n1 = lv.PZ + 1, nqt = (lv.P + 1) * (lv.P + 1);
+  const int npair = npt * (npt + 1) / 2;
+  const size_t lg = sizeof(double) * 6 * size_t(nqt) * n1;  // one element's factors
+  // elements per workgroup: fill the 256 threads with node pairs, within 64 KB of LDS
+  int epb = npair >= 256 ? 1 : 256 / npair;
+  while (epb > 1 && lg * epb > 32768) --epb;
   // tables in LDS beside G when both fit in 64 KB, else read through the caches
   const size_t ltab = sizeof(double) * (3 * size_t(nqt) * npt + 2 * size_t(n1) * n1);
-  const size_t lg = sizeof(double) * 6 * size_t(nqt) * n1;
-  const int tab_lds = ltab + lg <= 65536 ? 1 : 0;
-  hipLaunchKernelGGL(k_elem_mats, dim3(grid_of(lv.n_elem)), dim3(256), tab_lds ? ltab + lg : lg, st, lv.n_elem, npt,
-                     nqt, n1, tab_lds, mats, G64, K);
+  const int tab_lds = ltab + lg * epb <= 65536 ? 1 : 0;
+  const size_t lds = (tab_lds ? ltab : 0) + lg * size_t(epb);
+  const int64_t nb = (lv.n_elem + epb - 1) / epb;
+  const dim3 grid(grid_of(nb));
+  switch (n1) {
+#define PMG_EM(N)                                                                                        \
+  case N:                                                                                                \
+    hipLaunchKernelGGL(k_elem_mats<N>, grid, dim3(256), lds, st, lv.n_elem, npt, nqt, epb, tab_lds, mats, \
+                       G64, K);                                                                          \
+    break;
+    PMG_EM(2) PMG_EM(3) PMG_EM(4) PMG_EM(5) PMG_EM(6) PMG_EM(7) PMG_EM(8) PMG_EM(9)
+#undef PMG_EM
+    default: throw std::runtime_error("element matrices: vertical order outside 1..8");
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -120,116 +170,164 @@ void launch_sd_assemble(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t b
 }
 
 // ---------------------------------------------------------------------------
-// blocked Gauss-Jordan inversion in place (pivot blocks of GJ_B, no pivoting).
-// Per pivot block K: A_KK <- A_KK^-1 (in LDS); A_KJ <- A_KK^-1 A_KJ;
-// A_IJ <- A_IJ - A_IK A_KJ; A_IK <- -A_IK A_KK^-1, rows in chunks of GJ_RC
-// whose A_IK is staged in LDS.  One workgroup per matrix.
+// blocked Gauss-Jordan inversion in place (pivot blocks of GJ_T = 32, no
+// pivoting: the blocks are SPD; m a multiple of 32, identity on the padding).
+// Per pivot block K:
+//   (a) every wave inverts its own LDS copy of A_KK (unblocked Gauss-Jordan);
+//   (b) row panel A_KJ <- A_KK^-1 A_KJ;
+//   (c) A_IJ <- A_IJ - A_IK A_KJ for I, J != K, each wave a contiguous run of
+//       the tiles in row order (A_IK stays in registers along a row);
+//   (d) column panel A_IK <- -A_IK A_KK^-1, and A_KK <- A_KK^-1.
+// The 32 x 32 tile products run on v_mfma_f64_16x16x4f64 (2 x 2 blocks of
+// 16 x 16, eight K = 4 steps).  One workgroup per matrix.
+// Register layouts (g = lane / 16, j = lane % 16): A operand A[j][g], B operand
+// B[g][j], accumulator D[g + 4r][j], r = 0..3.
 // ---------------------------------------------------------------------------
-constexpr int GJ_B = 16, GJ_RC = 256;
+constexpr int GJ_T = 32;
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4_t mfma_f64(double a, double b, d4_t c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
 
 __global__ __launch_bounds__(256) void k_sd_invert(int64_t k0, int64_t k1, int64_t base,
-                                                   const int32_t* __restrict__ sd_ptr,
                                                    const int32_t* __restrict__ msz,
                                                    const int64_t* __restrict__ inv_off, double* __restrict__ A,
                                                    int* __restrict__ bad) {
-  __shared__ double sKK[GJ_B][GJ_B + 1];
-  __shared__ double sCol[GJ_RC][GJ_B + 1];
-  const int tid = threadIdx.x;
+  __shared__ double sK[4][GJ_T][GJ_T + 1];
+  const int tid = threadIdx.x, l = tid & 63, lj = l & 15, lg = l >> 4;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  double(*Kw)[GJ_T + 1] = sK[wv];
   for (int64_t k = k0 + blockIdx.x; k < k1; k += gridDim.x) {
-    const int m = msz[k], n = sd_ptr[k + 1] - sd_ptr[k];
+    const int m = msz[k], mt = m / GJ_T;
     double* Ak = A + (inv_off[k] - base);
-    for (int p0 = 0; p0 < n; p0 += GJ_B) {
-      const int bb = n - p0 < GJ_B ? n - p0 : GJ_B;
-      const int r = tid / GJ_B, c = tid - r * GJ_B;
-      __syncthreads();
-      if (r < bb && c < bb) sKK[r][c] = Ak[size_t(p0 + r) * m + p0 + c];
-      __syncthreads();
-      // 1. A_KK^-1 by unblocked Gauss-Jordan
-      for (int p = 0; p < bb; ++p) {
-        const double piv = sKK[p][p];
-        if (tid == 0 && !(piv > 0.0)) atomicOr(bad, 1);
+    auto at = [&](int r, int c) -> double& { return Ak[size_t(r) * m + c]; };
+    for (int kb = 0; kb < mt; ++kb) {
+      const int p0 = kb * GJ_T;
+      // (a) A_KK^-1 in this wave's LDS copy; lane l owns column l % 32 of rows 2t + l / 32
+      for (int t = 0; t < 16; ++t) Kw[2 * t + (l >> 5)][l & 31] = at(p0 + 2 * t + (l >> 5), p0 + (l & 31));
+      wave_sync();
+      for (int p = 0; p < GJ_T; ++p) {
+        const double piv = Kw[p][p];
+        if (wv == 0 && l == 0 && !(piv > 0.0)) atomicOr(bad, 1);
         const double d = 1.0 / piv;
-        double v = 0.0;
-        if (r < bb && c < bb) {
-          if (r == p && c == p) v = d;
-          else if (r == p) v = sKK[p][c] * d;
-          else if (c == p) v = -sKK[r][p] * d;
-          else v = sKK[r][c] - sKK[r][p] * (sKK[p][c] * d);
+        const int c = l & 31;
+        const double pc = Kw[p][c] * d;
+        double v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+          const int r = 2 * t + (l >> 5);
+          const double rp = Kw[r][p];
+          v[t] = r == p ? (c == p ? d : pc) : (c == p ? -rp * d : Kw[r][c] - rp * pc);
         }
-        __syncthreads();
-        if (r < bb && c < bb) sKK[r][c] = v;
-        __syncthreads();
+        wave_sync();
+#pragma unroll
+        for (int t = 0; t < 16; ++t) Kw[2 * t + (l >> 5)][c] = v[t];
+        wave_sync();
       }
-      // 2. row panel A_KJ <- A_KK^-1 A_KJ
-      for (int j = tid; j < n; j += 256) {
-        if (j >= p0 && j < p0 + bb) continue;
-        double x[GJ_B], y[GJ_B];
+      // (b) row panel
+      for (int J = wv; J < mt; J += 4) {
+        if (J == kb) continue;
+        double bo[2][8];
 #pragma unroll
-        for (int s = 0; s < GJ_B; ++s) x[s] = s < bb ? Ak[size_t(p0 + s) * m + j] : 0.0;
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-        for (int s = 0; s < GJ_B; ++s) {
-          double a = 0.0;
+          for (int s = 0; s < 8; ++s) bo[bj][s] = at(p0 + 4 * s + lg, J * GJ_T + 16 * bj + lj);
+        d4_t acc[2][2];
 #pragma unroll
-          for (int u = 0; u < GJ_B; ++u)
-            if (u < bb) a += sKK[s][u] * x[u];
-          y[s] = a;
-        }
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int s = 0; s < GJ_B; ++s)
-          if (s < bb) Ak[size_t(p0 + s) * m + j] = y[s];
+          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi) {
+            const double a = Kw[16 * bi + lj][4 * s + lg];
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_f64(a, bo[bj][s], acc[bi][bj]);
+          }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) at(p0 + 16 * bi + lg + 4 * r, J * GJ_T + 16 * bj + lj) = acc[bi][bj][r];
       }
       __syncthreads();
-      // 3. rank-bb update and column panel, by row chunks
-      for (int i0 = 0; i0 < n; i0 += GJ_RC) {
-        const int nr = n - i0 < GJ_RC ? n - i0 : GJ_RC;
-        for (int idx = tid; idx < nr * GJ_B; idx += 256) {
-          const int ii = idx / GJ_B, s = idx - ii * GJ_B;
-          const int i = i0 + ii;
-          sCol[ii][s] = (s < bb && !(i >= p0 && i < p0 + bb)) ? Ak[size_t(i) * m + p0 + s] : 0.0;
+      // (c) trailing update
+      const int mo = mt - 1, nu = mo * mo;
+      const int u0 = nu * wv / 4, u1 = nu * (wv + 1) / 4;
+      int Ic = -1;
+      double ao[2][8];
+      for (int u = u0; u < u1; ++u) {
+        int I = u / mo, J = u - (u / mo) * mo;
+        I += I >= kb ? 1 : 0;
+        J += J >= kb ? 1 : 0;
+        if (I != Ic) {
+#pragma unroll
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int s = 0; s < 8; ++s) ao[bi][s] = -at(I * GJ_T + 16 * bi + lj, p0 + 4 * s + lg);
+          Ic = I;
         }
-        __syncthreads();
-        for (int j = tid; j < n; j += 256) {
-          if (j >= p0 && j < p0 + bb) continue;
-          double rp[GJ_B];
+        double bo[2][8];
+        d4_t acc[2][2];
 #pragma unroll
-          for (int s = 0; s < GJ_B; ++s) rp[s] = s < bb ? Ak[size_t(p0 + s) * m + j] : 0.0;
-          int ii = 0;
-          for (; ii + 4 <= nr; ii += 4) {
-            double a[4];
+        for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int h = 0; h < 4; ++h) a[h] = Ak[size_t(i0 + ii + h) * m + j];
+          for (int s = 0; s < 8; ++s) bo[bj][s] = at(p0 + 4 * s + lg, J * GJ_T + 16 * bj + lj);
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-              for (int s = 0; s < GJ_B; ++s) a[h] -= sCol[ii + h][s] * rp[s];
-            }
+          for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-              const int i = i0 + ii + h;
-              if (!(i >= p0 && i < p0 + bb)) Ak[size_t(i) * m + j] = a[h];
-            }
-          }
-          for (; ii < nr; ++ii) {
-            const int i = i0 + ii;
-            if (i >= p0 && i < p0 + bb) continue;
-            double a = Ak[size_t(i) * m + j];
+            for (int r = 0; r < 4; ++r) acc[bi][bj][r] = at(I * GJ_T + 16 * bi + lg + 4 * r, J * GJ_T + 16 * bj + lj);
 #pragma unroll
-            for (int s = 0; s < GJ_B; ++s) a -= sCol[ii][s] * rp[s];
-            Ak[size_t(i) * m + j] = a;
-          }
-        }
-        for (int idx = tid; idx < nr * GJ_B; idx += 256) {
-          const int ii = idx / GJ_B, s = idx - ii * GJ_B;
-          const int i = i0 + ii;
-          if (s >= bb || (i >= p0 && i < p0 + bb)) continue;
-          double a = 0.0;
+        for (int s = 0; s < 8; ++s)
 #pragma unroll
-          for (int u = 0; u < GJ_B; ++u) a -= sCol[ii][u] * sKK[u][s];
-          Ak[size_t(i) * m + p0 + s] = a;
-        }
-        __syncthreads();
+          for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = mfma_f64(ao[bi][s], bo[bj][s], acc[bi][bj]);
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) at(I * GJ_T + 16 * bi + lg + 4 * r, J * GJ_T + 16 * bj + lj) = acc[bi][bj][r];
       }
-      if (r < bb && c < bb) Ak[size_t(p0 + r) * m + p0 + c] = sKK[r][c];
+      __syncthreads();
+      // (d) column panel, and the inverted pivot block
+      for (int I = wv; I < mt; I += 4) {
+        if (I == kb) {
+          for (int t = 0; t < 16; ++t) at(p0 + 2 * t + (l >> 5), p0 + (l & 31)) = Kw[2 * t + (l >> 5)][l & 31];
+          continue;
+        }
+        double a2[2][8];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int s = 0; s < 8; ++s) a2[bi][s] = -at(I * GJ_T + 16 * bi + lj, p0 + 4 * s + lg);
+        d4_t acc[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = d4_t{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj) {
+            const double b = Kw[4 * s + lg][16 * bj + lj];
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi) acc[bi][bj] = mfma_f64(a2[bi][s], b, acc[bi][bj]);
+          }
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+          for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) at(I * GJ_T + 16 * bi + lg + 4 * r, p0 + 16 * bj + lj) = acc[bi][bj][r];
+      }
+      __syncthreads();
     }
   }
 }
@@ -263,8 +361,8 @@ __global__ __launch_bounds__(256) void k_sd_symm(int64_t k0, int64_t k1, int64_t
 
 void launch_sd_invert(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t base, double* A, double* A64,
                       float* A32, bf16_t* A16, int* bad, hipStream_t st) {
-  hipLaunchKernelGGL(k_sd_invert, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.sd_ptr, sv.msz,
-                     sv.inv_off, A, bad);
+  hipLaunchKernelGGL(k_sd_invert, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.msz, sv.inv_off, A,
+                     bad);
   hipLaunchKernelGGL(k_sd_symm, dim3(grid_of(k1 - k0)), dim3(256), 0, st, k0, k1, base, sv.sd_ptr, sv.msz,
                      sv.inv_off, sv.tile_off, A, A64, A32, A16);
 }
@@ -293,7 +391,7 @@ template <> struct TileT<double> {
   static __device__ __forceinline__ double get(const double* p, int i) { return p[i]; }
   static __device__ __forceinline__ void row(const double* p, double (&o)[16]) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
-#pragma unroll
+    #pragma unroll
     for (int h = 0; h < 8; ++h) {
       const u32x4 v = q[h];
       o[2 * h] = __hiloint2double(int(v.y), int(v.x));
@@ -305,7 +403,7 @@ template <> struct TileT<float> {
   static __device__ __forceinline__ float get(const float* p, int i) { return p[i]; }
   static __device__ __forceinline__ void row(const float* p, float (&o)[16]) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
-#pragma unroll
+    #pragma unroll
     for (int h = 0; h < 4; ++h) {
       const u32x4 v = q[h];
       o[4 * h] = __uint_as_float(v.x);
@@ -319,11 +417,11 @@ template <> struct TileT<bf16_t> {
   static __device__ __forceinline__ float get(const bf16_t* p, int i) { return __uint_as_float(uint32_t(p[i]) << 16); }
   static __device__ __forceinline__ void row(const bf16_t* p, float (&o)[16]) {
     const u32x4* q = reinterpret_cast<const u32x4*>(p);
-#pragma unroll
+    #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const u32x4 v = q[h];
       const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
+      #pragma unroll
       for (int c = 0; c < 4; ++c) {
         o[8 * h + 2 * c] = __uint_as_float(wd[c] << 16);
         o[8 * h + 2 * c + 1] = __uint_as_float(wd[c] & 0xFFFF0000u);
@@ -331,12 +429,6 @@ template <> struct TileT<bf16_t> {
     }
   }
 };
-
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 template <typename T, typename TI>
 __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const int32_t* __restrict__ sd_ptr,
@@ -379,21 +471,21 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const 
       while ((J + 1) * (J + 2) / 2 <= t0) ++J;
       int I = t0 - J * (J + 1) / 2;
       u32x4 a[NCH];
-#pragma unroll
+      #pragma unroll
       for (int h = 0; h < NCH; ++h) a[h] = At[size_t(t0) * 64 * NCH + h * 64 + l];
       T xj[16];
-#pragma unroll
+      #pragma unroll
       for (int i = 0; i < 16; ++i) xj[i] = sx[J * TS + lh * 16 + i];
       T zj = T(0);
       for (int t = t0; t < t1; ++t) {
         wave_sync();
-#pragma unroll
+        #pragma unroll
         for (int h = 0; h < NCH; ++h) {
           const int e = (h * 64 + l) * EC;  // first entry of the chunk
           *reinterpret_cast<u32x4*>(st + (e / TS) * RS + e % TS) = a[h];
         }
         if (t + 1 < t1) {
-#pragma unroll
+          #pragma unroll
           for (int h = 0; h < NCH; ++h) a[h] = At[size_t(t + 1) * 64 * NCH + h * 64 + l];
         }
         wave_sync();
@@ -402,7 +494,7 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const 
         {
           T e[16];
           TileT<TI>::row(st + lr * RS + lh * 16, e);
-#pragma unroll
+          #pragma unroll
           for (int i = 0; i < 16; ++i) pr += e[i] * xj[i];
         }
         const bool diag = I == J;
@@ -411,7 +503,7 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const 
           // column pass: column lr, rows lh*16 .. lh*16+15
           const TI* col = st + lh * 16 * RS + lr;
           const T* xi = sx + I * TS + lh * 16;
-#pragma unroll
+          #pragma unroll
           for (int i = 0; i < 16; ++i) pc += T(TileT<TI>::get(col, i * RS)) * xi[i];
         }
         // lanes < 32 complete row sums, lanes >= 32 column sums
@@ -429,7 +521,7 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const 
           I = 0;
           zj = T(0);
           if (t + 1 < t1) {
-#pragma unroll
+            #pragma unroll
             for (int i = 0; i < 16; ++i) xj[i] = sx[J * TS + lh * 16 + i];
           }
         } else {

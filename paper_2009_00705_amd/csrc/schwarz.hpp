@@ -44,7 +44,7 @@ struct SchwarzPlan {
   int64_t total = 0;             // sum of the subdomain sizes
   std::vector<int32_t> sd_ptr;   // [n_sub+1] into sd_node
   std::vector<int32_t> sd_node;  // sorted free global nodes of every subdomain
-  std::vector<int32_t> msz;      // padded size of every local matrix (multiple of 4)
+  std::vector<int32_t> msz;      // padded size of every local matrix (multiple of 32)
   std::vector<int64_t> inv_off;  // [n_sub+1] entry offsets of the padded msz x msz blocks (set-up work)
   std::vector<int64_t> tile_off; // [n_sub+1] entry offsets of the kept inverses (packed tiles, sz_tiles)
   std::vector<int32_t> blk_ptr;  // [n_sub+1] element blocks of every subdomain

@@ -159,7 +159,7 @@ void build_schwarz(const MeshIn& m, const Numbering& num, const std::vector<uint
       throw std::runtime_error("Schwarz plan exceeds 2^31 entries");
     o.sd_ptr[size_t(k) + 1] = int32_t(tot);
     o.max_n = std::max(o.max_n, n);
-    const int ms = (n + 3) & ~3;
+    const int ms = (n + 31) & ~31;
     o.msz[size_t(k)] = ms;
     o.inv_off[size_t(k) + 1] = o.inv_off[size_t(k)] + int64_t(ms) * ms;
     o.tile_off[size_t(k) + 1] = o.tile_off[size_t(k)] + sz_tiles(n);
