@@ -196,18 +196,23 @@ def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16
 
 def schwarz_roofline(ctx, prec, level=0, reps=10):
     """Roofline of the Schwarz local-solve kernel of a level: per subdomain of n
-    nodes it reads the n x n inverse (8, 4 or 2 bytes an entry), n node ids and
-    n gathered residual values, and writes n corrections."""
+    nodes it reads the n (n + 1) / 2 distinct entries of the symmetric inverse
+    (8, 4 or 2 bytes an entry), n node ids and n gathered residual values, and
+    writes n corrections.  stored_bytes counts the entries the library keeps
+    (whole 32 x 32 tiles of the upper block triangle, padding included)."""
     sizes = np.array([s.size for s in ctx.schwarz_nodes(level)], dtype=np.float64)
     s_inv = {"fp64": 8, "fp32": 4, "bf16": 2, "bf16g": 2, "bf16x3": 2, "bf16x2": 2}[prec]
     s_v = 8 if prec == "fp64" else 4
-    byts = float(np.sum(sizes * sizes) * s_inv + np.sum(sizes) * (4 + 2 * s_v))
+    vec = float(np.sum(sizes) * (4 + 2 * s_v))
+    byts = float(np.sum(sizes * (sizes + 1) / 2) * s_inv) + vec
     flops = float(2 * np.sum(sizes * sizes))
     ms = ctx.time_kernel("schwarz", level, prec, reps=reps)
     r = roofline(byts, flops, ms, prec)
     info = ctx.schwarz_info(level)
+    stored = float(info["inv_entries"]) * s_inv + vec
     r.update({"traffic": None, "kernel": f"Schwarz local solves (level {level}, overlap {info['dt']}), {prec} inverses",
-              "ms_per_launch": ms, "bytes_per_launch": byts, "flops_per_launch": flops,
+              "ms_per_launch": ms, "bytes_per_launch": byts, "stored_bytes": stored,
+              "stored_GB_per_s": round(stored / (ms * 1e-3) / 1e9, 1), "flops_per_launch": flops,
               "subdomains": info["n_sub"], "max_size": info["max_size"], "mean_size": float(sizes.mean())})
     return r
 

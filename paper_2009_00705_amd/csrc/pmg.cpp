@@ -606,9 +606,7 @@ static void upload_levels(pmg_ctx* c) {
       const int keep = c->opt.schwarz_store == 0 ? 7 : c->opt.schwarz_store;
       int lds_max = 0;
       HIPCHK(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device));
-      const size_t lds = std::max({(keep & 1) ? sd_apply_lds(P.max_n, 8, 8) : size_t(0),
-                                   (keep & 2) ? sd_apply_lds(P.max_n, 4, 4) : size_t(0),
-                                   (keep & 4) ? sd_apply_lds(P.max_n, 4, 2) : size_t(0)});
+      const size_t lds = sd_apply_lds(P.max_n, (keep & 1) ? 8 : 4);
       if (lds > size_t(lds_max))
         throw Error(PMG_EINVAL, "Schwarz subdomains too large for the local solve (" + std::to_string(P.max_n) +
                                     " nodes)");

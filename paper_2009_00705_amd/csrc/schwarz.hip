@@ -333,7 +333,7 @@ __global__ __launch_bounds__(256) void k_sd_invert(int64_t k0, int64_t k1, int64
 }
 
 // (A + A^T)/2 on the n x n block, written as the packed upper block-triangle
-// tiles of the kept copies (zero outside n x n)
+// tiles of the kept copies (zero outside n x n; entry order sz_tile_pos)
 __global__ __launch_bounds__(256) void k_sd_symm(int64_t k0, int64_t k1, int64_t base,
                                                  const int32_t* __restrict__ sd_ptr,
                                                  const int32_t* __restrict__ msz,
@@ -352,9 +352,10 @@ __global__ __launch_bounds__(256) void k_sd_symm(int64_t k0, int64_t k1, int64_t
           const int i = I * SZ_TS + (e / SZ_TS), j = J * SZ_TS + (e % SZ_TS);
           const int lo = i < j ? i : j, hi = i < j ? j : i;
           const double v = hi < n ? 0.5 * (Ak[size_t(lo) * m + hi] + Ak[size_t(hi) * m + lo]) : 0.0;
-          if (A64) A64[off + e] = v;
-          if (A32) A32[off + e] = float(v);
-          if (A16) A16[off + e] = sz_f32_to_bf16(float(v));
+          const int r = e / SZ_TS, c = e % SZ_TS;
+          if (A64) A64[off + sz_tile_pos(r, c, 8)] = v;
+          if (A32) A32[off + sz_tile_pos(r, c, 4)] = float(v);
+          if (A16) A16[off + sz_tile_pos(r, c, 2)] = sz_f32_to_bf16(float(v));
         }
   }
 }
@@ -372,56 +373,48 @@ void launch_sd_invert(const SchwarzView& sv, int64_t k0, int64_t k1, int64_t bas
 // tiles (I, J), I <= J, of its upper block triangle.  A tile off the diagonal
 // serves twice: z_I += A_IJ x_J (row pass) and z_J += A_IJ^T x_I (column
 // pass); a diagonal tile (stored whole) only in the row pass.  Each wave takes
-// a contiguous run of the tiles in their storage order (J-major), so x_J sits
-// in registers and z_J accumulates in registers until the column ends.  A tile
-// is read from HBM once, with 16-byte loads (the next tile's are issued before
-// the current one is used), and staged in the wave's own LDS slice (rows
-// padded by 16 bytes: both passes read it without bank conflicts).  Lane l
-// takes row l mod 32 over the column half l / 32 in the row pass and column
-// l mod 32 over the row half l / 32 in the column pass; one cross-half
-// exchange completes both sums.  z_I goes to the wave's own LDS accumulator;
-// the four accumulators are added in a fixed order at the end.
+// a contiguous run of the tiles in their storage order (J-major) and keeps
+// two tiles in flight.  Lane l holds the strip of row l % 32, columns
+// 16 (l / 32) .. +15 of the tile (the tile is stored so that every load of a
+// wave reads 1 KB contiguously, see sz_tile_pos), and uses it for both passes:
+//   row pass: one dot product with x_J (in registers for the whole column),
+//     the two half rows joined by one cross-half exchange, added to the
+//     wave's LDS accumulator of z_I;
+//   column pass: 16 running sums x_I[row] A[row][c] in registers, reduced
+//     over the 32 rows once per column (at its diagonal tile or where the
+//     wave's run ends) and added to z_J.
+// The four wave accumulators are added in a fixed order at the end.
 // ---------------------------------------------------------------------------
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// Entries of a staged tile: get(p, i) one entry, row(p, o) the 16 entries at
-// p (16-byte aligned) read as 16-byte words.
-template <typename TI> struct TileT;
-template <> struct TileT<double> {
-  static __device__ __forceinline__ double get(const double* p, int i) { return p[i]; }
-  static __device__ __forceinline__ void row(const double* p, double (&o)[16]) {
-    const u32x4* q = reinterpret_cast<const u32x4*>(p);
-    #pragma unroll
+// The 16 entries of a strip from its NCH = sizeof(TI) 16-byte chunks.
+template <typename TI> struct Strip;
+template <> struct Strip<double> {
+  static __device__ __forceinline__ void get(const u32x4 (&q)[8], double (&o)[16]) {
+#pragma unroll
     for (int h = 0; h < 8; ++h) {
-      const u32x4 v = q[h];
-      o[2 * h] = __hiloint2double(int(v.y), int(v.x));
-      o[2 * h + 1] = __hiloint2double(int(v.w), int(v.z));
+      o[2 * h] = __hiloint2double(int(q[h].y), int(q[h].x));
+      o[2 * h + 1] = __hiloint2double(int(q[h].w), int(q[h].z));
     }
   }
 };
-template <> struct TileT<float> {
-  static __device__ __forceinline__ float get(const float* p, int i) { return p[i]; }
-  static __device__ __forceinline__ void row(const float* p, float (&o)[16]) {
-    const u32x4* q = reinterpret_cast<const u32x4*>(p);
-    #pragma unroll
+template <> struct Strip<float> {
+  static __device__ __forceinline__ void get(const u32x4 (&q)[4], float (&o)[16]) {
+#pragma unroll
     for (int h = 0; h < 4; ++h) {
-      const u32x4 v = q[h];
-      o[4 * h] = __uint_as_float(v.x);
-      o[4 * h + 1] = __uint_as_float(v.y);
-      o[4 * h + 2] = __uint_as_float(v.z);
-      o[4 * h + 3] = __uint_as_float(v.w);
+      o[4 * h] = __uint_as_float(q[h].x);
+      o[4 * h + 1] = __uint_as_float(q[h].y);
+      o[4 * h + 2] = __uint_as_float(q[h].z);
+      o[4 * h + 3] = __uint_as_float(q[h].w);
     }
   }
 };
-template <> struct TileT<bf16_t> {
-  static __device__ __forceinline__ float get(const bf16_t* p, int i) { return __uint_as_float(uint32_t(p[i]) << 16); }
-  static __device__ __forceinline__ void row(const bf16_t* p, float (&o)[16]) {
-    const u32x4* q = reinterpret_cast<const u32x4*>(p);
-    #pragma unroll
+template <> struct Strip<bf16_t> {
+  static __device__ __forceinline__ void get(const u32x4 (&q)[2], float (&o)[16]) {
+#pragma unroll
     for (int h = 0; h < 2; ++h) {
-      const u32x4 v = q[h];
-      const uint32_t wd[4] = {v.x, v.y, v.z, v.w};
-      #pragma unroll
+      const uint32_t wd[4] = {q[h].x, q[h].y, q[h].z, q[h].w};
+#pragma unroll
       for (int c = 0; c < 4; ++c) {
         o[8 * h + 2 * c] = __uint_as_float(wd[c] << 16);
         o[8 * h + 2 * c + 1] = __uint_as_float(wd[c] & 0xFFFF0000u);
@@ -437,18 +430,15 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const 
                                                   const T* __restrict__ r, const T* __restrict__ w,
                                                   T* __restrict__ zS) {
   constexpr int TS = SZ_TS;
-  constexpr int EC = 16 / int(sizeof(TI));   // entries per 16-byte chunk
-  constexpr int NCH = int(sizeof(TI));       // 16-byte chunks per lane and tile (TS*TS/64 entries)
-  constexpr int RS = TS + EC;                // padded LDS row (entries)
-  static_assert(TS * TS * int(sizeof(TI)) == 64 * 16 * NCH, "tile = 64 lanes x NCH chunks");
+  constexpr int NCH = int(sizeof(TI));  // 16-byte chunks of a 16-entry strip
   extern __shared__ __align__(16) unsigned char smraw[];
-  T* sx = reinterpret_cast<T*>(smraw);                       // [ntm*TS]
-  T* zacc = sx + size_t(ntm) * TS;                           // [4][ntm*TS]
-  TI* stile = reinterpret_cast<TI*>(zacc + 4 * size_t(ntm) * TS);  // [4][TS*RS]
+  T* sx = reinterpret_cast<T*>(smraw);  // [ntm*TS]
+  T* zacc = sx + size_t(ntm) * TS;      // [4][ntm*TS]
+  T* red = zacc + 4 * size_t(ntm) * TS;  // [4][16][SD_RED]
   const int tid = threadIdx.x, l = tid & 63, lr = l & 31, lh = l >> 5;
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: the tile loop is scalar
   T* zw = zacc + size_t(wv) * ntm * TS;
-  TI* st = stile + wv * TS * RS;
+  T* rw = red + wv * 16 * SD_RED;
   for (int64_t k = blockIdx.x; k < n_sub; k += gridDim.x) {
     const int32_t b = sd_ptr[k];
     const int n = sd_ptr[k + 1] - b, nt = (n + TS - 1) / TS, np = nt * TS;
@@ -470,66 +460,67 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const 
       int J = 0;
       while ((J + 1) * (J + 2) / 2 <= t0) ++J;
       int I = t0 - J * (J + 1) / 2;
-      u32x4 a[NCH];
-      #pragma unroll
-      for (int h = 0; h < NCH; ++h) a[h] = At[size_t(t0) * 64 * NCH + h * 64 + l];
-      T xj[16];
-      #pragma unroll
-      for (int i = 0; i < 16; ++i) xj[i] = sx[J * TS + lh * 16 + i];
-      T zj = T(0);
-      for (int t = t0; t < t1; ++t) {
+      T xj[16], zc[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        xj[i] = sx[J * TS + lh * 16 + i];
+        zc[i] = T(0);
+      }
+      auto load = [&](u32x4(&a)[NCH], int t) {
+#pragma unroll
+        for (int h = 0; h < NCH; ++h) a[h] = At[size_t(t) * 64 * NCH + h * 64 + l];
+      };
+      // column J's running sums of this run: reduce over the 32 rows, add to z_J
+      auto flush = [&]() {
+#pragma unroll
+        for (int i = 0; i < 16; ++i) rw[i * SD_RED + l] = zc[i];
         wave_sync();
-        #pragma unroll
-        for (int h = 0; h < NCH; ++h) {
-          const int e = (h * 64 + l) * EC;  // first entry of the chunk
-          *reinterpret_cast<u32x4*>(st + (e / TS) * RS + e % TS) = a[h];
-        }
-        if (t + 1 < t1) {
-          #pragma unroll
-          for (int h = 0; h < NCH; ++h) a[h] = At[size_t(t + 1) * 64 * NCH + h * 64 + l];
-        }
+        const int c = lr;  // lane l sums column c over rows 16 lh .. 16 lh + 15
+        const T* q = rw + (c & 15) * SD_RED + (c >> 4) * 32 + 16 * lh;
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s += q[i];
+        s += __shfl_xor(s, 32);
+        if (lh == 0) zw[J * TS + c] += s;
         wave_sync();
-        // row pass: row lr, columns lh*16 .. lh*16+15
+#pragma unroll
+        for (int i = 0; i < 16; ++i) zc[i] = T(0);
+      };
+      auto tile = [&](u32x4(&a)[NCH], int t) {
+        T e[16];
+        Strip<TI>::get(a, e);
+        if (t + 2 < t1) load(a, t + 2);
         T pr = T(0);
-        {
-          T e[16];
-          TileT<TI>::row(st + lr * RS + lh * 16, e);
-          #pragma unroll
-          for (int i = 0; i < 16; ++i) pr += e[i] * xj[i];
-        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) pr += e[i] * xj[i];
         const bool diag = I == J;
-        T pc = T(0);
         if (!diag) {
-          // column pass: column lr, rows lh*16 .. lh*16+15
-          const TI* col = st + lh * 16 * RS + lr;
-          const T* xi = sx + I * TS + lh * 16;
-          #pragma unroll
-          for (int i = 0; i < 16; ++i) pc += T(TileT<TI>::get(col, i * RS)) * xi[i];
+          const T xr = sx[I * TS + lr];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) zc[i] += e[i] * xr;
         }
-        // lanes < 32 complete row sums, lanes >= 32 column sums
-        const T o = __shfl_xor((lh == 0 && !diag) ? pc : pr, 32);
-        // at the diagonal the upper lanes hand over the column's z_J (same rows)
-        const T oz = diag ? __shfl_xor(zj, 32) : T(0);
-        if (lh == 0) {
-          zw[I * TS + lr] += (pr + o) + oz;
-        } else if (!diag) {
-          zj += pc + o;
-        }
+        const T o = __shfl_xor(pr, 32);
+        if (lh == 0) zw[I * TS + lr] += pr + o;
         if (diag) {
-          // next column
+          flush();
           ++J;
           I = 0;
-          zj = T(0);
           if (t + 1 < t1) {
-            #pragma unroll
+#pragma unroll
             for (int i = 0; i < 16; ++i) xj[i] = sx[J * TS + lh * 16 + i];
           }
         } else {
           ++I;
         }
+      };
+      u32x4 a0[NCH], a1[NCH];
+      load(a0, t0);
+      if (t0 + 1 < t1) load(a1, t0 + 1);
+      for (int t = t0; t < t1; t += 2) {
+        tile(a0, t);
+        if (t + 1 < t1) tile(a1, t + 1);
       }
-      // run ended inside a column: flush the upper lanes' z_J
-      if (I != 0 && lh == 1) zw[J * TS + lr] += zj;
+      if (I != 0) flush();  // run ended inside column J
     }
     __syncthreads();
     for (int i = tid; i < n; i += 256) {
@@ -542,8 +533,9 @@ __global__ __launch_bounds__(256) void k_sd_apply(int64_t n_sub, int ntm, const 
 template <typename T, typename TI>
 void launch_sd_apply(const SchwarzView& sv, const TI* inv, const T* r, const T* w, T* zS, hipStream_t st) {
   const int ntm = (sv.max_n + SZ_TS - 1) / SZ_TS;
-  hipLaunchKernelGGL((k_sd_apply<T, TI>), dim3(grid_of(sv.n_sub)), dim3(256), sd_apply_lds(sv.max_n, sizeof(T), sizeof(TI)), st,
-                     sv.n_sub, ntm, sv.sd_ptr, sv.sd_node, sv.tile_off, inv, r, w, zS);
+  const size_t lds = sd_apply_lds(sv.max_n, sizeof(T));
+  hipLaunchKernelGGL((k_sd_apply<T, TI>), dim3(grid_of(sv.n_sub)), dim3(256), lds, st, sv.n_sub, ntm, sv.sd_ptr,
+                     sv.sd_node, sv.tile_off, inv, r, w, zS);
 }
 
 template <typename T>

@@ -20,20 +20,29 @@ namespace pmg {
 
 // The kept local inverses are symmetric: each is stored as the SZ_TS x SZ_TS
 // tiles (I, J), I <= J, of its upper block triangle, tile J(J+1)/2 + I at
-// SZ_TS^2 (J(J+1)/2 + I), row-major inside the tile; entries past the
-// subdomain size are zero.  About 57% of the full square at the sizes of the
-// c3 finest level (428 nodes on average).
+// SZ_TS^2 (J(J+1)/2 + I); entries past the subdomain size are zero.  About
+// 58% of the full square at the sizes of the c3 finest level (428 nodes on
+// average).
 constexpr int SZ_TS = 32;
 inline int64_t sz_tiles(int n) {
   const int64_t t = (n + SZ_TS - 1) / SZ_TS;
   return t * (t + 1) / 2 * SZ_TS * SZ_TS;
 }
+// Position of entry (r, c) inside a tile whose entries take es bytes: the
+// tile is 64 strips (row r, columns 16 h .. 16 h + 15, strip 32 h + r) of
+// 16-byte chunks of ec = 16 / es entries; chunk q of strip s sits at 64 q + s.
+__host__ __device__ inline int sz_tile_pos(int r, int c, int es) {
+  const int ec = 16 / es;
+  return ((((c & 15) / ec) * 64) + (c >> 4) * 32 + r) * ec + c % ec;
+}
 
 // LDS bytes of the local solve on subdomains of up to max_n nodes, for
-// compute values of ts bytes and stored entries of tis bytes.
-inline size_t sd_apply_lds(int max_n, size_t ts, size_t tis) {
+// compute values of ts bytes: x, four wave accumulators of z and four column
+// reduction buffers of 16 x SD_RED values.
+constexpr int SD_RED = 65;
+inline size_t sd_apply_lds(int max_n, size_t ts) {
   const size_t ntm = size_t(max_n + SZ_TS - 1) / SZ_TS;
-  return ts * 5 * ntm * SZ_TS + 4 * tis * SZ_TS * (SZ_TS + 16 / tis);
+  return ts * (5 * ntm * SZ_TS + 4 * 16 * SD_RED);
 }
 
 // Host plan of one level's subdomains.
