@@ -255,6 +255,55 @@ __device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, c
   }
 }
 
+// vertical_out with S staged one half at a time (S[k][a][el] of Yr, then of
+// Yt), for kernels whose LDS cannot hold both; the sums and their order are
+// those of vertical_out.  Every thread holds the Yr partials of its (a, el)
+// pairs (at most two) across the second staging.
+template <int PT, int PZ, typename T, typename ACC, bool F64ROW>
+__device__ __forceinline__ void vertical_out_halves(int L, ColSlot cs, int k, const ACC (&yr)[MD<PT, PZ>::NAT],
+                                                    const ACC (&yt)[MD<PT, PZ>::NAT], T* __restrict__ sR,
+                                                    const T* __restrict__ sV, T* __restrict__ Y) {
+  using D = MD<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NAT = D::NAT, NTH = 64 * N1;
+  static_assert(16 * NPT <= 2 * NTH, "at most two (node, prism) pairs per thread");
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  T hr[2][N1];
+#pragma unroll
+  for (int at = 0; at < NAT; ++at)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sR[(k * NAT * 16 + 16 * at + row_of<F64ROW>(g, r)) * 16 + j] = yr[at][r];
+  __syncthreads();
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int pr = threadIdx.x + p * NTH, a = pr >> 4, el = pr & 15;
+#pragma unroll
+    for (int kk = 0; kk < N1; ++kk) hr[p][kk] = pr < 16 * NPT ? sR[(kk * NAT * 16 + a) * 16 + el] : T(0);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int at = 0; at < NAT; ++at)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) sR[(k * NAT * 16 + 16 * at + row_of<F64ROW>(g, r)) * 16 + j] = yt[at][r];
+  __syncthreads();
+  if (cs.te < 0) return;
+#pragma unroll
+  for (int p = 0; p < 2; ++p) {
+    const int pr = threadIdx.x + p * NTH, a = pr >> 4, el = pr & 15;
+    if (pr >= 16 * NPT) continue;
+    T ht[N1];
+#pragma unroll
+    for (int kk = 0; kk < N1; ++kk) ht[kk] = sR[(kk * NAT * 16 + a) * 16 + el];
+    T* out = Y + ((size_t(cs.te) * NPT + a) * L + cs.layer) * N1;
+#pragma unroll 1
+    for (int c = 0; c < N1; ++c) {
+      T y = 0;
+#pragma unroll
+      for (int kk = 0; kk < N1; ++kk) y += sV[kk * N1 + c] * hr[p][kk] + sV[N1 * N1 + kk * N1 + c] * ht[kk];
+      out[c] = y;
+    }
+  }
+}
+
 // Phase 2 writing column sums (CS; 16 % L == 0, so the batch holds 16/L whole
 // columns and prism el + 1 is the layer above el).  Thread (a, el) reads its
 // partials from S, then (once every thread holds its own) writes y[c] of prism
@@ -414,9 +463,11 @@ __device__ __forceinline__ void pointwise(const T (&gv)[6][4], ACC& dr, ACC& ds,
   }
 }
 
-// FP32 / FP64 flavours (K = 4).  GT: the reference tables are read through the
-// caches instead of LDS (FP64 at P = 8, whose tables and staging buffer do not
-// fit in the LDS together); one workgroup per CU then.
+// FP32 / FP64 flavours (K = 4).  GT (FP64 at P = 8, whose padded operand
+// tables and staging buffer do not fit in the LDS together): the three
+// reference tables sit in LDS once, unpadded ([m][q][a], 87.5 KB), and serve
+// the operands of both contractions by index; the staging buffer holds one
+// half of S at a time (Yr, then Yt); one workgroup per CU.
 // GEO: G from the column factors (Gnat is then geo[t][q][8] of type T) instead
 // of the stored lane-native G.
 // CS: phase 2 writes column sums (vertical_colsum) instead of the E-layout output.
@@ -432,13 +483,18 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
   constexpr int NS4 = n_steps4<PT, PZ, F64ROW>();
   constexpr int NTAB2 = 3 * NT2 * KS * 64, NTAB4 = 3 * NAT * NS4 * 64;
   constexpr int NTH = 64 * N1;
-  __shared__ T s2buf[GT ? 1 : NTAB2];
+  constexpr int NCT = 3 * D::NQT * NPT;                    // GT: unpadded tables
+  constexpr int SH_WORDS = N1 * NAT * 16 * 16;             // GT: one half of S
+  constexpr int GT_R = KS_LDS<PT, PZ>::U_WORDS > SH_WORDS ? KS_LDS<PT, PZ>::U_WORDS : SH_WORDS;
+  __shared__ T s2buf[GT ? NCT + 8 : NTAB2];
   __shared__ T s4buf[GT ? 1 : NTAB4];
-  __shared__ T sR[KS_LDS<PT, PZ>::R_WORDS];
+  __shared__ T sR[GT ? GT_R : KS_LDS<PT, PZ>::R_WORDS];
   __shared__ T sV[2 * N1 * N1];
-  const T* __restrict__ s2 = GT ? tab2 : s2buf;
-  const T* __restrict__ s4 = GT ? tab4 : s4buf;
-  if constexpr (!GT) {
+  const T* __restrict__ s2 = s2buf;
+  const T* __restrict__ s4 = s4buf;
+  if constexpr (GT) {
+    for (int i = threadIdx.x; i < NCT + 8; i += NTH) s2buf[i] = i < NCT ? tab2[i] : T(0);
+  } else {
     for (int i = threadIdx.x; i < NTAB2; i += NTH) s2buf[i] = tab2[i];
     for (int i = threadIdx.x; i < NTAB4; i += NTH) s4buf[i] = tab4[i];
   }
@@ -450,6 +506,22 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     sV[N1 * N1 + i] = vm.Dz[i] * w;
   }
   const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  // operand of stage 2 (M_m[16 t + j][4 s + g]) and stage 4 (M_m[q][16 at + j]
+  // with q the K row of step st = 4 t + r); with GT read from the unpadded
+  // tables, where entries past a = NPT wrap into the next row (multiplied by a
+  // zero of w, or landing in output rows past NPT) and q past NQT reads 0
+  auto op2 = [&](int m, int t, int s) -> T {
+    if constexpr (GT) return s2[(m * D::NQT + 16 * t + j) * NPT + 4 * s + g];
+    else return s2[((m * NT2 + t) * KS + s) * 64 + lane];
+  };
+  auto op4 = [&](int m, int at, int st, int t, int r) -> T {
+    if constexpr (GT) {
+      const int q = 16 * t + row_of<F64ROW>(g, r);
+      return q < D::NQT ? s2[(m * D::NQT + q) * NPT + 16 * at + j] : T(0);
+    } else {
+      return s4[((m * NAT + at) * NS4 + st) * 64 + lane];
+    }
+  };
   // wave-uniform vertical level: its Bz/Dz row stays in scalar registers
   const int k = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   T bzk[N1], dzk[N1];
@@ -539,9 +611,9 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
       ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        dr = mfma4(s2[((0 * NT2 + t) * KS + s) * 64 + lane], w[s], dr);
-        ds = mfma4(s2[((1 * NT2 + t) * KS + s) * 64 + lane], w[s], ds);
-        db = mfma4(s2[((2 * NT2 + t) * KS + s) * 64 + lane], wz[s], db);
+        dr = mfma4(op2(0, t, s), w[s], dr);
+        ds = mfma4(op2(1, t, s), w[s], ds);
+        db = mfma4(op2(2, t, s), wz[s], db);
       }
       pointwise<T, ACC>(ga, dr, ds, db);
 #pragma unroll
@@ -549,9 +621,9 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
         const int st = 4 * t + r;
 #pragma unroll
         for (int at = 0; at < NAT; ++at) {
-          yr[at] = mfma4(s4[((0 * NAT + at) * NS4 + st) * 64 + lane], dr[r], yr[at]);
-          yr[at] = mfma4(s4[((1 * NAT + at) * NS4 + st) * 64 + lane], ds[r], yr[at]);
-          yt[at] = mfma4(s4[((2 * NAT + at) * NS4 + st) * 64 + lane], db[r], yt[at]);
+          yr[at] = mfma4(op4(0, at, st, t, r), dr[r], yr[at]);
+          yr[at] = mfma4(op4(1, at, st, t, r), ds[r], yr[at]);
+          yt[at] = mfma4(op4(2, at, st, t, r), db[r], yt[at]);
         }
       }
     }
@@ -566,11 +638,15 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
         // padding.  Lane (g, j) holds W at a = 4 s + g; the row's coefficients are
         // the table entries of lane 16 g (row 0 of the tile, column 4 s + g).
         T pr = 0, ps = 0, pb = 0;
+        auto row0 = [&](int m, int s) -> T {
+          if constexpr (GT) return s2[(m * D::NQT + 16 * t) * NPT + 4 * s + g];
+          else return s2[((m * NT2 + t) * KS + s) * 64 + 16 * g];
+        };
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          pr += s2[((0 * NT2 + t) * KS + s) * 64 + 16 * g] * w[s];
-          ps += s2[((1 * NT2 + t) * KS + s) * 64 + 16 * g] * w[s];
-          pb += s2[((2 * NT2 + t) * KS + s) * 64 + 16 * g] * wz[s];
+          pr += row0(0, s) * w[s];
+          ps += row0(1, s) * w[s];
+          pb += row0(2, s) * wz[s];
         }
 #pragma unroll
         for (int o = 16; o < 64; o <<= 1) {
@@ -584,11 +660,12 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
           db[0] = pb;
         }
       } else {
+        static_assert(!GT || D::NQR == 1, "GT stage 2 reads full rows of the remainder tile");
 #pragma unroll
         for (int s = 0; s < KS; ++s) {
-          dr = mfma4(s2[((0 * NT2 + t) * KS + s) * 64 + lane], w[s], dr);
-          ds = mfma4(s2[((1 * NT2 + t) * KS + s) * 64 + lane], w[s], ds);
-          db = mfma4(s2[((2 * NT2 + t) * KS + s) * 64 + lane], wz[s], db);
+          dr = mfma4(op2(0, t, s), w[s], dr);
+          ds = mfma4(op2(1, t, s), w[s], ds);
+          db = mfma4(op2(2, t, s), wz[s], db);
         }
       }
       pointwise<T, ACC>(ga, dr, ds, db);
@@ -598,13 +675,18 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
         if (row_of<F64ROW>(0, r) < D::NQR) {
 #pragma unroll
           for (int at = 0; at < NAT; ++at) {
-            yr[at] = mfma4(s4[((0 * NAT + at) * NS4 + st) * 64 + lane], dr[r], yr[at]);
-            yr[at] = mfma4(s4[((1 * NAT + at) * NS4 + st) * 64 + lane], ds[r], yr[at]);
-            yt[at] = mfma4(s4[((2 * NAT + at) * NS4 + st) * 64 + lane], db[r], yt[at]);
+            yr[at] = mfma4(op4(0, at, st, t, r), dr[r], yr[at]);
+            yr[at] = mfma4(op4(1, at, st, t, r), ds[r], yr[at]);
+            yt[at] = mfma4(op4(2, at, st, t, r), db[r], yt[at]);
           }
           ++st;
         }
       }
+    }
+    if constexpr (GT) {
+      static_assert(!CS, "GT keeps the element layout");
+      vertical_out_halves<PT, PZ, T, ACC, F64ROW>(L, cs, k, yr, yt, sR, sV, Y);
+      continue;
     }
     // S[k][h][a][el]: lane holds a = 16 at + row(g, r) of element j
 #pragma unroll

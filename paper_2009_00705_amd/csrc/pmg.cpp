@@ -504,7 +504,14 @@ static void upload_mfma(pmg_ctx* c, Level& L) {
       L.tab4lo = c->U(l4);
       L.mfx3 = true;
     }
-    if (f == MF_F64) {
+    if (f == MF_F64 && L.P == 8) {
+      // the in-plane order 8 FP64 kernel reads the unpadded tables [m][q][a]
+      std::vector<double> m3;
+      for (const Mat* M : {&re.Dr, &re.Ds, &re.B}) m3.insert(m3.end(), M->v.begin(), M->v.end());
+      L.tab2[f] = c->U(m3);
+      L.tab4[f] = L.tab2[f];
+      if (!col) L.gnat[f] = c->A<double>(ng);
+    } else if (f == MF_F64) {
       L.tab2[f] = c->U(t2);
       L.tab4[f] = c->U(t4);
       if (!col) L.gnat[f] = c->A<double>(ng);
