@@ -1234,8 +1234,8 @@ static void relayout_p(int64_t n_elem, const double* G, void* out, int flavour, 
 }
 
 // orders with MFMA kernels: (3,3), (6,6), (3,6), (4,8), (2,8) [the in-plane-
-// coarsened levels of P = 6 and P = 8] and (8,8) (its FP64 tables are read
-// through the caches); split-BF16 kernels at in-plane order 6 only
+// coarsened levels of P = 6 and P = 8] and (8,8) (its FP64 kernel with
+// unpadded LDS tables); split-BF16 kernels at in-plane order 6 only
 #define PMG_MFMA_ORDERS(X) X(3, 3) X(6, 6) X(3, 6) X(8, 8) X(4, 8) X(2, 8)
 
 void launch_g_native(int PT, int PZ, int64_t n_elem, const double* G, void* out, int flavour, hipStream_t st,
