@@ -935,6 +935,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
   __shared__ s4_t s4[NTAB4];
   __shared__ s4_t s4l[LO ? NTAB4 : 1];
   __shared__ float sR[XS::R_WORDS];
+  __shared__ float sC[CS ? 1 : 2 * N1 * N1];  // phase-2 coefficients [h][kk][c]
   for (int i = threadIdx.x; i < NTAB2; i += NTH) {
     s2[i] = tab2[i];
     if constexpr (LO) s2l[i] = tab2lo[i];
@@ -957,6 +958,17 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
   auto vD = [&](int i) {
     if constexpr (GEO) return vm.Dzw[i]; else return vm.Dz[i];
   };
+  if constexpr (!CS) {
+    // one lane copies the coefficients (uniform indices: scalar loads); the
+    // first batch's barrier publishes them
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < N1 * N1; ++i) {
+        sC[i] = vB(i);
+        sC[N1 * N1 + i] = vD(i);
+      }
+    }
+  }
   const int64_t bnd_off = CS ? int64_t(n_elem / L) * ((PT - 1) * (PT - 2) / 2) * nz : 0;
   const int64_t lb = xcd_block(gridDim.x);
   for (int64_t b = lb; b < n_batch; b += gridDim.x) {
@@ -1069,22 +1081,24 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
         }
       }
     __syncthreads();
-    // phase 2: thread (a, el) sums over the Gauss levels for its PZ+1 outputs
+    // phase 2: y[c] of (node a, prism el) = sum over the Gauss levels kk of
+    // vB[kk][c] Yr[kk][a][el] + vD[kk][c] Yt[kk][a][el]
     static_assert(16 * NPT <= NTH, "one (node, prism) pair per thread");
     const int pr2 = threadIdx.x, a2 = pr2 >> 4, el = pr2 & 15;
     const bool act = pr2 < 16 * NPT;
     const int64_t e = b * 16 + el;
     const uint32_t eu = uint32_t(e), tu = eu / uint32_t(L);  // e < 2^31 (pmg_create)
     const int te = e < n_elem ? int(tu) : -1, layer = int(eu - tu * uint32_t(L));
-    float yv[N1], zv[N1];
-    if (act) {
-#pragma unroll
-      for (int kk = 0; kk < N1; ++kk) {
-        yv[kk] = sR[x3_srow(kk, 0, a2, NPT) + el];
-        zv[kk] = sR[x3_srow(kk, 1, a2, NPT) + el];
-      }
-    }
     if constexpr (CS) {
+      // thread (a, el) sums over the Gauss levels for its PZ+1 outputs
+      float yv[N1], zv[N1];
+      if (act) {
+#pragma unroll
+        for (int kk = 0; kk < N1; ++kk) {
+          yv[kk] = sR[x3_srow(kk, 0, a2, NPT) + el];
+          zv[kk] = sR[x3_srow(kk, 1, a2, NPT) + el];
+        }
+      }
       // column sums (16 % L == 0: whole columns per batch, prism el + 1 is the
       // layer above el): y[c] of prism el to Ycol[el][a][c], then the column
       // values z = layer PZ + c, c = (layer > 0) .. PZ, of (triangle, node a),
@@ -1116,17 +1130,31 @@ __global__ __launch_bounds__(64 * (PZ + 1), (LO && PZ >= 8) ? 2 : 4) void k_ax_m
         for (int c = layer > 0 ? 1 : 0; c < N1; ++c) dst[c] = c == PZ && above ? ycol[c] + top : ycol[c];
       }
     } else {
-      if (act && te >= 0) {
-        float* out = Y + ((size_t(te) * NPT + a2) * L + layer) * N1;
-#pragma unroll 1
-        for (int c = 0; c < N1; ++c) {
-          float y = 0.f;
+      // on the FP32 matrix cores: per node a (wave k takes a = k, k + N1, ...),
+      // D[c][el] = sum_kappa C[c][kappa] S[kappa][a][el] with kappa = 2 kk + h,
+      // C[c][2 kk + h] = (h ? vD : vB)[kk][c]; M = c (N1 of 16 rows), K = 2 N1
+      // (padded to 4 KS2), N = the 16 prisms.  Lane (g, j) holds rows
+      // c = 4 g + r of prism j, the prism of this thread's te and layer.
+      constexpr int KS2 = (2 * N1 + 3) / 4;
+      float ca[KS2];
 #pragma unroll
-          for (int kk = 0; kk < N1; ++kk) {
-            y = __builtin_fmaf(vB(kk * N1 + c), yv[kk], y);
-            y = __builtin_fmaf(vD(kk * N1 + c), zv[kk], y);
-          }
-          out[c] = y;
+      for (int s = 0; s < KS2; ++s) {
+        const int kap = 4 * s + g;
+        ca[s] = (j < N1 && kap < 2 * N1) ? sC[(kap & 1) * N1 * N1 + (kap >> 1) * N1 + j] : 0.f;
+      }
+      for (int a = k; a < NPT; a += N1) {
+        f4_t acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS2; ++s) {
+          const int kap = 4 * s + g;
+          const float bv = kap < 2 * N1 ? sR[x3_srow(kap >> 1, kap & 1, a, NPT) + j] : 0.f;
+          acc = mfma4(ca[s], bv, acc);
+        }
+        if (4 * g < N1 && te >= 0) {
+          float* out = Y + ((size_t(te) * NPT + a) * L + layer) * N1 + 4 * g;
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (4 * g + r < N1) out[r] = acc[r];
         }
       }
     }
