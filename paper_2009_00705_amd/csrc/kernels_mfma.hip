@@ -255,6 +255,41 @@ __device__ __forceinline__ void vertical_out(int L, int64_t n_elem, int64_t b, c
   }
 }
 
+// vertical_out on the FP32 matrix cores: for node a (wave k takes a = k,
+// k + N1, ...) D[c][el] = sum_kappa C[c][kappa] S[kappa][a][el], kappa =
+// 2 kk + h, C[c][kappa] = sV[h][kk][c]; M = c (N1 of 16 rows), K = 2 N1 padded
+// to a multiple of 4, N = the 16 prisms.  Lane (g, j) holds rows c = 4 g + r of
+// prism j (the prism of this lane's column slot).
+template <int PT, int PZ>
+__device__ __forceinline__ void vertical_out_mfma(int L, ColSlot cs, int k, const float* __restrict__ sR,
+                                                  const float* __restrict__ sV, float* __restrict__ Y) {
+  using D = MD<PT, PZ>;
+  constexpr int N1 = D::N1, NPT = D::NPT, NAT = D::NAT, KS2 = (2 * N1 + 3) / 4;
+  static_assert(N1 <= 16, "the outputs of a node fit one 16-row tile");
+  const int lane = threadIdx.x & 63, g = lane >> 4, j = lane & 15;
+  float ca[KS2];
+#pragma unroll
+  for (int s = 0; s < KS2; ++s) {
+    const int kap = 4 * s + g;
+    ca[s] = (j < N1 && kap < 2 * N1) ? sV[(kap & 1) * N1 * N1 + (kap >> 1) * N1 + j] : 0.f;
+  }
+  const float* sb = sR + g * NAT * 256 + j;  // S[kappa = g][a = 0][el = j]
+  for (int a = k; a < NPT; a += N1) {
+    f4_t acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int s = 0; s < KS2; ++s) {
+      const float bv = 4 * s + g < 2 * N1 ? sb[(4 * s * NAT * 16 + a) * 16] : 0.f;
+      acc = mfma4(ca[s], bv, acc);
+    }
+    if (4 * g < N1 && cs.te >= 0) {
+      float* out = Y + ((size_t(cs.te) * NPT + a) * L + cs.layer) * N1 + 4 * g;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * g + r < N1) out[r] = acc[r];
+    }
+  }
+}
+
 // vertical_out with S staged one half at a time (S[k][a][el] of Yr, then of
 // Yt), for kernels whose LDS cannot hold both; the sums and their order are
 // those of vertical_out.  Every thread holds the Yr partials of its (a, el)
@@ -700,6 +735,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     __syncthreads();
     // phase 2: y[el][c][a] = sum_k Bz[k][c] Yr[k][a] + Dz[k][c] Yt[k][a]
     if constexpr (CS) vertical_colsum<PT, PZ, T>(cs.te, cs.layer, L, nz, bnd_off, sR, sV, Y);
+    else if constexpr (sizeof(T) == 4) vertical_out_mfma<PT, PZ>(L, cs, k, sR, sV, Y);
     else vertical_out<PT, PZ, T>(L, cs, sR, sV, Y);
   }
 }
