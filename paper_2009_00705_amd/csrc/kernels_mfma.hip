@@ -898,7 +898,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), PZ >= 8 ? 3 : 4) void k_ax_mfma_bf16
       vertical_colsum<PT, PZ, float>(e < n_elem ? int(tu) : -1, int(eu - tu * uint32_t(L)), L, nz, bnd_off, sR, sV,
                                      Y);
     } else {
-      vertical_out<PT, PZ, float>(L, n_elem, b, sR, sV, Y);
+      vertical_out_mfma<PT, PZ>(L, col_slot(b, threadIdx.x & 15, n_elem, L), k, sR, sV, Y);
     }
   }
 }
