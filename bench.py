@@ -33,8 +33,9 @@ METRIC = "Laplace solves/s and DOF/s to 1e-8 rel residual at P=6 (mixed/learned 
 
 def smoother_kw(a):
     """Options shared by every workload of one run: the Chebyshev interval
-    [lambda/ratio, lambda], the summation mode and the V-cycle graphs."""
-    kw = {"smooth_ratio": a.smooth_ratio, "fused_sum": 1 if a.fused_sum else 0, "graphs": 1 if a.graphs else 0}
+    [lambda/ratio, lambda], the summation modes and the V-cycle graphs."""
+    kw = {"smooth_ratio": a.smooth_ratio, "fused_sum": 1 if a.fused_sum else 0, "graphs": 1 if a.graphs else 0,
+          "dss": 1 if a.dss == "colour" else 0}
     return kw
 
 
@@ -605,6 +606,8 @@ def main():
     ap.add_argument("--smooth-ratio", type=float, default=8.0,
                     help="Chebyshev smoother interval [lambda/ratio, lambda]")
     ap.add_argument("--graphs", action="store_true", help="replay the solve's V-cycle from a captured HIP graph")
+    ap.add_argument("--dss", default="node", choices=["node", "colour"],
+                    help="direct-stiffness sum: node-centric (default) or coloured passes")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg (c5 history)")
     ap.add_argument("--no-c2", action="store_true", help="skip the FP64 c2 row")
@@ -771,7 +774,7 @@ def main():
                       "n_dof": info0["n_dof"], "n_elem": info0["n_elem"], "rtol": a.rtol,
                       "smoother": f"{a.smoother} {nu}+{nu}" + (f" on [lambda/{a.smooth_ratio:g}, lambda]" if a.smoother == "chebyshev" else "") + (f", overlap {a.overlap}" if a.smoother == "schwarz" else ""),
                       "coarsening": a.coarsening,
-                      "coarse": cinfo,
+                      "coarse": cinfo, "dss": "column sums" if a.fused_sum else a.dss,
                       "guess": "zero", "precision": best, "krylov": res["krylov"]},
            "paths": paths, "roofline": roof}
     if "fp64" in paths and best != "fp64":

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PMG_ABI_VERSION 5
+#define PMG_ABI_VERSION 6
 
 enum pmg_status {
   PMG_OK = 0,
@@ -200,6 +200,17 @@ typedef struct pmg_options {
                              benchmark meshes the GPU never waits for the
                              host's launches, so replay gains nothing there,
                              and each capture costs a V-cycle's launches    */
+  int32_t dss;            /* direct-stiffness sum of the element-layout results
+                             (Sec. 3.1): 0 (default) node-centric, one thread
+                             per node gathering its triangles' values in
+                             ascending order; 1 coloured: the triangles are
+                             coloured so that no two of a colour share a node
+                             (pmg_dss_colours), each colour's triangle columns
+                             are added into an L-vector in one launch, and one
+                             more pass applies the step's epilogue.  No
+                             atomics and a fixed order either way (bitwise
+                             reproducible); the two differ by rounding.
+                             fused_sum, where it applies, takes precedence   */
 } pmg_options;
 
 /* Geometric factors read by the MFMA element operators.  STORED: the six
@@ -282,6 +293,11 @@ int pmg_gather_map(const pmg_ctx* ctx, int level, int32_t* map);
 /* Greedy element colouring (host [n_elem]): ascending elements take the
  * smallest colour not used by a lower element sharing a node. */
 int pmg_colours(const pmg_ctx* ctx, int level, int32_t* colour);
+/* Triangle colouring of the coloured direct-stiffness sum (pmg_options.dss,
+ * host [n_triangles]): ascending triangles take the smallest colour not used
+ * by a lower triangle sharing a vertex (triangles sharing any 2D node share a
+ * vertex).  Host-only contexts too. */
+int pmg_dss_colours(const pmg_ctx* ctx, int level, int32_t* colour);
 /* xy of the surface (= 2D) nodes of the finest level, host [n_surface][2]. */
 int pmg_surface_xy(const pmg_ctx* ctx, double* xy);
 /* 1 for Dirichlet nodes of a level, host [n_dof]. */
@@ -394,7 +410,10 @@ enum pmg_kernel { PMG_K_ELEMENT_OP = 0, PMG_K_ASSEMBLE = 1, PMG_K_GEOMETRY = 2, 
 /* Average duration (ms) of `reps` back-to-back launches of one kernel of
  * level `level` on `stream`, bracketed by hipEvents on that stream (for
  * roofline measurement).  The element operator reads the level's work vector;
- * results are discarded.  PMG_K_COPY is a plain device copy of the level's
+ * results are discarded.  PMG_K_ASSEMBLE is the direct-stiffness sum of the
+ * element layout with the store epilogue, in the form pmg_options.dss selects
+ * (node-centric, or every colour pass and the epilogue pass of the coloured
+ * sum).  PMG_K_COPY is a plain device copy of the level's
  * FP64 vector (n_dof * 8 bytes read and written): the reference point that
  * scales hardware byte counters.  PMG_K_PROLONG is the prolongation from
  * level + 1 to `level` as the V-cycle runs it (node-wise where the level pair

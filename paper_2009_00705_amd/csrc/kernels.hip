@@ -321,6 +321,105 @@ template void launch_assemble<double>(const LevelView&, int, const double*, doub
 template void launch_assemble<float>(const LevelView&, int, const float*, float*, const float*, const float*, float*, double, double, double*, hipStream_t, float*);
 
 // ---------------------------------------------------------------------------
+// Coloured direct-stiffness sum (see launch_dss in kernels.hpp)
+// ---------------------------------------------------------------------------
+// One colour: item (i, a, z), z fastest, of the colour's triangles tri[i]: the
+// node's value in the triangle's column (its two layers' values at a layer
+// interface) added to S at the node.  Reads and writes run along z.
+template <typename T>
+__global__ __launch_bounds__(256) void k_dss_colour(uint32_t n_items, uint32_t nz, int L, int P, int np_tri,
+                                                    const int32_t* __restrict__ tri,
+                                                    const int32_t* __restrict__ map2d, const T* __restrict__ Y,
+                                                    T* __restrict__ S) {
+  const uint32_t colen = uint32_t(L * (P + 1));
+  for (uint64_t it = uint64_t(blockIdx.x) * 256 + threadIdx.x; it < n_items; it += uint64_t(gridDim.x) * 256) {
+    const uint32_t q = uint32_t(it) / nz, z = uint32_t(it) - q * nz;
+    const uint32_t i = q / uint32_t(np_tri), a = q - i * uint32_t(np_tri);
+    const uint32_t inc = uint32_t(tri[i]) * uint32_t(np_tri) + a;
+    int p1, p2;
+    column_pos(int(z), P, L, p1, p2);
+    const T* col = Y + size_t(inc) * colen;
+    T v = col[p1];
+    if (p2 >= 0) v += col[p2];
+    T* sp = S + size_t(uint32_t(map2d[inc])) * nz + z;
+    *sp += v;
+  }
+}
+
+// Epilogue per node from the summed S (then S back to zero); the averaging ops
+// divide by the node's number of element values, as k_assemble does.
+template <typename T, int OP>
+__global__ __launch_bounds__(256) void k_dss_finish(uint32_t n_dof, uint32_t nz, int L, int P,
+                                                    const int32_t* __restrict__ inc_ptr,
+                                                    const uint8_t* __restrict__ dir2d, int top_dir,
+                                                    T* __restrict__ S, T* __restrict__ out,
+                                                    const T* __restrict__ a1, const T* __restrict__ a2,
+                                                    T* __restrict__ a3, T omega, T c1,
+                                                    double* __restrict__ partial, T* __restrict__ a4) {
+  double acc = 0.0;
+  for (uint64_t gl = uint64_t(blockIdx.x) * 256 + threadIdx.x; gl < n_dof; gl += uint64_t(gridDim.x) * 256) {
+    const uint32_t g = uint32_t(gl), g2 = g / nz, z = g - g2 * nz;
+    const bool dir = dir2d[g2] || (top_dir && z == nz - 1);
+    const NodeIn<T> in = node_in<T, OP>(g, out, a1, a2, a3);
+    const T s = S[g];
+    S[g] = T(0);
+    if constexpr (OP == OP_AVG_RAW || OP == OP_AVG_ADD || OP == OP_AVG_STORE) {
+      int p1, p2;
+      column_pos(int(z), P, L, p1, p2);
+      const T m = T((inc_ptr[g2 + 1] - inc_ptr[g2]) * (p2 >= 0 ? 2 : 1));
+      if constexpr (OP == OP_AVG_RAW) {
+        out[g] = s / m;
+      } else {
+        const T v = dir ? T(0) : s / m;
+        if (OP == OP_AVG_ADD) out[g] = in.o + v; else out[g] = v;
+      }
+    } else {
+      node_epilogue<T, OP>(g, dir, s, in, out, const_cast<T*>(a1), a3, a4, omega, c1, acc);
+    }
+  }
+  if constexpr (OP == OP_STORE_DOT) {
+    const double b = block_sum256(acc);
+    if (threadIdx.x == 0) partial[blockIdx.x] = b;
+  }
+}
+
+template <typename T>
+void launch_dss(const LevelView& lv, const std::vector<int64_t>& tcol_ptr, int op, const T* Y, T* S, T* out,
+                const T* a1, const T* a2, T* a3, double omega, double c1, double* partial, hipStream_t st, T* a4) {
+  const int npt = lv.np_tri;
+  for (size_t c = 0; c + 1 < tcol_ptr.size(); ++c) {
+    const int64_t n_items = (tcol_ptr[c + 1] - tcol_ptr[c]) * npt * lv.nz;
+    if (n_items <= 0) continue;
+    hipLaunchKernelGGL((k_dss_colour<T>), dim3(grid_for(n_items)), dim3(256), 0, st, uint32_t(n_items),
+                       uint32_t(lv.nz), lv.L, lv.PZ, npt, lv.tcol_list + tcol_ptr[c], lv.map2d, Y, S);
+  }
+  const int grid = op == OP_STORE_DOT ? RED_BLOCKS : grid_for(lv.n_dof);
+#define PMG_DF(OPV)                                                                                          \
+  hipLaunchKernelGGL((k_dss_finish<T, OPV>), dim3(grid), dim3(256), 0, st, uint32_t(lv.n_dof), uint32_t(lv.nz), \
+                     lv.L, lv.PZ, lv.inc_ptr, lv.dir2d, lv.top_dir, S, out, a1, a2, a3, T(omega), T(c1), partial, \
+                     a4)
+  switch (op) {
+    case OP_STORE: PMG_DF(OP_STORE); break;
+    case OP_AVG_ADD: PMG_DF(OP_AVG_ADD); break;
+    case OP_RESID: PMG_DF(OP_RESID); break;
+    case OP_JACOBI: PMG_DF(OP_JACOBI); break;
+    case OP_STORE_DOT: PMG_DF(OP_STORE_DOT); break;
+    case OP_AVG_STORE: PMG_DF(OP_AVG_STORE); break;
+    case OP_CHEB: PMG_DF(OP_CHEB); break;
+    case OP_RAW: PMG_DF(OP_RAW); break;
+    case OP_AVG_RAW: PMG_DF(OP_AVG_RAW); break;
+    case OP_CHEB0: PMG_DF(OP_CHEB0); break;
+    default: break;
+  }
+#undef PMG_DF
+}
+template void launch_dss<double>(const LevelView&, const std::vector<int64_t>&, int, const double*, double*, double*,
+                                 const double*, const double*, double*, double, double, double*, hipStream_t,
+                                 double*);
+template void launch_dss<float>(const LevelView&, const std::vector<int64_t>&, int, const float*, float*, float*,
+                                const float*, const float*, float*, double, double, double*, hipStream_t, float*);
+
+// ---------------------------------------------------------------------------
 // Node sum from column sums (see launch_col_sum in kernels.hpp).  Thread per
 // global node g = n nz + z: a triangle-interior node (n >= n_bnd) reads its one
 // value, cv[g - n_bnd nz], in global order; a vertex or edge node adds the

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace pmg {
 
@@ -75,7 +76,22 @@ struct LevelView {
   const int32_t* sh_ptr;   // [n_bnd+1]
   const int32_t* sh_idx;   // [sh_ptr[n_bnd]] = t*3P + s
   int colsum;
+  // Coloured direct-stiffness sum (launch_dss): the triangles grouped by
+  // colour (no two of one colour share a vertex), ascending within a colour.
+  const int32_t* tcol_list;  // [nt]
 };
+
+// Coloured direct-stiffness sum (alternative to launch_assemble, same ops and
+// arguments): S (an L-vector of zeros) += the element values of every
+// triangle column, one launch per triangle colour (ranges tcol_ptr of
+// lv.tcol_list, host), thread per (triangle, node a, z) with z fastest: no two
+// triangles of a colour share a node, so the adds need no atomics and every
+// node sums its triangles in colour order.  Then one pass per node applies
+// the epilogue op to S and puts the zeros back.
+template <typename T>
+void launch_dss(const LevelView& lv, const std::vector<int64_t>& tcol_ptr, int op, const T* Y, T* S, T* out,
+                const T* a1, const T* a2, T* a3, double omega, double c1, double* partial, hipStream_t st,
+                T* a4 = nullptr);
 
 // Direct-stiffness sum from column sums.  A batch of 16 prisms holds 16/L whole
 // triangle columns (L divides 16), so the element operator sums each column's

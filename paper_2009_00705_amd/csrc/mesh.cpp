@@ -83,6 +83,36 @@ void Numbering::gather_map(int32_t* out) const {
     }
 }
 
+std::vector<int32_t> Numbering::tri_colours() const {
+  // triangles t and t' share a 2D node iff they share a vertex; ascending
+  // triangles take the smallest colour no lower vertex neighbour holds
+  const std::vector<Ijk> lat = tri_lattice(P);
+  int corner[3] = {-1, -1, -1};
+  for (int a = 0; a < np_tri; ++a) {
+    if (lat[a].i == 0 && lat[a].j == 0) corner[0] = a;
+    if (lat[a].i == P && lat[a].j == 0) corner[1] = a;
+    if (lat[a].i == 0 && lat[a].j == P) corner[2] = a;
+  }
+  std::vector<std::vector<int32_t>> vtri(nv);
+  for (int t = 0; t < nt; ++t)
+    for (int i = 0; i < 3; ++i) vtri[map2d[size_t(t) * np_tri + corner[i]]].push_back(t);
+  std::vector<int32_t> col(size_t(nt), -1);
+  std::vector<char> used;
+  for (int t = 0; t < nt; ++t) {
+    used.assign(64, 0);
+    for (int i = 0; i < 3; ++i)
+      for (int32_t u : vtri[map2d[size_t(t) * np_tri + corner[i]]])
+        if (u < t) {
+          if (col[u] >= int32_t(used.size())) used.resize(size_t(col[u]) + 1, 0);
+          used[size_t(col[u])] = 1;
+        }
+    int32_t c = 0;
+    while (c < int32_t(used.size()) && used[size_t(c)]) ++c;
+    col[size_t(t)] = c;
+  }
+  return col;
+}
+
 std::vector<int32_t> Numbering::colours() const {
   // elements (t, layer) and (t', layer') share a node iff t and t' share a
   // vertex and |layer - layer'| <= 1

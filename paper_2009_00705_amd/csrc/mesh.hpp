@@ -38,6 +38,7 @@ struct Numbering {
   void build(const MeshIn& m, int P, int PZ = -1);
   void gather_map(int32_t* out) const;       // [n_elem][np]
   std::vector<int32_t> colours() const;      // greedy, ascending element order
+  std::vector<int32_t> tri_colours() const;  // [nt] greedy over vertex-sharing triangles, ascending
 };
 
 // xy of the order-P triangle nodes of every triangle, [nt][np_tri][2]: affine

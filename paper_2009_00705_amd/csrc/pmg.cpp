@@ -79,6 +79,8 @@ struct Level {
   // device
   int32_t *map2d = nullptr, *inc_ptr = nullptr, *inc = nullptr;
   int32_t *sh_ptr = nullptr, *sh_idx = nullptr;  // boundary nodes of the column-sum path
+  std::vector<int64_t> tcol_ptr;                  // coloured sum: colour ranges of tcol_list (host)
+  int32_t* tcol_list = nullptr;                   // triangles grouped by colour (device)
   int64_t n_bnd = 0;
   int nint = 0, colsum = 0;
   uint8_t* dir2d = nullptr;
@@ -219,6 +221,7 @@ struct pmg_ctx {
   int reuse = PMG_REUSE_NONE;
   double* eta_flat = nullptr;
   std::vector<void*> allocs;
+  double* dss_s = nullptr;  // accumulator of the coloured direct-stiffness sum (pmg_options.dss)
 
   template <typename T> T* A(size_t n) {
     T* p = pmg::dalloc<T>(n);
@@ -656,9 +659,23 @@ static void upload_levels(pmg_ctx* c) {
       }
       L.colsum = ok ? 1 : 0;
     }
+    if (c->opt.dss == 1) {
+      // triangles grouped by colour, ascending within a colour (32-bit item ids per colour)
+      if (int64_t(L.num.nt) * L.num.np_tri * L.num.nz >= (int64_t(1) << 32))
+        throw Error(PMG_EINVAL, "coloured sum: 2^32 or more (triangle, node, z) items on a level");
+      const std::vector<int32_t> col = L.num.tri_colours();
+      const int ncol = col.empty() ? 0 : 1 + *std::max_element(col.begin(), col.end());
+      L.tcol_ptr.assign(size_t(ncol) + 1, 0);
+      for (int32_t v : col) L.tcol_ptr[size_t(v) + 1]++;
+      for (int k = 0; k < ncol; ++k) L.tcol_ptr[size_t(k) + 1] += L.tcol_ptr[size_t(k)];
+      std::vector<int32_t> list(col.size());
+      std::vector<int64_t> fill(L.tcol_ptr.begin(), L.tcol_ptr.end() - 1);
+      for (int t = 0; t < int(col.size()); ++t) list[size_t(fill[size_t(col[size_t(t)])]++)] = t;
+      L.tcol_list = c->U(list);
+    }
     L.view = LevelView{L.P, L.PZ, L.num.L, L.num.nt, re.np_tri, re.np, re.nq, L.num.n2d, L.num.nz, N, E,
                        L.map2d, L.inc_ptr, L.inc, L.dir2d, L.top_dir, L.n_bnd, L.nint, L.sh_ptr, L.sh_idx,
-                       L.colsum};
+                       L.colsum, L.tcol_list};
     if (i + 1 < c->nl) {
       const RefElem& rc = *c->lv[i + 1].re;
       // coarse nodal basis at the fine nodes
@@ -678,6 +695,11 @@ static void upload_levels(pmg_ctx* c) {
   for (int i = 0; i < c->nl; ++i)
     maxE = std::max<int64_t>(maxE, int64_t(c->lv[i].num.nt) * c->lv[i].num.np_tri * c->lv[i].num.nz);
   c->Y = c->A<double>(size_t(maxE));
+  if (c->opt.dss == 1) {
+    // L-vector accumulator of the coloured sum: zero here, put back to zero by every sum
+    c->dss_s = c->A<double>(size_t(c->lv[0].num.n_dof));
+    HIPCHK(hipMemset(c->dss_s, 0, size_t(c->lv[0].num.n_dof) * sizeof(double)));
+  }
   c->partial = c->A<double>(2 * RED_BLOCKS);
   c->scal = c->A<double>(N_SCAL);
   HIPCHK(hipHostMalloc((void**)&c->scal_h, N_SCAL * sizeof(double), hipHostMallocDefault));
@@ -776,10 +798,24 @@ static bool ax_elem(pmg_ctx* c, int i, const T* x, hipStream_t st, bool colsum =
   return ok;
 }
 
+// Direct-stiffness sum of the element layout in c->Y with epilogue op: the
+// node-centric kernel, or the coloured passes (pmg_options.dss = 1).
+template <typename T>
+static void dss_sum(pmg_ctx* c, int i, int op, T* out, const T* a1, const T* a2, T* a3, double w, double c1,
+                    hipStream_t st, T* a4 = nullptr) {
+  const Level& L = c->lv[i];
+  const T* Y = reinterpret_cast<const T*>(c->Y);
+  if (c->opt.dss == 1)
+    launch_dss<T>(L.view, L.tcol_ptr, op, Y, reinterpret_cast<T*>(c->dss_s), out, a1, a2, a3, w, c1, c->partial, st,
+                  a4);
+  else
+    launch_assemble<T>(L.view, op, Y, out, a1, a2, a3, w, c1, c->partial, st, a4);
+}
+
 template <typename T>
 static void assemble(pmg_ctx* c, int i, int op, T* out, const T* a1, const T* a2, T* a3, double w, double c1,
                      hipStream_t st) {
-  launch_assemble<T>(c->lv[i].view, op, reinterpret_cast<const T*>(c->Y), out, a1, a2, a3, w, c1, c->partial, st);
+  dss_sum<T>(c, i, op, out, a1, a2, a3, w, c1, st);
 }
 
 // Prolongation from level i+1 to level i, then op (OP_AVG_ADD, OP_AVG_STORE or
@@ -808,7 +844,7 @@ static void apply_op(pmg_ctx* c, int i, const T* x, int op, T* out, const T* a1,
     return;
   }
   ax_elem<T>(c, i, x, st);
-  launch_assemble<T>(L.view, op, reinterpret_cast<const T*>(c->Y), out, a1, a2, a3, w, c1, c->partial, st, a4);
+  dss_sum<T>(c, i, op, out, a1, a2, a3, w, c1, st, a4);
 }
 
 template <typename T>
@@ -2042,6 +2078,7 @@ void pmg_options_default(pmg_options* o) {
   o->geometry = PMG_GEOM_COLUMN;
   o->PZ = 0;
   o->fused_sum = 0;
+  o->dss = 0;
   o->graphs = 0;
 }
 
@@ -2067,6 +2104,7 @@ int pmg_create(const pmg_mesh* m, const pmg_options* o, pmg_ctx** out) {
     if (o->coarsening < 0 || o->coarsening > 2) throw Error(PMG_EINVAL, "bad coarsening");
     if (o->PZ > 8) throw Error(PMG_EINVAL, "PZ must be in 1..8 (or <= 0 for P)");
     if (o->geometry < 0 || o->geometry > 1) throw Error(PMG_EINVAL, "bad geometry mode");
+    if (o->dss < 0 || o->dss > 1) throw Error(PMG_EINVAL, "bad dss mode");
     if (o->smoother == PMG_SMOOTH_CHEBYSHEV && !(o->smooth_ratio > 1.0))
       throw Error(PMG_EINVAL, "smooth_ratio must exceed 1");
     c = new pmg_ctx();
@@ -2139,6 +2177,16 @@ int pmg_gather_map(const pmg_ctx* c, int level, int32_t* map) {
   PMG_TRY(const_cast<pmg_ctx*>(c), {
     check_level(c, level);
     c->lv[level].num.gather_map(map);
+  });
+  return PMG_OK;
+}
+
+int pmg_dss_colours(const pmg_ctx* c, int level, int32_t* colour) {
+  if (!c || !colour) return PMG_EINVAL;
+  PMG_TRY(const_cast<pmg_ctx*>(c), {
+    check_level(c, level);
+    const std::vector<int32_t> col = c->lv[level].num.tri_colours();
+    std::copy(col.begin(), col.end(), colour);
   });
   return PMG_OK;
 }

@@ -54,7 +54,7 @@ class Options(C.Structure):
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
                 ("coarsening", C.c_int32), ("overlap", C.c_int32), ("schwarz_store", C.c_int32),
                 ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32), ("PZ", C.c_int32),
-                ("fused_sum", C.c_int32), ("graphs", C.c_int32)]
+                ("fused_sum", C.c_int32), ("graphs", C.c_int32), ("dss", C.c_int32)]
 
 
 class FnpfStats(C.Structure):
@@ -106,6 +106,7 @@ SIGNATURES = {
     "pmg_level_info_get": (_I, [_VP, _I, C.POINTER(LevelInfo)]),
     "pmg_gather_map": (_I, [_VP, _I, _VP]),
     "pmg_colours": (_I, [_VP, _I, _VP]),
+    "pmg_dss_colours": (_I, [_VP, _I, _VP]),
     "pmg_surface_xy": (_I, [_VP, _VP]),
     "pmg_dirichlet_mask": (_I, [_VP, _I, _VP]),
     "pmg_set_surface": (_I, [_VP, _VP, _VP]),
@@ -237,6 +238,7 @@ class Context:
         m.nv = xy.shape[0]
         m.xy = xy.ctypes.data_as(C.POINTER(C.c_double))
         m.nt = tri.shape[0]
+        self.n_tri = int(tri.shape[0])
         m.tri = tri.ctypes.data_as(C.POINTER(C.c_int32))
         m.edge_tag = tags.ctypes.data_as(C.POINTER(C.c_int32))
         m.ncurved = ce.shape[0]
@@ -280,6 +282,12 @@ class Context:
     def colours(self, level: int = 0) -> np.ndarray:
         out = np.empty(self.levels[level]["n_elem"], dtype=np.int32)
         self._c(lib().pmg_colours(self.h, level, out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def dss_colours(self, level: int = 0) -> np.ndarray:
+        """Triangle colours of the coloured direct-stiffness sum (pmg_dss_colours)."""
+        out = np.empty(self.n_tri, dtype=np.int32)
+        self._c(lib().pmg_dss_colours(self.h, level, out.ctypes.data_as(C.c_void_p)))
         return out
 
     def surface_xy(self) -> np.ndarray:

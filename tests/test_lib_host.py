@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
         assert n in pmg.SIGNATURES, f"binding lacks {n}"
-    assert L.pmg_abi_version() == 5
+    assert L.pmg_abi_version() == 6
 
 
 def _host_ctx(mesh, P, **kw):
@@ -68,6 +68,37 @@ def test_colours_bit_exact(meshname, P):
     m = MESHES[meshname]()
     ctx = _host_ctx(m, P)
     np.testing.assert_array_equal(ctx.colours(0), M.Numbering(m, P).colours().astype(np.int32))
+
+
+@pytest.mark.parametrize("meshname", sorted(MESHES))
+@pytest.mark.parametrize("P", [1, 3, 6])
+def test_dss_colours_bit_exact(meshname, P):
+    """Triangle colours of the coloured direct-stiffness sum: greedy over
+    ascending triangles, each taking the smallest colour of no lower triangle
+    that shares a 2D node with it (brute force over the 2D gather map), so no
+    two triangles of a colour share a node; the same on every level."""
+    m = MESHES[meshname]()
+    ctx = _host_ctx(m, P)
+    for lvl in range(ctx.n_levels):
+        p = ctx.levels[lvl]["order"]
+        m2 = M.Numbering(m, p).map2d
+        nt = m2.shape[0]
+        node_tris = {}
+        for t in range(nt):
+            for g in set(m2[t].tolist()):
+                node_tris.setdefault(g, []).append(t)
+        want = -np.ones(nt, dtype=np.int32)
+        for t in range(nt):
+            used = {int(want[u]) for g in set(m2[t].tolist()) for u in node_tris[g] if u < t}
+            c = 0
+            while c in used:
+                c += 1
+            want[t] = c
+        got = ctx.dss_colours(lvl)
+        np.testing.assert_array_equal(got, want, err_msg=f"level {lvl}")
+        for g, ts in node_tris.items():
+            assert len({int(got[t]) for t in ts}) == len(ts), (lvl, g)
+    ctx.close()
 
 
 @pytest.mark.parametrize("meshname", sorted(MESHES))
