@@ -1765,7 +1765,7 @@ static void learned_guess(pmg_ctx* c, pmg_net* n, const double* surf, const doub
   features(c, surf, p1, p2, p3, nullptr, n->X1, nullptr, st);
   launch_normalize(n->X1, n1, n->din, n->mean, n->istd, n->Xn, st);
   const int L = int(n->fin.size());
-  const int chunk = 16384;
+  const int chunk = 65536;  // one or two chunks on the benchmark meshes: fewer, larger GEMMs
   for (int64_t r0 = 0; r0 < n1; r0 += chunk) {
     const int B = int(std::min<int64_t>(chunk, n1 - r0));
     net_forward(n, n->Xn + r0 * n->din, B, st);
