@@ -469,14 +469,13 @@ def bench_history(a):
     print(json.dumps(out), flush=True)
 
 
-def bench_scaling(a):
+def scaling_rows(a, steps, warmup, log):
     """O(n) series (Sec. 6.3): FP64 PCG with the exact coarse solve on split-quad
     boxes refined at a fixed element aspect ratio, (N, L) = (4,1) ... (32,8) at
     P = 6; mean convergence factor q, iterations and time per node."""
     import torch
     from paper_2009_00705_amd import pmg
     from paper_2009_00705_amd import workloads as W
-    log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
     nu = a.nu if a.nu > 0 else (3 if a.smoother == "chebyshev" else 2)
     rows = []
     for nq, L in ((4, 1), (8, 2), (16, 4), (32, 8)):
@@ -489,16 +488,16 @@ def bench_scaling(a):
         surf = torch.from_numpy(W.mode_sum(xy[:, 0], xy[:, 1], eta, W.mode_amplitudes(3), W.mode_pairs())).cuda()
         n = ctx.levels[0]["n_dof"]
         phi = torch.zeros(n, dtype=torch.float64, device="cuda")
-        for _ in range(a.warmup):
+        for _ in range(warmup):
             phi.zero_()
             ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(a.steps):
+        for _ in range(steps):
             phi.zero_()
             rc, st = ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / a.steps
+        dt = (time.perf_counter() - t0) / steps
         q = st["q"]
         row = {"N": nq, "L": L, "prisms": ctx.levels[0]["n_elem"], "n_dof": n, "iters": st["iters"],
                "q_mean": float(np.exp(np.mean(np.log(q)))), "q_max": float(q.max()), "ms_per_solve": dt * 1e3,
@@ -506,6 +505,23 @@ def bench_scaling(a):
         rows.append(row)
         log(f"[scaling] {row}")
         ctx.close()
+    return rows, nu
+
+
+def o_n_leg(a, log):
+    """The O(n) series as a compact leg of the default run (two timed solves
+    per mesh): q stays flat while the element count grows 64x."""
+    rows, nu = scaling_rows(a, 2, 1, log)
+    qs = [r["q_mean"] for r in rows]
+    return {"workload": f"box [0,2pi]^2 x [-1,0], (N,L) = (4,1)..(32,8), P={a.P}, FP64 PCG, exact coarse solve, "
+                        f"{a.smoother} {nu}+{nu}, rtol {a.rtol:g}",
+            "q_max_over_min": round(max(qs) / min(qs), 4), "rows": rows}
+
+
+def bench_scaling(a):
+    """O(n) series as its own workload (see scaling_rows)."""
+    log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
+    rows, nu = scaling_rows(a, a.steps, a.warmup, log)
     qs = [r["q_mean"] for r in rows]
     out = {"metric": "mean convergence factor q and time per node over refinement at a fixed aspect ratio",
            "value": round(max(qs) / min(qs), 4), "unit": "max q / min q", "n_gpus": 1, "steps": a.steps,
@@ -783,6 +799,8 @@ def main():
         out["c2_fp64"] = c2_fp64_row(a, log)
     if a.workload == "c3" and a.P == 6 and not a.no_learned:
         out["learned"] = learned_leg(a, log)
+    if a.workload == "c3" and a.P == 6 and not a.no_c2:
+        out["o_n"] = o_n_leg(a, log)
     if not a.no_cpu:
         p64 = paths.get("fp64", res)
         out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"],
