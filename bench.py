@@ -533,15 +533,14 @@ def bench_scaling(a):
     print(json.dumps(out), flush=True)
 
 
-def bench_cylinder(a):
+def cylinder_run(a, precisions, steps, warmup, log):
     """C4: unstructured cylinder mesh at P = 6.  (i) no-flux cylinder, walls and
-    bottom with the k = 1 linear wave on the surface, every precision; (ii) the
+    bottom with the k = 1 linear wave on the surface, each precision; (ii) the
     uniform flow past the cylinder with Dirichlet surface and walls, against its
     closed form."""
     import torch
     from paper_2009_00705_amd import pmg
     from paper_2009_00705_amd import workloads as W
-    log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
     nu = a.nu if a.nu > 0 else 3
     mesh = W.config_mesh("c4")
     paths = {}
@@ -555,18 +554,18 @@ def bench_cylinder(a):
     top = np.arange(info0["n_dof"]) % (4 * a.P + 1) == 4 * a.P
     surf = torch.from_numpy(np.ascontiguousarray(field[top])).cuda()
     phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
-    for prec in [p for p in a.precisions.split(",") if p]:
+    for prec in precisions:
         ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
-        for _ in range(a.warmup):
+        for _ in range(warmup):
             phi.zero_()
             ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(a.steps):
+        for _ in range(steps):
             phi.zero_()
             rc, st = ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / a.steps
+        dt = (time.perf_counter() - t0) / steps
         paths[prec] = {"solves_per_s": 1 / dt, "ms_per_solve": dt * 1e3, "dof_per_s": info0["n_dof"] / dt,
                        "iters": st["iters"], "rel_res": st["rel_res"], "status": int(rc)}
         log(f"[c4] no-flux cylinder {prec}: {paths[prec]}")
@@ -582,6 +581,24 @@ def bench_cylinder(a):
     err = float(np.abs(phi.cpu().numpy() - exact).max() / np.abs(exact).max())
     log(f"[c4] uniform flow past the cylinder: {st['iters']} iterations, max error vs closed form {err:.3e}")
     ctx.close()
+    check = {"iters": st["iters"], "rel_res": st["rel_res"], "max_rel_error": err}
+    return paths, info0, cinfo, check
+
+
+def c4_leg(a, log):
+    """C4 as a compact leg of the default run: FP64 and the split-BF16 path
+    (two timed solves each) and the uniform-flow check."""
+    paths, info0, cinfo, check = cylinder_run(a, ("fp64", "bf16x3"), 2, 1, log)
+    return {"workload": f"c4: seeded Delaunay cylinder mesh, {info0['n_elem']} prisms, P={a.P}, "
+                        f"{info0['n_dof']} nodes, no-flux cylinder, k=1 surface data, rtol {a.rtol:g}",
+            "paths": paths, "speedup_vs_fp64": paths["bf16x3"]["solves_per_s"] / paths["fp64"]["solves_per_s"],
+            "uniform_flow_check": check}
+
+
+def bench_cylinder(a):
+    """C4 as its own workload (see cylinder_run), every precision of --precisions."""
+    log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
+    paths, info0, cinfo, check = cylinder_run(a, [p for p in a.precisions.split(",") if p], a.steps, a.warmup, log)
     best = max(paths, key=lambda k: paths[k]["solves_per_s"])
     out = {"metric": METRIC, "value": round(paths[best]["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": round(paths[best]["ms_per_solve"], 3),
@@ -591,7 +608,7 @@ def bench_cylinder(a):
                                   "cylinder, k=1 surface data", "n_dof": info0["n_dof"], "rtol": a.rtol,
                       "coarse": cinfo, "precision": best},
            "paths": paths,
-           "uniform_flow_check": {"iters": st["iters"], "rel_res": st["rel_res"], "max_rel_error": err}}
+           "uniform_flow_check": check}
     if "fp64" in paths:
         out["speedup_vs_fp64"] = paths[best]["solves_per_s"] / paths["fp64"]["solves_per_s"]
     print(json.dumps(out), flush=True)
@@ -626,7 +643,7 @@ def main():
                     help="direct-stiffness sum: node-centric (default) or coloured passes")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg (c5 history)")
-    ap.add_argument("--no-c2", action="store_true", help="skip the FP64 c2 row")
+    ap.add_argument("--no-c2", action="store_true", help="skip the FP64 c2 row, the O(n) series and the c4 leg")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--kernel-only", action="store_true",
@@ -801,6 +818,7 @@ def main():
         out["learned"] = learned_leg(a, log)
     if a.workload == "c3" and a.P == 6 and not a.no_c2:
         out["o_n"] = o_n_leg(a, log)
+        out["c4"] = c4_leg(a, log)
     if not a.no_cpu:
         p64 = paths.get("fp64", res)
         out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"],
