@@ -595,6 +595,44 @@ def c4_leg(a, log):
             "uniform_flow_check": check}
 
 
+def p8_leg(a, log):
+    """c3 at P = 8 (levels (8,8) ... (1,1), in-plane first) as a compact leg of
+    the default run: FP64 PCG and the FP32 V-cycle (the fastest mixed path at
+    this order), two timed solves each."""
+    import torch
+    from paper_2009_00705_amd import pmg
+    from paper_2009_00705_amd import workloads as W
+    mesh = W.config_mesh("c3")
+    ctx = pmg.Context(mesh, P=8, coarse="chebyshev", smoother="chebyshev", nu1=3, nu2=3, coarsening=a.coarsening,
+                      **smoother_kw(a))
+    info0 = ctx.levels[0]
+    xy = ctx.surface_xy()
+    eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
+    ctx.set_surface(torch.from_numpy(eta).cuda())
+    surf = torch.from_numpy(W.mode_sum(xy[:, 0], xy[:, 1], eta, W.mode_amplitudes(3), W.mode_pairs())).cuda()
+    phi = torch.zeros(info0["n_dof"], dtype=torch.float64, device="cuda")
+    paths = {}
+    for prec in ("fp64", "fp32"):
+        ctx.set_solver(prec, "pcg" if prec == "fp64" else "fpcg")
+        phi.zero_()
+        ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(2):
+            phi.zero_()
+            rc, st = ctx.solve(phi, phi_surf=surf, rtol=a.rtol, imax=500)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 2
+        paths[prec] = {"solves_per_s": 1 / dt, "ms_per_solve": dt * 1e3, "dof_per_s": info0["n_dof"] / dt,
+                       "iters": st["iters"], "rel_res": st["rel_res"], "status": int(rc)}
+        log(f"[P8] {prec}: {paths[prec]}")
+    levels = [[l["order"], l["order_z"]] for l in ctx.levels]
+    ctx.close()
+    return {"workload": f"c3 at P=8: {info0['n_elem']} prisms, {info0['n_dof']} nodes, levels {levels}, "
+                        f"chebyshev 3+3, rtol {a.rtol:g}",
+            "paths": paths, "speedup_vs_fp64": paths["fp32"]["solves_per_s"] / paths["fp64"]["solves_per_s"]}
+
+
 def bench_cylinder(a):
     """C4 as its own workload (see cylinder_run), every precision of --precisions."""
     log = (lambda *x: None) if a.quiet else (lambda *x: print(*x, file=sys.stderr, flush=True))
@@ -643,7 +681,7 @@ def main():
                     help="direct-stiffness sum: node-centric (default) or coloured passes")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned warm-start leg (c5 history)")
-    ap.add_argument("--no-c2", action="store_true", help="skip the FP64 c2 row, the O(n) series and the c4 leg")
+    ap.add_argument("--no-c2", action="store_true", help="skip the FP64 c2 row, the O(n) series and the c4 and P = 8 legs")
     ap.add_argument("--quiet", action="store_true")
     ap.add_argument("--train-steps", type=int, default=3000)
     ap.add_argument("--kernel-only", action="store_true",
@@ -819,6 +857,7 @@ def main():
     if a.workload == "c3" and a.P == 6 and not a.no_c2:
         out["o_n"] = o_n_leg(a, log)
         out["c4"] = c4_leg(a, log)
+        out["p8"] = p8_leg(a, log)
     if not a.no_cpu:
         p64 = paths.get("fp64", res)
         out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"],
