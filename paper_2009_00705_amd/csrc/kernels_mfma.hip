@@ -172,7 +172,8 @@ __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int n
 }
 // Per-use form for the BF16 and split-BF16 kernels: the slot is derived where it
 // is used, so it is not held across the batch (at their 128-VGPR cap that costs
-// more than the repeated division: 189 -> 208 us for the split kernel at c3).
+// more than the repeated division: 189 -> 208 us for the split kernel on the
+// 131,072-prism box at P = 6).
 template <int PT, int PZ, typename T>
 __device__ __forceinline__ void stage_u(const int32_t* __restrict__ map2d, int L, int nz, int64_t n_elem,
                                         int64_t b, const T* __restrict__ u, T* __restrict__ sR) {

@@ -21,8 +21,8 @@ namespace pmg {
 // The kept local inverses are symmetric: each is stored as the SZ_TS x SZ_TS
 // tiles (I, J), I <= J, of its upper block triangle, tile J(J+1)/2 + I at
 // SZ_TS^2 (J(J+1)/2 + I); entries past the subdomain size are zero.  About
-// 58% of the full square at the sizes of the c3 finest level (428 nodes on
-// average).
+// 58% of the full square for subdomains of 428 nodes (the mean of the finest
+// level of the 131,072-prism box at P = 6, overlap 1).
 constexpr int SZ_TS = 32;
 inline int64_t sz_tiles(int n) {
   const int64_t t = (n + SZ_TS - 1) / SZ_TS;
