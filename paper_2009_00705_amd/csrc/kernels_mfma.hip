@@ -640,8 +640,57 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     T gp, gps, gps2;
     if constexpr (GEO) geo_lane<T>(cs, L, T(1), vm.zh[k], tri, gp, gps, gps2);
     T ga[6][4];
+    // GT: G one row at a time (the next row's loads in flight), pointwise and
+    // stage 4 per row: six live factors instead of 24 plus four rows of loads
+    auto g_row = [&](int t, int r, T (&gv)[6]) {
+      if constexpr (GEO) {
+        const int q = 16 * t + row_of<F64ROW>(g, r);
+        const int64_t tc = tri >= 0 ? tri : 0;
+        T bq[8];
+        load8((const T*)Gnat + (tc * D::NQT + (q < D::NQT ? q : D::NQT - 1)) * 8, bq);
+        gv[0] = bq[0];
+        gv[1] = bq[1];
+        gv[3] = bq[3];
+        gv[5] = gps2 * bq[5] + bq[6];
+        gv[2] = gps * bq[2];
+        gv[4] = gps * bq[4];
+      } else {
+#pragma unroll
+        for (int m = 0; m < 6; ++m) gv[m] = T(gld_any(Gnat, blk + m * MST + t * 256 + lane * 4 + r));
+      }
+    };
 #pragma unroll 1
     for (int t = 0; t < D::NTF; ++t) {
+      if constexpr (GT) {
+        T gn[6];
+        g_row(t, 0, gn);
+        ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          dr = mfma4(op2(0, t, s), w[s], dr);
+          ds = mfma4(op2(1, t, s), w[s], ds);
+          db = mfma4(op2(2, t, s), wz[s], db);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          T gv[6];
+#pragma unroll
+          for (int m = 0; m < 6; ++m) gv[m] = gn[m];
+          if (r + 1 < 4) g_row(t, r + 1, gn);
+          const T ur = dr[r], us = ds[r], ut = db[r];
+          const T pr = gv[0] * ur + gv[1] * us + gv[2] * ut;
+          const T ps = gv[1] * ur + gv[3] * us + gv[4] * ut;
+          const T pt = gv[2] * ur + gv[4] * us + gv[5] * ut;
+          const int st = 4 * t + r;
+#pragma unroll
+          for (int at = 0; at < NAT; ++at) {
+            yr[at] = mfma4(op4(0, at, st, t, r), pr, yr[at]);
+            yr[at] = mfma4(op4(1, at, st, t, r), ps, yr[at]);
+            yt[at] = mfma4(op4(2, at, st, t, r), pt, yt[at]);
+          }
+        }
+        continue;
+      }
       if constexpr (GEO) load_geo<T, PT, PZ, F64ROW, true>((const T*)Gnat, tri, t, g, gp, gps, gps2, ga);
       else load_full<T>(Gnat, blk, MST, t, lane, ga);
       ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
