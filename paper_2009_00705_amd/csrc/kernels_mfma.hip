@@ -640,8 +640,10 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     T gp, gps, gps2;
     if constexpr (GEO) geo_lane<T>(cs, L, T(1), vm.zh[k], tri, gp, gps, gps2);
     T ga[6][4];
-    // GT: G one row at a time (the next row's loads in flight), pointwise and
+    // FP64: G one row at a time (the next row's loads in flight), pointwise and
     // stage 4 per row: six live factors instead of 24 plus four rows of loads
+    // (FP32 measured slower this way at order 6 and keeps the whole tile)
+    constexpr bool ROWWISE = sizeof(T) == 8;
     auto g_row = [&](int t, int r, T (&gv)[6]) {
       if constexpr (GEO) {
         const int q = 16 * t + row_of<F64ROW>(g, r);
@@ -661,7 +663,7 @@ __global__ __launch_bounds__(64 * (PZ + 1), GT ? 1 : (sizeof(T) == 8 ? 2 : (PZ >
     };
 #pragma unroll 1
     for (int t = 0; t < D::NTF; ++t) {
-      if constexpr (GT) {
+      if constexpr (ROWWISE) {
         T gn[6];
         g_row(t, 0, gn);
         ACC dr = {0, 0, 0, 0}, ds = {0, 0, 0, 0}, db = {0, 0, 0, 0};
