@@ -35,7 +35,7 @@ def smoother_kw(a):
     """Options shared by every workload of one run: the Chebyshev interval
     [lambda/ratio, lambda], the summation modes and the V-cycle graphs."""
     kw = {"smooth_ratio": a.smooth_ratio, "fused_sum": 1 if a.fused_sum else 0, "graphs": 1 if a.graphs else 0,
-          "dss": 1 if a.dss == "colour" else 0}
+          "dss": 1 if a.dss == "colour" else 0, "nu1_coarse": a.nu_coarse, "nu2_coarse": a.nu_coarse}
     return kw
 
 
@@ -99,7 +99,7 @@ def op_bytes(info0, nt, np_tri, prec, P):
     return geo + info0["n_dof"] * s_v + info0["n_elem"] * info0["np"] * s_v + nt * np_tri * 4
 
 
-def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening, smooth_ratio=8.0):
+def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening, smooth_ratio=8.0, nu_coarse=-1):
     """One oracle FP64 PCG solve (rtol 1e-8) of an n_side x n_side x n_layers slice
     of the box workload: (set-up s, solve s, iterations, prisms, nodes)."""
     import oracle.mesh as OM
@@ -110,8 +110,9 @@ def _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening, smooth_ra
     num = OM.Numbering(m, P)
     xy = OM.unique_xy_2d(m, num)
     eta = W.surface_elevation_c2(xy[:, 0], xy[:, 1])
+    nc = None if nu_coarse < 0 else nu_coarse
     h = mg.Hierarchy(m, P, eta, nu1=nu, nu2=nu, smoother=smoother, coarse="exact", coarsening=coarsening,
-                     smooth_ratio=smooth_ratio)
+                     smooth_ratio=smooth_ratio, nu1_coarse=nc, nu2_coarse=nc)
     t_setup = time.perf_counter() - t0
     xyz = OM.node_xyz(m, num, eta)
     phi_dir = W.mode_sum(xyz[:, 0], xyz[:, 1], xyz[:, 2], W.mode_amplitudes(3), W.mode_pairs())
@@ -141,7 +142,7 @@ def cheb_bytes(info0, nt, np_tri, prec, P):
 
 
 def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16, n_layers=4, coarsening="both",
-                 smooth_ratio=8.0):
+                 smooth_ratio=8.0, nu_coarse=-1):
     """The oracle's complete FP64 PCG solve on slices of the workload, scaled to the full mesh.
 
     The slices are the same split-quad box, order, layer count, surface
@@ -162,9 +163,9 @@ def cpu_baseline(P, nu, smoother, iters_full, n_elem_full, n_dof_full, n_side=16
     for label, nthreads in (("all", cores), ("one", 1)):
         lim = threadpool_limits(limits=nthreads) if threadpool_limits else None
         try:
-            small = (_oracle_slice_solve(P, nu, smoother, n_side // 2, n_layers, coarsening, smooth_ratio)
+            small = (_oracle_slice_solve(P, nu, smoother, n_side // 2, n_layers, coarsening, smooth_ratio, nu_coarse)
                      if label == "all" else None)
-            big = _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening, smooth_ratio)
+            big = _oracle_slice_solve(P, nu, smoother, n_side, n_layers, coarsening, smooth_ratio, nu_coarse)
         finally:
             if lim is not None:
                 lim.unregister()
@@ -665,6 +666,8 @@ def main():
     ap.add_argument("--smoother", default="chebyshev", choices=["chebyshev", "jacobi", "schwarz"])
     ap.add_argument("--nu", type=int, default=0,
                     help="smoothing degree/sweeps (0: 3 Chebyshev, 2 Jacobi, 1 Schwarz)")
+    ap.add_argument("--nu-coarse", type=int, default=-1,
+                    help="pre and post sweeps of the levels below the finest (-1: those of the finest level)")
     ap.add_argument("--overlap", type=int, default=1, help="Schwarz overlap (-1: refined)")
     ap.add_argument("--omega", type=float, default=0.0, help="smoother damping on every level (0: automatic)")
     ap.add_argument("--reuse", default="none", choices=["none", "t0", "lin"],
@@ -843,7 +846,7 @@ def main():
            "data": "synthetic", "dof_per_s": res["dof_per_s"],
            "config": {"workload": wl_desc, "P": a.P, "levels": [[l["order"], l["order_z"]] for l in ctx.levels],
                       "n_dof": info0["n_dof"], "n_elem": info0["n_elem"], "rtol": a.rtol,
-                      "smoother": f"{a.smoother} {nu}+{nu}" + (f" on [lambda/{a.smooth_ratio:g}, lambda]" if a.smoother == "chebyshev" else "") + (f", overlap {a.overlap}" if a.smoother == "schwarz" else ""),
+                      "smoother": f"{a.smoother} {nu}+{nu}" + (f" ({a.nu_coarse}+{a.nu_coarse} below the finest level)" if a.nu_coarse >= 0 else "") + (f" on [lambda/{a.smooth_ratio:g}, lambda]" if a.smoother == "chebyshev" else "") + (f", overlap {a.overlap}" if a.smoother == "schwarz" else ""),
                       "coarsening": a.coarsening,
                       "coarse": cinfo, "dss": "column sums" if a.fused_sum else a.dss,
                       "guess": "zero", "precision": best, "krylov": res["krylov"]},
@@ -861,7 +864,8 @@ def main():
     if not a.no_cpu:
         p64 = paths.get("fp64", res)
         out["cpu_baseline"] = cpu_baseline(a.P, nu, a.smoother, p64["iters"], info0["n_elem"], info0["n_dof"],
-                                           coarsening=a.coarsening, smooth_ratio=a.smooth_ratio)
+                                           coarsening=a.coarsening, smooth_ratio=a.smooth_ratio,
+                                           nu_coarse=a.nu_coarse)
     print(json.dumps(out), flush=True)
 
 

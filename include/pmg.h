@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define PMG_ABI_VERSION 6
+#define PMG_ABI_VERSION 7
 
 enum pmg_status {
   PMG_OK = 0,
@@ -128,7 +128,9 @@ typedef struct pmg_mesh {
 
 typedef struct pmg_options {
   int32_t P;              /* finest triangle order, 1..8 (vertical order: PZ)   */
-  int32_t nu1, nu2;       /* damped-Jacobi pre/post sweeps (Alg. 1)              */
+  int32_t nu1, nu2;       /* pre/post smoothing sweeps (Alg. 1) of the finest
+                             level, and of every level unless nu1_coarse /
+                             nu2_coarse say otherwise                          */
   double omega[8];        /* per level; <= 0: 4/(3*lambda) with lambda = 1.05 x
                              30-step power estimate of lambda_max(D^-1 A)
                              (Schwarz: of the spectral radius of S^-1 A, the
@@ -211,6 +213,13 @@ typedef struct pmg_options {
                              atomics and a fixed order either way (bitwise
                              reproducible); the two differ by rounding.
                              fused_sum, where it applies, takes precedence   */
+  int32_t nu1_coarse, nu2_coarse; /* pre/post sweeps of the levels below the
+                             finest (the coarsest level is solved, never
+                             smoothed); < 0 (default): nu1, nu2, one pair for
+                             every level as Alg. 1 passes it down the
+                             recursion.  Fewer sweeps there are a tuning: the
+                             V-cycle stays symmetric while each level's pre and
+                             post counts agree                                  */
 } pmg_options;
 
 /* Geometric factors read by the MFMA element operators.  STORED: the six

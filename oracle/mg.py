@@ -141,7 +141,7 @@ class Hierarchy:
                  dirichlet_tags: int = 0, top_neumann: bool = False,
                  coarse: str = "exact", cheb=None, seed: int = 0,
                  smoother: str = "jacobi", smooth_ratio: float = 15.0, coarsening: str = "both",
-                 overlap: int = 1, PZ: int = None):
+                 overlap: int = 1, PZ: int = None, nu1_coarse: int = None, nu2_coarse: int = None):
         self.mesh = mesh
         # P: triangle order of the finest level, which is also the order of the
         # isoparametric map every level's geometry comes from (the sigma map is
@@ -163,6 +163,9 @@ class Hierarchy:
             d2 = lateral_dirichlet_2d(mesh, nl, dirichlet_tags) if dirichlet_tags else None
             self.levels.append(Level(mesh, p, P, xyz_f, d2, top_neumann))
         self.nu1, self.nu2 = nu1, nu2
+        # sweeps on the levels below the finest (None: nu1, nu2 on every level,
+        # as in Alg. 1, which passes one pair down the recursion)
+        self.nu1_coarse, self.nu2_coarse = nu1_coarse, nu2_coarse
         self.Pi = [element_prolongation(self.orders[i], self.orders[i + 1])
                    for i in range(len(self.orders) - 1)]
         if smoother not in ("jacobi", "chebyshev", "schwarz"):
@@ -305,17 +308,26 @@ class Hierarchy:
             u = u + lv.omega * lv.dinv * (f - lv.A(u))
         return u
 
+    def sweeps(self, i: int):
+        """(pre, post) smoothing sweeps of level i: nu1, nu2 on the finest level,
+        nu1_coarse, nu2_coarse (where given) on the levels below it."""
+        if i == 0:
+            return self.nu1, self.nu2
+        return (self.nu1 if self.nu1_coarse is None else self.nu1_coarse,
+                self.nu2 if self.nu2_coarse is None else self.nu2_coarse)
+
     def vcycle(self, f: np.ndarray, i: int = 0, u0=None) -> np.ndarray:
         if i == len(self.levels) - 1:
             return self.coarse_solve(f)
         lv = self.levels[i]
+        pre, post = self.sweeps(i)
         u = np.zeros_like(f) if u0 is None else u0.copy()
-        u = self.smooth(i, u, f, self.nu1)
+        u = self.smooth(i, u, f, pre)
         r = f - lv.A(u)
         rc = self.restrict(i, r)
         uc = self.vcycle(rc, i + 1)
         u = u + self.prolong(i, uc)
-        u = self.smooth(i, u, f, self.nu2, post=True)
+        u = self.smooth(i, u, f, post, post=True)
         return u
 
 

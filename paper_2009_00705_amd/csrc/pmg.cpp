@@ -1545,6 +1545,15 @@ static void coarse_setup(pmg_ctx* c, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // V-cycle (Alg. 1) with zero initial guess
 // ---------------------------------------------------------------------------
+// Pre/post sweeps of level i: nu1, nu2 on the finest level, and on the levels
+// below it unless nu1_coarse / nu2_coarse (>= 0) override them.
+static int sweeps_pre(const pmg_ctx* c, int i) {
+  return i > 0 && c->opt.nu1_coarse >= 0 ? c->opt.nu1_coarse : c->opt.nu1;
+}
+static int sweeps_post(const pmg_ctx* c, int i) {
+  return i > 0 && c->opt.nu2_coarse >= 0 ? c->opt.nu2_coarse : c->opt.nu2;
+}
+
 template <typename T>
 static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   if (i == c->nl - 1) {
@@ -1556,13 +1565,14 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   const int64_t N = L.num.n_dof;
   const bool cheb = c->opt.smoother == PMG_SMOOTH_CHEBYSHEV;
   const bool asm_ = c->opt.smoother == PMG_SMOOTH_SCHWARZ;
-  if (c->opt.nu1 >= 1 && asm_) {
-    schwarz_smooth<T>(c, i, f, u, true, false, c->opt.nu1, st);
-  } else if (c->opt.nu1 >= 1 && cheb) {
-    cheb_smooth<T>(c, i, f, u, true, c->opt.nu1, st);
-  } else if (c->opt.nu1 >= 1) {
+  const int nu1 = sweeps_pre(c, i), nu2 = sweeps_post(c, i);
+  if (nu1 >= 1 && asm_) {
+    schwarz_smooth<T>(c, i, f, u, true, false, nu1, st);
+  } else if (nu1 >= 1 && cheb) {
+    cheb_smooth<T>(c, i, f, u, true, nu1, st);
+  } else if (nu1 >= 1) {
     launch_scale_diag<T>(L.dinv<T>(), f, u, L.omega, N, st);
-    for (int m = 1; m < c->opt.nu1; ++m) jacobi_sweep<T>(c, i, f, u, st);
+    for (int m = 1; m < nu1; ++m) jacobi_sweep<T>(c, i, f, u, st);
   } else {
     launch_fill<T>(u, T(0), N, st);
   }
@@ -1573,11 +1583,11 @@ static void vcycle(pmg_ctx* c, int i, const T* f, T* u, hipStream_t st) {
   vcycle<T>(c, i + 1, C.f<T>(), C.u<T>(), st);
   prolong_add<T>(c, i, C.u<T>(), u, OP_AVG_ADD, st);
   if (asm_) {
-    schwarz_smooth<T>(c, i, f, u, false, true, c->opt.nu2, st);
+    schwarz_smooth<T>(c, i, f, u, false, true, nu2, st);
   } else if (cheb) {
-    if (c->opt.nu2 >= 1) cheb_smooth<T>(c, i, f, u, false, c->opt.nu2, st);
+    if (nu2 >= 1) cheb_smooth<T>(c, i, f, u, false, nu2, st);
   } else {
-    for (int m = 0; m < c->opt.nu2; ++m) jacobi_sweep<T>(c, i, f, u, st);
+    for (int m = 0; m < nu2; ++m) jacobi_sweep<T>(c, i, f, u, st);
   }
 }
 
@@ -2080,6 +2090,8 @@ void pmg_options_default(pmg_options* o) {
   o->fused_sum = 0;
   o->dss = 0;
   o->graphs = 0;
+  o->nu1_coarse = -1;
+  o->nu2_coarse = -1;
 }
 
 int pmg_abi_version(void) { return PMG_ABI_VERSION; }

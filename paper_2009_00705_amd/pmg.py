@@ -54,7 +54,8 @@ class Options(C.Structure):
                 ("kernel_variant", C.c_int32), ("smoother", C.c_int32), ("smooth_ratio", C.c_double),
                 ("coarsening", C.c_int32), ("overlap", C.c_int32), ("schwarz_store", C.c_int32),
                 ("schwarz_chunk", C.c_int64), ("geometry", C.c_int32), ("PZ", C.c_int32),
-                ("fused_sum", C.c_int32), ("graphs", C.c_int32), ("dss", C.c_int32)]
+                ("fused_sum", C.c_int32), ("graphs", C.c_int32), ("dss", C.c_int32),
+                ("nu1_coarse", C.c_int32), ("nu2_coarse", C.c_int32)]
 
 
 class FnpfStats(C.Structure):

@@ -48,6 +48,9 @@ def make_pair(mesh, P, eta_kind="wavy", omega=0.3, **kw):
         okw["PZ"] = kw["PZ"]
     if "overlap" in kw:
         okw["overlap"] = kw["overlap"]
+    for k in ("nu1_coarse", "nu2_coarse"):
+        if k in kw:
+            okw[k] = kw[k]
     if kw.get("coarse") == "chebyshev":
         okw["coarse"] = "chebyshev"
         okw["cheb"] = (kw["cheb_degree"], kw["cheb_lmin"], kw["cheb_lmax"])

@@ -276,10 +276,13 @@ def test_pcg_solve_parity(solve_pair):
     assert torch.equal(phi, phi2)
 
 
-@pytest.fixture(scope="module", params=["box5x5_L3_P6", "cyl_P3"])
+@pytest.fixture(scope="module", params=["box5x5_L3_P6", "cyl_P3", "box5x5_L3_P6_nu22"])
 def cheb_pair(request):
-    mk, P = CASES[request.param]
-    h, ctx = make_pair(mk(), P, omega="auto", smoother="chebyshev", nu1=3, nu2=3)
+    # the last case smooths the levels below the finest with 2 + 2 sweeps
+    name = request.param.replace("_nu22", "")
+    kw = dict(nu1_coarse=2, nu2_coarse=2) if request.param.endswith("_nu22") else {}
+    mk, P = CASES[name]
+    h, ctx = make_pair(mk(), P, omega="auto", smoother="chebyshev", nu1=3, nu2=3, **kw)
     yield request.param, h, ctx
     ctx.close()
 

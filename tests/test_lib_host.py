@@ -30,7 +30,11 @@ def test_library_exports_every_declared_symbol():
     for n in names:
         assert hasattr(L, n), n
         assert n in pmg.SIGNATURES, f"binding lacks {n}"
-    assert L.pmg_abi_version() == 6
+    assert L.pmg_abi_version() == 7
+    # the binding's struct ends where the header's does: the last fields' defaults
+    o = pmg.default_options()
+    assert (o.dss, o.nu1_coarse, o.nu2_coarse) == (0, -1, -1)
+    assert pmg.default_options(nu1_coarse=2).nu1_coarse == 2
 
 
 def _host_ctx(mesh, P, **kw):

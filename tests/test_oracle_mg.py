@@ -198,3 +198,42 @@ def test_chebyshev_smoother_closed_form():
     e0 = np.linalg.solve(A, f[free])
     want = e0 - (V @ (p * (V.T @ (np.sqrt(d) * e0)))) / np.sqrt(d)
     np.testing.assert_allclose(u[free], want, atol=1e-10 * np.abs(want).max())
+
+
+def test_coarse_level_sweep_counts():
+    """Sweep counts of the levels below the finest (a tuning beside Alg. 1,
+    which passes one (nu1, nu2) pair down the recursion): they act only on the
+    levels strictly between the finest and the coarsest, the V-cycle stays a
+    symmetric operator when every level's pre and post counts agree (and not
+    when they differ), and the preconditioned solve still reaches the direct
+    solution."""
+    import math
+    m = W.box_mesh(4, 2, lx=math.pi / 4, ly=math.pi / 4)
+    # two levels (2 -> 1, exact coarse solve): no level below the finest smooths
+    h2 = Hierarchy(m, 2, smoother="chebyshev", nu1=3, nu2=3, smooth_ratio=8.0)
+    h2c = Hierarchy(m, 2, smoother="chebyshev", nu1=3, nu2=3, smooth_ratio=8.0, nu1_coarse=0, nu2_coarse=5)
+    lv = h2.levels[0]
+    rng = np.random.default_rng(21)
+    x = np.where(lv.free, rng.standard_normal(lv.num.n_dof), 0)
+    y = np.where(lv.free, rng.standard_normal(lv.num.n_dof), 0)
+    np.testing.assert_array_equal(h2.vcycle(x), h2c.vcycle(x))
+    # three levels (4 -> 2 -> 1): the middle level's counts change the cycle
+    kw = dict(smoother="chebyshev", nu1=3, nu2=3, smooth_ratio=8.0)
+    h3 = Hierarchy(m, 4, **kw)
+    lv = h3.levels[0]
+    x = np.where(lv.free, rng.standard_normal(lv.num.n_dof), 0)
+    y = np.where(lv.free, rng.standard_normal(lv.num.n_dof), 0)
+    nxy = np.linalg.norm(x) * np.linalg.norm(y)
+    hs = Hierarchy(m, 4, nu1_coarse=2, nu2_coarse=2, omega=[l.omega for l in h3.levels[:-1]], **kw)
+    ha = Hierarchy(m, 4, nu1_coarse=1, nu2_coarse=3, omega=[l.omega for l in h3.levels[:-1]], **kw)
+    assert hs.sweeps(0) == (3, 3) and hs.sweeps(1) == (2, 2)
+    z3, zs = h3.vcycle(x), hs.vcycle(x)
+    assert np.linalg.norm(zs - z3) > 1e-3 * np.linalg.norm(z3)
+    assert abs(zs @ y - x @ hs.vcycle(y)) < 1e-10 * nxy
+    assert abs(ha.vcycle(x) @ y - x @ ha.vcycle(y)) > 1e-6 * nxy
+    xyz = M.node_xyz(m, lv.num, np.zeros(lv.num.n2d))
+    phi_ex = W.linear_wave(xyz[:, 0], xyz[:, 1], xyz[:, 2], 1.0)
+    ref = K.direct_solve(hs, phi_ex)
+    r = K.solve(hs, phi_ex, method="pcg", rtol=1e-10, imax=200)
+    assert r.rel_res <= 1e-10
+    assert np.abs(r.phi - ref).max() < 1e-8 * np.abs(ref).max()
