@@ -268,3 +268,16 @@ def test_frozen_cylinder_mesh():
     ctx = _host_ctx(m, 1)
     np.testing.assert_array_equal(ctx.gather_map(0), M.Numbering(m, 1).map.astype(np.int32))
     ctx.close()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU: --gpus above 1 ends with exit code 2 and a
+    JSON line that says so, before anything touches a device."""
+    import json
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=300, cwd=ROOT)
+    assert r.returncode == 2, r.stderr[-2000:]
+    msg = json.loads(r.stdout.strip().splitlines()[-1])
+    assert "one GPU" in msg["error"]
