@@ -281,3 +281,14 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2, r.stderr[-2000:]
     msg = json.loads(r.stdout.strip().splitlines()[-1])
     assert "one GPU" in msg["error"]
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without the built library the binding raises; there is no fallback path."""
+    from paper_2009_00705_amd import pmg
+    monkeypatch.setattr(pmg, "_lib", None)
+    monkeypatch.setattr(pmg, "LIB_PATH", str(tmp_path / "libpmg.so"))
+    with pytest.raises(ImportError, match="not built"):
+        pmg.lib()
+    with pytest.raises(ImportError):
+        pmg.Context(W.box_mesh(2, 1), P=2, host_only=1)
